@@ -1,0 +1,174 @@
+/*
+ * octen.h - C ABI of the MI355X (gfx950) online compressed CP decomposition.
+ *
+ * The library implements, for a 3-mode tensor that grows along mode 3 in
+ * batches of frontal slices, the update of OCTen (Gujral et al., "OCTen:
+ * Online Compression-based Tensor Decomposition"):
+ *   Sec. 4.1 / Eq. 1   compress the batch into P replicas with random
+ *                      multi-mode products sharing S anchor columns,
+ *   Sec. 4.1 / Eq. 2   add the compressed batch onto the stored summaries,
+ *   Sec. 4.1           fit every replica by rank-R CP-ALS,
+ *   Sec. 4.2 / Eq. 5   match replica components through the anchor rows,
+ *   Sec. 4.3 / Eq. 6-7 recover the full factors by least squares,
+ *   Sec. 5.1           and measure the fitness of the recovered model.
+ * Algorithm 1 (supplement) gives the loop these calls make up:
+ *   octen_compress_batch -> octen_update_replicas -> octen_cp_als_replicas
+ *   -> octen_recover_factors, repeated per batch; octen_fit on demand.
+ *
+ * Conventions for every call:
+ *  - Bulk arrays are DEVICE pointers owned by the caller (row-major, C order).
+ *    Arrays named "_host" are host pointers.
+ *  - Calls enqueue work on the stream given to octen_init and return without
+ *    waiting, except the ones that write a host result (they synchronise the
+ *    stream first).  Caller inputs must stay valid until the stream reaches
+ *    the call.
+ *  - Arguments are validated before anything is launched; on error nothing
+ *    is enqueued and the handle state is unchanged.  No exception crosses the
+ *    ABI.  octen_last_error() gives a text for the last failure of a handle.
+ *  - One handle is used by one host thread at a time.
+ *
+ * Notation: M1 = S + P*(Q - S) distinct compression columns per mode.
+ * Replica p uses compression columns [0, S) (shared anchors, Eq. 1) and
+ * [S + p*(Q-S), S + (p+1)*(Q-S)) (its own).
+ */
+#ifndef OCTEN_H
+#define OCTEN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OCTEN_ABI_VERSION 1
+
+typedef struct octen_ctx* octen_t;
+
+typedef enum {
+  OCTEN_OK = 0,
+  OCTEN_ERR_ARG = 1,         /* invalid argument (null pointer, bad size) */
+  OCTEN_ERR_STATE = 2,       /* call out of order (e.g. update before compress) */
+  OCTEN_ERR_HIP = 3,         /* HIP runtime error; see octen_last_error */
+  OCTEN_ERR_NOMEM = 4,       /* device allocation failed */
+  OCTEN_ERR_NUMERIC = 5,     /* non-finite values or a failed solve */
+  OCTEN_ERR_UNSUPPORTED = 6  /* valid request this build does not implement */
+} octen_status;
+
+typedef enum { OCTEN_F64 = 0, OCTEN_F32 = 1, OCTEN_BF16 = 2, OCTEN_F16 = 3 } octen_dtype;
+
+/* ALS starting point (octen_cp_als_replicas). */
+enum { OCTEN_INIT_GIVEN = 0, OCTEN_INIT_PREV = 1 };
+
+/* Internal arrays readable through octen_get_state (for tests). */
+enum {
+  OCTEN_STATE_Y = 0,        /* [P][Q][Q][Q] summaries, accumulation type      */
+  OCTEN_STATE_Z = 1,        /* [P][Q][Q][Q] last compressed batch             */
+  OCTEN_STATE_FACTORS = 2,  /* [P][3][Q][R] f64 replica factors, unit columns */
+  OCTEN_STATE_LAMBDA = 3,   /* [P][R] f64 replica weights                     */
+  OCTEN_STATE_PERM = 4,     /* [P][R] int32: replica column r -> reference    */
+  OCTEN_STATE_ALIGNED = 5,  /* [P][3][Q][R] f64 aligned replica factors       */
+  OCTEN_STATE_RHS = 6,      /* [3][M1][R] f64 deduplicated stacked factors    */
+  OCTEN_STATE_H = 7,        /* [M1][R] f64 temporal carry W_old^T C_old       */
+  OCTEN_STATE_TPERM = 8,    /* [R] int32 column pairing with previous batch   */
+  OCTEN_STATE_ITERS = 9,    /* [P] int32 ALS sweeps done                      */
+  OCTEN_STATE_MARGIN = 10,  /* [P] f64 matching margin (replica 0: +inf)      */
+  OCTEN_STATE_FLAGS = 11    /* [P] int32 health flags, bit0 solve fallback    */
+};
+
+/* Flags (octen_config.flags). */
+#define OCTEN_FLAG_FUSE_UPDATE 0x1ull   /* compression adds into Y directly */
+#define OCTEN_FLAG_REFERENCE_PATH 0x2ull /* plain FP64 kernels, no MFMA      */
+
+typedef struct {
+  int32_t abi_version;     /* must be OCTEN_ABI_VERSION                        */
+  int32_t R;               /* CP rank (Sec. 2), 1 <= R <= 32                   */
+  int32_t P;               /* number of replicas p (Sec. 4.1), P >= 1          */
+  int32_t Q;               /* replica side Q (Sec. 4.1), S < Q <= 128, R <= Q  */
+  int32_t S;               /* shared anchor columns (Eq. 1), S >= 1            */
+  int32_t x_dtype;         /* element type of X: OCTEN_F64 or OCTEN_F32        */
+  int32_t compress_dtype;  /* compression arithmetic: F64, F32 or BF16 inputs;
+                              accumulation is F64 for F64, else F32           */
+  int32_t als_dtype;       /* MTTKRP arithmetic: OCTEN_F64 or OCTEN_F32;
+                              R x R solves and recovery are always F64        */
+  int64_t I;               /* mode-1 size I (problem statement, Sec. 3)        */
+  int64_t J;               /* mode-2 size J                                    */
+  uint64_t flags;          /* OCTEN_FLAG_*                                     */
+} octen_config;
+
+/* Create a handle.  U: [I][M1] f64, V: [J][M1] f64 device arrays, the fixed
+ * mode-1 and mode-2 compression matrices in deduplicated layout (shared
+ * columns first, then each replica's own; Eq. 1).  They are copied; the
+ * least-squares operators of Eq. 7 for modes 1 and 2 are built here once.
+ * stream: a hipStream_t (NULL = default stream).  Summaries start at zero. */
+octen_status octen_init(const octen_config* cfg, const double* U, const double* V,
+                        void* stream, octen_t* out);
+
+/* Sec. 4.1 compression of one batch: Z_p = X x1 U_p^T x2 V_p^T x3 W_p^T.
+ * X: [t][I][J] in cfg.x_dtype (frontal slices, j fastest).  W: [t][M1] f64,
+ * the batch's mode-3 compression rows.  slice_scale: NULL or [t] f32 powers of
+ * two applied to slice k before rounding to a narrow type and undone exactly
+ * after the contraction (needed for F16 range; no effect on F32/F64).
+ * Replaces the previous batch's Z. */
+octen_status octen_compress_batch(octen_t h, const void* X, int64_t t, const double* W,
+                                  const float* slice_scale);
+
+/* Same for a sparse batch given as sorted COO (by k, then i, then j) with
+ * slice indices k in [0, t) relative to the batch.  k, i, j: [nnz] int32,
+ * v: [nnz] f32.  Duplicated coordinates add up. */
+octen_status octen_compress_batch_coo(octen_t h, int64_t nnz, const int32_t* k,
+                                      const int32_t* i, const int32_t* j, const float* v,
+                                      int64_t t, const double* W);
+
+/* Eq. 2: Y_p += Z_p for every replica; the slice count K grows by t. */
+octen_status octen_update_replicas(octen_t h);
+
+/* Sec. 4.1: rank-R CP-ALS of every replica summary.  Gauss-Seidel sweeps
+ * over modes 1, 2, 3; each mode solves the R x R normal equations in f64
+ * (Cholesky) and scales the columns to unit 2-norm; lambda = norms of mode 3.
+ * max_iters >= 1 sweeps, or fewer when tol > 0 and the replica fit changes by
+ * less than tol in one sweep.  init_mode OCTEN_INIT_GIVEN: init is
+ * [P][3][Q][R] f64 (device); OCTEN_INIT_PREV: start from the factors of the
+ * previous call (init ignored).  iters_done_host: NULL or [P] host int32
+ * (synchronises). */
+octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int32_t init_mode,
+                                   const double* init, int32_t* iters_done_host);
+
+/* Sec. 4.2 and 4.3 / Eq. 5-7: distribute lambda^(1/3), align every replica
+ * to replica 0 through the anchor rows, stack, and solve for the factors in
+ * f64 (minimum-norm least squares).  Outputs, all f64 device arrays:
+ * A: [I][R], B: [J][R] with unit-norm columns whose largest-magnitude entry is
+ * positive, and C: [K][R] (all slices seen so far; the columns of earlier
+ * rows follow the current A, B).  c_capacity: rows available in C (>= K).
+ * K_out_host: NULL or host int64 (synchronises). */
+octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C,
+                                   int64_t c_capacity, int64_t* K_out_host);
+
+/* Sec. 5.1 fitness terms over the slices X [t][I][J] (cfg.x_dtype) with global
+ * slice index k0..k0+t-1: out_host[0] += sum (X - [[A,B,C]])^2,
+ * out_host[1] += sum X^2, accumulated in f64 (synchronises).
+ * fit = 1 - sqrt(out[0] / out[1]) over all slices. */
+octen_status octen_fit(octen_t h, const void* X, int64_t t, int64_t k0, const double* A,
+                       const double* B, const double* C, double* out_host);
+
+/* Copy one internal array (OCTEN_STATE_*) into dst (device), bytes must be
+ * at least its size. */
+octen_status octen_get_state(octen_t h, int32_t what, void* dst, size_t bytes);
+
+/* Host-only identifiability verdicts (Eq. 4, Eq. 8): bit0 Eq. 8 holds,
+ * bit1 M1 >= I, bit2 M1 >= J, bit3 M1 >= t, bit4 Eq. 4 with generic Kruskal
+ * ranks.  A violation is not an error: recovery is then minimum-norm. */
+octen_status octen_check_identifiable(const octen_config* cfg, int64_t K, int64_t t,
+                                      int32_t* bits_host, double* p_min_host);
+
+/* Release every device buffer of the handle (synchronises its stream). */
+octen_status octen_destroy(octen_t h);
+
+const char* octen_status_str(octen_status s);
+const char* octen_last_error(octen_t h);
+int32_t octen_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OCTEN_H */

@@ -1,0 +1,180 @@
+// Reference compression path (Sec. 4.1, Eq. 1): plain FP64-accumulating
+// kernels for any slice type, used for the FP64 form and as the baseline the
+// MFMA path is measured against.
+//
+// The multi-mode product is evaluated as
+//   T2[k] = X_k V            (contract j; one strided GEMM over all slices)
+//   M[k][p] = U_p^T T2[k]_p  (contract i per replica; Q x Q per slice)
+//   Z_p = sum_k M[k][p] (x) W_p(k, :)   (contract k)
+// which is the same trilinear form as the paper's mode-1, mode-2, mode-3
+// order; only the order of the two non-temporal contractions differs.
+#include <hip/hip_runtime.h>
+
+#include "octen_internal.h"
+
+namespace octen {
+
+namespace {
+
+__device__ __forceinline__ int rep_col(int p, int q, int Q, int S) {
+  return q < S ? q : S + p * (Q - S) + (q - S);
+}
+
+constexpr int S2_ROWS = 16;   // output rows a per block
+constexpr int S2_KT = 32;     // i per LDS tile
+
+// M[k][p][a][b] = sum_i U[i][col_p(a)] * T2[k][i][col_p(b)], a in a block of 16.
+__global__ __launch_bounds__(256) void stage2_kernel(const double* __restrict__ U,
+                                                     const double* __restrict__ T2, int64_t I,
+                                                     int M1, int P, int Q, int S,
+                                                     double* __restrict__ Mout) {
+  extern __shared__ double sm[];
+  double* Us = sm;                      // [S2_KT][S2_ROWS]
+  double* Ts = sm + S2_KT * S2_ROWS;    // [S2_KT][Q]
+  const int k = blockIdx.x, p = blockIdx.y, a0 = blockIdx.z * S2_ROWS;
+  const int tid = threadIdx.x;
+  const int nout = S2_ROWS * Q;
+  double acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+  const double* T2k = T2 + (int64_t)k * I * M1;
+  for (int64_t i0 = 0; i0 < I; i0 += S2_KT) {
+    for (int e = tid; e < S2_KT * S2_ROWS; e += 256) {
+      int ii = e / S2_ROWS, aa = e % S2_ROWS;
+      int64_t gi = i0 + ii;
+      int a = a0 + aa;
+      Us[e] = (gi < I && a < Q) ? U[gi * M1 + rep_col(p, a, Q, S)] : 0.0;
+    }
+    for (int e = tid; e < S2_KT * Q; e += 256) {
+      int ii = e / Q, b = e % Q;
+      int64_t gi = i0 + ii;
+      Ts[e] = gi < I ? T2k[gi * M1 + rep_col(p, b, Q, S)] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int o = tid + u * 256;
+      if (o < nout) {
+        int aa = o / Q, b = o % Q;
+        double s = acc[u];
+        for (int ii = 0; ii < S2_KT; ++ii) s = fma(Us[ii * S2_ROWS + aa], Ts[ii * Q + b], s);
+        acc[u] = s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    int o = tid + u * 256;
+    if (o < nout) {
+      int aa = o / Q, b = o % Q;
+      int a = a0 + aa;
+      if (a < Q) Mout[(((int64_t)k * P + p) * Q + a) * Q + b] = acc[u];
+    }
+  }
+}
+
+constexpr int S3_B = 16;   // b per block
+constexpr int S3_KT = 32;  // k per LDS tile
+
+// Z[p][a][b][c] = sum_k M[k][p][a][b] * W[k][col_p(c)], b in a block of 16.
+template <typename TM, typename TZ>
+__global__ __launch_bounds__(256) void mode3_kernel(const TM* __restrict__ Mk,
+                                                    const double* __restrict__ W, int64_t t,
+                                                    int M1, int P, int Q, int S,
+                                                    TZ* __restrict__ Z) {
+  extern __shared__ double sm[];
+  double* Ms = sm;                     // [S3_KT][S3_B]
+  double* Ws = sm + S3_KT * S3_B;      // [S3_KT][Q]
+  const int p = blockIdx.x, a = blockIdx.y, b0 = blockIdx.z * S3_B;
+  const int tid = threadIdx.x;
+  const int nout = S3_B * Q;
+  double acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+  for (int64_t k0 = 0; k0 < t; k0 += S3_KT) {
+    for (int e = tid; e < S3_KT * S3_B; e += 256) {
+      int kk = e / S3_B, bb = e % S3_B;
+      int64_t gk = k0 + kk;
+      int b = b0 + bb;
+      Ms[e] = (gk < t && b < Q) ? (double)Mk[((gk * P + p) * Q + a) * Q + b] : 0.0;
+    }
+    for (int e = tid; e < S3_KT * Q; e += 256) {
+      int kk = e / Q, c = e % Q;
+      int64_t gk = k0 + kk;
+      Ws[e] = gk < t ? W[gk * M1 + rep_col(p, c, Q, S)] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int o = tid + u * 256;
+      if (o < nout) {
+        int bb = o / Q, c = o % Q;
+        double s = acc[u];
+        for (int kk = 0; kk < S3_KT; ++kk) s = fma(Ms[kk * S3_B + bb], Ws[kk * Q + c], s);
+        acc[u] = s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    int o = tid + u * 256;
+    if (o < nout) {
+      int bb = o / Q, c = o % Q;
+      int b = b0 + bb;
+      if (b < Q) Z[(((int64_t)p * Q + a) * Q + b) * Q + c] = (TZ)acc[u];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t compress_mode3(hipStream_t s, const CompressShape& sh, int64_t t, const void* M,
+                          bool m_f64, const double* W, void* Z, bool z_f64) {
+  dim3 grid(sh.P, sh.Q, (sh.Q + S3_B - 1) / S3_B);
+  size_t lds = (size_t)(S3_KT * S3_B + S3_KT * sh.Q) * sizeof(double);
+  if (m_f64 && z_f64)
+    hipLaunchKernelGGL((mode3_kernel<double, double>), grid, dim3(256), lds, s,
+                       (const double*)M, W, t, sh.M1, sh.P, sh.Q, sh.S, (double*)Z);
+  else if (m_f64 && !z_f64)
+    hipLaunchKernelGGL((mode3_kernel<double, float>), grid, dim3(256), lds, s, (const double*)M,
+                       W, t, sh.M1, sh.P, sh.Q, sh.S, (float*)Z);
+  else if (!m_f64 && z_f64)
+    hipLaunchKernelGGL((mode3_kernel<float, double>), grid, dim3(256), lds, s, (const float*)M,
+                       W, t, sh.M1, sh.P, sh.Q, sh.S, (double*)Z);
+  else
+    hipLaunchKernelGGL((mode3_kernel<float, float>), grid, dim3(256), lds, s, (const float*)M, W,
+                       t, sh.M1, sh.P, sh.Q, sh.S, (float*)Z);
+  return hipGetLastError();
+}
+
+hipError_t compress_reference(hipStream_t s, const CompressShape& sh, const void* X, bool x_f64,
+                              int64_t t, const double* U, const double* V, const double* W,
+                              double* T2work, int64_t t2_rows_cap, double* Mwork, void* Z,
+                              bool z_f64) {
+  const int64_t I = sh.I, J = sh.J;
+  const int M1 = sh.M1;
+  int64_t chunk = t2_rows_cap / I;
+  if (chunk < 1) return hipErrorInvalidValue;
+  for (int64_t k0 = 0; k0 < t; k0 += chunk) {
+    int64_t tc = t - k0 < chunk ? t - k0 : chunk;
+    // T2 (tc*I x M1) = X[k0:k0+tc] (tc*I x J) * V (J x M1)
+    hipError_t e;
+    if (x_f64)
+      e = gemm_f64(s, (int)(tc * I), M1, (int)J, 1, (const double*)X + k0 * I * J, J, 1, 0, V, M1,
+                   1, 0, T2work, M1, 1, 0, nullptr, 1.0, 0.0);
+    else
+      e = gemm_f32in_f64(s, (int)(tc * I), M1, (int)J, 1, (const float*)X + k0 * I * J, J, 1, 0,
+                         V, M1, 1, 0, T2work, M1, 1, 0, nullptr, 1.0, 0.0);
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)tc, sh.P, (sh.Q + S2_ROWS - 1) / S2_ROWS);
+    size_t lds = (size_t)(S2_KT * S2_ROWS + S2_KT * sh.Q) * sizeof(double);
+    hipLaunchKernelGGL(stage2_kernel, grid, dim3(256), lds, s, U, T2work, I, M1, sh.P, sh.Q, sh.S,
+                       Mwork + k0 * sh.P * sh.Q * sh.Q);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return compress_mode3(s, sh, t, Mwork, true, W, Z, z_f64);
+}
+
+}  // namespace octen

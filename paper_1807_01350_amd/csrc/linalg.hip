@@ -1,0 +1,315 @@
+// FP64 building blocks: a strided batched GEMM, SPD inversion and small SPD
+// solves.  They carry the least-squares steps of the method (Sec. 4.3, Eq. 7)
+// and the set-up of its operators; all arithmetic is double precision.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "octen_internal.h"
+
+namespace octen {
+
+namespace {
+
+constexpr int GT = 64;   // output tile (GT x GT)
+constexpr int GK = 16;   // k step
+
+template <typename TA>
+__global__ __launch_bounds__(256) void gemm_kernel(
+    int M, int N, int K, const TA* __restrict__ A, int64_t sam, int64_t sak, int64_t sab,
+    const double* __restrict__ B, int64_t sbk, int64_t sbn, int64_t sbb, double* __restrict__ C,
+    int64_t scm, int64_t scn, int64_t scb, const double* __restrict__ d, double alpha,
+    double beta) {
+  __shared__ double As[GK][GT + 1];
+  __shared__ double Bs[GK][GT + 1];
+  const int b = blockIdx.z;
+  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  const int tid = threadIdx.x;
+  const int tx = tid % 16, ty = tid / 16;
+  A += (int64_t)b * sab;
+  B += (int64_t)b * sbb;
+  C += (int64_t)b * scb;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    for (int e = tid; e < GK * GT; e += 256) {
+      // A tile: m fastest when A is k-major, else k fastest
+      int kk, mm;
+      if (sam == 1) { mm = e % GT; kk = e / GT; } else { kk = e % GK; mm = e / GK; }
+      int gm = m0 + mm, gk = k0 + kk;
+      double v = 0.0;
+      if (gm < M && gk < K) {
+        v = (double)A[(int64_t)gm * sam + (int64_t)gk * sak];
+        if (d) v *= d[gk];
+      }
+      As[kk][mm] = v;
+      int nn, kb;
+      if (sbn == 1) { nn = e % GT; kb = e / GT; } else { kb = e % GK; nn = e / GK; }
+      int gn = n0 + nn, gk2 = k0 + kb;
+      Bs[kb][nn] = (gn < N && gk2 < K) ? B[(int64_t)gk2 * sbk + (int64_t)gn * sbn] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      double a[4], bb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], bb[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int gm = m0 + ty + 16 * i;
+    if (gm >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int gn = n0 + tx + 16 * j;
+      if (gn >= N) continue;
+      double* c = C + (int64_t)gm * scm + (int64_t)gn * scn;
+      double v = alpha * acc[i][j];
+      if (beta != 0.0) v += beta * (*c);
+      *c = v;
+    }
+  }
+}
+
+template <typename TA>
+hipError_t gemm_launch(hipStream_t s, int M, int N, int K, int batch, const TA* A, int64_t sam,
+                       int64_t sak, int64_t sab, const double* B, int64_t sbk, int64_t sbn,
+                       int64_t sbb, double* C, int64_t scm, int64_t scn, int64_t scb,
+                       const double* d, double alpha, double beta) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, batch);
+  hipLaunchKernelGGL(gemm_kernel<TA>, grid, dim3(256), 0, s, M, N, K, A, sam, sak, sab, B, sbk, sbn,
+                     sbb, C, scm, scn, scb, d, alpha, beta);
+  return hipGetLastError();
+}
+
+// Gauss-Jordan step k: save row k and column k before the in-place update.
+__global__ void gj_save(const double* __restrict__ A, int n, int k, double* __restrict__ row,
+                        double* __restrict__ col) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    row[i] = A[(int64_t)k * n + i];
+    col[i] = A[(int64_t)i * n + k];
+  }
+}
+
+__global__ void gj_update(double* __restrict__ A, int n, int k, const double* __restrict__ row,
+                          const double* __restrict__ col, int* info) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = blockIdx.y;
+  if (j >= n) return;
+  double piv = row[k];
+  if (!(piv > 0.0)) {
+    if (i == 0 && j == 0 && *info == 0) *info = k + 1;
+    return;
+  }
+  double inv = 1.0 / piv;
+  double v;
+  if (i == k && j == k) v = inv;
+  else if (i == k) v = row[j] * inv;
+  else if (j == k) v = -col[i] * inv;
+  else v = A[(int64_t)i * n + j] - col[i] * row[j] * inv;
+  A[(int64_t)i * n + j] = v;
+}
+
+// One workgroup: in-place Cholesky of N (lower factor), then two triangular
+// solves for nrhs right-hand sides.
+__global__ __launch_bounds__(1024) void spd_solve_kernel(double* __restrict__ Nm, int n,
+                                                         double* __restrict__ Bm, int nrhs,
+                                                         int* info) {
+  __shared__ int bad;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      double dv = Nm[(int64_t)j * n + j];
+      if (!(dv > 0.0)) { bad = j + 1; dv = 1.0; }
+      Nm[(int64_t)j * n + j] = sqrt(dv);
+    }
+    __syncthreads();
+    const double ljj = Nm[(int64_t)j * n + j];
+    for (int i = j + 1 + tid; i < n; i += nt) Nm[(int64_t)i * n + j] /= ljj;
+    __syncthreads();
+    const int m = n - j - 1;
+    const int64_t tri = (int64_t)m * (m + 1) / 2;
+    for (int64_t e = tid; e < tri; e += nt) {
+      // e -> (ii, kk) with 0 <= kk <= ii < m (row-major lower triangle)
+      int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+      while ((int64_t)ii * (ii + 1) / 2 > e) --ii;
+      while ((int64_t)(ii + 1) * (ii + 2) / 2 <= e) ++ii;
+      int kk = (int)(e - (int64_t)ii * (ii + 1) / 2);
+      int gi = j + 1 + ii, gk = j + 1 + kk;
+      Nm[(int64_t)gi * n + gk] -= Nm[(int64_t)gi * n + j] * Nm[(int64_t)gk * n + j];
+    }
+    __syncthreads();
+  }
+  // forward: L y = b
+  for (int j = 0; j < n; ++j) {
+    const double ljj = Nm[(int64_t)j * n + j];
+    for (int c = tid; c < nrhs; c += nt) Bm[(int64_t)j * nrhs + c] /= ljj;
+    __syncthreads();
+    const int64_t tot = (int64_t)(n - j - 1) * nrhs;
+    for (int64_t e = tid; e < tot; e += nt) {
+      int i = j + 1 + (int)(e / nrhs), c = (int)(e % nrhs);
+      Bm[(int64_t)i * nrhs + c] -= Nm[(int64_t)i * n + j] * Bm[(int64_t)j * nrhs + c];
+    }
+    __syncthreads();
+  }
+  // backward: L^T x = y
+  for (int j = n - 1; j >= 0; --j) {
+    const double ljj = Nm[(int64_t)j * n + j];
+    for (int c = tid; c < nrhs; c += nt) Bm[(int64_t)j * nrhs + c] /= ljj;
+    __syncthreads();
+    const int64_t tot = (int64_t)j * nrhs;
+    for (int64_t e = tid; e < tot; e += nt) {
+      int i = (int)(e / nrhs), c = (int)(e % nrhs);
+      Bm[(int64_t)i * nrhs + c] -= Nm[(int64_t)j * n + i] * Bm[(int64_t)j * nrhs + c];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && bad && *info == 0) *info = bad;
+}
+
+__global__ void fill_f64_kernel(double* p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void fill_i32_kernel(int* p, int64_t n, int v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void cvt_kernel(const double* in, float* out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+template <typename T>
+__global__ void axpy_kernel(T* y, const T* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += x[i];
+}
+template <typename T>
+__global__ void nonfinite_kernel(const T* x, int64_t n, int* flag) {
+  int bad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite((double)x[i])) bad = 1;
+  if (bad) atomicOr(flag, 1);
+}
+
+__global__ void scale_kernel(double* X, int64_t rows, int64_t cols, const double* vr,
+                             const double* vc) {
+  const int64_t tot = rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double f = 1.0;
+    if (vr) f *= vr[e / cols];
+    if (vc) f *= vc[e % cols];
+    X[e] *= f;
+  }
+}
+
+inline int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t scale_cols(hipStream_t s, double* X, int64_t rows, int64_t cols, const double* v) {
+  hipLaunchKernelGGL(scale_kernel, dim3(grid_for(rows * cols)), dim3(256), 0, s, X, rows, cols,
+                     (const double*)nullptr, v);
+  return hipGetLastError();
+}
+hipError_t scale_rows(hipStream_t s, double* X, int64_t rows, int64_t cols, const double* v) {
+  hipLaunchKernelGGL(scale_kernel, dim3(grid_for(rows * cols)), dim3(256), 0, s, X, rows, cols, v,
+                     (const double*)nullptr);
+  return hipGetLastError();
+}
+hipError_t scale_rows_cols(hipStream_t s, double* X, int64_t n, const double* v) {
+  hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n * n)), dim3(256), 0, s, X, n, n, v, v);
+  return hipGetLastError();
+}
+
+hipError_t gemm_f64(hipStream_t s, int M, int N, int K, int batch, const double* A, int64_t sam,
+                    int64_t sak, int64_t sab, const double* B, int64_t sbk, int64_t sbn,
+                    int64_t sbb, double* C, int64_t scm, int64_t scn, int64_t scb,
+                    const double* d, double alpha, double beta) {
+  return gemm_launch<double>(s, M, N, K, batch, A, sam, sak, sab, B, sbk, sbn, sbb, C, scm, scn,
+                             scb, d, alpha, beta);
+}
+
+hipError_t gemm_f32in_f64(hipStream_t s, int M, int N, int K, int batch, const float* A,
+                          int64_t sam, int64_t sak, int64_t sab, const double* B, int64_t sbk,
+                          int64_t sbn, int64_t sbb, double* C, int64_t scm, int64_t scn,
+                          int64_t scb, const double* d, double alpha, double beta) {
+  return gemm_launch<float>(s, M, N, K, batch, A, sam, sak, sab, B, sbk, sbn, sbb, C, scm, scn,
+                            scb, d, alpha, beta);
+}
+
+hipError_t spd_invert(hipStream_t s, double* A, int n, double* work, int* info) {
+  double* row = work;
+  double* col = work + n;
+  for (int k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(gj_save, dim3((n + 255) / 256), dim3(256), 0, s, A, n, k, row, col);
+    hipLaunchKernelGGL(gj_update, dim3((n + 255) / 256, n), dim3(256), 0, s, A, n, k, row, col,
+                       info);
+  }
+  return hipGetLastError();
+}
+
+hipError_t spd_solve_small(hipStream_t s, double* N, int n, double* Bm, int nrhs, int* info) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(spd_solve_kernel, dim3(1), dim3(1024), 0, s, N, n, Bm, nrhs, info);
+  return hipGetLastError();
+}
+
+hipError_t fill_f64(hipStream_t s, double* p, int64_t n, double v) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t fill_i32(hipStream_t s, int* p, int64_t n, int v) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t convert_f64_to_f32(hipStream_t s, const double* in, float* out, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cvt_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+hipError_t axpy_acc(hipStream_t s, void* y, const void* x, int64_t n, bool f64) {
+  if (n <= 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(axpy_kernel<double>, dim3(grid_for(n)), dim3(256), 0, s, (double*)y,
+                       (const double*)x, n);
+  else
+    hipLaunchKernelGGL(axpy_kernel<float>, dim3(grid_for(n)), dim3(256), 0, s, (float*)y,
+                       (const float*)x, n);
+  return hipGetLastError();
+}
+hipError_t any_nonfinite(hipStream_t s, const void* x, int64_t n, bool f64, int* flag) {
+  if (n <= 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(nonfinite_kernel<double>, dim3(grid_for(n)), dim3(256), 0, s,
+                       (const double*)x, n, flag);
+  else
+    hipLaunchKernelGGL(nonfinite_kernel<float>, dim3(grid_for(n)), dim3(256), 0, s,
+                       (const float*)x, n, flag);
+  return hipGetLastError();
+}
+
+}  // namespace octen

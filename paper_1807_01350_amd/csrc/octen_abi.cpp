@@ -1,0 +1,595 @@
+// C ABI of libocten: argument validation, handle state and the sequence of
+// kernel launches for each step of the online update (Algorithm 1).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/octen.h"
+#include "octen_internal.h"
+
+using namespace octen;
+
+struct octen_ctx {
+  octen_config cfg;
+  int64_t I = 0, J = 0;
+  int R = 0, P = 0, Q = 0, S = 0, M1 = 0;
+  hipStream_t stream = nullptr;
+  bool acc_f64 = true;  // summaries (Y, Z) in f64, else f32
+  std::string err;
+
+  // state machine
+  bool z_ready = false;       // a compressed batch waits for octen_update_replicas
+  int64_t t_z = 0;            // depth of that batch
+  int64_t t_pend = 0;         // slices added since the last recovery
+  bool have_factors = false;  // replica factors exist
+  bool factors_fresh = false; // ALS ran after the last update
+  bool have_prev = false;     // a previous recovery exists (canonical A, B)
+  int64_t K = 0;              // slices recovered so far (rows of C)
+
+  // fixed operators
+  double *U = nullptr, *V = nullptr;       // [I][M1], [J][M1]
+  double *OpA = nullptr, *OpB = nullptr;   // [I][M1], [J][M1] least-squares operators
+  double *w = nullptr, *w2 = nullptr;      // [M1] row weights
+  MfmaPlan* plan = nullptr;
+
+  // summaries
+  void *Y = nullptr, *Z = nullptr;         // [P][Q][Q][Q]
+  // batch workspace
+  double* Wz = nullptr;   int64_t Wz_cap = 0;    // W of the compressed, not yet added batch
+  double* Wp = nullptr;   int64_t Wp_cap = 0;    // W rows of slices added since last recovery
+  double* T2 = nullptr;   int64_t T2_rows = 0;   // reference path workspace
+  double* Mk = nullptr;   int64_t Mk_cap = 0;    // [t][P][Q][Q] f64
+  void* mfma_work = nullptr; size_t mfma_work_bytes = 0;
+
+  // ALS
+  double *F = nullptr, *lam = nullptr;     // [P][3][Q][R], [P][R]
+  int *iters = nullptr, *flags = nullptr;  // [P]
+  // recovery
+  double *aligned = nullptr, *margin = nullptr, *rhs = nullptr, *rhs_c = nullptr;
+  int* perm = nullptr;
+  double *Araw = nullptr, *Braw = nullptr, *Ac = nullptr, *Bc = nullptr;
+  double *Aprev = nullptr, *Bprev = nullptr;
+  double *ka = nullptr, *kb = nullptr, *kappa = nullptr, *tsign = nullptr, *tmargin = nullptr;
+  int* tperm = nullptr;
+  double *cross = nullptr, *norms = nullptr;
+  double *H = nullptr, *Hcur = nullptr;
+  double *Chist = nullptr, *Ctmp = nullptr; int64_t C_cap = 0;
+  double *Nt = nullptr; int64_t Nt_cap = 0;      // temporal normal matrix
+  double *bt = nullptr; int64_t bt_cap = 0;      // temporal rhs / solution
+  int* info = nullptr;
+  // fit
+  double* partials = nullptr;
+  double* fit_out = nullptr;
+  double* gj_work = nullptr;
+
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+constexpr int FIT_PARTS = 2048;
+
+octen_status fail(octen_t h, octen_status st, const std::string& msg) {
+  if (h) h->err = msg;
+  return st;
+}
+
+#define HIPCHK(h, expr)                                                             \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail((h), OCTEN_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+octen_status dalloc(octen_t h, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) return fail(h, OCTEN_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  h->allocs.push_back(q);
+  *p = (T*)q;
+  return OCTEN_OK;
+}
+
+void dfree(octen_t h, void* p) {
+  if (!p) return;
+  for (auto& a : h->allocs)
+    if (a == p) { hipFree(p); a = nullptr; return; }
+}
+
+// grow a device array to at least `count` elements (contents discarded)
+template <typename T>
+octen_status dgrow(octen_t h, T** p, int64_t* cap, int64_t count) {
+  if (*p && *cap >= count) return OCTEN_OK;
+  if (*p) { hipStreamSynchronize(h->stream); dfree(h, *p); *p = nullptr; }
+  int64_t n = count < 1 ? 1 : count;
+  octen_status st = dalloc(h, p, (size_t)n);
+  if (st == OCTEN_OK) *cap = n;
+  return st;
+}
+
+#define OKCHK(expr)                      \
+  do {                                   \
+    octen_status s_ = (expr);            \
+    if (s_ != OCTEN_OK) return s_;       \
+  } while (0)
+
+bool valid_dtype_x(int d) { return d == OCTEN_F64 || d == OCTEN_F32; }
+
+octen_status validate(const octen_config* c, std::string* msg) {
+  if (!c) { *msg = "config is NULL"; return OCTEN_ERR_ARG; }
+  if (c->abi_version != OCTEN_ABI_VERSION) { *msg = "ABI version mismatch"; return OCTEN_ERR_ARG; }
+  if (c->I < 1 || c->J < 1) { *msg = "I and J must be >= 1"; return OCTEN_ERR_ARG; }
+  if (c->I > (1LL << 30) || c->J > (1LL << 30)) { *msg = "I or J too large"; return OCTEN_ERR_ARG; }
+  if (c->R < 1 || c->R > 32) { *msg = "R must be in [1, 32]"; return OCTEN_ERR_ARG; }
+  if (c->P < 1) { *msg = "P must be >= 1"; return OCTEN_ERR_ARG; }
+  if (c->S < 1) { *msg = "S must be >= 1 (anchor rows are needed for matching)"; return OCTEN_ERR_ARG; }
+  if (c->Q <= c->S || c->Q > 128) { *msg = "Q must satisfy S < Q <= 128"; return OCTEN_ERR_ARG; }
+  if (c->R > c->Q) { *msg = "R must be <= Q"; return OCTEN_ERR_ARG; }
+  if (!valid_dtype_x(c->x_dtype)) { *msg = "x_dtype must be F64 or F32"; return OCTEN_ERR_ARG; }
+  if (c->compress_dtype != OCTEN_F64 && c->compress_dtype != OCTEN_F32 &&
+      c->compress_dtype != OCTEN_BF16) {
+    *msg = "compress_dtype must be F64, F32 or BF16";
+    return OCTEN_ERR_UNSUPPORTED;
+  }
+  if (c->compress_dtype == OCTEN_F64 && c->x_dtype != OCTEN_F64) {
+    // f32 slices with f64 arithmetic are allowed (exact upcast)
+  }
+  if (c->compress_dtype != OCTEN_F64 && c->x_dtype == OCTEN_F64) {
+    *msg = "narrow compression needs f32 slices";
+    return OCTEN_ERR_UNSUPPORTED;
+  }
+  if (c->als_dtype != OCTEN_F64 && c->als_dtype != OCTEN_F32) {
+    *msg = "als_dtype must be F64 or F32";
+    return OCTEN_ERR_UNSUPPORTED;
+  }
+  int64_t M1 = (int64_t)c->S + (int64_t)c->P * (c->Q - c->S);
+  if (M1 > (1 << 20)) { *msg = "too many compression columns"; return OCTEN_ERR_ARG; }
+  return OCTEN_OK;
+}
+
+// Least-squares operator of Eq. 7 for a fixed deduplicated compression matrix
+// Pt (n x M1): the minimum-norm solution of the sqrt(P)-weighted stack is
+// x = Op * rhs with Op (n x M1) built once here.
+octen_status build_operator(octen_t h, const double* Pt, int64_t n, double* Op) {
+  hipStream_t s = h->stream;
+  const int M1 = h->M1;
+  double* N = nullptr;
+  if (n <= M1) {
+    OKCHK(dalloc(h, &N, (size_t)(n * n)));
+    HIPCHK(h, gemm_f64(s, (int)n, (int)n, M1, 1, Pt, M1, 1, 0, Pt, 1, M1, 0, N, n, 1, 0, h->w2,
+                       1.0, 0.0));
+    HIPCHK(h, spd_invert(s, N, (int)n, h->gj_work, h->info));
+    HIPCHK(h, gemm_f64(s, (int)n, M1, (int)n, 1, N, n, 1, 0, Pt, M1, 1, 0, Op, M1, 1, 0, nullptr,
+                       1.0, 0.0));
+    HIPCHK(h, scale_cols(s, Op, n, M1, h->w2));
+  } else {
+    OKCHK(dalloc(h, &N, (size_t)M1 * M1));
+    HIPCHK(h, gemm_f64(s, M1, M1, (int)n, 1, Pt, 1, M1, 0, Pt, M1, 1, 0, N, M1, 1, 0, nullptr, 1.0,
+                       0.0));
+    HIPCHK(h, scale_rows_cols(s, N, M1, h->w));
+    HIPCHK(h, spd_invert(s, N, M1, h->gj_work, h->info));
+    HIPCHK(h, gemm_f64(s, (int)n, M1, M1, 1, Pt, M1, 1, 0, N, M1, 1, 0, Op, M1, 1, 0, h->w, 1.0,
+                       0.0));
+    HIPCHK(h, scale_cols(s, Op, n, M1, h->w));
+  }
+  HIPCHK(h, hipStreamSynchronize(s));
+  dfree(h, N);
+  return OCTEN_OK;
+}
+
+int host_info(octen_t h) {
+  int v = 0;
+  hipMemcpyAsync(&v, h->info, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  hipStreamSynchronize(h->stream);
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t octen_abi_version(void) { return OCTEN_ABI_VERSION; }
+
+const char* octen_status_str(octen_status s) {
+  switch (s) {
+    case OCTEN_OK: return "ok";
+    case OCTEN_ERR_ARG: return "invalid argument";
+    case OCTEN_ERR_STATE: return "call out of order";
+    case OCTEN_ERR_HIP: return "HIP runtime error";
+    case OCTEN_ERR_NOMEM: return "out of device memory";
+    case OCTEN_ERR_NUMERIC: return "numerical failure";
+    case OCTEN_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* octen_last_error(octen_t h) { return h ? h->err.c_str() : "null handle"; }
+
+octen_status octen_check_identifiable(const octen_config* cfg, int64_t K, int64_t t,
+                                      int32_t* bits_host, double* p_min_host) {
+  std::string msg;
+  octen_status st = validate(cfg, &msg);
+  if (st != OCTEN_OK) return st;
+  if (K < 0 || t < 0 || !bits_host) return OCTEN_ERR_ARG;
+  const double I = (double)cfg->I, J = (double)cfg->J, Q = cfg->Q, S = cfg->S;
+  // Eq. 8 as printed: p >= max((I - shared)/(Q - shared), J/Q, K/Q)
+  double pmin = (I - S) / (Q - S);
+  if (J / Q > pmin) pmin = J / Q;
+  if ((double)K / Q > pmin) pmin = (double)K / Q;
+  const int64_t M1 = (int64_t)cfg->S + (int64_t)cfg->P * (cfg->Q - cfg->S);
+  int32_t bits = 0;
+  if ((double)cfg->P >= ceil(pmin - 1e-12)) bits |= 1;
+  if (M1 >= cfg->I) bits |= 2;
+  if (M1 >= cfg->J) bits |= 4;
+  if (M1 >= t) bits |= 8;
+  auto mn = [](int64_t a, int64_t b) { return a < b ? a : b; };
+  const int64_t R = cfg->R;
+  const int64_t kr = mn(cfg->Q, mn(cfg->I, R)) + mn(cfg->Q, mn(cfg->J, R)) + mn(cfg->Q, mn(K, R));
+  if (kr >= 2 * R + 2) bits |= 16;
+  *bits_host = bits;
+  if (p_min_host) *p_min_host = pmin;
+  return OCTEN_OK;
+}
+
+octen_status octen_init(const octen_config* cfg, const double* U, const double* V, void* stream,
+                        octen_t* out) {
+  if (!out) return OCTEN_ERR_ARG;
+  *out = nullptr;
+  std::string msg;
+  octen_status st = validate(cfg, &msg);
+  if (st != OCTEN_OK) return st;
+  if (!U || !V) return OCTEN_ERR_ARG;
+  octen_t h = new octen_ctx();
+  h->cfg = *cfg;
+  h->I = cfg->I; h->J = cfg->J; h->R = cfg->R; h->P = cfg->P; h->Q = cfg->Q; h->S = cfg->S;
+  h->M1 = h->S + h->P * (h->Q - h->S);
+  h->stream = (hipStream_t)stream;
+  h->acc_f64 = cfg->compress_dtype == OCTEN_F64;
+  const int64_t I = h->I, J = h->J, M1 = h->M1, P = h->P, Q = h->Q, R = h->R;
+  const int64_t Q3 = Q * Q * Q;
+  const size_t accsz = h->acc_f64 ? 8 : 4;
+  auto bail = [&](octen_status s2) { octen_destroy(h); return s2; };
+#define IOK(expr)                       \
+  do {                                  \
+    octen_status s_ = (expr);           \
+    if (s_ != OCTEN_OK) return bail(s_); \
+  } while (0)
+  IOK(dalloc(h, &h->U, I * M1));
+  IOK(dalloc(h, &h->V, J * M1));
+  IOK(dalloc(h, &h->OpA, I * M1));
+  IOK(dalloc(h, &h->OpB, J * M1));
+  IOK(dalloc(h, &h->w, M1));
+  IOK(dalloc(h, &h->w2, M1));
+  IOK(dalloc(h, (char**)&h->Y, P * Q3 * accsz));
+  IOK(dalloc(h, (char**)&h->Z, P * Q3 * accsz));
+  IOK(dalloc(h, &h->F, P * 3 * Q * R));
+  IOK(dalloc(h, &h->lam, P * R));
+  IOK(dalloc(h, &h->iters, P));
+  IOK(dalloc(h, &h->flags, P));
+  IOK(dalloc(h, &h->aligned, P * 3 * Q * R));
+  IOK(dalloc(h, &h->margin, P));
+  IOK(dalloc(h, &h->perm, P * R));
+  IOK(dalloc(h, &h->rhs, 3 * M1 * R));
+  IOK(dalloc(h, &h->rhs_c, M1 * R));
+  IOK(dalloc(h, &h->Araw, I * R));
+  IOK(dalloc(h, &h->Braw, J * R));
+  IOK(dalloc(h, &h->Ac, I * R));
+  IOK(dalloc(h, &h->Bc, J * R));
+  IOK(dalloc(h, &h->Aprev, I * R));
+  IOK(dalloc(h, &h->Bprev, J * R));
+  IOK(dalloc(h, &h->ka, R));
+  IOK(dalloc(h, &h->kb, R));
+  IOK(dalloc(h, &h->kappa, R));
+  IOK(dalloc(h, &h->tsign, R));
+  IOK(dalloc(h, &h->tmargin, 1));
+  IOK(dalloc(h, &h->tperm, R));
+  IOK(dalloc(h, &h->cross, 2 * R * R));
+  IOK(dalloc(h, &h->norms, 4 * R));
+  IOK(dalloc(h, &h->H, M1 * R));
+  IOK(dalloc(h, &h->Hcur, M1 * R));
+  IOK(dalloc(h, &h->info, 1));
+  IOK(dalloc(h, &h->partials, 2 * FIT_PARTS));
+  IOK(dalloc(h, &h->fit_out, 2));
+  IOK(dalloc(h, &h->gj_work, 2 * (I > J ? (I > M1 ? I : M1) : (J > M1 ? J : M1))));
+  hipStream_t s = h->stream;
+  auto hip_ok = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess) { h->err = std::string(what) + ": " + hipGetErrorString(e); return false; }
+    return true;
+  };
+  if (!hip_ok(hipMemcpyAsync(h->U, U, I * M1 * 8, hipMemcpyDeviceToDevice, s), "copy U") ||
+      !hip_ok(hipMemcpyAsync(h->V, V, J * M1 * 8, hipMemcpyDeviceToDevice, s), "copy V") ||
+      !hip_ok(hipMemsetAsync(h->Y, 0, P * Q3 * accsz, s), "zero Y") ||
+      !hip_ok(hipMemsetAsync(h->Z, 0, P * Q3 * accsz, s), "zero Z") ||
+      !hip_ok(hipMemsetAsync(h->H, 0, M1 * R * 8, s), "zero H") ||
+      !hip_ok(hipMemsetAsync(h->info, 0, sizeof(int), s), "zero info") ||
+      !hip_ok(hipMemsetAsync(h->flags, 0, P * sizeof(int), s), "zero flags") ||
+      !hip_ok(rec_weights(s, (int)M1, h->S, (int)P, h->w, h->w2), "weights")) {
+    octen_destroy(h);
+    return OCTEN_ERR_HIP;
+  }
+  {
+    std::vector<int> ident(R);
+    std::vector<double> ones(R, 1.0);
+    for (int r = 0; r < R; ++r) ident[r] = r;
+    if (!hip_ok(hipMemcpy(h->tperm, ident.data(), R * sizeof(int), hipMemcpyHostToDevice), "tperm") ||
+        !hip_ok(hipMemcpy(h->tsign, ones.data(), R * sizeof(double), hipMemcpyHostToDevice), "tsign")) {
+      octen_destroy(h);
+      return OCTEN_ERR_HIP;
+    }
+  }
+  IOK(build_operator(h, h->U, I, h->OpA));
+  IOK(build_operator(h, h->V, J, h->OpB));
+  if (host_info(h) != 0) {
+    octen_destroy(h);
+    return OCTEN_ERR_NUMERIC;
+  }
+  if (h->cfg.compress_dtype != OCTEN_F64 && !(h->cfg.flags & OCTEN_FLAG_REFERENCE_PATH)) {
+    CompressShape sh{I, J, (int)P, (int)Q, h->S, (int)M1};
+    hipError_t e = mfma_plan_create(sh, h->cfg.compress_dtype == OCTEN_BF16 ? 2 : 1, h->U, h->V, s,
+                                    &h->plan);
+    if (e != hipSuccess) {
+      h->err = std::string("mfma plan: ") + hipGetErrorString(e);
+      octen_destroy(h);
+      return e == hipErrorNotSupported ? OCTEN_ERR_UNSUPPORTED : OCTEN_ERR_HIP;
+    }
+  }
+#undef IOK
+  *out = h;
+  return OCTEN_OK;
+}
+
+octen_status octen_destroy(octen_t h) {
+  if (!h) return OCTEN_ERR_ARG;
+  hipStreamSynchronize(h->stream);
+  if (h->plan) mfma_plan_destroy(h->plan);
+  for (void* p : h->allocs)
+    if (p) hipFree(p);
+  delete h;
+  return OCTEN_OK;
+}
+
+octen_status octen_compress_batch(octen_t h, const void* X, int64_t t, const double* W,
+                                  const float* slice_scale) {
+  if (!h) return OCTEN_ERR_ARG;
+  if (!X || !W || t < 1) return fail(h, OCTEN_ERR_ARG, "X, W must be non-null and t >= 1");
+  if (t > (1 << 24)) return fail(h, OCTEN_ERR_ARG, "t too large");
+  hipStream_t s = h->stream;
+  const int64_t I = h->I, J = h->J, M1 = h->M1;
+  CompressShape sh{I, J, h->P, h->Q, h->S, h->M1};
+  OKCHK(dgrow(h, &h->Wz, &h->Wz_cap, t * M1));
+  HIPCHK(h, hipMemcpyAsync(h->Wz, W, t * M1 * 8, hipMemcpyDeviceToDevice, s));
+  const bool x_f64 = h->cfg.x_dtype == OCTEN_F64;
+  if (h->plan) {
+    size_t need = mfma_workspace_bytes(h->plan, t);
+    if (need > h->mfma_work_bytes) {
+      if (h->mfma_work) { hipStreamSynchronize(s); dfree(h, h->mfma_work); h->mfma_work = nullptr; }
+      OKCHK(dalloc(h, (char**)&h->mfma_work, need));
+      h->mfma_work_bytes = need;
+    }
+    HIPCHK(h, compress_mfma(s, h->plan, (const float*)X, t, slice_scale, h->Wz, h->mfma_work,
+                            (float*)h->Z));
+  } else {
+    // reference path: T2 chunk of at most ~64 Mi doubles
+    int64_t rows_cap = (int64_t)1 << 26;
+    rows_cap /= M1;
+    if (rows_cap < I) rows_cap = I;
+    int64_t want = rows_cap < t * I ? rows_cap : t * I;
+    want = (want / I) * I;
+    OKCHK(dgrow(h, &h->T2, &h->T2_rows, want * M1));
+    OKCHK(dgrow(h, &h->Mk, &h->Mk_cap, t * h->P * h->Q * h->Q));
+    HIPCHK(h, compress_reference(s, sh, X, x_f64, t, h->U, h->V, h->Wz, h->T2, h->T2_rows / M1,
+                                 h->Mk, h->Z, h->acc_f64));
+  }
+  h->z_ready = true;
+  h->t_z = t;
+  return OCTEN_OK;
+}
+
+octen_status octen_compress_batch_coo(octen_t h, int64_t nnz, const int32_t* k, const int32_t* i,
+                                      const int32_t* j, const float* v, int64_t t, const double* W) {
+  if (!h) return OCTEN_ERR_ARG;
+  (void)nnz; (void)k; (void)i; (void)j; (void)v; (void)t; (void)W;
+  return fail(h, OCTEN_ERR_UNSUPPORTED, "sparse compression not built yet");
+}
+
+octen_status octen_update_replicas(octen_t h) {
+  if (!h) return OCTEN_ERR_ARG;
+  if (!h->z_ready) return fail(h, OCTEN_ERR_STATE, "update before compress");
+  hipStream_t s = h->stream;
+  const int64_t n = (int64_t)h->P * h->Q * h->Q * h->Q;
+  HIPCHK(h, axpy_acc(s, h->Y, h->Z, n, h->acc_f64));
+  // append this batch's W rows to the pending temporal block
+  const int64_t M1 = h->M1;
+  if (h->t_pend + h->t_z > h->Wp_cap / (M1 > 0 ? M1 : 1)) {
+    double* nw = nullptr;
+    const int64_t cap = (h->t_pend + h->t_z) * 2 * M1;
+    OKCHK(dalloc(h, &nw, cap));
+    if (h->t_pend > 0)
+      HIPCHK(h, hipMemcpyAsync(nw, h->Wp, h->t_pend * M1 * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    dfree(h, h->Wp);
+    h->Wp = nw;
+    h->Wp_cap = cap;
+  }
+  HIPCHK(h, hipMemcpyAsync(h->Wp + h->t_pend * M1, h->Wz, h->t_z * M1 * 8,
+                           hipMemcpyDeviceToDevice, s));
+  h->t_pend += h->t_z;
+  h->z_ready = false;
+  h->factors_fresh = false;
+  return OCTEN_OK;
+}
+
+octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int32_t init_mode,
+                                   const double* init, int32_t* iters_done_host) {
+  if (!h) return OCTEN_ERR_ARG;
+  if (max_iters < 1) return fail(h, OCTEN_ERR_ARG, "max_iters must be >= 1");
+  if (!(tol >= 0.0)) return fail(h, OCTEN_ERR_ARG, "tol must be >= 0");
+  if (h->K + h->t_pend == 0) return fail(h, OCTEN_ERR_STATE, "no summaries yet");
+  const double* src;
+  if (init_mode == OCTEN_INIT_GIVEN) {
+    if (!init) return fail(h, OCTEN_ERR_ARG, "init is NULL with OCTEN_INIT_GIVEN");
+    src = init;
+  } else if (init_mode == OCTEN_INIT_PREV) {
+    if (!h->have_factors) return fail(h, OCTEN_ERR_STATE, "no previous factors");
+    src = h->F;
+  } else {
+    return fail(h, OCTEN_ERR_ARG, "unknown init_mode");
+  }
+  hipStream_t s = h->stream;
+  HIPCHK(h, fill_i32(s, h->flags, h->P, 0));
+  HIPCHK(h, als_reference(s, h->Y, h->acc_f64, h->P, h->Q, h->R, src, h->F, h->lam, h->iters,
+                          h->flags, max_iters, tol));
+  h->have_factors = true;
+  h->factors_fresh = true;
+  if (iters_done_host) {
+    HIPCHK(h, hipMemcpyAsync(iters_done_host, h->iters, h->P * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+  }
+  return OCTEN_OK;
+}
+
+octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, int64_t c_capacity,
+                                   int64_t* K_out_host) {
+  if (!h) return OCTEN_ERR_ARG;
+  if (!A || !B || !C) return fail(h, OCTEN_ERR_ARG, "A, B, C must be non-null");
+  if (!h->factors_fresh || h->t_pend == 0)
+    return fail(h, OCTEN_ERR_STATE, "recover needs ALS after the latest update");
+  const int64_t Knew = h->K + h->t_pend;
+  if (c_capacity < Knew) return fail(h, OCTEN_ERR_ARG, "C capacity smaller than K");
+  hipStream_t s = h->stream;
+  const int P = h->P, Q = h->Q, R = h->R, S = h->S, M1 = h->M1;
+  const int64_t I = h->I, J = h->J, t = h->t_pend;
+  // Sec. 4.2: align replicas; Eq. 5 stack
+  HIPCHK(h, rec_align(s, P, Q, R, S, h->F, h->lam, h->aligned, h->perm, h->margin));
+  HIPCHK(h, rec_stack(s, P, Q, R, S, h->aligned, h->rhs));
+  // Eq. 7 for modes 1 and 2
+  HIPCHK(h, gemm_f64(s, (int)I, R, M1, 1, h->OpA, M1, 1, 0, h->rhs, R, 1, 0, h->Araw, R, 1, 0,
+                     nullptr, 1.0, 0.0));
+  HIPCHK(h, gemm_f64(s, (int)J, R, M1, 1, h->OpB, M1, 1, 0, h->rhs + (int64_t)M1 * R, R, 1, 0,
+                     h->Braw, R, 1, 0, nullptr, 1.0, 0.0));
+  HIPCHK(h, rec_canon(s, I, R, h->Araw, h->Ac, h->ka));
+  HIPCHK(h, rec_canon(s, J, R, h->Braw, h->Bc, h->kb));
+  if (h->have_prev) {
+    HIPCHK(h, gemm_f64(s, R, R, (int)I, 1, h->Ac, 1, R, 0, h->Aprev, R, 1, 0, h->cross, R, 1, 0,
+                       nullptr, 1.0, 0.0));
+    HIPCHK(h, gemm_f64(s, R, R, (int)J, 1, h->Bc, 1, R, 0, h->Bprev, R, 1, 0, h->cross + R * R, R,
+                       1, 0, nullptr, 1.0, 0.0));
+    HIPCHK(h, rec_col_norms(s, I, R, h->Ac, h->norms));
+    HIPCHK(h, rec_col_norms(s, I, R, h->Aprev, h->norms + R));
+    HIPCHK(h, rec_col_norms(s, J, R, h->Bc, h->norms + 2 * R));
+    HIPCHK(h, rec_col_norms(s, J, R, h->Bprev, h->norms + 3 * R));
+    HIPCHK(h, rec_tmatch(s, R, h->cross, h->norms, h->tperm, h->tsign, h->tmargin));
+  }
+  // temporal rows (reading: incremental solve with the carried history removed)
+  const double* rhs2 = h->rhs + 2 * (int64_t)M1 * R;
+  HIPCHK(h, rec_temporal_prep(s, M1, R, h->H, h->tperm, h->tsign, h->ka, h->kb, h->kappa, h->Hcur,
+                              rhs2, h->rhs_c, h->have_prev ? 1 : 0));
+  OKCHK(dgrow(h, &h->bt, &h->bt_cap, (t > M1 ? t : (int64_t)M1) * R));
+  if (t <= M1) {
+    OKCHK(dgrow(h, &h->Nt, &h->Nt_cap, t * t));
+    HIPCHK(h, gemm_f64(s, (int)t, (int)t, M1, 1, h->Wp, M1, 1, 0, h->Wp, 1, M1, 0, h->Nt, t, 1, 0,
+                       h->w2, 1.0, 0.0));
+    HIPCHK(h, gemm_f64(s, (int)t, R, M1, 1, h->Wp, M1, 1, 0, h->rhs_c, R, 1, 0, h->bt, R, 1, 0,
+                       h->w2, 1.0, 0.0));
+    HIPCHK(h, spd_solve_small(s, h->Nt, (int)t, h->bt, R, h->info));
+  } else {
+    OKCHK(dgrow(h, &h->Nt, &h->Nt_cap, (int64_t)M1 * M1 + (int64_t)M1 * R));
+    double* y = h->Nt + (int64_t)M1 * M1;
+    HIPCHK(h, gemm_f64(s, M1, M1, (int)t, 1, h->Wp, 1, M1, 0, h->Wp, M1, 1, 0, h->Nt, M1, 1, 0,
+                       nullptr, 1.0, 0.0));
+    HIPCHK(h, scale_rows_cols(s, h->Nt, M1, h->w));
+    HIPCHK(h, hipMemcpyAsync(y, h->rhs_c, (size_t)M1 * R * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, scale_rows(s, y, M1, R, h->w));
+    HIPCHK(h, spd_solve_small(s, h->Nt, M1, y, R, h->info));
+    HIPCHK(h, gemm_f64(s, (int)t, R, M1, 1, h->Wp, M1, 1, 0, y, R, 1, 0, h->bt, R, 1, 0, h->w, 1.0,
+                       0.0));
+  }
+  if (h->C_cap < Knew * R) {
+    int64_t cap = Knew * R * 2;
+    double *nc = nullptr, *nt = nullptr;
+    OKCHK(dalloc(h, &nc, cap));
+    OKCHK(dalloc(h, &nt, cap));
+    if (h->K > 0)
+      HIPCHK(h, hipMemcpyAsync(nc, h->Chist, h->K * R * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    dfree(h, h->Chist);
+    dfree(h, h->Ctmp);
+    h->Chist = nc;
+    h->Ctmp = nt;
+    h->C_cap = cap;
+  }
+  HIPCHK(h, rec_temporal_finish(s, R, h->K, t, h->kappa, h->tperm, h->tsign, h->bt, h->Chist,
+                                h->Ctmp, h->have_prev ? 1 : 0));
+  // H = Hcur + W^T C_new (canonical convention)
+  HIPCHK(h, hipMemcpyAsync(h->H, h->Hcur, (size_t)M1 * R * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, gemm_f64(s, M1, R, (int)t, 1, h->Wp, 1, M1, 0, h->bt, R, 1, 0, h->H, R, 1, 0, nullptr,
+                     1.0, 1.0));
+  HIPCHK(h, hipMemcpyAsync(h->Aprev, h->Ac, I * R * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->Bprev, h->Bc, J * R * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(A, h->Ac, I * R * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(B, h->Bc, J * R * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(C, h->Chist, Knew * R * 8, hipMemcpyDeviceToDevice, s));
+  h->K = Knew;
+  h->t_pend = 0;
+  h->have_prev = true;
+  h->factors_fresh = false;
+  if (K_out_host) {
+    HIPCHK(h, hipStreamSynchronize(s));
+    *K_out_host = h->K;
+  }
+  return OCTEN_OK;
+}
+
+octen_status octen_fit(octen_t h, const void* X, int64_t t, int64_t k0, const double* A,
+                       const double* B, const double* C, double* out_host) {
+  if (!h) return OCTEN_ERR_ARG;
+  if (!X || !A || !B || !C || !out_host || t < 1 || k0 < 0)
+    return fail(h, OCTEN_ERR_ARG, "bad fit arguments");
+  hipStream_t s = h->stream;
+  int64_t rows = t * h->I;
+  int parts = rows < FIT_PARTS ? (int)rows : FIT_PARTS;
+  HIPCHK(h, fit_dense(s, X, h->cfg.x_dtype == OCTEN_F64, t, h->I, h->J, h->R, k0, A, B, C,
+                      h->partials, parts, h->fit_out));
+  double o[2];
+  HIPCHK(h, hipMemcpyAsync(o, h->fit_out, sizeof(o), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  out_host[0] += o[0];
+  out_host[1] += o[1];
+  return OCTEN_OK;
+}
+
+octen_status octen_get_state(octen_t h, int32_t what, void* dst, size_t bytes) {
+  if (!h) return OCTEN_ERR_ARG;
+  if (!dst) return fail(h, OCTEN_ERR_ARG, "dst is NULL");
+  const int64_t P = h->P, Q = h->Q, R = h->R, M1 = h->M1;
+  const void* src = nullptr;
+  size_t n = 0;
+  const size_t acc = h->acc_f64 ? 8 : 4;
+  switch (what) {
+    case OCTEN_STATE_Y: src = h->Y; n = P * Q * Q * Q * acc; break;
+    case OCTEN_STATE_Z: src = h->Z; n = P * Q * Q * Q * acc; break;
+    case OCTEN_STATE_FACTORS: src = h->F; n = P * 3 * Q * R * 8; break;
+    case OCTEN_STATE_LAMBDA: src = h->lam; n = P * R * 8; break;
+    case OCTEN_STATE_PERM: src = h->perm; n = P * R * 4; break;
+    case OCTEN_STATE_ALIGNED: src = h->aligned; n = P * 3 * Q * R * 8; break;
+    case OCTEN_STATE_RHS: src = h->rhs; n = 3 * M1 * R * 8; break;
+    case OCTEN_STATE_H: src = h->H; n = M1 * R * 8; break;
+    case OCTEN_STATE_TPERM: src = h->tperm; n = R * 4; break;
+    case OCTEN_STATE_ITERS: src = h->iters; n = P * 4; break;
+    case OCTEN_STATE_MARGIN: src = h->margin; n = P * 8; break;
+    case OCTEN_STATE_FLAGS: src = h->flags; n = P * 4; break;
+    default: return fail(h, OCTEN_ERR_ARG, "unknown state id");
+  }
+  if (bytes < n) return fail(h, OCTEN_ERR_ARG, "destination too small");
+  HIPCHK(h, hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, h->stream));
+  return OCTEN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Internal declarations shared by the HIP translation units of libocten.
+// Every launcher enqueues on the given stream and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace octen {
+
+// ---------------------------------------------------------------- linalg ---
+// C[b] = alpha * opA[b] * diag(d) * opB[b] + beta * C[b]   (f64 accumulate)
+// A element (m, k) at A[b*sab + m*sam + k*sak]; B element (k, n) at
+// B[b*sbb + k*sbk + n*sbn]; C element (m, n) at C[b*scb + m*scm + n*scn].
+// d may be null (identity).  beta == 0 never reads C.
+hipError_t gemm_f64(hipStream_t s, int M, int N, int K, int batch,
+                    const double* A, int64_t sam, int64_t sak, int64_t sab,
+                    const double* B, int64_t sbk, int64_t sbn, int64_t sbb,
+                    double* C, int64_t scm, int64_t scn, int64_t scb,
+                    const double* d, double alpha, double beta);
+hipError_t gemm_f32in_f64(hipStream_t s, int M, int N, int K, int batch,
+                          const float* A, int64_t sam, int64_t sak, int64_t sab,
+                          const double* B, int64_t sbk, int64_t sbn, int64_t sbb,
+                          double* C, int64_t scm, int64_t scn, int64_t scb,
+                          const double* d, double alpha, double beta);
+
+// In-place inverse of an n x n symmetric positive definite matrix (leading
+// dimension n) by Gauss-Jordan elimination without pivoting; work: 2n doubles.
+// info (device int) is set to k+1 if pivot k is not positive.
+hipError_t spd_invert(hipStream_t s, double* A, int n, double* work, int* info);
+
+// One-workgroup Cholesky solve of N X = Bm (N: n x n, Bm: n x nrhs, both
+// row-major, overwritten: N by its factor, Bm by the solution).
+hipError_t spd_solve_small(hipStream_t s, double* N, int n, double* Bm, int nrhs, int* info);
+
+hipError_t fill_f64(hipStream_t s, double* p, int64_t n, double v);
+hipError_t fill_i32(hipStream_t s, int* p, int64_t n, int v);
+hipError_t convert_f64_to_f32(hipStream_t s, const double* in, float* out, int64_t n);
+// y[i] += x[i]
+hipError_t axpy_acc(hipStream_t s, void* y, const void* x, int64_t n, bool f64);
+hipError_t any_nonfinite(hipStream_t s, const void* x, int64_t n, bool f64, int* flag);
+// X[i][j] *= v[j] (rows x cols)
+hipError_t scale_cols(hipStream_t s, double* X, int64_t rows, int64_t cols, const double* v);
+// X[i][j] *= v[i] * v[j] (n x n)
+hipError_t scale_rows_cols(hipStream_t s, double* X, int64_t n, const double* v);
+// X[i][j] *= v[i] (rows x cols)
+hipError_t scale_rows(hipStream_t s, double* X, int64_t rows, int64_t cols, const double* v);
+
+// ----------------------------------------------------------- compression ---
+struct CompressShape {
+  int64_t I, J;
+  int P, Q, S, M1;
+};
+// Generic FP64-accumulating compression (reference path, any dtype of X):
+// M[k][p][Q][Q] for k in [0, t) via T2 = X V (chunked), then
+// Z[p] = sum_k M[k][p] (x) W_p(k, :).
+hipError_t compress_reference(hipStream_t s, const CompressShape& sh, const void* X, bool x_f64,
+                              int64_t t, const double* U, const double* V, const double* W,
+                              double* T2work, int64_t t2_rows_cap, double* Mwork, void* Z,
+                              bool z_f64);
+
+// Mode-3 product and store: Z[p][a][b][c] = sum_k M[k][p][a][b] * W[k][col_p(c)].
+// M is f32 or f64 ([t][P][Q][Q]); Z f32 or f64; if accumulate, Y += result too.
+hipError_t compress_mode3(hipStream_t s, const CompressShape& sh, int64_t t, const void* M,
+                          bool m_f64, const double* W, void* Z, bool z_f64);
+
+// MFMA path (f32 or bf16 inputs, f32 accumulate) for dense f32 slices.
+struct MfmaPlan;
+hipError_t mfma_plan_create(const CompressShape& sh, int in_kind /*1=f32, 2=bf16*/, const double* U,
+                            const double* V, hipStream_t s, MfmaPlan** out);
+void mfma_plan_destroy(MfmaPlan* p);
+size_t mfma_workspace_bytes(const MfmaPlan* p, int64_t t);
+hipError_t compress_mfma(hipStream_t s, const MfmaPlan* plan, const float* X, int64_t t,
+                         const float* slice_scale, const double* W, void* work, float* Z);
+
+// ------------------------------------------------------------------- ALS ---
+// One workgroup per replica; Y is [P][Q][Q][Q] (f32 or f64).
+hipError_t als_reference(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int R,
+                         const double* init, double* F, double* lam, int* iters, int* flags,
+                         int max_iters, double tol);
+
+// -------------------------------------------------------------- recovery ---
+// lambda^(1/3), anchor similarity, exclusive greedy matching, scale alignment.
+hipError_t rec_align(hipStream_t s, int P, int Q, int R, int S, const double* F,
+                     const double* lam, double* aligned, int* perm, double* margin);
+// rhs[n][M1][R] from aligned [P][3][Q][R].
+hipError_t rec_stack(hipStream_t s, int P, int Q, int R, int S, const double* aligned, double* rhs);
+// Canonical columns: out = X / (norm * sign of largest-magnitude entry);
+// kfac[r] = norm * sign.  X, out: [n][R].
+hipError_t rec_canon(hipStream_t s, int64_t n, int R, const double* X, double* out, double* kfac);
+// Pairing with the previous canonical factors: cross [2][R][R] = (Ac^T Ap, Bc^T Bp),
+// norms [4][R] = column norms of Ac, Ap, Bc, Bp.  Writes tperm, tsign.
+hipError_t rec_col_norms(hipStream_t s, int64_t n, int R, const double* X, double* norms);
+hipError_t rec_tmatch(hipStream_t s, int R, const double* cross, const double* norms, int* tperm,
+                      double* tsign, double* tmargin);
+// Hcur = H[:, tperm] * tsign; rhs_c = rhs2 - Hcur / kappa; kappa = ka * kb.
+hipError_t rec_temporal_prep(hipStream_t s, int M1, int R, const double* H, const int* tperm,
+                             const double* tsign, const double* ka, const double* kb, double* kappa,
+                             double* Hcur, const double* rhs2, double* rhs_c, int have_prev);
+// Cnew *= kappa (column scaling), Chist rows [0, Kold) permuted/sign-fixed via
+// tmp, Cnew appended at row Kold.
+hipError_t rec_temporal_finish(hipStream_t s, int R, int64_t Kold, int64_t t, const double* kappa,
+                               const int* tperm, const double* tsign, double* Cnew, double* Chist,
+                               double* tmp, int have_prev);
+// Row weights of the deduplicated stack: sqrt(P) on the first S rows.
+hipError_t rec_weights(hipStream_t s, int M1, int S, int P, double* w, double* w2);
+
+// ------------------------------------------------------------------- fit ---
+hipError_t fit_dense(hipStream_t s, const void* X, bool x_f64, int64_t t, int64_t I, int64_t J,
+                     int R, int64_t k0, const double* A, const double* B, const double* C,
+                     double* partials, int nparts, double* out2);
+
+}  // namespace octen

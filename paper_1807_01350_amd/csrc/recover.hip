@@ -1,0 +1,398 @@
+// Factor matching and recovery (Sec. 4.2, Eq. 5; Sec. 4.3, Eq. 6-7;
+// Algorithm 1 matching loop and final solve).  All FP64.
+//
+// Matching reads only the anchor rows (the first S rows of every replica
+// factor, produced by the shared compression columns of Eq. 1).  Pairing is
+// an exclusive greedy assignment done by one wavefront: each round every lane
+// scans a strided share of the free entries and a butterfly reduction picks
+// the maximum, ties going to the smallest reference column, then the
+// smallest replica column.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "octen_internal.h"
+
+namespace octen {
+
+namespace {
+
+constexpr int MAXR = 32;
+
+struct Cand {
+  double v;
+  int c, r;
+};
+
+__device__ __forceinline__ bool better(const Cand& a, const Cand& b) {
+  if (a.v > b.v) return true;
+  if (a.v == b.v) return a.c < b.c || (a.c == b.c && a.r < b.r);
+  return false;
+}
+
+__device__ __forceinline__ Cand wave_best(Cand x) {
+  for (int off = 32; off > 0; off >>= 1) {
+    Cand y;
+    y.v = __shfl_xor(x.v, off, 64);
+    y.c = __shfl_xor(x.c, off, 64);
+    y.r = __shfl_xor(x.r, off, 64);
+    if (better(y, x)) x = y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    double o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Exclusive greedy assignment on sim[r][c] (R x R in LDS) by one wavefront of
+// 64 lanes.  perm[r] = c.  Returns the smallest gap between a chosen entry and
+// its best free competitor in the same row or column (+inf if none).
+__device__ double greedy_wave(const double* sim, int R, int* perm, int* rowfree, int* colfree) {
+  const int lane = threadIdx.x;
+  for (int e = lane; e < R; e += 64) { rowfree[e] = 1; colfree[e] = 1; perm[e] = -1; }
+  __syncthreads();
+  double margin = INFINITY;
+  for (int round = 0; round < R; ++round) {
+    Cand best{-INFINITY, 1 << 30, 1 << 30};
+    for (int e = lane; e < R * R; e += 64) {
+      const int r = e / R, c = e % R;
+      if (!rowfree[r] || !colfree[c]) continue;
+      Cand x{sim[e], c, r};
+      if (better(x, best)) best = x;
+    }
+    best = wave_best(best);
+    int br = best.r, bc = best.c;
+    if (br >= R || bc >= R) {   // every free entry is NaN: take the first free pair
+      br = 0; bc = 0;
+      while (br < R && !rowfree[br]) ++br;
+      while (bc < R && !colfree[bc]) ++bc;
+    }
+    double rival = -INFINITY;
+    for (int e = lane; e < R * R; e += 64) {
+      const int r = e / R, c = e % R;
+      if (!rowfree[r] || !colfree[c]) continue;
+      if ((r == br) != (c == bc)) rival = sim[e] > rival ? sim[e] : rival;
+    }
+    rival = wave_max(rival);
+    if (rival > -INFINITY) {
+      const double g = best.v - rival;
+      margin = g < margin ? g : margin;
+    }
+    __syncthreads();
+    if (lane == 0) { perm[br] = bc; rowfree[br] = 0; colfree[bc] = 0; }
+    __syncthreads();
+  }
+  return margin;
+}
+
+// One block (64 lanes) per replica p.
+__global__ __launch_bounds__(64) void align_kernel(int P, int Q, int R, int S,
+                                                   const double* __restrict__ F,
+                                                   const double* __restrict__ lam,
+                                                   double* __restrict__ aligned,
+                                                   int* __restrict__ perm_out,
+                                                   double* __restrict__ margin_out) {
+  extern __shared__ double sm[];
+  const int SR = S * R;
+  double* a0 = sm;                 // [3][S][R] reference anchors (lambda distributed)
+  double* ap = a0 + 3 * SR;        // [3][S][R] this replica's anchors
+  double* sim = ap + 3 * SR;       // [R][R]
+  __shared__ double c0[MAXR], cp[MAXR];
+  __shared__ int perm[MAXR], rowfree[MAXR], colfree[MAXR];
+  const int p = blockIdx.x, lane = threadIdx.x;
+  const int64_t QR = (int64_t)Q * R;
+  const double* F0 = F;
+  const double* Fp = F + (int64_t)p * 3 * QR;
+  if (lane < R) {
+    c0[lane] = cbrt(lam[lane]);
+    cp[lane] = cbrt(lam[(int64_t)p * R + lane]);
+  }
+  __syncthreads();
+  double* Ap = aligned + (int64_t)p * 3 * QR;
+  if (p == 0) {
+    for (int64_t e = lane; e < 3 * QR; e += 64) Ap[e] = F0[e] * c0[e % R];
+    if (lane < R) perm_out[lane] = lane;
+    if (lane == 0) margin_out[0] = INFINITY;
+    return;
+  }
+  for (int e = lane; e < 3 * SR; e += 64) {
+    const int n = e / SR, rem = e % SR;       // rem = s * R + r
+    const int r = rem % R;
+    a0[e] = F0[n * QR + rem] * c0[r];
+    ap[e] = Fp[n * QR + rem] * cp[r];
+  }
+  __syncthreads();
+  // sim[r][c] = prod_n |cos(ap[n][:, r], a0[n][:, c])|
+  for (int e = lane; e < R * R; e += 64) {
+    const int r = e / R, c = e % R;
+    double s = 1.0;
+    for (int n = 0; n < 3; ++n) {
+      double num = 0.0, na = 0.0, nb = 0.0;
+      for (int q = 0; q < S; ++q) {
+        const double x = ap[n * SR + q * R + r], y = a0[n * SR + q * R + c];
+        num = fma(x, y, num);
+        na = fma(x, x, na);
+        nb = fma(y, y, nb);
+      }
+      const double den = sqrt(na) * sqrt(nb);
+      s *= den > 0.0 ? fabs(num) / den : 0.0;
+    }
+    sim[e] = s;
+  }
+  __syncthreads();
+  const double margin = greedy_wave(sim, R, perm, rowfree, colfree);
+  if (lane == 0) margin_out[p] = margin;
+  if (lane < R) perm_out[(int64_t)p * R + lane] = perm[lane];
+  // least-squares scale of each anchor column onto the reference's
+  for (int e = lane; e < 3 * R; e += 64) {
+    const int n = e / R, r = e % R, rr = perm[r];
+    double num = 0.0, den = 0.0;
+    for (int q = 0; q < S; ++q) {
+      const double x = ap[n * SR + q * R + r];
+      num = fma(a0[n * SR + q * R + rr], x, num);
+      den = fma(x, x, den);
+    }
+    sim[e] = den > 0.0 ? num / den : 0.0;   // sim reused as d[n][r]
+  }
+  __syncthreads();
+  for (int64_t e = lane; e < 3 * QR; e += 64) {
+    const int n = (int)(e / QR);
+    const int64_t rem = e % QR;
+    const int q = (int)(rem / R), r = (int)(rem % R);
+    Ap[n * QR + (int64_t)q * R + perm[r]] = sim[n * R + r] * (Fp[e] * cp[r]);
+  }
+}
+
+__global__ void stack_kernel(int P, int Q, int R, int S, const double* __restrict__ aligned,
+                             double* __restrict__ rhs) {
+  const int M1 = S + P * (Q - S);
+  const int64_t tot = (int64_t)3 * M1 * R;
+  const int64_t QR = (int64_t)Q * R;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int n = (int)(e / ((int64_t)M1 * R));
+    const int64_t rem = e % ((int64_t)M1 * R);
+    const int row = (int)(rem / R), r = (int)(rem % R);
+    double v;
+    if (row < S) {
+      v = 0.0;
+      for (int p = 0; p < P; ++p) v += aligned[((int64_t)p * 3 + n) * QR + (int64_t)row * R + r];
+      v /= (double)P;
+    } else {
+      const int p = (row - S) / (Q - S), q = S + (row - S) % (Q - S);
+      v = aligned[((int64_t)p * 3 + n) * QR + (int64_t)q * R + r];
+    }
+    rhs[e] = v;
+  }
+}
+
+// Column r of X [n][R]: 2-norm and first index of the largest |x|; one block
+// per column.
+__device__ void column_stats(int64_t n, int R, const double* X, int r, double* s_sum, double* s_val,
+                             int64_t* s_idx, double* nrm, double* signv) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double s = 0.0, best = -1.0;
+  int64_t bi = INT64_MAX;
+  for (int64_t i = tid; i < n; i += nt) {
+    const double v = X[i * R + r];
+    s = fma(v, v, s);
+    const double a = fabs(v);
+    if (a > best) { best = a; bi = i; }
+  }
+  s_sum[tid] = s;
+  s_val[tid] = best;
+  s_idx[tid] = bi;
+  __syncthreads();
+  for (int w = nt / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      s_sum[tid] += s_sum[tid + w];
+      const double ov = s_val[tid + w];
+      const int64_t oi = s_idx[tid + w];
+      if (ov > s_val[tid] || (ov == s_val[tid] && oi < s_idx[tid])) { s_val[tid] = ov; s_idx[tid] = oi; }
+    }
+    __syncthreads();
+  }
+  *nrm = sqrt(s_sum[0]);
+  const int64_t idx = s_idx[0];
+  *signv = idx < n ? X[idx * R + r] : 0.0;
+}
+
+__global__ __launch_bounds__(256) void canon_kernel(int64_t n, int R, const double* __restrict__ X,
+                                                    double* __restrict__ out,
+                                                    double* __restrict__ kfac) {
+  __shared__ double s_sum[256], s_val[256];
+  __shared__ int64_t s_idx[256];
+  const int r = blockIdx.x;
+  double nrm, sv;
+  column_stats(n, R, X, r, s_sum, s_val, s_idx, &nrm, &sv);
+  const double sg = sv > 0.0 ? 1.0 : (sv < 0.0 ? -1.0 : 1.0);
+  const double k = (nrm > 0.0 ? nrm : 1.0) * sg;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) out[i * R + r] = X[i * R + r] / k;
+  if (threadIdx.x == 0) kfac[r] = k;
+}
+
+__global__ __launch_bounds__(256) void colnorm_kernel(int64_t n, int R, const double* __restrict__ X,
+                                                      double* __restrict__ norms) {
+  __shared__ double s_sum[256], s_val[256];
+  __shared__ int64_t s_idx[256];
+  const int r = blockIdx.x;
+  double nrm, sv;
+  column_stats(n, R, X, r, s_sum, s_val, s_idx, &nrm, &sv);
+  if (threadIdx.x == 0) norms[r] = nrm;
+}
+
+// cross: [2][R][R] = Ac^T Ap and Bc^T Bp; norms: [4][R] = |Ac|, |Ap|, |Bc|, |Bp|.
+__global__ __launch_bounds__(64) void tmatch_kernel(int R, const double* __restrict__ cross,
+                                                    const double* __restrict__ norms,
+                                                    int* __restrict__ tperm,
+                                                    double* __restrict__ tsign,
+                                                    double* __restrict__ tmargin) {
+  __shared__ double sim[MAXR * MAXR];
+  __shared__ int perm[MAXR], rowfree[MAXR], colfree[MAXR];
+  const int lane = threadIdx.x;
+  const double* ca = cross;
+  const double* cb = cross + R * R;
+  const double *nac = norms, *nap = norms + R, *nbc = norms + 2 * R, *nbp = norms + 3 * R;
+  for (int e = lane; e < R * R; e += 64) {
+    const int r = e / R, c = e % R;
+    const double da = nac[r] * nap[c], db = nbc[r] * nbp[c];
+    sim[e] = fabs(ca[e]) / (da > 0.0 ? da : 1.0) * fabs(cb[e]) / (db > 0.0 ? db : 1.0);
+  }
+  __syncthreads();
+  const double margin = greedy_wave(sim, R, perm, rowfree, colfree);
+  if (lane < R) {
+    const int c = perm[lane];
+    const double a = ca[lane * R + c], b = cb[lane * R + c];
+    double s = (a > 0.0 ? 1.0 : (a < 0.0 ? -1.0 : 0.0)) * (b > 0.0 ? 1.0 : (b < 0.0 ? -1.0 : 0.0));
+    tperm[lane] = c;
+    tsign[lane] = s == 0.0 ? 1.0 : s;
+  }
+  if (lane == 0) *tmargin = margin;
+}
+
+__global__ void temporal_prep_kernel(int M1, int R, const double* __restrict__ H,
+                                     const int* __restrict__ tperm,
+                                     const double* __restrict__ tsign,
+                                     const double* __restrict__ ka, const double* __restrict__ kb,
+                                     double* __restrict__ kappa, double* __restrict__ Hcur,
+                                     const double* __restrict__ rhs2, double* __restrict__ rhs_c,
+                                     int have_prev) {
+  const int64_t tot = (int64_t)M1 * R;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = e / R;
+    const int r = (int)(e % R);
+    const double kap = ka[r] * kb[r];
+    if (e < R) kappa[e] = ka[e] * kb[e];
+    double h = 0.0;
+    if (have_prev) h = H[m * R + tperm[r]] * tsign[r];
+    Hcur[e] = h;
+    rhs_c[e] = rhs2[e] - h / kap;
+  }
+}
+
+__global__ void temporal_finish_kernel(int R, int64_t Kold, int64_t t,
+                                       const double* __restrict__ kappa,
+                                       const int* __restrict__ tperm,
+                                       const double* __restrict__ tsign,
+                                       double* __restrict__ Cnew, double* __restrict__ Chist,
+                                       double* __restrict__ tmp, int have_prev, int phase) {
+  if (phase == 0) {
+    // tmp = old rows permuted and sign-fixed; Cnew scaled by kappa
+    const int64_t tot = Kold * R;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t k = e / R;
+      const int r = (int)(e % R);
+      tmp[e] = have_prev ? Chist[k * R + tperm[r]] * tsign[r] : Chist[e];
+    }
+    const int64_t tn = t * R;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tn;
+         e += (int64_t)gridDim.x * blockDim.x)
+      Cnew[e] *= kappa[e % R];
+  } else {
+    const int64_t tot = (Kold + t) * R;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x)
+      Chist[e] = e < Kold * R ? tmp[e] : Cnew[e - Kold * R];
+  }
+}
+
+__global__ void weights_kernel(int M1, int S, int P, double* w, double* w2) {
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < M1; m += gridDim.x * blockDim.x) {
+    w[m] = m < S ? sqrt((double)P) : 1.0;
+    w2[m] = m < S ? (double)P : 1.0;
+  }
+}
+
+inline int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  return (int)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+}
+
+}  // namespace
+
+hipError_t rec_align(hipStream_t s, int P, int Q, int R, int S, const double* F,
+                     const double* lam, double* aligned, int* perm, double* margin) {
+  if (R > MAXR) return hipErrorInvalidValue;
+  const int simn = R * R > 3 * R ? R * R : 3 * R;
+  size_t lds = (size_t)(6 * S * R + simn) * sizeof(double);
+  hipLaunchKernelGGL(align_kernel, dim3(P), dim3(64), lds, s, P, Q, R, S, F, lam, aligned, perm,
+                     margin);
+  return hipGetLastError();
+}
+
+hipError_t rec_stack(hipStream_t s, int P, int Q, int R, int S, const double* aligned, double* rhs) {
+  const int M1 = S + P * (Q - S);
+  hipLaunchKernelGGL(stack_kernel, dim3(grid_for((int64_t)3 * M1 * R)), dim3(256), 0, s, P, Q, R,
+                     S, aligned, rhs);
+  return hipGetLastError();
+}
+
+hipError_t rec_canon(hipStream_t s, int64_t n, int R, const double* X, double* out, double* kfac) {
+  hipLaunchKernelGGL(canon_kernel, dim3(R), dim3(256), 0, s, n, R, X, out, kfac);
+  return hipGetLastError();
+}
+
+hipError_t rec_col_norms(hipStream_t s, int64_t n, int R, const double* X, double* norms) {
+  hipLaunchKernelGGL(colnorm_kernel, dim3(R), dim3(256), 0, s, n, R, X, norms);
+  return hipGetLastError();
+}
+
+hipError_t rec_tmatch(hipStream_t s, int R, const double* cross, const double* norms, int* tperm,
+                      double* tsign, double* tmargin) {
+  if (R > MAXR) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tmatch_kernel, dim3(1), dim3(64), 0, s, R, cross, norms, tperm, tsign,
+                     tmargin);
+  return hipGetLastError();
+}
+
+hipError_t rec_temporal_prep(hipStream_t s, int M1, int R, const double* H, const int* tperm,
+                             const double* tsign, const double* ka, const double* kb, double* kappa,
+                             double* Hcur, const double* rhs2, double* rhs_c, int have_prev) {
+  hipLaunchKernelGGL(temporal_prep_kernel, dim3(grid_for((int64_t)M1 * R)), dim3(256), 0, s, M1, R,
+                     H, tperm, tsign, ka, kb, kappa, Hcur, rhs2, rhs_c, have_prev);
+  return hipGetLastError();
+}
+
+hipError_t rec_temporal_finish(hipStream_t s, int R, int64_t Kold, int64_t t, const double* kappa,
+                               const int* tperm, const double* tsign, double* Cnew, double* Chist,
+                               double* tmp, int have_prev) {
+  const int64_t big = (Kold + t) * R;
+  hipLaunchKernelGGL(temporal_finish_kernel, dim3(grid_for(big)), dim3(256), 0, s, R, Kold, t,
+                     kappa, tperm, tsign, Cnew, Chist, tmp, have_prev, 0);
+  hipLaunchKernelGGL(temporal_finish_kernel, dim3(grid_for(big)), dim3(256), 0, s, R, Kold, t,
+                     kappa, tperm, tsign, Cnew, Chist, tmp, have_prev, 1);
+  return hipGetLastError();
+}
+
+hipError_t rec_weights(hipStream_t s, int M1, int S, int P, double* w, double* w2) {
+  hipLaunchKernelGGL(weights_kernel, dim3(grid_for(M1)), dim3(256), 0, s, M1, S, P, w, w2);
+  return hipGetLastError();
+}
+
+}  // namespace octen

@@ -1,0 +1,266 @@
+"""Python binding of libocten (ctypes).  Argument marshalling only: every step
+of the update runs in the HIP library; torch supplies device memory and the
+stream.  The functions carry the C names; `Octen` wraps a handle.
+
+Importing this module loads the built library and fails loudly if it is
+missing: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libocten.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"libocten.so is not built ({LIB_PATH}); run `python -m paper_1807_01350_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OCTEN_ABI_VERSION = 1
+OCTEN_OK, OCTEN_ERR_ARG, OCTEN_ERR_STATE, OCTEN_ERR_HIP, OCTEN_ERR_NOMEM, OCTEN_ERR_NUMERIC, \
+    OCTEN_ERR_UNSUPPORTED = range(7)
+OCTEN_F64, OCTEN_F32, OCTEN_BF16, OCTEN_F16 = range(4)
+OCTEN_INIT_GIVEN, OCTEN_INIT_PREV = 0, 1
+(OCTEN_STATE_Y, OCTEN_STATE_Z, OCTEN_STATE_FACTORS, OCTEN_STATE_LAMBDA, OCTEN_STATE_PERM,
+ OCTEN_STATE_ALIGNED, OCTEN_STATE_RHS, OCTEN_STATE_H, OCTEN_STATE_TPERM, OCTEN_STATE_ITERS,
+ OCTEN_STATE_MARGIN, OCTEN_STATE_FLAGS) = range(12)
+OCTEN_FLAG_FUSE_UPDATE = 0x1
+OCTEN_FLAG_REFERENCE_PATH = 0x2
+
+DTYPES = {"f64": OCTEN_F64, "f32": OCTEN_F32, "bf16": OCTEN_BF16, "f16": OCTEN_F16}
+
+
+class octen_config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("R", ctypes.c_int32),
+        ("P", ctypes.c_int32),
+        ("Q", ctypes.c_int32),
+        ("S", ctypes.c_int32),
+        ("x_dtype", ctypes.c_int32),
+        ("compress_dtype", ctypes.c_int32),
+        ("als_dtype", ctypes.c_int32),
+        ("I", ctypes.c_int64),
+        ("J", ctypes.c_int64),
+        ("flags", ctypes.c_uint64),
+    ]
+
+
+_vp = ctypes.c_void_p
+_i32, _i64, _f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_SIGS = {
+    "octen_init": ([ctypes.POINTER(octen_config), _vp, _vp, _vp, ctypes.POINTER(_vp)], _i32),
+    "octen_compress_batch": ([_vp, _vp, _i64, _vp, _vp], _i32),
+    "octen_compress_batch_coo": ([_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp], _i32),
+    "octen_update_replicas": ([_vp], _i32),
+    "octen_cp_als_replicas": ([_vp, _i32, _f64, _i32, _vp, _vp], _i32),
+    "octen_recover_factors": ([_vp, _vp, _vp, _vp, _i64, _vp], _i32),
+    "octen_fit": ([_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp], _i32),
+    "octen_get_state": ([_vp, _i32, _vp, ctypes.c_size_t], _i32),
+    "octen_check_identifiable": ([ctypes.POINTER(octen_config), _i64, _i64, _vp, _vp], _i32),
+    "octen_destroy": ([_vp], _i32),
+    "octen_status_str": ([_i32], ctypes.c_char_p),
+    "octen_last_error": ([_vp], ctypes.c_char_p),
+    "octen_abi_version": ([], _i32),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_SIGS)
+
+
+class OctenError(RuntimeError):
+    def __init__(self, status, where, detail=""):
+        self.status = status
+        msg = f"{where}: {_lib.octen_status_str(status).decode()}"
+        if detail:
+            msg += f" ({detail})"
+        super().__init__(msg)
+
+
+def _ptr(x):
+    """Device/host address of a torch tensor, or an int, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def make_config(I, J, R, P, Q, S, x_dtype="f64", compress_dtype="f64", als_dtype="f64", flags=0):
+    c = octen_config()
+    c.abi_version = OCTEN_ABI_VERSION
+    c.I, c.J, c.R, c.P, c.Q, c.S = int(I), int(J), int(R), int(P), int(Q), int(S)
+    c.x_dtype = DTYPES[x_dtype]
+    c.compress_dtype = DTYPES[compress_dtype]
+    c.als_dtype = DTYPES[als_dtype]
+    c.flags = int(flags)
+    return c
+
+
+# ---------------------------------------------------------------------------
+# Functions with the C names (status codes returned as ints).
+# ---------------------------------------------------------------------------
+
+def octen_abi_version():
+    return _lib.octen_abi_version()
+
+
+def octen_init(cfg, U, V, stream=None):
+    h = _vp()
+    st = _lib.octen_init(ctypes.byref(cfg), _ptr(U), _ptr(V), stream, ctypes.byref(h))
+    return st, h
+
+
+def octen_compress_batch(h, X, t, W, slice_scale=None):
+    return _lib.octen_compress_batch(h, _ptr(X), int(t), _ptr(W), _ptr(slice_scale))
+
+
+def octen_compress_batch_coo(h, nnz, k, i, j, v, t, W):
+    return _lib.octen_compress_batch_coo(h, int(nnz), _ptr(k), _ptr(i), _ptr(j), _ptr(v), int(t),
+                                         _ptr(W))
+
+
+def octen_update_replicas(h):
+    return _lib.octen_update_replicas(h)
+
+
+def octen_cp_als_replicas(h, max_iters, tol, init_mode, init=None, iters_done=None):
+    return _lib.octen_cp_als_replicas(h, int(max_iters), float(tol), int(init_mode), _ptr(init),
+                                      iters_done)
+
+
+def octen_recover_factors(h, A, B, C, c_capacity, K_out=None):
+    return _lib.octen_recover_factors(h, _ptr(A), _ptr(B), _ptr(C), int(c_capacity), K_out)
+
+
+def octen_fit(h, X, t, k0, A, B, C, out):
+    return _lib.octen_fit(h, _ptr(X), int(t), int(k0), _ptr(A), _ptr(B), _ptr(C), out)
+
+
+def octen_get_state(h, what, dst, nbytes):
+    return _lib.octen_get_state(h, int(what), _ptr(dst), int(nbytes))
+
+
+def octen_check_identifiable(cfg, K, t):
+    bits = ctypes.c_int32(0)
+    pmin = ctypes.c_double(0.0)
+    st = _lib.octen_check_identifiable(ctypes.byref(cfg), int(K), int(t),
+                                       ctypes.cast(ctypes.byref(bits), _vp),
+                                       ctypes.cast(ctypes.byref(pmin), _vp))
+    return st, bits.value, pmin.value
+
+
+def octen_destroy(h):
+    return _lib.octen_destroy(h)
+
+
+def octen_status_str(st):
+    return _lib.octen_status_str(int(st)).decode()
+
+
+def octen_last_error(h):
+    return _lib.octen_last_error(h).decode()
+
+
+# ---------------------------------------------------------------------------
+# Handle wrapper raising on errors; tensors come from torch (device memory).
+# ---------------------------------------------------------------------------
+
+class Octen:
+    """One online CP stream on one GPU.  U, V: torch float64 device tensors
+    [I][M1] and [J][M1]."""
+
+    def __init__(self, I, J, R, P, Q, S, U, V, x_dtype="f64", compress_dtype="f64",
+                 als_dtype="f64", flags=0, stream=None):
+        import torch
+        self.torch = torch
+        self.cfg = make_config(I, J, R, P, Q, S, x_dtype, compress_dtype, als_dtype, flags)
+        self.I, self.J, self.R, self.P, self.Q, self.S = int(I), int(J), int(R), int(P), int(Q), int(S)
+        self.M1 = self.S + self.P * (self.Q - self.S)
+        self.acc_dtype = torch.float64 if compress_dtype == "f64" else torch.float32
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        st, h = octen_init(self.cfg, U, V, stream.cuda_stream)
+        if st != OCTEN_OK:
+            raise OctenError(st, "octen_init")
+        self.h = h
+        self.K = 0
+
+    def _check(self, st, where):
+        if st != OCTEN_OK:
+            raise OctenError(st, where, octen_last_error(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            octen_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def compress_batch(self, X, W, slice_scale=None):
+        self._check(octen_compress_batch(self.h, X, X.shape[0], W, slice_scale), "octen_compress_batch")
+
+    def compress_batch_coo(self, k, i, j, v, t, W):
+        self._check(octen_compress_batch_coo(self.h, v.numel(), k, i, j, v, t, W),
+                    "octen_compress_batch_coo")
+
+    def update_replicas(self):
+        self._check(octen_update_replicas(self.h), "octen_update_replicas")
+
+    def cp_als_replicas(self, iters, tol=0.0, init=None, want_iters=False):
+        mode = OCTEN_INIT_GIVEN if init is not None else OCTEN_INIT_PREV
+        buf = (ctypes.c_int32 * self.P)() if want_iters else None
+        self._check(octen_cp_als_replicas(self.h, iters, tol, mode, init,
+                                          ctypes.cast(buf, _vp) if buf is not None else None),
+                    "octen_cp_als_replicas")
+        return np.array(buf[:], dtype=np.int32) if buf is not None else None
+
+    def recover_factors(self, A, B, C):
+        K = ctypes.c_int64(0)
+        self._check(octen_recover_factors(self.h, A, B, C, C.shape[0],
+                                          ctypes.cast(ctypes.byref(K), _vp)),
+                    "octen_recover_factors")
+        self.K = K.value
+        return self.K
+
+    def fit_terms(self, X, k0, A, B, C, acc=None):
+        out = (ctypes.c_double * 2)(*(acc if acc is not None else (0.0, 0.0)))
+        self._check(octen_fit(self.h, X, X.shape[0], k0, A, B, C, ctypes.cast(out, _vp)), "octen_fit")
+        return out[0], out[1]
+
+    def state(self, what):
+        torch = self.torch
+        P, Q, R, M1 = self.P, self.Q, self.R, self.M1
+        dev = "cuda"
+        shapes = {
+            OCTEN_STATE_Y: ((P, Q, Q, Q), self.acc_dtype),
+            OCTEN_STATE_Z: ((P, Q, Q, Q), self.acc_dtype),
+            OCTEN_STATE_FACTORS: ((P, 3, Q, R), torch.float64),
+            OCTEN_STATE_LAMBDA: ((P, R), torch.float64),
+            OCTEN_STATE_PERM: ((P, R), torch.int32),
+            OCTEN_STATE_ALIGNED: ((P, 3, Q, R), torch.float64),
+            OCTEN_STATE_RHS: ((3, M1, R), torch.float64),
+            OCTEN_STATE_H: ((M1, R), torch.float64),
+            OCTEN_STATE_TPERM: ((R,), torch.int32),
+            OCTEN_STATE_ITERS: ((P,), torch.int32),
+            OCTEN_STATE_MARGIN: ((P,), torch.float64),
+            OCTEN_STATE_FLAGS: ((P,), torch.int32),
+        }
+        shape, dt = shapes[what]
+        out = torch.empty(shape, dtype=dt, device=dev)
+        self._check(octen_get_state(self.h, what, out, out.numel() * out.element_size()),
+                    "octen_get_state")
+        return out
