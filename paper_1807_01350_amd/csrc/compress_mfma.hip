@@ -1,24 +1,470 @@
-// MFMA compression path (placeholder until the fused gfx950 kernel lands).
+// Dense compression on gfx950 matrix cores (Sec. 4.1, Eq. 1: every replica
+// is X x1 U_p^T x2 V_p^T x3 W_p^T of the batch).
+//
+// The two non-temporal products are one fused kernel per (slice k, block of
+// BM rows i, column block cb):
+//   stage 1  T = X_k[rows, :] V[:, cols(cb)]      (BM x 256, K = J)
+//   stage 2  M_p += U_p[rows, :]^T T[:, cols(p)]  (Q x Q for each replica p in cb)
+// A column block holds the S shared columns and G replicas' own columns, so
+// both stages finish inside one workgroup.  Stage 1 streams X once from HBM
+// (f32 rows, converted on the fly to the MFMA input type with the optional
+// per-slice power-of-two scale), takes V from a pre-packed fragment image that
+// stays in L2, and double-buffers both operands through LDS.  Stage 2 reads T
+// back from LDS (transposed) and U from a pre-packed fragment image.  Partial
+// M of each row block go to a workspace; a second kernel sums them and applies
+// the mode-3 product with the batch's W rows (FP64 accumulation).
+//
+// Tile order is XCD-aware: workgroup x runs on XCD x % 8, and the column
+// blocks that share one X tile are consecutive on the same XCD so that the
+// second and third reads of the tile hit that XCD's L2.
 #include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
 
 #include "octen_internal.h"
 
 namespace octen {
 
-struct MfmaPlan {
-  int dummy;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int BM = 128;   // rows i per tile
+constexpr int BN = 256;   // stage-1 columns per tile (shared + G replicas)
+constexpr int KC = 32;    // j per pipeline chunk
+constexpr int NT = 256;   // threads (4 waves, 2 x 2 over the BM x BN tile)
+
+// Input kinds: 1 = f32 MFMA (32x32x2), 2 = bf16 MFMA (32x32x16).
+template <int KIND> struct Kind;
+template <> struct Kind<1> {
+  using T = float;
+  using Frag = float;
+  static constexpr int KSTEP = 2;                  // k per MFMA
+  static constexpr int EPL = 1;                    // elements per lane per fragment
+  __device__ static Frag ld(const T* p) { return *p; }
+  __device__ static f32x16 mma(Frag a, Frag b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Kind<2> {
+  using T = __bf16;
+  using Frag = bf16x8;
+  static constexpr int KSTEP = 16;
+  static constexpr int EPL = 8;
+  __device__ static Frag ld(const T* p) { return *(const bf16x8*)p; }
+  __device__ static f32x16 mma(Frag a, Frag b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
 };
 
-hipError_t mfma_plan_create(const CompressShape&, int, const double*, const double*, hipStream_t,
-                            MfmaPlan** out) {
-  *out = nullptr;
-  return hipErrorNotSupported;
+// Fragment image of one KC chunk: [ks][tile][lane][EPL]
+template <int KIND>
+__host__ __device__ constexpr int chunk_elems(int tiles) {
+  return (KC / Kind<KIND>::KSTEP) * tiles * 64 * Kind<KIND>::EPL;
 }
-void mfma_plan_destroy(MfmaPlan* p) { delete p; }
-size_t mfma_workspace_bytes(const MfmaPlan*, int64_t) { return 0; }
-hipError_t compress_mfma(hipStream_t, const MfmaPlan*, const float*, int64_t, const float*,
-                         const double*, void*, float*) {
-  return hipErrorNotSupported;
+
+template <int KIND>
+__device__ __forceinline__ typename Kind<KIND>::T cvt(float x) {
+  return (typename Kind<KIND>::T)x;
+}
+
+// Position of k index kk (0..KC) of row r inside the A fragment image.
+template <int KIND>
+__device__ __forceinline__ int a_pos(int r, int kk) {
+  constexpr int KS = Kind<KIND>::KSTEP, E = Kind<KIND>::EPL;
+  const int ks = kk / KS, kin = kk % KS;
+  const int lane = (r % 32) + 32 * (kin / E);
+  return ((ks * (BM / 32) + r / 32) * 64 + lane) * E + (kin % E);
+}
+
+struct Args {
+  const float* X;
+  const float* scale;       // [t] or null
+  const void* Vpack;        // [ncb][nchunk][chunk image]
+  const void* Upack;        // [nrb][P][BM/KSTEP][QT][64][EPL]
+  const int* tilecol;       // [ncb][G][QT*32] -> column of T (BN = zero row)
+  float* Mpart;             // [t][nrb][P][Q][Q]
+  int64_t I, J;
+  int t, P, Q, G, ncb, nrb, nchunk, tiles;
+};
+
+template <int KIND, int QT, bool VEC>
+__global__ __launch_bounds__(NT) void compress_fused(Args g) {
+  using T = typename Kind<KIND>::T;
+  using Frag = typename Kind<KIND>::Frag;
+  constexpr int KS = Kind<KIND>::KSTEP, E = Kind<KIND>::EPL;
+  constexpr int A_EL = chunk_elems<KIND>(BM / 32);   // A chunk image elements
+  constexpr int B_EL = chunk_elems<KIND>(BN / 32);   // B chunk image elements
+  constexpr int T2LD = BM + 16 / (int)sizeof(T);     // padded row of T^T
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* As = (T*)smem;                 // [2][A_EL]
+  T* Bs = As + 2 * A_EL;            // [2][B_EL]
+  T* T2t = (T*)smem;                // [BN + 1][T2LD], reuses the staging buffers
+
+  // XCD-aware tile index
+  const int per = (g.tiles + 7) / 8;
+  const int u = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (u >= g.tiles) return;
+  const int cb = u % g.ncb;
+  const int rb = (u / g.ncb) % g.nrb;
+  const int k = u / (g.ncb * g.nrb);
+
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const float sc = g.scale ? g.scale[k] : 1.0f;
+  const int64_t row0 = (int64_t)rb * BM;
+  const float* Xk = g.X + (int64_t)k * g.I * g.J;
+  const T* Vc = (const T*)g.Vpack + (int64_t)cb * g.nchunk * B_EL;
+
+  // global -> register staging: thread loads 16 consecutive floats of one row
+  const int lr = tid / 2, lh = tid % 2;
+  const int64_t gi = row0 + lr;
+  const bool row_ok = gi < g.I;
+  const float* xrow = Xk + gi * g.J;
+  float xr[16];
+  constexpr int VB = B_EL * (int)sizeof(T) / NT / 16;   // 16-byte words per thread for B
+  u32x4 vr[VB];
+
+#define OCTEN_LOAD_CHUNK(c)                                                          \
+  do {                                                                               \
+    const int64_t j0 = (int64_t)(c) * KC + lh * 16;                                  \
+    if (VEC) {                                                                       \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                \
+        f32x4 v = {0.f, 0.f, 0.f, 0.f};                                              \
+        if (row_ok && j0 + 4 * q < g.J) v = *(const f32x4*)(xrow + j0 + 4 * q);      \
+        xr[4 * q] = v[0]; xr[4 * q + 1] = v[1]; xr[4 * q + 2] = v[2]; xr[4 * q + 3] = v[3]; \
+      }                                                                              \
+    } else {                                                                         \
+      _Pragma("unroll") for (int q = 0; q < 16; ++q)                                 \
+        xr[q] = (row_ok && j0 + q < g.J) ? xrow[j0 + q] : 0.f;                       \
+    }                                                                                \
+    const u32x4* vsrc = (const u32x4*)(Vc + (int64_t)(c) * B_EL);                    \
+    _Pragma("unroll") for (int q = 0; q < VB; ++q) vr[q] = vsrc[q * NT + tid];       \
+  } while (0)
+
+#define OCTEN_STORE_CHUNK(buf)                                                       \
+  do {                                                                               \
+    T* a_ = As + (buf) * A_EL;                                                       \
+    if constexpr (KIND == 2) {                                                       \
+      bf16x8 lo, hi;                                                                 \
+      _Pragma("unroll") for (int q = 0; q < 8; ++q) {                                \
+        lo[q] = (__bf16)(xr[q] * sc);                                                \
+        hi[q] = (__bf16)(xr[8 + q] * sc);                                            \
+      }                                                                              \
+      *(bf16x8*)(a_ + a_pos<KIND>(lr, lh * 16)) = lo;                                \
+      *(bf16x8*)(a_ + a_pos<KIND>(lr, lh * 16 + 8)) = hi;                            \
+    } else {                                                                         \
+      _Pragma("unroll") for (int q = 0; q < 16; ++q)                                 \
+        a_[a_pos<KIND>(lr, lh * 16 + q)] = cvt<KIND>(xr[q] * sc);                    \
+    }                                                                                \
+    u32x4* b_ = (u32x4*)(Bs + (buf) * B_EL);                                         \
+    _Pragma("unroll") for (int q = 0; q < VB; ++q) b_[q * NT + tid] = vr[q];         \
+  } while (0)
+
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  OCTEN_LOAD_CHUNK(0);
+  OCTEN_STORE_CHUNK(0);
+  __syncthreads();
+  for (int c = 0; c < g.nchunk; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < g.nchunk) OCTEN_LOAD_CHUNK(c + 1);
+    const T* a = As + buf * A_EL;
+    const T* b = Bs + buf * B_EL;
+#pragma unroll
+    for (int ks = 0; ks < KC / KS; ++ks) {
+      Frag af[2], bfr[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        af[i] = Kind<KIND>::ld(a + ((ks * (BM / 32) + wm * 2 + i) * 64 + lane) * E);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        bfr[j] = Kind<KIND>::ld(b + ((ks * (BN / 32) + wn * 4 + j) * 64 + lane) * E);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = Kind<KIND>::mma(af[i], bfr[j], acc[i][j]);
+    }
+    if (c + 1 < g.nchunk) OCTEN_STORE_CHUNK(buf ^ 1);
+    __syncthreads();
+  }
+
+#undef OCTEN_LOAD_CHUNK
+#undef OCTEN_STORE_CHUNK
+
+  // ---- stage 2: T^T into LDS (in the MFMA input type), zero row at BN
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = wn * 128 + j * 32 + lane % 32;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = wm * 64 + i * 32 + 8 * q + 4 * (lane / 32);
+        T* dst = T2t + col * T2LD + r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[e] = cvt<KIND>(acc[i][j][4 * q + e]);
+      }
+    }
+  for (int e = tid; e < T2LD; e += NT) T2t[BN * T2LD + e] = cvt<KIND>(0.f);
+  __syncthreads();
+
+  const int p0 = cb * g.G;
+  const int gcount = (g.P - p0) < g.G ? (g.P - p0) : g.G;
+  const float inv = 1.0f / sc;
+  for (int gg = wave; gg < gcount; gg += 4) {
+    const int p = p0 + gg;
+    f32x16 m[QT][QT];
+#pragma unroll
+    for (int i = 0; i < QT; ++i)
+#pragma unroll
+      for (int j = 0; j < QT; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) m[i][j][e] = 0.f;
+    const T* Up = (const T*)g.Upack + ((int64_t)rb * g.P + p) * (BM / KS) * QT * 64 * E;
+    const int* tc = g.tilecol + ((int64_t)cb * g.G + gg) * QT * 32;
+    int colrow[QT];
+#pragma unroll
+    for (int j = 0; j < QT; ++j) colrow[j] = tc[j * 32 + lane % 32];
+    for (int ks = 0; ks < BM / KS; ++ks) {
+      Frag af[QT];
+#pragma unroll
+      for (int i = 0; i < QT; ++i) af[i] = Kind<KIND>::ld(Up + ((int64_t)(ks * QT + i) * 64 + lane) * E);
+#pragma unroll
+      for (int j = 0; j < QT; ++j) {
+        const Frag bf = Kind<KIND>::ld(T2t + colrow[j] * T2LD + ks * KS + (lane / 32) * E);
+#pragma unroll
+        for (int i = 0; i < QT; ++i) m[i][j] = Kind<KIND>::mma(af[i], bf, m[i][j]);
+      }
+    }
+    float* out = g.Mpart + (((int64_t)k * g.nrb + rb) * g.P + p) * g.Q * g.Q;
+#pragma unroll
+    for (int i = 0; i < QT; ++i)
+#pragma unroll
+      for (int j = 0; j < QT; ++j) {
+        const int bcol = j * 32 + lane % 32;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int arow = i * 32 + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+          if (arow < g.Q && bcol < g.Q) out[arow * g.Q + bcol] = m[i][j][e] * inv;
+        }
+      }
+  }
+}
+
+// V image: [cb][chunk][ks][nt][lane][E]; element V[j][col] with
+// j = c*KC + ks*KS + (lane/32)*E + e (KS = 16) or c*KC + ks*2 + lane/32 (KS = 2).
+template <int KIND>
+__global__ void pack_v(const double* __restrict__ V, int64_t J, int M1, const int* __restrict__ colmap,
+                       int ncb, int nchunk, typename Kind<KIND>::T* __restrict__ out) {
+  constexpr int KS = Kind<KIND>::KSTEP, E = Kind<KIND>::EPL;
+  const int64_t per_chunk = chunk_elems<KIND>(BN / 32);
+  const int64_t tot = (int64_t)ncb * nchunk * per_chunk;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < tot;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = x;
+    const int e = (int)(r % E); r /= E;
+    const int lane = (int)(r % 64); r /= 64;
+    const int nt = (int)(r % (BN / 32)); r /= (BN / 32);
+    const int ks = (int)(r % (KC / KS)); r /= (KC / KS);
+    const int c = (int)(r % nchunk); r /= nchunk;
+    const int cb = (int)r;
+    const int64_t j = (int64_t)c * KC + ks * KS + (lane / 32) * E + e;
+    const int col = colmap[cb * BN + nt * 32 + lane % 32];
+    float v = (j < J && col >= 0) ? (float)V[j * M1 + col] : 0.f;
+    out[x] = (typename Kind<KIND>::T)v;
+  }
+}
+
+// U image: [rb][p][ks][mt][lane][E]; element U[i][col_p(a)] with
+// i = rb*BM + ks*KS + (lane/32)*E + e, a = mt*32 + lane%32.
+template <int KIND>
+__global__ void pack_u(const double* __restrict__ U, int64_t I, int M1, int P, int Q, int S,
+                       int QT, int nrb, typename Kind<KIND>::T* __restrict__ out) {
+  constexpr int KS = Kind<KIND>::KSTEP, E = Kind<KIND>::EPL;
+  const int64_t tot = (int64_t)nrb * P * (BM / KS) * QT * 64 * E;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < tot;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = x;
+    const int e = (int)(r % E); r /= E;
+    const int lane = (int)(r % 64); r /= 64;
+    const int mt = (int)(r % QT); r /= QT;
+    const int ks = (int)(r % (BM / KS)); r /= (BM / KS);
+    const int p = (int)(r % P); r /= P;
+    const int rb = (int)r;
+    const int64_t i = (int64_t)rb * BM + ks * KS + (lane / 32) * E + e;
+    const int a = mt * 32 + lane % 32;
+    float v = 0.f;
+    if (i < I && a < Q) {
+      const int col = a < S ? a : S + p * (Q - S) + (a - S);
+      v = (float)U[i * M1 + col];
+    }
+    out[x] = (typename Kind<KIND>::T)v;
+  }
+}
+
+inline int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+template <int KIND, int QT, bool VEC>
+hipError_t launch_fused(hipStream_t s, const Args& a, size_t lds) {
+  auto fn = compress_fused<KIND, QT, VEC>;
+  hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  const int per = (a.tiles + 7) / 8;
+  hipLaunchKernelGGL(fn, dim3(8 * per), dim3(NT), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int KIND, bool VEC>
+hipError_t launch_q(hipStream_t s, const Args& a, int QT, size_t lds) {
+  switch (QT) {
+    case 1: return launch_fused<KIND, 1, VEC>(s, a, lds);
+    case 2: return launch_fused<KIND, 2, VEC>(s, a, lds);
+    case 3: return launch_fused<KIND, 3, VEC>(s, a, lds);
+    case 4: return launch_fused<KIND, 4, VEC>(s, a, lds);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+struct MfmaPlan {
+  CompressShape sh;
+  int kind = 0;   // 1 f32, 2 bf16
+  int G = 0, ncb = 0, nrb = 0, nchunk = 0, QT = 0;
+  void* Vpack = nullptr;
+  void* Upack = nullptr;
+  int* tilecol = nullptr;
+  int* colmap = nullptr;
+  size_t lds = 0;
+};
+
+hipError_t mfma_plan_create(const CompressShape& sh, int in_kind, const double* U, const double* V,
+                            hipStream_t s, MfmaPlan** out) {
+  *out = nullptr;
+  if (in_kind != 1 && in_kind != 2) return hipErrorInvalidValue;
+  const int P = sh.P, Q = sh.Q, S = sh.S, M1 = sh.M1;
+  if (Q > 128 || S + (Q - S) > BN) return hipErrorNotSupported;
+  MfmaPlan* p = new MfmaPlan();
+  p->sh = sh;
+  p->kind = in_kind;
+  int G = (BN - S) / (Q - S);
+  if (G > P) G = P;
+  if (G < 1) { delete p; return hipErrorNotSupported; }
+  p->G = G;
+  p->ncb = (P + G - 1) / G;
+  p->nrb = (int)((sh.I + BM - 1) / BM);
+  p->nchunk = (int)((sh.J + KC - 1) / KC);
+  p->QT = (Q + 31) / 32;
+  std::vector<int> colmap((size_t)p->ncb * BN, -1);
+  std::vector<int> tilecol((size_t)p->ncb * G * p->QT * 32, BN);
+  for (int cb = 0; cb < p->ncb; ++cb) {
+    for (int c = 0; c < S; ++c) colmap[(size_t)cb * BN + c] = c;
+    for (int gg = 0; gg < G; ++gg) {
+      const int pr = cb * G + gg;
+      if (pr >= P) break;
+      for (int c = 0; c < Q - S; ++c)
+        colmap[(size_t)cb * BN + S + gg * (Q - S) + c] = S + pr * (Q - S) + c;
+      for (int b = 0; b < Q; ++b)
+        tilecol[((size_t)cb * G + gg) * p->QT * 32 + b] = b < S ? b : S + gg * (Q - S) + (b - S);
+    }
+  }
+  const size_t esz = in_kind == 1 ? 4 : 2;
+  const int64_t vcount = (int64_t)p->ncb * p->nchunk *
+                         (in_kind == 1 ? chunk_elems<1>(BN / 32) : chunk_elems<2>(BN / 32));
+  const int KS = in_kind == 1 ? 2 : 16, E = in_kind == 1 ? 1 : 8;
+  const int64_t ucount = (int64_t)p->nrb * P * (BM / KS) * p->QT * 64 * E;
+  hipError_t e;
+  if ((e = hipMalloc(&p->Vpack, vcount * esz)) != hipSuccess ||
+      (e = hipMalloc(&p->Upack, ucount * esz)) != hipSuccess ||
+      (e = hipMalloc(&p->colmap, colmap.size() * sizeof(int))) != hipSuccess ||
+      (e = hipMalloc(&p->tilecol, tilecol.size() * sizeof(int))) != hipSuccess) {
+    mfma_plan_destroy(p);
+    return e;
+  }
+  hipMemcpy(p->colmap, colmap.data(), colmap.size() * sizeof(int), hipMemcpyHostToDevice);
+  hipMemcpy(p->tilecol, tilecol.data(), tilecol.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (in_kind == 1) {
+    hipLaunchKernelGGL(pack_v<1>, dim3(grid_for(vcount)), dim3(256), 0, s, V, sh.J, M1, p->colmap,
+                       p->ncb, p->nchunk, (float*)p->Vpack);
+    hipLaunchKernelGGL(pack_u<1>, dim3(grid_for(ucount)), dim3(256), 0, s, U, sh.I, M1, P, Q, S,
+                       p->QT, p->nrb, (float*)p->Upack);
+  } else {
+    hipLaunchKernelGGL(pack_v<2>, dim3(grid_for(vcount)), dim3(256), 0, s, V, sh.J, M1, p->colmap,
+                       p->ncb, p->nchunk, (__bf16*)p->Vpack);
+    hipLaunchKernelGGL(pack_u<2>, dim3(grid_for(ucount)), dim3(256), 0, s, U, sh.I, M1, P, Q, S,
+                       p->QT, p->nrb, (__bf16*)p->Upack);
+  }
+  if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess) {
+    mfma_plan_destroy(p);
+    return e;
+  }
+  const int T2LD = BM + (in_kind == 1 ? 4 : 8);
+  const size_t stage = 2 * (size_t)((in_kind == 1 ? chunk_elems<1>(BM / 32) : chunk_elems<2>(BM / 32)) +
+                                    (in_kind == 1 ? chunk_elems<1>(BN / 32) : chunk_elems<2>(BN / 32))) * esz;
+  const size_t t2 = (size_t)(BN + 1) * T2LD * esz;
+  p->lds = stage > t2 ? stage : t2;
+  *out = p;
+  return hipSuccess;
+}
+
+void mfma_plan_destroy(MfmaPlan* p) {
+  if (!p) return;
+  if (p->Vpack) hipFree(p->Vpack);
+  if (p->Upack) hipFree(p->Upack);
+  if (p->colmap) hipFree(p->colmap);
+  if (p->tilecol) hipFree(p->tilecol);
+  delete p;
+}
+
+size_t mfma_workspace_bytes(const MfmaPlan* p, int64_t t) {
+  return (size_t)t * p->nrb * p->sh.P * p->sh.Q * p->sh.Q * sizeof(float);
+}
+
+hipError_t compress_mfma(hipStream_t s, const MfmaPlan* p, const float* X, int64_t t,
+                         const float* slice_scale, const double* W, void* work, float* Z) {
+  Args a;
+  a.X = X;
+  a.scale = slice_scale;
+  a.Vpack = p->Vpack;
+  a.Upack = p->Upack;
+  a.tilecol = p->tilecol;
+  a.Mpart = (float*)work;
+  a.I = p->sh.I;
+  a.J = p->sh.J;
+  a.t = (int)t;
+  a.P = p->sh.P;
+  a.Q = p->sh.Q;
+  a.G = p->G;
+  a.ncb = p->ncb;
+  a.nrb = p->nrb;
+  a.nchunk = p->nchunk;
+  const int64_t tiles = t * p->nrb * p->ncb;
+  if (tiles > (int64_t)1 << 30) return hipErrorInvalidValue;
+  a.tiles = (int)tiles;
+  const bool vec = (p->sh.J % 4 == 0) && (((uintptr_t)X & 15) == 0);
+  hipError_t e;
+  if (p->kind == 1)
+    e = vec ? launch_q<1, true>(s, a, p->QT, p->lds) : launch_q<1, false>(s, a, p->QT, p->lds);
+  else
+    e = vec ? launch_q<2, true>(s, a, p->QT, p->lds) : launch_q<2, false>(s, a, p->QT, p->lds);
+  if (e != hipSuccess) return e;
+  return compress_mode3_partials(s, p->sh, t, p->nrb, (const float*)work, W, Z);
 }
 
 }  // namespace octen

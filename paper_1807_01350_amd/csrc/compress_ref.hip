@@ -81,7 +81,7 @@ constexpr int S3_KT = 32;  // k per LDS tile
 template <typename TM, typename TZ>
 __global__ __launch_bounds__(256) void mode3_kernel(const TM* __restrict__ Mk,
                                                     const double* __restrict__ W, int64_t t,
-                                                    int M1, int P, int Q, int S,
+                                                    int nrb, int M1, int P, int Q, int S,
                                                     TZ* __restrict__ Z) {
   extern __shared__ double sm[];
   double* Ms = sm;                     // [S3_KT][S3_B]
@@ -97,7 +97,10 @@ __global__ __launch_bounds__(256) void mode3_kernel(const TM* __restrict__ Mk,
       int kk = e / S3_B, bb = e % S3_B;
       int64_t gk = k0 + kk;
       int b = b0 + bb;
-      Ms[e] = (gk < t && b < Q) ? (double)Mk[((gk * P + p) * Q + a) * Q + b] : 0.0;
+      double v = 0.0;
+      if (gk < t && b < Q)
+        for (int rb = 0; rb < nrb; ++rb) v += (double)Mk[(((gk * nrb + rb) * P + p) * Q + a) * Q + b];
+      Ms[e] = v;
     }
     for (int e = tid; e < S3_KT * Q; e += 256) {
       int kk = e / Q, c = e % Q;
@@ -130,22 +133,31 @@ __global__ __launch_bounds__(256) void mode3_kernel(const TM* __restrict__ Mk,
 
 }  // namespace
 
+hipError_t compress_mode3_partials(hipStream_t s, const CompressShape& sh, int64_t t, int nrb,
+                                  const float* Mpart, const double* W, float* Z) {
+  dim3 grid(sh.P, sh.Q, (sh.Q + S3_B - 1) / S3_B);
+  size_t lds = (size_t)(S3_KT * S3_B + S3_KT * sh.Q) * sizeof(double);
+  hipLaunchKernelGGL((mode3_kernel<float, float>), grid, dim3(256), lds, s, Mpart, W, t, nrb,
+                     sh.M1, sh.P, sh.Q, sh.S, Z);
+  return hipGetLastError();
+}
+
 hipError_t compress_mode3(hipStream_t s, const CompressShape& sh, int64_t t, const void* M,
                           bool m_f64, const double* W, void* Z, bool z_f64) {
   dim3 grid(sh.P, sh.Q, (sh.Q + S3_B - 1) / S3_B);
   size_t lds = (size_t)(S3_KT * S3_B + S3_KT * sh.Q) * sizeof(double);
   if (m_f64 && z_f64)
     hipLaunchKernelGGL((mode3_kernel<double, double>), grid, dim3(256), lds, s,
-                       (const double*)M, W, t, sh.M1, sh.P, sh.Q, sh.S, (double*)Z);
+                       (const double*)M, W, t, 1, sh.M1, sh.P, sh.Q, sh.S, (double*)Z);
   else if (m_f64 && !z_f64)
     hipLaunchKernelGGL((mode3_kernel<double, float>), grid, dim3(256), lds, s, (const double*)M,
-                       W, t, sh.M1, sh.P, sh.Q, sh.S, (float*)Z);
+                       W, t, 1, sh.M1, sh.P, sh.Q, sh.S, (float*)Z);
   else if (!m_f64 && z_f64)
     hipLaunchKernelGGL((mode3_kernel<float, double>), grid, dim3(256), lds, s, (const float*)M,
-                       W, t, sh.M1, sh.P, sh.Q, sh.S, (double*)Z);
+                       W, t, 1, sh.M1, sh.P, sh.Q, sh.S, (double*)Z);
   else
     hipLaunchKernelGGL((mode3_kernel<float, float>), grid, dim3(256), lds, s, (const float*)M, W,
-                       t, sh.M1, sh.P, sh.Q, sh.S, (float*)Z);
+                       t, 1, sh.M1, sh.P, sh.Q, sh.S, (float*)Z);
   return hipGetLastError();
 }
 

@@ -63,6 +63,10 @@ hipError_t compress_reference(hipStream_t s, const CompressShape& sh, const void
 hipError_t compress_mode3(hipStream_t s, const CompressShape& sh, int64_t t, const void* M,
                           bool m_f64, const double* W, void* Z, bool z_f64);
 
+// Same with per-row-block partials Mpart [t][nrb][P][Q][Q] f32 summed first.
+hipError_t compress_mode3_partials(hipStream_t s, const CompressShape& sh, int64_t t, int nrb,
+                                  const float* Mpart, const double* W, float* Z);
+
 // MFMA path (f32 or bf16 inputs, f32 accumulate) for dense f32 slices.
 struct MfmaPlan;
 hipError_t mfma_plan_create(const CompressShape& sh, int in_kind /*1=f32, 2=bf16*/, const double* U,
