@@ -1,0 +1,229 @@
+"""Benchmark of the online compressed CP update on one MI355X.
+
+Workload: the dense 1000 x 1000 stream with rank-10 ground truth (U[0,1]
+factors, Gaussian noise sigma = 0.01), streamed along mode 3: 500 initial
+slices, then batches of 50; P = 12 replicas of 60^3 with S = 3 shared anchor
+rows, 50 ALS sweeps per batch, FP64 solves and recovery.  One step = one
+batch through compress -> update -> ALS -> recover (the whole update).
+
+Synthetic data are generated on the GPU from a seeded generator (no dataset
+exists for this workload).  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--form bf16|f32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "new slices/sec & compression HBM GB/s (% peak) at fit within 1e-3 of FP64 oracle"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--form", choices=("bf16", "f32"), default="bf16")
+    ap.add_argument("--iters", type=int, default=50)
+    ap.add_argument("--batch", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fit", action="store_true")
+    return ap.parse_args()
+
+
+def gen_stream(torch, I, J, K, R, sigma, seed, dev):
+    """X[k] = A diag(C[k]) B^T + sigma N(0,1), f32 on the device (seeded)."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    A = torch.rand((I, R), generator=g, device=dev, dtype=torch.float64)
+    B = torch.rand((J, R), generator=g, device=dev, dtype=torch.float64)
+    C = torch.rand((K, R), generator=g, device=dev, dtype=torch.float64)
+    Bt = B.t().contiguous()
+    X = torch.empty((K, I, J), dtype=torch.float32, device=dev)
+    ch = 25
+    for k0 in range(0, K, ch):
+        k1 = min(K, k0 + ch)
+        blk = torch.matmul(A.unsqueeze(0) * C[k0:k1].unsqueeze(1), Bt)
+        blk += sigma * torch.randn(blk.shape, generator=g, device=dev, dtype=torch.float64)
+        X[k0:k1] = blk.float()
+    return X
+
+
+def traffic_from_profile(form):
+    """HBM bytes per launch of the compression kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1807_01350_amd", "csrc", "compress_mfma.hip")
+    prof = os.path.join(ROOT, "profiles", f"compress_fused_{form}_dense1000_counters.md")
+    if not os.path.exists(prof):
+        return None
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    txt = open(prof).read()
+    m = re.search(r"source_sha256_16:\s*([0-9a-f]{16})", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != h:
+        return None
+    return float(b.group(1))
+
+
+def cpu_baseline(X_batch_np, U, V, W, init, c, iters):
+    """The oracle, untuned, on one batch of the same workload."""
+    import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    threads = cores
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        if info:
+            threads = max(int(x.get("num_threads", 1)) for x in info)
+    except Exception:
+        pass
+    o = oracle.OctenOracle(c.I, c.J, c.R, c.P, c.Q, c.S, U, V)
+    t0 = time.perf_counter()
+    o.compress_batch(X_batch_np, W)
+    o.update_replicas()
+    o.cp_als_replicas(iters, init=init)
+    o.recover_factors()
+    dt = time.perf_counter() - t0
+    t = X_batch_np.shape[0]
+    return {"value": t / dt, "unit": "slices/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one batch of {t} slices of the same stream through the FP64 oracle "
+                      f"(compress, update, {iters} ALS sweeps on all {c.P} replicas, recover) "
+                      f"in {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1807_01350_amd import octen as oc
+    from paper_1807_01350_amd import synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    c = synth.C2
+    t = args.batch
+    nsteps = args.warmup + args.steps
+    K = c.t0 + t * nsteps
+    X = gen_stream(torch, c.I, c.J, K, c.R, c.sigma, synth.seed_of(c.config_id, 1), dev)
+    U, V = synth.compression_UV(c.I, c.J, c.P, c.Q, c.S, c.config_id)
+    Ws = [synth.temporal_W(c.t0 if b == 0 else t, c.M1, c.config_id, b) for b in range(nsteps + 1)]
+    tW = [torch.from_numpy(w).to(dev) for w in Ws]
+    init = synth.als_init(c.P, c.Q, c.R, c.config_id)
+    tinit = torch.from_numpy(init).to(dev)
+    eng = oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, torch.from_numpy(U).to(dev),
+                   torch.from_numpy(V).to(dev), x_dtype="f32", compress_dtype=args.form,
+                   flags=oc.OCTEN_FLAG_TIMING)
+    A = torch.empty((c.I, c.R), dtype=torch.float64, device=dev)
+    B = torch.empty((c.J, c.R), dtype=torch.float64, device=dev)
+    C = torch.empty((K, c.R), dtype=torch.float64, device=dev)
+
+    def step(b, k0, tt):
+        eng.compress_batch(X[k0:k0 + tt], tW[b])
+        eng.update_replicas()
+        eng.cp_als_replicas(args.iters, init=tinit if b == 0 else None)
+        eng.recover_factors_async(A, B, C)
+
+    # initial summary (untimed), then warmup batches
+    step(0, 0, c.t0)
+    k0 = c.t0
+    for b in range(1, args.warmup + 1):
+        step(b, k0, t)
+        k0 += t
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for b in range(args.warmup + 1, nsteps + 1):
+        step(b, k0, t)
+        k0 += t
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_step = 1e3 * elapsed / args.steps
+    value = t * args.steps / elapsed
+
+    def last(stage):
+        v = eng.stage_ms(stage, args.steps)
+        return float(np.mean(v)) if v else None
+
+    st = {
+        "compress_main": last(oc.OCTEN_STAGE_COMPRESS_MAIN),
+        "compress_mode3": last(oc.OCTEN_STAGE_COMPRESS_MODE3),
+        "update": last(oc.OCTEN_STAGE_UPDATE),
+        "als": last(oc.OCTEN_STAGE_ALS),
+        "recover": last(oc.OCTEN_STAGE_RECOVER),
+    }
+    # algorithmic bytes / flops of one launch of the compression kernel (modes 1, 2)
+    esz = 2 if args.form == "bf16" else 4
+    bytes_launch = t * c.I * c.J * 4 + (c.I + c.J) * c.M1 * esz
+    flops_launch = 2.0 * t * c.I * c.J * c.M1 + 2.0 * t * c.I * c.P * c.Q * c.Q
+    kms = st["compress_main"]
+    gbs = bytes_launch / (kms * 1e-3) / 1e9
+    tflops = flops_launch / (kms * 1e-3) / 1e12
+    traffic = traffic_from_profile(args.form)
+    if args.form == "bf16":
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+    else:
+        roof = {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_PEAK_TFLOPS["f32"],
+                "unit": "TFLOP/s", "frac": round(tflops / MFMA_PEAK_TFLOPS["f32"], 4),
+                "traffic": traffic}
+    roof["kernel"] = "compress_fused (modes 1 and 2 of the batch compression)"
+    roof["algorithmic_bytes_per_launch"] = bytes_launch
+    roof["algorithmic_flops_per_launch"] = flops_launch
+    roof["mfma_frac"] = round(tflops / MFMA_PEAK_TFLOPS[args.form], 4)
+
+    fit = None
+    if not args.no_fit:
+        sse = nx = 0.0
+        for q0 in range(0, eng.K, 100):
+            q1 = min(eng.K, q0 + 100)
+            sse, nx = eng.fit_terms(X[q0:q1], q0, A, B, C, acc=(sse, nx))
+        fit = 1.0 - float(np.sqrt(sse / nx))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        kb = c.t0 + t * args.warmup
+        Xb = X[kb:kb + t].double().cpu().numpy()
+        cpu = cpu_baseline(Xb, U, V, Ws[args.warmup + 1], init, c, args.iters)
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "slices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.form,
+        "data": "synthetic (seeded on-device generator; rank-10 U[0,1] CP model + N(0, 0.01^2))",
+        "config": {"workload": f"dense1000_f32: I=J=1000, R=10, {c.t0} initial slices then "
+                               f"batches of {t}; P=12, Q=60, S=3; {args.iters} ALS sweeps; "
+                               f"{args.form} compression, f64 solves",
+                   "I": c.I, "J": c.J, "R": c.R, "P": c.P, "Q": c.Q, "S": c.S, "batch": t,
+                   "initial_slices": c.t0, "als_iters": args.iters, "compress_dtype": args.form},
+        "compression_gbs": round(gbs, 1),
+        "compression_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+        "stage_ms": {k: (round(v, 4) if v is not None else None) for k, v in st.items()},
+        "fit": fit,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    eng.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

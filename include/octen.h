@@ -77,8 +77,19 @@ enum {
 };
 
 /* Flags (octen_config.flags). */
-#define OCTEN_FLAG_FUSE_UPDATE 0x1ull   /* compression adds into Y directly */
-#define OCTEN_FLAG_REFERENCE_PATH 0x2ull /* plain FP64 kernels, no MFMA      */
+#define OCTEN_FLAG_FUSE_UPDATE 0x1ull    /* compression adds into Y directly  */
+#define OCTEN_FLAG_REFERENCE_PATH 0x2ull /* plain FP64 kernels, no MFMA       */
+#define OCTEN_FLAG_TIMING 0x4ull         /* record HIP events around stages   */
+
+/* Stages timed with OCTEN_FLAG_TIMING (octen_stage_time). */
+enum {
+  OCTEN_STAGE_COMPRESS_MAIN = 0,   /* modes 1 and 2 of the compression kernel */
+  OCTEN_STAGE_COMPRESS_MODE3 = 1,  /* mode-3 product (and partial sums)       */
+  OCTEN_STAGE_UPDATE = 2,
+  OCTEN_STAGE_ALS = 3,
+  OCTEN_STAGE_RECOVER = 4,
+  OCTEN_NUM_STAGES = 5
+};
 
 typedef struct {
   int32_t abi_version;     /* must be OCTEN_ABI_VERSION                        */
@@ -160,6 +171,15 @@ octen_status octen_get_state(octen_t h, int32_t what, void* dst, size_t bytes);
  * ranks.  A violation is not an error: recovery is then minimum-norm. */
 octen_status octen_check_identifiable(const octen_config* cfg, int64_t K, int64_t t,
                                       int32_t* bits_host, double* p_min_host);
+
+/* Durations in milliseconds of the most recent runs of one stage, from HIP
+ * events recorded on the handle's stream around the stage's kernels (needs
+ * OCTEN_FLAG_TIMING; the last OCTEN_TIMING_RING runs are kept, no
+ * synchronisation happens while they are recorded).  Writes at most n values,
+ * oldest first, into ms_host and their number into count_host; synchronises. */
+#define OCTEN_TIMING_RING 256
+octen_status octen_stage_times(octen_t h, int32_t stage, double* ms_host, int32_t n,
+                               int32_t* count_host);
 
 /* Release every device buffer of the handle (synchronises its stream). */
 octen_status octen_destroy(octen_t h);

@@ -436,8 +436,8 @@ size_t mfma_workspace_bytes(const MfmaPlan* p, int64_t t) {
   return (size_t)t * p->nrb * p->sh.P * p->sh.Q * p->sh.Q * sizeof(float);
 }
 
-hipError_t compress_mfma(hipStream_t s, const MfmaPlan* p, const float* X, int64_t t,
-                         const float* slice_scale, const double* W, void* work, float* Z) {
+hipError_t compress_mfma_main(hipStream_t s, const MfmaPlan* p, const float* X, int64_t t,
+                              const float* slice_scale, void* work) {
   Args a;
   a.X = X;
   a.scale = slice_scale;
@@ -463,7 +463,11 @@ hipError_t compress_mfma(hipStream_t s, const MfmaPlan* p, const float* X, int64
     e = vec ? launch_q<1, true>(s, a, p->QT, p->lds) : launch_q<1, false>(s, a, p->QT, p->lds);
   else
     e = vec ? launch_q<2, true>(s, a, p->QT, p->lds) : launch_q<2, false>(s, a, p->QT, p->lds);
-  if (e != hipSuccess) return e;
+  return e;
+}
+
+hipError_t compress_mfma_mode3(hipStream_t s, const MfmaPlan* p, int64_t t, const double* W,
+                               const void* work, float* Z) {
   return compress_mode3_partials(s, p->sh, t, p->nrb, (const float*)work, W, Z);
 }
 

@@ -67,7 +67,32 @@ struct octen_ctx {
   double* gj_work = nullptr;
 
   std::vector<void*> allocs;
+
+  // stage timing (OCTEN_FLAG_TIMING): ring of event pairs per stage
+  std::vector<hipEvent_t> ev[OCTEN_NUM_STAGES];   // 2 * OCTEN_TIMING_RING
+  int64_t ev_count[OCTEN_NUM_STAGES] = {};
+  bool timing = false;
 };
+
+namespace {
+struct StageTimer {
+  octen_t h;
+  int stage;
+  int slot;
+  StageTimer(octen_t hh, int st) : h(hh), stage(st), slot(0) {
+    if (h->timing) {
+      slot = (int)(h->ev_count[stage] % OCTEN_TIMING_RING);
+      hipEventRecord(h->ev[stage][2 * slot], h->stream);
+    }
+  }
+  ~StageTimer() {
+    if (h->timing) {
+      hipEventRecord(h->ev[stage][2 * slot + 1], h->stream);
+      ++h->ev_count[stage];
+    }
+  }
+};
+}  // namespace
 
 namespace {
 
@@ -324,6 +349,14 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
       return OCTEN_ERR_HIP;
     }
   }
+  if (cfg->flags & OCTEN_FLAG_TIMING) {
+    for (int st2 = 0; st2 < OCTEN_NUM_STAGES; ++st2) {
+      h->ev[st2].assign(2 * OCTEN_TIMING_RING, nullptr);
+      for (auto& e2 : h->ev[st2])
+        if (!hip_ok(hipEventCreate(&e2), "event")) { octen_destroy(h); return OCTEN_ERR_HIP; }
+    }
+    h->timing = true;
+  }
   IOK(build_operator(h, h->U, I, h->OpA));
   IOK(build_operator(h, h->V, J, h->OpB));
   if (host_info(h) != 0) {
@@ -349,6 +382,9 @@ octen_status octen_destroy(octen_t h) {
   if (!h) return OCTEN_ERR_ARG;
   hipStreamSynchronize(h->stream);
   if (h->plan) mfma_plan_destroy(h->plan);
+  for (int st = 0; st < OCTEN_NUM_STAGES; ++st)
+    for (auto e : h->ev[st])
+      if (e) hipEventDestroy(e);
   for (void* p : h->allocs)
     if (p) hipFree(p);
   delete h;
@@ -373,8 +409,14 @@ octen_status octen_compress_batch(octen_t h, const void* X, int64_t t, const dou
       OKCHK(dalloc(h, (char**)&h->mfma_work, need));
       h->mfma_work_bytes = need;
     }
-    HIPCHK(h, compress_mfma(s, h->plan, (const float*)X, t, slice_scale, h->Wz, h->mfma_work,
-                            (float*)h->Z));
+    {
+      StageTimer tm(h, OCTEN_STAGE_COMPRESS_MAIN);
+      HIPCHK(h, compress_mfma_main(s, h->plan, (const float*)X, t, slice_scale, h->mfma_work));
+    }
+    {
+      StageTimer tm(h, OCTEN_STAGE_COMPRESS_MODE3);
+      HIPCHK(h, compress_mfma_mode3(s, h->plan, t, h->Wz, h->mfma_work, (float*)h->Z));
+    }
   } else {
     // reference path: T2 chunk of at most ~64 Mi doubles
     int64_t rows_cap = (int64_t)1 << 26;
@@ -384,6 +426,7 @@ octen_status octen_compress_batch(octen_t h, const void* X, int64_t t, const dou
     want = (want / I) * I;
     OKCHK(dgrow(h, &h->T2, &h->T2_rows, want * M1));
     OKCHK(dgrow(h, &h->Mk, &h->Mk_cap, t * h->P * h->Q * h->Q));
+    StageTimer tm(h, OCTEN_STAGE_COMPRESS_MAIN);
     HIPCHK(h, compress_reference(s, sh, X, x_f64, t, h->U, h->V, h->Wz, h->T2, h->T2_rows / M1,
                                  h->Mk, h->Z, h->acc_f64));
   }
@@ -404,7 +447,10 @@ octen_status octen_update_replicas(octen_t h) {
   if (!h->z_ready) return fail(h, OCTEN_ERR_STATE, "update before compress");
   hipStream_t s = h->stream;
   const int64_t n = (int64_t)h->P * h->Q * h->Q * h->Q;
-  HIPCHK(h, axpy_acc(s, h->Y, h->Z, n, h->acc_f64));
+  {
+    StageTimer tm(h, OCTEN_STAGE_UPDATE);
+    HIPCHK(h, axpy_acc(s, h->Y, h->Z, n, h->acc_f64));
+  }
   // append this batch's W rows to the pending temporal block
   const int64_t M1 = h->M1;
   if (h->t_pend + h->t_z > h->Wp_cap / (M1 > 0 ? M1 : 1)) {
@@ -443,9 +489,12 @@ octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int
     return fail(h, OCTEN_ERR_ARG, "unknown init_mode");
   }
   hipStream_t s = h->stream;
-  HIPCHK(h, fill_i32(s, h->flags, h->P, 0));
-  HIPCHK(h, als_reference(s, h->Y, h->acc_f64, h->P, h->Q, h->R, src, h->F, h->lam, h->iters,
-                          h->flags, max_iters, tol));
+  {
+    StageTimer tm(h, OCTEN_STAGE_ALS);
+    HIPCHK(h, fill_i32(s, h->flags, h->P, 0));
+    HIPCHK(h, als_reference(s, h->Y, h->acc_f64, h->P, h->Q, h->R, src, h->F, h->lam, h->iters,
+                            h->flags, max_iters, tol));
+  }
   h->have_factors = true;
   h->factors_fresh = true;
   if (iters_done_host) {
@@ -466,6 +515,7 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, i
   hipStream_t s = h->stream;
   const int P = h->P, Q = h->Q, R = h->R, S = h->S, M1 = h->M1;
   const int64_t I = h->I, J = h->J, t = h->t_pend;
+  StageTimer tm(h, OCTEN_STAGE_RECOVER);
   // Sec. 4.2: align replicas; Eq. 5 stack
   HIPCHK(h, rec_align(s, P, Q, R, S, h->F, h->lam, h->aligned, h->perm, h->margin));
   HIPCHK(h, rec_stack(s, P, Q, R, S, h->aligned, h->rhs));
@@ -562,6 +612,26 @@ octen_status octen_fit(octen_t h, const void* X, int64_t t, int64_t k0, const do
   HIPCHK(h, hipStreamSynchronize(s));
   out_host[0] += o[0];
   out_host[1] += o[1];
+  return OCTEN_OK;
+}
+
+octen_status octen_stage_times(octen_t h, int32_t stage, double* ms_host, int32_t n,
+                               int32_t* count_host) {
+  if (!h || !ms_host || !count_host || n < 0) return OCTEN_ERR_ARG;
+  if (stage < 0 || stage >= OCTEN_NUM_STAGES) return fail(h, OCTEN_ERR_ARG, "unknown stage");
+  if (!h->timing) return fail(h, OCTEN_ERR_STATE, "handle created without OCTEN_FLAG_TIMING");
+  const int64_t total = h->ev_count[stage];
+  int64_t avail = total < OCTEN_TIMING_RING ? total : OCTEN_TIMING_RING;
+  if (avail > n) avail = n;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int64_t q = 0; q < avail; ++q) {
+    const int64_t run = total - avail + q;
+    const int slot = (int)(run % OCTEN_TIMING_RING);
+    float ms = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&ms, h->ev[stage][2 * slot], h->ev[stage][2 * slot + 1]));
+    ms_host[q] = ms;
+  }
+  *count_host = (int32_t)avail;
   return OCTEN_OK;
 }
 

@@ -73,8 +73,12 @@ hipError_t mfma_plan_create(const CompressShape& sh, int in_kind /*1=f32, 2=bf16
                             const double* V, hipStream_t s, MfmaPlan** out);
 void mfma_plan_destroy(MfmaPlan* p);
 size_t mfma_workspace_bytes(const MfmaPlan* p, int64_t t);
-hipError_t compress_mfma(hipStream_t s, const MfmaPlan* plan, const float* X, int64_t t,
-                         const float* slice_scale, const double* W, void* work, float* Z);
+// Modes 1 and 2: partial M per row block into work.
+hipError_t compress_mfma_main(hipStream_t s, const MfmaPlan* plan, const float* X, int64_t t,
+                              const float* slice_scale, void* work);
+// Sum of partials and mode 3 into Z.
+hipError_t compress_mfma_mode3(hipStream_t s, const MfmaPlan* plan, int64_t t, const double* W,
+                               const void* work, float* Z);
 
 // ------------------------------------------------------------------- ALS ---
 // One workgroup per replica; Y is [P][Q][Q][Q] (f32 or f64).

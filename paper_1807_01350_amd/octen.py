@@ -31,6 +31,9 @@ OCTEN_INIT_GIVEN, OCTEN_INIT_PREV = 0, 1
  OCTEN_STATE_MARGIN, OCTEN_STATE_FLAGS) = range(12)
 OCTEN_FLAG_FUSE_UPDATE = 0x1
 OCTEN_FLAG_REFERENCE_PATH = 0x2
+OCTEN_FLAG_TIMING = 0x4
+(OCTEN_STAGE_COMPRESS_MAIN, OCTEN_STAGE_COMPRESS_MODE3, OCTEN_STAGE_UPDATE, OCTEN_STAGE_ALS,
+ OCTEN_STAGE_RECOVER) = range(5)
 
 DTYPES = {"f64": OCTEN_F64, "f32": OCTEN_F32, "bf16": OCTEN_BF16, "f16": OCTEN_F16}
 
@@ -63,6 +66,7 @@ _SIGS = {
     "octen_fit": ([_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp], _i32),
     "octen_get_state": ([_vp, _i32, _vp, ctypes.c_size_t], _i32),
     "octen_check_identifiable": ([ctypes.POINTER(octen_config), _i64, _i64, _vp, _vp], _i32),
+    "octen_stage_times": ([_vp, _i32, _vp, _i32, _vp], _i32),
     "octen_destroy": ([_vp], _i32),
     "octen_status_str": ([_i32], ctypes.c_char_p),
     "octen_last_error": ([_vp], ctypes.c_char_p),
@@ -158,6 +162,17 @@ def octen_check_identifiable(cfg, K, t):
     return st, bits.value, pmin.value
 
 
+OCTEN_TIMING_RING = 256
+
+
+def octen_stage_times(h, stage, n=OCTEN_TIMING_RING):
+    buf = (ctypes.c_double * n)()
+    cnt = ctypes.c_int32(0)
+    st = _lib.octen_stage_times(h, int(stage), ctypes.cast(buf, _vp), int(n),
+                                ctypes.cast(ctypes.byref(cnt), _vp))
+    return st, list(buf[:cnt.value])
+
+
 def octen_destroy(h):
     return _lib.octen_destroy(h)
 
@@ -194,6 +209,8 @@ class Octen:
             raise OctenError(st, "octen_init")
         self.h = h
         self.K = 0
+        self._tz = 0
+        self._pend = 0
 
     def _check(self, st, where):
         if st != OCTEN_OK:
@@ -212,13 +229,17 @@ class Octen:
 
     def compress_batch(self, X, W, slice_scale=None):
         self._check(octen_compress_batch(self.h, X, X.shape[0], W, slice_scale), "octen_compress_batch")
+        self._tz = int(X.shape[0])
 
     def compress_batch_coo(self, k, i, j, v, t, W):
         self._check(octen_compress_batch_coo(self.h, v.numel(), k, i, j, v, t, W),
                     "octen_compress_batch_coo")
+        self._tz = int(t)
 
     def update_replicas(self):
         self._check(octen_update_replicas(self.h), "octen_update_replicas")
+        self._pend += self._tz
+        self._tz = 0
 
     def cp_als_replicas(self, iters, tol=0.0, init=None, want_iters=False):
         mode = OCTEN_INIT_GIVEN if init is not None else OCTEN_INIT_PREV
@@ -234,12 +255,26 @@ class Octen:
                                           ctypes.cast(ctypes.byref(K), _vp)),
                     "octen_recover_factors")
         self.K = K.value
+        self._pend = 0
+        return self.K
+
+    def recover_factors_async(self, A, B, C):
+        """Same without waiting for the stream (K tracked on the host)."""
+        self._check(octen_recover_factors(self.h, A, B, C, C.shape[0], None), "octen_recover_factors")
+        self.K += self._pend
+        self._pend = 0
         return self.K
 
     def fit_terms(self, X, k0, A, B, C, acc=None):
         out = (ctypes.c_double * 2)(*(acc if acc is not None else (0.0, 0.0)))
         self._check(octen_fit(self.h, X, X.shape[0], k0, A, B, C, ctypes.cast(out, _vp)), "octen_fit")
         return out[0], out[1]
+
+    def stage_ms(self, stage, n=OCTEN_TIMING_RING):
+        """Durations (ms) of the last n runs of a stage, oldest first."""
+        st, ms = octen_stage_times(self.h, stage, n)
+        self._check(st, "octen_stage_times")
+        return ms
 
     def state(self, what):
         torch = self.torch
