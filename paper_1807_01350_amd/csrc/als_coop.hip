@@ -1,0 +1,524 @@
+// Per-replica CP-ALS across many workgroups (Sec. 4.1: each replica summary
+// is decomposed on its own; the model and unfoldings are those of Sec. 2).
+//
+// Each replica is cut along mode 1 into NW slabs of rows a; a workgroup keeps
+// its slab of the summary X_p in LDS for the whole sweep loop, plus the small
+// factor state, all in FP64.  One sweep:
+//   mode 1  T(a,b,:) = sum_c X(a,b,c) C(c,:)                  slab-local, MFMA
+//           A(a,:)   = [sum_b T(a,b,:) * B(b,:)] G1^{-1},  G1 = B'B * C'C
+//   mode 2  M2(b,:)  = sum_a T(a,b,:) * A(a,:),  and A'A      slab partials
+//           -- reduction 1 over the replica's workgroups --
+//           normalise A (norms from diag(A'A)); B = M2 G2^{-1}; normalise B
+//   mode 3  M3(c,:)  = sum_{a,b} X(a,b,c) A(a,:) * B(b,:)     slab partial, MFMA
+//           -- reduction 2 --
+//           C = M3 G3^{-1}; normalise; lambda = column norms of C
+// B and C (Q x R) are solved redundantly by every workgroup of the replica, so
+// only two reductions per sweep cross workgroups.  Reductions add the slab
+// partials in slab order: results do not depend on timing.
+//
+// The R x R normal matrices are inverted by one wavefront (Gauss-Jordan on
+// the SPD matrix, one row per lane, rows exchanged with lane reads), while the
+// other wavefronts run the slab contractions on v_mfma_f64_16x16x4.
+//
+// Workgroups of a replica synchronise through a monotonically increasing
+// counter (agent-scope release, relaxed polling, one acquire); every wait is
+// bounded and raises an error flag when exceeded, after which all workgroups
+// skip to the end.  The launch is cooperative, so all workgroups are resident.
+// Replica p is placed on XCD p % 8 (workgroup x runs on XCD x % 8) so that its
+// counter and partial sums stay in one L2.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "octen_internal.h"
+
+namespace octen {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int MAXR = 32;
+constexpr unsigned SPIN_LIMIT = 1u << 22;
+
+struct CoopArgs {
+  const void* Y;          // [P][Q][Q][Q]
+  const double* init;     // [P][3][Q][R]
+  double* F;              // [P][3][Q][R]
+  double* lam;            // [P][R]
+  int* iters;             // [P]
+  int* flags;             // [P]
+  double* slots;          // [2][P][NW][slot_len]
+  unsigned* counters;     // [P]
+  int* err;               // [1]
+  int P, Q, R, NW, na_max, npair_pad, per_xcd, slot_len, max_iters;
+  double tol;
+};
+
+// D(16 x 16) += A(16 x 4) B(4 x 16); lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; element i of lane l holds D[l/16 + 4 i][l%16].
+__device__ __forceinline__ f64x4 mfma64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Barrier of the NW workgroups of one replica.  Every wave first waits for
+// its own global stores to complete (a plain workgroup barrier does not), then
+// one thread publishes them with a single agent-scope release, bumps the
+// counter, polls it with relaxed loads (no cache invalidation per poll) and
+// performs one agent-scope acquire before the workgroup continues.
+__device__ bool replica_barrier(unsigned* ctr, unsigned target, int* err, int* s_ok) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+      if (++spins > SPIN_LIMIT) {
+        __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+// Inverse of the SPD matrix G (R x R, LDS) by Gauss-Jordan elimination
+// without pivoting, run by one wavefront: lane i keeps row i of [G | I] in
+// registers and the pivot row is read from lane j.  Writes Ginv (LDS) and
+// sets *bad when a pivot is not positive.
+template <int RMAX>
+__device__ void spd_inverse_wave(const double* G, double* Ginv, int R, int* bad) {
+  const int lane = threadIdx.x & 63;
+  double g[RMAX], v[RMAX];
+#pragma unroll
+  for (int k = 0; k < RMAX; ++k) {
+    g[k] = (lane < R && k < R) ? G[lane * R + k] : 0.0;
+    v[k] = (lane == k) ? 1.0 : 0.0;
+  }
+  int badl = 0;
+#pragma unroll
+  for (int j = 0; j < RMAX; ++j) {
+    if (j < R) {
+      double piv = __shfl(g[j], j, 64);
+      if (!(piv > 0.0)) { badl = 1; piv = 1e-300; }
+      const double ip = 1.0 / piv;
+      const double f = g[j];
+#pragma unroll
+      for (int k = 0; k < RMAX; ++k) {
+        if (k < R) {
+          const double gj = __shfl(g[k], j, 64) * ip;
+          const double vj = __shfl(v[k], j, 64) * ip;
+          if (lane == j) {
+            g[k] = gj;
+            v[k] = vj;
+          } else {
+            g[k] = fma(-f, gj, g[k]);
+            v[k] = fma(-f, vj, v[k]);
+          }
+        }
+      }
+    }
+  }
+  if (lane < R) {
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k)
+      if (k < R) Ginv[lane * R + k] = v[k];
+  }
+  if (lane == 0 && badl) *bad = 1;
+}
+
+// G = F^T F (F: n x R in LDS, row stride R) by one wavefront on MFMA; R <= 32.
+__device__ void gram_wave(const double* Fm, int n, int R, double* G) {
+  const int lane = threadIdx.x & 63;
+  const int ntile = (R + 15) / 16;
+  for (int ti = 0; ti < ntile; ++ti)
+    for (int tj = 0; tj < ntile; ++tj) {
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+      const int r1 = ti * 16 + lane % 16, r2 = tj * 16 + lane % 16;
+      for (int k0 = 0; k0 < n; k0 += 4) {
+        const int q = k0 + lane / 16;
+        const double a = (q < n && r1 < R) ? Fm[q * R + r1] : 0.0;
+        const double b = (q < n && r2 < R) ? Fm[q * R + r2] : 0.0;
+        acc = mfma64(a, b, acc);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = ti * 16 + lane / 16 + 4 * i, col = r2;
+        if (row < R && col < R) G[row * R + col] = acc[i];
+      }
+    }
+}
+
+// out(q, :) = M(q, :) Ginv for q < n (all threads; independent loads).
+__device__ void apply_inverse(const double* M, const double* Ginv, double* out, int n, int R) {
+  for (int e = threadIdx.x; e < n * R; e += NT) {
+    const int q = e / R, r = e % R;
+    const double* m = M + q * R;
+    double s0 = 0.0, s1 = 0.0;
+    int k = 0;
+    for (; k + 1 < R; k += 2) {
+      s0 = fma(m[k], Ginv[k * R + r], s0);
+      s1 = fma(m[k + 1], Ginv[(k + 1) * R + r], s1);
+    }
+    if (k < R) s0 = fma(m[k], Ginv[k * R + r], s0);
+    out[e] = s0 + s1;
+  }
+}
+
+// Column 2-norms of F (n x R): lam[r] (0 replaced by 1); one wave per column,
+// lanes split the rows, butterfly sum.
+__device__ void col_norms(const double* Fm, int n, int R, double* lam) {
+  const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
+  for (int r = wave; r < R; r += NT / 64) {
+    double s = 0.0;
+    for (int q = lane; q < n; q += 64) s = fma(Fm[q * R + r], Fm[q * R + r], s);
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+      const double nr = sqrt(s);
+      lam[r] = nr > 0.0 ? nr : 1.0;
+    }
+  }
+}
+
+// Sum over the NW slab partials of element e, slab order; loads are issued
+// eight at a time before they are added, so that they are in flight together.
+__device__ __forceinline__ double sum_slots(const double* base, int64_t stride, int NW) {
+  double s = 0.0;
+  for (int w0 = 0; w0 < NW; w0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = w0 + u < NW ? base[(w0 + u) * stride] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (w0 + u < NW) s += v[u];
+  }
+  return s;
+}
+
+template <typename T, int RMAX>
+__global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_ok, s_bad, s_stop;
+  __shared__ double s_nx2, s_fit_old;
+  __shared__ int s_have_old;
+
+  // placement: workgroup x -> XCD x % 8; replicas p = x % 8 + 8 k live there
+  const int xcd = blockIdx.x % 8, loc = blockIdx.x / 8;
+  const int p = xcd + 8 * (loc / g.NW);
+  const int w = loc % g.NW;
+  if (p >= g.P) return;
+
+  const int Q = g.Q, R = g.R, NW = g.NW, QR = Q * R, RR = R * R;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid & 63;
+  const int a0 = (int)((int64_t)w * Q / NW), a1 = (int)((int64_t)(w + 1) * Q / NW);
+  const int na = a1 - a0;
+  const int npair = na * Q;                   // rows (a, b) of the slab
+  const int QP = Q + 1;                       // padded slab row (bank spread)
+  const int RT = (R + 15) / 16;               // 16-wide tiles over r
+  const int64_t Q2 = (int64_t)Q * Q;
+
+  double* Ts = (double*)smem;                 // [npair_pad][R]  T, then W
+  double* Bf = Ts + (int64_t)g.npair_pad * R; // [Q][R]
+  double* Cf = Bf + QR;
+  double* Mf = Cf + QR;                       // reduced M2 / M3
+  double* Ml = Mf + QR;                       // [Q][R] scratch (M1 rows)
+  double* Al = Ml + QR;                       // [na_max][R]
+  double* G = Al + g.na_max * R;              // [R][R]
+  double* Gi = G + RR;                        // inverse
+  double* AtA = Gi + RR;
+  double* BtB = AtA + RR;
+  double* CtC = BtB + RR;
+  double* lamv = CtC + RR;                    // [MAXR]
+  double* scr = lamv + MAXR;                  // [NT]
+  T* Xs = (T*)(scr + NT);                     // [na_max * Q][Q + 1]
+
+  const T* Xp = (const T*)g.Y + (int64_t)p * Q2 * Q;
+  for (int64_t e = tid; e < (int64_t)npair * Q; e += NT)
+    Xs[(e / Q) * QP + e % Q] = Xp[(int64_t)a0 * Q2 + e];
+  const double* F0 = g.init + (int64_t)p * 3 * QR;
+  for (int e = tid; e < na * R; e += NT) Al[e] = F0[a0 * R + e];
+  for (int e = tid; e < QR; e += NT) { Bf[e] = F0[QR + e]; Cf[e] = F0[2 * QR + e]; }
+  if (tid == 0) { s_bad = 0; s_stop = 0; s_have_old = 0; s_fit_old = 0.0; s_nx2 = 0.0; }
+  __syncthreads();
+
+  unsigned* ctr = g.counters + p;
+  unsigned nbar = 0;
+  bool alive = true;
+  const int slot_len = g.slot_len;
+  // the slot set alternates with the barrier count: a set is rewritten two
+  // barriers later, when every workgroup has finished reading it
+  auto slot = [&](int set, int ww) {
+    return g.slots + (((int64_t)set * g.P + p) * NW + ww) * slot_len;
+  };
+
+  if (g.tol > 0.0) {
+    double s = 0.0;
+    for (int64_t e = tid; e < (int64_t)npair * Q; e += NT) {
+      const double v = (double)Xs[(e / Q) * QP + e % Q];
+      s = fma(v, v, s);
+    }
+    scr[tid] = s;
+    __syncthreads();
+    for (int st = NT / 2; st > 0; st >>= 1) {
+      if (tid < st) scr[tid] += scr[tid + st];
+      __syncthreads();
+    }
+    if (NW > 1) {
+      const int bs = (nbar + 1) & 1;
+      if (tid == 0) slot(bs, w)[0] = scr[0];
+      alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok);
+      if (alive && tid == 0) {
+        double t = 0.0;
+        for (int ww = 0; ww < NW; ++ww) t += slot(bs, ww)[0];
+        s_nx2 = t;
+      }
+    } else if (tid == 0) {
+      s_nx2 = scr[0];
+    }
+    __syncthreads();
+  }
+  if (wave == 0) gram_wave(Bf, Q, R, BtB);
+  if (wave == 1) gram_wave(Cf, Q, R, CtC);
+  __syncthreads();
+
+  int done = 0;
+  for (int it = 0; it < g.max_iters && alive; ++it) {
+    // ------------------------------------------------ mode 1 (rows of A)
+    for (int e = tid; e < RR; e += NT) G[e] = BtB[e] * CtC[e];
+    __syncthreads();
+    if (wave == 0) {
+      spd_inverse_wave<RMAX>(G, Gi, R, &s_bad);
+    } else {
+      // T(pair, r) = sum_c X(pair, c) C(c, r) on MFMA, tiles over pairs x r
+      const int ptiles = (npair + 15) / 16;
+      for (int tt = wave - 1; tt < ptiles * RT; tt += NT / 64 - 1) {
+        const int pt = tt / RT, rt = tt % RT;
+        const int pr = pt * 16 + lane % 16;
+        const int rr = rt * 16 + lane % 16;
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int c0 = 0; c0 < Q; c0 += 4) {
+          const int c = c0 + lane / 16;
+          const double a = (pr < npair && c < Q) ? (double)Xs[pr * QP + c] : 0.0;
+          const double b = (c < Q && rr < R) ? Cf[c * R + rr] : 0.0;
+          acc = mfma64(a, b, acc);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = pt * 16 + lane / 16 + 4 * i;
+          if (row < npair && rr < R) Ts[row * R + rr] = acc[i];
+        }
+      }
+    }
+    __syncthreads();
+    // M1(la, r) = sum_b T(la, b, r) B(b, r)
+    for (int e = tid; e < na * R; e += NT) {
+      const int la = e / R, r = e % R;
+      const double* tr = Ts + (int64_t)la * QR + r;
+      double s0 = 0.0, s1 = 0.0;
+      int b = 0;
+      for (; b + 1 < Q; b += 2) {
+        s0 = fma(tr[b * R], Bf[b * R + r], s0);
+        s1 = fma(tr[(b + 1) * R], Bf[(b + 1) * R + r], s1);
+      }
+      if (b < Q) s0 = fma(tr[b * R], Bf[b * R + r], s0);
+      Ml[e] = s0 + s1;
+    }
+    __syncthreads();
+    apply_inverse(Ml, Gi, Al, na, R);
+    __syncthreads();
+    // ------------------------------------------------ mode 2 partials
+    const int set1 = (nbar + 1) & 1;
+    double* sl = NW > 1 ? slot(set1, w) : nullptr;
+    for (int e = tid; e < QR + RR; e += NT) {
+      double s = 0.0;
+      if (e < QR) {
+        const int b = e / R, r = e % R;
+        for (int la = 0; la < na; ++la) s = fma(Ts[((int64_t)la * Q + b) * R + r], Al[la * R + r], s);
+      } else {
+        const int r1 = (e - QR) / R, r2 = (e - QR) % R;
+        for (int la = 0; la < na; ++la) s = fma(Al[la * R + r1], Al[la * R + r2], s);
+      }
+      if (NW > 1) sl[e] = s;
+      else if (e < QR) Mf[e] = s;
+      else AtA[e - QR] = s;
+    }
+    if (NW > 1) {
+      alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok);
+      if (!alive) break;
+      for (int e = tid; e < QR + RR; e += NT) {
+        const double s = sum_slots(slot(set1, 0) + e, slot_len, NW);
+        if (e < QR) Mf[e] = s; else AtA[e - QR] = s;
+      }
+    }
+    __syncthreads();
+    // normalise A: lambda_A = sqrt(diag(A'A))
+    if (tid < R) {
+      const double n = sqrt(AtA[tid * R + tid]);
+      lamv[tid] = n > 0.0 ? n : 1.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < na * R; e += NT) Al[e] /= lamv[e % R];
+    for (int e = tid; e < QR; e += NT) Mf[e] /= lamv[e % R];
+    for (int e = tid; e < RR; e += NT) {
+      AtA[e] /= lamv[e / R] * lamv[e % R];
+      G[e] = AtA[e] * CtC[e];
+    }
+    __syncthreads();
+    // ------------------------------------------------ mode 2 solve (B)
+    if (wave == 0) spd_inverse_wave<RMAX>(G, Gi, R, &s_bad);
+    __syncthreads();
+    apply_inverse(Mf, Gi, Bf, Q, R);
+    __syncthreads();
+    col_norms(Bf, Q, R, lamv);
+    __syncthreads();
+    for (int e = tid; e < QR; e += NT) Bf[e] /= lamv[e % R];
+    __syncthreads();
+    // W(pair, r) = A(a, r) B(b, r) into Ts; B'B by wave 0
+    if (wave == 0) gram_wave(Bf, Q, R, BtB);
+    for (int e = tid; e < npair * R; e += NT) {
+      const int pr = e / R, r = e % R;
+      Ts[e] = Al[(pr / Q) * R + r] * Bf[(pr % Q) * R + r];
+    }
+    __syncthreads();
+    // ------------------------------------------------ mode 3 partial
+    for (int e = tid; e < RR; e += NT) G[e] = AtA[e] * BtB[e];
+    __syncthreads();
+    {
+      const int set2 = (nbar + 1) & 1;
+      double* dst = NW > 1 ? slot(set2, w) : Mf;
+      if (wave == 0) {
+        spd_inverse_wave<RMAX>(G, Gi, R, &s_bad);
+      } else {
+        // M3(c, r) = sum_pair X(pair, c) W(pair, r): tiles over c x r
+        const int ctiles = (Q + 15) / 16;
+        for (int tt = wave - 1; tt < ctiles * RT; tt += NT / 64 - 1) {
+          const int ct = tt / RT, rt = tt % RT;
+          const int c = ct * 16 + lane % 16;
+          const int rr = rt * 16 + lane % 16;
+          f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+          for (int k0 = 0; k0 < npair; k0 += 4) {
+            const int pr = k0 + lane / 16;
+            const double a = (pr < npair && c < Q) ? (double)Xs[pr * QP + c] : 0.0;
+            const double b = (pr < npair && rr < R) ? Ts[pr * R + rr] : 0.0;
+            acc = mfma64(a, b, acc);
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = ct * 16 + lane / 16 + 4 * i;
+            if (row < Q && rr < R) dst[row * R + rr] = acc[i];
+          }
+        }
+      }
+      if (NW > 1) {
+        alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok);
+        if (!alive) break;
+        for (int e = tid; e < QR; e += NT) Mf[e] = sum_slots(slot(set2, 0) + e, slot_len, NW);
+      }
+    }
+    __syncthreads();
+    // ------------------------------------------------ mode 3 solve (C)
+    apply_inverse(Mf, Gi, Cf, Q, R);
+    __syncthreads();
+    col_norms(Cf, Q, R, lamv);
+    __syncthreads();
+    for (int e = tid; e < QR; e += NT) Cf[e] /= lamv[e % R];
+    __syncthreads();
+    if (wave == 0) gram_wave(Cf, Q, R, CtC);
+    __syncthreads();
+    ++done;
+    if (g.tol > 0.0) {
+      if (tid == 0) {
+        double inner = 0.0;
+        for (int r = 0; r < R; ++r) {
+          double d = 0.0;
+          for (int q = 0; q < Q; ++q) d = fma(Mf[q * R + r], Cf[q * R + r], d);
+          inner += lamv[r] * d;
+        }
+        double nh = 0.0;
+        for (int r1 = 0; r1 < R; ++r1)
+          for (int r2 = 0; r2 < R; ++r2)
+            nh += lamv[r1] * (AtA[r1 * R + r2] * BtB[r1 * R + r2] * CtC[r1 * R + r2]) * lamv[r2];
+        double res = s_nx2 - 2.0 * inner + nh;
+        if (res < 0.0) res = 0.0;
+        const double fit = s_nx2 > 0.0 ? 1.0 - sqrt(res) / sqrt(s_nx2) : 0.0;
+        s_stop = (s_have_old && fabs(fit - s_fit_old) < g.tol) ? 1 : 0;
+        s_fit_old = fit;
+        s_have_old = 1;
+      }
+      __syncthreads();
+      if (s_stop) break;
+    }
+  }
+  // write back: slab rows of A from every workgroup; B, C, lambda from slab 0
+  double* Fo = g.F + (int64_t)p * 3 * QR;
+  for (int e = tid; e < na * R; e += NT) Fo[a0 * R + e] = Al[e];
+  if (w == 0) {
+    for (int e = tid; e < QR; e += NT) { Fo[QR + e] = Bf[e]; Fo[2 * QR + e] = Cf[e]; }
+    if (tid < R) g.lam[(int64_t)p * R + tid] = lamv[tid];
+    if (tid == 0) {
+      g.iters[p] = done;
+      if (s_bad) g.flags[p] |= 1;
+      if (!alive) g.flags[p] |= 2;
+    }
+  } else if (tid == 0 && s_bad) {
+    atomicOr(g.flags + p, 1);
+  }
+}
+
+}  // namespace
+
+static int pad_pairs(int Q, int NW) {
+  const int na_max = (Q + NW - 1) / NW;
+  return ((na_max * Q + 15) / 16) * 16;
+}
+
+size_t als_coop_lds_bytes(int Q, int R, int NW, bool x_f64) {
+  const int na_max = (Q + NW - 1) / NW;
+  const size_t QR = (size_t)Q * R;
+  const size_t dbl = (size_t)pad_pairs(Q, NW) * R + 4 * QR + (size_t)na_max * R +
+                     5 * (size_t)R * R + MAXR + NT;
+  return dbl * 8 + (size_t)na_max * Q * (Q + 1) * (x_f64 ? 8 : 4);
+}
+
+hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int R, int NW,
+                    const double* init, double* F, double* lam, int* iters, int* flags,
+                    double* slots, unsigned* counters, int* err, int max_iters, double tol) {
+  if (R > MAXR || Q > 128 || NW < 1 || NW > Q || NW > 32) return hipErrorInvalidValue;
+  CoopArgs a;
+  a.Y = Y; a.init = init; a.F = F; a.lam = lam; a.iters = iters; a.flags = flags;
+  a.slots = slots; a.counters = counters; a.err = err;
+  a.P = P; a.Q = Q; a.R = R; a.NW = NW;
+  a.na_max = (Q + NW - 1) / NW;
+  a.npair_pad = pad_pairs(Q, NW);
+  a.per_xcd = (P + 7) / 8;
+  a.slot_len = als_coop_slot_len(Q, R);
+  a.max_iters = max_iters; a.tol = tol;
+  const size_t lds = als_coop_lds_bytes(Q, R, NW, y_f64);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  hipError_t e = fill_i32(s, (int*)counters, P, 0);
+  if (e != hipSuccess) return e;
+  e = fill_i32(s, err, 1, 0);
+  if (e != hipSuccess) return e;
+  const int grid = 8 * a.per_xcd * NW;
+  void* args[] = {&a};
+  const void* fn;
+  if (R <= 8)
+    fn = y_f64 ? (const void*)als_coop_kernel<double, 8> : (const void*)als_coop_kernel<float, 8>;
+  else if (R <= 16)
+    fn = y_f64 ? (const void*)als_coop_kernel<double, 16> : (const void*)als_coop_kernel<float, 16>;
+  else
+    fn = y_f64 ? (const void*)als_coop_kernel<double, 32> : (const void*)als_coop_kernel<float, 32>;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(NT), args, (unsigned)lds, s);
+}
+
+}  // namespace octen

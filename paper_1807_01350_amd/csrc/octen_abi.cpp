@@ -48,6 +48,10 @@ struct octen_ctx {
   // ALS
   double *F = nullptr, *lam = nullptr;     // [P][3][Q][R], [P][R]
   int *iters = nullptr, *flags = nullptr;  // [P]
+  int als_nw = 0;                          // workgroups per replica (0: reference kernel)
+  double* als_slots = nullptr;
+  unsigned* als_ctr = nullptr;
+  int* als_err = nullptr;
   // recovery
   double *aligned = nullptr, *margin = nullptr, *rhs = nullptr, *rhs_c = nullptr;
   int* perm = nullptr;
@@ -349,6 +353,27 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
       return OCTEN_ERR_HIP;
     }
   }
+  if (!(cfg->flags & OCTEN_FLAG_REFERENCE_PATH)) {
+    // workgroups per replica for the cooperative ALS: enough to spread ~2e5
+    // FMAs per workgroup per sweep, at most the CUs of one XCD per replica,
+    // and few enough that the slab fits in LDS
+    const int per_xcd = (int)((P + 7) / 8);
+    int max_nw = per_xcd > 0 ? 32 / per_xcd : 0;
+    if (max_nw > Q) max_nw = (int)Q;
+    if (max_nw >= 1) {
+      const double work = 4.0 * (double)Q * Q * Q * R;
+      int nw = (int)ceil(work / 2.0e5);
+      if (nw < 1) nw = 1;
+      if (nw > max_nw) nw = max_nw;
+      while (nw < max_nw && als_coop_lds_bytes((int)Q, (int)R, nw, h->acc_f64) > 160 * 1024) ++nw;
+      if (als_coop_lds_bytes((int)Q, (int)R, nw, h->acc_f64) <= 160 * 1024) {
+        h->als_nw = nw;
+        IOK(dalloc(h, &h->als_slots, (size_t)2 * P * nw * als_coop_slot_len((int)Q, (int)R)));
+        IOK(dalloc(h, &h->als_ctr, (size_t)P));
+        IOK(dalloc(h, &h->als_err, 1));
+      }
+    }
+  }
   if (cfg->flags & OCTEN_FLAG_TIMING) {
     for (int st2 = 0; st2 < OCTEN_NUM_STAGES; ++st2) {
       h->ev[st2].assign(2 * OCTEN_TIMING_RING, nullptr);
@@ -492,14 +517,27 @@ octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int
   {
     StageTimer tm(h, OCTEN_STAGE_ALS);
     HIPCHK(h, fill_i32(s, h->flags, h->P, 0));
-    HIPCHK(h, als_reference(s, h->Y, h->acc_f64, h->P, h->Q, h->R, src, h->F, h->lam, h->iters,
-                            h->flags, max_iters, tol));
+    hipError_t e = hipErrorNotSupported;
+    if (h->als_nw > 0) {
+      e = als_coop(s, h->Y, h->acc_f64, h->P, h->Q, h->R, h->als_nw, src, h->F, h->lam, h->iters,
+                   h->flags, h->als_slots, h->als_ctr, h->als_err, max_iters, tol);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        h->als_nw = 0;   // cooperative launch not possible here: use the reference kernel
+      }
+    }
+    if (e != hipSuccess)
+      HIPCHK(h, als_reference(s, h->Y, h->acc_f64, h->P, h->Q, h->R, src, h->F, h->lam, h->iters,
+                              h->flags, max_iters, tol));
   }
   h->have_factors = true;
   h->factors_fresh = true;
   if (iters_done_host) {
     HIPCHK(h, hipMemcpyAsync(iters_done_host, h->iters, h->P * sizeof(int), hipMemcpyDeviceToHost, s));
+    int err = 0;
+    if (h->als_err) HIPCHK(h, hipMemcpyAsync(&err, h->als_err, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
+    if (err) return fail(h, OCTEN_ERR_HIP, "ALS workgroup synchronisation timed out");
   }
   return OCTEN_OK;
 }

@@ -24,6 +24,8 @@ CASES = [
     Case("wide_t", 40, 40, 3, 2, 10, 3, (30, 5), iters=40, config_id=12),
     # rank one (matching is trivial) with two anchors
     Case("rank1", 30, 30, 1, 3, 8, 2, (12, 6), iters=20, config_id=13),
+    # large replicas: ALS spreads each replica over several workgroups
+    Case("wideq", 90, 90, 4, 3, 40, 3, (20, 8), iters=30, config_id=14),
 ]
 
 _cache = {}
@@ -91,8 +93,21 @@ def test_fit(result):
         assert abs(g["fit"] - r["fit"]) <= 1e-10, (b, g["fit"], r["fit"])
 
 
+def test_reference_kernels_agree():
+    """The plain reference kernels (no MFMA, one workgroup per replica) give
+    the same stream as the default kernels, both within the oracle's bars."""
+    from paper_1807_01350_amd import octen as oc
+    case = CASES[4]
+    X, U, V, Ws, init = make_inputs(case)
+    a = _run(case)[1]
+    b = run_gpu(case, X, U, V, Ws, init, flags=oc.OCTEN_FLAG_REFERENCE_PATH)
+    for x, y in zip(a, b):
+        for key in ("F", "A", "B", "C"):
+            assert rel(x[key], y[key]) <= 1e-10, key
+
+
 def test_deterministic_rerun():
-    case = CASES[1]
+    case = CASES[4]
     X, U, V, Ws, init = make_inputs(case)
     a = run_gpu(case, X, U, V, Ws, init)
     b = run_gpu(case, X, U, V, Ws, init)
