@@ -141,18 +141,22 @@ __device__ void gram_wave(const double* Fm, int n, int R, double* G) {
   const int ntile = (R + 15) / 16;
   for (int ti = 0; ti < ntile; ++ti)
     for (int tj = 0; tj < ntile; ++tj) {
-      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+      f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
       const int r1 = ti * 16 + lane % 16, r2 = tj * 16 + lane % 16;
-      for (int k0 = 0; k0 < n; k0 += 4) {
-        const int q = k0 + lane / 16;
-        const double a = (q < n && r1 < R) ? Fm[q * R + r1] : 0.0;
-        const double b = (q < n && r2 < R) ? Fm[q * R + r2] : 0.0;
-        acc = mfma64(a, b, acc);
+#pragma unroll 4
+      for (int k0 = 0; k0 < n; k0 += 8) {
+        const int q = k0 + lane / 16, q2 = q + 4;
+        const double a0 = (q < n && r1 < R) ? Fm[q * R + r1] : 0.0;
+        const double b0 = (q < n && r2 < R) ? Fm[q * R + r2] : 0.0;
+        const double a1 = (q2 < n && r1 < R) ? Fm[q2 * R + r1] : 0.0;
+        const double b1 = (q2 < n && r2 < R) ? Fm[q2 * R + r2] : 0.0;
+        acc0 = mfma64(a0, b0, acc0);
+        acc1 = mfma64(a1, b1, acc1);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = ti * 16 + lane / 16 + 4 * i, col = r2;
-        if (row < R && col < R) G[row * R + col] = acc[i];
+        if (row < R && col < R) G[row * R + col] = acc0[i] + acc1[i];
       }
     }
 }
@@ -303,17 +307,22 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
         const int pt = tt / RT, rt = tt % RT;
         const int pr = pt * 16 + lane % 16;
         const int rr = rt * 16 + lane % 16;
-        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int c0 = 0; c0 < Q; c0 += 4) {
-          const int c = c0 + lane / 16;
-          const double a = (pr < npair && c < Q) ? (double)Xs[pr * QP + c] : 0.0;
-          const double b = (c < Q && rr < R) ? Cf[c * R + rr] : 0.0;
-          acc = mfma64(a, b, acc);
+        f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+        const bool okr = pr < npair, okc = rr < R;
+#pragma unroll 4
+        for (int c0 = 0; c0 < Q; c0 += 8) {
+          const int c = c0 + lane / 16, c2 = c + 4;
+          const double a0 = (okr && c < Q) ? (double)Xs[pr * QP + c] : 0.0;
+          const double b0 = (okc && c < Q) ? Cf[c * R + rr] : 0.0;
+          const double a1 = (okr && c2 < Q) ? (double)Xs[pr * QP + c2] : 0.0;
+          const double b1 = (okc && c2 < Q) ? Cf[c2 * R + rr] : 0.0;
+          acc0 = mfma64(a0, b0, acc0);
+          acc1 = mfma64(a1, b1, acc1);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int row = pt * 16 + lane / 16 + 4 * i;
-          if (row < npair && rr < R) Ts[row * R + rr] = acc[i];
+          if (row < npair && okc) Ts[row * R + rr] = acc0[i] + acc1[i];
         }
       }
     }
@@ -403,17 +412,22 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
           const int ct = tt / RT, rt = tt % RT;
           const int c = ct * 16 + lane % 16;
           const int rr = rt * 16 + lane % 16;
-          f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-          for (int k0 = 0; k0 < npair; k0 += 4) {
-            const int pr = k0 + lane / 16;
-            const double a = (pr < npair && c < Q) ? (double)Xs[pr * QP + c] : 0.0;
-            const double b = (pr < npair && rr < R) ? Ts[pr * R + rr] : 0.0;
-            acc = mfma64(a, b, acc);
+          f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+          const bool okc = c < Q, okr = rr < R;
+#pragma unroll 4
+          for (int k0 = 0; k0 < npair; k0 += 8) {
+            const int pr = k0 + lane / 16, pr2 = pr + 4;
+            const double a0 = (okc && pr < npair) ? (double)Xs[pr * QP + c] : 0.0;
+            const double b0 = (okr && pr < npair) ? Ts[pr * R + rr] : 0.0;
+            const double a1 = (okc && pr2 < npair) ? (double)Xs[pr2 * QP + c] : 0.0;
+            const double b1 = (okr && pr2 < npair) ? Ts[pr2 * R + rr] : 0.0;
+            acc0 = mfma64(a0, b0, acc0);
+            acc1 = mfma64(a1, b1, acc1);
           }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int row = ct * 16 + lane / 16 + 4 * i;
-            if (row < Q && rr < R) dst[row * R + rr] = acc[i];
+            if (row < Q && okr) dst[row * R + rr] = acc0[i] + acc1[i];
           }
         }
       }

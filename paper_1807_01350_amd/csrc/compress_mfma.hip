@@ -263,6 +263,201 @@ __global__ __launch_bounds__(NT) void compress_fused(Args g) {
   }
 }
 
+// s_waitcnt immediate that waits until at most n vector-memory operations of
+// this wave are outstanding (lgkm and exp counters left unconstrained).
+__host__ __device__ constexpr unsigned vmcnt_imm(unsigned n) {
+  return (n & 0xFu) | ((n >> 4) << 14) | (0x7u << 4) | (0xFu << 8);
+}
+
+typedef __attribute__((address_space(3))) void* lds_vptr;
+typedef __attribute__((address_space(1))) void* gbl_vptr;
+
+// Same tile and output as compress_fused, with a deeper pipeline: NSTAGE LDS
+// stages filled by direct global->LDS loads (16 bytes per lane) issued
+// NSTAGE-1 chunks ahead, so that enough bytes are in flight to cover the
+// memory latency.  X is staged as raw f32 rows (16-byte slots XOR-swizzled by
+// row to spread LDS banks) and converted to the MFMA input type when the A
+// fragments are formed; V is staged as its fragment image.  Rows past I and
+// columns past J read clamped in-bounds addresses; they meet zero rows of the
+// U image or zero rows of the V image, so they add nothing.  Needs J % 4 == 0
+// and 16-byte aligned X.
+template <int KIND, int QT, int NSTAGE>
+__global__ __launch_bounds__(NT) void compress_pipe(Args g) {
+  using T = typename Kind<KIND>::T;
+  using Frag = typename Kind<KIND>::Frag;
+  constexpr int KS = Kind<KIND>::KSTEP, E = Kind<KIND>::EPL;
+  constexpr int B_EL = chunk_elems<KIND>(BN / 32);
+  constexpr int XBYTES = BM * KC * 4;                       // raw f32 X chunk
+  constexpr int VBYTES = B_EL * (int)sizeof(T);
+  constexpr int STAGE = XBYTES + VBYTES;
+  constexpr int XL = XBYTES / (NT * 16);                    // X loads per thread per chunk
+  constexpr int VL = VBYTES / (NT * 16);                    // V loads per thread per chunk
+  constexpr int LPC = XL + VL;
+  constexpr int T2LD = BM + 16 / (int)sizeof(T);
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* T2t = (T*)smem;
+
+  const int per = (g.tiles + 7) / 8;
+  const int u = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (u >= g.tiles) return;
+  const int cb = u % g.ncb;
+  const int rb = (u / g.ncb) % g.nrb;
+  const int k = u / (g.ncb * g.nrb);
+
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const float sc = g.scale ? g.scale[k] : 1.0f;
+  const int64_t row0 = (int64_t)rb * BM;
+  const float* Xk = g.X + (int64_t)k * g.I * g.J;
+  const unsigned char* Vc = (const unsigned char*)g.Vpack + (int64_t)cb * g.nchunk * VBYTES;
+
+  // per-thread X source rows (clamped) and swizzled segments, fixed per tile
+  const float* xsrc[XL];
+  int xseg[XL];
+#pragma unroll
+  for (int q = 0; q < XL; ++q) {
+    const int r = (wave * XL + q) * 8 + lane / 8;
+    int64_t gr = row0 + r;
+    if (gr > g.I - 1) gr = g.I - 1;
+    xsrc[q] = Xk + gr * g.J;
+    xseg[q] = (lane % 8) ^ (r % 8);
+  }
+
+  auto issue = [&](int c, int st) {
+    unsigned char* base = smem + st * STAGE;
+#pragma unroll
+    for (int q = 0; q < XL; ++q) {
+      int64_t j = (int64_t)c * KC + xseg[q] * 4;
+      if (j > g.J - 4) j = g.J - 4;
+      __builtin_amdgcn_global_load_lds((gbl_vptr)(xsrc[q] + j),
+                                       (lds_vptr)(base + (wave * XL + q) * 1024), 16, 0, 0);
+    }
+    const unsigned char* vs = Vc + (int64_t)c * VBYTES;
+#pragma unroll
+    for (int q = 0; q < VL; ++q)
+      __builtin_amdgcn_global_load_lds((gbl_vptr)(vs + (q * NT + tid) * 16),
+                                       (lds_vptr)(base + XBYTES + (q * NT + wave * 64) * 16), 16, 0,
+                                       0);
+  };
+
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  const int nchunk = g.nchunk;
+#pragma unroll
+  for (int c = 0; c < NSTAGE - 1; ++c)
+    if (c < nchunk) issue(c, c);
+  for (int c = 0; c < nchunk; ++c) {
+    const int ahead = (nchunk - 1 - c) < (NSTAGE - 2) ? (nchunk - 1 - c) : (NSTAGE - 2);
+    if (ahead >= 2) __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * LPC));
+    else if (ahead == 1) __builtin_amdgcn_s_waitcnt(vmcnt_imm(LPC));
+    else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    // bare barrier: the explicit wait above already covers this chunk's loads;
+    // a full __syncthreads would also wait for the prefetches still in flight
+    __builtin_amdgcn_s_barrier();
+    if (c + NSTAGE - 1 < nchunk) issue(c + NSTAGE - 1, (c + NSTAGE - 1) % NSTAGE);
+    const unsigned char* base = smem + (c % NSTAGE) * STAGE;
+    const float* xs = (const float*)base;
+    const T* b = (const T*)(base + XBYTES);
+#pragma unroll
+    for (int ks = 0; ks < KC / KS; ++ks) {
+      Frag af[2], bfr[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int m = (wm * 2 + i) * 32 + lane % 32;
+        const float* xrow = xs + m * KC;
+        if constexpr (KIND == 2) {
+          const int s0 = ks * 4 + 2 * (lane / 32);
+          const f32x4 lo = *(const f32x4*)(xrow + 4 * (s0 ^ (m % 8)));
+          const f32x4 hi = *(const f32x4*)(xrow + 4 * ((s0 + 1) ^ (m % 8)));
+          bf16x8 f;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            f[e] = (__bf16)(lo[e] * sc);
+            f[4 + e] = (__bf16)(hi[e] * sc);
+          }
+          af[i] = f;
+        } else {
+          const int kk = ks * 2 + lane / 32;
+          af[i] = xrow[4 * ((kk / 4) ^ (m % 8)) + kk % 4] * sc;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        bfr[j] = Kind<KIND>::ld(b + ((ks * (BN / 32) + wn * 4 + j) * 64 + lane) * E);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = Kind<KIND>::mma(af[i], bfr[j], acc[i][j]);
+    }
+  }
+  __syncthreads();
+
+  // ---- stage 2 (as in compress_fused)
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = wn * 128 + j * 32 + lane % 32;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = wm * 64 + i * 32 + 8 * q + 4 * (lane / 32);
+        T* dst = T2t + col * T2LD + r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[e] = cvt<KIND>(acc[i][j][4 * q + e]);
+      }
+    }
+  for (int e = tid; e < T2LD; e += NT) T2t[BN * T2LD + e] = cvt<KIND>(0.f);
+  __syncthreads();
+
+  const int p0 = cb * g.G;
+  const int gcount = (g.P - p0) < g.G ? (g.P - p0) : g.G;
+  const float inv = 1.0f / sc;
+  for (int gg = wave; gg < gcount; gg += 4) {
+    const int p = p0 + gg;
+    f32x16 m[QT][QT];
+#pragma unroll
+    for (int i = 0; i < QT; ++i)
+#pragma unroll
+      for (int j = 0; j < QT; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) m[i][j][e] = 0.f;
+    const T* Up = (const T*)g.Upack + ((int64_t)rb * g.P + p) * (BM / KS) * QT * 64 * E;
+    const int* tc = g.tilecol + ((int64_t)cb * g.G + gg) * QT * 32;
+    int colrow[QT];
+#pragma unroll
+    for (int j = 0; j < QT; ++j) colrow[j] = tc[j * 32 + lane % 32];
+    for (int ks = 0; ks < BM / KS; ++ks) {
+      Frag af[QT];
+#pragma unroll
+      for (int i = 0; i < QT; ++i) af[i] = Kind<KIND>::ld(Up + ((int64_t)(ks * QT + i) * 64 + lane) * E);
+#pragma unroll
+      for (int j = 0; j < QT; ++j) {
+        const Frag bf = Kind<KIND>::ld(T2t + colrow[j] * T2LD + ks * KS + (lane / 32) * E);
+#pragma unroll
+        for (int i = 0; i < QT; ++i) m[i][j] = Kind<KIND>::mma(af[i], bf, m[i][j]);
+      }
+    }
+    float* out = g.Mpart + (((int64_t)k * g.nrb + rb) * g.P + p) * g.Q * g.Q;
+#pragma unroll
+    for (int i = 0; i < QT; ++i)
+#pragma unroll
+      for (int j = 0; j < QT; ++j) {
+        const int bcol = j * 32 + lane % 32;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int arow = i * 32 + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+          if (arow < g.Q && bcol < g.Q) out[arow * g.Q + bcol] = m[i][j][e] * inv;
+        }
+      }
+  }
+}
+
 // V image: [cb][chunk][ks][nt][lane][E]; element V[j][col] with
 // j = c*KC + ks*KS + (lane/32)*E + e (KS = 16) or c*KC + ks*2 + lane/32 (KS = 2).
 template <int KIND>
@@ -328,6 +523,34 @@ hipError_t launch_fused(hipStream_t s, const Args& a, size_t lds) {
   const int per = (a.tiles + 7) / 8;
   hipLaunchKernelGGL(fn, dim3(8 * per), dim3(NT), lds, s, a);
   return hipGetLastError();
+}
+
+template <int KIND, int QT>
+hipError_t launch_pipe(hipStream_t s, const Args& a) {
+  constexpr int NS = KIND == 2 ? 4 : 3;
+  constexpr size_t stage = (size_t)BM * KC * 4 + (size_t)chunk_elems<KIND>(BN / 32) *
+                                                     sizeof(typename Kind<KIND>::T);
+  const size_t t2 = (size_t)(BN + 1) * (BM + 16 / sizeof(typename Kind<KIND>::T)) *
+                    sizeof(typename Kind<KIND>::T);
+  const size_t lds = NS * stage > t2 ? NS * stage : t2;
+  auto fn = compress_pipe<KIND, QT, NS>;
+  hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  const int per = (a.tiles + 7) / 8;
+  hipLaunchKernelGGL(fn, dim3(8 * per), dim3(NT), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int KIND>
+hipError_t launch_pipe_q(hipStream_t s, const Args& a, int QT) {
+  switch (QT) {
+    case 1: return launch_pipe<KIND, 1>(s, a);
+    case 2: return launch_pipe<KIND, 2>(s, a);
+    case 3: return launch_pipe<KIND, 3>(s, a);
+    case 4: return launch_pipe<KIND, 4>(s, a);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int KIND, bool VEC>
@@ -459,10 +682,11 @@ hipError_t compress_mfma_main(hipStream_t s, const MfmaPlan* p, const float* X, 
   a.tiles = (int)tiles;
   const bool vec = (p->sh.J % 4 == 0) && (((uintptr_t)X & 15) == 0);
   hipError_t e;
-  if (p->kind == 1)
-    e = vec ? launch_q<1, true>(s, a, p->QT, p->lds) : launch_q<1, false>(s, a, p->QT, p->lds);
+  // the pipelined kernel needs 16-byte rows chunks: J % 4 == 0 and aligned X
+  if (vec)
+    e = p->kind == 1 ? launch_pipe_q<1>(s, a, p->QT) : launch_pipe_q<2>(s, a, p->QT);
   else
-    e = vec ? launch_q<2, true>(s, a, p->QT, p->lds) : launch_q<2, false>(s, a, p->QT, p->lds);
+    e = p->kind == 1 ? launch_q<1, false>(s, a, p->QT, p->lds) : launch_q<2, false>(s, a, p->QT, p->lds);
   return e;
 }
 

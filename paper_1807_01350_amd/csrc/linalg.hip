@@ -119,60 +119,66 @@ __global__ void gj_update(double* __restrict__ A, int n, int k, const double* __
 }
 
 // One workgroup: in-place Cholesky of N (lower factor), then two triangular
-// solves for nrhs right-hand sides.
+// solves for nrhs right-hand sides.  One barrier per column: step j updates
+// the trailing lower triangle from the still unscaled column j divided by the
+// pivot, and scales column j - 1 (nobody reads it any more) in the same pass.
+// The substitutions write each solved row into Z and update the remaining
+// rows from the unsolved value, again one barrier per step.
 __global__ __launch_bounds__(1024) void spd_solve_kernel(double* __restrict__ Nm, int n,
                                                          double* __restrict__ Bm, int nrhs,
-                                                         int* info) {
+                                                         double* __restrict__ Z, int* info) {
   __shared__ int bad;
   const int tid = threadIdx.x, nt = blockDim.x;
   if (tid == 0) bad = 0;
   __syncthreads();
   for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      double dv = Nm[(int64_t)j * n + j];
-      if (!(dv > 0.0)) { bad = j + 1; dv = 1.0; }
-      Nm[(int64_t)j * n + j] = sqrt(dv);
+    const double djj = Nm[(int64_t)j * n + j];
+    if (tid == 0 && !(djj > 0.0) && !bad) bad = j + 1;
+    const double inv = djj > 0.0 ? 1.0 / djj : 0.0;
+    // scale column j - 1 by its pivot (kept on the diagonal until now)
+    if (j > 0) {
+      const double lp = sqrt(fmax(Nm[(int64_t)(j - 1) * n + (j - 1)], 1e-300));
+      for (int i = j + tid; i < n; i += nt) Nm[(int64_t)i * n + (j - 1)] /= lp;
     }
-    __syncthreads();
-    const double ljj = Nm[(int64_t)j * n + j];
-    for (int i = j + 1 + tid; i < n; i += nt) Nm[(int64_t)i * n + j] /= ljj;
-    __syncthreads();
     const int m = n - j - 1;
     const int64_t tri = (int64_t)m * (m + 1) / 2;
     for (int64_t e = tid; e < tri; e += nt) {
-      // e -> (ii, kk) with 0 <= kk <= ii < m (row-major lower triangle)
       int ii = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
       while ((int64_t)ii * (ii + 1) / 2 > e) --ii;
       while ((int64_t)(ii + 1) * (ii + 2) / 2 <= e) ++ii;
-      int kk = (int)(e - (int64_t)ii * (ii + 1) / 2);
-      int gi = j + 1 + ii, gk = j + 1 + kk;
-      Nm[(int64_t)gi * n + gk] -= Nm[(int64_t)gi * n + j] * Nm[(int64_t)gk * n + j];
+      const int kk = (int)(e - (int64_t)ii * (ii + 1) / 2);
+      const int gi = j + 1 + ii, gk = j + 1 + kk;
+      Nm[(int64_t)gi * n + gk] -= Nm[(int64_t)gi * n + j] * Nm[(int64_t)gk * n + j] * inv;
     }
     __syncthreads();
   }
-  // forward: L y = b
+  // the diagonal becomes the factor's diagonal (the last column has nothing below it)
+  for (int j = tid; j < n; j += nt) Z[j] = sqrt(fmax(Nm[(int64_t)j * n + j], 1e-300));
+  __syncthreads();
+  for (int j = tid; j < n; j += nt) Nm[(int64_t)j * n + j] = Z[j];
+  __syncthreads();
+  // forward: L y = b; row j solved into Bm (scaled) while the rest is updated
   for (int j = 0; j < n; ++j) {
     const double ljj = Nm[(int64_t)j * n + j];
-    for (int c = tid; c < nrhs; c += nt) Bm[(int64_t)j * nrhs + c] /= ljj;
-    __syncthreads();
     const int64_t tot = (int64_t)(n - j - 1) * nrhs;
     for (int64_t e = tid; e < tot; e += nt) {
-      int i = j + 1 + (int)(e / nrhs), c = (int)(e % nrhs);
-      Bm[(int64_t)i * nrhs + c] -= Nm[(int64_t)i * n + j] * Bm[(int64_t)j * nrhs + c];
+      const int i = j + 1 + (int)(e / nrhs), c = (int)(e % nrhs);
+      Bm[(int64_t)i * nrhs + c] -= Nm[(int64_t)i * n + j] * (Bm[(int64_t)j * nrhs + c] / ljj);
     }
     __syncthreads();
+    for (int c = tid; c < nrhs; c += nt) Bm[(int64_t)j * nrhs + c] /= ljj;
   }
+  __syncthreads();
   // backward: L^T x = y
   for (int j = n - 1; j >= 0; --j) {
     const double ljj = Nm[(int64_t)j * n + j];
-    for (int c = tid; c < nrhs; c += nt) Bm[(int64_t)j * nrhs + c] /= ljj;
-    __syncthreads();
     const int64_t tot = (int64_t)j * nrhs;
     for (int64_t e = tid; e < tot; e += nt) {
-      int i = (int)(e / nrhs), c = (int)(e % nrhs);
-      Bm[(int64_t)i * nrhs + c] -= Nm[(int64_t)j * n + i] * Bm[(int64_t)j * nrhs + c];
+      const int i = (int)(e / nrhs), c = (int)(e % nrhs);
+      Bm[(int64_t)i * nrhs + c] -= Nm[(int64_t)j * n + i] * (Bm[(int64_t)j * nrhs + c] / ljj);
     }
     __syncthreads();
+    for (int c = tid; c < nrhs; c += nt) Bm[(int64_t)j * nrhs + c] /= ljj;
   }
   if (tid == 0 && bad && *info == 0) *info = bad;
 }
@@ -270,9 +276,10 @@ hipError_t spd_invert(hipStream_t s, double* A, int n, double* work, int* info) 
   return hipGetLastError();
 }
 
-hipError_t spd_solve_small(hipStream_t s, double* N, int n, double* Bm, int nrhs, int* info) {
+hipError_t spd_solve_small(hipStream_t s, double* N, int n, double* Bm, int nrhs, double* work,
+                           int* info) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(spd_solve_kernel, dim3(1), dim3(1024), 0, s, N, n, Bm, nrhs, info);
+  hipLaunchKernelGGL(spd_solve_kernel, dim3(1), dim3(1024), 0, s, N, n, Bm, nrhs, work, info);
   return hipGetLastError();
 }
 
@@ -312,4 +319,66 @@ hipError_t any_nonfinite(hipStream_t s, const void* x, int64_t n, bool f64, int*
   return hipGetLastError();
 }
 
+}  // namespace octen
+
+// ---------------------------------------------------------------------------
+// Products with a small output width: out(i, r) = alpha * sum_k A(i,k) d(k) B(k,r)
+// + beta * out(i, r) for r < ncols (<= any), one wavefront per (row i, block of
+// 32 columns); lanes split k, partial sums meet in a butterfly.  Operands are
+// strided: A(i,k) = A[i*sai + k*sak], B(k,r) = B[k*sbk + r*sbr].
+namespace octen {
+namespace {
+__global__ __launch_bounds__(256) void rowdot_kernel(int64_t nrows, int ncols, int64_t K,
+                                                     const double* __restrict__ A, int64_t sai,
+                                                     int64_t sak, const double* __restrict__ B,
+                                                     int64_t sbk, int64_t sbr,
+                                                     const double* __restrict__ d, double alpha,
+                                                     double beta, double* __restrict__ out,
+                                                     int64_t ldo) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  const int nblk = (ncols + 31) / 32;
+  if (wid >= nrows * nblk) return;
+  const int64_t i = wid / nblk;
+  const int r0 = (int)(wid % nblk) * 32;
+  const int nr = ncols - r0 < 32 ? ncols - r0 : 32;
+  double acc[32];
+#pragma unroll
+  for (int r = 0; r < 32; ++r) acc[r] = 0.0;
+  const double* a = A + i * sai;
+  for (int64_t k = lane; k < K; k += 64) {
+    double av = a[k * sak];
+    if (d) av *= d[k];
+    const double* b = B + k * sbk + (int64_t)r0 * sbr;
+#pragma unroll
+    for (int r = 0; r < 32; ++r)
+      if (r < nr) acc[r] = fma(av, b[r * sbr], acc[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < 32; ++r) {
+    if (r < nr) {
+      double v = acc[r];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      acc[r] = v;
+    }
+  }
+  if (lane == 0) {
+    double* o = out + i * ldo + r0;
+#pragma unroll
+    for (int r = 0; r < 32; ++r)
+      if (r < nr) o[r] = beta != 0.0 ? alpha * acc[r] + beta * o[r] : alpha * acc[r];
+  }
+}
+}  // namespace
+
+hipError_t rowdot(hipStream_t s, int64_t nrows, int ncols, int64_t K, const double* A, int64_t sai,
+                  int64_t sak, const double* B, int64_t sbk, int64_t sbr, const double* d,
+                  double alpha, double beta, double* out, int64_t ldo) {
+  if (nrows <= 0 || ncols <= 0) return hipSuccess;
+  const int64_t waves = nrows * ((ncols + 31) / 32);
+  const int64_t blocks = (waves + 3) / 4;
+  hipLaunchKernelGGL(rowdot_kernel, dim3((unsigned)blocks), dim3(256), 0, s, nrows, ncols, K, A, sai,
+                     sak, B, sbk, sbr, d, alpha, beta, out, ldo);
+  return hipGetLastError();
+}
 }  // namespace octen

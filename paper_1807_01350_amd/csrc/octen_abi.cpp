@@ -558,17 +558,15 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, i
   HIPCHK(h, rec_align(s, P, Q, R, S, h->F, h->lam, h->aligned, h->perm, h->margin));
   HIPCHK(h, rec_stack(s, P, Q, R, S, h->aligned, h->rhs));
   // Eq. 7 for modes 1 and 2
-  HIPCHK(h, gemm_f64(s, (int)I, R, M1, 1, h->OpA, M1, 1, 0, h->rhs, R, 1, 0, h->Araw, R, 1, 0,
-                     nullptr, 1.0, 0.0));
-  HIPCHK(h, gemm_f64(s, (int)J, R, M1, 1, h->OpB, M1, 1, 0, h->rhs + (int64_t)M1 * R, R, 1, 0,
-                     h->Braw, R, 1, 0, nullptr, 1.0, 0.0));
+  HIPCHK(h, rowdot(s, I, R, M1, h->OpA, M1, 1, h->rhs, R, 1, nullptr, 1.0, 0.0, h->Araw, R));
+  HIPCHK(h, rowdot(s, J, R, M1, h->OpB, M1, 1, h->rhs + (int64_t)M1 * R, R, 1, nullptr, 1.0, 0.0,
+                   h->Braw, R));
   HIPCHK(h, rec_canon(s, I, R, h->Araw, h->Ac, h->ka));
   HIPCHK(h, rec_canon(s, J, R, h->Braw, h->Bc, h->kb));
   if (h->have_prev) {
-    HIPCHK(h, gemm_f64(s, R, R, (int)I, 1, h->Ac, 1, R, 0, h->Aprev, R, 1, 0, h->cross, R, 1, 0,
-                       nullptr, 1.0, 0.0));
-    HIPCHK(h, gemm_f64(s, R, R, (int)J, 1, h->Bc, 1, R, 0, h->Bprev, R, 1, 0, h->cross + R * R, R,
-                       1, 0, nullptr, 1.0, 0.0));
+    HIPCHK(h, rowdot(s, R, R, I, h->Ac, 1, R, h->Aprev, R, 1, nullptr, 1.0, 0.0, h->cross, R));
+    HIPCHK(h, rowdot(s, R, R, J, h->Bc, 1, R, h->Bprev, R, 1, nullptr, 1.0, 0.0, h->cross + R * R,
+                     R));
     HIPCHK(h, rec_col_norms(s, I, R, h->Ac, h->norms));
     HIPCHK(h, rec_col_norms(s, I, R, h->Aprev, h->norms + R));
     HIPCHK(h, rec_col_norms(s, J, R, h->Bc, h->norms + 2 * R));
@@ -582,11 +580,9 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, i
   OKCHK(dgrow(h, &h->bt, &h->bt_cap, (t > M1 ? t : (int64_t)M1) * R));
   if (t <= M1) {
     OKCHK(dgrow(h, &h->Nt, &h->Nt_cap, t * t));
-    HIPCHK(h, gemm_f64(s, (int)t, (int)t, M1, 1, h->Wp, M1, 1, 0, h->Wp, 1, M1, 0, h->Nt, t, 1, 0,
-                       h->w2, 1.0, 0.0));
-    HIPCHK(h, gemm_f64(s, (int)t, R, M1, 1, h->Wp, M1, 1, 0, h->rhs_c, R, 1, 0, h->bt, R, 1, 0,
-                       h->w2, 1.0, 0.0));
-    HIPCHK(h, spd_solve_small(s, h->Nt, (int)t, h->bt, R, h->info));
+    HIPCHK(h, rowdot(s, t, (int)t, M1, h->Wp, M1, 1, h->Wp, 1, M1, h->w2, 1.0, 0.0, h->Nt, t));
+    HIPCHK(h, rowdot(s, t, R, M1, h->Wp, M1, 1, h->rhs_c, R, 1, h->w2, 1.0, 0.0, h->bt, R));
+    HIPCHK(h, spd_solve_small(s, h->Nt, (int)t, h->bt, R, h->gj_work, h->info));
   } else {
     OKCHK(dgrow(h, &h->Nt, &h->Nt_cap, (int64_t)M1 * M1 + (int64_t)M1 * R));
     double* y = h->Nt + (int64_t)M1 * M1;
@@ -595,7 +591,7 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, i
     HIPCHK(h, scale_rows_cols(s, h->Nt, M1, h->w));
     HIPCHK(h, hipMemcpyAsync(y, h->rhs_c, (size_t)M1 * R * 8, hipMemcpyDeviceToDevice, s));
     HIPCHK(h, scale_rows(s, y, M1, R, h->w));
-    HIPCHK(h, spd_solve_small(s, h->Nt, M1, y, R, h->info));
+    HIPCHK(h, spd_solve_small(s, h->Nt, M1, y, R, h->gj_work, h->info));
     HIPCHK(h, gemm_f64(s, (int)t, R, M1, 1, h->Wp, M1, 1, 0, y, R, 1, 0, h->bt, R, 1, 0, h->w, 1.0,
                        0.0));
   }
@@ -617,8 +613,7 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, i
                                 h->Ctmp, h->have_prev ? 1 : 0));
   // H = Hcur + W^T C_new (canonical convention)
   HIPCHK(h, hipMemcpyAsync(h->H, h->Hcur, (size_t)M1 * R * 8, hipMemcpyDeviceToDevice, s));
-  HIPCHK(h, gemm_f64(s, M1, R, (int)t, 1, h->Wp, 1, M1, 0, h->bt, R, 1, 0, h->H, R, 1, 0, nullptr,
-                     1.0, 1.0));
+  HIPCHK(h, rowdot(s, M1, R, t, h->Wp, 1, M1, h->bt, R, 1, nullptr, 1.0, 1.0, h->H, R));
   HIPCHK(h, hipMemcpyAsync(h->Aprev, h->Ac, I * R * 8, hipMemcpyDeviceToDevice, s));
   HIPCHK(h, hipMemcpyAsync(h->Bprev, h->Bc, J * R * 8, hipMemcpyDeviceToDevice, s));
   HIPCHK(h, hipMemcpyAsync(A, h->Ac, I * R * 8, hipMemcpyDeviceToDevice, s));

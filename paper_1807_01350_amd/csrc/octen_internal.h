@@ -28,9 +28,17 @@ hipError_t gemm_f32in_f64(hipStream_t s, int M, int N, int K, int batch,
 // info (device int) is set to k+1 if pivot k is not positive.
 hipError_t spd_invert(hipStream_t s, double* A, int n, double* work, int* info);
 
+// out(i, r) = alpha * sum_k A(i,k) d(k) B(k,r) + beta * out(i, r), i < nrows,
+// r < ncols; A(i,k) = A[i*sai + k*sak], B(k,r) = B[k*sbk + r*sbr]; d may be
+// null.  One wavefront per row and block of 32 columns (small outputs, long k).
+hipError_t rowdot(hipStream_t s, int64_t nrows, int ncols, int64_t K, const double* A, int64_t sai,
+                  int64_t sak, const double* B, int64_t sbk, int64_t sbr, const double* d,
+                  double alpha, double beta, double* out, int64_t ldo);
+
 // One-workgroup Cholesky solve of N X = Bm (N: n x n, Bm: n x nrhs, both
-// row-major, overwritten: N by its factor, Bm by the solution).
-hipError_t spd_solve_small(hipStream_t s, double* N, int n, double* Bm, int nrhs, int* info);
+// row-major, overwritten: N by its factor, Bm by the solution); work: n doubles.
+hipError_t spd_solve_small(hipStream_t s, double* N, int n, double* Bm, int nrhs, double* work,
+                           int* info);
 
 hipError_t fill_f64(hipStream_t s, double* p, int64_t n, double v);
 hipError_t fill_i32(hipStream_t s, int* p, int64_t n, int v);
