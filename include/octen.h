@@ -73,7 +73,15 @@ enum {
   OCTEN_STATE_TPERM = 8,    /* [R] int32 column pairing with previous batch   */
   OCTEN_STATE_ITERS = 9,    /* [P] int32 ALS sweeps done                      */
   OCTEN_STATE_MARGIN = 10,  /* [P] f64 matching margin (replica 0: +inf)      */
-  OCTEN_STATE_FLAGS = 11    /* [P] int32 health flags, bit0 solve fallback    */
+  OCTEN_STATE_FLAGS = 11,   /* [P] int32 health flags, bit0 solve fallback    */
+  /* bookkeeping of the last sparse batch (octen_compress_batch_coo); a
+   * segment is one distinct (k, i) pair, numbered in input order */
+  OCTEN_STATE_COO_SIZES = 12,     /* [2] int32: nseg, t                      */
+  OCTEN_STATE_COO_SEG_START = 13, /* [nseg+1] int32 first nonzero of each
+                                     segment, then nnz                       */
+  OCTEN_STATE_COO_SEG_ROW = 14,   /* [nseg] int32 row i of each segment      */
+  OCTEN_STATE_COO_SLICE_SEG = 15  /* [t+1] int32 first segment of each slice,
+                                     then nseg                               */
 };
 
 /* Flags (octen_config.flags). */
@@ -88,7 +96,8 @@ enum {
   OCTEN_STAGE_UPDATE = 2,
   OCTEN_STAGE_ALS = 3,
   OCTEN_STAGE_RECOVER = 4,
-  OCTEN_NUM_STAGES = 5
+  OCTEN_STAGE_COO_INDEX = 5,       /* checks and segments of a sparse batch   */
+  OCTEN_NUM_STAGES = 6
 };
 
 typedef struct {
@@ -126,7 +135,11 @@ octen_status octen_compress_batch(octen_t h, const void* X, int64_t t, const dou
 
 /* Same for a sparse batch given as sorted COO (by k, then i, then j) with
  * slice indices k in [0, t) relative to the batch.  k, i, j: [nnz] int32,
- * v: [nnz] f32.  Duplicated coordinates add up. */
+ * v: [nnz] f32, all device arrays; 0 <= nnz < 2^31.  Duplicated coordinates
+ * add up.  The coordinates are checked on the device first (synchronises):
+ * OCTEN_ERR_ARG if one is out of range or the order is violated.  The
+ * summaries are dense (Sec. 4.1): f64 arithmetic for compress_dtype F64,
+ * f32 gathers and MFMA f32 accumulation otherwise (also for BF16). */
 octen_status octen_compress_batch_coo(octen_t h, int64_t nnz, const int32_t* k,
                                       const int32_t* i, const int32_t* j, const float* v,
                                       int64_t t, const double* W);
@@ -161,6 +174,18 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C,
  * fit = 1 - sqrt(out[0] / out[1]) over all slices. */
 octen_status octen_fit(octen_t h, const void* X, int64_t t, int64_t k0, const double* A,
                        const double* B, const double* C, double* out_host);
+
+/* Sec. 5.1 fitness of a sparse tensor through
+ * ||X - Xh||^2 = ||X||^2 - 2 <X, Xh> + sum((A^T A) * (B^T B) * (C^T C)).
+ * Nonzeros as in octen_compress_batch_coo (bounds are checked, order is not),
+ * slice k of the nonzeros is row k0 + k of C, k0 + k < kc.  out_host (f64,
+ * synchronises): [0] += sum v^2, [1] += sum v * Xh over the given nonzeros;
+ * [2] = sum of (A^T A) * (B^T B) * (C^T C) with C over its rows [0, kc)
+ * (set, not accumulated).  Over all nonzeros of the tensor:
+ * fit = 1 - sqrt(max(out[0] - 2 out[1] + out[2], 0) / out[0]). */
+octen_status octen_fit_coo(octen_t h, int64_t nnz, const int32_t* k, const int32_t* i,
+                           const int32_t* j, const float* v, int64_t k0, const double* A,
+                           const double* B, const double* C, int64_t kc, double* out_host);
 
 /* Copy one internal array (OCTEN_STATE_*) into dst (device), bytes must be
  * at least its size. */

@@ -41,7 +41,8 @@ import math
 import numpy as np
 
 __all__ = [
-    "replica_cols", "compress_dense", "compress_coo", "update_summaries",
+    "replica_cols", "compress_dense", "compress_coo", "coo_segments",
+    "compress_coo_entries", "update_summaries",
     "mttkrp", "gram_hadamard", "solve_normal", "cp_als", "replica_fit",
     "distribute_lambda", "greedy_assign", "match_replicas", "stack_rhs",
     "weighted_minnorm_lstsq", "canonicalize", "match_previous",
@@ -101,6 +102,41 @@ def compress_coo(k, i, j, v, t, U, V, W, P, Q, S):
             M[kk] = (Up[i[sel]] * v[sel, None]).T @ Vp[j[sel]]
         Z[p] = np.tensordot(M, Wp, axes=([0], [0]))
     return Z
+
+
+def coo_segments(k, i, t):
+    """Bookkeeping of a COO batch sorted by (k, i, j) (Sec. 4.1 sparse input).
+    A segment is a maximal run of nonzeros sharing (k, i), numbered in input
+    order.  Returns int64 arrays seg_start [nseg + 1] (first nonzero of each
+    segment, then nnz), seg_row [nseg] (its i) and slice_seg [t + 1] (number
+    of segments of slices before x, for x = 0..t)."""
+    k = np.asarray(k, np.int64); i = np.asarray(i, np.int64)
+    nnz = k.size
+    head = np.ones(nnz, bool)
+    if nnz > 1:
+        head[1:] = (k[1:] != k[:-1]) | (i[1:] != i[:-1])
+    starts = np.flatnonzero(head)
+    seg_start = np.append(starts, nnz).astype(np.int64)
+    seg_row = i[starts]
+    seg_slice = k[starts]
+    slice_seg = np.array([np.count_nonzero(seg_slice < x) for x in range(t + 1)], np.int64)
+    return seg_start, seg_row, slice_seg
+
+
+def compress_coo_entries(k, i, j, v, t, U, V, W, P, Q, S, picks):
+    """Selected fibres of the compressed batch, one at a time: for each
+    (p, a, b) in picks, Z_p[a, b, :] = sum_k m_k W_p(k, :) with
+    m_k = sum over the nonzeros of slice k of v U_p(i, a) V_p(j, b)
+    (Eq. 1 written entrywise for one mode-1 and one mode-2 index)."""
+    k = np.asarray(k, np.int64); i = np.asarray(i, np.int64); j = np.asarray(j, np.int64)
+    v = np.asarray(v, np.float64)
+    out = []
+    for p, a, b in picks:
+        c = replica_cols(P, Q, S, p)
+        m = np.zeros(t)
+        np.add.at(m, k, v * U[i, c[a]] * V[j, c[b]])
+        out.append(m @ W[:, c])
+    return np.array(out)
 
 
 def update_summaries(Y, Z):

@@ -69,6 +69,18 @@ struct octen_ctx {
   double* partials = nullptr;
   double* fit_out = nullptr;
   double* gj_work = nullptr;
+  // sparse batches
+  int* coo_work = nullptr;  int64_t coo_work_cap = 0;
+  int* seg_start = nullptr; int64_t seg_start_cap = 0;
+  int* seg_row = nullptr;   int64_t seg_row_cap = 0;
+  int* seg_slice = nullptr; int64_t seg_slice_cap = 0;
+  int* slice_seg = nullptr; int64_t slice_seg_cap = 0;
+  int* coo_small = nullptr;          // [4]: error bits, nseg, t, unused
+  int coo_nseg = -1;                 // segments of the last sparse batch
+  int64_t coo_t = 0;
+  float *Uf = nullptr, *Vf = nullptr;            // f32 copies for sparse gathers
+  float* Mkf = nullptr; int64_t Mkf_cap = 0;     // [t][P][Q][Q] f32
+  double* fitG = nullptr;                        // [3][R][R] Gram matrices
 
   std::vector<void*> allocs;
 
@@ -325,7 +337,9 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
   IOK(dalloc(h, &h->Hcur, M1 * R));
   IOK(dalloc(h, &h->info, 1));
   IOK(dalloc(h, &h->partials, 2 * FIT_PARTS));
-  IOK(dalloc(h, &h->fit_out, 2));
+  IOK(dalloc(h, &h->fit_out, 3));
+  IOK(dalloc(h, &h->coo_small, 4));
+  IOK(dalloc(h, &h->fitG, 3 * R * R));
   IOK(dalloc(h, &h->gj_work, 2 * (I > J ? (I > M1 ? I : M1) : (J > M1 ? J : M1))));
   hipStream_t s = h->stream;
   auto hip_ok = [&](hipError_t e, const char* what) {
@@ -463,8 +477,65 @@ octen_status octen_compress_batch(octen_t h, const void* X, int64_t t, const dou
 octen_status octen_compress_batch_coo(octen_t h, int64_t nnz, const int32_t* k, const int32_t* i,
                                       const int32_t* j, const float* v, int64_t t, const double* W) {
   if (!h) return OCTEN_ERR_ARG;
-  (void)nnz; (void)k; (void)i; (void)j; (void)v; (void)t; (void)W;
-  return fail(h, OCTEN_ERR_UNSUPPORTED, "sparse compression not built yet");
+  if (!W || t < 1) return fail(h, OCTEN_ERR_ARG, "W must be non-null and t >= 1");
+  if (t > (1 << 24)) return fail(h, OCTEN_ERR_ARG, "t too large");
+  if (nnz < 0 || nnz >= 0x7fffffffLL) return fail(h, OCTEN_ERR_ARG, "nnz must be in [0, 2^31 - 1)");
+  if (nnz > 0 && (!k || !i || !j || !v)) return fail(h, OCTEN_ERR_ARG, "k, i, j, v must be non-null");
+  hipStream_t s = h->stream;
+  const int64_t M1 = h->M1, P = h->P, Q = h->Q;
+  OKCHK(dgrow(h, &h->coo_work, &h->coo_work_cap, (int64_t)coo_work_ints(nnz)));
+  OKCHK(dgrow(h, &h->seg_start, &h->seg_start_cap, nnz + 1));
+  OKCHK(dgrow(h, &h->seg_row, &h->seg_row_cap, nnz));
+  OKCHK(dgrow(h, &h->seg_slice, &h->seg_slice_cap, nnz));
+  OKCHK(dgrow(h, &h->slice_seg, &h->slice_seg_cap, t + 1));
+  {
+    StageTimer tm(h, OCTEN_STAGE_COO_INDEX);
+    HIPCHK(h, fill_i32(s, h->coo_small, 4, 0));
+    HIPCHK(h, coo_check(s, nnz, k, i, j, t, h->I, h->J, true, h->coo_small));
+    HIPCHK(h, coo_segments(s, nnz, k, i, t, h->coo_work, h->seg_start, h->seg_row, h->seg_slice,
+                           h->slice_seg, h->coo_small + 1));
+    HIPCHK(h, fill_i32(s, h->coo_small + 2, 1, (int)t));
+  }
+  int hs[2] = {0, 0};
+  HIPCHK(h, hipMemcpyAsync(hs, h->coo_small, sizeof(hs), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (hs[0] & 1) return fail(h, OCTEN_ERR_ARG, "COO coordinate out of range");
+  if (hs[0] & 2) return fail(h, OCTEN_ERR_ARG, "COO entries not sorted by (k, i, j)");
+  h->coo_nseg = hs[1];
+  h->coo_t = t;
+  OKCHK(dgrow(h, &h->Wz, &h->Wz_cap, t * M1));
+  HIPCHK(h, hipMemcpyAsync(h->Wz, W, t * M1 * 8, hipMemcpyDeviceToDevice, s));
+  CompressShape sh{h->I, h->J, h->P, h->Q, h->S, h->M1};
+  const bool f64 = h->cfg.compress_dtype == OCTEN_F64;
+  const void *Um = h->U, *Vm = h->V;
+  void* Mk = nullptr;
+  if (f64) {
+    OKCHK(dgrow(h, &h->Mk, &h->Mk_cap, t * P * Q * Q));
+    Mk = h->Mk;
+  } else {
+    if (!h->Uf) {
+      OKCHK(dalloc(h, &h->Uf, (size_t)(h->I * M1)));
+      OKCHK(dalloc(h, &h->Vf, (size_t)(h->J * M1)));
+      HIPCHK(h, convert_f64_to_f32(s, h->U, h->Uf, h->I * M1));
+      HIPCHK(h, convert_f64_to_f32(s, h->V, h->Vf, h->J * M1));
+    }
+    OKCHK(dgrow(h, &h->Mkf, &h->Mkf_cap, t * P * Q * Q));
+    Um = h->Uf;
+    Vm = h->Vf;
+    Mk = h->Mkf;
+  }
+  {
+    StageTimer tm(h, OCTEN_STAGE_COMPRESS_MAIN);
+    HIPCHK(h, coo_compress(s, f64, t, h->P, h->Q, h->S, h->M1, h->seg_start, h->seg_row,
+                           h->slice_seg, j, v, Vm, Um, Mk));
+  }
+  {
+    StageTimer tm(h, OCTEN_STAGE_COMPRESS_MODE3);
+    HIPCHK(h, compress_mode3(s, sh, t, Mk, f64, h->Wz, h->Z, h->acc_f64));
+  }
+  h->z_ready = true;
+  h->t_z = t;
+  return OCTEN_OK;
 }
 
 octen_status octen_update_replicas(octen_t h) {
@@ -648,6 +719,32 @@ octen_status octen_fit(octen_t h, const void* X, int64_t t, int64_t k0, const do
   return OCTEN_OK;
 }
 
+octen_status octen_fit_coo(octen_t h, int64_t nnz, const int32_t* k, const int32_t* i,
+                           const int32_t* j, const float* v, int64_t k0, const double* A,
+                           const double* B, const double* C, int64_t kc, double* out_host) {
+  if (!h) return OCTEN_ERR_ARG;
+  if (!A || !B || !C || !out_host || k0 < 0 || kc < 1 || nnz < 0 || nnz >= 0x7fffffffLL)
+    return fail(h, OCTEN_ERR_ARG, "bad sparse fit arguments");
+  if (nnz > 0 && (!k || !i || !j || !v)) return fail(h, OCTEN_ERR_ARG, "k, i, j, v must be non-null");
+  if (nnz > 0 && k0 >= kc) return fail(h, OCTEN_ERR_ARG, "k0 must be < kc");
+  hipStream_t s = h->stream;
+  HIPCHK(h, fill_i32(s, h->coo_small, 1, 0));
+  HIPCHK(h, coo_check(s, nnz, k, i, j, kc - k0, h->I, h->J, false, h->coo_small));
+  int bad = 0;
+  HIPCHK(h, hipMemcpyAsync(&bad, h->coo_small, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (bad) return fail(h, OCTEN_ERR_ARG, "COO coordinate out of range");
+  HIPCHK(h, fit_coo(s, nnz, k, i, j, v, k0, h->I, h->J, kc, h->R, A, B, C, h->fitG, h->partials,
+                    FIT_PARTS, h->fit_out));
+  double o[3];
+  HIPCHK(h, hipMemcpyAsync(o, h->fit_out, sizeof(o), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  out_host[0] += o[0];
+  out_host[1] += o[1];
+  out_host[2] = o[2];
+  return OCTEN_OK;
+}
+
 octen_status octen_stage_times(octen_t h, int32_t stage, double* ms_host, int32_t n,
                                int32_t* count_host) {
   if (!h || !ms_host || !count_host || n < 0) return OCTEN_ERR_ARG;
@@ -688,6 +785,16 @@ octen_status octen_get_state(octen_t h, int32_t what, void* dst, size_t bytes) {
     case OCTEN_STATE_ITERS: src = h->iters; n = P * 4; break;
     case OCTEN_STATE_MARGIN: src = h->margin; n = P * 8; break;
     case OCTEN_STATE_FLAGS: src = h->flags; n = P * 4; break;
+    case OCTEN_STATE_COO_SIZES:
+    case OCTEN_STATE_COO_SEG_START:
+    case OCTEN_STATE_COO_SEG_ROW:
+    case OCTEN_STATE_COO_SLICE_SEG:
+      if (h->coo_nseg < 0) return fail(h, OCTEN_ERR_STATE, "no sparse batch compressed yet");
+      if (what == OCTEN_STATE_COO_SIZES) { src = h->coo_small + 1; n = 2 * 4; }
+      if (what == OCTEN_STATE_COO_SEG_START) { src = h->seg_start; n = ((size_t)h->coo_nseg + 1) * 4; }
+      if (what == OCTEN_STATE_COO_SEG_ROW) { src = h->seg_row; n = (size_t)h->coo_nseg * 4; }
+      if (what == OCTEN_STATE_COO_SLICE_SEG) { src = h->slice_seg; n = ((size_t)h->coo_t + 1) * 4; }
+      break;
     default: return fail(h, OCTEN_ERR_ARG, "unknown state id");
   }
   if (bytes < n) return fail(h, OCTEN_ERR_ARG, "destination too small");

@@ -128,6 +128,31 @@ hipError_t rec_temporal_finish(hipStream_t s, int R, int64_t Kold, int64_t t, co
 // Row weights of the deduplicated stack: sqrt(P) on the first S rows.
 hipError_t rec_weights(hipStream_t s, int M1, int S, int P, double* w, double* w2);
 
+// ---------------------------------------------------------------- sparse ---
+// COO batches sorted by (k, i, j).  bad |= 1 for a coordinate outside
+// [0,t) x [0,I) x [0,J), |= 2 for an order violation (if check_order).
+hipError_t coo_check(hipStream_t s, int64_t nnz, const int* k, const int* i, const int* j,
+                     int64_t t, int64_t I, int64_t J, bool check_order, int* bad);
+// Ints of scratch needed by coo_segments.
+size_t coo_work_ints(int64_t nnz);
+// Segments = distinct (k, i) pairs in input order: seg_start [nseg + 1]
+// (last = nnz), seg_row, seg_slice [nseg], slice_seg [t + 1]; nseg_dev gets
+// the count.  Arrays sized for nseg = nnz.
+hipError_t coo_segments(hipStream_t s, int64_t nnz, const int* k, const int* i, int64_t t,
+                        int* work, int* seg_start, int* seg_row, int* seg_slice, int* slice_seg,
+                        int* nseg_dev);
+// M[k][p][Q][Q] (f64 or f32, with U, V of the same type, [n][M1]) from the
+// segments; one workgroup per (slice, replica).
+hipError_t coo_compress(hipStream_t s, bool f64, int64_t t, int P, int Q, int S, int M1,
+                        const int* seg_start, const int* seg_row, const int* slice_seg,
+                        const int* j, const float* v, const void* Vm, const void* Um, void* Mout);
+// out3 = (sum v^2, sum v * Xh, sum (A^T A)*(B^T B)*(C[0:kc]^T C[0:kc])); G: 3 R^2
+// doubles, partials: 2 * nparts doubles.
+hipError_t fit_coo(hipStream_t s, int64_t nnz, const int* k, const int* i, const int* j,
+                   const float* v, int64_t k0, int64_t I, int64_t J, int64_t kc, int R,
+                   const double* A, const double* B, const double* C, double* G, double* partials,
+                   int nparts, double* out3);
+
 // ------------------------------------------------------------------- fit ---
 hipError_t fit_dense(hipStream_t s, const void* X, bool x_f64, int64_t t, int64_t I, int64_t J,
                      int R, int64_t k0, const double* A, const double* B, const double* C,

@@ -3,7 +3,9 @@ of the update runs in the HIP library; torch supplies device memory and the
 stream.  The functions carry the C names; `Octen` wraps a handle.
 
 Importing this module loads the built library and fails loudly if it is
-missing: there is no fallback implementation.
+missing: there is no fallback implementation.  torch is imported first so
+that the library binds to the HIP runtime torch has loaded: a process must
+hold one HIP runtime, or device memory from one is unknown to the other.
 """
 from __future__ import annotations
 
@@ -11,6 +13,7 @@ import ctypes
 import os
 
 import numpy as np
+import torch  # noqa: F401  (must precede the library load, see above)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libocten.so")
@@ -28,12 +31,13 @@ OCTEN_F64, OCTEN_F32, OCTEN_BF16, OCTEN_F16 = range(4)
 OCTEN_INIT_GIVEN, OCTEN_INIT_PREV = 0, 1
 (OCTEN_STATE_Y, OCTEN_STATE_Z, OCTEN_STATE_FACTORS, OCTEN_STATE_LAMBDA, OCTEN_STATE_PERM,
  OCTEN_STATE_ALIGNED, OCTEN_STATE_RHS, OCTEN_STATE_H, OCTEN_STATE_TPERM, OCTEN_STATE_ITERS,
- OCTEN_STATE_MARGIN, OCTEN_STATE_FLAGS) = range(12)
+ OCTEN_STATE_MARGIN, OCTEN_STATE_FLAGS, OCTEN_STATE_COO_SIZES, OCTEN_STATE_COO_SEG_START,
+ OCTEN_STATE_COO_SEG_ROW, OCTEN_STATE_COO_SLICE_SEG) = range(16)
 OCTEN_FLAG_FUSE_UPDATE = 0x1
 OCTEN_FLAG_REFERENCE_PATH = 0x2
 OCTEN_FLAG_TIMING = 0x4
 (OCTEN_STAGE_COMPRESS_MAIN, OCTEN_STAGE_COMPRESS_MODE3, OCTEN_STAGE_UPDATE, OCTEN_STAGE_ALS,
- OCTEN_STAGE_RECOVER) = range(5)
+ OCTEN_STAGE_RECOVER, OCTEN_STAGE_COO_INDEX) = range(6)
 
 DTYPES = {"f64": OCTEN_F64, "f32": OCTEN_F32, "bf16": OCTEN_BF16, "f16": OCTEN_F16}
 
@@ -64,6 +68,7 @@ _SIGS = {
     "octen_cp_als_replicas": ([_vp, _i32, _f64, _i32, _vp, _vp], _i32),
     "octen_recover_factors": ([_vp, _vp, _vp, _vp, _i64, _vp], _i32),
     "octen_fit": ([_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp], _i32),
+    "octen_fit_coo": ([_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _i64, _vp], _i32),
     "octen_get_state": ([_vp, _i32, _vp, ctypes.c_size_t], _i32),
     "octen_check_identifiable": ([ctypes.POINTER(octen_config), _i64, _i64, _vp, _vp], _i32),
     "octen_stage_times": ([_vp, _i32, _vp, _i32, _vp], _i32),
@@ -147,6 +152,11 @@ def octen_recover_factors(h, A, B, C, c_capacity, K_out=None):
 
 def octen_fit(h, X, t, k0, A, B, C, out):
     return _lib.octen_fit(h, _ptr(X), int(t), int(k0), _ptr(A), _ptr(B), _ptr(C), out)
+
+
+def octen_fit_coo(h, nnz, k, i, j, v, k0, A, B, C, kc, out):
+    return _lib.octen_fit_coo(h, int(nnz), _ptr(k), _ptr(i), _ptr(j), _ptr(v), int(k0), _ptr(A),
+                              _ptr(B), _ptr(C), int(kc), out)
 
 
 def octen_get_state(h, what, dst, nbytes):
@@ -270,6 +280,29 @@ class Octen:
         self._check(octen_fit(self.h, X, X.shape[0], k0, A, B, C, ctypes.cast(out, _vp)), "octen_fit")
         return out[0], out[1]
 
+    def fit_coo_terms(self, k, i, j, v, k0, A, B, C, kc, acc=None):
+        """(sum v^2, sum v * Xh, Gram term) for the given nonzeros; the first
+        two are added to acc, the third is over the rows [0, kc) of C."""
+        a = acc if acc is not None else (0.0, 0.0, 0.0)
+        out = (ctypes.c_double * 3)(*a)
+        self._check(octen_fit_coo(self.h, v.numel(), k, i, j, v, k0, A, B, C, kc,
+                                  ctypes.cast(out, _vp)), "octen_fit_coo")
+        return out[0], out[1], out[2]
+
+    def coo_segments(self):
+        """Bookkeeping of the last sparse batch: (seg_start, seg_row, slice_seg)
+        as int32 device tensors."""
+        torch = self.torch
+        sizes = self.state(OCTEN_STATE_COO_SIZES).cpu()
+        nseg, t = int(sizes[0]), int(sizes[1])
+        out = []
+        for what, n in ((OCTEN_STATE_COO_SEG_START, nseg + 1), (OCTEN_STATE_COO_SEG_ROW, nseg),
+                        (OCTEN_STATE_COO_SLICE_SEG, t + 1)):
+            buf = torch.empty((max(n, 1),), dtype=torch.int32, device="cuda")
+            self._check(octen_get_state(self.h, what, buf, buf.numel() * 4), "octen_get_state")
+            out.append(buf[:n])
+        return tuple(out)
+
     def stage_ms(self, stage, n=OCTEN_TIMING_RING):
         """Durations (ms) of the last n runs of a stage, oldest first."""
         st, ms = octen_stage_times(self.h, stage, n)
@@ -293,6 +326,7 @@ class Octen:
             OCTEN_STATE_ITERS: ((P,), torch.int32),
             OCTEN_STATE_MARGIN: ((P,), torch.float64),
             OCTEN_STATE_FLAGS: ((P,), torch.int32),
+            OCTEN_STATE_COO_SIZES: ((2,), torch.int32),
         }
         shape, dt = shapes[what]
         out = torch.empty(shape, dtype=dt, device=dev)

@@ -3,7 +3,8 @@ against brute force, closed forms and special cases."""
 import numpy as np
 import pytest
 
-from oracle import compress_dense, compress_coo, update_summaries, replica_cols
+from oracle import (compress_dense, compress_coo, compress_coo_entries, coo_segments,
+                    update_summaries, replica_cols)
 from paper_1807_01350_amd import synth
 
 
@@ -115,3 +116,55 @@ def test_zero_batch_leaves_summary_unchanged(rng):
     Z0 = compress_dense(np.zeros_like(X), U, V, W, P, Q, S)
     assert np.all(Z0 == 0)
     assert np.array_equal(update_summaries(Y, Z0), Y)
+
+
+def _sorted_coo(rng, t, I, J, nnz, empty_slices=()):
+    k = rng.integers(0, t, nnz); i = rng.integers(0, I, nnz); j = rng.integers(0, J, nnz)
+    keep = ~np.isin(k, list(empty_slices))
+    k, i, j = k[keep], i[keep], j[keep]
+    order = np.lexsort((j, i, k))
+    return k[order], i[order], j[order]
+
+
+def test_coo_segments_against_loop(rng):
+    # brute force: walk the nonzeros once, opening a segment at every change
+    # of (k, i); slices 1 and 4 (and the last) have no nonzeros
+    t = 7
+    k, i, j = _sorted_coo(rng, t, 5, 6, 80, empty_slices=(1, 4, 6))
+    seg_start, seg_row, slice_seg = coo_segments(k, i, t)
+    starts, rows, first = [], [], {}
+    for n in range(len(k)):
+        if n == 0 or (k[n], i[n]) != (k[n - 1], i[n - 1]):
+            first.setdefault(int(k[n]), len(starts))
+            starts.append(n); rows.append(int(i[n]))
+    assert seg_start.tolist() == starts + [len(k)]
+    assert seg_row.tolist() == rows
+    # slice_seg: a slice without nonzeros starts where the next one does
+    expect = []
+    for x in range(t + 1):
+        later = [first[q] for q in first if q >= x]
+        expect.append(min(later) if later else len(starts))
+    assert slice_seg.tolist() == expect
+    assert slice_seg[1] == slice_seg[2] and slice_seg[4] == slice_seg[5]
+    assert slice_seg[6] == slice_seg[7] == len(starts)
+    # each segment holds one (k, i), and neighbours differ
+    for s in range(len(starts)):
+        sl = slice(seg_start[s], seg_start[s + 1])
+        assert len(set(zip(k[sl].tolist(), i[sl].tolist()))) == 1
+
+
+def test_coo_segments_empty_batch():
+    seg_start, seg_row, slice_seg = coo_segments(np.zeros(0, int), np.zeros(0, int), 3)
+    assert seg_start.tolist() == [0] and seg_row.size == 0 and slice_seg.tolist() == [0] * 4
+
+
+def test_coo_entries_match_full_compression(rng):
+    I, J, t, P, Q, S = 9, 8, 6, 3, 4, 2
+    _, U, V, W = _rand_problem(rng, I, J, t, P, Q, S)
+    k, i, j = _sorted_coo(rng, t, I, J, 70)
+    v = rng.standard_normal(k.size)
+    Z = compress_coo(k, i, j, v, t, U, V, W, P, Q, S)
+    picks = [(0, 0, 0), (1, 3, 2), (2, 1, 3), (2, 0, 1)]
+    got = compress_coo_entries(k, i, j, v, t, U, V, W, P, Q, S, picks)
+    for (p, a, b), row in zip(picks, got):
+        assert np.allclose(row, Z[p, a, b, :], rtol=1e-13, atol=1e-13)
