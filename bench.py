@@ -1,15 +1,20 @@
 """Benchmark of the online compressed CP update on one MI355X.
 
-Workload: the dense 1000 x 1000 stream with rank-10 ground truth (U[0,1]
-factors, Gaussian noise sigma = 0.01), streamed along mode 3: 500 initial
-slices, then batches of 50; P = 12 replicas of 60^3 with S = 3 shared anchor
-rows, 50 ALS sweeps per batch, FP64 solves and recovery.  One step = one
-batch through compress -> update -> ALS -> recover (the whole update).
+Default workload: the dense 1000 x 1000 stream with rank-10 ground truth
+(U[0,1] factors, Gaussian noise sigma = 0.01), streamed along mode 3: 500
+initial slices, then batches of 50; P = 12 replicas of 60^3 with S = 3 shared
+anchor rows, 50 ALS sweeps per batch, FP64 solves and recovery.  One step =
+one batch through compress -> update -> ALS -> recover (the whole update).
+
+--workload sparse: the 10^5 x 10^5 COO stream (10^5 truncated-Zipf(1.2)
+coordinate draws per slice in modes 1 and 2, rank 20), 200 initial slices then
+batches of 100; P = 16 replicas of 80^3, S = 3.
 
 Synthetic data are generated on the GPU from a seeded generator (no dataset
-exists for this workload).  Prints one JSON line.
+exists for these workloads).  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--form bf16|f32]
+                  [--workload dense|sparse]
 """
 from __future__ import annotations
 
@@ -41,6 +46,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fit", action="store_true")
+    ap.add_argument("--workload", choices=("dense", "sparse"), default="dense")
     return ap.parse_args()
 
 
@@ -108,12 +114,220 @@ def cpu_baseline(X_batch_np, U, V, W, init, c, iters):
                       f"in {dt:.2f} s"}
 
 
+def cores_used():
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    threads = cores
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        if info:
+            threads = max(int(x.get("num_threads", 1)) for x in info)
+    except Exception:
+        pass
+    return int(threads)
+
+
+def gen_coo_batches(torch, c, schedule, seed, dev):
+    """Seeded on-device COO stream: per slice nnz_per_slice draws of (i, j),
+    each truncated Zipf(a) over its mode then a fixed random relabelling;
+    duplicates removed; sorted by (k, i, j); values = rank-R CP model with
+    U[0,1] factors at the coordinates + sigma N(0,1).  Returns the factors and
+    a list of (k, i, j, v) per batch (k relative to the batch)."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    f64 = torch.float64
+    A = torch.rand((c.I, c.R), generator=g, device=dev, dtype=f64)
+    B = torch.rand((c.J, c.R), generator=g, device=dev, dtype=f64)
+    C = torch.rand((c.K, c.R), generator=g, device=dev, dtype=f64)
+
+    def zipf_sampler(n):
+        w = torch.arange(1, n + 1, device=dev, dtype=f64) ** (-c.zipf_a)
+        cdf = torch.cumsum(w, 0)
+        cdf /= cdf[-1].clone()
+        relabel = torch.randperm(n, generator=g, device=dev)
+        return lambda m: relabel[torch.searchsorted(
+            cdf, torch.rand(m, generator=g, device=dev, dtype=f64), right=True).clamp_(max=n - 1)]
+
+    draw_i, draw_j = zipf_sampler(c.I), zipf_sampler(c.J)
+    out = []
+    for k0, t in schedule:
+        per = c.nnz_per_slice
+        kk = torch.arange(t, device=dev, dtype=torch.int64).repeat_interleave(per)
+        key = (kk * c.I + draw_i(t * per)) * c.J + draw_j(t * per)
+        key = torch.unique(key)
+        k = key // (c.I * c.J)
+        rem = key - k * (c.I * c.J)
+        i = rem // c.J
+        j = rem - i * c.J
+        v = torch.empty(key.numel(), dtype=torch.float32, device=dev)
+        for q0 in range(0, key.numel(), 1 << 22):
+            q1 = min(key.numel(), q0 + (1 << 22))
+            val = (A[i[q0:q1]] * B[j[q0:q1]] * C[k0 + k[q0:q1]]).sum(1)
+            val += c.sigma * torch.randn(val.shape, generator=g, device=dev, dtype=f64)
+            v[q0:q1] = val.float()
+        out.append((k.int(), i.int(), j.int(), v))
+        del key, kk, rem
+    return A, B, C, out
+
+
+def cpu_baseline_sparse(c, U, V, W, init, iters, batch_slices):
+    """The oracle, untuned, on a bounded sample of one sparse batch:
+    compression of 2 of its slices, 5 ALS sweeps on all replicas, one
+    recovery; scaled to a whole batch (compression x t/2, ALS x iters/5)."""
+    import oracle
+    from paper_1807_01350_amd import synth
+    ns, sweeps = 2, 5
+    _, _, _, k, i, j, v = synth.coo_stream(c.I, c.J, ns, c.R, c.nnz_per_slice, c.sigma,
+                                           c.config_id)
+    o = oracle.OctenOracle(c.I, c.J, c.R, c.P, c.Q, c.S, U, V)
+    t0 = time.perf_counter()
+    o.compress_batch_coo(k, i, j, v, ns, W[:ns])
+    t_c = time.perf_counter() - t0
+    o.update_replicas()
+    t0 = time.perf_counter()
+    o.cp_als_replicas(sweeps, init=init)
+    t_a = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o.recover_factors()
+    t_r = time.perf_counter() - t0
+    est = t_c * batch_slices / ns + t_a * iters / sweeps + t_r
+    return {"value": batch_slices / est, "unit": "slices/s", "cores": cores_used(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle on {ns} slices ({v.size} nonzeros) of the sparse stream: "
+                      f"compression {t_c:.2f} s, {sweeps} ALS sweeps on all {c.P} replicas "
+                      f"{t_a:.2f} s, recovery {t_r:.2f} s; scaled to a batch of "
+                      f"{batch_slices} slices and {iters} sweeps = {est:.1f} s"}
+
+
+def run_sparse(args):
+    import torch
+    from paper_1807_01350_amd import octen as oc
+    from paper_1807_01350_amd import synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    c = synth.C3
+    t = 100 if args.batch == 50 else args.batch
+    nsteps = args.warmup + args.steps
+    sched = [(0, c.t0)] + [(c.t0 + t * b, t) for b in range(nsteps)]
+    Kuse = c.t0 + t * nsteps
+    assert Kuse <= c.K, "more slices than the stream holds"
+    print(f"[bench] generating {len(sched)} sparse batches", file=sys.stderr, flush=True)
+    Af, Bf, Cf, batches = gen_coo_batches(torch, c, sched, synth.seed_of(c.config_id, 5), dev)
+    U, V = synth.compression_UV(c.I, c.J, c.P, c.Q, c.S, c.config_id)
+    Ws = [synth.temporal_W(tt, c.M1, c.config_id, b) for b, (_, tt) in enumerate(sched)]
+    tW = [torch.from_numpy(w).to(dev) for w in Ws]
+    init = synth.als_init(c.P, c.Q, c.R, c.config_id)
+    tinit = torch.from_numpy(init).to(dev)
+    print("[bench] init", file=sys.stderr, flush=True)
+    eng = oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, torch.from_numpy(U).to(dev),
+                   torch.from_numpy(V).to(dev), x_dtype="f32", compress_dtype=args.form,
+                   flags=oc.OCTEN_FLAG_TIMING)
+    A = torch.empty((c.I, c.R), dtype=torch.float64, device=dev)
+    B = torch.empty((c.J, c.R), dtype=torch.float64, device=dev)
+    C = torch.empty((Kuse, c.R), dtype=torch.float64, device=dev)
+
+    def step(b):
+        k, i, j, v = batches[b]
+        eng.compress_batch_coo(k, i, j, v, sched[b][1], tW[b])
+        eng.update_replicas()
+        eng.cp_als_replicas(args.iters, init=tinit if b == 0 else None)
+        eng.recover_factors_async(A, B, C)
+
+    for b in range(0, args.warmup + 1):
+        step(b)
+    torch.cuda.synchronize()
+    print("[bench] timed steps", file=sys.stderr, flush=True)
+    t_start = time.perf_counter()
+    for b in range(args.warmup + 1, nsteps + 1):
+        step(b)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_step = 1e3 * elapsed / args.steps
+    value = t * args.steps / elapsed
+
+    def last(stage):
+        vv = eng.stage_ms(stage, args.steps)
+        return float(np.mean(vv)) if vv else None
+
+    st = {
+        "coo_index": last(oc.OCTEN_STAGE_COO_INDEX),
+        "compress_main": last(oc.OCTEN_STAGE_COMPRESS_MAIN),
+        "compress_mode3": last(oc.OCTEN_STAGE_COMPRESS_MODE3),
+        "update": last(oc.OCTEN_STAGE_UPDATE),
+        "als": last(oc.OCTEN_STAGE_ALS),
+        "recover": last(oc.OCTEN_STAGE_RECOVER),
+    }
+    # algorithmic bytes of one launch of the gather + MFMA kernel, averaged
+    # over the timed batches: (j, v) per nonzero, (start, row) per segment,
+    # the distinct rows of U and V (M1 f32 each), the t x P x Q^2 output
+    byts, flops, nnz_avg = [], [], []
+    for b in range(args.warmup + 1, nsteps + 1):
+        k, i, j, v = batches[b]
+        nnz = v.numel()
+        nseg = int(torch.unique(k.long() * c.I + i.long()).numel())
+        di = int(torch.unique(i).numel())
+        dj = int(torch.unique(j).numel())
+        byts.append(nnz * 8 + nseg * 8 + (di + dj) * c.M1 * 4 + t * c.P * c.Q * c.Q * 4)
+        flops.append(2.0 * nnz * c.M1 + 2.0 * nseg * c.P * c.Q * c.Q)
+        nnz_avg.append(nnz)
+    bytes_launch = float(np.mean(byts))
+    kms = st["compress_main"]
+    gbs = bytes_launch / (kms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "coo_compress (gather of V rows per (k, i) segment + MFMA U^T R)",
+            "algorithmic_bytes_per_launch": bytes_launch,
+            "algorithmic_flops_per_launch": float(np.mean(flops)),
+            "nnz_per_batch": float(np.mean(nnz_avg))}
+
+    fit = None
+    if not args.no_fit:
+        acc = (0.0, 0.0, 0.0)
+        for b, (k0, tt) in enumerate(sched):
+            k, i, j, v = batches[b]
+            acc = eng.fit_coo_terms(k, i, j, v, k0, A, B, C, Kuse, acc=acc)
+        nx, inner, gram = acc
+        fit = 1.0 - float(np.sqrt(max(nx - 2 * inner + gram, 0.0) / nx))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_sparse(c, U, V, Ws[args.warmup + 1], init, args.iters, t)
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "slices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded on-device generator; truncated Zipf(1.2) coordinates, "
+                "rank-20 U[0,1] CP values + N(0, 0.01^2))",
+        "config": {"workload": f"sparse1e5_coo: I=J=100000, R=20, {c.nnz_per_slice} coordinate "
+                               f"draws per slice, {c.t0} initial slices then batches of {t}; "
+                               f"P=16, Q=80, S=3; {args.iters} ALS sweeps; f32 gathers with "
+                               f"f32 MFMA accumulation, f64 solves",
+                   "I": c.I, "J": c.J, "R": c.R, "P": c.P, "Q": c.Q, "S": c.S, "batch": t,
+                   "initial_slices": c.t0, "als_iters": args.iters, "compress_dtype": args.form},
+        "compression_gbs": round(gbs, 1),
+        "compression_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+        "stage_ms": {kk: (round(vv, 4) if vv is not None else None) for kk, vv in st.items()},
+        "fit": fit,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    eng.close()
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "sparse":
+        return run_sparse(args)
     import torch
     from paper_1807_01350_amd import octen as oc
     from paper_1807_01350_amd import synth

@@ -207,7 +207,10 @@ __device__ __forceinline__ double sum_slots(const double* base, int64_t stride, 
   return s;
 }
 
-template <typename T, int RMAX>
+// GX: the slab is read from the summary in global memory on every use (it
+// stays in L2: the replicas of one XCD total a few MB) instead of being held
+// in LDS; for replicas whose slab does not fit next to the factor state.
+template <typename T, int RMAX, bool GX>
 __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_ok, s_bad, s_stop;
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   const int a0 = (int)((int64_t)w * Q / NW), a1 = (int)((int64_t)(w + 1) * Q / NW);
   const int na = a1 - a0;
   const int npair = na * Q;                   // rows (a, b) of the slab
-  const int QP = Q + 1;                       // padded slab row (bank spread)
+  const int QP = GX ? Q : Q + 1;              // slab row stride (LDS: padded)
   const int RT = (R + 15) / 16;               // 16-wide tiles over r
   const int64_t Q2 = (int64_t)Q * Q;
 
@@ -242,11 +245,16 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   double* CtC = BtB + RR;
   double* lamv = CtC + RR;                    // [MAXR]
   double* scr = lamv + MAXR;                  // [NT]
-  T* Xs = (T*)(scr + NT);                     // [na_max * Q][Q + 1]
-
   const T* Xp = (const T*)g.Y + (int64_t)p * Q2 * Q;
-  for (int64_t e = tid; e < (int64_t)npair * Q; e += NT)
-    Xs[(e / Q) * QP + e % Q] = Xp[(int64_t)a0 * Q2 + e];
+  const T* Xs;                                // [na * Q][QP]
+  if constexpr (GX) {
+    Xs = Xp + (int64_t)a0 * Q2;
+  } else {
+    T* xl = (T*)(scr + NT);
+    for (int64_t e = tid; e < (int64_t)npair * Q; e += NT)
+      xl[(e / Q) * QP + e % Q] = Xp[(int64_t)a0 * Q2 + e];
+    Xs = xl;
+  }
   const double* F0 = g.init + (int64_t)p * 3 * QR;
   for (int e = tid; e < na * R; e += NT) Al[e] = F0[a0 * R + e];
   for (int e = tid; e < QR; e += NT) { Bf[e] = F0[QR + e]; Cf[e] = F0[2 * QR + e]; }
@@ -494,17 +502,18 @@ static int pad_pairs(int Q, int NW) {
   return ((na_max * Q + 15) / 16) * 16;
 }
 
-size_t als_coop_lds_bytes(int Q, int R, int NW, bool x_f64) {
+size_t als_coop_lds_bytes(int Q, int R, int NW, bool x_f64, bool slab_global) {
   const int na_max = (Q + NW - 1) / NW;
   const size_t QR = (size_t)Q * R;
   const size_t dbl = (size_t)pad_pairs(Q, NW) * R + 4 * QR + (size_t)na_max * R +
                      5 * (size_t)R * R + MAXR + NT;
-  return dbl * 8 + (size_t)na_max * Q * (Q + 1) * (x_f64 ? 8 : 4);
+  return dbl * 8 + (slab_global ? 0 : (size_t)na_max * Q * (Q + 1) * (x_f64 ? 8 : 4));
 }
 
 hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int R, int NW,
-                    const double* init, double* F, double* lam, int* iters, int* flags,
-                    double* slots, unsigned* counters, int* err, int max_iters, double tol) {
+                    bool slab_global, const double* init, double* F, double* lam, int* iters,
+                    int* flags, double* slots, unsigned* counters, int* err, int max_iters,
+                    double tol) {
   if (R > MAXR || Q > 128 || NW < 1 || NW > Q || NW > 32) return hipErrorInvalidValue;
   CoopArgs a;
   a.Y = Y; a.init = init; a.F = F; a.lam = lam; a.iters = iters; a.flags = flags;
@@ -515,7 +524,7 @@ hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int 
   a.per_xcd = (P + 7) / 8;
   a.slot_len = als_coop_slot_len(Q, R);
   a.max_iters = max_iters; a.tol = tol;
-  const size_t lds = als_coop_lds_bytes(Q, R, NW, y_f64);
+  const size_t lds = als_coop_lds_bytes(Q, R, NW, y_f64, slab_global);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   hipError_t e = fill_i32(s, (int*)counters, P, 0);
   if (e != hipSuccess) return e;
@@ -524,12 +533,19 @@ hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int 
   const int grid = 8 * a.per_xcd * NW;
   void* args[] = {&a};
   const void* fn;
+#define OCTEN_ALS_PICK(RM)                                                          \
+  fn = slab_global                                                                  \
+           ? (y_f64 ? (const void*)als_coop_kernel<double, RM, true>                \
+                    : (const void*)als_coop_kernel<float, RM, true>)                \
+           : (y_f64 ? (const void*)als_coop_kernel<double, RM, false>               \
+                    : (const void*)als_coop_kernel<float, RM, false>)
   if (R <= 8)
-    fn = y_f64 ? (const void*)als_coop_kernel<double, 8> : (const void*)als_coop_kernel<float, 8>;
+    OCTEN_ALS_PICK(8);
   else if (R <= 16)
-    fn = y_f64 ? (const void*)als_coop_kernel<double, 16> : (const void*)als_coop_kernel<float, 16>;
+    OCTEN_ALS_PICK(16);
   else
-    fn = y_f64 ? (const void*)als_coop_kernel<double, 32> : (const void*)als_coop_kernel<float, 32>;
+    OCTEN_ALS_PICK(32);
+#undef OCTEN_ALS_PICK
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(NT), args, (unsigned)lds, s);

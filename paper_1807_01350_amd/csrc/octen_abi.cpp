@@ -49,6 +49,7 @@ struct octen_ctx {
   double *F = nullptr, *lam = nullptr;     // [P][3][Q][R], [P][R]
   int *iters = nullptr, *flags = nullptr;  // [P]
   int als_nw = 0;                          // workgroups per replica (0: reference kernel)
+  bool als_gx = false;                     // slab read from global memory, not LDS
   double* als_slots = nullptr;
   unsigned* als_ctr = nullptr;
   int* als_err = nullptr;
@@ -370,18 +371,26 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
   if (!(cfg->flags & OCTEN_FLAG_REFERENCE_PATH)) {
     // workgroups per replica for the cooperative ALS: enough to spread ~2e5
     // FMAs per workgroup per sweep, at most the CUs of one XCD per replica,
-    // and few enough that the slab fits in LDS
+    // and few enough that the slab fits in LDS; if no count lets it fit, the
+    // slab stays in global memory and the most workgroups are used
     const int per_xcd = (int)((P + 7) / 8);
     int max_nw = per_xcd > 0 ? 32 / per_xcd : 0;
     if (max_nw > Q) max_nw = (int)Q;
     if (max_nw >= 1) {
+      const size_t lds_cap = 160 * 1024;
       const double work = 4.0 * (double)Q * Q * Q * R;
       int nw = (int)ceil(work / 2.0e5);
       if (nw < 1) nw = 1;
       if (nw > max_nw) nw = max_nw;
-      while (nw < max_nw && als_coop_lds_bytes((int)Q, (int)R, nw, h->acc_f64) > 160 * 1024) ++nw;
-      if (als_coop_lds_bytes((int)Q, (int)R, nw, h->acc_f64) <= 160 * 1024) {
+      bool gx = false;
+      while (nw < max_nw && als_coop_lds_bytes((int)Q, (int)R, nw, h->acc_f64, false) > lds_cap) ++nw;
+      if (als_coop_lds_bytes((int)Q, (int)R, nw, h->acc_f64, false) > lds_cap) {
+        nw = max_nw;
+        gx = true;
+      }
+      if (als_coop_lds_bytes((int)Q, (int)R, nw, h->acc_f64, gx) <= lds_cap) {
         h->als_nw = nw;
+        h->als_gx = gx;
         IOK(dalloc(h, &h->als_slots, (size_t)2 * P * nw * als_coop_slot_len((int)Q, (int)R)));
         IOK(dalloc(h, &h->als_ctr, (size_t)P));
         IOK(dalloc(h, &h->als_err, 1));
@@ -590,8 +599,9 @@ octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int
     HIPCHK(h, fill_i32(s, h->flags, h->P, 0));
     hipError_t e = hipErrorNotSupported;
     if (h->als_nw > 0) {
-      e = als_coop(s, h->Y, h->acc_f64, h->P, h->Q, h->R, h->als_nw, src, h->F, h->lam, h->iters,
-                   h->flags, h->als_slots, h->als_ctr, h->als_err, max_iters, tol);
+      e = als_coop(s, h->Y, h->acc_f64, h->P, h->Q, h->R, h->als_nw, h->als_gx, src, h->F,
+                   h->lam, h->iters, h->flags, h->als_slots, h->als_ctr, h->als_err, max_iters,
+                   tol);
       if (e != hipSuccess) {
         (void)hipGetLastError();
         h->als_nw = 0;   // cooperative launch not possible here: use the reference kernel

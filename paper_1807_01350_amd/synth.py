@@ -59,6 +59,8 @@ class StreamConfig:
     sigma: float = 0.01     # noise standard deviation
     iters: int = 50         # fixed ALS iterations
     x_dtype: str = "f64"    # element type of the streamed slices
+    nnz_per_slice: int = 0  # sparse streams: coordinate draws per slice
+    zipf_a: float = 0.0     # sparse streams: Zipf exponent of modes 1 and 2
 
     @property
     def M1(self) -> int:
@@ -86,6 +88,12 @@ C1 = StreamConfig("dense50_f64", 1, I=50, J=50, R=5, P=4, Q=20, S=3, t0=30,
 # replicas of 60^3, 3 shared anchor rows, 50 ALS iterations, FP32 slices.
 C2 = StreamConfig("dense1000_f32", 2, I=1000, J=1000, R=10, P=12, Q=60, S=3,
                   t0=500, batches=(50,) * 10, x_dtype="f32")
+# The sparse 10^5 x 10^5 stream: 2000 slices of 10^5 Zipf(1.2)-distributed
+# coordinate draws each (density about 1e-5), rank 20; 200 initial slices then
+# batches of 100; P=16 replicas of 80^3 with 3 shared anchor rows.
+C3 = StreamConfig("sparse1e5_f32", 3, I=100_000, J=100_000, R=20, P=16, Q=80, S=3,
+                  t0=200, batches=(100,) * 18, x_dtype="f32", nnz_per_slice=100_000,
+                  zipf_a=1.2)
 
 
 def replica_columns(P: int, Q: int, S: int, p: int) -> np.ndarray:

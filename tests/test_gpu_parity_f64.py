@@ -26,6 +26,10 @@ CASES = [
     Case("rank1", 30, 30, 1, 3, 8, 2, (12, 6), iters=20, config_id=13),
     # large replicas: ALS spreads each replica over several workgroups
     Case("wideq", 90, 90, 4, 3, 40, 3, (20, 8), iters=30, config_id=14),
+    # nine replicas of 64^3 at rank 16: the FP64 slab of a workgroup does not
+    # fit in LDS next to the factor state, so the ALS reads it from global
+    # memory (16 workgroups per replica, two replicas on some XCDs)
+    Case("gx_slab", 120, 110, 16, 9, 64, 3, (30, 10), iters=20, config_id=15),
 ]
 
 _cache = {}
