@@ -58,7 +58,7 @@ typedef enum {
 typedef enum { OCTEN_F64 = 0, OCTEN_F32 = 1, OCTEN_BF16 = 2, OCTEN_F16 = 3 } octen_dtype;
 
 /* ALS starting point (octen_cp_als_replicas). */
-enum { OCTEN_INIT_GIVEN = 0, OCTEN_INIT_PREV = 1 };
+enum { OCTEN_INIT_GIVEN = 0, OCTEN_INIT_PREV = 1, OCTEN_INIT_LEARNED = 2 };
 
 /* Internal arrays readable through octen_get_state (for tests). */
 enum {
@@ -80,8 +80,12 @@ enum {
   OCTEN_STATE_COO_SEG_START = 13, /* [nseg+1] int32 first nonzero of each
                                      segment, then nnz                       */
   OCTEN_STATE_COO_SEG_ROW = 14,   /* [nseg] int32 row i of each segment      */
-  OCTEN_STATE_COO_SLICE_SEG = 15  /* [t+1] int32 first segment of each slice,
+  OCTEN_STATE_COO_SLICE_SEG = 15, /* [t+1] int32 first segment of each slice,
                                      then nseg                               */
+  /* last learned warm start (OCTEN_INIT_LEARNED) */
+  OCTEN_STATE_WARM_KEEP = 16,     /* [P] int32: 1 = network start kept       */
+  OCTEN_STATE_WARM_FITS = 17      /* [P][2] f64 replica fit of the plain and
+                                     of the network start                    */
 };
 
 /* Flags (octen_config.flags). */
@@ -153,8 +157,11 @@ octen_status octen_update_replicas(octen_t h);
  * max_iters >= 1 sweeps, or fewer when tol > 0 and the replica fit changes by
  * less than tol in one sweep.  init_mode OCTEN_INIT_GIVEN: init is
  * [P][3][Q][R] f64 (device); OCTEN_INIT_PREV: start from the factors of the
- * previous call (init ignored).  iters_done_host: NULL or [P] host int32
- * (synchronises). */
+ * previous call (init ignored); OCTEN_INIT_LEARNED: start from the network
+ * set by octen_warmstart_set where its start fits the updated summary at
+ * least as well as the previous factors do, else from those (init ignored;
+ * the choice per replica is readable as OCTEN_STATE_WARM_KEEP).
+ * iters_done_host: NULL or [P] host int32 (synchronises). */
 octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int32_t init_mode,
                                    const double* init, int32_t* iters_done_host);
 
@@ -212,6 +219,71 @@ octen_status octen_destroy(octen_t h);
 const char* octen_status_str(octen_status s);
 const char* octen_last_error(octen_t h);
 int32_t octen_abi_version(void);
+
+/* ---- Learned warm start of the replica ALS (an addition to the method of
+ * the paper, whose Algorithm 1 restarts ALS from the previous factors).
+ * A residual MLP maps the features of one replica column,
+ *   x = [s_a a ; s_b b ; s_a s_b c ; sketch_p]   (3Q + D values)
+ * with a, b, c the previous unit columns times lambda^(1/3) (Sec. 4.2),
+ * s_a, s_b the signs of the entries of largest magnitude of a and b (first
+ * on ties) and sketch_p = G vec(Z_p) / ||Z_p|| (G: D x Q^3, the new batch),
+ * to y = x[0:3Q] + W3 relu(W2 relu(W1 x + b1) + b2) + b3, a predicted column
+ * after ALS.  Products run on BF16 MFMA with FP32 accumulation; parameters,
+ * gradients and Adam moments are FP32. */
+typedef struct octen_mlp* octen_mlp_t;
+
+/* Number of FP32 parameters; layout W1 [H][In], b1 [H], W2 [H][H], b2 [H],
+ * W3 [Out][H], b3 [Out] (weights as [out][in], row-major).  -1 if invalid
+ * (needs Out <= In). */
+int64_t octen_mlp_param_count(int32_t n_in, int32_t n_hidden, int32_t n_out);
+
+/* Create a network from params (device, FP32, the layout above; copied).
+ * Adam moments start at zero.  stream: hipStream_t or NULL. */
+octen_status octen_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, const float* params,
+                              void* stream, octen_mlp_t* out);
+octen_status octen_mlp_destroy(octen_mlp_t m);
+const char* octen_mlp_last_error(octen_mlp_t m);
+
+/* Y [n][Out] = network(X [n][In]), device FP32, 1 <= n <= 2^24. */
+octen_status octen_mlp_forward(octen_mlp_t m, const float* X, int64_t n, float* Y);
+
+/* Gradients of loss = mean over all n * Out entries of (Y - T)^2 with
+ * respect to every parameter, into grads (device, the parameter layout);
+ * loss_host: NULL or the loss (synchronises). */
+octen_status octen_mlp_gradients(octen_mlp_t m, const float* X, const float* T, int64_t n,
+                                 float* grads, double* loss_host);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
+ * given gradients (device, parameter layout). */
+octen_status octen_mlp_adam(octen_mlp_t m, const float* grads, float lr);
+
+/* Gradients of the loss above on (X, T), then one Adam step; loss_host: NULL
+ * or the loss before the step (synchronises). */
+octen_status octen_mlp_train_step(octen_mlp_t m, const float* X, const float* T, int64_t n,
+                                  float lr, double* loss_host);
+
+/* Hidden activations relu(W1 x + b1), relu(W2 h1 + b2) [n][H] of the first
+ * n rows of the last forward pass (forward, gradients or training step). */
+octen_status octen_mlp_last_activations(octen_mlp_t m, int64_t n, float* H1, float* H2);
+
+/* Copy the FP32 parameters into dst (device). */
+octen_status octen_mlp_get_params(octen_mlp_t m, float* dst);
+
+/* Attach a network (In = 3Q + D, Out = 3Q; not copied: it must outlive its
+ * use by the handle; NULL: features and targets only, for collecting
+ * training pairs) and a sketch matrix G [D][Q^3] (device FP32, copied),
+ * 1 <= D <= 32. */
+octen_status octen_warmstart_set(octen_t h, octen_mlp_t m, const float* G, int32_t D);
+
+/* Features of every replica column (rows ordered replica-major) from the
+ * current replica factors and the last compressed batch: X [P*R][3Q+D]
+ * device FP32 (NULL: only kept inside the handle).  The signs are kept for
+ * octen_warmstart_targets. */
+octen_status octen_warmstart_features(octen_t h, float* X);
+
+/* Training targets: the current replica factors (after ALS) as columns
+ * lambda^(1/3)-scaled with the signs of the last features: T [P*R][3Q]. */
+octen_status octen_warmstart_targets(octen_t h, float* T);
 
 #ifdef __cplusplus
 }

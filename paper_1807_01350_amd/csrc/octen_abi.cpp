@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/octen.h"
+#include "mlp_ctx.h"
 #include "octen_internal.h"
 
 using namespace octen;
@@ -82,6 +83,20 @@ struct octen_ctx {
   float *Uf = nullptr, *Vf = nullptr;            // f32 copies for sparse gathers
   float* Mkf = nullptr; int64_t Mkf_cap = 0;     // [t][P][Q][Q] f32
   double* fitG = nullptr;                        // [3][R][R] Gram matrices
+  bool z_any = false;                            // some batch has been compressed
+  // learned warm start
+  octen_mlp_t ws_mlp = nullptr;
+  float* ws_G = nullptr;  int ws_D = 0;          // sketch matrix [D][Q^3]
+  float* ws_sk = nullptr;                        // [P][D]
+  double* ws_part = nullptr; int64_t ws_part_len = 0;
+  double* ws_signs = nullptr;                    // [P*R][2]
+  double *ws_plain = nullptr, *ws_cand = nullptr, *ws_init = nullptr;   // [P][3][Q][R]
+  float* ws_X = nullptr;                         // [P*R][3Q+D]
+  float* ws_Y = nullptr;                         // [P*R][3Q]
+  double* ws_jpart = nullptr;                    // judge partials
+  double* ws_fits = nullptr;                     // [P][2]
+  int* ws_keep = nullptr;                        // [P]
+  bool ws_signs_ok = false;
 
   std::vector<void*> allocs;
 
@@ -479,6 +494,7 @@ octen_status octen_compress_batch(octen_t h, const void* X, int64_t t, const dou
                                  h->Mk, h->Z, h->acc_f64));
   }
   h->z_ready = true;
+  h->z_any = true;
   h->t_z = t;
   return OCTEN_OK;
 }
@@ -543,6 +559,7 @@ octen_status octen_compress_batch_coo(octen_t h, int64_t nnz, const int32_t* k, 
     HIPCHK(h, compress_mode3(s, sh, t, Mk, f64, h->Wz, h->Z, h->acc_f64));
   }
   h->z_ready = true;
+  h->z_any = true;
   h->t_z = t;
   return OCTEN_OK;
 }
@@ -577,6 +594,37 @@ octen_status octen_update_replicas(octen_t h) {
   return OCTEN_OK;
 }
 
+namespace {
+
+octen_status ws_features(octen_t h) {
+  if (!h->have_factors) return fail(h, OCTEN_ERR_STATE, "no previous replica factors");
+  if (!h->z_any) return fail(h, OCTEN_ERR_STATE, "no compressed batch to sketch");
+  hipStream_t s = h->stream;
+  HIPCHK(h, ws_sketch(s, h->Z, h->acc_f64, h->P, h->Q, h->ws_G, h->ws_D, h->ws_part,
+                      h->ws_part_len, h->ws_sk));
+  HIPCHK(h, ws_columns(s, h->F, h->lam, h->P, h->Q, h->R, h->ws_sk, h->ws_D, false, h->ws_X,
+                       h->ws_signs, h->ws_plain));
+  h->ws_signs_ok = true;
+  return OCTEN_OK;
+}
+
+// features -> network -> candidate -> judge; the chosen start goes to ws_init
+octen_status learned_init(octen_t h) {
+  OKCHK(ws_features(h));
+  octen_mlp_t m = h->ws_mlp;
+  const int64_t n = (int64_t)h->P * h->R;
+  octen_status st = octen_mlp_ensure_rows(m, n);
+  if (st != OCTEN_OK) return fail(h, st, "warm-start network buffers: " + m->err);
+  hipStream_t s = h->stream;
+  HIPCHK(h, mlp_forward(s, m->L, m->w, h->ws_X, n, m->H1, m->H2, h->ws_Y));
+  HIPCHK(h, ws_candidate(s, h->ws_Y, h->ws_signs, h->P, h->Q, h->R, h->ws_cand));
+  HIPCHK(h, ws_judge(s, h->Y, h->acc_f64, h->P, h->Q, h->R, h->ws_plain, h->ws_cand, h->ws_jpart,
+                     h->ws_fits, h->ws_keep, h->ws_init));
+  return OCTEN_OK;
+}
+
+}  // namespace
+
 octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int32_t init_mode,
                                    const double* init, int32_t* iters_done_host) {
   if (!h) return OCTEN_ERR_ARG;
@@ -590,6 +638,10 @@ octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int
   } else if (init_mode == OCTEN_INIT_PREV) {
     if (!h->have_factors) return fail(h, OCTEN_ERR_STATE, "no previous factors");
     src = h->F;
+  } else if (init_mode == OCTEN_INIT_LEARNED) {
+    if (!h->ws_mlp) return fail(h, OCTEN_ERR_STATE, "no warm-start network set");
+    OKCHK(learned_init(h));
+    src = h->ws_init;
   } else {
     return fail(h, OCTEN_ERR_ARG, "unknown init_mode");
   }
@@ -775,6 +827,58 @@ octen_status octen_stage_times(octen_t h, int32_t stage, double* ms_host, int32_
   return OCTEN_OK;
 }
 
+octen_status octen_warmstart_set(octen_t h, octen_mlp_t m, const float* G, int32_t D) {
+  if (!h) return OCTEN_ERR_ARG;
+  if (!G) return fail(h, OCTEN_ERR_ARG, "sketch matrix must be non-null");
+  if (D < 1 || D > 32) return fail(h, OCTEN_ERR_ARG, "sketch length must be in [1, 32]");
+  const int Q = h->Q, R = h->R, P = h->P;
+  if (m && (m->L.nin != 3 * Q + D || m->L.nout != 3 * Q))
+    return fail(h, OCTEN_ERR_ARG, "network must map 3Q + D inputs to 3Q outputs");
+  const int64_t Q3 = (int64_t)Q * Q * Q;
+  if (!h->ws_G || h->ws_D != D) {
+    if (h->ws_G) { hipStreamSynchronize(h->stream); dfree(h, h->ws_G); dfree(h, h->ws_sk); dfree(h, h->ws_part); dfree(h, h->ws_X); }
+    OKCHK(dalloc(h, &h->ws_G, (size_t)(D * Q3)));
+    OKCHK(dalloc(h, &h->ws_sk, (size_t)P * D));
+    h->ws_part_len = ws_sketch_part_len(P, Q, D);
+    OKCHK(dalloc(h, &h->ws_part, (size_t)h->ws_part_len));
+    OKCHK(dalloc(h, &h->ws_X, (size_t)P * R * (3 * Q + D)));
+  }
+  if (!h->ws_signs) {
+    OKCHK(dalloc(h, &h->ws_signs, (size_t)P * R * 2));
+    OKCHK(dalloc(h, &h->ws_plain, (size_t)P * 3 * Q * R));
+    OKCHK(dalloc(h, &h->ws_cand, (size_t)P * 3 * Q * R));
+    OKCHK(dalloc(h, &h->ws_init, (size_t)P * 3 * Q * R));
+    OKCHK(dalloc(h, &h->ws_Y, (size_t)P * R * 3 * Q));
+    OKCHK(dalloc(h, &h->ws_jpart, (size_t)P * 2 * ws_judge_splits(Q) * 2));
+    OKCHK(dalloc(h, &h->ws_fits, (size_t)P * 2));
+    OKCHK(dalloc(h, &h->ws_keep, (size_t)P));
+  }
+  h->ws_D = D;
+  HIPCHK(h, hipMemcpyAsync(h->ws_G, G, (size_t)D * Q3 * 4, hipMemcpyDeviceToDevice, h->stream));
+  h->ws_mlp = m;
+  h->ws_signs_ok = false;
+  return OCTEN_OK;
+}
+
+octen_status octen_warmstart_features(octen_t h, float* X) {
+  if (!h) return OCTEN_ERR_ARG;
+  if (!h->ws_G) return fail(h, OCTEN_ERR_STATE, "octen_warmstart_set first");
+  OKCHK(ws_features(h));
+  if (X)
+    HIPCHK(h, hipMemcpyAsync(X, h->ws_X, (size_t)h->P * h->R * (3 * h->Q + h->ws_D) * 4,
+                             hipMemcpyDeviceToDevice, h->stream));
+  return OCTEN_OK;
+}
+
+octen_status octen_warmstart_targets(octen_t h, float* T) {
+  if (!h) return OCTEN_ERR_ARG;
+  if (!T) return fail(h, OCTEN_ERR_ARG, "T is NULL");
+  if (!h->ws_signs_ok) return fail(h, OCTEN_ERR_STATE, "features must be built first");
+  HIPCHK(h, ws_columns(h->stream, h->F, h->lam, h->P, h->Q, h->R, h->ws_sk, h->ws_D, true, T,
+                       h->ws_signs, nullptr));
+  return OCTEN_OK;
+}
+
 octen_status octen_get_state(octen_t h, int32_t what, void* dst, size_t bytes) {
   if (!h) return OCTEN_ERR_ARG;
   if (!dst) return fail(h, OCTEN_ERR_ARG, "dst is NULL");
@@ -804,6 +908,12 @@ octen_status octen_get_state(octen_t h, int32_t what, void* dst, size_t bytes) {
       if (what == OCTEN_STATE_COO_SEG_START) { src = h->seg_start; n = ((size_t)h->coo_nseg + 1) * 4; }
       if (what == OCTEN_STATE_COO_SEG_ROW) { src = h->seg_row; n = (size_t)h->coo_nseg * 4; }
       if (what == OCTEN_STATE_COO_SLICE_SEG) { src = h->slice_seg; n = ((size_t)h->coo_t + 1) * 4; }
+      break;
+    case OCTEN_STATE_WARM_KEEP:
+    case OCTEN_STATE_WARM_FITS:
+      if (!h->ws_keep) return fail(h, OCTEN_ERR_STATE, "no warm start set");
+      if (what == OCTEN_STATE_WARM_KEEP) { src = h->ws_keep; n = P * 4; }
+      else { src = h->ws_fits; n = P * 2 * 8; }
       break;
     default: return fail(h, OCTEN_ERR_ARG, "unknown state id");
   }

@@ -155,6 +155,44 @@ hipError_t fit_coo(hipStream_t s, int64_t nnz, const int* k, const int* i, const
                    const double* A, const double* B, const double* C, double* G, double* partials,
                    int nparts, double* out3);
 
+// ------------------------------------------------------------ warm start ---
+// Offsets of the MLP parameters in the flat FP32 buffer:
+// W1 [nh][nin], b1 [nh], W2 [nh][nh], b2 [nh], W3 [nout][nh], b3 [nout].
+struct MlpLayout {
+  int nin, nh, nout;
+  int64_t W1, b1, W2, b2, W3, b3, total;
+};
+int64_t mlp_param_count(int nin, int nh, int nout);
+MlpLayout mlp_layout(int nin, int nh, int nout);
+// Y = X[:, :nout] + W3 relu(W2 relu(W1 X + b1) + b2) + b3; H1, H2: [n][nh]
+hipError_t mlp_forward(hipStream_t s, const MlpLayout& L, const float* w, const float* X, int64_t n,
+                       float* H1, float* H2, float* Y);
+// gradients of a loss with dL/dY given (activations from mlp_forward)
+hipError_t mlp_backward(hipStream_t s, const MlpLayout& L, const float* w, const float* X,
+                        int64_t n, const float* H1, const float* H2, const float* dY, float* dZ2,
+                        float* dZ1, float* grad);
+// loss = mean (Y - T)^2 (device double), dY = 2 (Y - T) / cnt
+hipError_t mlp_mse(hipStream_t s, const float* Y, const float* T, int64_t cnt, float* dY,
+                   double* partials, int nparts, double* loss);
+hipError_t mlp_adam(hipStream_t s, float* w, const float* g, float* m, float* v, int64_t n,
+                    float lr, float beta1, float beta2, float eps, int64_t step);
+// sketch sk[p] = G vec(Z_p) / ||Z_p||, G: [D][Q^3] f32, D <= 32
+int64_t ws_sketch_part_len(int P, int Q, int D);
+hipError_t ws_sketch(hipStream_t s, const void* Z, bool z_f64, int P, int Q, const float* G, int D,
+                     double* part, int64_t part_cap, float* sk);
+// features (targets = false; writes signs [P*R][2] and the plain scaled start
+// [P][3][Q][R]) or targets (targets = true; reads signs) of every column
+hipError_t ws_columns(hipStream_t s, const double* F, const double* lam, int P, int Q, int R,
+                      const float* sk, int D, bool targets, float* out, double* signs,
+                      double* plain);
+hipError_t ws_candidate(hipStream_t s, const float* Y, const double* signs, int P, int Q, int R,
+                        double* cand);
+// judge: part [P][2][ws_judge_splits(Q)][2], fits [P][2], keep [P], init [P][3][Q][R]
+int ws_judge_splits(int Q);
+hipError_t ws_judge(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int R,
+                    const double* plain, const double* cand, double* part, double* fits,
+                    int* keep, double* init);
+
 // ------------------------------------------------------------------- fit ---
 hipError_t fit_dense(hipStream_t s, const void* X, bool x_f64, int64_t t, int64_t I, int64_t J,
                      int R, int64_t k0, const double* A, const double* B, const double* C,

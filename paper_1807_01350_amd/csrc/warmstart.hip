@@ -1,0 +1,324 @@
+// Learned warm start of the replica ALS: batch sketch, column features and
+// targets, candidate factors and the judge that keeps a candidate only when
+// its replica fit (Sec. 5.1 on the summary) is at least that of the plain
+// warm start of Algorithm 1 (the previous factors).
+//
+// Column r of replica p (previous unit columns a, b, c, weight lambda):
+//   a~ = lambda^(1/3) a etc. (the lambda distribution of Sec. 4.2);
+//   s_a, s_b = sign of the entry of largest magnitude of a~, b~ (first on ties)
+//   features = [s_a a~ ; s_b b~ ; s_a s_b c~ ; sketch_p]   (FP32, 3Q + D)
+//   sketch_p = G vec(Z_p) / ||Z_p||                         (G: D x Q^3)
+// Candidate = network output with the signs undone (FP64 factors).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "octen_internal.h"
+
+namespace octen {
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int DMAX = 32;   // sketch length
+constexpr int MAXR = 32;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// partials[p][ch][0..D-1] = G[:, chunk] . z[chunk], [D] = ||z[chunk]||^2
+template <typename TZ>
+__global__ __launch_bounds__(NT) void sketch_partial_kernel(const TZ* __restrict__ Z,
+                                                            const float* __restrict__ G,
+                                                            int64_t Q3, int D, int64_t chunk,
+                                                            int nch, double* __restrict__ part) {
+  __shared__ double red[4][DMAX + 1];
+  const int ch = blockIdx.x, p = blockIdx.y;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t e0 = ch * chunk, e1 = e0 + chunk < Q3 ? e0 + chunk : Q3;
+  const TZ* z = Z + (int64_t)p * Q3;
+  double acc[DMAX], zz = 0.0;
+#pragma unroll
+  for (int d = 0; d < DMAX; ++d) acc[d] = 0.0;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += NT) {
+    const double v = (double)z[e];
+    zz = fma(v, v, zz);
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d)
+      if (d < D) acc[d] = fma((double)G[(int64_t)d * Q3 + e], v, acc[d]);
+  }
+#pragma unroll
+  for (int d = 0; d < DMAX; ++d) {
+    if (d < D) {
+      const double s = wave_sum(acc[d]);
+      if (lane == 0) red[wave][d] = s;
+    }
+  }
+  {
+    const double s = wave_sum(zz);
+    if (lane == 0) red[wave][DMAX] = s;
+  }
+  __syncthreads();
+  double* out = part + ((int64_t)p * nch + ch) * (D + 1);
+  if (threadIdx.x < D)
+    out[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                       red[3][threadIdx.x];
+  if (threadIdx.x == D) out[D] = red[0][DMAX] + red[1][DMAX] + red[2][DMAX] + red[3][DMAX];
+}
+
+// sk[p][d] = sum_ch dots / sqrt(sum_ch norms), chunks in order
+__global__ void sketch_final_kernel(const double* __restrict__ part, int nch, int D,
+                                    float* __restrict__ sk) {
+  const int p = blockIdx.x, d = threadIdx.x;
+  if (d >= D) return;
+  const double* base = part + (int64_t)p * nch * (D + 1);
+  double s = 0.0, zz = 0.0;
+  for (int ch = 0; ch < nch; ++ch) {
+    s += base[(int64_t)ch * (D + 1) + d];
+    zz += base[(int64_t)ch * (D + 1) + D];
+  }
+  sk[p * D + d] = zz > 0.0 ? (float)(s / sqrt(zz)) : 0.f;
+}
+
+// index of the entry of largest magnitude of x[0..Q) (first on ties), over
+// one wavefront; x read with stride
+__device__ int wave_argmax_abs(const double* __restrict__ x, int64_t stride, int Q, int lane) {
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int q = lane; q < Q; q += 64) {
+    const double v = fabs(x[q * stride]);
+    if (v > best) { best = v; bi = q; }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  return bi;
+}
+
+// One wavefront per column (p, r).  mode 0: features (and signs, and the
+// plain scaled start); mode 1: targets with the stored signs.
+__global__ __launch_bounds__(64) void columns_kernel(const double* __restrict__ F,
+                                                     const double* __restrict__ lam, int P,
+                                                     int Q, int R, const float* __restrict__ sk,
+                                                     int D, int mode, float* __restrict__ out,
+                                                     double* __restrict__ signs,
+                                                     double* __restrict__ plain) {
+  const int pr = blockIdx.x, p = pr / R, r = pr % R, lane = threadIdx.x;
+  const double* Fp = F + (int64_t)p * 3 * Q * R;
+  const double c3 = cbrt(lam[p * R + r]);
+  double sa, sb;
+  if (mode == 0) {
+    const int ia = wave_argmax_abs(Fp + r, R, Q, lane);
+    const int ib = wave_argmax_abs(Fp + (int64_t)Q * R + r, R, Q, lane);
+    const double va = Fp[(int64_t)ia * R + r], vb = Fp[(int64_t)Q * R + (int64_t)ib * R + r];
+    sa = va < 0.0 ? -1.0 : 1.0;
+    sb = vb < 0.0 ? -1.0 : 1.0;
+    if (lane == 0) { signs[2 * pr] = sa; signs[2 * pr + 1] = sb; }
+  } else {
+    sa = signs[2 * pr];
+    sb = signs[2 * pr + 1];
+  }
+  const int width = mode == 0 ? 3 * Q + D : 3 * Q;
+  float* row = out + (int64_t)pr * width;
+  for (int e = lane; e < 3 * Q; e += 64) {
+    const int n = e / Q, q = e % Q;
+    const double v = c3 * Fp[((int64_t)n * Q + q) * R + r];
+    const double sg = n == 0 ? sa : (n == 1 ? sb : sa * sb);
+    row[e] = (float)(sg * v);
+    if (mode == 0) plain[((int64_t)p * 3 * Q + (int64_t)n * Q + q) * R + r] = v;
+  }
+  if (mode == 0)
+    for (int d = lane; d < D; d += 64) row[3 * Q + d] = sk[p * D + d];
+}
+
+// network outputs [P*R][3Q] -> candidate factors [P][3][Q][R] (signs undone)
+__global__ void candidate_kernel(const float* __restrict__ Y, const double* __restrict__ signs,
+                                 int P, int Q, int R, double* __restrict__ cand) {
+  const int64_t total = (int64_t)P * 3 * Q * R;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % R);
+    const int64_t t = e / R;
+    const int q = (int)(t % Q), n = (int)((t / Q) % 3), p = (int)(t / (3 * Q));
+    const int pr = p * R + r;
+    const double sa = signs[2 * pr], sb = signs[2 * pr + 1];
+    const double s = n == 0 ? sa : (n == 1 ? sb : sa * sb);
+    cand[e] = s * (double)Y[(int64_t)pr * 3 * Q + (int64_t)n * Q + q];
+  }
+}
+
+// Partial fitness terms of two starting points per replica over a range of
+// the third index: <Y_p, [[A, B, C]]> and ||Y_p||^2.  One thread per (a, b)
+// pair at a time, products A(a,:) * B(b,:) held in registers, C(c0:c1, :)
+// in LDS.  part[p][which][split][2].
+template <typename TY>
+__global__ __launch_bounds__(NT) void judge_partial_kernel(const TY* __restrict__ Y, int P, int Q,
+                                                           int R, const double* __restrict__ plain,
+                                                           const double* __restrict__ cand,
+                                                           int nsplit, double* __restrict__ part) {
+  extern __shared__ double Cs[];   // [c1 - c0][R]
+  __shared__ double red[2][4];
+  const int split = blockIdx.x, which = blockIdx.y, p = blockIdx.z;
+  const int c0 = (int)((int64_t)split * Q / nsplit), c1 = (int)((int64_t)(split + 1) * Q / nsplit);
+  const double* Fp = (which == 0 ? plain : cand) + (int64_t)p * 3 * Q * R;
+  const double *A = Fp, *B = Fp + (int64_t)Q * R, *C = Fp + 2 * (int64_t)Q * R;
+  for (int e = threadIdx.x; e < (c1 - c0) * R; e += NT) Cs[e] = C[(int64_t)c0 * R + e];
+  __syncthreads();
+  const TY* Yp = Y + (int64_t)p * Q * Q * Q;
+  double inner = 0.0, yy = 0.0;
+  for (int ab = threadIdx.x; ab < Q * Q; ab += NT) {
+    const int a = ab / Q, b = ab % Q;
+    double w[MAXR];
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) w[r] = r < R ? A[(int64_t)a * R + r] * B[(int64_t)b * R + r] : 0.0;
+    const TY* y = Yp + (int64_t)ab * Q;
+    for (int c = c0; c < c1; ++c) {
+      const double* cr = Cs + (int64_t)(c - c0) * R;
+      double xh = 0.0;
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r)
+        if (r < R) xh = fma(w[r], cr[r], xh);
+      const double v = (double)y[c];
+      inner = fma(v, xh, inner);
+      yy = fma(v, v, yy);
+    }
+  }
+  inner = wave_sum(inner);
+  yy = wave_sum(yy);
+  const int wave = threadIdx.x / 64;
+  if (threadIdx.x % 64 == 0) { red[0][wave] = inner; red[1][wave] = yy; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* o = part + (((int64_t)p * 2 + which) * nsplit + split) * 2;
+    o[0] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    o[1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+// Per replica: fit of both starting points, the choice, and the chosen init.
+// fits[p][2] (plain, candidate); keep[p] = 1 when the candidate is kept.
+__global__ __launch_bounds__(NT) void judge_final_kernel(const double* __restrict__ part,
+                                                         int nsplit, int P, int Q, int R,
+                                                         const double* __restrict__ plain,
+                                                         const double* __restrict__ cand,
+                                                         double* __restrict__ fits,
+                                                         int* __restrict__ keep,
+                                                         double* __restrict__ init) {
+  __shared__ double gsum[2][NT];
+  __shared__ int s_keep;
+  const int p = blockIdx.x;
+  const int64_t QR = (int64_t)Q * R;
+  // ||[[A,B,C]]||^2 = sum_{r,s} (A^T A)(B^T B)(C^T C) for both starting points
+  for (int which = 0; which < 2; ++which) {
+    const double* Fp = (which == 0 ? plain : cand) + (int64_t)p * 3 * QR;
+    double s = 0.0;
+    for (int rs = threadIdx.x; rs < R * R; rs += NT) {
+      const int r = rs / R, t = rs % R;
+      double g = 1.0;
+      for (int n = 0; n < 3; ++n) {
+        double d = 0.0;
+        for (int q = 0; q < Q; ++q) d = fma(Fp[n * QR + (int64_t)q * R + r], Fp[n * QR + (int64_t)q * R + t], d);
+        g *= d;
+      }
+      s += g;
+    }
+    gsum[which][threadIdx.x] = s;
+  }
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      gsum[0][threadIdx.x] += gsum[0][threadIdx.x + w];
+      gsum[1][threadIdx.x] += gsum[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double f[2];
+    for (int which = 0; which < 2; ++which) {
+      double inner = 0.0, yy = 0.0;
+      for (int sp = 0; sp < nsplit; ++sp) {
+        const double* o = part + (((int64_t)p * 2 + which) * nsplit + sp) * 2;
+        inner += o[0];
+        yy += o[1];
+      }
+      const double sse = yy - 2.0 * inner + gsum[which][0];
+      f[which] = yy > 0.0 ? 1.0 - sqrt(sse > 0.0 ? sse : 0.0) / sqrt(yy) : 0.0;
+      fits[2 * p + which] = f[which];
+    }
+    s_keep = f[1] >= f[0] ? 1 : 0;
+    keep[p] = s_keep;
+  }
+  __syncthreads();
+  const double* src = (s_keep ? cand : plain) + (int64_t)p * 3 * QR;
+  for (int64_t e = threadIdx.x; e < 3 * QR; e += NT) init[(int64_t)p * 3 * QR + e] = src[e];
+}
+
+}  // namespace
+
+hipError_t ws_sketch(hipStream_t s, const void* Z, bool z_f64, int P, int Q, const float* G, int D,
+                     double* part, int64_t part_cap, float* sk) {
+  if (D < 1 || D > DMAX) return hipErrorInvalidValue;
+  const int64_t Q3 = (int64_t)Q * Q * Q;
+  const int64_t chunk = 8192;
+  const int nch = (int)((Q3 + chunk - 1) / chunk);
+  if ((int64_t)P * nch * (D + 1) > part_cap) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nch, (unsigned)P);
+  if (z_f64)
+    hipLaunchKernelGGL(sketch_partial_kernel<double>, grid, dim3(NT), 0, s, (const double*)Z, G,
+                       Q3, D, chunk, nch, part);
+  else
+    hipLaunchKernelGGL(sketch_partial_kernel<float>, grid, dim3(NT), 0, s, (const float*)Z, G, Q3,
+                       D, chunk, nch, part);
+  hipLaunchKernelGGL(sketch_final_kernel, dim3(P), dim3(64), 0, s, part, nch, D, sk);
+  return hipGetLastError();
+}
+
+int64_t ws_sketch_part_len(int P, int Q, int D) {
+  const int64_t Q3 = (int64_t)Q * Q * Q;
+  return (int64_t)P * ((Q3 + 8191) / 8192) * (D + 1);
+}
+
+hipError_t ws_columns(hipStream_t s, const double* F, const double* lam, int P, int Q, int R,
+                      const float* sk, int D, bool targets, float* out, double* signs,
+                      double* plain) {
+  hipLaunchKernelGGL(columns_kernel, dim3(P * R), dim3(64), 0, s, F, lam, P, Q, R, sk, D,
+                     targets ? 1 : 0, out, signs, plain);
+  return hipGetLastError();
+}
+
+hipError_t ws_candidate(hipStream_t s, const float* Y, const double* signs, int P, int Q, int R,
+                        double* cand) {
+  const int64_t total = (int64_t)P * 3 * Q * R;
+  int grid = (int)((total + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(candidate_kernel, dim3(grid), dim3(256), 0, s, Y, signs, P, Q, R, cand);
+  return hipGetLastError();
+}
+
+int ws_judge_splits(int Q) { return Q >= 8 ? Q / 8 : 1; }
+
+hipError_t ws_judge(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int R,
+                    const double* plain, const double* cand, double* part, double* fits,
+                    int* keep, double* init) {
+  if (R > MAXR) return hipErrorInvalidValue;
+  const int nsplit = ws_judge_splits(Q);
+  const int cmax = (Q + nsplit - 1) / nsplit + 1;
+  const size_t lds = (size_t)cmax * R * sizeof(double);
+  const dim3 grid((unsigned)nsplit, 2, (unsigned)P);
+  if (y_f64)
+    hipLaunchKernelGGL(judge_partial_kernel<double>, grid, dim3(NT), lds, s, (const double*)Y, P,
+                       Q, R, plain, cand, nsplit, part);
+  else
+    hipLaunchKernelGGL(judge_partial_kernel<float>, grid, dim3(NT), lds, s, (const float*)Y, P, Q,
+                       R, plain, cand, nsplit, part);
+  hipLaunchKernelGGL(judge_final_kernel, dim3(P), dim3(NT), 0, s, part, nsplit, P, Q, R, plain,
+                     cand, fits, keep, init);
+  return hipGetLastError();
+}
+
+}  // namespace octen

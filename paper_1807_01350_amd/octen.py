@@ -28,11 +28,12 @@ OCTEN_ABI_VERSION = 1
 OCTEN_OK, OCTEN_ERR_ARG, OCTEN_ERR_STATE, OCTEN_ERR_HIP, OCTEN_ERR_NOMEM, OCTEN_ERR_NUMERIC, \
     OCTEN_ERR_UNSUPPORTED = range(7)
 OCTEN_F64, OCTEN_F32, OCTEN_BF16, OCTEN_F16 = range(4)
-OCTEN_INIT_GIVEN, OCTEN_INIT_PREV = 0, 1
+OCTEN_INIT_GIVEN, OCTEN_INIT_PREV, OCTEN_INIT_LEARNED = 0, 1, 2
 (OCTEN_STATE_Y, OCTEN_STATE_Z, OCTEN_STATE_FACTORS, OCTEN_STATE_LAMBDA, OCTEN_STATE_PERM,
  OCTEN_STATE_ALIGNED, OCTEN_STATE_RHS, OCTEN_STATE_H, OCTEN_STATE_TPERM, OCTEN_STATE_ITERS,
  OCTEN_STATE_MARGIN, OCTEN_STATE_FLAGS, OCTEN_STATE_COO_SIZES, OCTEN_STATE_COO_SEG_START,
- OCTEN_STATE_COO_SEG_ROW, OCTEN_STATE_COO_SLICE_SEG) = range(16)
+ OCTEN_STATE_COO_SEG_ROW, OCTEN_STATE_COO_SLICE_SEG, OCTEN_STATE_WARM_KEEP,
+ OCTEN_STATE_WARM_FITS) = range(18)
 OCTEN_FLAG_FUSE_UPDATE = 0x1
 OCTEN_FLAG_REFERENCE_PATH = 0x2
 OCTEN_FLAG_TIMING = 0x4
@@ -76,6 +77,19 @@ _SIGS = {
     "octen_status_str": ([_i32], ctypes.c_char_p),
     "octen_last_error": ([_vp], ctypes.c_char_p),
     "octen_abi_version": ([], _i32),
+    "octen_mlp_param_count": ([_i32, _i32, _i32], _i64),
+    "octen_mlp_create": ([_i32, _i32, _i32, _vp, _vp, ctypes.POINTER(_vp)], _i32),
+    "octen_mlp_destroy": ([_vp], _i32),
+    "octen_mlp_last_error": ([_vp], ctypes.c_char_p),
+    "octen_mlp_forward": ([_vp, _vp, _i64, _vp], _i32),
+    "octen_mlp_gradients": ([_vp, _vp, _vp, _i64, _vp, _vp], _i32),
+    "octen_mlp_adam": ([_vp, _vp, ctypes.c_float], _i32),
+    "octen_mlp_train_step": ([_vp, _vp, _vp, _i64, ctypes.c_float, _vp], _i32),
+    "octen_mlp_get_params": ([_vp, _vp], _i32),
+    "octen_mlp_last_activations": ([_vp, _i64, _vp, _vp], _i32),
+    "octen_warmstart_set": ([_vp, _vp, _vp, _i32], _i32),
+    "octen_warmstart_features": ([_vp, _vp], _i32),
+    "octen_warmstart_targets": ([_vp, _vp], _i32),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -195,6 +209,130 @@ def octen_last_error(h):
     return _lib.octen_last_error(h).decode()
 
 
+def octen_mlp_param_count(n_in, n_hidden, n_out):
+    return int(_lib.octen_mlp_param_count(int(n_in), int(n_hidden), int(n_out)))
+
+
+def octen_mlp_create(n_in, n_hidden, n_out, params, stream=None):
+    m = _vp()
+    st = _lib.octen_mlp_create(int(n_in), int(n_hidden), int(n_out), _ptr(params), stream,
+                               ctypes.byref(m))
+    return st, m
+
+
+def octen_mlp_destroy(m):
+    return _lib.octen_mlp_destroy(m)
+
+
+def octen_mlp_last_error(m):
+    return _lib.octen_mlp_last_error(m).decode()
+
+
+def octen_mlp_forward(m, X, n, Y):
+    return _lib.octen_mlp_forward(m, _ptr(X), int(n), _ptr(Y))
+
+
+def octen_mlp_gradients(m, X, T, n, grads, loss_host=None):
+    return _lib.octen_mlp_gradients(m, _ptr(X), _ptr(T), int(n), _ptr(grads), loss_host)
+
+
+def octen_mlp_adam(m, grads, lr):
+    return _lib.octen_mlp_adam(m, _ptr(grads), float(lr))
+
+
+def octen_mlp_train_step(m, X, T, n, lr, loss_host=None):
+    return _lib.octen_mlp_train_step(m, _ptr(X), _ptr(T), int(n), float(lr), loss_host)
+
+
+def octen_mlp_last_activations(m, n, H1, H2):
+    return _lib.octen_mlp_last_activations(m, int(n), _ptr(H1), _ptr(H2))
+
+
+def octen_mlp_get_params(m, dst):
+    return _lib.octen_mlp_get_params(m, _ptr(dst))
+
+
+def octen_warmstart_set(h, m, G, D):
+    return _lib.octen_warmstart_set(h, m, _ptr(G), int(D))
+
+
+def octen_warmstart_features(h, X):
+    return _lib.octen_warmstart_features(h, _ptr(X))
+
+
+def octen_warmstart_targets(h, T):
+    return _lib.octen_warmstart_targets(h, _ptr(T))
+
+
+class Mlp:
+    """The warm-start network: n_in -> n_hidden -> n_hidden -> n_out with a
+    residual on the first n_out inputs.  params: torch float32 device tensor
+    in the layout of octen_mlp_param_count."""
+
+    def __init__(self, n_in, n_hidden, n_out, params, stream=None):
+        import torch
+        self.torch = torch
+        self.n_in, self.n_hidden, self.n_out = int(n_in), int(n_hidden), int(n_out)
+        self.nparam = octen_mlp_param_count(n_in, n_hidden, n_out)
+        if params.numel() != self.nparam or params.dtype != torch.float32:
+            raise ValueError(f"params must be {self.nparam} float32 values")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        st, m = octen_mlp_create(n_in, n_hidden, n_out, params, stream.cuda_stream)
+        if st != OCTEN_OK:
+            raise OctenError(st, "octen_mlp_create")
+        self.m = m
+
+    def _check(self, st, where):
+        if st != OCTEN_OK:
+            raise OctenError(st, where, octen_mlp_last_error(self.m))
+
+    def close(self):
+        if getattr(self, "m", None):
+            octen_mlp_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, X):
+        Y = self.torch.empty((X.shape[0], self.n_out), dtype=self.torch.float32, device=X.device)
+        self._check(octen_mlp_forward(self.m, X, X.shape[0], Y), "octen_mlp_forward")
+        return Y
+
+    def gradients(self, X, T):
+        g = self.torch.empty(self.nparam, dtype=self.torch.float32, device=X.device)
+        loss = ctypes.c_double(0.0)
+        self._check(octen_mlp_gradients(self.m, X, T, X.shape[0], g,
+                                        ctypes.cast(ctypes.byref(loss), _vp)),
+                    "octen_mlp_gradients")
+        return g, loss.value
+
+    def adam(self, grads, lr):
+        self._check(octen_mlp_adam(self.m, grads, lr), "octen_mlp_adam")
+
+    def train_step(self, X, T, lr, want_loss=True):
+        loss = ctypes.c_double(0.0)
+        self._check(octen_mlp_train_step(self.m, X, T, X.shape[0], lr,
+                                         ctypes.cast(ctypes.byref(loss), _vp) if want_loss else None),
+                    "octen_mlp_train_step")
+        return loss.value if want_loss else None
+
+    def last_activations(self, n):
+        H1 = self.torch.empty((n, self.n_hidden), dtype=self.torch.float32, device="cuda")
+        H2 = self.torch.empty_like(H1)
+        self._check(octen_mlp_last_activations(self.m, n, H1, H2), "octen_mlp_last_activations")
+        return H1, H2
+
+    def params(self):
+        out = self.torch.empty(self.nparam, dtype=self.torch.float32, device="cuda")
+        self._check(octen_mlp_get_params(self.m, out), "octen_mlp_get_params")
+        return out
+
+
 # ---------------------------------------------------------------------------
 # Handle wrapper raising on errors; tensors come from torch (device memory).
 # ---------------------------------------------------------------------------
@@ -251,8 +389,9 @@ class Octen:
         self._pend += self._tz
         self._tz = 0
 
-    def cp_als_replicas(self, iters, tol=0.0, init=None, want_iters=False):
-        mode = OCTEN_INIT_GIVEN if init is not None else OCTEN_INIT_PREV
+    def cp_als_replicas(self, iters, tol=0.0, init=None, want_iters=False, learned=False):
+        mode = OCTEN_INIT_GIVEN if init is not None else (
+            OCTEN_INIT_LEARNED if learned else OCTEN_INIT_PREV)
         buf = (ctypes.c_int32 * self.P)() if want_iters else None
         self._check(octen_cp_als_replicas(self.h, iters, tol, mode, init,
                                           ctypes.cast(buf, _vp) if buf is not None else None),
@@ -288,6 +427,24 @@ class Octen:
         self._check(octen_fit_coo(self.h, v.numel(), k, i, j, v, k0, A, B, C, kc,
                                   ctypes.cast(out, _vp)), "octen_fit_coo")
         return out[0], out[1], out[2]
+
+    def warmstart_set(self, mlp, G, D):
+        self._check(octen_warmstart_set(self.h, mlp.m if mlp is not None else None, G, D),
+                    "octen_warmstart_set")
+        self._ws_D = int(D)
+
+    def warmstart_features(self):
+        torch = self.torch
+        X = torch.empty((self.P * self.R, 3 * self.Q + self._ws_D), dtype=torch.float32,
+                        device="cuda")
+        self._check(octen_warmstart_features(self.h, X), "octen_warmstart_features")
+        return X
+
+    def warmstart_targets(self):
+        torch = self.torch
+        T = torch.empty((self.P * self.R, 3 * self.Q), dtype=torch.float32, device="cuda")
+        self._check(octen_warmstart_targets(self.h, T), "octen_warmstart_targets")
+        return T
 
     def coo_segments(self):
         """Bookkeeping of the last sparse batch: (seg_start, seg_row, slice_seg)
@@ -327,6 +484,8 @@ class Octen:
             OCTEN_STATE_MARGIN: ((P,), torch.float64),
             OCTEN_STATE_FLAGS: ((P,), torch.int32),
             OCTEN_STATE_COO_SIZES: ((2,), torch.int32),
+            OCTEN_STATE_WARM_KEEP: ((P,), torch.int32),
+            OCTEN_STATE_WARM_FITS: ((P, 2), torch.float64),
         }
         shape, dt = shapes[what]
         out = torch.empty(shape, dtype=dt, device=dev)

@@ -188,3 +188,22 @@ def coo_stream(I: int, J: int, K: int, R: int, nnz_per_slice: int, sigma: float,
     vals = np.einsum("nr,nr,nr->n", A[i], B[j], C[k])
     vals += sigma * rng(config_id, PURPOSE_NOISE).standard_normal(vals.shape)
     return A, B, C, k, i, j, vals.astype(np.float32)
+
+
+def mlp_params(n_in: int, n_hidden: int, n_out: int, config_id: int, last_scale: float = 0.0):
+    """Starting parameters of the warm-start network, FP32, in the layout
+    W1 [H][In], b1, W2 [H][H], b2, W3 [Out][H], b3: He-normal hidden weights,
+    zero biases, last layer N(0, last_scale^2 / H) (0: the network starts as
+    the identity on the previous columns)."""
+    g = rng(config_id, PURPOSE_MLP)
+    W1 = g.standard_normal((n_hidden, n_in)) * np.sqrt(2.0 / n_in)
+    W2 = g.standard_normal((n_hidden, n_hidden)) * np.sqrt(2.0 / n_hidden)
+    W3 = g.standard_normal((n_out, n_hidden)) * (last_scale / np.sqrt(n_hidden))
+    parts = [W1, np.zeros(n_hidden), W2, np.zeros(n_hidden), W3, np.zeros(n_out)]
+    return np.concatenate([x.reshape(-1) for x in parts]).astype(np.float32)
+
+
+def sketch_matrix(D: int, Q: int, config_id: int):
+    """Fixed Gaussian sketch of a replica summary: D x Q^3, N(0, 1/D), FP32."""
+    g = rng(config_id, PURPOSE_MLP, sub=77)
+    return (g.standard_normal((D, Q ** 3)) / np.sqrt(D)).astype(np.float32)

@@ -1,0 +1,177 @@
+"""GPU checks of the learned warm start through the C ABI: network forward,
+gradients and Adam against the FP64 oracle (BF16 products: 2e-2 normwise),
+features, sketch, targets and the judge against the oracle on the same
+factors, and the gain of a trained network over the plain warm start."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1807_01350_amd import synth
+from tests.stream_helpers import rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _split(flat, n_in, n_h, n_out):
+    from oracle.warmstart import mlp_param_shapes
+    out, o = [], 0
+    for shp in mlp_param_shapes(n_in, n_h, n_out):
+        k = int(np.prod(shp))
+        out.append(np.asarray(flat[o:o + k], np.float64).reshape(shp))
+        o += k
+    return out
+
+
+def _net(n_in, n_h, n_out, cid, last_scale=0.5):
+    import torch
+    from paper_1807_01350_amd import octen as oc
+    p = synth.mlp_params(n_in, n_h, n_out, cid, last_scale=last_scale)
+    return oc.Mlp(n_in, n_h, n_out, torch.from_numpy(p).cuda()), p
+
+
+DIMS = [(92, 64, 60, 37), (272, 256, 240, 320)]
+
+
+@pytest.mark.parametrize("n_in,n_h,n_out,n", DIMS)
+def test_forward_matches_oracle(n_in, n_h, n_out, n):
+    import torch
+    from oracle.warmstart import mlp_forward
+    net, p = _net(n_in, n_h, n_out, 31)
+    X = np.random.default_rng(1).standard_normal((n, n_in)).astype(np.float32)
+    Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    Yr, _ = mlp_forward(_split(p, n_in, n_h, n_out), X, n_out)
+    # compare the learned part (the residual is exact)
+    assert rel(Y - X[:, :n_out], Yr - X[:, :n_out]) <= 2e-2
+    assert np.array_equal(Y.shape, (n, n_out))
+    net.close()
+
+
+@pytest.mark.parametrize("n_in,n_h,n_out,n", DIMS)
+def test_gradients_match_oracle(n_in, n_h, n_out, n):
+    """The rectifier masks are decisions taken by floating point: both sides
+    take them from the kernel's forward pass (its hidden activations), and the
+    oracle then runs the backward pass in FP64 from the kernel's output."""
+    import torch
+    from oracle.warmstart import mlp_backward, mlp_forward, mse_loss
+    net, p = _net(n_in, n_h, n_out, 32)
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((n, n_in)).astype(np.float32)
+    T = rng.standard_normal((n, n_out)).astype(np.float32)
+    tX = torch.from_numpy(X).cuda()
+    g, loss = net.gradients(tX, torch.from_numpy(T).cuda())
+    Yg = net.forward(tX).cpu().numpy().astype(np.float64)
+    H1, H2 = (h.cpu().numpy().astype(np.float64) for h in net.last_activations(n))
+    params = _split(p, n_in, n_h, n_out)
+    L, dY = mse_loss(Yg, T.astype(np.float64))
+    gr = mlp_backward(params, (X.astype(np.float64), H1, H1, H2, H2), dY)
+    assert abs(loss - L) <= 1e-6 * L
+    # the loss of the exact forward pass is close as well
+    Lx = mse_loss(mlp_forward(params, X, n_out)[0], T.astype(np.float64))[0]
+    assert abs(loss - Lx) <= 1e-2 * Lx
+    got = _split(g.cpu().numpy(), n_in, n_h, n_out)
+    for name, a, b in zip(("W1", "b1", "W2", "b2", "W3", "b3"), got, gr):
+        assert rel(a, b) <= 2e-2, (name, rel(a, b))
+    net.close()
+
+
+def test_adam_matches_oracle():
+    import torch
+    from oracle.warmstart import adam_step
+    n_in, n_h, n_out = 40, 32, 30
+    net, p = _net(n_in, n_h, n_out, 33)
+    params = _split(p, n_in, n_h, n_out)
+    m = [np.zeros_like(w) for w in params]
+    v = [np.zeros_like(w) for w in params]
+    rng = np.random.default_rng(3)
+    for step in (1, 2, 3):
+        gflat = rng.standard_normal(p.size).astype(np.float32)
+        net.adam(torch.from_numpy(gflat).cuda(), 1e-3)
+        adam_step(params, _split(gflat, n_in, n_h, n_out), m, v, step, 1e-3)
+    got = net.params().cpu().numpy().astype(np.float64)
+    want = np.concatenate([w.reshape(-1) for w in params])
+    assert np.max(np.abs(got - want)) <= 2e-6
+    net.close()
+
+
+def test_training_fits_a_teacher():
+    import torch
+    from paper_1807_01350_amd import warmstart
+    n_in, n_h, n_out, n = 92, 128, 60, 4096
+    teacher, _ = _net(n_in, n_h, n_out, 34, last_scale=1.0)
+    X = torch.randn((n, n_in), generator=torch.Generator(device="cuda").manual_seed(5),
+                    device="cuda")
+    T = teacher.forward(X)
+    student, _ = _net(n_in, n_h, n_out, 35, last_scale=0.0)
+    before = warmstart.evaluate_loss(student, X, T)
+    losses = warmstart.train(student, X, T, steps=400, batch=512, lr=3e-3, seed=1)
+    after = warmstart.evaluate_loss(student, X, T)
+    print(f"[warmstart] teacher fit: loss {before:.4g} -> {after:.4g}", file=sys.stderr)
+    assert np.all(np.isfinite(losses))
+    assert after < 0.2 * before
+    teacher.close()
+    student.close()
+
+
+def _small_stream(cid, batches=(30, 10, 10), I=60, J=55, R=4, P=4, Q=20, S=3):
+    from tests.stream_helpers import Case, make_inputs
+    c = Case(f"ws{cid}", I, J, R, P, Q, S, batches, iters=30, config_id=cid)
+    X, U, V, Ws, init = make_inputs(c)
+    return c, X, U, V, Ws, init
+
+
+def test_features_targets_and_judge_match_oracle():
+    """Features, sketch and targets from the GPU factors, and the choice of
+    start, against the oracle fed the same factors and summaries."""
+    import torch
+    from oracle.warmstart import (candidate_init, judge, sketch, warmstart_features,
+                                  warmstart_targets)
+    from paper_1807_01350_amd import octen as oc
+    c, X, U, V, Ws, init = _small_stream(41)
+    D = 32
+    G = synth.sketch_matrix(D, c.Q, 41)
+    net, p = _net(3 * c.Q + D, 64, 3 * c.Q, 42, last_scale=0.3)
+    eng = oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, torch.from_numpy(U).cuda(),
+                   torch.from_numpy(V).cuda())
+    eng.warmstart_set(net, torch.from_numpy(G).cuda(), D)
+    tX = torch.from_numpy(X).cuda()
+    eng.compress_batch(tX[:30], torch.from_numpy(Ws[0]).cuda())
+    eng.update_replicas()
+    eng.cp_als_replicas(30, init=torch.from_numpy(init).cuda())
+    F0 = eng.state(oc.OCTEN_STATE_FACTORS).cpu().numpy()
+    lam0 = eng.state(oc.OCTEN_STATE_LAMBDA).cpu().numpy()
+    eng.compress_batch(tX[30:40], torch.from_numpy(Ws[1]).cuda())
+    Z = eng.state(oc.OCTEN_STATE_Z).cpu().numpy()
+    eng.update_replicas()
+    Ysum = eng.state(oc.OCTEN_STATE_Y).cpu().numpy()
+    feats = eng.warmstart_features().cpu().numpy()
+    sk = sketch(Z, G.astype(np.float64))
+    fr, signs = warmstart_features(F0, lam0, sk)
+    assert rel(feats, fr) <= 1e-6
+    # the signs are decided in FP64 on both sides: compare them exactly
+    gsig = np.sign(feats[:, :3 * c.Q])
+    osig = np.sign(fr[:, :3 * c.Q])
+    assert np.array_equal(gsig[np.abs(fr[:, :3 * c.Q]) > 1e-6], osig[np.abs(fr[:, :3 * c.Q]) > 1e-6])
+    # the learned start: network on the GPU features, judge on the oracle side
+    Yn = net.forward(torch.from_numpy(feats).cuda()).cpu().numpy().astype(np.float64)
+    cand = candidate_init(Yn, signs, c.Q)
+    chosen, keep = judge(Ysum, cand, F0, lam0)
+    eng.cp_als_replicas(1, learned=True)
+    gkeep = eng.state(oc.OCTEN_STATE_WARM_KEEP).cpu().numpy()
+    gfits = eng.state(oc.OCTEN_STATE_WARM_FITS).cpu().numpy()
+    from oracle.warmstart import replica_fit_of
+    c3 = np.cbrt(lam0)[:, None, :]
+    ofits = np.array([[replica_fit_of(Ysum[q], *(F0[q] * c3[q][None])),
+                       replica_fit_of(Ysum[q], *cand[q])] for q in range(c.P)])
+    assert np.max(np.abs(gfits - ofits)) <= 1e-10
+    margin = np.abs(ofits[:, 1] - ofits[:, 0])
+    sure = margin > 1e-9
+    assert np.array_equal(gkeep.astype(bool)[sure], keep[sure])
+    # targets after a converged ALS, with the stored signs
+    eng.cp_als_replicas(200, tol=1e-10)
+    F1 = eng.state(oc.OCTEN_STATE_FACTORS).cpu().numpy()
+    lam1 = eng.state(oc.OCTEN_STATE_LAMBDA).cpu().numpy()
+    T = eng.warmstart_targets().cpu().numpy()
+    assert rel(T, warmstart_targets(F1, lam1, signs)) <= 1e-6
+    eng.close()
+    net.close()
