@@ -223,11 +223,13 @@ int32_t octen_abi_version(void);
 /* ---- Learned warm start of the replica ALS (an addition to the method of
  * the paper, whose Algorithm 1 restarts ALS from the previous factors).
  * A residual MLP maps the features of one replica column,
- *   x = [s_a a ; s_b b ; s_a s_b c ; sketch_p]   (3Q + D values)
+ *   x = [s_a a ; s_b b ; s_a s_b (c + u) ; s_a s_b u ; sketch_p]  (4Q + D)
  * with a, b, c the previous unit columns times lambda^(1/3) (Sec. 4.2),
  * s_a, s_b the signs of the entries of largest magnitude of a and b (first
- * on ties) and sketch_p = G vec(Z_p) / ||Z_p|| (G: D x Q^3, the new batch),
- * to y = x[0:3Q] + W3 relu(W2 relu(W1 x + b1) + b2) + b3, a predicted column
+ * on ties), u = (Z_p x1 a x2 b) / (||a||^2 ||b||^2) the change of the mode-3
+ * least-squares column caused by the new batch Z_p with a, b held, and
+ * sketch_p = G vec(Z_p) / ||Z_p|| (G: D x Q^3), to
+ * y = x[0:3Q] + W3 relu(W2 relu(W1 x + b1) + b2) + b3, a predicted column
  * after ALS.  Products run on BF16 MFMA with FP32 accumulation; parameters,
  * gradients and Adam moments are FP32. */
 typedef struct octen_mlp* octen_mlp_t;
@@ -269,14 +271,14 @@ octen_status octen_mlp_last_activations(octen_mlp_t m, int64_t n, float* H1, flo
 /* Copy the FP32 parameters into dst (device). */
 octen_status octen_mlp_get_params(octen_mlp_t m, float* dst);
 
-/* Attach a network (In = 3Q + D, Out = 3Q; not copied: it must outlive its
+/* Attach a network (In = 4Q + D, Out = 3Q; not copied: it must outlive its
  * use by the handle; NULL: features and targets only, for collecting
  * training pairs) and a sketch matrix G [D][Q^3] (device FP32, copied),
  * 1 <= D <= 32. */
 octen_status octen_warmstart_set(octen_t h, octen_mlp_t m, const float* G, int32_t D);
 
 /* Features of every replica column (rows ordered replica-major) from the
- * current replica factors and the last compressed batch: X [P*R][3Q+D]
+ * current replica factors and the last compressed batch: X [P*R][4Q+D]
  * device FP32 (NULL: only kept inside the handle).  The signs are kept for
  * octen_warmstart_targets. */
 octen_status octen_warmstart_features(octen_t h, float* X);

@@ -5,14 +5,18 @@ The paper warm-starts each replica's ALS from its previous factors (Sec. 4.1,
 Algorithm 1 third step).  The learned form predicts a better starting point
 column by column:
 
-  features of column r of replica p (length 3Q + D):
-      [ s_a a_r ; s_b b_r ; s_a s_b c_r ; sketch_p ]
+  features of column r of replica p (length 4Q + D):
+      [ s_a a_r ; s_b b_r ; s_a s_b (c_r + u_r) ; s_a s_b u_r ; sketch_p ]
   where a_r, b_r, c_r are the previous unit columns times lambda_r^(1/3)
   (the lambda distribution of Sec. 4.2), s_a and s_b make the entry of
   largest magnitude of a_r and of b_r positive (ties: the first such entry),
+  u_r = (Z_p x1 a_r x2 b_r) / (||a_r||^2 ||b_r||^2) is the change of the
+  mode-3 least-squares column that the new compressed batch Z_p causes when
+  a_r, b_r are held and the other columns are ignored (exact for rank one),
   and sketch_p = G vec(Z_p) / ||Z_p|| is a fixed Gaussian projection of the
-  new compressed batch of that replica (D rows of G);
-  network: residual MLP  y = x[:3Q] + W3 relu(W2 relu(W1 x + b1) + b2) + b3;
+  new batch (D rows of G);
+  network: residual MLP  y = x[:3Q] + W3 relu(W2 relu(W1 x + b1) + b2) + b3,
+  so an untrained network (W3 = 0, b3 = 0) proposes [a; b; c + u];
   target: the columns after ALS on the updated summary, lambda^(1/3)-scaled
   and with the same s_a, s_b applied;
   candidate init: y with the signs undone; kept for a replica only if its
@@ -28,7 +32,7 @@ import numpy as np
 
 __all__ = [
     "mlp_param_shapes", "mlp_forward", "mlp_backward", "mse_loss", "adam_step",
-    "sketch", "column_signs", "warmstart_features", "warmstart_targets",
+    "sketch", "column_signs", "mode3_change", "warmstart_features", "warmstart_targets",
     "candidate_init", "replica_fit_of", "judge",
 ]
 
@@ -120,21 +124,28 @@ def _scaled(F, lam):
     return [F[n] * c for n in range(3)]
 
 
-def warmstart_features(F, lam, sk):
+def mode3_change(Z, a, b):
+    """u = (Z x1 a x2 b) / (||a||^2 ||b||^2) for one column pair, Z [Q][Q][Q]."""
+    return np.einsum("abc,a,b->c", Z, a, b) / (np.dot(a, a) * np.dot(b, b))
+
+
+def warmstart_features(F, lam, sk, Z):
     """Features of every column of every replica: rows ordered (p, r).
-    F: [P][3][Q][R] unit columns, lam: [P][R], sk: [P][D].
-    Returns X [P*R][3Q + D] and the signs [P][R][2] (s_a, s_b)."""
+    F: [P][3][Q][R] unit columns, lam: [P][R], sk: [P][D], Z: [P][Q][Q][Q].
+    Returns X [P*R][4Q + D] and the signs [P][R][2] (s_a, s_b)."""
     P, _, Q, R = F.shape
     D = sk.shape[1]
-    X = np.zeros((P * R, 3 * Q + D))
+    X = np.zeros((P * R, 4 * Q + D))
     signs = np.zeros((P, R, 2))
     for p in range(P):
         a, b, c = _scaled(F[p], lam[p])
         sa, sb = column_signs(a), column_signs(b)
         signs[p, :, 0], signs[p, :, 1] = sa, sb
         for r in range(R):
+            u = mode3_change(np.asarray(Z[p], np.float64), a[:, r], b[:, r])
+            s3 = sa[r] * sb[r]
             X[p * R + r] = np.concatenate([sa[r] * a[:, r], sb[r] * b[:, r],
-                                           sa[r] * sb[r] * c[:, r], sk[p]])
+                                           s3 * (c[:, r] + u), s3 * u, sk[p]])
     return X, signs
 
 

@@ -90,6 +90,7 @@ struct octen_ctx {
   float* ws_sk = nullptr;                        // [P][D]
   double* ws_part = nullptr; int64_t ws_part_len = 0;
   double* ws_signs = nullptr;                    // [P*R][2]
+  double* ws_u = nullptr;                        // [P*R][Q] mode-3 changes
   double *ws_plain = nullptr, *ws_cand = nullptr, *ws_init = nullptr;   // [P][3][Q][R]
   float* ws_X = nullptr;                         // [P*R][3Q+D]
   float* ws_Y = nullptr;                         // [P*R][3Q]
@@ -602,8 +603,9 @@ octen_status ws_features(octen_t h) {
   hipStream_t s = h->stream;
   HIPCHK(h, ws_sketch(s, h->Z, h->acc_f64, h->P, h->Q, h->ws_G, h->ws_D, h->ws_part,
                       h->ws_part_len, h->ws_sk));
-  HIPCHK(h, ws_columns(s, h->F, h->lam, h->P, h->Q, h->R, h->ws_sk, h->ws_D, false, h->ws_X,
-                       h->ws_signs, h->ws_plain));
+  HIPCHK(h, ws_mode3_change(s, h->Z, h->acc_f64, h->F, h->lam, h->P, h->Q, h->R, h->ws_u));
+  HIPCHK(h, ws_columns(s, h->F, h->lam, h->P, h->Q, h->R, h->ws_sk, h->ws_u, h->ws_D, false,
+                       h->ws_X, h->ws_signs, h->ws_plain));
   h->ws_signs_ok = true;
   return OCTEN_OK;
 }
@@ -832,8 +834,8 @@ octen_status octen_warmstart_set(octen_t h, octen_mlp_t m, const float* G, int32
   if (!G) return fail(h, OCTEN_ERR_ARG, "sketch matrix must be non-null");
   if (D < 1 || D > 32) return fail(h, OCTEN_ERR_ARG, "sketch length must be in [1, 32]");
   const int Q = h->Q, R = h->R, P = h->P;
-  if (m && (m->L.nin != 3 * Q + D || m->L.nout != 3 * Q))
-    return fail(h, OCTEN_ERR_ARG, "network must map 3Q + D inputs to 3Q outputs");
+  if (m && (m->L.nin != 4 * Q + D || m->L.nout != 3 * Q))
+    return fail(h, OCTEN_ERR_ARG, "network must map 4Q + D inputs to 3Q outputs");
   const int64_t Q3 = (int64_t)Q * Q * Q;
   if (!h->ws_G || h->ws_D != D) {
     if (h->ws_G) { hipStreamSynchronize(h->stream); dfree(h, h->ws_G); dfree(h, h->ws_sk); dfree(h, h->ws_part); dfree(h, h->ws_X); }
@@ -841,10 +843,11 @@ octen_status octen_warmstart_set(octen_t h, octen_mlp_t m, const float* G, int32
     OKCHK(dalloc(h, &h->ws_sk, (size_t)P * D));
     h->ws_part_len = ws_sketch_part_len(P, Q, D);
     OKCHK(dalloc(h, &h->ws_part, (size_t)h->ws_part_len));
-    OKCHK(dalloc(h, &h->ws_X, (size_t)P * R * (3 * Q + D)));
+    OKCHK(dalloc(h, &h->ws_X, (size_t)P * R * (4 * Q + D)));
   }
   if (!h->ws_signs) {
     OKCHK(dalloc(h, &h->ws_signs, (size_t)P * R * 2));
+    OKCHK(dalloc(h, &h->ws_u, (size_t)P * R * Q));
     OKCHK(dalloc(h, &h->ws_plain, (size_t)P * 3 * Q * R));
     OKCHK(dalloc(h, &h->ws_cand, (size_t)P * 3 * Q * R));
     OKCHK(dalloc(h, &h->ws_init, (size_t)P * 3 * Q * R));
@@ -865,7 +868,7 @@ octen_status octen_warmstart_features(octen_t h, float* X) {
   if (!h->ws_G) return fail(h, OCTEN_ERR_STATE, "octen_warmstart_set first");
   OKCHK(ws_features(h));
   if (X)
-    HIPCHK(h, hipMemcpyAsync(X, h->ws_X, (size_t)h->P * h->R * (3 * h->Q + h->ws_D) * 4,
+    HIPCHK(h, hipMemcpyAsync(X, h->ws_X, (size_t)h->P * h->R * (4 * h->Q + h->ws_D) * 4,
                              hipMemcpyDeviceToDevice, h->stream));
   return OCTEN_OK;
 }
@@ -874,8 +877,8 @@ octen_status octen_warmstart_targets(octen_t h, float* T) {
   if (!h) return OCTEN_ERR_ARG;
   if (!T) return fail(h, OCTEN_ERR_ARG, "T is NULL");
   if (!h->ws_signs_ok) return fail(h, OCTEN_ERR_STATE, "features must be built first");
-  HIPCHK(h, ws_columns(h->stream, h->F, h->lam, h->P, h->Q, h->R, h->ws_sk, h->ws_D, true, T,
-                       h->ws_signs, nullptr));
+  HIPCHK(h, ws_columns(h->stream, h->F, h->lam, h->P, h->Q, h->R, h->ws_sk, h->ws_u, h->ws_D,
+                       true, T, h->ws_signs, nullptr));
   return OCTEN_OK;
 }
 

@@ -180,11 +180,16 @@ hipError_t mlp_adam(hipStream_t s, float* w, const float* g, float* m, float* v,
 int64_t ws_sketch_part_len(int P, int Q, int D);
 hipError_t ws_sketch(hipStream_t s, const void* Z, bool z_f64, int P, int Q, const float* G, int D,
                      double* part, int64_t part_cap, float* sk);
-// features (targets = false; writes signs [P*R][2] and the plain scaled start
-// [P][3][Q][R]) or targets (targets = true; reads signs) of every column
+// u [P*R][Q]: change of each mode-3 column caused by the batch Z with the
+// mode-1 and mode-2 columns held (lambda^(1/3)-scaled factors)
+hipError_t ws_mode3_change(hipStream_t s, const void* Z, bool z_f64, const double* F,
+                           const double* lam, int P, int Q, int R, double* u);
+// features [P*R][4Q + D] (targets = false; writes signs [P*R][2] and the
+// plain scaled start [P][3][Q][R]) or targets [P*R][3Q] (targets = true;
+// reads signs) of every column
 hipError_t ws_columns(hipStream_t s, const double* F, const double* lam, int P, int Q, int R,
-                      const float* sk, int D, bool targets, float* out, double* signs,
-                      double* plain);
+                      const float* sk, const double* u, int D, bool targets, float* out,
+                      double* signs, double* plain);
 hipError_t ws_candidate(hipStream_t s, const float* Y, const double* signs, int P, int Q, int R,
                         double* cand);
 // judge: part [P][2][ws_judge_splits(Q)][2], fits [P][2], keep [P], init [P][3][Q][R]

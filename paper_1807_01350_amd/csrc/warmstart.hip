@@ -6,7 +6,10 @@
 // Column r of replica p (previous unit columns a, b, c, weight lambda):
 //   a~ = lambda^(1/3) a etc. (the lambda distribution of Sec. 4.2);
 //   s_a, s_b = sign of the entry of largest magnitude of a~, b~ (first on ties)
-//   features = [s_a a~ ; s_b b~ ; s_a s_b c~ ; sketch_p]   (FP32, 3Q + D)
+//   u = (Z_p x1 a~ x2 b~) / (||a~||^2 ||b~||^2): the change of the mode-3
+//       least-squares column caused by the new batch with a~, b~ held
+//   features = [s_a a~ ; s_b b~ ; s_a s_b (c~ + u) ; s_a s_b u ; sketch_p]
+//              (FP32, 4Q + D)
 //   sketch_p = G vec(Z_p) / ||Z_p||                         (G: D x Q^3)
 // Candidate = network output with the signs undone (FP64 factors).
 #include <hip/hip_runtime.h>
@@ -100,12 +103,67 @@ __device__ int wave_argmax_abs(const double* __restrict__ x, int64_t stride, int
   return bi;
 }
 
+// u[(p R + r) Q + c] for c in one range of at most UC values: one workgroup
+// per (range, r, p), threads over the (a, b) pairs, FP64 sums.
+constexpr int UC = 8;
+template <typename TZ>
+__global__ __launch_bounds__(NT) void mode3_change_kernel(const TZ* __restrict__ Z,
+                                                          const double* __restrict__ F,
+                                                          const double* __restrict__ lam, int Q,
+                                                          int R, double* __restrict__ u) {
+  __shared__ double av[128], bv[128];
+  __shared__ double red[4][UC + 2];
+  const int split = blockIdx.x, r = blockIdx.y, p = blockIdx.z;
+  const int c0 = split * UC, nc = Q - c0 < UC ? Q - c0 : UC;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const double* Fp = F + (int64_t)p * 3 * Q * R;
+  const double c3 = cbrt(lam[p * R + r]);
+  for (int q = threadIdx.x; q < Q; q += NT) {
+    av[q] = c3 * Fp[(int64_t)q * R + r];
+    bv[q] = c3 * Fp[(int64_t)(Q + q) * R + r];
+  }
+  __syncthreads();
+  const TZ* Zp = Z + (int64_t)p * Q * Q * Q;
+  double acc[UC], na = 0.0, nb = 0.0;
+#pragma unroll
+  for (int j = 0; j < UC; ++j) acc[j] = 0.0;
+  for (int ab = threadIdx.x; ab < Q * Q; ab += NT) {
+    const double w = av[ab / Q] * bv[ab % Q];
+    const TZ* z = Zp + (int64_t)ab * Q + c0;
+#pragma unroll
+    for (int j = 0; j < UC; ++j)
+      if (j < nc) acc[j] = fma((double)z[j], w, acc[j]);
+  }
+  for (int q = threadIdx.x; q < Q; q += NT) {
+    na = fma(av[q], av[q], na);
+    nb = fma(bv[q], bv[q], nb);
+  }
+#pragma unroll
+  for (int j = 0; j < UC; ++j) {
+    const double sj = wave_sum(acc[j]);
+    if (lane == 0) red[wave][j] = sj;
+  }
+  {
+    const double sa = wave_sum(na), sb = wave_sum(nb);
+    if (lane == 0) { red[wave][UC] = sa; red[wave][UC + 1] = sb; }
+  }
+  __syncthreads();
+  if (threadIdx.x < nc) {
+    const int j = threadIdx.x;
+    const double num = red[0][j] + red[1][j] + red[2][j] + red[3][j];
+    const double den = (red[0][UC] + red[1][UC] + red[2][UC] + red[3][UC]) *
+                       (red[0][UC + 1] + red[1][UC + 1] + red[2][UC + 1] + red[3][UC + 1]);
+    u[((int64_t)p * R + r) * Q + c0 + j] = den > 0.0 ? num / den : 0.0;
+  }
+}
+
 // One wavefront per column (p, r).  mode 0: features (and signs, and the
 // plain scaled start); mode 1: targets with the stored signs.
 __global__ __launch_bounds__(64) void columns_kernel(const double* __restrict__ F,
                                                      const double* __restrict__ lam, int P,
                                                      int Q, int R, const float* __restrict__ sk,
-                                                     int D, int mode, float* __restrict__ out,
+                                                     const double* __restrict__ u, int D,
+                                                     int mode, float* __restrict__ out,
                                                      double* __restrict__ signs,
                                                      double* __restrict__ plain) {
   const int pr = blockIdx.x, p = pr / R, r = pr % R, lane = threadIdx.x;
@@ -123,17 +181,21 @@ __global__ __launch_bounds__(64) void columns_kernel(const double* __restrict__ 
     sa = signs[2 * pr];
     sb = signs[2 * pr + 1];
   }
-  const int width = mode == 0 ? 3 * Q + D : 3 * Q;
+  const int width = mode == 0 ? 4 * Q + D : 3 * Q;
   float* row = out + (int64_t)pr * width;
+  const double* ur = u + (int64_t)pr * Q;
   for (int e = lane; e < 3 * Q; e += 64) {
     const int n = e / Q, q = e % Q;
     const double v = c3 * Fp[((int64_t)n * Q + q) * R + r];
     const double sg = n == 0 ? sa : (n == 1 ? sb : sa * sb);
-    row[e] = (float)(sg * v);
+    const double add = (mode == 0 && n == 2) ? ur[q] : 0.0;
+    row[e] = (float)(sg * (v + add));
     if (mode == 0) plain[((int64_t)p * 3 * Q + (int64_t)n * Q + q) * R + r] = v;
   }
-  if (mode == 0)
-    for (int d = lane; d < D; d += 64) row[3 * Q + d] = sk[p * D + d];
+  if (mode == 0) {
+    for (int q = lane; q < Q; q += 64) row[3 * Q + q] = (float)(sa * sb * ur[q]);
+    for (int d = lane; d < D; d += 64) row[4 * Q + d] = sk[p * D + d];
+  }
 }
 
 // network outputs [P*R][3Q] -> candidate factors [P][3][Q][R] (signs undone)
@@ -283,10 +345,23 @@ int64_t ws_sketch_part_len(int P, int Q, int D) {
   return (int64_t)P * ((Q3 + 8191) / 8192) * (D + 1);
 }
 
+hipError_t ws_mode3_change(hipStream_t s, const void* Z, bool z_f64, const double* F,
+                           const double* lam, int P, int Q, int R, double* u) {
+  if (Q > 128) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((Q + UC - 1) / UC), (unsigned)R, (unsigned)P);
+  if (z_f64)
+    hipLaunchKernelGGL(mode3_change_kernel<double>, grid, dim3(NT), 0, s, (const double*)Z, F, lam,
+                       Q, R, u);
+  else
+    hipLaunchKernelGGL(mode3_change_kernel<float>, grid, dim3(NT), 0, s, (const float*)Z, F, lam,
+                       Q, R, u);
+  return hipGetLastError();
+}
+
 hipError_t ws_columns(hipStream_t s, const double* F, const double* lam, int P, int Q, int R,
-                      const float* sk, int D, bool targets, float* out, double* signs,
-                      double* plain) {
-  hipLaunchKernelGGL(columns_kernel, dim3(P * R), dim3(64), 0, s, F, lam, P, Q, R, sk, D,
+                      const float* sk, const double* u, int D, bool targets, float* out,
+                      double* signs, double* plain) {
+  hipLaunchKernelGGL(columns_kernel, dim3(P * R), dim3(64), 0, s, F, lam, P, Q, R, sk, u, D,
                      targets ? 1 : 0, out, signs, plain);
   return hipGetLastError();
 }

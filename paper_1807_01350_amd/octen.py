@@ -435,7 +435,7 @@ class Octen:
 
     def warmstart_features(self):
         torch = self.torch
-        X = torch.empty((self.P * self.R, 3 * self.Q + self._ws_D), dtype=torch.float32,
+        X = torch.empty((self.P * self.R, 4 * self.Q + self._ws_D), dtype=torch.float32,
                         device="cuda")
         self._check(octen_warmstart_features(self.h, X), "octen_warmstart_features")
         return X

@@ -130,7 +130,7 @@ def test_features_targets_and_judge_match_oracle():
     c, X, U, V, Ws, init = _small_stream(41)
     D = 32
     G = synth.sketch_matrix(D, c.Q, 41)
-    net, p = _net(3 * c.Q + D, 64, 3 * c.Q, 42, last_scale=0.3)
+    net, p = _net(4 * c.Q + D, 64, 3 * c.Q, 42, last_scale=0.3)
     eng = oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, torch.from_numpy(U).cuda(),
                    torch.from_numpy(V).cuda())
     eng.warmstart_set(net, torch.from_numpy(G).cuda(), D)
@@ -146,7 +146,7 @@ def test_features_targets_and_judge_match_oracle():
     Ysum = eng.state(oc.OCTEN_STATE_Y).cpu().numpy()
     feats = eng.warmstart_features().cpu().numpy()
     sk = sketch(Z, G.astype(np.float64))
-    fr, signs = warmstart_features(F0, lam0, sk)
+    fr, signs = warmstart_features(F0, lam0, sk, Z)
     assert rel(feats, fr) <= 1e-6
     # the signs are decided in FP64 on both sides: compare them exactly
     gsig = np.sign(feats[:, :3 * c.Q])
@@ -175,3 +175,22 @@ def test_features_targets_and_judge_match_oracle():
     assert rel(T, warmstart_targets(F1, lam1, signs)) <= 1e-6
     eng.close()
     net.close()
+
+
+def test_trained_network_saves_sweeps():
+    """What the trained network gains over the method without it: 24 small
+    dense streams give the training pairs (ALS to 1e-8), 3 others are the
+    test.  On the test streams the judged learned start must need fewer ALS
+    sweeps to reach 1e-6 than the plain warm start and give a higher fit of
+    the recovered factors after 5 sweeps; the untrained network (skip
+    connection only) is reported alongside."""
+    from paper_1807_01350_amd import warmstart
+    c = dict(I=60, J=55, K=78, R=4, P=4, Q=20, S=3, batches=(30,) + (6,) * 8)
+    res = warmstart.experiment(c, list(range(100, 124)), list(range(200, 203)), steps=800,
+                               log=lambda m: print("[warmstart]", m, file=sys.stderr))
+    sw = res["sweeps_total"]
+    fb = res["fit_budget_mean"]
+    assert res["loss_trained"] < 0.2 * res["loss_skip"]
+    assert sw["trained"] < 0.9 * sw["plain"], sw
+    assert fb[5]["trained"] > fb[5]["plain"], fb
+    assert fb[20]["trained"] >= fb[20]["plain"], fb

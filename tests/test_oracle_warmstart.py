@@ -4,8 +4,8 @@ import numpy as np
 import pytest
 
 from oracle.warmstart import (adam_step, candidate_init, column_signs, judge, mlp_backward,
-                              mlp_forward, mlp_param_shapes, mse_loss, replica_fit_of, sketch,
-                              warmstart_features, warmstart_targets)
+                              mlp_forward, mlp_param_shapes, mode3_change, mse_loss,
+                              replica_fit_of, sketch, warmstart_features, warmstart_targets)
 
 
 def _params(rng, n_in, n_h, n_out, scale=0.4):
@@ -93,10 +93,13 @@ def test_features_targets_round_trip_and_sign_invariance(rng):
     F /= np.linalg.norm(F, axis=2, keepdims=True)
     lam = rng.uniform(0.5, 3.0, (P, R))
     sk = rng.standard_normal((P, D))
-    X, signs = warmstart_features(F, lam, sk)
-    assert X.shape == (P * R, 3 * Q + D)
+    Z = rng.standard_normal((P, Q, Q, Q))
+    X, signs = warmstart_features(F, lam, sk, Z)
+    assert X.shape == (P * R, 4 * Q + D)
     T = warmstart_targets(F, lam, signs)
-    assert np.allclose(T, X[:, :3 * Q], rtol=0, atol=1e-15)
+    # the third block is c + u, the fourth u
+    assert np.allclose(T[:, :2 * Q], X[:, :2 * Q], rtol=0, atol=1e-15)
+    assert np.allclose(T[:, 2 * Q:], X[:, 2 * Q:3 * Q] - X[:, 3 * Q:4 * Q], rtol=1e-12, atol=1e-12)
     back = candidate_init(T, signs, Q)
     c = np.cbrt(lam)[:, None, None, :]
     assert np.allclose(back, F * c, rtol=1e-14, atol=1e-15)
@@ -104,8 +107,25 @@ def test_features_targets_round_trip_and_sign_invariance(rng):
     G = F.copy()
     G[:, 0, :, 1] *= -1
     G[:, 2, :, 1] *= -1
-    X2, _ = warmstart_features(G, lam, sk)
-    assert np.allclose(X2, X, rtol=0, atol=1e-15)
+    X2, _ = warmstart_features(G, lam, sk, Z)
+    assert np.allclose(X2, X, rtol=0, atol=1e-14)
+
+
+def test_mode3_change_is_the_rank_one_least_squares_update(rng):
+    """For rank one, c + u is the mode-3 least-squares column of Y + Z when
+    c was that of Y (Sec. 2: the mode-3 normal equations with a, b held)."""
+    from oracle import mttkrp, solve_normal, gram_hadamard
+    Q = 7
+    Y = rng.standard_normal((Q, Q, Q))
+    Z = rng.standard_normal((Q, Q, Q))
+    a = rng.standard_normal((Q, 1)); b = rng.standard_normal((Q, 1))
+
+    def ls_c(T):
+        F = [a, b, np.zeros((Q, 1))]
+        return solve_normal(mttkrp(T, F, 2), gram_hadamard(F, 2))[0][:, 0]
+
+    c = ls_c(Y)
+    assert np.allclose(c + mode3_change(Z, a[:, 0], b[:, 0]), ls_c(Y + Z), rtol=1e-12, atol=1e-12)
 
 
 def test_replica_fit_matches_gram_identity(rng):
