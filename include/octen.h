@@ -92,6 +92,9 @@ enum {
 #define OCTEN_FLAG_FUSE_UPDATE 0x1ull    /* compression adds into Y directly  */
 #define OCTEN_FLAG_REFERENCE_PATH 0x2ull /* plain FP64 kernels, no MFMA       */
 #define OCTEN_FLAG_TIMING 0x4ull         /* record HIP events around stages   */
+#define OCTEN_FLAG_ALS_ONE_WG 0x8ull     /* ALS: one workgroup per replica, no
+                                            cooperative launch (group steps
+                                            always run this way)              */
 
 /* Stages timed with OCTEN_FLAG_TIMING (octen_stage_time). */
 enum {
@@ -219,6 +222,40 @@ octen_status octen_destroy(octen_t h);
 const char* octen_status_str(octen_status s);
 const char* octen_last_error(octen_t h);
 int32_t octen_abi_version(void);
+
+/* ---- Tuning and batched steps (not in the paper).
+ *
+ * octen_autotune: times the compression kernel variants on the batch X
+ * ([t][I][J] f32, as octen_compress_batch) -- pipelined direct-to-LDS loads,
+ * register-staged 16-byte loads, register-staged scalar loads -- for the
+ * default and for half the replicas per column block, and keeps the fastest
+ * for this handle.  choice_host: NULL or 10 * replicas_per_block + variant.
+ * Only handles with F32 or BF16 compression are tuned (else
+ * OCTEN_ERR_UNSUPPORTED).  Synchronises. */
+octen_status octen_autotune(octen_t h, const void* X, int64_t t, int32_t* choice_host);
+
+/* A group runs one update step (compress, update, ALS) of many handles as
+ * one captured HIP graph: each handle's launches form a parallel branch.
+ * The first step with given descriptors captures the graph; later steps
+ * with the same descriptors (pointers and depths), the same ALS settings and
+ * the same handle state replay it, otherwise the graph is captured again.
+ * The caller rewrites the batch buffers in place between steps.  Every
+ * handle must share one stream and hold replica factors already (its first
+ * batch goes through its own calls); ALS runs with OCTEN_INIT_PREV and one
+ * workgroup per replica.  Recovery stays per handle, outside the graph. */
+typedef struct octen_group* octen_group_t;
+typedef struct {
+  const void* X;            /* [t][I][J] in the handle's x_dtype (device)      */
+  int64_t t;                /* slices in the batch                              */
+  const double* W;          /* [t][M1] f64 mode-3 compression rows (device)     */
+  const float* slice_scale; /* NULL or [t] f32 powers of two                    */
+} octen_batch_desc;
+
+octen_status octen_group_create(const octen_t* handles, int32_t n, octen_group_t* out);
+octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int32_t max_iters,
+                              double tol, int32_t* replayed_host);
+octen_status octen_group_destroy(octen_group_t g);
+const char* octen_group_last_error(octen_group_t g);
 
 /* ---- Learned warm start of the replica ALS (an addition to the method of
  * the paper, whose Algorithm 1 restarts ALS from the previous factors).

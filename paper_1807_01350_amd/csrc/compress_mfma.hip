@@ -569,6 +569,7 @@ hipError_t launch_q(hipStream_t s, const Args& a, int QT, size_t lds) {
 struct MfmaPlan {
   CompressShape sh;
   int kind = 0;   // 1 f32, 2 bf16
+  int variant = 0;  // 0 pipelined, 1 register-staged 16-byte loads, 2 scalar loads
   int G = 0, ncb = 0, nrb = 0, nchunk = 0, QT = 0;
   void* Vpack = nullptr;
   void* Upack = nullptr;
@@ -577,8 +578,17 @@ struct MfmaPlan {
   size_t lds = 0;
 };
 
+int mfma_plan_max_G(const CompressShape& sh) {
+  int G = (BN - sh.S) / (sh.Q - sh.S);
+  return G > sh.P ? sh.P : G;
+}
+
+int mfma_plan_G(const MfmaPlan* p) { return p->G; }
+void mfma_plan_set_variant(MfmaPlan* p, int variant) { p->variant = variant; }
+int mfma_plan_variant(const MfmaPlan* p) { return p->variant; }
+
 hipError_t mfma_plan_create(const CompressShape& sh, int in_kind, const double* U, const double* V,
-                            hipStream_t s, MfmaPlan** out) {
+                            hipStream_t s, MfmaPlan** out, int G_request) {
   *out = nullptr;
   if (in_kind != 1 && in_kind != 2) return hipErrorInvalidValue;
   const int P = sh.P, Q = sh.Q, S = sh.S, M1 = sh.M1;
@@ -588,6 +598,7 @@ hipError_t mfma_plan_create(const CompressShape& sh, int in_kind, const double* 
   p->kind = in_kind;
   int G = (BN - S) / (Q - S);
   if (G > P) G = P;
+  if (G_request > 0 && G_request < G) G = G_request;
   if (G < 1) { delete p; return hipErrorNotSupported; }
   p->G = G;
   p->ncb = (P + G - 1) / G;
@@ -682,9 +693,12 @@ hipError_t compress_mfma_main(hipStream_t s, const MfmaPlan* p, const float* X, 
   a.tiles = (int)tiles;
   const bool vec = (p->sh.J % 4 == 0) && (((uintptr_t)X & 15) == 0);
   hipError_t e;
-  // the pipelined kernel needs 16-byte rows chunks: J % 4 == 0 and aligned X
-  if (vec)
+  // the 16-byte load paths need J % 4 == 0 and an aligned X
+  const int v = vec ? p->variant : 2;
+  if (v == 0)
     e = p->kind == 1 ? launch_pipe_q<1>(s, a, p->QT) : launch_pipe_q<2>(s, a, p->QT);
+  else if (v == 1)
+    e = p->kind == 1 ? launch_q<1, true>(s, a, p->QT, p->lds) : launch_q<2, true>(s, a, p->QT, p->lds);
   else
     e = p->kind == 1 ? launch_q<1, false>(s, a, p->QT, p->lds) : launch_q<2, false>(s, a, p->QT, p->lds);
   return e;

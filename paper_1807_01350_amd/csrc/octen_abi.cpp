@@ -100,6 +100,7 @@ struct octen_ctx {
   bool ws_signs_ok = false;
 
   std::vector<void*> allocs;
+  bool group_mode = false;       // inside a group step: one workgroup per replica ALS
 
   // stage timing (OCTEN_FLAG_TIMING): ring of event pairs per stage
   std::vector<hipEvent_t> ev[OCTEN_NUM_STAGES];   // 2 * OCTEN_TIMING_RING
@@ -652,7 +653,7 @@ octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int
     StageTimer tm(h, OCTEN_STAGE_ALS);
     HIPCHK(h, fill_i32(s, h->flags, h->P, 0));
     hipError_t e = hipErrorNotSupported;
-    if (h->als_nw > 0) {
+    if (h->als_nw > 0 && !h->group_mode && !(h->cfg.flags & OCTEN_FLAG_ALS_ONE_WG)) {
       e = als_coop(s, h->Y, h->acc_f64, h->P, h->Q, h->R, h->als_nw, h->als_gx, src, h->F,
                    h->lam, h->iters, h->flags, h->als_slots, h->als_ctr, h->als_err, max_iters,
                    tol);
@@ -922,6 +923,320 @@ octen_status octen_get_state(octen_t h, int32_t what, void* dst, size_t bytes) {
   }
   if (bytes < n) return fail(h, OCTEN_ERR_ARG, "destination too small");
   HIPCHK(h, hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, h->stream));
+  return OCTEN_OK;
+}
+
+// ------------------------------------------------------------- autotuner ---
+
+octen_status octen_autotune(octen_t h, const void* X, int64_t t, int32_t* choice_host) {
+  if (!h) return OCTEN_ERR_ARG;
+  if (!h->plan) return fail(h, OCTEN_ERR_UNSUPPORTED, "only MFMA compression is tuned");
+  if (!X || t < 1 || t > (1 << 24)) return fail(h, OCTEN_ERR_ARG, "X non-null and t >= 1 required");
+  hipStream_t s = h->stream;
+  const CompressShape sh{h->I, h->J, h->P, h->Q, h->S, h->M1};
+  const int kind = h->cfg.compress_dtype == OCTEN_BF16 ? 2 : 1;
+  const int gmax = mfma_plan_max_G(sh);
+  std::vector<int> gs{mfma_plan_G(h->plan)};
+  if ((gmax + 1) / 2 != gs[0] && gmax > 1) gs.push_back((gmax + 1) / 2);
+  const bool vec = (h->J % 4 == 0) && (((uintptr_t)X & 15) == 0);
+  std::vector<int> variants = vec ? std::vector<int>{0, 1, 2} : std::vector<int>{2};
+  std::vector<MfmaPlan*> plans{h->plan};
+  for (size_t q = 1; q < gs.size(); ++q) {
+    MfmaPlan* pl = nullptr;
+    hipError_t e = mfma_plan_create(sh, kind, h->U, h->V, s, &pl, gs[q]);
+    if (e != hipSuccess) break;
+    plans.push_back(pl);
+  }
+  const size_t need = mfma_workspace_bytes(h->plan, t);
+  if (need > h->mfma_work_bytes) {
+    if (h->mfma_work) { hipStreamSynchronize(s); dfree(h, h->mfma_work); h->mfma_work = nullptr; }
+    OKCHK(dalloc(h, (char**)&h->mfma_work, need));
+    h->mfma_work_bytes = need;
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  float best = 1e30f;
+  size_t best_plan = 0;
+  int best_var = mfma_plan_variant(h->plan);
+  octen_status st = OCTEN_OK;
+  for (size_t q = 0; q < plans.size() && st == OCTEN_OK; ++q) {
+    for (int v : variants) {
+      mfma_plan_set_variant(plans[q], v);
+      hipError_t e = compress_mfma_main(s, plans[q], (const float*)X, t, nullptr, h->mfma_work);
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r)
+        e = compress_mfma_main(s, plans[q], (const float*)X, t, nullptr, h->mfma_work);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = fail(h, OCTEN_ERR_HIP, std::string("autotune: ") + hipGetErrorString(e));
+        break;
+      }
+      if (ms < best) { best = ms; best_plan = q; best_var = v; }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  for (size_t q = 0; q < plans.size(); ++q)
+    if (q != best_plan && plans[q] != h->plan) mfma_plan_destroy(plans[q]);
+  if (st != OCTEN_OK) {
+    mfma_plan_set_variant(h->plan, 0);
+    return st;
+  }
+  if (plans[best_plan] != h->plan) {
+    mfma_plan_destroy(h->plan);
+    h->plan = plans[best_plan];
+  }
+  mfma_plan_set_variant(h->plan, best_var);
+  if (choice_host) *choice_host = 10 * mfma_plan_G(h->plan) + best_var;
+  return OCTEN_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- groups ---
+
+struct octen_group {
+  std::vector<octen_t> hs;
+  hipStream_t user = nullptr;              // the handles' stream
+  hipStream_t main = nullptr;              // capture origin
+  std::vector<hipStream_t> branch;
+  hipEvent_t fork = nullptr, done = nullptr;
+  std::vector<hipEvent_t> join;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<octen_batch_desc> cap_desc;
+  std::vector<int64_t> cap_tpend;
+  std::vector<std::vector<const void*>> cap_bufs;
+  int32_t cap_iters = 0;
+  double cap_tol = 0.0;
+  std::string err;
+};
+
+namespace {
+
+octen_status gfail(octen_group_t g, octen_status st, const std::string& m) {
+  if (g) g->err = m;
+  return st;
+}
+
+#define GHIP(g, expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return gfail((g), OCTEN_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// grow every buffer one step of depth t needs, so that a captured step
+// allocates nothing
+octen_status prepare_step(octen_t h, int64_t t) {
+  const int64_t M1 = h->M1;
+  OKCHK(dgrow(h, &h->Wz, &h->Wz_cap, t * M1));
+  if (h->plan) {
+    const size_t need = mfma_workspace_bytes(h->plan, t);
+    if (need > h->mfma_work_bytes) {
+      if (h->mfma_work) { hipStreamSynchronize(h->stream); dfree(h, h->mfma_work); h->mfma_work = nullptr; }
+      OKCHK(dalloc(h, (char**)&h->mfma_work, need));
+      h->mfma_work_bytes = need;
+    }
+  } else {
+    int64_t rows_cap = ((int64_t)1 << 26) / M1;
+    if (rows_cap < h->I) rows_cap = h->I;
+    int64_t want = rows_cap < t * h->I ? rows_cap : t * h->I;
+    want = (want / h->I) * h->I;
+    OKCHK(dgrow(h, &h->T2, &h->T2_rows, want * M1));
+    OKCHK(dgrow(h, &h->Mk, &h->Mk_cap, t * h->P * h->Q * h->Q));
+  }
+  if (h->t_pend + t > h->Wp_cap / M1) {
+    double* nw = nullptr;
+    const int64_t cap = (h->t_pend + t) * 2 * M1;
+    OKCHK(dalloc(h, &nw, cap));
+    if (h->t_pend > 0)
+      HIPCHK(h, hipMemcpyAsync(nw, h->Wp, h->t_pend * M1 * 8, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    dfree(h, h->Wp);
+    h->Wp = nw;
+    h->Wp_cap = cap;
+  }
+  return OCTEN_OK;
+}
+
+struct HostState {
+  bool z_ready, z_any, have_factors, factors_fresh;
+  int64_t t_z, t_pend;
+};
+HostState save_state(octen_t h) {
+  return {h->z_ready, h->z_any, h->have_factors, h->factors_fresh, h->t_z, h->t_pend};
+}
+void load_state(octen_t h, const HostState& s) {
+  h->z_ready = s.z_ready; h->z_any = s.z_any; h->have_factors = s.have_factors;
+  h->factors_fresh = s.factors_fresh; h->t_z = s.t_z; h->t_pend = s.t_pend;
+}
+
+// the buffers a captured step reads or writes besides the fixed ones
+std::vector<const void*> step_buffers(octen_t h) {
+  return {h->Wz, (const void*)h->Wz_cap, h->mfma_work, (const void*)h->mfma_work_bytes, h->T2,
+          (const void*)h->T2_rows, h->Mk, (const void*)h->Mk_cap, h->Wp, (const void*)h->Wp_cap,
+          h->plan, (const void*)(intptr_t)(h->plan ? mfma_plan_variant(h->plan) : -1)};
+}
+
+bool same_desc(const octen_batch_desc& a, const octen_batch_desc& b) {
+  return a.X == b.X && a.t == b.t && a.W == b.W && a.slice_scale == b.slice_scale;
+}
+
+void drop_graph(octen_group_t g) {
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  g->exec = nullptr;
+  g->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+octen_status octen_group_create(const octen_t* handles, int32_t n, octen_group_t* out) {
+  if (!out) return OCTEN_ERR_ARG;
+  *out = nullptr;
+  if (!handles || n < 1 || n > 4096) return OCTEN_ERR_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (!handles[i]) return OCTEN_ERR_ARG;
+    if (handles[i]->stream != handles[0]->stream) return OCTEN_ERR_ARG;
+    for (int j = 0; j < i; ++j)
+      if (handles[j] == handles[i]) return OCTEN_ERR_ARG;
+  }
+  octen_group_t g = new octen_group();
+  g->hs.assign(handles, handles + n);
+  g->user = handles[0]->stream;
+  bool ok = hipStreamCreateWithFlags(&g->main, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&g->done, hipEventDisableTiming) == hipSuccess;
+  g->branch.assign(n, nullptr);
+  g->join.assign(n, nullptr);
+  for (int i = 0; ok && i < n; ++i)
+    ok = hipStreamCreateWithFlags(&g->branch[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&g->join[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    octen_group_destroy(g);
+    return OCTEN_ERR_HIP;
+  }
+  *out = g;
+  return OCTEN_OK;
+}
+
+octen_status octen_group_destroy(octen_group_t g) {
+  if (!g) return OCTEN_ERR_ARG;
+  if (g->main) hipStreamSynchronize(g->main);
+  drop_graph(g);
+  for (auto b : g->branch)
+    if (b) hipStreamDestroy(b);
+  for (auto e : g->join)
+    if (e) hipEventDestroy(e);
+  if (g->fork) hipEventDestroy(g->fork);
+  if (g->done) hipEventDestroy(g->done);
+  if (g->main) hipStreamDestroy(g->main);
+  delete g;
+  return OCTEN_OK;
+}
+
+const char* octen_group_last_error(octen_group_t g) { return g ? g->err.c_str() : "null group"; }
+
+octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int32_t max_iters,
+                              double tol, int32_t* replayed_host) {
+  if (!g) return OCTEN_ERR_ARG;
+  if (!desc || max_iters < 1 || !(tol >= 0.0)) return gfail(g, OCTEN_ERR_ARG, "bad arguments");
+  const int n = (int)g->hs.size();
+  for (int i = 0; i < n; ++i) {
+    octen_t h = g->hs[i];
+    if (!desc[i].X || !desc[i].W || desc[i].t < 1 || desc[i].t > (1 << 24))
+      return gfail(g, OCTEN_ERR_ARG, "descriptor " + std::to_string(i) + " invalid");
+    if (!h->have_factors)
+      return gfail(g, OCTEN_ERR_STATE, "handle " + std::to_string(i) + " has no replica factors");
+    if (h->z_ready)
+      return gfail(g, OCTEN_ERR_STATE, "handle " + std::to_string(i) + " has a batch not yet added");
+    if (h->stream != g->user) return gfail(g, OCTEN_ERR_STATE, "handle stream changed");
+  }
+  bool replay = g->exec && g->cap_iters == max_iters && g->cap_tol == tol;
+  for (int i = 0; replay && i < n; ++i) {
+    octen_t h = g->hs[i];
+    replay = same_desc(desc[i], g->cap_desc[i]) && h->t_pend == g->cap_tpend[i] &&
+             step_buffers(h) == g->cap_bufs[i];
+  }
+  // order after the user's stream
+  GHIP(g, hipEventRecord(g->fork, g->user));
+  GHIP(g, hipStreamWaitEvent(g->main, g->fork, 0));
+  if (!replay) {
+    drop_graph(g);
+    std::vector<int64_t> tpend(n);
+    std::vector<HostState> saved(n);
+    for (int i = 0; i < n; ++i) {
+      OKCHK(prepare_step(g->hs[i], desc[i].t));
+      tpend[i] = g->hs[i]->t_pend;
+      saved[i] = save_state(g->hs[i]);
+    }
+    GHIP(g, hipStreamSynchronize(g->user));
+    GHIP(g, hipStreamBeginCapture(g->main, hipStreamCaptureModeThreadLocal));
+    octen_status st = OCTEN_OK;
+    hipError_t he = hipEventRecord(g->fork, g->main);
+    int done_i = 0;
+    for (int i = 0; i < n && st == OCTEN_OK && he == hipSuccess; ++i) {
+      octen_t h = g->hs[i];
+      he = hipStreamWaitEvent(g->branch[i], g->fork, 0);
+      if (he != hipSuccess) break;
+      const bool timing = h->timing;
+      h->timing = false;
+      h->group_mode = true;
+      h->stream = g->branch[i];
+      st = octen_compress_batch(h, desc[i].X, desc[i].t, desc[i].W, desc[i].slice_scale);
+      if (st == OCTEN_OK) st = octen_update_replicas(h);
+      if (st == OCTEN_OK) st = octen_cp_als_replicas(h, max_iters, tol, OCTEN_INIT_PREV, nullptr, nullptr);
+      h->stream = g->user;
+      h->group_mode = false;
+      h->timing = timing;
+      if (st != OCTEN_OK) { g->err = "handle " + std::to_string(i) + ": " + h->err; break; }
+      he = hipEventRecord(g->join[i], g->branch[i]);
+      if (he == hipSuccess) he = hipStreamWaitEvent(g->main, g->join[i], 0);
+      done_i = i + 1;
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(g->main, &graph);
+    if (st != OCTEN_OK || he != hipSuccess || ee != hipSuccess || done_i != n) {
+      if (graph) hipGraphDestroy(graph);
+      for (int i = 0; i < n; ++i) load_state(g->hs[i], saved[i]);
+      if (st == OCTEN_OK) {
+        st = OCTEN_ERR_HIP;
+        g->err = std::string("graph capture: ") + hipGetErrorString(he != hipSuccess ? he : ee);
+      }
+      return st;
+    }
+    g->graph = graph;
+    GHIP(g, hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    g->cap_desc.assign(desc, desc + n);
+    g->cap_tpend = tpend;
+    g->cap_bufs.resize(n);
+    for (int i = 0; i < n; ++i) g->cap_bufs[i] = step_buffers(g->hs[i]);
+    g->cap_iters = max_iters;
+    g->cap_tol = tol;
+  } else {
+    // the calls a capture records advance each handle's host state; a
+    // replay applies the same transitions
+    for (int i = 0; i < n; ++i) {
+      octen_t h = g->hs[i];
+      h->t_z = desc[i].t;
+      h->z_any = true;
+      h->t_pend += desc[i].t;
+      h->z_ready = false;
+      h->have_factors = true;
+      h->factors_fresh = true;
+    }
+  }
+  GHIP(g, hipGraphLaunch(g->exec, g->main));
+  GHIP(g, hipEventRecord(g->done, g->main));
+  GHIP(g, hipStreamWaitEvent(g->user, g->done, 0));
+  if (replayed_host) *replayed_host = replay ? 1 : 0;
   return OCTEN_OK;
 }
 

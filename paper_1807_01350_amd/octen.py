@@ -37,10 +37,20 @@ OCTEN_INIT_GIVEN, OCTEN_INIT_PREV, OCTEN_INIT_LEARNED = 0, 1, 2
 OCTEN_FLAG_FUSE_UPDATE = 0x1
 OCTEN_FLAG_REFERENCE_PATH = 0x2
 OCTEN_FLAG_TIMING = 0x4
+OCTEN_FLAG_ALS_ONE_WG = 0x8
 (OCTEN_STAGE_COMPRESS_MAIN, OCTEN_STAGE_COMPRESS_MODE3, OCTEN_STAGE_UPDATE, OCTEN_STAGE_ALS,
  OCTEN_STAGE_RECOVER, OCTEN_STAGE_COO_INDEX) = range(6)
 
 DTYPES = {"f64": OCTEN_F64, "f32": OCTEN_F32, "bf16": OCTEN_BF16, "f16": OCTEN_F16}
+
+
+class octen_batch_desc(ctypes.Structure):
+    _fields_ = [
+        ("X", ctypes.c_void_p),
+        ("t", ctypes.c_int64),
+        ("W", ctypes.c_void_p),
+        ("slice_scale", ctypes.c_void_p),
+    ]
 
 
 class octen_config(ctypes.Structure):
@@ -87,6 +97,11 @@ _SIGS = {
     "octen_mlp_train_step": ([_vp, _vp, _vp, _i64, ctypes.c_float, _vp], _i32),
     "octen_mlp_get_params": ([_vp, _vp], _i32),
     "octen_mlp_last_activations": ([_vp, _i64, _vp, _vp], _i32),
+    "octen_autotune": ([_vp, _vp, _i64, _vp], _i32),
+    "octen_group_create": ([_vp, _i32, ctypes.POINTER(_vp)], _i32),
+    "octen_group_step": ([_vp, _vp, _i32, _f64, _vp], _i32),
+    "octen_group_destroy": ([_vp], _i32),
+    "octen_group_last_error": ([_vp], ctypes.c_char_p),
     "octen_warmstart_set": ([_vp, _vp, _vp, _i32], _i32),
     "octen_warmstart_features": ([_vp, _vp], _i32),
     "octen_warmstart_targets": ([_vp, _vp], _i32),
@@ -250,6 +265,65 @@ def octen_mlp_last_activations(m, n, H1, H2):
 
 def octen_mlp_get_params(m, dst):
     return _lib.octen_mlp_get_params(m, _ptr(dst))
+
+
+def octen_autotune(h, X, t, choice=None):
+    return _lib.octen_autotune(h, _ptr(X), int(t), choice)
+
+
+def octen_group_create(handles):
+    arr = (_vp * len(handles))(*[h.value if isinstance(h, _vp) else h for h in handles])
+    g = _vp()
+    st = _lib.octen_group_create(ctypes.cast(arr, _vp), len(handles), ctypes.byref(g))
+    return st, g
+
+
+def octen_group_step(g, descs, max_iters, tol, replayed=None):
+    arr = (octen_batch_desc * len(descs))(*descs)
+    return _lib.octen_group_step(g, ctypes.cast(arr, _vp), int(max_iters), float(tol), replayed)
+
+
+def octen_group_destroy(g):
+    return _lib.octen_group_destroy(g)
+
+
+def octen_group_last_error(g):
+    return _lib.octen_group_last_error(g).decode()
+
+
+class Group:
+    """One update step of many handles as one captured HIP graph."""
+
+    def __init__(self, engines):
+        self.engines = list(engines)
+        st, g = octen_group_create([e.h for e in self.engines])
+        if st != OCTEN_OK:
+            raise OctenError(st, "octen_group_create")
+        self.g = g
+
+    def step(self, batches, max_iters, tol=0.0):
+        """batches: list of (X, W) device tensors (same objects each round
+        for replay).  Returns True when the captured graph was replayed."""
+        descs = [octen_batch_desc(X.data_ptr(), X.shape[0], W.data_ptr(), None)
+                 for X, W in batches]
+        rep = ctypes.c_int32(0)
+        st = octen_group_step(self.g, descs, max_iters, tol, ctypes.cast(ctypes.byref(rep), _vp))
+        if st != OCTEN_OK:
+            raise OctenError(st, "octen_group_step", octen_group_last_error(self.g))
+        for e, (X, _) in zip(self.engines, batches):
+            e._pend += int(X.shape[0])
+        return bool(rep.value)
+
+    def close(self):
+        if getattr(self, "g", None):
+            octen_group_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def octen_warmstart_set(h, m, G, D):
@@ -427,6 +501,12 @@ class Octen:
         self._check(octen_fit_coo(self.h, v.numel(), k, i, j, v, k0, A, B, C, kc,
                                   ctypes.cast(out, _vp)), "octen_fit_coo")
         return out[0], out[1], out[2]
+
+    def autotune(self, X):
+        ch = ctypes.c_int32(0)
+        self._check(octen_autotune(self.h, X, X.shape[0], ctypes.cast(ctypes.byref(ch), _vp)),
+                    "octen_autotune")
+        return ch.value
 
     def warmstart_set(self, mlp, G, D):
         self._check(octen_warmstart_set(self.h, mlp.m if mlp is not None else None, G, D),

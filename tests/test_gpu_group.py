@@ -1,0 +1,215 @@
+"""GPU checks of batched steps and the autotuner through the C ABI.
+
+A group runs compress -> update -> ALS of several streams of uneven shapes as
+one captured HIP graph; every round must give exactly the results of the same
+calls made handle by handle (the kernels and their order are the same), also
+on replays with eager work and synchronisation between them.  FP64 streams in
+a group are also compared with the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1807_01350_amd import synth
+from tests.stream_helpers import Case, make_inputs, rel
+
+pytestmark = pytest.mark.gpu
+
+# uneven streams: (I, J, R, P, Q, S, t0, t, form)
+SHAPES = [
+    (90, 70, 4, 4, 20, 3, 24, 8, "f32"),
+    (130, 160, 6, 6, 36, 3, 30, 12, "bf16"),
+    (64, 64, 3, 3, 24, 3, 20, 5, "f32"),
+    (200, 120, 8, 5, 40, 3, 40, 16, "bf16"),
+]
+ROUNDS = 4
+
+
+def _streams(shapes, seed0):
+    import torch
+    out = []
+    for q, (I, J, R, P, Q, S, t0, t, form) in enumerate(shapes):
+        c = Case(f"g{q}", I, J, R, P, Q, S, (t0,) + (t,) * ROUNDS, iters=20,
+                 config_id=seed0 + q)
+        X, U, V, Ws, init = make_inputs(c, x_dtype=np.float32 if form != "f64" else np.float64)
+        out.append((c, form, torch.from_numpy(X).cuda(), torch.from_numpy(U).cuda(),
+                    torch.from_numpy(V).cuda(), [torch.from_numpy(w).cuda() for w in Ws],
+                    torch.from_numpy(init).cuda()))
+    return out
+
+
+def _engine(c, form, U, V):
+    from paper_1807_01350_amd import octen as oc
+    x = "f64" if form == "f64" else "f32"
+    return oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, U, V, x_dtype=x, compress_dtype=form,
+                    flags=oc.OCTEN_FLAG_ALS_ONE_WG)
+
+
+def _run(shapes, seed0, iters=15, tol=0.0):
+    """Group and twin handles on the same streams; returns per round the
+    (group, eager) states and whether the group replayed."""
+    import torch
+    from paper_1807_01350_amd import octen as oc
+    streams = _streams(shapes, seed0)
+    grp_engs, twin_engs, bufs = [], [], []
+    for c, form, X, U, V, Ws, init in streams:
+        g, e = _engine(c, form, U, V), _engine(c, form, U, V)
+        t0 = c.batches[0]
+        for eng in (g, e):
+            eng.compress_batch(X[:t0], Ws[0])
+            eng.update_replicas()
+            eng.cp_als_replicas(iters, init=init)
+            eng.recover_factors(torch.empty((c.I, c.R), dtype=torch.float64, device="cuda"),
+                                torch.empty((c.J, c.R), dtype=torch.float64, device="cuda"),
+                                torch.empty((c.K, c.R), dtype=torch.float64, device="cuda"))
+        # fixed batch buffers, rewritten in place every round
+        bufs.append((torch.empty_like(X[t0:t0 + c.batches[1]]), torch.empty_like(Ws[1])))
+        grp_engs.append(g)
+        twin_engs.append(e)
+    group = oc.Group(grp_engs)
+    rounds = []
+    for r in range(1, ROUNDS + 1):
+        print(f"[group] round {r}", file=sys.stderr, flush=True)
+        for (c, form, X, U, V, Ws, init), (xb, wb) in zip(streams, bufs):
+            k0 = sum(c.batches[:r])
+            xb.copy_(X[k0:k0 + c.batches[r]])
+            wb.copy_(Ws[r])
+        replayed = group.step(bufs, iters, tol)
+        for e, (xb, wb) in zip(twin_engs, bufs):
+            e.compress_batch(xb, wb)
+            e.update_replicas()
+            e.cp_als_replicas(iters, tol=tol)
+        torch.cuda.synchronize()
+        # eager work between replays
+        _ = (torch.randn(1000, 1000, device="cuda") @ torch.randn(1000, 1000, device="cuda")).sum()
+        torch.cuda.synchronize()
+        res = []
+        for g, e, (c, *_rest) in zip(grp_engs, twin_engs, streams):
+            A = torch.empty((c.I, c.R), dtype=torch.float64, device="cuda")
+            B = torch.empty((c.J, c.R), dtype=torch.float64, device="cuda")
+            C = torch.empty((c.K, c.R), dtype=torch.float64, device="cuda")
+            A2, B2, C2 = torch.empty_like(A), torch.empty_like(B), torch.empty_like(C)
+            K = g.recover_factors(A, B, C)
+            assert e.recover_factors(A2, B2, C2) == K
+            C, C2 = C[:K], C2[:K]
+            res.append({
+                "Y": (g.state(oc.OCTEN_STATE_Y).cpu().numpy(), e.state(oc.OCTEN_STATE_Y).cpu().numpy()),
+                "F": (g.state(oc.OCTEN_STATE_FACTORS).cpu().numpy(),
+                      e.state(oc.OCTEN_STATE_FACTORS).cpu().numpy()),
+                "A": (A.cpu().numpy(), A2.cpu().numpy()), "C": (C.cpu().numpy(), C2.cpu().numpy())})
+        rounds.append((replayed, res))
+    group.close()
+    for e in grp_engs + twin_engs:
+        e.close()
+    return rounds
+
+
+def test_group_step_equals_handle_by_handle_calls():
+    rounds = _run(SHAPES, 60)
+    assert [rp for rp, _ in rounds] == [False] + [True] * (ROUNDS - 1)
+    for r, (_, res) in enumerate(rounds):
+        for q, item in enumerate(res):
+            for key, (a, b) in item.items():
+                assert np.array_equal(a, b), (r, q, key, float(np.max(np.abs(a - b))))
+
+
+def test_group_fp64_streams_match_oracle():
+    """Two FP64 streams in a group against the oracle (ALS with a fixed number
+    of sweeps, one workgroup per replica)."""
+    import torch
+    from oracle import OctenOracle
+    from paper_1807_01350_amd import octen as oc
+    cases = [Case("gf0", 50, 50, 5, 4, 20, 3, (30, 10, 10), iters=25, config_id=71),
+             Case("gf1", 70, 60, 3, 3, 16, 2, (20, 7, 7), iters=25, config_id=72)]
+    ins = [make_inputs(c) for c in cases]
+    engs, oras, bufs = [], [], []
+    for c, (X, U, V, Ws, init) in zip(cases, ins):
+        e = oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, torch.from_numpy(U).cuda(),
+                     torch.from_numpy(V).cuda(), flags=oc.OCTEN_FLAG_ALS_ONE_WG)
+        o = OctenOracle(c.I, c.J, c.R, c.P, c.Q, c.S, U, V)
+        t0 = c.batches[0]
+        e.compress_batch(torch.from_numpy(X[:t0]).cuda(), torch.from_numpy(Ws[0]).cuda())
+        e.update_replicas()
+        e.cp_als_replicas(c.iters, init=torch.from_numpy(init).cuda())
+        o.compress_batch(X[:t0], Ws[0]); o.update_replicas(); o.cp_als_replicas(c.iters, init=init)
+        engs.append(e); oras.append(o)
+        bufs.append((torch.empty((c.batches[1], c.I, c.J), dtype=torch.float64, device="cuda"),
+                     torch.empty((c.batches[1], c.M1), dtype=torch.float64, device="cuda")))
+    group = oc.Group(engs)
+    for r in (1, 2):
+        for c, (X, U, V, Ws, init), (xb, wb), o in zip(cases, ins, bufs, oras):
+            k0 = sum(c.batches[:r])
+            xb.copy_(torch.from_numpy(X[k0:k0 + c.batches[r]]))
+            wb.copy_(torch.from_numpy(Ws[r]))
+            o.compress_batch(X[k0:k0 + c.batches[r]], Ws[r]); o.update_replicas()
+            o.cp_als_replicas(c.iters)
+        group.step(bufs, cases[0].iters)
+        torch.cuda.synchronize()
+        for e, o in zip(engs, oras):
+            assert rel(e.state(oc.OCTEN_STATE_Y).cpu().numpy(), o.Y) <= 1e-12
+            assert rel(e.state(oc.OCTEN_STATE_FACTORS).cpu().numpy(), o.F) <= 1e-10
+    group.close()
+    for e in engs:
+        e.close()
+
+
+def test_group_recaptures_when_descriptors_change():
+    import torch
+    from paper_1807_01350_amd import octen as oc
+    streams = _streams(SHAPES[:2], 80)
+    engs, bufs = [], []
+    for c, form, X, U, V, Ws, init in streams:
+        e = _engine(c, form, U, V)
+        e.compress_batch(X[:c.batches[0]], Ws[0]); e.update_replicas()
+        e.cp_als_replicas(10, init=init)
+        e.recover_factors(torch.empty((c.I, c.R), dtype=torch.float64, device="cuda"),
+                          torch.empty((c.J, c.R), dtype=torch.float64, device="cuda"),
+                          torch.empty((c.batches[0] + 6 * c.batches[1], c.R), dtype=torch.float64,
+                                      device="cuda"))
+        engs.append(e)
+        bufs.append((X[c.batches[0]:c.batches[0] + c.batches[1]].clone(), Ws[1].clone()))
+    group = oc.Group(engs)
+    outs = []
+    for c, *_ in streams:
+        outs.append((torch.empty((c.I, c.R), dtype=torch.float64, device="cuda"),
+                     torch.empty((c.J, c.R), dtype=torch.float64, device="cuda"),
+                     torch.empty((c.batches[0] + 6 * c.batches[1], c.R), dtype=torch.float64,
+                                 device="cuda")))
+
+    def step(b, iters):
+        rep = group.step(b, iters)
+        for e, (A, B, C) in zip(engs, outs):
+            e.recover_factors_async(A, B, C)   # pending slices back to zero
+        return rep
+
+    flags = [step(bufs, 10), step(bufs, 10), step(bufs, 12)]   # then another sweep count
+    other = [(x.clone(), w) for x, w in bufs]                  # other buffers
+    flags += [step(other, 12), step(other, 12)]
+    assert flags == [False, True, False, False, True]
+    group.close()
+    for e in engs:
+        e.close()
+
+
+@pytest.mark.parametrize("form,J", [("bf16", 1000), ("f32", 1000), ("bf16", 998)])
+def test_autotune_keeps_results_within_tolerance(form, J):
+    import torch
+    from oracle import compress_dense
+    from paper_1807_01350_amd import octen as oc
+    I, R, P, Q, S, t = 300, 6, 12, 60, 3, 6
+    c = Case("tune", I, J, R, P, Q, S, (t,), config_id=90)
+    X, U, V, Ws, init = make_inputs(c, x_dtype=np.float32)
+    tX, tW = torch.from_numpy(X).cuda(), torch.from_numpy(Ws[0]).cuda()
+    e = oc.Octen(I, J, R, P, Q, S, torch.from_numpy(U).cuda(), torch.from_numpy(V).cuda(),
+                 x_dtype="f32", compress_dtype=form)
+    choice = e.autotune(tX)
+    G, variant = divmod(choice, 10)
+    assert 1 <= G <= P and variant in (0, 1, 2)
+    if J % 4:
+        assert variant == 2
+    e.compress_batch(tX, tW)
+    Z = e.state(oc.OCTEN_STATE_Z).cpu().numpy()
+    Zr = compress_dense(X.astype(np.float64), U, V, Ws[0], P, Q, S)
+    assert rel(Z, Zr) <= (2e-2 if form == "bf16" else 1e-5)
+    print(f"[autotune] {form} J={J}: choice {choice}", file=sys.stderr)
+    e.close()
