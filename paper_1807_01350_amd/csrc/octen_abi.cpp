@@ -653,7 +653,9 @@ octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int
     StageTimer tm(h, OCTEN_STAGE_ALS);
     HIPCHK(h, fill_i32(s, h->flags, h->P, 0));
     hipError_t e = hipErrorNotSupported;
-    if (h->als_nw > 0 && !h->group_mode && !(h->cfg.flags & OCTEN_FLAG_ALS_ONE_WG)) {
+    // group branches run concurrently: no cooperative grid there
+    const bool in_branch = h->group_mode;
+    if (h->als_nw > 0 && !in_branch && !(h->cfg.flags & OCTEN_FLAG_ALS_ONE_WG)) {
       e = als_coop(s, h->Y, h->acc_f64, h->P, h->Q, h->R, h->als_nw, h->als_gx, src, h->F,
                    h->lam, h->iters, h->flags, h->als_slots, h->als_ctr, h->als_err, max_iters,
                    tol);
@@ -1172,46 +1174,72 @@ octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int
     drop_graph(g);
     std::vector<int64_t> tpend(n);
     std::vector<HostState> saved(n);
+    int64_t replicas = 0;
     for (int i = 0; i < n; ++i) {
       OKCHK(prepare_step(g->hs[i], desc[i].t));
       tpend[i] = g->hs[i]->t_pend;
       saved[i] = save_state(g->hs[i]);
+      replicas += g->hs[i]->P;
     }
     GHIP(g, hipStreamSynchronize(g->user));
-    GHIP(g, hipStreamBeginCapture(g->main, hipStreamCaptureModeThreadLocal));
-    octen_status st = OCTEN_OK;
-    hipError_t he = hipEventRecord(g->fork, g->main);
-    int done_i = 0;
-    for (int i = 0; i < n && st == OCTEN_OK && he == hipSuccess; ++i) {
-      octen_t h = g->hs[i];
-      he = hipStreamWaitEvent(g->branch[i], g->fork, 0);
-      if (he != hipSuccess) break;
-      const bool timing = h->timing;
-      h->timing = false;
-      h->group_mode = true;
-      h->stream = g->branch[i];
-      st = octen_compress_batch(h, desc[i].X, desc[i].t, desc[i].W, desc[i].slice_scale);
-      if (st == OCTEN_OK) st = octen_update_replicas(h);
-      if (st == OCTEN_OK) st = octen_cp_als_replicas(h, max_iters, tol, OCTEN_INIT_PREV, nullptr, nullptr);
-      h->stream = g->user;
-      h->group_mode = false;
-      h->timing = timing;
-      if (st != OCTEN_OK) { g->err = "handle " + std::to_string(i) + ": " + h->err; break; }
-      he = hipEventRecord(g->join[i], g->branch[i]);
-      if (he == hipSuccess) he = hipStreamWaitEvent(g->main, g->join[i], 0);
-      done_i = i + 1;
-    }
+    // With many replicas in the group the ALS of every handle runs inside its
+    // branch, one workgroup per replica; otherwise the ALS runs after the
+    // join, one handle at a time, on its own (possibly cooperative) path, so
+    // that no two cooperative grids are ever in flight together.
+    bool parallel_als = replicas >= 128;
     hipGraph_t graph = nullptr;
-    const hipError_t ee = hipStreamEndCapture(g->main, &graph);
-    if (st != OCTEN_OK || he != hipSuccess || ee != hipSuccess || done_i != n) {
+    octen_status st = OCTEN_OK;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      st = OCTEN_OK;
+      graph = nullptr;
+      GHIP(g, hipStreamBeginCapture(g->main, hipStreamCaptureModeThreadLocal));
+      hipError_t he = hipEventRecord(g->fork, g->main);
+      int done_i = 0;
+      for (int i = 0; i < n && st == OCTEN_OK && he == hipSuccess; ++i) {
+        octen_t h = g->hs[i];
+        he = hipStreamWaitEvent(g->branch[i], g->fork, 0);
+        if (he != hipSuccess) break;
+        const bool timing = h->timing;
+        h->timing = false;
+        h->group_mode = true;
+        h->stream = g->branch[i];
+        st = octen_compress_batch(h, desc[i].X, desc[i].t, desc[i].W, desc[i].slice_scale);
+        if (st == OCTEN_OK) st = octen_update_replicas(h);
+        if (st == OCTEN_OK && parallel_als)
+          st = octen_cp_als_replicas(h, max_iters, tol, OCTEN_INIT_PREV, nullptr, nullptr);
+        h->stream = g->user;
+        h->group_mode = false;
+        h->timing = timing;
+        if (st != OCTEN_OK) { g->err = "handle " + std::to_string(i) + ": " + h->err; break; }
+        he = hipEventRecord(g->join[i], g->branch[i]);
+        if (he == hipSuccess) he = hipStreamWaitEvent(g->main, g->join[i], 0);
+        done_i = i + 1;
+      }
+      for (int i = 0; !parallel_als && i < n && st == OCTEN_OK && he == hipSuccess && done_i == n;
+           ++i) {
+        octen_t h = g->hs[i];
+        const bool timing = h->timing;
+        h->timing = false;
+        h->stream = g->main;
+        st = octen_cp_als_replicas(h, max_iters, tol, OCTEN_INIT_PREV, nullptr, nullptr);
+        h->stream = g->user;
+        h->timing = timing;
+        if (st != OCTEN_OK) g->err = "handle " + std::to_string(i) + ": " + h->err;
+      }
+      const hipError_t ee = hipStreamEndCapture(g->main, &graph);
+      if (st == OCTEN_OK && he == hipSuccess && ee == hipSuccess && done_i == n) break;
       if (graph) hipGraphDestroy(graph);
+      graph = nullptr;
       for (int i = 0; i < n; ++i) load_state(g->hs[i], saved[i]);
+      (void)hipGetLastError();
       if (st == OCTEN_OK) {
         st = OCTEN_ERR_HIP;
         g->err = std::string("graph capture: ") + hipGetErrorString(he != hipSuccess ? he : ee);
       }
-      return st;
+      if (parallel_als) return st;
+      parallel_als = true;   // capture again with the ALS inside the branches
     }
+    if (!graph) return st;
     g->graph = graph;
     GHIP(g, hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
     g->cap_desc.assign(desc, desc + n);

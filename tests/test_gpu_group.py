@@ -213,3 +213,46 @@ def test_autotune_keeps_results_within_tolerance(form, J):
     assert rel(Z, Zr) <= (2e-2 if form == "bf16" else 1e-5)
     print(f"[autotune] {form} J={J}: choice {choice}", file=sys.stderr)
     e.close()
+
+
+def test_small_group_runs_cooperative_als_after_the_join():
+    """With few replicas the group runs each ALS on the handle's cooperative
+    kernel after its branches join: results equal the handle-by-handle calls
+    of handles without OCTEN_FLAG_ALS_ONE_WG."""
+    import torch
+    from paper_1807_01350_amd import octen as oc
+    shapes = [(300, 280, 6, 12, 60, 3, 40, 10, "bf16"), (200, 240, 5, 8, 40, 3, 30, 8, "f32")]
+    streams = _streams(shapes, 95)
+    grp, twin, bufs = [], [], []
+    for c, form, X, U, V, Ws, init in streams:
+        pair = [oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, U, V, x_dtype="f32", compress_dtype=form)
+                for _ in range(2)]
+        for e in pair:
+            e.compress_batch(X[:c.batches[0]], Ws[0]); e.update_replicas()
+            e.cp_als_replicas(20, init=init)
+            e.recover_factors(torch.empty((c.I, c.R), dtype=torch.float64, device="cuda"),
+                              torch.empty((c.J, c.R), dtype=torch.float64, device="cuda"),
+                              torch.empty((c.K, c.R), dtype=torch.float64, device="cuda"))
+        grp.append(pair[0]); twin.append(pair[1])
+        bufs.append((torch.empty_like(X[:c.batches[1]]), torch.empty_like(Ws[1])))
+    group = oc.Group(grp)
+    flags = []
+    for r in (1, 2, 3):
+        for (c, form, X, U, V, Ws, init), (xb, wb) in zip(streams, bufs):
+            k0 = sum(c.batches[:r])
+            xb.copy_(X[k0:k0 + c.batches[r]]); wb.copy_(Ws[r])
+        flags.append(group.step(bufs, 20, 1e-7))
+        for e, (xb, wb) in zip(twin, bufs):
+            e.compress_batch(xb, wb); e.update_replicas(); e.cp_als_replicas(20, tol=1e-7)
+        for g, e, (c, *_r) in zip(grp, twin, streams):
+            for what in (oc.OCTEN_STATE_Y, oc.OCTEN_STATE_FACTORS, oc.OCTEN_STATE_ITERS):
+                a, b = g.state(what).cpu().numpy(), e.state(what).cpu().numpy()
+                assert np.array_equal(a, b), (r, what)
+            for e2 in (g, e):
+                e2.recover_factors(torch.empty((c.I, c.R), dtype=torch.float64, device="cuda"),
+                                   torch.empty((c.J, c.R), dtype=torch.float64, device="cuda"),
+                                   torch.empty((c.K, c.R), dtype=torch.float64, device="cuda"))
+    assert flags == [False, True, True]
+    group.close()
+    for e in grp + twin:
+        e.close()
