@@ -241,10 +241,11 @@ octen_status octen_autotune(octen_t h, const void* X, int64_t t, int32_t* choice
  * the same handle state replay it, otherwise the graph is captured again.
  * The caller rewrites the batch buffers in place between steps.  Every
  * handle must share one stream and hold replica factors already (its first
- * batch goes through its own calls); ALS runs with OCTEN_INIT_PREV.  With at
- * least 128 replicas in the group each handle's ALS runs in its branch with
- * one workgroup per replica; with fewer, the ALS steps run one after the
- * other after the branches join, each on the handle's usual kernel.
+ * batch goes through its own calls); ALS runs with OCTEN_INIT_PREV.  Handles
+ * whose ALS is a cooperative grid run it after the branches join, one after
+ * the other (no cooperative grid shares the GPU with other work of the
+ * step); the others (OCTEN_FLAG_ALS_ONE_WG, or replicas too large) run it in
+ * their branch, one workgroup per replica.
  * Recovery stays per handle, outside the graph. */
 typedef struct octen_group* octen_group_t;
 typedef struct {

@@ -1182,11 +1182,12 @@ octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int
       replicas += g->hs[i]->P;
     }
     GHIP(g, hipStreamSynchronize(g->user));
-    // With many replicas in the group the ALS of every handle runs inside its
-    // branch, one workgroup per replica; otherwise the ALS runs after the
-    // join, one handle at a time, on its own (possibly cooperative) path, so
-    // that no two cooperative grids are ever in flight together.
-    bool parallel_als = replicas >= 128;
+    // A handle whose ALS is a cooperative grid runs it after the branches
+    // join, one handle at a time, so that no cooperative grid ever shares the
+    // GPU with other work of the step; the other handles run their ALS (one
+    // workgroup per replica) inside their branch.
+    (void)replicas;
+    bool parallel_als = false;
     hipGraph_t graph = nullptr;
     octen_status st = OCTEN_OK;
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -1205,7 +1206,8 @@ octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int
         h->stream = g->branch[i];
         st = octen_compress_batch(h, desc[i].X, desc[i].t, desc[i].W, desc[i].slice_scale);
         if (st == OCTEN_OK) st = octen_update_replicas(h);
-        if (st == OCTEN_OK && parallel_als)
+        const bool coop = h->als_nw > 0 && !(h->cfg.flags & OCTEN_FLAG_ALS_ONE_WG);
+        if (st == OCTEN_OK && (parallel_als || !coop))
           st = octen_cp_als_replicas(h, max_iters, tol, OCTEN_INIT_PREV, nullptr, nullptr);
         h->stream = g->user;
         h->group_mode = false;
@@ -1218,6 +1220,7 @@ octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int
       for (int i = 0; !parallel_als && i < n && st == OCTEN_OK && he == hipSuccess && done_i == n;
            ++i) {
         octen_t h = g->hs[i];
+        if (!(h->als_nw > 0 && !(h->cfg.flags & OCTEN_FLAG_ALS_ONE_WG))) continue;
         const bool timing = h->timing;
         h->timing = false;
         h->stream = g->main;
