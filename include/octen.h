@@ -241,7 +241,7 @@ octen_status octen_autotune(octen_t h, const void* X, int64_t t, int32_t* choice
  * the same handle state replay it, otherwise the graph is captured again.
  * The caller rewrites the batch buffers in place between steps.  Every
  * handle must share one stream and hold replica factors already (its first
- * batch goes through its own calls); ALS runs with OCTEN_INIT_PREV.  Handles
+ * batch goes through its own calls).  Handles
  * whose ALS is a cooperative grid run it after the branches join, one after
  * the other (no cooperative grid shares the GPU with other work of the
  * step); the others (OCTEN_FLAG_ALS_ONE_WG, or replicas too large) run it in
@@ -256,8 +256,11 @@ typedef struct {
 } octen_batch_desc;
 
 octen_status octen_group_create(const octen_t* handles, int32_t n, octen_group_t* out);
+/* init_mode: OCTEN_INIT_PREV or OCTEN_INIT_LEARNED (every handle then needs
+ * a network, octen_warmstart_set).  replayed_host: NULL or 1 when the
+ * captured graph was replayed. */
 octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int32_t max_iters,
-                              double tol, int32_t* replayed_host);
+                              double tol, int32_t init_mode, int32_t* replayed_host);
 octen_status octen_group_destroy(octen_group_t g);
 const char* octen_group_last_error(octen_group_t g);
 
@@ -315,7 +318,7 @@ octen_status octen_mlp_get_params(octen_mlp_t m, float* dst);
 /* Attach a network (In = 4Q + D, Out = 3Q; not copied: it must outlive its
  * use by the handle; NULL: features and targets only, for collecting
  * training pairs) and a sketch matrix G [D][Q^3] (device FP32, copied),
- * 1 <= D <= 32. */
+ * 1 <= D <= 32; at most 32 replicas (else OCTEN_ERR_UNSUPPORTED). */
 octen_status octen_warmstart_set(octen_t h, octen_mlp_t m, const float* G, int32_t D);
 
 /* Features of every replica column (rows ordered replica-major) from the

@@ -837,6 +837,7 @@ octen_status octen_warmstart_set(octen_t h, octen_mlp_t m, const float* G, int32
   if (!G) return fail(h, OCTEN_ERR_ARG, "sketch matrix must be non-null");
   if (D < 1 || D > 32) return fail(h, OCTEN_ERR_ARG, "sketch length must be in [1, 32]");
   const int Q = h->Q, R = h->R, P = h->P;
+  if (P > 32) return fail(h, OCTEN_ERR_UNSUPPORTED, "the learned warm start takes at most 32 replicas");
   if (m && (m->L.nin != 4 * Q + D || m->L.nout != 3 * Q))
     return fail(h, OCTEN_ERR_ARG, "network must map 4Q + D inputs to 3Q outputs");
   const int64_t Q3 = (int64_t)Q * Q * Q;
@@ -1015,6 +1016,7 @@ struct octen_group {
   std::vector<std::vector<const void*>> cap_bufs;
   int32_t cap_iters = 0;
   double cap_tol = 0.0;
+  int32_t cap_init = 0;
   std::string err;
 };
 
@@ -1147,9 +1149,11 @@ octen_status octen_group_destroy(octen_group_t g) {
 const char* octen_group_last_error(octen_group_t g) { return g ? g->err.c_str() : "null group"; }
 
 octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int32_t max_iters,
-                              double tol, int32_t* replayed_host) {
+                              double tol, int32_t init_mode, int32_t* replayed_host) {
   if (!g) return OCTEN_ERR_ARG;
   if (!desc || max_iters < 1 || !(tol >= 0.0)) return gfail(g, OCTEN_ERR_ARG, "bad arguments");
+  if (init_mode != OCTEN_INIT_PREV && init_mode != OCTEN_INIT_LEARNED)
+    return gfail(g, OCTEN_ERR_ARG, "init_mode must be OCTEN_INIT_PREV or OCTEN_INIT_LEARNED");
   const int n = (int)g->hs.size();
   for (int i = 0; i < n; ++i) {
     octen_t h = g->hs[i];
@@ -1160,8 +1164,11 @@ octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int
     if (h->z_ready)
       return gfail(g, OCTEN_ERR_STATE, "handle " + std::to_string(i) + " has a batch not yet added");
     if (h->stream != g->user) return gfail(g, OCTEN_ERR_STATE, "handle stream changed");
+    if (init_mode == OCTEN_INIT_LEARNED && !h->ws_mlp)
+      return gfail(g, OCTEN_ERR_STATE, "handle " + std::to_string(i) + " has no warm-start network");
   }
-  bool replay = g->exec && g->cap_iters == max_iters && g->cap_tol == tol;
+  bool replay = g->exec && g->cap_iters == max_iters && g->cap_tol == tol &&
+                g->cap_init == init_mode;
   for (int i = 0; replay && i < n; ++i) {
     octen_t h = g->hs[i];
     replay = same_desc(desc[i], g->cap_desc[i]) && h->t_pend == g->cap_tpend[i] &&
@@ -1177,6 +1184,10 @@ octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int
     int64_t replicas = 0;
     for (int i = 0; i < n; ++i) {
       OKCHK(prepare_step(g->hs[i], desc[i].t));
+      if (init_mode == OCTEN_INIT_LEARNED) {
+        const octen_status ms = octen_mlp_ensure_rows(g->hs[i]->ws_mlp, (int64_t)g->hs[i]->P * g->hs[i]->R);
+        if (ms != OCTEN_OK) return gfail(g, ms, "warm-start network buffers");
+      }
       tpend[i] = g->hs[i]->t_pend;
       saved[i] = save_state(g->hs[i]);
       replicas += g->hs[i]->P;
@@ -1208,7 +1219,7 @@ octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int
         if (st == OCTEN_OK) st = octen_update_replicas(h);
         const bool coop = h->als_nw > 0 && !(h->cfg.flags & OCTEN_FLAG_ALS_ONE_WG);
         if (st == OCTEN_OK && (parallel_als || !coop))
-          st = octen_cp_als_replicas(h, max_iters, tol, OCTEN_INIT_PREV, nullptr, nullptr);
+          st = octen_cp_als_replicas(h, max_iters, tol, init_mode, nullptr, nullptr);
         h->stream = g->user;
         h->group_mode = false;
         h->timing = timing;
@@ -1224,7 +1235,7 @@ octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int
         const bool timing = h->timing;
         h->timing = false;
         h->stream = g->main;
-        st = octen_cp_als_replicas(h, max_iters, tol, OCTEN_INIT_PREV, nullptr, nullptr);
+        st = octen_cp_als_replicas(h, max_iters, tol, init_mode, nullptr, nullptr);
         h->stream = g->user;
         h->timing = timing;
         if (st != OCTEN_OK) g->err = "handle " + std::to_string(i) + ": " + h->err;
@@ -1251,6 +1262,7 @@ octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int
     for (int i = 0; i < n; ++i) g->cap_bufs[i] = step_buffers(g->hs[i]);
     g->cap_iters = max_iters;
     g->cap_tol = tol;
+    g->cap_init = init_mode;
   } else {
     // the calls a capture records advance each handle's host state; a
     // replay applies the same transitions

@@ -31,56 +31,72 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// partials[p][ch][0..D-1] = G[:, chunk] . z[chunk], [D] = ||z[chunk]||^2
+// Sketch as one contraction S[p][d] = sum_e Z_p[e] G[d][e] on
+// v_mfma_f32_32x32x2f32: rows are the replicas (up to 32), columns the
+// sketch rows.  Each wavefront walks a range of e eight entries at a time:
+// lane (r, h) loads four consecutive entries 4h .. 4h + 3 of row r of Z and
+// of G, and four MFMAs take entry i of both halves (the pairing over k is
+// the same on both operands, so the sum is unchanged).  The squared norms of
+// the rows of Z come along in the same pass.
+// part[ch][32][33]: dots (32 x 32, replica-major) then the squared norms.
+typedef float f32x16w __attribute__((ext_vector_type(16)));
+typedef float f32x4w __attribute__((ext_vector_type(4)));
+constexpr int SK_CHUNK = 4096;   // entries per workgroup (1024 per wavefront)
+
 template <typename TZ>
-__global__ __launch_bounds__(NT) void sketch_partial_kernel(const TZ* __restrict__ Z,
-                                                            const float* __restrict__ G,
-                                                            int64_t Q3, int D, int64_t chunk,
-                                                            int nch, double* __restrict__ part) {
-  __shared__ double red[4][DMAX + 1];
-  const int ch = blockIdx.x, p = blockIdx.y;
+__global__ __launch_bounds__(NT) void sketch_mfma_kernel(const TZ* __restrict__ Z,
+                                                         const float* __restrict__ G, int P,
+                                                         int64_t Q3, int D, int nch,
+                                                         float* __restrict__ part) {
+  __shared__ float red[4][32 * 33];
+  const int ch = blockIdx.x;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int64_t e0 = ch * chunk, e1 = e0 + chunk < Q3 ? e0 + chunk : Q3;
-  const TZ* z = Z + (int64_t)p * Q3;
-  double acc[DMAX], zz = 0.0;
+  const int r = lane % 32, h = lane / 32;
+  const int64_t w0 = (int64_t)ch * SK_CHUNK + (int64_t)wave * (SK_CHUNK / 4);
+  const int64_t w1 = w0 + SK_CHUNK / 4 < Q3 ? w0 + SK_CHUNK / 4 : Q3;
+  const bool zrow = r < P, grow = r < D;
+  const TZ* zr = Z + (int64_t)(zrow ? r : 0) * Q3;
+  const float* gr = G + (int64_t)(grow ? r : 0) * Q3;
+  f32x16w acc;
 #pragma unroll
-  for (int d = 0; d < DMAX; ++d) acc[d] = 0.0;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += NT) {
-    const double v = (double)z[e];
-    zz = fma(v, v, zz);
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  float zz = 0.f;
+  for (int64_t e0 = w0; e0 < w1; e0 += 8) {
+    float zv[4], gv[4];
 #pragma unroll
-    for (int d = 0; d < DMAX; ++d)
-      if (d < D) acc[d] = fma((double)G[(int64_t)d * Q3 + e], v, acc[d]);
-  }
-#pragma unroll
-  for (int d = 0; d < DMAX; ++d) {
-    if (d < D) {
-      const double s = wave_sum(acc[d]);
-      if (lane == 0) red[wave][d] = s;
+    for (int i = 0; i < 4; ++i) {
+      const int64_t e = e0 + 4 * h + i;
+      const bool ok = e < w1;
+      zv[i] = (zrow && ok) ? (float)zr[e] : 0.f;
+      gv[i] = (grow && ok) ? gr[e] : 0.f;
+      zz = fmaf(zv[i], zv[i], zz);
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(zv[i], gv[i], acc, 0, 0, 0);
   }
-  {
-    const double s = wave_sum(zz);
-    if (lane == 0) red[wave][DMAX] = s;
+  // D[i] of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4 (replica), column l % 32
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int row = 8 * (i / 4) + 4 * h + (i % 4);
+    red[wave][row * 33 + r] = acc[i];
   }
+  zz += __shfl_xor(zz, 32, 64);
+  if (h == 0) red[wave][r * 33 + 32] = zz;
   __syncthreads();
-  double* out = part + ((int64_t)p * nch + ch) * (D + 1);
-  if (threadIdx.x < D)
-    out[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
-                       red[3][threadIdx.x];
-  if (threadIdx.x == D) out[D] = red[0][DMAX] + red[1][DMAX] + red[2][DMAX] + red[3][DMAX];
+  float* out = part + (int64_t)ch * 32 * 33;
+  for (int e = threadIdx.x; e < 32 * 33; e += NT)
+    out[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
 }
 
-// sk[p][d] = sum_ch dots / sqrt(sum_ch norms), chunks in order
-__global__ void sketch_final_kernel(const double* __restrict__ part, int nch, int D,
+// sk[p][d] = sum_ch dots / sqrt(sum_ch norms), chunks in order (FP64 sums)
+__global__ void sketch_final_kernel(const float* __restrict__ part, int nch, int D,
                                     float* __restrict__ sk) {
   const int p = blockIdx.x, d = threadIdx.x;
   if (d >= D) return;
-  const double* base = part + (int64_t)p * nch * (D + 1);
   double s = 0.0, zz = 0.0;
   for (int ch = 0; ch < nch; ++ch) {
-    s += base[(int64_t)ch * (D + 1) + d];
-    zz += base[(int64_t)ch * (D + 1) + D];
+    s += part[(int64_t)ch * 32 * 33 + p * 33 + d];
+    zz += part[(int64_t)ch * 32 * 33 + p * 33 + 32];
   }
   sk[p * D + d] = zz > 0.0 ? (float)(s / sqrt(zz)) : 0.f;
 }
@@ -324,25 +340,27 @@ __global__ __launch_bounds__(NT) void judge_final_kernel(const double* __restric
 
 hipError_t ws_sketch(hipStream_t s, const void* Z, bool z_f64, int P, int Q, const float* G, int D,
                      double* part, int64_t part_cap, float* sk) {
-  if (D < 1 || D > DMAX) return hipErrorInvalidValue;
+  if (D < 1 || D > DMAX || P > 32) return hipErrorInvalidValue;
   const int64_t Q3 = (int64_t)Q * Q * Q;
-  const int64_t chunk = 8192;
-  const int nch = (int)((Q3 + chunk - 1) / chunk);
-  if ((int64_t)P * nch * (D + 1) > part_cap) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)nch, (unsigned)P);
+  const int nch = (int)((Q3 + SK_CHUNK - 1) / SK_CHUNK);
+  // the partials are FP32: part_cap counts doubles
+  if ((int64_t)nch * 32 * 33 > 2 * part_cap) return hipErrorInvalidValue;
+  float* pf = (float*)part;
   if (z_f64)
-    hipLaunchKernelGGL(sketch_partial_kernel<double>, grid, dim3(NT), 0, s, (const double*)Z, G,
-                       Q3, D, chunk, nch, part);
+    hipLaunchKernelGGL(sketch_mfma_kernel<double>, dim3(nch), dim3(NT), 0, s, (const double*)Z, G,
+                       P, Q3, D, nch, pf);
   else
-    hipLaunchKernelGGL(sketch_partial_kernel<float>, grid, dim3(NT), 0, s, (const float*)Z, G, Q3,
-                       D, chunk, nch, part);
-  hipLaunchKernelGGL(sketch_final_kernel, dim3(P), dim3(64), 0, s, part, nch, D, sk);
+    hipLaunchKernelGGL(sketch_mfma_kernel<float>, dim3(nch), dim3(NT), 0, s, (const float*)Z, G, P,
+                       Q3, D, nch, pf);
+  hipLaunchKernelGGL(sketch_final_kernel, dim3(P), dim3(64), 0, s, pf, nch, D, sk);
   return hipGetLastError();
 }
 
 int64_t ws_sketch_part_len(int P, int Q, int D) {
+  (void)P;
+  (void)D;
   const int64_t Q3 = (int64_t)Q * Q * Q;
-  return (int64_t)P * ((Q3 + 8191) / 8192) * (D + 1);
+  return ((Q3 + SK_CHUNK - 1) / SK_CHUNK) * 32 * 33 / 2 + 1;
 }
 
 hipError_t ws_mode3_change(hipStream_t s, const void* Z, bool z_f64, const double* F,

@@ -99,7 +99,7 @@ _SIGS = {
     "octen_mlp_last_activations": ([_vp, _i64, _vp, _vp], _i32),
     "octen_autotune": ([_vp, _vp, _i64, _vp], _i32),
     "octen_group_create": ([_vp, _i32, ctypes.POINTER(_vp)], _i32),
-    "octen_group_step": ([_vp, _vp, _i32, _f64, _vp], _i32),
+    "octen_group_step": ([_vp, _vp, _i32, _f64, _i32, _vp], _i32),
     "octen_group_destroy": ([_vp], _i32),
     "octen_group_last_error": ([_vp], ctypes.c_char_p),
     "octen_warmstart_set": ([_vp, _vp, _vp, _i32], _i32),
@@ -278,9 +278,10 @@ def octen_group_create(handles):
     return st, g
 
 
-def octen_group_step(g, descs, max_iters, tol, replayed=None):
+def octen_group_step(g, descs, max_iters, tol, init_mode=OCTEN_INIT_PREV, replayed=None):
     arr = (octen_batch_desc * len(descs))(*descs)
-    return _lib.octen_group_step(g, ctypes.cast(arr, _vp), int(max_iters), float(tol), replayed)
+    return _lib.octen_group_step(g, ctypes.cast(arr, _vp), int(max_iters), float(tol),
+                                 int(init_mode), replayed)
 
 
 def octen_group_destroy(g):
@@ -301,13 +302,15 @@ class Group:
             raise OctenError(st, "octen_group_create")
         self.g = g
 
-    def step(self, batches, max_iters, tol=0.0):
+    def step(self, batches, max_iters, tol=0.0, learned=False):
         """batches: list of (X, W) device tensors (same objects each round
         for replay).  Returns True when the captured graph was replayed."""
         descs = [octen_batch_desc(X.data_ptr(), X.shape[0], W.data_ptr(), None)
                  for X, W in batches]
         rep = ctypes.c_int32(0)
-        st = octen_group_step(self.g, descs, max_iters, tol, ctypes.cast(ctypes.byref(rep), _vp))
+        st = octen_group_step(self.g, descs, max_iters, tol,
+                              OCTEN_INIT_LEARNED if learned else OCTEN_INIT_PREV,
+                              ctypes.cast(ctypes.byref(rep), _vp))
         if st != OCTEN_OK:
             raise OctenError(st, "octen_group_step", octen_group_last_error(self.g))
         for e, (X, _) in zip(self.engines, batches):
