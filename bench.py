@@ -76,7 +76,7 @@ def traffic_from_profile(form):
     rocprofv3 counter summary, if it was taken on the current kernel source."""
     import hashlib
     src = os.path.join(ROOT, "paper_1807_01350_amd", "csrc", "compress_mfma.hip")
-    prof = os.path.join(ROOT, "profiles", f"compress_fused_{form}_dense1000_counters.md")
+    prof = os.path.join(ROOT, "profiles", f"compress_pipe_{form}_dense1000_counters.md")
     if not os.path.exists(prof):
         return None
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -661,7 +661,7 @@ def main():
         roof = {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_PEAK_TFLOPS["f32"],
                 "unit": "TFLOP/s", "frac": round(tflops / MFMA_PEAK_TFLOPS["f32"], 4),
                 "traffic": traffic}
-    roof["kernel"] = "compress_fused (modes 1 and 2 of the batch compression)"
+    roof["kernel"] = "compress_pipe (modes 1 and 2 of the batch compression)"
     roof["algorithmic_bytes_per_launch"] = bytes_launch
     roof["algorithmic_flops_per_launch"] = flops_launch
     roof["mfma_frac"] = round(tflops / MFMA_PEAK_TFLOPS[args.form], 4)

@@ -34,10 +34,24 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int BM = 128;   // rows i per tile
 constexpr int BN = 256;   // stage-1 columns per tile (shared + G replicas)
 constexpr int KC = 32;    // j per pipeline chunk
-constexpr int NT = 256;   // threads (4 waves, 2 x 2 over the BM x BN tile)
+
+// Rows per tile and threads per workgroup: the BF16 kernels take 256 rows
+// with eight wavefronts (4 x 2 over the tile), so V is streamed from L2 once
+// per 256 rows of X and half as many row-block partials are written; the
+// FP32 kernels keep 128 rows and four wavefronts (their transposed stage-2
+// tile would not fit in LDS at 256 rows).
+template <int KIND>
+struct Tile;
+template <>
+struct Tile<1> {
+  static constexpr int BM = 128, NT = 256;
+};
+template <>
+struct Tile<2> {
+  static constexpr int BM = 256, NT = 512;
+};
 
 // Input kinds: 1 = f32 MFMA (32x32x2), 2 = bf16 MFMA (32x32x16).
 template <int KIND> struct Kind;
@@ -77,6 +91,7 @@ __device__ __forceinline__ typename Kind<KIND>::T cvt(float x) {
 template <int KIND>
 __device__ __forceinline__ int a_pos(int r, int kk) {
   constexpr int KS = Kind<KIND>::KSTEP, E = Kind<KIND>::EPL;
+  constexpr int BM = Tile<KIND>::BM;
   const int ks = kk / KS, kin = kk % KS;
   const int lane = (r % 32) + 32 * (kin / E);
   return ((ks * (BM / 32) + r / 32) * 64 + lane) * E + (kin % E);
@@ -94,7 +109,8 @@ struct Args {
 };
 
 template <int KIND, int QT, bool VEC>
-__global__ __launch_bounds__(NT) void compress_fused(Args g) {
+__global__ __launch_bounds__(Tile<KIND>::NT) void compress_fused(Args g) {
+  constexpr int BM = Tile<KIND>::BM, NT = Tile<KIND>::NT;
   using T = typename Kind<KIND>::T;
   using Frag = typename Kind<KIND>::Frag;
   constexpr int KS = Kind<KIND>::KSTEP, E = Kind<KIND>::EPL;
@@ -223,11 +239,14 @@ __global__ __launch_bounds__(NT) void compress_fused(Args g) {
   const int p0 = cb * g.G;
   const int gcount = (g.P - p0) < g.G ? (g.P - p0) : g.G;
   const float inv = 1.0f / sc;
-  for (int gg = wave; gg < gcount; gg += 4) {
+  // each replica's Q x Q output is split between two wavefronts by tile rows
+  constexpr int QH = (QT + 1) / 2;
+  for (int item = wave; item < 2 * gcount; item += NT / 64) {
+    const int gg = item >> 1, ih = item & 1;
     const int p = p0 + gg;
-    f32x16 m[QT][QT];
+    f32x16 m[QH][QT];
 #pragma unroll
-    for (int i = 0; i < QT; ++i)
+    for (int i = 0; i < QH; ++i)
 #pragma unroll
       for (int j = 0; j < QT; ++j)
 #pragma unroll
@@ -238,28 +257,34 @@ __global__ __launch_bounds__(NT) void compress_fused(Args g) {
 #pragma unroll
     for (int j = 0; j < QT; ++j) colrow[j] = tc[j * 32 + lane % 32];
     for (int ks = 0; ks < BM / KS; ++ks) {
-      Frag af[QT];
+      Frag af[QH];
 #pragma unroll
-      for (int i = 0; i < QT; ++i) af[i] = Kind<KIND>::ld(Up + ((int64_t)(ks * QT + i) * 64 + lane) * E);
+      for (int ii = 0; ii < QH; ++ii) {
+        const int i = ih * QH + ii < QT ? ih * QH + ii : QT - 1;
+        af[ii] = Kind<KIND>::ld(Up + ((int64_t)(ks * QT + i) * 64 + lane) * E);
+      }
 #pragma unroll
       for (int j = 0; j < QT; ++j) {
         const Frag bf = Kind<KIND>::ld(T2t + colrow[j] * T2LD + ks * KS + (lane / 32) * E);
 #pragma unroll
-        for (int i = 0; i < QT; ++i) m[i][j] = Kind<KIND>::mma(af[i], bf, m[i][j]);
+        for (int ii = 0; ii < QH; ++ii) m[ii][j] = Kind<KIND>::mma(af[ii], bf, m[ii][j]);
       }
     }
     float* out = g.Mpart + (((int64_t)k * g.nrb + rb) * g.P + p) * g.Q * g.Q;
 #pragma unroll
-    for (int i = 0; i < QT; ++i)
+    for (int ii = 0; ii < QH; ++ii) {
+      const int i = ih * QH + ii;
+      if (i >= QT) continue;
 #pragma unroll
       for (int j = 0; j < QT; ++j) {
         const int bcol = j * 32 + lane % 32;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
           const int arow = i * 32 + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-          if (arow < g.Q && bcol < g.Q) out[arow * g.Q + bcol] = m[i][j][e] * inv;
+          if (arow < g.Q && bcol < g.Q) out[arow * g.Q + bcol] = m[ii][j][e] * inv;
         }
       }
+    }
   }
 }
 
@@ -282,7 +307,8 @@ typedef __attribute__((address_space(1))) void* gbl_vptr;
 // U image or zero rows of the V image, so they add nothing.  Needs J % 4 == 0
 // and 16-byte aligned X.
 template <int KIND, int QT, int NSTAGE>
-__global__ __launch_bounds__(NT) void compress_pipe(Args g) {
+__global__ __launch_bounds__(Tile<KIND>::NT) void compress_pipe(Args g) {
+  constexpr int BM = Tile<KIND>::BM, NT = Tile<KIND>::NT;
   using T = typename Kind<KIND>::T;
   using Frag = typename Kind<KIND>::Frag;
   constexpr int KS = Kind<KIND>::KSTEP, E = Kind<KIND>::EPL;
@@ -418,11 +444,14 @@ __global__ __launch_bounds__(NT) void compress_pipe(Args g) {
   const int p0 = cb * g.G;
   const int gcount = (g.P - p0) < g.G ? (g.P - p0) : g.G;
   const float inv = 1.0f / sc;
-  for (int gg = wave; gg < gcount; gg += 4) {
+  // each replica's Q x Q output is split between two wavefronts by tile rows
+  constexpr int QH = (QT + 1) / 2;
+  for (int item = wave; item < 2 * gcount; item += NT / 64) {
+    const int gg = item >> 1, ih = item & 1;
     const int p = p0 + gg;
-    f32x16 m[QT][QT];
+    f32x16 m[QH][QT];
 #pragma unroll
-    for (int i = 0; i < QT; ++i)
+    for (int i = 0; i < QH; ++i)
 #pragma unroll
       for (int j = 0; j < QT; ++j)
 #pragma unroll
@@ -433,28 +462,34 @@ __global__ __launch_bounds__(NT) void compress_pipe(Args g) {
 #pragma unroll
     for (int j = 0; j < QT; ++j) colrow[j] = tc[j * 32 + lane % 32];
     for (int ks = 0; ks < BM / KS; ++ks) {
-      Frag af[QT];
+      Frag af[QH];
 #pragma unroll
-      for (int i = 0; i < QT; ++i) af[i] = Kind<KIND>::ld(Up + ((int64_t)(ks * QT + i) * 64 + lane) * E);
+      for (int ii = 0; ii < QH; ++ii) {
+        const int i = ih * QH + ii < QT ? ih * QH + ii : QT - 1;
+        af[ii] = Kind<KIND>::ld(Up + ((int64_t)(ks * QT + i) * 64 + lane) * E);
+      }
 #pragma unroll
       for (int j = 0; j < QT; ++j) {
         const Frag bf = Kind<KIND>::ld(T2t + colrow[j] * T2LD + ks * KS + (lane / 32) * E);
 #pragma unroll
-        for (int i = 0; i < QT; ++i) m[i][j] = Kind<KIND>::mma(af[i], bf, m[i][j]);
+        for (int ii = 0; ii < QH; ++ii) m[ii][j] = Kind<KIND>::mma(af[ii], bf, m[ii][j]);
       }
     }
     float* out = g.Mpart + (((int64_t)k * g.nrb + rb) * g.P + p) * g.Q * g.Q;
 #pragma unroll
-    for (int i = 0; i < QT; ++i)
+    for (int ii = 0; ii < QH; ++ii) {
+      const int i = ih * QH + ii;
+      if (i >= QT) continue;
 #pragma unroll
       for (int j = 0; j < QT; ++j) {
         const int bcol = j * 32 + lane % 32;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
           const int arow = i * 32 + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-          if (arow < g.Q && bcol < g.Q) out[arow * g.Q + bcol] = m[i][j][e] * inv;
+          if (arow < g.Q && bcol < g.Q) out[arow * g.Q + bcol] = m[ii][j][e] * inv;
         }
       }
+    }
   }
 }
 
@@ -488,6 +523,7 @@ template <int KIND>
 __global__ void pack_u(const double* __restrict__ U, int64_t I, int M1, int P, int Q, int S,
                        int QT, int nrb, typename Kind<KIND>::T* __restrict__ out) {
   constexpr int KS = Kind<KIND>::KSTEP, E = Kind<KIND>::EPL;
+  constexpr int BM = Tile<KIND>::BM;
   const int64_t tot = (int64_t)nrb * P * (BM / KS) * QT * 64 * E;
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < tot;
        x += (int64_t)gridDim.x * blockDim.x) {
@@ -521,13 +557,14 @@ hipError_t launch_fused(hipStream_t s, const Args& a, size_t lds) {
                                      (int)lds);
   if (e != hipSuccess) return e;
   const int per = (a.tiles + 7) / 8;
-  hipLaunchKernelGGL(fn, dim3(8 * per), dim3(NT), lds, s, a);
+  hipLaunchKernelGGL(fn, dim3(8 * per), dim3(Tile<KIND>::NT), lds, s, a);
   return hipGetLastError();
 }
 
 template <int KIND, int QT>
 hipError_t launch_pipe(hipStream_t s, const Args& a) {
-  constexpr int NS = KIND == 2 ? 4 : 3;
+  constexpr int NS = 3;
+  constexpr int BM = Tile<KIND>::BM;
   constexpr size_t stage = (size_t)BM * KC * 4 + (size_t)chunk_elems<KIND>(BN / 32) *
                                                      sizeof(typename Kind<KIND>::T);
   const size_t t2 = (size_t)(BN + 1) * (BM + 16 / sizeof(typename Kind<KIND>::T)) *
@@ -538,7 +575,7 @@ hipError_t launch_pipe(hipStream_t s, const Args& a) {
                                      (int)lds);
   if (e != hipSuccess) return e;
   const int per = (a.tiles + 7) / 8;
-  hipLaunchKernelGGL(fn, dim3(8 * per), dim3(NT), lds, s, a);
+  hipLaunchKernelGGL(fn, dim3(8 * per), dim3(Tile<KIND>::NT), lds, s, a);
   return hipGetLastError();
 }
 
@@ -602,6 +639,7 @@ hipError_t mfma_plan_create(const CompressShape& sh, int in_kind, const double* 
   if (G < 1) { delete p; return hipErrorNotSupported; }
   p->G = G;
   p->ncb = (P + G - 1) / G;
+  const int BM = in_kind == 2 ? Tile<2>::BM : Tile<1>::BM;
   p->nrb = (int)((sh.I + BM - 1) / BM);
   p->nchunk = (int)((sh.J + KC - 1) / KC);
   p->QT = (Q + 31) / 32;
