@@ -619,8 +619,10 @@ def main():
         eng.cp_als_replicas(args.iters, init=tinit if b == 0 else None)
         eng.recover_factors_async(A, B, C)
 
-    # initial summary (untimed), then warmup batches
+    # initial summary (untimed), tuning of the compression kernel and of the
+    # ALS launch shape on it (untimed), then warmup batches
     step(0, 0, c.t0)
+    tuned = {"compress": eng.autotune(X[c.t0:c.t0 + t]), "als": eng.autotune_als(10)}
     k0 = c.t0
     for b in range(1, args.warmup + 1):
         step(b, k0, t)
@@ -693,6 +695,7 @@ def main():
         "compression_gbs": round(gbs, 1),
         "compression_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
         "stage_ms": {k: (round(v, 4) if v is not None else None) for k, v in st.items()},
+        "autotuned": tuned,
         "fit": fit,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -234,6 +234,14 @@ int32_t octen_abi_version(void);
  * OCTEN_ERR_UNSUPPORTED).  Synchronises. */
 octen_status octen_autotune(octen_t h, const void* X, int64_t t, int32_t* choice_host);
 
+/* Times the cooperative ALS for `sweeps` sweeps on the current summaries with
+ * each workgroups-per-replica count (powers of two and the largest that is
+ * co-resident) and the replica slab in LDS or in global memory, starting from
+ * the current factors, and keeps the fastest; the factors are restored
+ * afterwards.  choice_host: NULL or 10 * workgroups + (1 if the slab is in
+ * global memory).  Needs factors from an earlier ALS call.  Synchronises. */
+octen_status octen_autotune_als(octen_t h, int32_t sweeps, int32_t* choice_host);
+
 /* A group runs one update step (compress, update, ALS) of many handles as
  * one captured HIP graph: each handle's launches form a parallel branch.
  * The first step with given descriptors captures the graph; later steps

@@ -998,6 +998,84 @@ octen_status octen_autotune(octen_t h, const void* X, int64_t t, int32_t* choice
   return OCTEN_OK;
 }
 
+octen_status octen_autotune_als(octen_t h, int32_t sweeps, int32_t* choice_host) {
+  if (!h) return OCTEN_ERR_ARG;
+  if (sweeps < 1 || sweeps > 1000) return fail(h, OCTEN_ERR_ARG, "sweeps must be in [1, 1000]");
+  if (!h->have_factors) return fail(h, OCTEN_ERR_STATE, "ALS must have run once (factors needed)");
+  if (h->als_nw <= 0 || (h->cfg.flags & OCTEN_FLAG_ALS_ONE_WG))
+    return fail(h, OCTEN_ERR_UNSUPPORTED, "no cooperative ALS on this handle");
+  hipStream_t s = h->stream;
+  const int P = h->P, Q = h->Q, R = h->R;
+  const int per_xcd = (P + 7) / 8;
+  int max_nw = 32 / per_xcd;
+  if (max_nw > Q) max_nw = Q;
+  const size_t cap = 160 * 1024;
+  // candidates: (workgroups per replica, slab in global memory)
+  std::vector<std::pair<int, bool>> cand;
+  for (int nw = 1; nw <= max_nw; nw *= 2) {
+    if (nw < 2) continue;
+    if (als_coop_lds_bytes(Q, R, nw, h->acc_f64, false) <= cap) cand.push_back({nw, false});
+    if (als_coop_lds_bytes(Q, R, nw, h->acc_f64, true) <= cap) cand.push_back({nw, true});
+  }
+  if (max_nw > 1 && (max_nw & (max_nw - 1))) {
+    if (als_coop_lds_bytes(Q, R, max_nw, h->acc_f64, false) <= cap) cand.push_back({max_nw, false});
+    if (als_coop_lds_bytes(Q, R, max_nw, h->acc_f64, true) <= cap) cand.push_back({max_nw, true});
+  }
+  if (cand.empty()) return fail(h, OCTEN_ERR_UNSUPPORTED, "no cooperative configuration fits");
+  // slots for the largest candidate; the current factors are kept aside
+  int nw_big = 0;
+  for (auto& c : cand) nw_big = c.first > nw_big ? c.first : nw_big;
+  double* slots = nullptr;
+  OKCHK(dalloc(h, &slots, (size_t)2 * P * nw_big * als_coop_slot_len(Q, R)));
+  double *F0 = nullptr, *lam0 = nullptr;
+  OKCHK(dalloc(h, &F0, (size_t)P * 3 * Q * R));
+  OKCHK(dalloc(h, &lam0, (size_t)P * R));
+  HIPCHK(h, hipMemcpyAsync(F0, h->F, (size_t)P * 3 * Q * R * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(lam0, h->lam, (size_t)P * R * 8, hipMemcpyDeviceToDevice, s));
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_i = -1;
+  octen_status st = OCTEN_OK;
+  for (size_t q = 0; q < cand.size(); ++q) {
+    hipError_t e = als_coop(s, h->Y, h->acc_f64, P, Q, R, cand[q].first, cand[q].second, F0, h->F,
+                            h->lam, h->iters, h->flags, slots, h->als_ctr, h->als_err, 1, 0.0);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e == hipSuccess)
+      e = als_coop(s, h->Y, h->acc_f64, P, Q, R, cand[q].first, cand[q].second, F0, h->F, h->lam,
+                   h->iters, h->flags, slots, h->als_ctr, h->als_err, sweeps, 0.0);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    int err = 0;
+    if (e == hipSuccess) e = hipMemcpy(&err, h->als_err, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      continue;   // a configuration that cannot launch here is skipped
+    }
+    if (!err && ms < best) { best = ms; best_i = (int)q; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  HIPCHK(h, hipMemcpyAsync(h->F, F0, (size_t)P * 3 * Q * R * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->lam, lam0, (size_t)P * R * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  dfree(h, F0);
+  dfree(h, lam0);
+  if (best_i < 0) {
+    dfree(h, slots);
+    return fail(h, OCTEN_ERR_HIP, "no cooperative ALS configuration ran");
+  }
+  dfree(h, h->als_slots);
+  h->als_slots = slots;
+  h->als_nw = cand[best_i].first;
+  h->als_gx = cand[best_i].second;
+  if (choice_host) *choice_host = 10 * h->als_nw + (h->als_gx ? 1 : 0);
+  return st;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------- groups ---
