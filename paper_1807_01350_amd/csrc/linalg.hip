@@ -183,6 +183,52 @@ __global__ __launch_bounds__(1024) void spd_solve_kernel(double* __restrict__ Nm
   if (tid == 0 && bad && *info == 0) *info = bad;
 }
 
+// Small systems (n <= 96, nrhs <= 32): Gauss-Jordan elimination without
+// pivoting on [N | B] held in LDS, one workgroup; for symmetric positive
+// definite N every pivot is positive (an SPD Schur complement stays SPD).
+// Per pivot j: the multipliers N(i,j)/N(j,j) are taken, every row i != j
+// loses its multiple of row j, then row j is divided by its pivot.  The
+// right-hand columns end as N^{-1} B.  info = j + 1 for a pivot that is not
+// positive (the elimination continues with it skipped).
+constexpr int GJ_NMAX = 112, GJ_RMAX = 32;
+__global__ __launch_bounds__(256) void spd_solve_gj_kernel(const double* __restrict__ Nm, int n,
+                                                           double* __restrict__ Bm, int nrhs,
+                                                           int* info) {
+  extern __shared__ double gj_lds[];
+  __shared__ double f[GJ_NMAX];
+  __shared__ int bad;
+  const int tid = threadIdx.x, w = n + nrhs, ld = w + 1;
+  auto M = [&](int i, int c) -> double& { return gj_lds[i * ld + c]; };
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < n * w; e += 256) {
+    const int i = e / w, c = e % w;
+    M(i, c) = c < n ? Nm[(int64_t)i * n + c] : Bm[(int64_t)i * nrhs + (c - n)];
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double p = M(j, j);
+    const bool ok = p > 0.0;
+    if (tid == 0 && !ok && !bad) bad = j + 1;
+    for (int i = tid; i < n; i += 256) f[i] = (ok && i != j) ? M(i, j) / p : 0.0;
+    __syncthreads();
+    // rows i != j; columns right of j only (columns left of j are already
+    // zero below and above the diagonal, column j is not read again)
+    const int wc = w - j - 1;
+    for (int e = tid; e < n * wc; e += 256) {
+      const int i = e / wc, c = j + 1 + e % wc;
+      if (i != j) M(i, c) -= f[i] * M(j, c);
+    }
+    __syncthreads();
+    for (int c = j + 1 + tid; c < w; c += 256) M(j, c) = ok ? M(j, c) / p : M(j, c);
+    __syncthreads();
+  }
+  for (int e = tid; e < n * nrhs; e += 256) {
+    const int i = e / nrhs, c = e % nrhs;
+    Bm[(int64_t)i * nrhs + c] = M(i, n + c);
+  }
+  if (tid == 0 && bad && *info == 0) *info = bad;
+}
+
 __global__ void fill_f64_kernel(double* p, int64_t n, double v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -279,6 +325,14 @@ hipError_t spd_invert(hipStream_t s, double* A, int n, double* work, int* info) 
 hipError_t spd_solve_small(hipStream_t s, double* N, int n, double* Bm, int nrhs, double* work,
                            int* info) {
   if (n <= 0) return hipSuccess;
+  if (n <= GJ_NMAX && nrhs <= GJ_RMAX) {
+    const size_t lds = (size_t)n * (n + nrhs + 1) * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void*)spd_solve_gj_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(spd_solve_gj_kernel, dim3(1), dim3(256), lds, s, N, n, Bm, nrhs, info);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(spd_solve_kernel, dim3(1), dim3(1024), 0, s, N, n, Bm, nrhs, work, info);
   return hipGetLastError();
 }
@@ -324,8 +378,8 @@ hipError_t any_nonfinite(hipStream_t s, const void* x, int64_t n, bool f64, int*
 // ---------------------------------------------------------------------------
 // Products with a small output width: out(i, r) = alpha * sum_k A(i,k) d(k) B(k,r)
 // + beta * out(i, r) for r < ncols (<= any), one wavefront per (row i, block of
-// 32 columns); lanes split k, partial sums meet in a butterfly.  Operands are
-// strided: A(i,k) = A[i*sai + k*sak], B(k,r) = B[k*sbk + r*sbr].
+// 32 columns, range of k); lanes split k, partial sums meet in a butterfly.
+// Operands are strided: A(i,k) = A[i*sai + k*sak], B(k,r) = B[k*sbk + r*sbr].
 namespace octen {
 namespace {
 __global__ __launch_bounds__(256) void rowdot_kernel(int64_t nrows, int ncols, int64_t K,
@@ -334,19 +388,23 @@ __global__ __launch_bounds__(256) void rowdot_kernel(int64_t nrows, int ncols, i
                                                      int64_t sbk, int64_t sbr,
                                                      const double* __restrict__ d, double alpha,
                                                      double beta, double* __restrict__ out,
-                                                     int64_t ldo) {
+                                                     int64_t ldo, int nsplit, int64_t kchunk,
+                                                     double* __restrict__ part) {
   const int lane = threadIdx.x & 63;
   const int64_t wid = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   const int nblk = (ncols + 31) / 32;
-  if (wid >= nrows * nblk) return;
-  const int64_t i = wid / nblk;
-  const int r0 = (int)(wid % nblk) * 32;
+  if (wid >= nrows * nblk * nsplit) return;
+  const int sp = (int)(wid % nsplit);
+  const int64_t rest = wid / nsplit;
+  const int64_t i = rest / nblk;
+  const int r0 = (int)(rest % nblk) * 32;
   const int nr = ncols - r0 < 32 ? ncols - r0 : 32;
+  const int64_t k0 = sp * kchunk, k1 = k0 + kchunk < K ? k0 + kchunk : K;
   double acc[32];
 #pragma unroll
   for (int r = 0; r < 32; ++r) acc[r] = 0.0;
   const double* a = A + i * sai;
-  for (int64_t k = lane; k < K; k += 64) {
+  for (int64_t k = k0 + lane; k < k1; k += 64) {
     double av = a[k * sak];
     if (d) av *= d[k];
     const double* b = B + k * sbk + (int64_t)r0 * sbr;
@@ -363,22 +421,65 @@ __global__ __launch_bounds__(256) void rowdot_kernel(int64_t nrows, int ncols, i
     }
   }
   if (lane == 0) {
-    double* o = out + i * ldo + r0;
+    if (nsplit == 1) {
+      double* o = out + i * ldo + r0;
 #pragma unroll
-    for (int r = 0; r < 32; ++r)
-      if (r < nr) o[r] = beta != 0.0 ? alpha * acc[r] + beta * o[r] : alpha * acc[r];
+      for (int r = 0; r < 32; ++r)
+        if (r < nr) o[r] = beta != 0.0 ? alpha * acc[r] + beta * o[r] : alpha * acc[r];
+    } else {
+      double* o = part + ((int64_t)sp * nrows + i) * ncols + r0;
+#pragma unroll
+      for (int r = 0; r < 32; ++r)
+        if (r < nr) o[r] = acc[r];
+    }
   }
 }
+
+// out(i, r) = alpha * sum over the splits (in order) + beta * out(i, r)
+__global__ void rowdot_reduce_kernel(int64_t nrows, int ncols, int nsplit,
+                                     const double* __restrict__ part, double alpha, double beta,
+                                     double* __restrict__ out, int64_t ldo) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nrows * ncols) return;
+  const int64_t i = e / ncols;
+  const int r = (int)(e % ncols);
+  double sum = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) sum += part[(int64_t)sp * nrows * ncols + e];
+  double* o = out + i * ldo + r;
+  *o = beta != 0.0 ? alpha * sum + beta * *o : alpha * sum;
+}
+
 }  // namespace
 
 hipError_t rowdot(hipStream_t s, int64_t nrows, int ncols, int64_t K, const double* A, int64_t sai,
                   int64_t sak, const double* B, int64_t sbk, int64_t sbr, const double* d,
-                  double alpha, double beta, double* out, int64_t ldo) {
+                  double alpha, double beta, double* out, int64_t ldo, double* work,
+                  int64_t work_len) {
   if (nrows <= 0 || ncols <= 0) return hipSuccess;
-  const int64_t waves = nrows * ((ncols + 31) / 32);
-  const int64_t blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL(rowdot_kernel, dim3((unsigned)blocks), dim3(256), 0, s, nrows, ncols, K, A, sai,
-                     sak, B, sbk, sbr, d, alpha, beta, out, ldo);
+  const int nblk = (ncols + 31) / 32;
+  // split the long index when there are too few rows to fill the GPU; the
+  // partial sums are added in split order by a second kernel
+  int64_t nsplit = 1;
+  const int64_t waves = nrows * nblk;
+  if (work && waves < 2048 && K >= 512) {
+    nsplit = (2048 + waves - 1) / waves;
+    const int64_t maxs = K / 256;
+    if (nsplit > maxs) nsplit = maxs;
+    if (nsplit > 64) nsplit = 64;
+    while (nsplit > 1 && nsplit * nrows * ncols > work_len) --nsplit;
+    if (nsplit < 1) nsplit = 1;
+  }
+  int64_t kchunk = (K + nsplit - 1) / nsplit;
+  kchunk = (kchunk + 63) / 64 * 64;
+  const int64_t total = waves * nsplit;
+  const int64_t blocks = (total + 3) / 4;
+  hipLaunchKernelGGL(rowdot_kernel, dim3((unsigned)blocks), dim3(256), 0, s, nrows, ncols, K, A,
+                     sai, sak, B, sbk, sbr, d, alpha, beta, out, ldo, (int)nsplit, kchunk, work);
+  if (nsplit > 1) {
+    const int64_t n = nrows * ncols;
+    hipLaunchKernelGGL(rowdot_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       nrows, ncols, (int)nsplit, work, alpha, beta, out, ldo);
+  }
   return hipGetLastError();
 }
 }  // namespace octen

@@ -71,6 +71,8 @@ struct octen_ctx {
   double* partials = nullptr;
   double* fit_out = nullptr;
   double* gj_work = nullptr;
+  double* rd_work = nullptr;                     // partial sums of split products
+  static constexpr int64_t RD_WORK = 1 << 18;
   // sparse batches
   int* coo_work = nullptr;  int64_t coo_work_cap = 0;
   int* seg_start = nullptr; int64_t seg_start_cap = 0;
@@ -356,6 +358,7 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
   IOK(dalloc(h, &h->info, 1));
   IOK(dalloc(h, &h->partials, 2 * FIT_PARTS));
   IOK(dalloc(h, &h->fit_out, 3));
+  IOK(dalloc(h, &h->rd_work, (size_t)octen_ctx::RD_WORK));
   IOK(dalloc(h, &h->coo_small, 4));
   IOK(dalloc(h, &h->fitG, 3 * R * R));
   IOK(dalloc(h, &h->gj_work, 2 * (I > J ? (I > M1 ? I : M1) : (J > M1 ? J : M1))));
@@ -696,15 +699,16 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, i
   HIPCHK(h, rec_align(s, P, Q, R, S, h->F, h->lam, h->aligned, h->perm, h->margin));
   HIPCHK(h, rec_stack(s, P, Q, R, S, h->aligned, h->rhs));
   // Eq. 7 for modes 1 and 2
-  HIPCHK(h, rowdot(s, I, R, M1, h->OpA, M1, 1, h->rhs, R, 1, nullptr, 1.0, 0.0, h->Araw, R));
+  HIPCHK(h, rowdot(s, I, R, M1, h->OpA, M1, 1, h->rhs, R, 1, nullptr, 1.0, 0.0, h->Araw, R,
+                   h->rd_work, octen_ctx::RD_WORK));
   HIPCHK(h, rowdot(s, J, R, M1, h->OpB, M1, 1, h->rhs + (int64_t)M1 * R, R, 1, nullptr, 1.0, 0.0,
-                   h->Braw, R));
+                   h->Braw, R, h->rd_work, octen_ctx::RD_WORK));
   HIPCHK(h, rec_canon(s, I, R, h->Araw, h->Ac, h->ka));
   HIPCHK(h, rec_canon(s, J, R, h->Braw, h->Bc, h->kb));
   if (h->have_prev) {
-    HIPCHK(h, rowdot(s, R, R, I, h->Ac, 1, R, h->Aprev, R, 1, nullptr, 1.0, 0.0, h->cross, R));
+    HIPCHK(h, rowdot(s, R, R, I, h->Ac, 1, R, h->Aprev, R, 1, nullptr, 1.0, 0.0, h->cross, R, h->rd_work, octen_ctx::RD_WORK));
     HIPCHK(h, rowdot(s, R, R, J, h->Bc, 1, R, h->Bprev, R, 1, nullptr, 1.0, 0.0, h->cross + R * R,
-                     R));
+                     R, h->rd_work, octen_ctx::RD_WORK));
     HIPCHK(h, rec_col_norms(s, I, R, h->Ac, h->norms));
     HIPCHK(h, rec_col_norms(s, I, R, h->Aprev, h->norms + R));
     HIPCHK(h, rec_col_norms(s, J, R, h->Bc, h->norms + 2 * R));
@@ -718,8 +722,8 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, i
   OKCHK(dgrow(h, &h->bt, &h->bt_cap, (t > M1 ? t : (int64_t)M1) * R));
   if (t <= M1) {
     OKCHK(dgrow(h, &h->Nt, &h->Nt_cap, t * t));
-    HIPCHK(h, rowdot(s, t, (int)t, M1, h->Wp, M1, 1, h->Wp, 1, M1, h->w2, 1.0, 0.0, h->Nt, t));
-    HIPCHK(h, rowdot(s, t, R, M1, h->Wp, M1, 1, h->rhs_c, R, 1, h->w2, 1.0, 0.0, h->bt, R));
+    HIPCHK(h, rowdot(s, t, (int)t, M1, h->Wp, M1, 1, h->Wp, 1, M1, h->w2, 1.0, 0.0, h->Nt, t, h->rd_work, octen_ctx::RD_WORK));
+    HIPCHK(h, rowdot(s, t, R, M1, h->Wp, M1, 1, h->rhs_c, R, 1, h->w2, 1.0, 0.0, h->bt, R, h->rd_work, octen_ctx::RD_WORK));
     HIPCHK(h, spd_solve_small(s, h->Nt, (int)t, h->bt, R, h->gj_work, h->info));
   } else {
     OKCHK(dgrow(h, &h->Nt, &h->Nt_cap, (int64_t)M1 * M1 + (int64_t)M1 * R));
@@ -751,7 +755,7 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, i
                                 h->Ctmp, h->have_prev ? 1 : 0));
   // H = Hcur + W^T C_new (canonical convention)
   HIPCHK(h, hipMemcpyAsync(h->H, h->Hcur, (size_t)M1 * R * 8, hipMemcpyDeviceToDevice, s));
-  HIPCHK(h, rowdot(s, M1, R, t, h->Wp, 1, M1, h->bt, R, 1, nullptr, 1.0, 1.0, h->H, R));
+  HIPCHK(h, rowdot(s, M1, R, t, h->Wp, 1, M1, h->bt, R, 1, nullptr, 1.0, 1.0, h->H, R, h->rd_work, octen_ctx::RD_WORK));
   HIPCHK(h, hipMemcpyAsync(h->Aprev, h->Ac, I * R * 8, hipMemcpyDeviceToDevice, s));
   HIPCHK(h, hipMemcpyAsync(h->Bprev, h->Bc, J * R * 8, hipMemcpyDeviceToDevice, s));
   HIPCHK(h, hipMemcpyAsync(A, h->Ac, I * R * 8, hipMemcpyDeviceToDevice, s));

@@ -31,12 +31,16 @@ hipError_t spd_invert(hipStream_t s, double* A, int n, double* work, int* info);
 // out(i, r) = alpha * sum_k A(i,k) d(k) B(k,r) + beta * out(i, r), i < nrows,
 // r < ncols; A(i,k) = A[i*sai + k*sak], B(k,r) = B[k*sbk + r*sbr]; d may be
 // null.  One wavefront per row and block of 32 columns (small outputs, long k).
+// work (optional, work_len doubles): partial sums for splitting K when there
+// are few rows; without it, one wavefront covers all of K.
 hipError_t rowdot(hipStream_t s, int64_t nrows, int ncols, int64_t K, const double* A, int64_t sai,
                   int64_t sak, const double* B, int64_t sbk, int64_t sbr, const double* d,
-                  double alpha, double beta, double* out, int64_t ldo);
+                  double alpha, double beta, double* out, int64_t ldo, double* work = nullptr,
+                  int64_t work_len = 0);
 
-// One-workgroup Cholesky solve of N X = Bm (N: n x n, Bm: n x nrhs, both
-// row-major, overwritten: N by its factor, Bm by the solution); work: n doubles.
+// One-workgroup solve of N X = Bm for SPD N (N: n x n, Bm: n x nrhs, both
+// row-major; Bm is overwritten by the solution, N by its Cholesky factor for
+// n > 96 or nrhs > 32, else left as it was: Gauss-Jordan in LDS); work: n doubles.
 hipError_t spd_solve_small(hipStream_t s, double* N, int n, double* Bm, int nrhs, double* work,
                            int* info);
 
