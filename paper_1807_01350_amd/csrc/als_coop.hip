@@ -37,7 +37,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 512;            // eight wavefronts: two per SIMD
 constexpr int MAXR = 32;
 constexpr unsigned SPIN_LIMIT = 1u << 22;
 
@@ -90,47 +90,58 @@ __device__ bool replica_barrier(unsigned* ctr, unsigned target, int* err, int* s
   return *s_ok != 0;
 }
 
+// Value of x held by lane j (j uniform), through two scalar lane reads.
+__device__ __forceinline__ double lane_value(double x, int j) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), j);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), j);
+  return __hiloint2double(hi, lo);
+}
+
+// Orders the LDS accesses of one wavefront: what a lane wrote before is seen
+// by every lane after (LDS operations of a wavefront complete in order; this
+// keeps the compiler from moving memory operations across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Inverse of the SPD matrix G (R x R, LDS) by Gauss-Jordan elimination
-// without pivoting, run by one wavefront: lane i keeps row i of [G | I] in
-// registers and the pivot row is read from lane j.  Writes Ginv (LDS) and
-// sets *bad when a pivot is not positive.
+// without pivoting, run by one wavefront on [G | I] stored by columns: lane
+// c keeps column c (c < 2R <= 64) in registers.  At step j every lane needs
+// the pivot column, which lives in lane j and is read with scalar lane reads
+// (R values per step, no LDS traffic, no cross-lane permutes); the pivot row
+// entry of its own column is already in its registers.  Writes Ginv (LDS)
+// and sets *bad when a pivot is not positive.
 template <int RMAX>
 __device__ void spd_inverse_wave(const double* G, double* Ginv, int R, int* bad) {
   const int lane = threadIdx.x & 63;
-  double g[RMAX], v[RMAX];
+  double a[RMAX];
 #pragma unroll
-  for (int k = 0; k < RMAX; ++k) {
-    g[k] = (lane < R && k < R) ? G[lane * R + k] : 0.0;
-    v[k] = (lane == k) ? 1.0 : 0.0;
+  for (int i = 0; i < RMAX; ++i) {
+    double v = 0.0;
+    if (i < R) {
+      if (lane < R) v = G[i * R + lane];
+      else if (lane == R + i) v = 1.0;
+    }
+    a[i] = v;
   }
   int badl = 0;
 #pragma unroll
   for (int j = 0; j < RMAX; ++j) {
     if (j < R) {
-      double piv = __shfl(g[j], j, 64);
+      double piv = lane_value(a[j], j);
       if (!(piv > 0.0)) { badl = 1; piv = 1e-300; }
-      const double ip = 1.0 / piv;
-      const double f = g[j];
+      const double rj = a[j] * (1.0 / piv);
 #pragma unroll
-      for (int k = 0; k < RMAX; ++k) {
-        if (k < R) {
-          const double gj = __shfl(g[k], j, 64) * ip;
-          const double vj = __shfl(v[k], j, 64) * ip;
-          if (lane == j) {
-            g[k] = gj;
-            v[k] = vj;
-          } else {
-            g[k] = fma(-f, gj, g[k]);
-            v[k] = fma(-f, vj, v[k]);
-          }
-        }
-      }
+      for (int i = 0; i < RMAX; ++i)
+        if (i != j && i < R) a[i] = fma(-lane_value(a[i], j), rj, a[i]);
+      a[j] = rj;
     }
   }
-  if (lane < R) {
+  if (lane >= R && lane < 2 * R) {
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k)
-      if (k < R) Ginv[lane * R + k] = v[k];
+    for (int i = 0; i < RMAX; ++i)
+      if (i < R) Ginv[i * R + (lane - R)] = a[i];
   }
   if (lane == 0 && badl) *bad = 1;
 }
@@ -193,15 +204,15 @@ __device__ void col_norms(const double* Fm, int n, int R, double* lam) {
 }
 
 // Sum over the NW slab partials of element e, slab order; loads are issued
-// eight at a time before they are added, so that they are in flight together.
+// sixteen at a time before they are added, so that they are in flight together.
 __device__ __forceinline__ double sum_slots(const double* base, int64_t stride, int NW) {
   double s = 0.0;
-  for (int w0 = 0; w0 < NW; w0 += 8) {
-    double v[8];
+  for (int w0 = 0; w0 < NW; w0 += 16) {
+    double v[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = w0 + u < NW ? base[(w0 + u) * stride] : 0.0;
+    for (int u = 0; u < 16; ++u) v[u] = w0 + u < NW ? base[(w0 + u) * stride] : 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < 16; ++u)
       if (w0 + u < NW) s += v[u];
   }
   return s;
@@ -367,30 +378,38 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       else if (e < QR) Mf[e] = s;
       else AtA[e - QR] = s;
     }
+    // sums of the partials: wavefront 0 takes A'A and goes on to lambda_A
+    // (norms from diag(A'A)), the normalised A'A, G2 and its inverse, while
+    // the other wavefronts sum M2
     if (NW > 1) {
       alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok);
       if (!alive) break;
-      for (int e = tid; e < QR + RR; e += NT) {
-        const double s = sum_slots(slot(set1, 0) + e, slot_len, NW);
-        if (e < QR) Mf[e] = s; else AtA[e - QR] = s;
+      if (wave == 0) {
+        for (int e = lane; e < RR; e += 64) AtA[e] = sum_slots(slot(set1, 0) + QR + e, slot_len, NW);
+      } else {
+        for (int e = tid - 64; e < QR; e += NT - 64) Mf[e] = sum_slots(slot(set1, 0) + e, slot_len, NW);
       }
+    } else {
+      __syncthreads();
     }
-    __syncthreads();
-    // normalise A: lambda_A = sqrt(diag(A'A))
-    if (tid < R) {
-      const double n = sqrt(AtA[tid * R + tid]);
-      lamv[tid] = n > 0.0 ? n : 1.0;
+    if (wave == 0) {
+      wave_sync();
+      if (lane < R) {
+        const double n = sqrt(AtA[lane * R + lane]);
+        lamv[lane] = n > 0.0 ? n : 1.0;
+      }
+      wave_sync();
+      for (int e = lane; e < RR; e += 64) {
+        AtA[e] /= lamv[e / R] * lamv[e % R];
+        G[e] = AtA[e] * CtC[e];
+      }
+      wave_sync();
+      // ---------------------------------------------- mode 2 solve (B)
+      spd_inverse_wave<RMAX>(G, Gi, R, &s_bad);
     }
     __syncthreads();
     for (int e = tid; e < na * R; e += NT) Al[e] /= lamv[e % R];
     for (int e = tid; e < QR; e += NT) Mf[e] /= lamv[e % R];
-    for (int e = tid; e < RR; e += NT) {
-      AtA[e] /= lamv[e / R] * lamv[e % R];
-      G[e] = AtA[e] * CtC[e];
-    }
-    __syncthreads();
-    // ------------------------------------------------ mode 2 solve (B)
-    if (wave == 0) spd_inverse_wave<RMAX>(G, Gi, R, &s_bad);
     __syncthreads();
     apply_inverse(Mf, Gi, Bf, Q, R);
     __syncthreads();
@@ -411,31 +430,59 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     {
       const int set2 = (nbar + 1) & 1;
       double* dst = NW > 1 ? slot(set2, w) : Mf;
+      // M3(c, r) = sum_pair X(pair, c) W(pair, r): tiles over c x r; when the
+      // tiles are fewer than half the MFMA wavefronts, the pair range is cut
+      // in two and the second halves are added through LDS (fixed order)
+      const int ctiles = (Q + 15) / 16, ntl = ctiles * RT;
+      constexpr int NMW = NT / 64 - 1;
+      const int ksp = 2 * ntl <= NMW ? 2 : 1;
+      const int kh = ksp == 1 ? npair : ((npair + 15) / 16) * 8;
+      f64x4 keep = {0.0, 0.0, 0.0, 0.0};
+      int keep_tile = -1;
       if (wave == 0) {
         spd_inverse_wave<RMAX>(G, Gi, R, &s_bad);
       } else {
-        // M3(c, r) = sum_pair X(pair, c) W(pair, r): tiles over c x r
-        const int ctiles = (Q + 15) / 16;
-        for (int tt = wave - 1; tt < ctiles * RT; tt += NT / 64 - 1) {
+        for (int item = wave - 1; item < ntl * ksp; item += NMW) {
+          const int tt = item % ntl, part = item / ntl;
+          const int kb = part * kh, ke = kb + kh < npair ? kb + kh : npair;
           const int ct = tt / RT, rt = tt % RT;
           const int c = ct * 16 + lane % 16;
           const int rr = rt * 16 + lane % 16;
           f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
           const bool okc = c < Q, okr = rr < R;
 #pragma unroll 4
-          for (int k0 = 0; k0 < npair; k0 += 8) {
+          for (int k0 = kb; k0 < ke; k0 += 8) {
             const int pr = k0 + lane / 16, pr2 = pr + 4;
-            const double a0 = (okc && pr < npair) ? (double)Xs[pr * QP + c] : 0.0;
-            const double b0 = (okr && pr < npair) ? Ts[pr * R + rr] : 0.0;
-            const double a1 = (okc && pr2 < npair) ? (double)Xs[pr2 * QP + c] : 0.0;
-            const double b1 = (okr && pr2 < npair) ? Ts[pr2 * R + rr] : 0.0;
+            const double a0 = (okc && pr < ke) ? (double)Xs[pr * QP + c] : 0.0;
+            const double b0 = (okr && pr < ke) ? Ts[pr * R + rr] : 0.0;
+            const double a1 = (okc && pr2 < ke) ? (double)Xs[pr2 * QP + c] : 0.0;
+            const double b1 = (okr && pr2 < ke) ? Ts[pr2 * R + rr] : 0.0;
             acc0 = mfma64(a0, b0, acc0);
             acc1 = mfma64(a1, b1, acc1);
           }
+          const f64x4 acc = acc0 + acc1;
+          if (ksp == 2 && part == 0) {
+            keep = acc;
+            keep_tile = tt;
+            continue;
+          }
+          double* o = ksp == 2 ? Ml : dst;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int row = ct * 16 + lane / 16 + 4 * i;
-            if (row < Q && okr) dst[row * R + rr] = acc0[i] + acc1[i];
+            if (row < Q && okr) o[row * R + rr] = acc[i];
+          }
+        }
+      }
+      if (ksp == 2) {
+        __syncthreads();
+        if (keep_tile >= 0) {
+          const int ct = keep_tile / RT, rt = keep_tile % RT;
+          const int rr = rt * 16 + lane % 16;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = ct * 16 + lane / 16 + 4 * i;
+            if (row < Q && rr < R) dst[row * R + rr] = keep[i] + Ml[row * R + rr];
           }
         }
       }
@@ -457,23 +504,25 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     __syncthreads();
     ++done;
     if (g.tol > 0.0) {
-      if (tid == 0) {
-        double inner = 0.0;
-        for (int r = 0; r < R; ++r) {
-          double d = 0.0;
-          for (int q = 0; q < Q; ++q) d = fma(Mf[q * R + r], Cf[q * R + r], d);
-          inner += lamv[r] * d;
+      // replica fit from the Gram identity, summed by wavefront 0 in a fixed
+      // order (every workgroup of the replica reaches the same decision)
+      if (wave == 0) {
+        double inner = 0.0, nh = 0.0;
+        for (int e = lane; e < QR; e += 64) inner = fma(Mf[e] * lamv[e % R], Cf[e], inner);
+        for (int e = lane; e < RR; e += 64)
+          nh += lamv[e / R] * (AtA[e] * BtB[e] * CtC[e]) * lamv[e % R];
+        for (int off = 32; off > 0; off >>= 1) {
+          inner += __shfl_xor(inner, off, 64);
+          nh += __shfl_xor(nh, off, 64);
         }
-        double nh = 0.0;
-        for (int r1 = 0; r1 < R; ++r1)
-          for (int r2 = 0; r2 < R; ++r2)
-            nh += lamv[r1] * (AtA[r1 * R + r2] * BtB[r1 * R + r2] * CtC[r1 * R + r2]) * lamv[r2];
-        double res = s_nx2 - 2.0 * inner + nh;
-        if (res < 0.0) res = 0.0;
-        const double fit = s_nx2 > 0.0 ? 1.0 - sqrt(res) / sqrt(s_nx2) : 0.0;
-        s_stop = (s_have_old && fabs(fit - s_fit_old) < g.tol) ? 1 : 0;
-        s_fit_old = fit;
-        s_have_old = 1;
+        if (lane == 0) {
+          double res = s_nx2 - 2.0 * inner + nh;
+          if (res < 0.0) res = 0.0;
+          const double fit = s_nx2 > 0.0 ? 1.0 - sqrt(res) / sqrt(s_nx2) : 0.0;
+          s_stop = (s_have_old && fabs(fit - s_fit_old) < g.tol) ? 1 : 0;
+          s_fit_old = fit;
+          s_have_old = 1;
+        }
       }
       __syncthreads();
       if (s_stop) break;

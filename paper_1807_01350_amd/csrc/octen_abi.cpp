@@ -254,6 +254,15 @@ int host_info(octen_t h) {
 
 }  // namespace
 
+// Smallest workgroup count with the same slab height ceil(Q / nw) as nw: the
+// slowest workgroup of a replica sets the pace, so extra workgroups that do
+// not lower the tallest slab only add barrier participants.
+static int balanced_nw(int Q, int nw) {
+  if (nw < 1) return 1;
+  const int na = (Q + nw - 1) / nw;
+  return (Q + na - 1) / na;
+}
+
 extern "C" {
 
 int32_t octen_abi_version(void) { return OCTEN_ABI_VERSION; }
@@ -408,6 +417,7 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
         nw = max_nw;
         gx = true;
       }
+      nw = balanced_nw((int)Q, nw);   // same slab height, so the same LDS size
       if (als_coop_lds_bytes((int)Q, (int)R, nw, h->acc_f64, gx) <= lds_cap) {
         h->als_nw = nw;
         h->als_gx = gx;
@@ -1016,14 +1026,11 @@ octen_status octen_autotune_als(octen_t h, int32_t sweeps, int32_t* choice_host)
   const size_t cap = 160 * 1024;
   // candidates: (workgroups per replica, slab in global memory)
   std::vector<std::pair<int, bool>> cand;
-  for (int nw = 1; nw <= max_nw; nw *= 2) {
-    if (nw < 2) continue;
+  // every count that is the smallest one for its slab height ceil(Q / nw)
+  for (int nw = 2; nw <= max_nw; ++nw) {
+    if (balanced_nw(Q, nw) != nw) continue;
     if (als_coop_lds_bytes(Q, R, nw, h->acc_f64, false) <= cap) cand.push_back({nw, false});
     if (als_coop_lds_bytes(Q, R, nw, h->acc_f64, true) <= cap) cand.push_back({nw, true});
-  }
-  if (max_nw > 1 && (max_nw & (max_nw - 1))) {
-    if (als_coop_lds_bytes(Q, R, max_nw, h->acc_f64, false) <= cap) cand.push_back({max_nw, false});
-    if (als_coop_lds_bytes(Q, R, max_nw, h->acc_f64, true) <= cap) cand.push_back({max_nw, true});
   }
   if (cand.empty()) return fail(h, OCTEN_ERR_UNSUPPORTED, "no cooperative configuration fits");
   // slots for the largest candidate; the current factors are kept aside
