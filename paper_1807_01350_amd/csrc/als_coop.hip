@@ -154,15 +154,15 @@ __device__ void gram_wave(const double* Fm, int n, int R, double* G) {
     for (int tj = 0; tj < ntile; ++tj) {
       f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
       const int r1 = ti * 16 + lane % 16, r2 = tj * 16 + lane % 16;
+      const double* f1 = Fm + (r1 < R ? r1 : R - 1);
+      const double* f2 = Fm + (r2 < R ? r2 : R - 1);
 #pragma unroll 4
       for (int k0 = 0; k0 < n; k0 += 8) {
         const int q = k0 + lane / 16, q2 = q + 4;
-        const double a0 = (q < n && r1 < R) ? Fm[q * R + r1] : 0.0;
-        const double b0 = (q < n && r2 < R) ? Fm[q * R + r2] : 0.0;
-        const double a1 = (q2 < n && r1 < R) ? Fm[q2 * R + r1] : 0.0;
-        const double b1 = (q2 < n && r2 < R) ? Fm[q2 * R + r2] : 0.0;
-        acc0 = mfma64(a0, b0, acc0);
-        acc1 = mfma64(a1, b1, acc1);
+        const int qc = q < n ? q : n - 1, qc2 = q2 < n ? q2 : n - 1;
+        const double a0 = f1[qc * R], b0 = f2[qc * R], a1 = f1[qc2 * R], b1 = f2[qc2 * R];
+        acc0 = mfma64(q < n ? a0 : 0.0, b0, acc0);
+        acc1 = mfma64(q2 < n ? a1 : 0.0, b1, acc1);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -327,16 +327,19 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
         const int pr = pt * 16 + lane % 16;
         const int rr = rt * 16 + lane % 16;
         f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-        const bool okr = pr < npair, okc = rr < R;
+        const bool okc = rr < R;
+        // indices clamped into range and the k tail zeroed after the load:
+        // no branches around the loads, so unrolled iterations overlap them
+        const T* xr = Xs + (pr < npair ? pr : npair - 1) * QP;
+        const double* cr = Cf + (okc ? rr : R - 1);
 #pragma unroll 4
         for (int c0 = 0; c0 < Q; c0 += 8) {
           const int c = c0 + lane / 16, c2 = c + 4;
-          const double a0 = (okr && c < Q) ? (double)Xs[pr * QP + c] : 0.0;
-          const double b0 = (okc && c < Q) ? Cf[c * R + rr] : 0.0;
-          const double a1 = (okr && c2 < Q) ? (double)Xs[pr * QP + c2] : 0.0;
-          const double b1 = (okc && c2 < Q) ? Cf[c2 * R + rr] : 0.0;
-          acc0 = mfma64(a0, b0, acc0);
-          acc1 = mfma64(a1, b1, acc1);
+          const int cc = c < Q ? c : Q - 1, cc2 = c2 < Q ? c2 : Q - 1;
+          const double x0 = (double)xr[cc], x1 = (double)xr[cc2];
+          const double b0 = cr[cc * R], b1 = cr[cc2 * R];
+          acc0 = mfma64(c < Q ? x0 : 0.0, b0, acc0);
+          acc1 = mfma64(c2 < Q ? x1 : 0.0, b1, acc1);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -449,16 +452,17 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
           const int c = ct * 16 + lane % 16;
           const int rr = rt * 16 + lane % 16;
           f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-          const bool okc = c < Q, okr = rr < R;
+          const bool okr = rr < R;
+          const T* xc = Xs + (c < Q ? c : Q - 1);
+          const double* wc = Ts + (okr ? rr : R - 1);
 #pragma unroll 4
           for (int k0 = kb; k0 < ke; k0 += 8) {
             const int pr = k0 + lane / 16, pr2 = pr + 4;
-            const double a0 = (okc && pr < ke) ? (double)Xs[pr * QP + c] : 0.0;
-            const double b0 = (okr && pr < ke) ? Ts[pr * R + rr] : 0.0;
-            const double a1 = (okc && pr2 < ke) ? (double)Xs[pr2 * QP + c] : 0.0;
-            const double b1 = (okr && pr2 < ke) ? Ts[pr2 * R + rr] : 0.0;
-            acc0 = mfma64(a0, b0, acc0);
-            acc1 = mfma64(a1, b1, acc1);
+            const int pc = pr < ke ? pr : ke - 1, pc2 = pr2 < ke ? pr2 : ke - 1;
+            const double x0 = (double)xc[pc * QP], x1 = (double)xc[pc2 * QP];
+            const double b0 = wc[pc * R], b1 = wc[pc2 * R];
+            acc0 = mfma64(pr < ke ? x0 : 0.0, b0, acc0);
+            acc1 = mfma64(pr2 < ke ? x1 : 0.0, b1, acc1);
           }
           const f64x4 acc = acc0 + acc1;
           if (ksp == 2 && part == 0) {
