@@ -306,7 +306,7 @@ typedef __attribute__((address_space(1))) void* gbl_vptr;
 // columns past J read clamped in-bounds addresses; they meet zero rows of the
 // U image or zero rows of the V image, so they add nothing.  Needs J % 4 == 0
 // and 16-byte aligned X.
-template <int KIND, int QT, int NSTAGE, bool SCALED>
+template <int KIND, int QT, int NSTAGE>
 __global__ __launch_bounds__(Tile<KIND>::NT) void compress_pipe(Args g) {
   constexpr int BM = Tile<KIND>::BM, NT = Tile<KIND>::NT;
   using T = typename Kind<KIND>::T;
@@ -390,61 +390,6 @@ __global__ __launch_bounds__(Tile<KIND>::NT) void compress_pipe(Args g) {
     const unsigned char* base = smem + (c % NSTAGE) * STAGE;
     const float* xs = (const float*)base;
     const T* b = (const T*)(base + XBYTES);
-    if constexpr (KIND == 2) {
-      // both k steps of the chunk (KC / KS == 2): all LDS reads first, then
-      // every A fragment converted, then the sixteen MFMAs back to back, so
-      // no conversion waits on an MFMA still reading a fragment register and
-      // the other wavefront of the SIMD can fill the gaps.  The scheduling
-      // barrier keeps that order.  Without a slice scale the f32 -> bf16
-      // conversion needs no multiply (the scale is a power of two and is
-      // divided out again at the end).
-      static_assert(KC / KS == 2, "two k steps per chunk");
-      f32x4 ra[2][2][2];
-      Frag bq[2][4];
-      auto read_a = [&](int ks) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int m = (wm * 2 + i) * 32 + lane % 32;
-          const float* xrow = xs + m * KC;
-          const int s0 = ks * 4 + 2 * (lane / 32);
-          ra[ks][i][0] = *(const f32x4*)(xrow + 4 * (s0 ^ (m % 8)));
-          ra[ks][i][1] = *(const f32x4*)(xrow + 4 * ((s0 + 1) ^ (m % 8)));
-        }
-      };
-      auto read_b = [&](int ks) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          bq[ks][j] = Kind<KIND>::ld(b + ((ks * (BN / 32) + wn * 4 + j) * 64 + lane) * E);
-      };
-      auto convert = [&](int ks, Frag (&af)[2]) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          bf16x8 f;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            f[e] = (__bf16)(SCALED ? ra[ks][i][0][e] * sc : ra[ks][i][0][e]);
-            f[4 + e] = (__bf16)(SCALED ? ra[ks][i][1][e] * sc : ra[ks][i][1][e]);
-          }
-          af[i] = f;
-        }
-      };
-      auto mfmas = [&](int ks, const Frag (&af)[2]) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = Kind<KIND>::mma(af[i], bq[ks][j], acc[i][j]);
-      };
-      Frag af0[2], af1[2];
-      read_a(0);
-      read_b(0);
-      read_a(1);
-      read_b(1);
-      convert(0, af0);
-      convert(1, af1);
-      __builtin_amdgcn_sched_barrier(0);
-      mfmas(0, af0);
-      mfmas(1, af1);
-    } else {
 #pragma unroll
     for (int ks = 0; ks < KC / KS; ++ks) {
       Frag af[2], bfr[4];
@@ -475,7 +420,6 @@ __global__ __launch_bounds__(Tile<KIND>::NT) void compress_pipe(Args g) {
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = Kind<KIND>::mma(af[i], bfr[j], acc[i][j]);
-    }
     }
   }
   __syncthreads();
@@ -617,7 +561,7 @@ hipError_t launch_fused(hipStream_t s, const Args& a, size_t lds) {
   return hipGetLastError();
 }
 
-template <int KIND, int QT, bool SCALED>
+template <int KIND, int QT>
 hipError_t launch_pipe(hipStream_t s, const Args& a) {
   constexpr int NS = 3;
   constexpr int BM = Tile<KIND>::BM;
@@ -626,7 +570,7 @@ hipError_t launch_pipe(hipStream_t s, const Args& a) {
   const size_t t2 = (size_t)(BN + 1) * (BM + 16 / sizeof(typename Kind<KIND>::T)) *
                     sizeof(typename Kind<KIND>::T);
   const size_t lds = NS * stage > t2 ? NS * stage : t2;
-  auto fn = compress_pipe<KIND, QT, NS, SCALED>;
+  auto fn = compress_pipe<KIND, QT, NS>;
   hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -638,10 +582,10 @@ hipError_t launch_pipe(hipStream_t s, const Args& a) {
 template <int KIND>
 hipError_t launch_pipe_q(hipStream_t s, const Args& a, int QT) {
   switch (QT) {
-    case 1: return a.scale ? launch_pipe<KIND, 1, true>(s, a) : launch_pipe<KIND, 1, false>(s, a);
-    case 2: return a.scale ? launch_pipe<KIND, 2, true>(s, a) : launch_pipe<KIND, 2, false>(s, a);
-    case 3: return a.scale ? launch_pipe<KIND, 3, true>(s, a) : launch_pipe<KIND, 3, false>(s, a);
-    case 4: return a.scale ? launch_pipe<KIND, 4, true>(s, a) : launch_pipe<KIND, 4, false>(s, a);
+    case 1: return launch_pipe<KIND, 1>(s, a);
+    case 2: return launch_pipe<KIND, 2>(s, a);
+    case 3: return launch_pipe<KIND, 3>(s, a);
+    case 4: return launch_pipe<KIND, 4>(s, a);
   }
   return hipErrorInvalidValue;
 }
