@@ -7,9 +7,11 @@
 //   seg_row[s] = its i, seg_slice[s] = its k,
 //   slice_seg[k] .. slice_seg[k+1] = the segments of slice k.
 // Then per slice k and replica p (one workgroup each):
-//   r_s(b) = sum_{n in s} v_n V_p(j_n, b)        one wavefront per segment,
-//                                                 lanes over b (gather)
-//   M_k^p  = sum_s U_p(i_s, :)^T r_s              32 segments per pass;
+//   r_s(b) = sum_{n in s} v_n V_p(j_n, b)        lanes over b (gather); a
+//                                                 segment of more than 32
+//                                                 nonzeros is cut into
+//                                                 chunks summed separately
+//   M_k^p  = sum_s U_p(i_s, :)^T r_s              32 rows per pass;
 //                                                 MFMA 32x32x2 for f32,
 //                                                 plain FMAs for f64
 // and the mode-3 product of the dense path produces Z_p.
@@ -211,36 +213,104 @@ __global__ __launch_bounds__(NT) void coo_compress_kernel(
     for (int q = 0; q < NOUT; ++q) accd[q] = 0.0;
   }
 
-  for (int c0 = s0; c0 < s1; c0 += SC) {
-    // gather: wavefront w builds rows w, w + 4, ... of this pass
-    for (int sg = wave; sg < SC; sg += 4) {
-      const int s = c0 + sg;
-      T r[NX], uu[NX];
+  // Passes over the slice's segments.  A pass is either up to SC consecutive
+  // segments of at most CH nonzeros (one row each), or one longer segment cut
+  // into SC chunks of its nonzeros (one row per chunk, each with the same U
+  // row): a few rows of a Zipf-skewed slice hold thousands of nonzeros and
+  // would otherwise serialise one wavefront.  Each wavefront walks its SPW
+  // rows together, one nonzero of each per step, so their loads overlap.
+  constexpr int CH = 32;
+  constexpr int SPW = SC / 4;
+  int c0 = s0;
+  while (c0 < s1) {
+    // segment starts c0 .. c0 + SC (lanes), their lengths and the long ones
+    const int sl = c0 + lane <= s1 ? c0 + lane : s1;
+    const int st = seg_start[sl];
+    const int st1 = __shfl_down(st, 1, 64);
+    const bool is_long = lane < SC && c0 + lane < s1 && st1 - st > CH;
+    const unsigned long long longm = __ballot(is_long);
+    const int n_first = __builtin_amdgcn_readfirstlane(st);
+    const bool long_pass = (longm & 1ull) != 0;
+    int ns = 1;
+    if (!long_pass) {
+      ns = longm ? __builtin_ctzll(longm) : SC;
+      if (ns > s1 - c0) ns = s1 - c0;
+      if (ns > SC) ns = SC;
+    }
+    const int n_last = long_pass ? __builtin_amdgcn_readlane(st, 1) : 0;
+    const int chunk = long_pass ? (n_last - n_first + SC - 1) / SC : 0;
+    const int64_t irow_long = long_pass ? (int64_t)seg_row[c0] * M1 : 0;
+
+    int nb[SPW], ne[SPW];
+    int64_t irow[SPW];
+    bool rowok[SPW];
+    int maxlen = 0;
 #pragma unroll
-      for (int x = 0; x < NX; ++x) { r[x] = T(0); uu[x] = T(0); }
-      if (s < s1) {
-        const int n0 = seg_start[s], n1 = seg_start[s + 1];
-        const int64_t irow = (int64_t)seg_row[s] * M1;
-#pragma unroll
-        for (int x = 0; x < NX; ++x)
-          if (okx[x]) uu[x] = Um[irow + colx[x]];
-#pragma unroll 4
-        for (int n = n0; n < n1; ++n) {
-          const T v = (T)vv[n];
-          const T* vrow = Vm + (int64_t)jj[n] * M1;
-#pragma unroll
-          for (int x = 0; x < NX; ++x)
-            if (okx[x]) r[x] = fma(v, vrow[colx[x]], r[x]);
-        }
+    for (int q = 0; q < SPW; ++q) {
+      const int r = wave + 4 * q;
+      if (long_pass) {
+        nb[q] = n_first + r * chunk;
+        ne[q] = nb[q] + chunk < n_last ? nb[q] + chunk : n_last;
+        if (ne[q] < nb[q]) ne[q] = nb[q];
+        irow[q] = irow_long;
+        rowok[q] = true;
+      } else {
+        rowok[q] = r < ns;
+        nb[q] = __builtin_amdgcn_readlane(st, r);
+        ne[q] = rowok[q] ? __builtin_amdgcn_readlane(st, r + 1) : nb[q];
+        irow[q] = rowok[q] ? (int64_t)seg_row[c0 + r] * M1 : 0;
       }
+      maxlen = ne[q] - nb[q] > maxlen ? ne[q] - nb[q] : maxlen;
+    }
+    T r[SPW][NX], uu[SPW][NX];
+#pragma unroll
+    for (int q = 0; q < SPW; ++q)
+#pragma unroll
+      for (int x = 0; x < NX; ++x) {
+        r[q][x] = T(0);
+        uu[q][x] = (okx[x] && rowok[q]) ? Um[irow[q] + colx[x]] : T(0);
+      }
+    // the value and row index of step m + 1 are loaded while the rows of
+    // step m are in flight (scalar loads, a separate counter)
+    T vn[SPW];
+    const T* rn[SPW];
+    auto load_idx = [&](int m) {
+#pragma unroll
+      for (int q = 0; q < SPW; ++q) {
+        const int n = nb[q] + m;
+        const bool ok = n < ne[q];
+        const int nn = ok ? n : n_first;   // a valid index; its value is not used
+        vn[q] = ok ? (T)vv[nn] : T(0);
+        rn[q] = Vm + (int64_t)jj[nn] * M1;
+      }
+    };
+    if (maxlen > 0) load_idx(0);
+    for (int m = 0; m < maxlen; ++m) {
+      T v[SPW], val[SPW][NX];
+#pragma unroll
+      for (int q = 0; q < SPW; ++q) {
+        v[q] = vn[q];
+#pragma unroll
+        for (int x = 0; x < NX; ++x) val[q][x] = okx[x] ? rn[q][colx[x]] : T(0);
+      }
+      if (m + 1 < maxlen) load_idx(m + 1);
+#pragma unroll
+      for (int q = 0; q < SPW; ++q)
+#pragma unroll
+        for (int x = 0; x < NX; ++x) r[q][x] = fma(v[q], val[q][x], r[q][x]);
+    }
+#pragma unroll
+    for (int q = 0; q < SPW; ++q) {
+      const int sg = wave + 4 * q;
 #pragma unroll
       for (int x = 0; x < NX; ++x) {
         if (okx[x]) {
-          Ub[sg][lane + 64 * x] = uu[x];
-          Rb[sg][lane + 64 * x] = r[x];
+          Ub[sg][lane + 64 * x] = uu[q][x];
+          Rb[sg][lane + 64 * x] = r[q][x];
         }
       }
     }
+    c0 += long_pass ? 1 : ns;
     __syncthreads();
     if constexpr (sizeof(T) == 4) {
 #pragma unroll
