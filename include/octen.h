@@ -226,13 +226,24 @@ int32_t octen_abi_version(void);
 /* ---- Tuning and batched steps (not in the paper).
  *
  * octen_autotune: times the compression kernel variants on the batch X
- * ([t][I][J] f32, as octen_compress_batch) -- pipelined direct-to-LDS loads,
- * register-staged 16-byte loads, register-staged scalar loads -- for the
- * default and for half the replicas per column block, and keeps the fastest
- * for this handle.  choice_host: NULL or 10 * replicas_per_block + variant.
+ * ([t][I][J] f32, as octen_compress_batch) -- 0 pipelined direct-to-LDS
+ * loads, 1 register-staged 16-byte loads, 2 register-staged scalar loads,
+ * 3 (BF16 only) half chunks with the next chunk's fragments read during the
+ * current chunk's MFMAs -- for the default and for half the replicas per
+ * column block, and keeps the fastest for this handle.  choice_host: NULL or
+ * 10 * replicas_per_block + variant.
  * Only handles with F32 or BF16 compression are tuned (else
  * OCTEN_ERR_UNSUPPORTED).  Synchronises. */
 octen_status octen_autotune(octen_t h, const void* X, int64_t t, int32_t* choice_host);
+
+/* octen_compress_variant: selects one of the compression kernel variants
+ * above (0..3) for this handle without timing (for callers that know their
+ * shapes, and for checking the variants against each other).  A variant
+ * that needs 16-byte rows falls back to 2 on a batch with J % 4 != 0 or an
+ * unaligned X.  OCTEN_ERR_ARG for a variant outside [0, 3];
+ * OCTEN_ERR_UNSUPPORTED for a handle without F32 or BF16 compression, or
+ * variant 3 on a handle without BF16 compression. */
+octen_status octen_compress_variant(octen_t h, int32_t variant);
 
 /* Times the cooperative ALS for `sweeps` sweeps on the current summaries with
  * each workgroups-per-replica count (powers of two and the largest that is

@@ -493,6 +493,235 @@ __global__ __launch_bounds__(Tile<KIND>::NT) void compress_pipe(Args g) {
   }
 }
 
+// BF16 only: the tile and output of compress_pipe with half-size chunks (16
+// columns of X, one MFMA k step) in NS2 = 6 LDS stages, and the fragments of
+// chunk c + 1 read into registers while the MFMAs of chunk c run.  With one
+// barrier per chunk and the reads issued right after it, the wavefronts of a
+// workgroup otherwise move between all-LDS and all-MFMA phases in lockstep;
+// here each wavefront overlaps its own LDS reads with its matrix work.  Global
+// loads are issued NS2 - 2 chunks ahead of their first use.  X rows are 64
+// bytes per stage, their four 16-byte slots XOR-swizzled by ((m >> 1) ^
+// (m >> 2)) & 3, which keeps the A-fragment reads free of bank conflicts for
+// both 8 and 16 lanes per LDS cycle.  The V image is the one of the other
+// kernels: a 32-column chunk holds two k steps, i.e. two half chunks.
+constexpr int NS2 = 6;
+constexpr int KC2 = 16;
+
+__device__ __forceinline__ int swz4(int m) { return ((m >> 1) ^ (m >> 2)) & 3; }
+
+template <int QT, bool SCALED>
+__global__ __launch_bounds__(Tile<2>::NT) void compress_pipe2(Args g) {
+  constexpr int BM = Tile<2>::BM, NT = Tile<2>::NT;
+  using T = __bf16;
+  using Frag = bf16x8;
+  constexpr int E = 8;
+  constexpr int XBYTES = BM * KC2 * 4;                 // 16 KB of raw f32 X
+  constexpr int VBYTES = (BN / 32) * 64 * E * 2;       // 8 KB: one k step of the V image
+  constexpr int STAGE = XBYTES + VBYTES;
+  constexpr int XL = XBYTES / (NT * 16);               // X loads per thread per chunk
+  constexpr int VL = VBYTES / (NT * 16);               // V loads per thread per chunk
+  constexpr int LPC = XL + VL;
+  constexpr int T2LD = BM + 16 / (int)sizeof(T);
+  static_assert(XL * NT * 16 == XBYTES && VL * NT * 16 == VBYTES, "whole 16-byte loads");
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* T2t = (T*)smem;
+
+  const int per = (g.tiles + 7) / 8;
+  const int u = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (u >= g.tiles) return;
+  const int cb = u % g.ncb;
+  const int rb = (u / g.ncb) % g.nrb;
+  const int k = u / (g.ncb * g.nrb);
+
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const float sc = SCALED ? g.scale[k] : 1.0f;
+  const int64_t row0 = (int64_t)rb * BM;
+  const float* Xk = g.X + (int64_t)k * g.I * g.J;
+  const unsigned char* Vc = (const unsigned char*)g.Vpack + (int64_t)cb * g.nchunk * 2 * VBYTES;
+  const int n2 = 2 * g.nchunk;
+
+  // per-thread X source rows (clamped) and swizzled 16-byte segments
+  const float* xsrc[XL];
+  int xseg[XL];
+#pragma unroll
+  for (int q = 0; q < XL; ++q) {
+    const int r = (wave * XL + q) * 16 + lane / 4;
+    int64_t gr = row0 + r;
+    if (gr > g.I - 1) gr = g.I - 1;
+    xsrc[q] = Xk + gr * g.J;
+    xseg[q] = (lane % 4) ^ swz4(r);
+  }
+
+  auto issue = [&](int c) {
+    unsigned char* base = smem + (c % NS2) * STAGE;
+#pragma unroll
+    for (int q = 0; q < XL; ++q) {
+      int64_t j = (int64_t)c * KC2 + xseg[q] * 4;
+      if (j > g.J - 4) j = g.J - 4;
+      __builtin_amdgcn_global_load_lds((gbl_vptr)(xsrc[q] + j),
+                                       (lds_vptr)(base + (wave * XL + q) * 1024), 16, 0, 0);
+    }
+    const unsigned char* vs = Vc + (int64_t)c * VBYTES;
+#pragma unroll
+    for (int q = 0; q < VL; ++q)
+      __builtin_amdgcn_global_load_lds((gbl_vptr)(vs + (q * NT + tid) * 16),
+                                       (lds_vptr)(base + XBYTES + (q * NT + wave * 64) * 16), 16, 0,
+                                       0);
+  };
+  // waits until at most `ahead` chunks of this thread's loads are outstanding
+  auto wait_ahead = [&](int ahead) {
+    if (ahead >= 3) __builtin_amdgcn_s_waitcnt(vmcnt_imm(3 * LPC));
+    else if (ahead == 2) __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * LPC));
+    else if (ahead == 1) __builtin_amdgcn_s_waitcnt(vmcnt_imm(LPC));
+    else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+  };
+
+  struct Frags {
+    f32x4 a[2][2];
+    Frag b[4];
+  };
+  auto read_frags = [&](int c, Frags& f) {
+    const unsigned char* base = smem + (c % NS2) * STAGE;
+    const float* xs = (const float*)base;
+    const T* bimg = (const T*)(base + XBYTES);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int m = (wm * 2 + i) * 32 + lane % 32;
+      const float* xrow = xs + m * KC2;
+      const int s0 = 2 * (lane / 32);
+      f.a[i][0] = *(const f32x4*)(xrow + 4 * (s0 ^ swz4(m)));
+      f.a[i][1] = *(const f32x4*)(xrow + 4 * ((s0 + 1) ^ swz4(m)));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) f.b[j] = *(const Frag*)(bimg + ((wn * 4 + j) * 64 + lane) * E);
+  };
+
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  auto mfmas = [&](const Frags& f) {
+    Frag af[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      bf16x8 v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        v[e] = (__bf16)(SCALED ? f.a[i][0][e] * sc : f.a[i][0][e]);
+        v[4 + e] = (__bf16)(SCALED ? f.a[i][1][e] * sc : f.a[i][1][e]);
+      }
+      af[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], f.b[j], acc[i][j], 0, 0, 0);
+  };
+
+  // prologue: chunks 0 .. NS2 - 1 in flight; chunks 0 and 1 landed
+  const int pro = n2 < NS2 ? n2 : NS2;
+  for (int c = 0; c < pro; ++c) issue(c);
+  wait_ahead(pro - 2 > 0 ? (pro - 2 > 3 ? 3 : pro - 2) : 0);
+  if (pro - 2 > 3) __builtin_amdgcn_s_waitcnt(vmcnt_imm(4 * LPC));
+  __builtin_amdgcn_s_barrier();
+
+  // one chunk: read the next chunk's fragments, run this chunk's MFMAs, wait
+  // for chunk c + 2, barrier, refill the stage of chunk c with chunk c + NS2
+  auto step = [&](int c, Frags& cur, Frags& nxt) {
+    if (c + 1 < n2) read_frags(c + 1, nxt);
+    mfmas(cur);
+    const int last = (c + NS2 - 1 < n2 - 1 ? c + NS2 - 1 : n2 - 1);   // last chunk issued
+    const int ahead = last - (c + 2);
+    wait_ahead(ahead < 0 ? 0 : (ahead > 3 ? 3 : ahead));
+    __builtin_amdgcn_s_barrier();
+    if (c + NS2 < n2) issue(c + NS2);
+  };
+  Frags f0, f1;
+  read_frags(0, f0);
+  int c = 0;
+  for (; c + 1 < n2; c += 2) {
+    step(c, f0, f1);
+    step(c + 1, f1, f0);
+  }
+  if (c < n2) step(c, f0, f1);
+  __syncthreads();
+
+  // ---- stage 2 (as in compress_pipe)
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = wn * 128 + j * 32 + lane % 32;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = wm * 64 + i * 32 + 8 * q + 4 * (lane / 32);
+        T* dst = T2t + col * T2LD + r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[e] = (T)acc[i][j][4 * q + e];
+      }
+    }
+  for (int e = tid; e < T2LD; e += NT) T2t[BN * T2LD + e] = (T)0.f;
+  __syncthreads();
+
+  const int p0 = cb * g.G;
+  const int gcount = (g.P - p0) < g.G ? (g.P - p0) : g.G;
+  const float inv = 1.0f / sc;
+  constexpr int KS = 16;
+  constexpr int QH = (QT + 1) / 2;
+  for (int item = wave; item < 2 * gcount; item += NT / 64) {
+    const int gg = item >> 1, ih = item & 1;
+    const int p = p0 + gg;
+    f32x16 m[QH][QT];
+#pragma unroll
+    for (int i = 0; i < QH; ++i)
+#pragma unroll
+      for (int j = 0; j < QT; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) m[i][j][e] = 0.f;
+    const T* Up = (const T*)g.Upack + ((int64_t)rb * g.P + p) * (BM / KS) * QT * 64 * E;
+    const int* tc = g.tilecol + ((int64_t)cb * g.G + gg) * QT * 32;
+    int colrow[QT];
+#pragma unroll
+    for (int j = 0; j < QT; ++j) colrow[j] = tc[j * 32 + lane % 32];
+    for (int ks = 0; ks < BM / KS; ++ks) {
+      Frag af[QH];
+#pragma unroll
+      for (int ii = 0; ii < QH; ++ii) {
+        const int i = ih * QH + ii < QT ? ih * QH + ii : QT - 1;
+        af[ii] = *(const Frag*)(Up + ((int64_t)(ks * QT + i) * 64 + lane) * E);
+      }
+#pragma unroll
+      for (int j = 0; j < QT; ++j) {
+        const Frag bf = *(const Frag*)(T2t + colrow[j] * T2LD + ks * KS + (lane / 32) * E);
+#pragma unroll
+        for (int ii = 0; ii < QH; ++ii)
+          m[ii][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ii], bf, m[ii][j], 0, 0, 0);
+      }
+    }
+    float* out = g.Mpart + (((int64_t)k * g.nrb + rb) * g.P + p) * g.Q * g.Q;
+#pragma unroll
+    for (int ii = 0; ii < QH; ++ii) {
+      const int i = ih * QH + ii;
+      if (i >= QT) continue;
+#pragma unroll
+      for (int j = 0; j < QT; ++j) {
+        const int bcol = j * 32 + lane % 32;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int arow = i * 32 + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+          if (arow < g.Q && bcol < g.Q) out[arow * g.Q + bcol] = m[ii][j][e] * inv;
+        }
+      }
+    }
+  }
+}
+
 // V image: [cb][chunk][ks][nt][lane][E]; element V[j][col] with
 // j = c*KC + ks*KS + (lane/32)*E + e (KS = 16) or c*KC + ks*2 + lane/32 (KS = 2).
 template <int KIND>
@@ -579,6 +808,31 @@ hipError_t launch_pipe(hipStream_t s, const Args& a) {
   return hipGetLastError();
 }
 
+template <int QT, bool SCALED>
+hipError_t launch_pipe2(hipStream_t s, const Args& a) {
+  constexpr int BM = Tile<2>::BM;
+  constexpr size_t stage = (size_t)BM * KC2 * 4 + (size_t)(BN / 32) * 64 * 8 * 2;
+  const size_t t2 = (size_t)(BN + 1) * (BM + 8) * 2;
+  const size_t lds = NS2 * stage > t2 ? NS2 * stage : t2;
+  auto fn = compress_pipe2<QT, SCALED>;
+  hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  const int per = (a.tiles + 7) / 8;
+  hipLaunchKernelGGL(fn, dim3(8 * per), dim3(Tile<2>::NT), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pipe2_q(hipStream_t s, const Args& a, int QT) {
+  switch (QT) {
+    case 1: return a.scale ? launch_pipe2<1, true>(s, a) : launch_pipe2<1, false>(s, a);
+    case 2: return a.scale ? launch_pipe2<2, true>(s, a) : launch_pipe2<2, false>(s, a);
+    case 3: return a.scale ? launch_pipe2<3, true>(s, a) : launch_pipe2<3, false>(s, a);
+    case 4: return a.scale ? launch_pipe2<4, true>(s, a) : launch_pipe2<4, false>(s, a);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int KIND>
 hipError_t launch_pipe_q(hipStream_t s, const Args& a, int QT) {
   switch (QT) {
@@ -606,7 +860,8 @@ hipError_t launch_q(hipStream_t s, const Args& a, int QT, size_t lds) {
 struct MfmaPlan {
   CompressShape sh;
   int kind = 0;   // 1 f32, 2 bf16
-  int variant = 0;  // 0 pipelined, 1 register-staged 16-byte loads, 2 scalar loads
+  int variant = 0;  // 0 pipelined, 1 register-staged 16-byte loads, 2 scalar loads,
+                    // 3 half chunks with register double buffering (bf16 only)
   int G = 0, ncb = 0, nrb = 0, nchunk = 0, QT = 0;
   void* Vpack = nullptr;
   void* Upack = nullptr;
@@ -733,7 +988,9 @@ hipError_t compress_mfma_main(hipStream_t s, const MfmaPlan* p, const float* X, 
   hipError_t e;
   // the 16-byte load paths need J % 4 == 0 and an aligned X
   const int v = vec ? p->variant : 2;
-  if (v == 0)
+  if (v == 3 && p->kind == 2)
+    e = launch_pipe2_q(s, a, p->QT);
+  else if (v == 0 || v == 3)
     e = p->kind == 1 ? launch_pipe_q<1>(s, a, p->QT) : launch_pipe_q<2>(s, a, p->QT);
   else if (v == 1)
     e = p->kind == 1 ? launch_q<1, true>(s, a, p->QT, p->lds) : launch_q<2, true>(s, a, p->QT, p->lds);

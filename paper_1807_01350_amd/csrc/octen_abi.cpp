@@ -945,6 +945,16 @@ octen_status octen_get_state(octen_t h, int32_t what, void* dst, size_t bytes) {
 
 // ------------------------------------------------------------- autotuner ---
 
+octen_status octen_compress_variant(octen_t h, int32_t variant) {
+  if (!h) return OCTEN_ERR_ARG;
+  if (!h->plan) return fail(h, OCTEN_ERR_UNSUPPORTED, "only MFMA compression has variants");
+  if (variant < 0 || variant > 3) return fail(h, OCTEN_ERR_ARG, "variant must be in [0, 3]");
+  if (variant == 3 && h->cfg.compress_dtype != OCTEN_BF16)
+    return fail(h, OCTEN_ERR_UNSUPPORTED, "variant 3 is BF16 only");
+  mfma_plan_set_variant(h->plan, variant);
+  return OCTEN_OK;
+}
+
 octen_status octen_autotune(octen_t h, const void* X, int64_t t, int32_t* choice_host) {
   if (!h) return OCTEN_ERR_ARG;
   if (!h->plan) return fail(h, OCTEN_ERR_UNSUPPORTED, "only MFMA compression is tuned");
@@ -957,6 +967,7 @@ octen_status octen_autotune(octen_t h, const void* X, int64_t t, int32_t* choice
   if ((gmax + 1) / 2 != gs[0] && gmax > 1) gs.push_back((gmax + 1) / 2);
   const bool vec = (h->J % 4 == 0) && (((uintptr_t)X & 15) == 0);
   std::vector<int> variants = vec ? std::vector<int>{0, 1, 2} : std::vector<int>{2};
+  if (vec && kind == 2) variants.push_back(3);   // half chunks, double-buffered fragments
   std::vector<MfmaPlan*> plans{h->plan};
   for (size_t q = 1; q < gs.size(); ++q) {
     MfmaPlan* pl = nullptr;

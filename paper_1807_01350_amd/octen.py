@@ -98,6 +98,7 @@ _SIGS = {
     "octen_mlp_get_params": ([_vp, _vp], _i32),
     "octen_mlp_last_activations": ([_vp, _i64, _vp, _vp], _i32),
     "octen_autotune": ([_vp, _vp, _i64, _vp], _i32),
+    "octen_compress_variant": ([_vp, _i32], _i32),
     "octen_autotune_als": ([_vp, _i32, _vp], _i32),
     "octen_group_create": ([_vp, _i32, ctypes.POINTER(_vp)], _i32),
     "octen_group_step": ([_vp, _vp, _i32, _f64, _i32, _vp], _i32),
@@ -270,6 +271,10 @@ def octen_mlp_get_params(m, dst):
 
 def octen_autotune(h, X, t, choice=None):
     return _lib.octen_autotune(h, _ptr(X), int(t), choice)
+
+
+def octen_compress_variant(h, variant):
+    return _lib.octen_compress_variant(h, int(variant))
 
 
 def octen_autotune_als(h, sweeps, choice=None):
@@ -515,6 +520,9 @@ class Octen:
         self._check(octen_autotune(self.h, X, X.shape[0], ctypes.cast(ctypes.byref(ch), _vp)),
                     "octen_autotune")
         return ch.value
+
+    def compress_variant(self, variant):
+        self._check(octen_compress_variant(self.h, int(variant)), "octen_compress_variant")
 
     def autotune_als(self, sweeps=10):
         ch = ctypes.c_int32(0)

@@ -204,7 +204,7 @@ def test_autotune_keeps_results_within_tolerance(form, J):
                  x_dtype="f32", compress_dtype=form)
     choice = e.autotune(tX)
     G, variant = divmod(choice, 10)
-    assert 1 <= G <= P and variant in (0, 1, 2)
+    assert 1 <= G <= P and variant in ((0, 1, 2, 3) if form == "bf16" else (0, 1, 2))
     if J % 4:
         assert variant == 2
     e.compress_batch(tX, tW)
@@ -212,6 +212,35 @@ def test_autotune_keeps_results_within_tolerance(form, J):
     Zr = compress_dense(X.astype(np.float64), U, V, Ws[0], P, Q, S)
     assert rel(Z, Zr) <= (2e-2 if form == "bf16" else 1e-5)
     print(f"[autotune] {form} J={J}: choice {choice}", file=sys.stderr)
+    e.close()
+
+
+@pytest.mark.parametrize("J", [1000, 998])
+def test_compress_variants_agree(J):
+    """Every compression variant of a BF16 handle gives the oracle's summary
+    within the BF16 bar; the half-chunk variant (3) accumulates the same k
+    steps in the same order as the pipelined one (0), so the two agree bit
+    for bit.  With J % 4 != 0 the 16-byte variants fall back to the scalar
+    kernel."""
+    import torch
+    from oracle import compress_dense
+    from paper_1807_01350_amd import octen as oc
+    I, R, P, Q, S, t = 600, 6, 12, 60, 3, 5
+    c = Case("variants", I, J, R, P, Q, S, (t,), config_id=91)
+    X, U, V, Ws, init = make_inputs(c, x_dtype=np.float32)
+    tX, tW = torch.from_numpy(X).cuda(), torch.from_numpy(Ws[0]).cuda()
+    e = oc.Octen(I, J, R, P, Q, S, torch.from_numpy(U).cuda(), torch.from_numpy(V).cuda(),
+                 x_dtype="f32", compress_dtype="bf16")
+    Zr = compress_dense(X.astype(np.float64), U, V, Ws[0], P, Q, S)
+    Zs = {}
+    for v in (0, 1, 2, 3):
+        e.compress_variant(v)
+        e.compress_batch(tX, tW)
+        Zs[v] = e.state(oc.OCTEN_STATE_Z).cpu().numpy()
+        assert rel(Zs[v], Zr) <= 2e-2, (v, rel(Zs[v], Zr))
+    assert np.array_equal(Zs[0], Zs[3])
+    with pytest.raises(oc.OctenError):
+        e.compress_variant(4)
     e.close()
 
 
