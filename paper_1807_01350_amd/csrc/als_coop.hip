@@ -146,6 +146,20 @@ __device__ void spd_inverse_wave(const double* G, double* Ginv, int R, int* bad)
   if (lane == 0 && badl) *bad = 1;
 }
 
+// Quotient of e by a fixed divisor d through a 64-bit product with
+// m = ceil(2^32 / d) (2^32 itself for d = 1): exact for e * d < 2^32 (here
+// e < 2^20, d <= 128); the divisors are runtime values, and a general integer
+// division is a long instruction sequence on the GPU.
+struct FastDiv {
+  unsigned long long m;
+  int d;
+  __device__ explicit FastDiv(int dd) : m(0xFFFFFFFFull / (unsigned)dd + 1ull), d(dd) {}
+  __device__ __forceinline__ int div(int e) const {
+    return (int)(((unsigned long long)(unsigned)e * m) >> 32);
+  }
+  __device__ __forceinline__ int mod(int e) const { return e - div(e) * d; }
+};
+
 // G = F^T F (F: n x R in LDS, row stride R) by one wavefront on MFMA; R <= 32.
 __device__ void gram_wave(const double* Fm, int n, int R, double* G) {
   const int lane = threadIdx.x & 63;
@@ -172,10 +186,38 @@ __device__ void gram_wave(const double* Fm, int n, int R, double* G) {
     }
 }
 
+// G = F^T F (F: n x R in LDS) by all threads: four lanes per entry split the
+// rows (two accumulators each), then the four partial sums are added across
+// lanes in a fixed order.
+__device__ void gram_all(const double* Fm, int n, int R, double* G) {
+  const int RR = R * R;
+  for (int base = 0; base < RR * 4; base += NT) {
+    const int idx = base + (int)threadIdx.x;
+    const int e = idx >> 2, sub = idx & 3;
+    double s0 = 0.0, s1 = 0.0;
+    if (e < RR) {
+      const FastDiv fr(R);
+      const double* f1 = Fm + fr.div(e);
+      const double* f2 = Fm + fr.mod(e);
+      int q = sub;
+      for (; q + 4 < n; q += 8) {
+        s0 = fma(f1[q * R], f2[q * R], s0);
+        s1 = fma(f1[(q + 4) * R], f2[(q + 4) * R], s1);
+      }
+      if (q < n) s0 = fma(f1[q * R], f2[q * R], s0);
+    }
+    double s = s0 + s1;
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    if (e < RR && sub == 0) G[e] = s;
+  }
+}
+
 // out(q, :) = M(q, :) Ginv for q < n (all threads; independent loads).
 __device__ void apply_inverse(const double* M, const double* Ginv, double* out, int n, int R) {
+  const FastDiv fr(R);
   for (int e = threadIdx.x; e < n * R; e += NT) {
-    const int q = e / R, r = e % R;
+    const int q = fr.div(e), r = e - q * R;
     const double* m = M + q * R;
     double s0 = 0.0, s1 = 0.0;
     int k = 0;
@@ -241,6 +283,7 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   const int npair = na * Q;                   // rows (a, b) of the slab
   const int QP = GX ? Q : Q + 1;              // slab row stride (LDS: padded)
   const int RT = (R + 15) / 16;               // 16-wide tiles over r
+  const FastDiv fR(R), fQ(Q);
   const int64_t Q2 = (int64_t)Q * Q;
 
   double* Ts = (double*)smem;                 // [npair_pad][R]  T, then W
@@ -349,18 +392,27 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       }
     }
     __syncthreads();
-    // M1(la, r) = sum_b T(la, b, r) B(b, r)
-    for (int e = tid; e < na * R; e += NT) {
-      const int la = e / R, r = e % R;
-      const double* tr = Ts + (int64_t)la * QR + r;
+    // M1(la, r) = sum_b T(la, b, r) B(b, r): eight lanes per entry split b,
+    // their partial sums are added across lanes in a fixed order
+    for (int base = 0; base < na * R * 8; base += NT) {
+      const int idx = base + tid, e = idx >> 3, sub = idx & 7;
       double s0 = 0.0, s1 = 0.0;
-      int b = 0;
-      for (; b + 1 < Q; b += 2) {
-        s0 = fma(tr[b * R], Bf[b * R + r], s0);
-        s1 = fma(tr[(b + 1) * R], Bf[(b + 1) * R + r], s1);
+      if (e < na * R) {
+        const int la = fR.div(e), r = e - la * R;
+        const double* tr = Ts + (int64_t)la * QR + r;
+        const double* br = Bf + r;
+        int b = sub;
+        for (; b + 8 < Q; b += 16) {
+          s0 = fma(tr[b * R], br[b * R], s0);
+          s1 = fma(tr[(b + 8) * R], br[(b + 8) * R], s1);
+        }
+        if (b < Q) s0 = fma(tr[b * R], br[b * R], s0);
       }
-      if (b < Q) s0 = fma(tr[b * R], Bf[b * R + r], s0);
-      Ml[e] = s0 + s1;
+      double sm = s0 + s1;
+      sm += __shfl_xor(sm, 1, 64);
+      sm += __shfl_xor(sm, 2, 64);
+      sm += __shfl_xor(sm, 4, 64);
+      if (e < na * R && sub == 0) Ml[e] = sm;
     }
     __syncthreads();
     apply_inverse(Ml, Gi, Al, na, R);
@@ -371,10 +423,10 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     for (int e = tid; e < QR + RR; e += NT) {
       double s = 0.0;
       if (e < QR) {
-        const int b = e / R, r = e % R;
+        const int b = fR.div(e), r = e - b * R;
         for (int la = 0; la < na; ++la) s = fma(Ts[((int64_t)la * Q + b) * R + r], Al[la * R + r], s);
       } else {
-        const int r1 = (e - QR) / R, r2 = (e - QR) % R;
+        const int r1 = fR.div(e - QR), r2 = e - QR - r1 * R;
         for (int la = 0; la < na; ++la) s = fma(Al[la * R + r1], Al[la * R + r2], s);
       }
       if (NW > 1) sl[e] = s;
@@ -388,7 +440,25 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok);
       if (!alive) break;
       if (wave == 0) {
-        for (int e = lane; e < RR; e += 64) AtA[e] = sum_slots(slot(set1, 0) + QR + e, slot_len, NW);
+        // two entries per lane, both sets of loads in flight together
+        for (int e = lane; e < RR; e += 128) {
+          const double* b0 = slot(set1, 0) + QR + e;
+          const bool two = e + 64 < RR;
+          double v0[16], v1[16];
+          double a0 = 0.0, a1 = 0.0;
+          for (int w0 = 0; w0 < NW; w0 += 16) {
+#pragma unroll
+            for (int u2 = 0; u2 < 16; ++u2) {
+              v0[u2] = w0 + u2 < NW ? b0[(int64_t)(w0 + u2) * slot_len] : 0.0;
+              v1[u2] = (two && w0 + u2 < NW) ? b0[(int64_t)(w0 + u2) * slot_len + 64] : 0.0;
+            }
+#pragma unroll
+            for (int u2 = 0; u2 < 16; ++u2)
+              if (w0 + u2 < NW) { a0 += v0[u2]; a1 += v1[u2]; }
+          }
+          AtA[e] = a0;
+          if (two) AtA[e + 64] = a1;
+        }
       } else {
         for (int e = tid - 64; e < QR; e += NT - 64) Mf[e] = sum_slots(slot(set1, 0) + e, slot_len, NW);
       }
@@ -403,28 +473,31 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       }
       wave_sync();
       for (int e = lane; e < RR; e += 64) {
-        AtA[e] /= lamv[e / R] * lamv[e % R];
+        AtA[e] /= lamv[fR.div(e)] * lamv[fR.mod(e)];
         G[e] = AtA[e] * CtC[e];
       }
       wave_sync();
       // ---------------------------------------------- mode 2 solve (B)
       spd_inverse_wave<RMAX>(G, Gi, R, &s_bad);
+      // M2 was formed with the unnormalised A: B = (M2 / lambda_A) G2^{-1},
+      // so row k of the inverse takes the factor 1 / lambda_A(k)
+      wave_sync();
+      for (int e = lane; e < RR; e += 64) Gi[e] /= lamv[fR.div(e)];
     }
     __syncthreads();
-    for (int e = tid; e < na * R; e += NT) Al[e] /= lamv[e % R];
-    for (int e = tid; e < QR; e += NT) Mf[e] /= lamv[e % R];
-    __syncthreads();
+    for (int e = tid; e < na * R; e += NT) Al[e] /= lamv[fR.mod(e)];
     apply_inverse(Mf, Gi, Bf, Q, R);
     __syncthreads();
     col_norms(Bf, Q, R, lamv);
     __syncthreads();
-    for (int e = tid; e < QR; e += NT) Bf[e] /= lamv[e % R];
+    for (int e = tid; e < QR; e += NT) Bf[e] /= lamv[fR.mod(e)];
     __syncthreads();
-    // W(pair, r) = A(a, r) B(b, r) into Ts; B'B by wave 0
-    if (wave == 0) gram_wave(Bf, Q, R, BtB);
+    // W(pair, r) = A(a, r) B(b, r) into Ts; B'B
+    gram_all(Bf, Q, R, BtB);
     for (int e = tid; e < npair * R; e += NT) {
-      const int pr = e / R, r = e % R;
-      Ts[e] = Al[(pr / Q) * R + r] * Bf[(pr % Q) * R + r];
+      const int pr = fR.div(e), r = e - pr * R;
+      const int a = fQ.div(pr), b = pr - a * Q;
+      Ts[e] = Al[a * R + r] * Bf[b * R + r];
     }
     __syncthreads();
     // ------------------------------------------------ mode 3 partial
@@ -502,9 +575,9 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     __syncthreads();
     col_norms(Cf, Q, R, lamv);
     __syncthreads();
-    for (int e = tid; e < QR; e += NT) Cf[e] /= lamv[e % R];
+    for (int e = tid; e < QR; e += NT) Cf[e] /= lamv[fR.mod(e)];
     __syncthreads();
-    if (wave == 0) gram_wave(Cf, Q, R, CtC);
+    gram_all(Cf, Q, R, CtC);
     __syncthreads();
     ++done;
     if (g.tol > 0.0) {
@@ -512,9 +585,9 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       // order (every workgroup of the replica reaches the same decision)
       if (wave == 0) {
         double inner = 0.0, nh = 0.0;
-        for (int e = lane; e < QR; e += 64) inner = fma(Mf[e] * lamv[e % R], Cf[e], inner);
+        for (int e = lane; e < QR; e += 64) inner = fma(Mf[e] * lamv[fR.mod(e)], Cf[e], inner);
         for (int e = lane; e < RR; e += 64)
-          nh += lamv[e / R] * (AtA[e] * BtB[e] * CtC[e]) * lamv[e % R];
+          nh += lamv[fR.div(e)] * (AtA[e] * BtB[e] * CtC[e]) * lamv[fR.mod(e)];
         for (int off = 32; off > 0; off >>= 1) {
           inner += __shfl_xor(inner, off, 64);
           nh += __shfl_xor(nh, off, 64);
