@@ -183,49 +183,49 @@ __global__ __launch_bounds__(1024) void spd_solve_kernel(double* __restrict__ Nm
   if (tid == 0 && bad && *info == 0) *info = bad;
 }
 
-// Small systems (n <= 96, nrhs <= 32): Gauss-Jordan elimination without
+// Small systems (n <= 112, nrhs <= 32): Gauss-Jordan elimination without
 // pivoting on [N | B] held in LDS, one workgroup; for symmetric positive
 // definite N every pivot is positive (an SPD Schur complement stays SPD).
-// Per pivot j: the multipliers N(i,j)/N(j,j) are taken, every row i != j
-// loses its multiple of row j, then row j is divided by its pivot.  The
-// right-hand columns end as N^{-1} B.  info = j + 1 for a pivot that is not
-// positive (the elimination continues with it skipped).
+// Per pivot j: every row i != j loses N(i,j)/N(j,j) times row j (columns
+// right of j only: the ones left of j are already eliminated and column j is
+// not read again), then row j is divided by its pivot; two barriers per
+// pivot.  Thread t owns rows t/16 + 16k and columns t%16 + 16m, so no
+// element index is divided at run time.  The right-hand columns end as
+// N^{-1} B.  info = j + 1 for a pivot that is not positive (the elimination
+// continues with it skipped).
 constexpr int GJ_NMAX = 112, GJ_RMAX = 32;
 __global__ __launch_bounds__(256) void spd_solve_gj_kernel(const double* __restrict__ Nm, int n,
                                                            double* __restrict__ Bm, int nrhs,
                                                            int* info) {
   extern __shared__ double gj_lds[];
-  __shared__ double f[GJ_NMAX];
   __shared__ int bad;
   const int tid = threadIdx.x, w = n + nrhs, ld = w + 1;
+  const int rg = tid >> 4, cg = tid & 15;
   auto M = [&](int i, int c) -> double& { return gj_lds[i * ld + c]; };
   if (tid == 0) bad = 0;
-  for (int e = tid; e < n * w; e += 256) {
-    const int i = e / w, c = e % w;
-    M(i, c) = c < n ? Nm[(int64_t)i * n + c] : Bm[(int64_t)i * nrhs + (c - n)];
-  }
+  for (int i = rg; i < n; i += 16)
+    for (int c = cg; c < w; c += 16)
+      M(i, c) = c < n ? Nm[(int64_t)i * n + c] : Bm[(int64_t)i * nrhs + (c - n)];
   __syncthreads();
   for (int j = 0; j < n; ++j) {
     const double p = M(j, j);
     const bool ok = p > 0.0;
+    const double ip = ok ? 1.0 / p : 0.0;
     if (tid == 0 && !ok && !bad) bad = j + 1;
-    for (int i = tid; i < n; i += 256) f[i] = (ok && i != j) ? M(i, j) / p : 0.0;
-    __syncthreads();
-    // rows i != j; columns right of j only (columns left of j are already
-    // zero below and above the diagonal, column j is not read again)
-    const int wc = w - j - 1;
-    for (int e = tid; e < n * wc; e += 256) {
-      const int i = e / wc, c = j + 1 + e % wc;
-      if (i != j) M(i, c) -= f[i] * M(j, c);
+    if (ok) {
+      for (int i = rg; i < n; i += 16) {
+        if (i == j) continue;
+        const double f = M(i, j) * ip;
+        for (int c = j + 1 + cg; c < w; c += 16) M(i, c) = fma(-f, M(j, c), M(i, c));
+      }
     }
     __syncthreads();
-    for (int c = j + 1 + tid; c < w; c += 256) M(j, c) = ok ? M(j, c) / p : M(j, c);
+    if (ok && rg == 0)
+      for (int c = j + 1 + cg; c < w; c += 16) M(j, c) *= ip;
     __syncthreads();
   }
-  for (int e = tid; e < n * nrhs; e += 256) {
-    const int i = e / nrhs, c = e % nrhs;
-    Bm[(int64_t)i * nrhs + c] = M(i, n + c);
-  }
+  for (int i = rg; i < n; i += 16)
+    for (int c = cg; c < nrhs; c += 16) Bm[(int64_t)i * nrhs + c] = M(i, n + c);
   if (tid == 0 && bad && *info == 0) *info = bad;
 }
 
@@ -461,9 +461,9 @@ hipError_t rowdot(hipStream_t s, int64_t nrows, int ncols, int64_t K, const doub
   // partial sums are added in split order by a second kernel
   int64_t nsplit = 1;
   const int64_t waves = nrows * nblk;
-  if (work && waves < 2048 && K >= 512) {
+  if (work && waves < 2048 && K >= 256) {
     nsplit = (2048 + waves - 1) / waves;
-    const int64_t maxs = K / 256;
+    const int64_t maxs = K / 128;   // at least two 64-wide steps per wavefront
     if (nsplit > maxs) nsplit = maxs;
     if (nsplit > 64) nsplit = 64;
     while (nsplit > 1 && nsplit * nrows * ncols > work_len) --nsplit;
