@@ -661,7 +661,9 @@ def main():
         roof = {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_PEAK_TFLOPS["f32"],
                 "unit": "TFLOP/s", "frac": round(tflops / MFMA_PEAK_TFLOPS["f32"], 4),
                 "traffic": traffic}
-    roof["kernel"] = "compress_pipe (modes 1 and 2 of the batch compression)"
+    kname = {0: "compress_pipe", 1: "compress_fused (16-byte loads)", 2: "compress_fused",
+             3: "compress_pipe2"}.get(tuned["compress"] % 10, "compress")
+    roof["kernel"] = f"{kname} (modes 1 and 2 of the batch compression)"
     roof["algorithmic_bytes_per_launch"] = bytes_launch
     roof["algorithmic_flops_per_launch"] = flops_launch
     roof["mfma_frac"] = round(tflops / MFMA_PEAK_TFLOPS[args.form], 4)
