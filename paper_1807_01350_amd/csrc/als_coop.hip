@@ -49,7 +49,7 @@ struct CoopArgs {
   int* iters;             // [P]
   int* flags;             // [P]
   double* slots;          // [2][P][NW][slot_len]
-  unsigned* counters;     // [P]
+  unsigned* counters;     // [2][P]: barrier counts, then masks of XCDs
   int* err;               // [1]
   int P, Q, R, NW, na_max, npair_pad, per_xcd, slot_len, max_iters;
   double tol;
@@ -61,17 +61,31 @@ __device__ __forceinline__ f64x4 mfma64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Index of the accelerator complex die (XCD) the calling wavefront runs on.
+__device__ __forceinline__ unsigned xcd_id() {
+  unsigned v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(v));
+  return v;
+}
+
 // Barrier of the NW workgroups of one replica.  Every wave first waits for
 // its own global stores to complete (a plain workgroup barrier does not), then
-// one thread publishes them with a single agent-scope release, bumps the
-// counter, polls it with relaxed loads (no cache invalidation per poll) and
-// performs one agent-scope acquire before the workgroup continues.
-__device__ bool replica_barrier(unsigned* ctr, unsigned target, int* err, int* s_ok) {
+// one thread bumps the counter and polls it with relaxed loads (no cache
+// invalidation per poll).  Completed stores sit in the L2 of the writer's XCD;
+// readers take slot data with device-coherent loads (slot_load), which miss
+// in the CU's L1, where a copy from two barriers earlier may still live.
+//  - across XCDs (local false): one agent-scope release before the bump
+//    writes the L2 back and one agent-scope acquire after the poll
+//    invalidates the reader's L2;
+//  - within one XCD (local true): the L2 is shared by writer and reader and
+//    neither is needed.
+__device__ bool replica_barrier(unsigned* ctr, unsigned target, int* err, int* s_ok,
+                                bool local) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = 1;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned spins = 0;
     while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -83,11 +97,16 @@ __device__ bool replica_barrier(unsigned* ctr, unsigned target, int* err, int* s
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *s_ok = ok;
   }
   __syncthreads();
   return *s_ok != 0;
+}
+
+// Slot entry written by another workgroup of the replica (see above).
+__device__ __forceinline__ double slot_load(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Value of x held by lane j (j uniform), through two scalar lane reads.
@@ -252,7 +271,7 @@ __device__ __forceinline__ double sum_slots(const double* base, int64_t stride, 
   for (int w0 = 0; w0 < NW; w0 += 16) {
     double v[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = w0 + u < NW ? base[(w0 + u) * stride] : 0.0;
+    for (int u = 0; u < 16; ++u) v[u] = w0 + u < NW ? slot_load(base + (w0 + u) * stride) : 0.0;
 #pragma unroll
     for (int u = 0; u < 16; ++u)
       if (w0 + u < NW) s += v[u];
@@ -266,7 +285,7 @@ __device__ __forceinline__ double sum_slots(const double* base, int64_t stride, 
 template <typename T, int RMAX, bool GX>
 __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_ok, s_bad, s_stop;
+  __shared__ int s_ok, s_bad, s_stop, s_local;
   __shared__ double s_nx2, s_fit_old;
   __shared__ int s_have_old;
 
@@ -318,6 +337,19 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   unsigned* ctr = g.counters + p;
   unsigned nbar = 0;
   bool alive = true;
+  // a replica whose workgroups all landed on one XCD synchronises through
+  // that XCD's L2 (the placement above asks for this; the mask checks it)
+  bool local = false;
+  if (NW > 1) {
+    unsigned* xmask = g.counters + g.P + p;
+    if (tid == 0)
+      __hip_atomic_fetch_or(xmask, 1u << xcd_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok, false);
+    if (tid == 0)
+      s_local = __popc(__hip_atomic_load(xmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 1;
+    __syncthreads();
+    local = alive && s_local;
+  }
   const int slot_len = g.slot_len;
   // the slot set alternates with the barrier count: a set is rewritten two
   // barriers later, when every workgroup has finished reading it
@@ -340,10 +372,10 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     if (NW > 1) {
       const int bs = (nbar + 1) & 1;
       if (tid == 0) slot(bs, w)[0] = scr[0];
-      alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok);
+      alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok, local) && alive;
       if (alive && tid == 0) {
         double t = 0.0;
-        for (int ww = 0; ww < NW; ++ww) t += slot(bs, ww)[0];
+        for (int ww = 0; ww < NW; ++ww) t += slot_load(slot(bs, ww));
         s_nx2 = t;
       }
     } else if (tid == 0) {
@@ -437,7 +469,7 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     // (norms from diag(A'A)), the normalised A'A, G2 and its inverse, while
     // the other wavefronts sum M2
     if (NW > 1) {
-      alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok);
+      alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok, local);
       if (!alive) break;
       if (wave == 0) {
         // two entries per lane, both sets of loads in flight together
@@ -449,8 +481,8 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
           for (int w0 = 0; w0 < NW; w0 += 16) {
 #pragma unroll
             for (int u2 = 0; u2 < 16; ++u2) {
-              v0[u2] = w0 + u2 < NW ? b0[(int64_t)(w0 + u2) * slot_len] : 0.0;
-              v1[u2] = (two && w0 + u2 < NW) ? b0[(int64_t)(w0 + u2) * slot_len + 64] : 0.0;
+              v0[u2] = w0 + u2 < NW ? slot_load(b0 + (int64_t)(w0 + u2) * slot_len) : 0.0;
+              v1[u2] = (two && w0 + u2 < NW) ? slot_load(b0 + (int64_t)(w0 + u2) * slot_len + 64) : 0.0;
             }
 #pragma unroll
             for (int u2 = 0; u2 < 16; ++u2)
@@ -564,7 +596,7 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
         }
       }
       if (NW > 1) {
-        alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok);
+        alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok, local);
         if (!alive) break;
         for (int e = tid; e < QR; e += NT) Mf[e] = sum_slots(slot(set2, 0) + e, slot_len, NW);
       }
@@ -652,7 +684,7 @@ hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int 
   a.max_iters = max_iters; a.tol = tol;
   const size_t lds = als_coop_lds_bytes(Q, R, NW, y_f64, slab_global);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipError_t e = fill_i32(s, (int*)counters, P, 0);
+  hipError_t e = fill_i32(s, (int*)counters, 2 * P, 0);
   if (e != hipSuccess) return e;
   e = fill_i32(s, err, 1, 0);
   if (e != hipSuccess) return e;

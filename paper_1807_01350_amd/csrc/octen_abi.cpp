@@ -422,7 +422,7 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
         h->als_nw = nw;
         h->als_gx = gx;
         IOK(dalloc(h, &h->als_slots, (size_t)2 * P * nw * als_coop_slot_len((int)Q, (int)R)));
-        IOK(dalloc(h, &h->als_ctr, (size_t)P));
+        IOK(dalloc(h, &h->als_ctr, 2 * (size_t)P));
         IOK(dalloc(h, &h->als_err, 1));
       }
     }

@@ -106,7 +106,7 @@ hipError_t als_reference(hipStream_t s, const void* Y, bool y_f64, int P, int Q,
                          int max_iters, double tol);
 
 // Many workgroups per replica, slabs of X_p in LDS, cooperative launch.
-// slots: [2][P][NW][als_coop_slot_len] f64; counters: [P]; err: [1].
+// slots: [2][P][NW][als_coop_slot_len] f64; counters: [2][P]; err: [1].
 inline int als_coop_slot_len(int Q, int R) { return Q * R + R * R + 8; }
 // slab_global: the slab is read from Y in global memory instead of LDS.
 size_t als_coop_lds_bytes(int Q, int R, int NW, bool x_f64, bool slab_global);
