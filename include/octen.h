@@ -95,6 +95,11 @@ enum {
 #define OCTEN_FLAG_ALS_ONE_WG 0x8ull     /* ALS: one workgroup per replica, no
                                             cooperative launch (group steps
                                             always run this way)              */
+#define OCTEN_FLAG_ALS_DEVICE_SYNC 0x10ull /* ALS: the barriers between the
+                                            workgroups of a replica always
+                                            write back and invalidate the L2,
+                                            also where all of them run on one
+                                            XCD (same results, slower)        */
 
 /* Stages timed with OCTEN_FLAG_TIMING (octen_stage_time). */
 enum {

@@ -52,6 +52,7 @@ struct CoopArgs {
   unsigned* counters;     // [2][P]: barrier counts, then masks of XCDs
   int* err;               // [1]
   int P, Q, R, NW, na_max, npair_pad, per_xcd, slot_len, max_iters;
+  int allow_local;        // 0: device-wide cache maintenance at every barrier
   double tol;
 };
 
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     if (tid == 0)
       s_local = __popc(__hip_atomic_load(xmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 1;
     __syncthreads();
-    local = alive && s_local;
+    local = alive && s_local && g.allow_local;
   }
   const int slot_len = g.slot_len;
   // the slot set alternates with the barrier count: a set is rewritten two
@@ -671,7 +672,7 @@ size_t als_coop_lds_bytes(int Q, int R, int NW, bool x_f64, bool slab_global) {
 hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int R, int NW,
                     bool slab_global, const double* init, double* F, double* lam, int* iters,
                     int* flags, double* slots, unsigned* counters, int* err, int max_iters,
-                    double tol) {
+                    double tol, bool allow_local) {
   if (R > MAXR || Q > 128 || NW < 1 || NW > Q || NW > 32) return hipErrorInvalidValue;
   CoopArgs a;
   a.Y = Y; a.init = init; a.F = F; a.lam = lam; a.iters = iters; a.flags = flags;
@@ -681,7 +682,7 @@ hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int 
   a.npair_pad = pad_pairs(Q, NW);
   a.per_xcd = (P + 7) / 8;
   a.slot_len = als_coop_slot_len(Q, R);
-  a.max_iters = max_iters; a.tol = tol;
+  a.max_iters = max_iters; a.tol = tol; a.allow_local = allow_local ? 1 : 0;
   const size_t lds = als_coop_lds_bytes(Q, R, NW, y_f64, slab_global);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   hipError_t e = fill_i32(s, (int*)counters, 2 * P, 0);

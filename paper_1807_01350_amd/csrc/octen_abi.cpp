@@ -671,7 +671,7 @@ octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int
     if (h->als_nw > 0 && !in_branch && !(h->cfg.flags & OCTEN_FLAG_ALS_ONE_WG)) {
       e = als_coop(s, h->Y, h->acc_f64, h->P, h->Q, h->R, h->als_nw, h->als_gx, src, h->F,
                    h->lam, h->iters, h->flags, h->als_slots, h->als_ctr, h->als_err, max_iters,
-                   tol);
+                   tol, !(h->cfg.flags & OCTEN_FLAG_ALS_DEVICE_SYNC));
       if (e != hipSuccess) {
         (void)hipGetLastError();
         h->als_nw = 0;   // cooperative launch not possible here: use the reference kernel
@@ -1062,11 +1062,13 @@ octen_status octen_autotune_als(octen_t h, int32_t sweeps, int32_t* choice_host)
   octen_status st = OCTEN_OK;
   for (size_t q = 0; q < cand.size(); ++q) {
     hipError_t e = als_coop(s, h->Y, h->acc_f64, P, Q, R, cand[q].first, cand[q].second, F0, h->F,
-                            h->lam, h->iters, h->flags, slots, h->als_ctr, h->als_err, 1, 0.0);
+                            h->lam, h->iters, h->flags, slots, h->als_ctr, h->als_err, 1, 0.0,
+                            !(h->cfg.flags & OCTEN_FLAG_ALS_DEVICE_SYNC));
     if (e == hipSuccess) e = hipEventRecord(e0, s);
     if (e == hipSuccess)
       e = als_coop(s, h->Y, h->acc_f64, P, Q, R, cand[q].first, cand[q].second, F0, h->F, h->lam,
-                   h->iters, h->flags, slots, h->als_ctr, h->als_err, sweeps, 0.0);
+                   h->iters, h->flags, slots, h->als_ctr, h->als_err, sweeps, 0.0,
+                   !(h->cfg.flags & OCTEN_FLAG_ALS_DEVICE_SYNC));
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;

@@ -38,6 +38,7 @@ OCTEN_FLAG_FUSE_UPDATE = 0x1
 OCTEN_FLAG_REFERENCE_PATH = 0x2
 OCTEN_FLAG_TIMING = 0x4
 OCTEN_FLAG_ALS_ONE_WG = 0x8
+OCTEN_FLAG_ALS_DEVICE_SYNC = 0x10
 (OCTEN_STAGE_COMPRESS_MAIN, OCTEN_STAGE_COMPRESS_MODE3, OCTEN_STAGE_UPDATE, OCTEN_STAGE_ALS,
  OCTEN_STAGE_RECOVER, OCTEN_STAGE_COO_INDEX) = range(6)
 

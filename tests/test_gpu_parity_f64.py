@@ -118,3 +118,22 @@ def test_deterministic_rerun():
     for x, y in zip(a, b):
         for key in ("Z", "Y", "F", "A", "B", "C"):
             assert np.array_equal(x[key], y[key]), key
+
+
+@pytest.mark.parametrize("idx", [4, 5], ids=["wideq", "gx_slab"])
+def test_device_sync_barriers_give_identical_als(idx):
+    """Replicas spread over several workgroups: the barriers that keep the
+    slot exchange inside one XCD's L2 and the ones that write back and
+    invalidate the L2 at every step give bit-identical ALS results (the slot
+    sums run in a fixed order either way), with and without a tolerance."""
+    from paper_1807_01350_amd import octen as oc
+    case = CASES[idx]
+    X, U, V, Ws, init = make_inputs(case)
+    for tol in (0.0, 1e-9):
+        a = run_gpu(case, X, U, V, Ws, init, tol=tol)
+        b = run_gpu(case, X, U, V, Ws, init, tol=tol, flags=oc.OCTEN_FLAG_ALS_DEVICE_SYNC)
+        for x, y in zip(a, b):
+            assert np.array_equal(x["iters"], y["iters"])
+            for key in ("F", "lam", "A", "B", "C"):
+                assert np.array_equal(x[key], y[key]), (tol, key)
+            assert not np.any(x["flags"]) and not np.any(y["flags"])
