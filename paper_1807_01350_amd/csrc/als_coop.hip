@@ -127,41 +127,50 @@ __device__ __forceinline__ void wave_sync() {
 
 // Inverse of the SPD matrix G (R x R, LDS) by Gauss-Jordan elimination
 // without pivoting, run by one wavefront on [G | I] stored by columns: lane
-// c keeps column c (c < 2R <= 64) in registers.  At step j every lane needs
-// the pivot column, which lives in lane j and is read with scalar lane reads
-// (R values per step, no LDS traffic, no cross-lane permutes); the pivot row
-// entry of its own column is already in its registers.  Writes Ginv (LDS)
-// and sets *bad when a pivot is not positive.
+// c keeps column c in registers.  G is padded to RMAX x RMAX with the
+// identity (lanes 0..RMAX-1 hold its columns, lanes RMAX..RMAX+R-1 the
+// inverse's), so all RMAX steps run as straight-line code; the padding only
+// adds exact zeros to the real entries.  At step j every lane needs the pivot
+// column, which lives in lane j: its RMAX entries are read with scalar lane
+// reads, all before the updates so that the reads are not serialised behind
+// them (no LDS traffic, no cross-lane permutes).  Writes Ginv (LDS) and sets
+// *bad when a pivot is not positive.
 template <int RMAX>
-__device__ void spd_inverse_wave(const double* G, double* Ginv, int R, int* bad) {
+__device__ __forceinline__ void spd_inverse_wave(const double* G, double* Ginv, int R, int* bad) {
+  static_assert(2 * RMAX <= 64, "one wavefront holds [G | I]");
   const int lane = threadIdx.x & 63;
   double a[RMAX];
 #pragma unroll
   for (int i = 0; i < RMAX; ++i) {
     double v = 0.0;
-    if (i < R) {
-      if (lane < R) v = G[i * R + lane];
-      else if (lane == R + i) v = 1.0;
+    if (lane < RMAX) {
+      if (i < R && lane < R) v = G[i * R + lane];
+      else if (i == lane) v = 1.0;
+    } else if (lane == RMAX + i) {
+      v = 1.0;
     }
     a[i] = v;
   }
   int badl = 0;
 #pragma unroll
   for (int j = 0; j < RMAX; ++j) {
-    if (j < R) {
-      double piv = lane_value(a[j], j);
-      if (!(piv > 0.0)) { badl = 1; piv = 1e-300; }
-      const double rj = a[j] * (1.0 / piv);
+    double col[RMAX];
 #pragma unroll
-      for (int i = 0; i < RMAX; ++i)
-        if (i != j && i < R) a[i] = fma(-lane_value(a[i], j), rj, a[i]);
-      a[j] = rj;
-    }
-  }
-  if (lane >= R && lane < 2 * R) {
+    for (int i = 0; i < RMAX; ++i) col[i] = lane_value(a[i], j);
+    __builtin_amdgcn_sched_barrier(0);
+    double piv = col[j];
+    badl |= !(piv > 0.0);
+    piv = piv > 0.0 ? piv : 1e-300;
+    const double rj = a[j] * (1.0 / piv);
 #pragma unroll
     for (int i = 0; i < RMAX; ++i)
-      if (i < R) Ginv[i * R + (lane - R)] = a[i];
+      if (i != j) a[i] = fma(-col[i], rj, a[i]);
+    a[j] = rj;
+  }
+  if (lane >= RMAX && lane < RMAX + R) {
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i)
+      if (i < R) Ginv[i * R + (lane - RMAX)] = a[i];
   }
   if (lane == 0 && badl) *bad = 1;
 }
@@ -404,12 +413,37 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
         const int rr = rt * 16 + lane % 16;
         f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
         const bool okc = rr < R;
-        // indices clamped into range and the k tail zeroed after the load:
-        // no branches around the loads, so unrolled iterations overlap them
         const T* xr = Xs + (pr < npair ? pr : npair - 1) * QP;
         const double* cr = Cf + (okc ? rr : R - 1);
-#pragma unroll 4
-        for (int c0 = 0; c0 < Q; c0 += 8) {
+        // whole groups of 32 columns: all sixteen loads first, then the
+        // conversions, then the eight MFMAs (a VALU instruction issued
+        // between MFMAs of one wavefront waits for them); same order of
+        // accumulation as the step loop below
+        int c0 = 0;
+        {
+          const T* xp = xr + lane / 16;
+          const double* cp = cr + (lane / 16) * R;
+          for (; c0 + 32 <= Q; c0 += 32) {
+            T xv[8];
+            double bv[8], xd[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) { xv[u] = xp[4 * u]; bv[u] = cp[4 * u * R]; }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) xd[u] = (double)xv[u];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 8; u += 2) {
+              acc0 = mfma64(xd[u], bv[u], acc0);
+              acc1 = mfma64(xd[u + 1], bv[u + 1], acc1);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            xp += 32;
+            cp += 32 * R;
+          }
+        }
+        // the rest: indices clamped into range and the k tail zeroed after
+        // the load (no branches around the loads)
+        for (; c0 < Q; c0 += 8) {
           const int c = c0 + lane / 16, c2 = c + 4;
           const int cc = c < Q ? c : Q - 1, cc2 = c2 < Q ? c2 : Q - 1;
           const double x0 = (double)xr[cc], x1 = (double)xr[cc2];
@@ -561,8 +595,30 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
           const bool okr = rr < R;
           const T* xc = Xs + (c < Q ? c : Q - 1);
           const double* wc = Ts + (okr ? rr : R - 1);
-#pragma unroll 4
-          for (int k0 = kb; k0 < ke; k0 += 8) {
+          // whole groups of 32 pairs as for T above, then the clamped steps
+          int k0 = kb;
+          {
+            const T* xp = xc + (kb + lane / 16) * QP;
+            const double* wp = wc + (kb + lane / 16) * R;
+            for (; k0 + 32 <= ke; k0 += 32) {
+              T xv[8];
+              double bv[8], xd[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) { xv[u] = xp[4 * u * QP]; bv[u] = wp[4 * u * R]; }
+#pragma unroll
+              for (int u = 0; u < 8; ++u) xd[u] = (double)xv[u];
+              __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+              for (int u = 0; u < 8; u += 2) {
+                acc0 = mfma64(xd[u], bv[u], acc0);
+                acc1 = mfma64(xd[u + 1], bv[u + 1], acc1);
+              }
+              __builtin_amdgcn_sched_barrier(0);
+              xp += 32 * QP;
+              wp += 32 * R;
+            }
+          }
+          for (; k0 < ke; k0 += 8) {
             const int pr = k0 + lane / 16, pr2 = pr + 4;
             const int pc = pr < ke ? pr : ke - 1, pc2 = pr2 < ke ? pr2 : ke - 1;
             const double x0 = (double)xc[pc * QP], x1 = (double)xc[pc2 * QP];
@@ -700,8 +756,12 @@ hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int 
                     : (const void*)als_coop_kernel<float, RM, false>)
   if (R <= 8)
     OCTEN_ALS_PICK(8);
+  else if (R <= 12)
+    OCTEN_ALS_PICK(12);
   else if (R <= 16)
     OCTEN_ALS_PICK(16);
+  else if (R <= 24)
+    OCTEN_ALS_PICK(24);
   else
     OCTEN_ALS_PICK(32);
 #undef OCTEN_ALS_PICK
