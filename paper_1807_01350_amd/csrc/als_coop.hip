@@ -242,34 +242,54 @@ __device__ void gram_all(const double* Fm, int n, int R, double* G) {
   }
 }
 
-// out(q, :) = M(q, :) Ginv for q < n (all threads; independent loads).
+// out(q, :) = M(q, :) Ginv for q < n (all threads).  The sum over k runs in
+// blocks of 8 whose sixteen loads are issued together (indices clamped, the
+// terms past R skipped); even and odd k go to two accumulators.
 __device__ void apply_inverse(const double* M, const double* Ginv, double* out, int n, int R) {
   const FastDiv fr(R);
   for (int e = threadIdx.x; e < n * R; e += NT) {
     const int q = fr.div(e), r = e - q * R;
     const double* m = M + q * R;
     double s0 = 0.0, s1 = 0.0;
-    int k = 0;
-    for (; k + 1 < R; k += 2) {
-      s0 = fma(m[k], Ginv[k * R + r], s0);
-      s1 = fma(m[k + 1], Ginv[(k + 1) * R + r], s1);
+    for (int k0 = 0; k0 < R; k0 += 8) {
+      double mv[8], gv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + u < R ? k0 + u : R - 1;
+        mv[u] = m[k];
+        gv[u] = Ginv[k * R + r];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; u += 2) {
+        if (k0 + u < R) s0 = fma(mv[u], gv[u], s0);
+        if (k0 + u + 1 < R) s1 = fma(mv[u + 1], gv[u + 1], s1);
+      }
     }
-    if (k < R) s0 = fma(m[k], Ginv[k * R + r], s0);
     out[e] = s0 + s1;
   }
 }
 
-// Column 2-norms of F (n x R): lam[r] (0 replaced by 1); one wave per column,
-// lanes split the rows, butterfly sum.
-__device__ void col_norms(const double* Fm, int n, int R, double* lam) {
-  const int wave = threadIdx.x / 64, lane = threadIdx.x & 63;
-  for (int r = wave; r < R; r += NT / 64) {
-    double s = 0.0;
-    for (int q = lane; q < n; q += 64) s = fma(Fm[q * R + r], Fm[q * R + r], s);
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) {
+// Column 2-norms of F (n x R): lam[r] (0 replaced by 1) and rlam[r] =
+// 1 / lam[r]; sixteen lanes per column split the rows (two accumulators),
+// then a butterfly within the sixteen; all columns in one round (R <= 32).
+__device__ void col_norms(const double* Fm, int n, int R, double* lam, double* rlam) {
+  const int grp = threadIdx.x / 16, sub = threadIdx.x & 15;
+  for (int r = grp; r < R; r += NT / 16) {
+    double s0 = 0.0, s1 = 0.0;
+    int q = sub;
+    for (; q + 16 < n; q += 32) {
+      const double a = Fm[q * R + r], b = Fm[(q + 16) * R + r];
+      s0 = fma(a, a, s0);
+      s1 = fma(b, b, s1);
+    }
+    if (q < n) s0 = fma(Fm[q * R + r], Fm[q * R + r], s0);
+    double s = s0 + s1;
+    for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (sub == 0) {
       const double nr = sqrt(s);
-      lam[r] = nr > 0.0 ? nr : 1.0;
+      const double l = nr > 0.0 ? nr : 1.0;
+      lam[r] = l;
+      rlam[r] = 1.0 / l;
     }
   }
 }
@@ -327,7 +347,8 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   double* BtB = AtA + RR;
   double* CtC = BtB + RR;
   double* lamv = CtC + RR;                    // [MAXR]
-  double* scr = lamv + MAXR;                  // [NT]
+  double* rlam = lamv + MAXR;                 // [MAXR] 1 / lamv
+  double* scr = rlam + MAXR;                  // [NT]
   const T* Xp = (const T*)g.Y + (int64_t)p * Q2 * Q;
   const T* Xs;                                // [na * Q][QP]
   if constexpr (GX) {
@@ -536,11 +557,13 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       wave_sync();
       if (lane < R) {
         const double n = sqrt(AtA[lane * R + lane]);
-        lamv[lane] = n > 0.0 ? n : 1.0;
+        const double l = n > 0.0 ? n : 1.0;
+        lamv[lane] = l;
+        rlam[lane] = 1.0 / l;
       }
       wave_sync();
       for (int e = lane; e < RR; e += 64) {
-        AtA[e] /= lamv[fR.div(e)] * lamv[fR.mod(e)];
+        AtA[e] *= rlam[fR.div(e)] * rlam[fR.mod(e)];
         G[e] = AtA[e] * CtC[e];
       }
       wave_sync();
@@ -549,15 +572,15 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       // M2 was formed with the unnormalised A: B = (M2 / lambda_A) G2^{-1},
       // so row k of the inverse takes the factor 1 / lambda_A(k)
       wave_sync();
-      for (int e = lane; e < RR; e += 64) Gi[e] /= lamv[fR.div(e)];
+      for (int e = lane; e < RR; e += 64) Gi[e] *= rlam[fR.div(e)];
     }
     __syncthreads();
-    for (int e = tid; e < na * R; e += NT) Al[e] /= lamv[fR.mod(e)];
+    for (int e = tid; e < na * R; e += NT) Al[e] *= rlam[fR.mod(e)];
     apply_inverse(Mf, Gi, Bf, Q, R);
     __syncthreads();
-    col_norms(Bf, Q, R, lamv);
+    col_norms(Bf, Q, R, lamv, rlam);
     __syncthreads();
-    for (int e = tid; e < QR; e += NT) Bf[e] /= lamv[fR.mod(e)];
+    for (int e = tid; e < QR; e += NT) Bf[e] *= rlam[fR.mod(e)];
     __syncthreads();
     // W(pair, r) = A(a, r) B(b, r) into Ts; B'B
     gram_all(Bf, Q, R, BtB);
@@ -662,9 +685,9 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     // ------------------------------------------------ mode 3 solve (C)
     apply_inverse(Mf, Gi, Cf, Q, R);
     __syncthreads();
-    col_norms(Cf, Q, R, lamv);
+    col_norms(Cf, Q, R, lamv, rlam);
     __syncthreads();
-    for (int e = tid; e < QR; e += NT) Cf[e] /= lamv[fR.mod(e)];
+    for (int e = tid; e < QR; e += NT) Cf[e] *= rlam[fR.mod(e)];
     __syncthreads();
     gram_all(Cf, Q, R, CtC);
     __syncthreads();
@@ -721,7 +744,7 @@ size_t als_coop_lds_bytes(int Q, int R, int NW, bool x_f64, bool slab_global) {
   const int na_max = (Q + NW - 1) / NW;
   const size_t QR = (size_t)Q * R;
   const size_t dbl = (size_t)pad_pairs(Q, NW) * R + 4 * QR + (size_t)na_max * R +
-                     5 * (size_t)R * R + MAXR + NT;
+                     5 * (size_t)R * R + 2 * MAXR + NT;
   return dbl * 8 + (slab_global ? 0 : (size_t)na_max * Q * (Q + 1) * (x_f64 ? 8 : 4));
 }
 
