@@ -330,15 +330,20 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   const int a0 = (int)((int64_t)w * Q / NW), a1 = (int)((int64_t)(w + 1) * Q / NW);
   const int na = a1 - a0;
   const int npair = na * Q;                   // rows (a, b) of the slab
-  const int QP = GX ? Q : Q + 1;              // slab row stride (LDS: padded)
+  // LDS slab: rows padded to npair_pad and columns to QPAD (a multiple of
+  // 32) with zeros, plus one column against bank conflicts, so that the MFMA
+  // loops run whole groups of 32 without clamping (Cf carries QPAD rows, Ts
+  // npair_pad rows, zero past the data)
+  const int QPAD = ((Q + 31) / 32) * 32;
+  const int QP = GX ? Q : QPAD + 1;           // slab row stride
   const int RT = (R + 15) / 16;               // 16-wide tiles over r
   const FastDiv fR(R), fQ(Q);
   const int64_t Q2 = (int64_t)Q * Q;
 
   double* Ts = (double*)smem;                 // [npair_pad][R]  T, then W
   double* Bf = Ts + (int64_t)g.npair_pad * R; // [Q][R]
-  double* Cf = Bf + QR;
-  double* Mf = Cf + QR;                       // reduced M2 / M3
+  double* Cf = Bf + QR;                       // [QPAD][R]
+  double* Mf = Cf + QPAD * R;                 // reduced M2 / M3
   double* Ml = Mf + QR;                       // [Q][R] scratch (M1 rows)
   double* Al = Ml + QR;                       // [na_max][R]
   double* G = Al + g.na_max * R;              // [R][R]
@@ -350,15 +355,20 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   double* rlam = lamv + MAXR;                 // [MAXR] 1 / lamv
   double* scr = rlam + MAXR;                  // [NT]
   const T* Xp = (const T*)g.Y + (int64_t)p * Q2 * Q;
-  const T* Xs;                                // [na * Q][QP]
+  const T* Xs;                                // [na * Q][QP] (LDS: [npair_pad][QP])
   if constexpr (GX) {
     Xs = Xp + (int64_t)a0 * Q2;
   } else {
     T* xl = (T*)(scr + NT);
-    for (int64_t e = tid; e < (int64_t)npair * Q; e += NT)
-      xl[(e / Q) * QP + e % Q] = Xp[(int64_t)a0 * Q2 + e];
+    const FastDiv fQP(QP);
+    for (int e = tid; e < g.npair_pad * QP; e += NT) {
+      const int row = fQP.div(e), col = e - row * QP;
+      xl[e] = (row < npair && col < Q) ? Xp[(int64_t)a0 * Q2 + (int64_t)row * Q + col] : (T)0;
+    }
     Xs = xl;
   }
+  for (int e = npair * R + tid; e < g.npair_pad * R; e += NT) Ts[e] = 0.0;
+  for (int e = QR + tid; e < QPAD * R; e += NT) Cf[e] = 0.0;
   const double* F0 = g.init + (int64_t)p * 3 * QR;
   for (int e = tid; e < na * R; e += NT) Al[e] = F0[a0 * R + e];
   for (int e = tid; e < QR; e += NT) { Bf[e] = F0[QR + e]; Cf[e] = F0[2 * QR + e]; }
@@ -434,17 +444,15 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
         const int rr = rt * 16 + lane % 16;
         f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
         const bool okc = rr < R;
-        const T* xr = Xs + (pr < npair ? pr : npair - 1) * QP;
         const double* cr = Cf + (okc ? rr : R - 1);
-        // whole groups of 32 columns: all sixteen loads first, then the
-        // conversions, then the eight MFMAs (a VALU instruction issued
-        // between MFMAs of one wavefront waits for them); same order of
-        // accumulation as the step loop below
-        int c0 = 0;
-        {
-          const T* xp = xr + lane / 16;
+        if constexpr (!GX) {
+          // LDS slab padded with zeros (rows and columns) and Cf with zero
+          // rows: groups of 32 columns (four steps of 8), all sixteen loads,
+          // then the conversions, then the eight MFMAs (a VALU instruction
+          // issued between MFMAs of one wavefront waits for them)
+          const T* xp = Xs + pr * QP + lane / 16;
           const double* cp = cr + (lane / 16) * R;
-          for (; c0 + 32 <= Q; c0 += 32) {
+          for (int c0 = 0; c0 < Q; c0 += 32) {
             T xv[8];
             double bv[8], xd[8];
 #pragma unroll
@@ -461,16 +469,44 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
             xp += 32;
             cp += 32 * R;
           }
-        }
-        // the rest: indices clamped into range and the k tail zeroed after
-        // the load (no branches around the loads)
-        for (; c0 < Q; c0 += 8) {
-          const int c = c0 + lane / 16, c2 = c + 4;
-          const int cc = c < Q ? c : Q - 1, cc2 = c2 < Q ? c2 : Q - 1;
-          const double x0 = (double)xr[cc], x1 = (double)xr[cc2];
-          const double b0 = cr[cc * R], b1 = cr[cc2 * R];
-          acc0 = mfma64(c < Q ? x0 : 0.0, b0, acc0);
-          acc1 = mfma64(c2 < Q ? x1 : 0.0, b1, acc1);
+        } else {
+          const T* xr = Xs + (pr < npair ? pr : npair - 1) * QP;
+          // whole groups of 32 columns: all sixteen loads first, then the
+          // conversions, then the eight MFMAs (a VALU instruction issued
+          // between MFMAs of one wavefront waits for them); same order of
+          // accumulation as the step loop below
+          int c0 = 0;
+          {
+            const T* xp = xr + lane / 16;
+            const double* cp = cr + (lane / 16) * R;
+            for (; c0 + 32 <= Q; c0 += 32) {
+              T xv[8];
+              double bv[8], xd[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) { xv[u] = xp[4 * u]; bv[u] = cp[4 * u * R]; }
+#pragma unroll
+              for (int u = 0; u < 8; ++u) xd[u] = (double)xv[u];
+              __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+              for (int u = 0; u < 8; u += 2) {
+                acc0 = mfma64(xd[u], bv[u], acc0);
+                acc1 = mfma64(xd[u + 1], bv[u + 1], acc1);
+              }
+              __builtin_amdgcn_sched_barrier(0);
+              xp += 32;
+              cp += 32 * R;
+            }
+          }
+          // the rest: indices clamped into range and the k tail zeroed after
+          // the load (no branches around the loads)
+          for (; c0 < Q; c0 += 8) {
+            const int c = c0 + lane / 16, c2 = c + 4;
+            const int cc = c < Q ? c : Q - 1, cc2 = c2 < Q ? c2 : Q - 1;
+            const double x0 = (double)xr[cc], x1 = (double)xr[cc2];
+            const double b0 = cr[cc * R], b1 = cr[cc2 * R];
+            acc0 = mfma64(c < Q ? x0 : 0.0, b0, acc0);
+            acc1 = mfma64(c2 < Q ? x1 : 0.0, b1, acc1);
+          }
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -602,7 +638,10 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       const int ctiles = (Q + 15) / 16, ntl = ctiles * RT;
       constexpr int NMW = NT / 64 - 1;
       const int ksp = 2 * ntl <= NMW ? 2 : 1;
-      const int kh = ksp == 1 ? npair : ((npair + 15) / 16) * 8;
+      // pair range: padded to a multiple of 32 in LDS (zero rows), halves
+      // cut at a multiple of 32; from global memory, the exact range
+      const int npp = GX ? npair : ((npair + 31) / 32) * 32;
+      const int kh = ksp == 1 ? npp : (GX ? ((npair + 15) / 16) * 8 : ((npp / 32 + 1) / 2) * 32);
       f64x4 keep = {0.0, 0.0, 0.0, 0.0};
       int keep_tile = -1;
       if (wave == 0) {
@@ -610,20 +649,18 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       } else {
         for (int item = wave - 1; item < ntl * ksp; item += NMW) {
           const int tt = item % ntl, part = item / ntl;
-          const int kb = part * kh, ke = kb + kh < npair ? kb + kh : npair;
+          const int kb = part * kh, ke = kb + kh < npp ? kb + kh : npp;
           const int ct = tt / RT, rt = tt % RT;
           const int c = ct * 16 + lane % 16;
           const int rr = rt * 16 + lane % 16;
           f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
           const bool okr = rr < R;
-          const T* xc = Xs + (c < Q ? c : Q - 1);
           const double* wc = Ts + (okr ? rr : R - 1);
-          // whole groups of 32 pairs as for T above, then the clamped steps
-          int k0 = kb;
-          {
-            const T* xp = xc + (kb + lane / 16) * QP;
+          if constexpr (!GX) {
+            // zero-padded LDS slab and W: groups of 32 pairs as for T
+            const T* xp = Xs + c + (kb + lane / 16) * QP;
             const double* wp = wc + (kb + lane / 16) * R;
-            for (; k0 + 32 <= ke; k0 += 32) {
+            for (int k0 = kb; k0 < ke; k0 += 32) {
               T xv[8];
               double bv[8], xd[8];
 #pragma unroll
@@ -640,14 +677,39 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
               xp += 32 * QP;
               wp += 32 * R;
             }
-          }
-          for (; k0 < ke; k0 += 8) {
-            const int pr = k0 + lane / 16, pr2 = pr + 4;
-            const int pc = pr < ke ? pr : ke - 1, pc2 = pr2 < ke ? pr2 : ke - 1;
-            const double x0 = (double)xc[pc * QP], x1 = (double)xc[pc2 * QP];
-            const double b0 = wc[pc * R], b1 = wc[pc2 * R];
-            acc0 = mfma64(pr < ke ? x0 : 0.0, b0, acc0);
-            acc1 = mfma64(pr2 < ke ? x1 : 0.0, b1, acc1);
+          } else {
+            const T* xc = Xs + (c < Q ? c : Q - 1);
+            // whole groups of 32 pairs as for T above, then the clamped steps
+            int k0 = kb;
+            {
+              const T* xp = xc + (kb + lane / 16) * QP;
+              const double* wp = wc + (kb + lane / 16) * R;
+              for (; k0 + 32 <= ke; k0 += 32) {
+                T xv[8];
+                double bv[8], xd[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) { xv[u] = xp[4 * u * QP]; bv[u] = wp[4 * u * R]; }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) xd[u] = (double)xv[u];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < 8; u += 2) {
+                  acc0 = mfma64(xd[u], bv[u], acc0);
+                  acc1 = mfma64(xd[u + 1], bv[u + 1], acc1);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                xp += 32 * QP;
+                wp += 32 * R;
+              }
+            }
+            for (; k0 < ke; k0 += 8) {
+              const int pr = k0 + lane / 16, pr2 = pr + 4;
+              const int pc = pr < ke ? pr : ke - 1, pc2 = pr2 < ke ? pr2 : ke - 1;
+              const double x0 = (double)xc[pc * QP], x1 = (double)xc[pc2 * QP];
+              const double b0 = wc[pc * R], b1 = wc[pc2 * R];
+              acc0 = mfma64(pr < ke ? x0 : 0.0, b0, acc0);
+              acc1 = mfma64(pr2 < ke ? x1 : 0.0, b1, acc1);
+            }
           }
           const f64x4 acc = acc0 + acc1;
           if (ksp == 2 && part == 0) {
@@ -737,15 +799,16 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
 
 static int pad_pairs(int Q, int NW) {
   const int na_max = (Q + NW - 1) / NW;
-  return ((na_max * Q + 15) / 16) * 16;
+  return ((na_max * Q + 31) / 32) * 32;
 }
 
 size_t als_coop_lds_bytes(int Q, int R, int NW, bool x_f64, bool slab_global) {
   const int na_max = (Q + NW - 1) / NW;
   const size_t QR = (size_t)Q * R;
-  const size_t dbl = (size_t)pad_pairs(Q, NW) * R + 4 * QR + (size_t)na_max * R +
+  const size_t QPAD = (size_t)((Q + 31) / 32) * 32;
+  const size_t dbl = (size_t)pad_pairs(Q, NW) * R + 3 * QR + QPAD * R + (size_t)na_max * R +
                      5 * (size_t)R * R + 2 * MAXR + NT;
-  return dbl * 8 + (slab_global ? 0 : (size_t)na_max * Q * (Q + 1) * (x_f64 ? 8 : 4));
+  return dbl * 8 + (slab_global ? 0 : (size_t)pad_pairs(Q, NW) * (QPAD + 1) * (x_f64 ? 8 : 4));
 }
 
 hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int R, int NW,
