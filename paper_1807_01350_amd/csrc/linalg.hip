@@ -449,6 +449,70 @@ __global__ void rowdot_reduce_kernel(int64_t nrows, int ncols, int nsplit,
   *o = beta != 0.0 ? alpha * sum + beta * *o : alpha * sum;
 }
 
+typedef double tg_f64x4 __attribute__((ext_vector_type(4)));
+constexpr int TG_KC = 128;   // k rows of B per LDS chunk
+
+// out[i][r] = alpha sum_k A[i][k] B[k][r] (+ beta out[i][r]) for a tall A
+// (n x K, row stride lda, unit column stride) and B (K x R, row stride ldb),
+// R <= 32, on v_mfma_f64_16x16x4f64: each wavefront owns 16 rows of A and
+// both 16-column halves of the output; the four wavefronts of a workgroup
+// share a chunk of TG_KC rows of B in LDS (zero past K and past R, row
+// padded to 33 against bank conflicts).  A is read once, in the MFMA
+// operand layout (16 rows x 4 consecutive k per load, clamped into range:
+// the zero rows of the B chunk cancel the clamped terms).  Per group of 8
+// steps, all operand loads are issued before the MFMAs.
+__global__ __launch_bounds__(256) void tall_gemm_kernel(int64_t n, int R, int64_t K,
+                                                        const double* __restrict__ A, int64_t lda,
+                                                        const double* __restrict__ B, int64_t ldb,
+                                                        double alpha, double beta,
+                                                        double* __restrict__ out, int64_t ldo) {
+  __shared__ double Bs[TG_KC][33];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid & 63;
+  const int kq = lane / 16, nl = lane % 16;
+  const int64_t i0 = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t row = i0 + nl;
+  const double* a = A + (row < n ? row : n - 1) * lda;
+  const bool two = R > 16;
+  tg_f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t kc = 0; kc < K; kc += TG_KC) {
+    __syncthreads();
+    for (int e = tid; e < TG_KC * 32; e += 256) {
+      const int kk = e >> 5, rr = e & 31;
+      const int64_t k = kc + kk;
+      Bs[kk][rr] = (k < K && rr < R) ? B[k * ldb + rr] : 0.0;
+    }
+    __syncthreads();
+    const int steps = K - kc < TG_KC ? (int)(K - kc) : TG_KC;
+    for (int s0 = 0; s0 < steps; s0 += 32) {
+      double av[8], b0[8], b1[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t k = kc + s0 + 4 * u + kq;
+        av[u] = a[k < K ? k : K - 1];
+        b0[u] = Bs[s0 + 4 * u + kq][nl];
+        b1[u] = Bs[s0 + 4 * u + kq][16 + nl];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b0[u], acc0, 0, 0, 0);
+        if (two) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b1[u], acc1, 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // element i of lane l holds D[l/16 + 4 i][l%16]
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t orow = i0 + kq + 4 * i;
+    if (orow >= n) continue;
+    double* o = out + orow * ldo;
+    if (nl < R) o[nl] = beta != 0.0 ? alpha * acc0[i] + beta * o[nl] : alpha * acc0[i];
+    if (two && 16 + nl < R)
+      o[16 + nl] = beta != 0.0 ? alpha * acc1[i] + beta * o[16 + nl] : alpha * acc1[i];
+  }
+}
+
 }  // namespace
 
 hipError_t rowdot(hipStream_t s, int64_t nrows, int ncols, int64_t K, const double* A, int64_t sai,
@@ -456,6 +520,13 @@ hipError_t rowdot(hipStream_t s, int64_t nrows, int ncols, int64_t K, const doub
                   double alpha, double beta, double* out, int64_t ldo, double* work,
                   int64_t work_len) {
   if (nrows <= 0 || ncols <= 0) return hipSuccess;
+  if (sak == 1 && sbr == 1 && !d && ncols <= 32 && nrows >= 16384 && K >= 32) {
+    // tall product with unit inner strides and enough 64-row blocks to fill
+    // the GPU: FP64 MFMA, A streamed once
+    hipLaunchKernelGGL(tall_gemm_kernel, dim3((unsigned)((nrows + 63) / 64)), dim3(256), 0, s,
+                       nrows, ncols, K, A, sai, B, sbk, alpha, beta, out, ldo);
+    return hipGetLastError();
+  }
   const int nblk = (ncols + 31) / 32;
   // split the long index when there are too few rows to fill the GPU; the
   // partial sums are added in split order by a second kernel

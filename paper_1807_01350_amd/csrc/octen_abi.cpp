@@ -713,16 +713,16 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, i
                    h->rd_work, octen_ctx::RD_WORK));
   HIPCHK(h, rowdot(s, J, R, M1, h->OpB, M1, 1, h->rhs + (int64_t)M1 * R, R, 1, nullptr, 1.0, 0.0,
                    h->Braw, R, h->rd_work, octen_ctx::RD_WORK));
-  HIPCHK(h, rec_canon(s, I, R, h->Araw, h->Ac, h->ka));
-  HIPCHK(h, rec_canon(s, J, R, h->Braw, h->Bc, h->kb));
+  HIPCHK(h, rec_canon(s, I, R, h->Araw, h->Ac, h->ka, h->rd_work, octen_ctx::RD_WORK));
+  HIPCHK(h, rec_canon(s, J, R, h->Braw, h->Bc, h->kb, h->rd_work, octen_ctx::RD_WORK));
   if (h->have_prev) {
     HIPCHK(h, rowdot(s, R, R, I, h->Ac, 1, R, h->Aprev, R, 1, nullptr, 1.0, 0.0, h->cross, R, h->rd_work, octen_ctx::RD_WORK));
     HIPCHK(h, rowdot(s, R, R, J, h->Bc, 1, R, h->Bprev, R, 1, nullptr, 1.0, 0.0, h->cross + R * R,
                      R, h->rd_work, octen_ctx::RD_WORK));
-    HIPCHK(h, rec_col_norms(s, I, R, h->Ac, h->norms));
-    HIPCHK(h, rec_col_norms(s, I, R, h->Aprev, h->norms + R));
-    HIPCHK(h, rec_col_norms(s, J, R, h->Bc, h->norms + 2 * R));
-    HIPCHK(h, rec_col_norms(s, J, R, h->Bprev, h->norms + 3 * R));
+    HIPCHK(h, rec_col_norms(s, I, R, h->Ac, h->norms, h->rd_work, octen_ctx::RD_WORK));
+    HIPCHK(h, rec_col_norms(s, I, R, h->Aprev, h->norms + R, h->rd_work, octen_ctx::RD_WORK));
+    HIPCHK(h, rec_col_norms(s, J, R, h->Bc, h->norms + 2 * R, h->rd_work, octen_ctx::RD_WORK));
+    HIPCHK(h, rec_col_norms(s, J, R, h->Bprev, h->norms + 3 * R, h->rd_work, octen_ctx::RD_WORK));
     HIPCHK(h, rec_tmatch(s, R, h->cross, h->norms, h->tperm, h->tsign, h->tmargin));
   }
   // temporal rows (reading: incremental solve with the carried history removed)

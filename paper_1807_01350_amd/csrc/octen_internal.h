@@ -30,7 +30,9 @@ hipError_t spd_invert(hipStream_t s, double* A, int n, double* work, int* info);
 
 // out(i, r) = alpha * sum_k A(i,k) d(k) B(k,r) + beta * out(i, r), i < nrows,
 // r < ncols; A(i,k) = A[i*sai + k*sak], B(k,r) = B[k*sbk + r*sbr]; d may be
-// null.  One wavefront per row and block of 32 columns (small outputs, long k).
+// null.  Tall products with unit inner strides (sak = sbr = 1, no d, at least
+// 16384 rows, ncols <= 32) run on FP64 MFMA with A streamed once; otherwise
+// one wavefront per row and block of 32 columns (small outputs, long k).
 // work (optional, work_len doubles): partial sums for splitting K when there
 // are few rows; without it, one wavefront covers all of K.
 hipError_t rowdot(hipStream_t s, int64_t nrows, int ncols, int64_t K, const double* A, int64_t sai,
@@ -125,10 +127,12 @@ hipError_t rec_align(hipStream_t s, int P, int Q, int R, int S, const double* F,
 hipError_t rec_stack(hipStream_t s, int P, int Q, int R, int S, const double* aligned, double* rhs);
 // Canonical columns: out = X / (norm * sign of largest-magnitude entry);
 // kfac[r] = norm * sign.  X, out: [n][R].
-hipError_t rec_canon(hipStream_t s, int64_t n, int R, const double* X, double* out, double* kfac);
+hipError_t rec_canon(hipStream_t s, int64_t n, int R, const double* X, double* out, double* kfac,
+                     double* work, int64_t work_len);
 // Pairing with the previous canonical factors: cross [2][R][R] = (Ac^T Ap, Bc^T Bp),
 // norms [4][R] = column norms of Ac, Ap, Bc, Bp.  Writes tperm, tsign.
-hipError_t rec_col_norms(hipStream_t s, int64_t n, int R, const double* X, double* norms);
+hipError_t rec_col_norms(hipStream_t s, int64_t n, int R, const double* X, double* norms,
+                         double* work, int64_t work_len);
 hipError_t rec_tmatch(hipStream_t s, int R, const double* cross, const double* norms, int* tperm,
                       double* tsign, double* tmargin);
 // Hcur = H[:, tperm] * tsign; rhs_c = rhs2 - Hcur / kappa; kappa = ka * kb.

@@ -191,7 +191,7 @@ __global__ void stack_kernel(int P, int Q, int R, int S, const double* __restric
 }
 
 // Column r of X [n][R]: 2-norm and first index of the largest |x|; one block
-// per column.
+// per column (short columns: one launch).
 __device__ void column_stats(int64_t n, int R, const double* X, int r, double* s_sum, double* s_val,
                              int64_t* s_idx, double* nrm, double* signv) {
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -243,6 +243,85 @@ __global__ __launch_bounds__(256) void colnorm_kernel(int64_t n, int R, const do
   double nrm, sv;
   column_stats(n, R, X, r, s_sum, s_val, s_idx, &nrm, &sv);
   if (threadIdx.x == 0) norms[r] = nrm;
+}
+
+// Column statistics of X [n][R] (R <= 32) in two passes.  Pass 1: block b
+// takes rows [b rows_per, (b + 1) rows_per); its threads form groups of R,
+// thread (g, r) reads column r of rows g, g + ngrp, ... (a group reads whole
+// rows: coalesced); per block and column it keeps the sum of squares and the
+// largest |x| with its first row, combining the groups in order.
+// part: [2][G][R] f64 (sums, largest |x|), pidx: [G][R] rows.
+__global__ __launch_bounds__(256) void colstat_part_kernel(int64_t n, int R, int64_t rows_per,
+                                                           const double* __restrict__ X,
+                                                           double* __restrict__ part,
+                                                           int64_t* __restrict__ pidx, int G) {
+  __shared__ double s_sum[256], s_val[256];
+  __shared__ int64_t s_idx[256];
+  const int tid = threadIdx.x, ngrp = 256 / R;
+  const int grp = tid / R, r = tid - grp * R;
+  const int64_t i0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t i1 = i0 + rows_per < n ? i0 + rows_per : n;
+  double sum = 0.0, best = -1.0;
+  int64_t bi = INT64_MAX;
+  if (grp < ngrp) {
+    for (int64_t i = i0 + grp; i < i1; i += ngrp) {
+      const double v = X[i * R + r];
+      sum = fma(v, v, sum);
+      const double av = fabs(v);
+      if (av > best) { best = av; bi = i; }
+    }
+  }
+  s_sum[tid] = sum;
+  s_val[tid] = best;
+  s_idx[tid] = bi;
+  __syncthreads();
+  if (tid < R) {
+    double ss = 0.0, bv = -1.0;
+    int64_t bx = INT64_MAX;
+    for (int g = 0; g < ngrp; ++g) {
+      const int t = g * R + tid;
+      ss += s_sum[t];
+      if (s_val[t] > bv || (s_val[t] == bv && s_idx[t] < bx)) { bv = s_val[t]; bx = s_idx[t]; }
+    }
+    part[(int64_t)blockIdx.x * R + tid] = ss;
+    part[((int64_t)G + blockIdx.x) * R + tid] = bv;
+    pidx[(int64_t)blockIdx.x * R + tid] = bx;
+  }
+}
+
+// Pass 2 (one thread per column, blocks in order): 2-norm; with kfac, also
+// kfac[r] = norm (1 when zero) times the sign of the first largest-magnitude
+// entry.
+__global__ void colstat_final_kernel(int64_t n, int R, int G, const double* __restrict__ part,
+                                     const int64_t* __restrict__ pidx,
+                                     const double* __restrict__ X, double* __restrict__ norms,
+                                     double* __restrict__ kfac) {
+  const int r = threadIdx.x;
+  if (r >= R) return;
+  double ss = 0.0, bv = -1.0;
+  int64_t bx = INT64_MAX;
+  for (int b = 0; b < G; ++b) {
+    ss += part[(int64_t)b * R + r];
+    const double v = part[((int64_t)G + b) * R + r];
+    const int64_t x = pidx[(int64_t)b * R + r];
+    if (v > bv || (v == bv && x < bx)) { bv = v; bx = x; }
+  }
+  const double nrm = sqrt(ss);
+  if (norms) norms[r] = nrm;
+  if (kfac) {
+    const double sv = bx < n ? X[bx * R + r] : 0.0;
+    const double sg = sv > 0.0 ? 1.0 : (sv < 0.0 ? -1.0 : 1.0);
+    kfac[r] = (nrm > 0.0 ? nrm : 1.0) * sg;
+  }
+}
+
+// out[i][r] = X[i][r] / kfac[r].
+__global__ __launch_bounds__(256) void colscale_kernel(int64_t n, int R, const double* __restrict__ X,
+                                                       const double* __restrict__ kfac,
+                                                       double* __restrict__ out) {
+  const int64_t total = n * R;
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256)
+    out[e] = X[e] / kfac[e % R];
 }
 
 // cross: [2][R][R] = Ac^T Ap and Bc^T Bp; norms: [4][R] = |Ac|, |Ap|, |Bc|, |Bp|.
@@ -353,14 +432,58 @@ hipError_t rec_stack(hipStream_t s, int P, int Q, int R, int S, const double* al
   return hipGetLastError();
 }
 
-hipError_t rec_canon(hipStream_t s, int64_t n, int R, const double* X, double* out, double* kfac) {
-  hipLaunchKernelGGL(canon_kernel, dim3(R), dim3(256), 0, s, n, R, X, out, kfac);
+// Blocks of pass 1: at least 64 rows each, at most 256 blocks (and within
+// the work buffer: 3 G R values).
+static int colstat_blocks(int64_t n, int R, int64_t work_len, int64_t* rows_per) {
+  int64_t rp = (n + 255) / 256;
+  if (rp < 64) rp = 64;
+  int64_t G = (n + rp - 1) / rp;
+  while (G > 1 && 3 * G * R > work_len) {
+    rp *= 2;
+    G = (n + rp - 1) / rp;
+  }
+  *rows_per = rp;
+  return (int)(G < 1 ? 1 : G);
+}
+
+static hipError_t colstat(hipStream_t s, int64_t n, int R, const double* X, double* norms,
+                          double* kfac, double* work, int64_t work_len) {
+  if (R > 32 || 3 * (int64_t)R > work_len) return hipErrorInvalidValue;
+  int64_t rows_per;
+  const int G = colstat_blocks(n, R, work_len, &rows_per);
+  double* part = work;
+  int64_t* pidx = (int64_t*)(work + 2 * (int64_t)G * R);
+  hipLaunchKernelGGL(colstat_part_kernel, dim3(G), dim3(256), 0, s, n, R, rows_per, X, part, pidx, G);
+  hipLaunchKernelGGL(colstat_final_kernel, dim3(1), dim3(64), 0, s, n, R, G, part, pidx, X, norms,
+                     kfac);
   return hipGetLastError();
 }
 
-hipError_t rec_col_norms(hipStream_t s, int64_t n, int R, const double* X, double* norms) {
-  hipLaunchKernelGGL(colnorm_kernel, dim3(R), dim3(256), 0, s, n, R, X, norms);
+// Columns shorter than this take the one-launch kernels (one block per column).
+constexpr int64_t COLSTAT_SHORT = 16384;
+
+hipError_t rec_canon(hipStream_t s, int64_t n, int R, const double* X, double* out, double* kfac,
+                     double* work, int64_t work_len) {
+  if (n < COLSTAT_SHORT) {
+    hipLaunchKernelGGL(canon_kernel, dim3(R), dim3(256), 0, s, n, R, X, out, kfac);
+    return hipGetLastError();
+  }
+  hipError_t e = colstat(s, n, R, X, nullptr, kfac, work, work_len);
+  if (e != hipSuccess) return e;
+  const int64_t total = n * R;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(colscale_kernel, dim3((unsigned)blocks), dim3(256), 0, s, n, R, X, kfac, out);
   return hipGetLastError();
+}
+
+hipError_t rec_col_norms(hipStream_t s, int64_t n, int R, const double* X, double* norms,
+                         double* work, int64_t work_len) {
+  if (n < COLSTAT_SHORT) {
+    hipLaunchKernelGGL(colnorm_kernel, dim3(R), dim3(256), 0, s, n, R, X, norms);
+    return hipGetLastError();
+  }
+  return colstat(s, n, R, X, norms, nullptr, work, work_len);
 }
 
 hipError_t rec_tmatch(hipStream_t s, int R, const double* cross, const double* norms, int* tperm,

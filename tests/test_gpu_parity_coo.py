@@ -158,17 +158,21 @@ def test_coo_rejects_bad_coordinates_then_recovers():
     eng.close()
 
 
-def test_coo_stream_update_and_fit_f64():
+@pytest.mark.parametrize("shape", [(700, 650, 4, 5, 30, 3, 1500, 25),
+                                   (20000, 17000, 3, 3, 12, 2, 3000, 26)],
+                         ids=["small", "tall_recovery"])
+def test_coo_stream_update_and_fit_f64(shape):
     """Three sparse batches through compress -> update -> ALS -> recover, and
-    the sparse fitness identity, against the oracle on the same inputs."""
+    the sparse fitness identity, against the oracle on the same inputs.  The
+    second shape has enough rows for the MFMA product of the mode-1 and
+    mode-2 recovery and for the many-block column statistics."""
     import torch
     from oracle import OctenOracle, fit_coo_identity
     from paper_1807_01350_amd import octen as oc
-    I, J, R, P, Q, S = 700, 650, 4, 5, 30, 3
+    I, J, R, P, Q, S, per, cid = shape
     batches = (20, 8, 6)
-    cid = 25
     K = sum(batches)
-    _, _, _, k, i, j, v = synth.coo_stream(I, J, K, R, 1500, 0.01, cid)
+    _, _, _, k, i, j, v = synth.coo_stream(I, J, K, R, per, 0.01, cid)
     U, V = synth.compression_UV(I, J, P, Q, S, cid)
     M1 = S + P * (Q - S)
     init = synth.als_init(P, Q, R, cid)
@@ -214,8 +218,12 @@ def test_coo_stream_update_and_fit_f64():
     assert abs(sse - sse_ref) <= 1e-8 * nx_ref
     assert abs(fit - fit_ref) <= 1e-10
     # values sit on a sparse Zipf support, so a rank-R model of the whole
-    # tensor (zeros included) fits it poorly: only the range is checked
-    assert 0.0 <= fit <= 1.0
+    # tensor (zeros included) fits it poorly: only the range is checked (with
+    # M1 far below I, J the recovered factors are minimum-norm and the fit
+    # can drop below zero)
+    assert fit <= 1.0
+    if I * J < 10**7:
+        assert fit >= 0.0
     eng.close()
 
 
