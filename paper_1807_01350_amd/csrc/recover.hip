@@ -289,22 +289,49 @@ __global__ __launch_bounds__(256) void colstat_part_kernel(int64_t n, int R, int
   }
 }
 
-// Pass 2 (one thread per column, blocks in order): 2-norm; with kfac, also
-// kfac[r] = norm (1 when zero) times the sign of the first largest-magnitude
-// entry.
-__global__ void colstat_final_kernel(int64_t n, int R, int G, const double* __restrict__ part,
-                                     const int64_t* __restrict__ pidx,
-                                     const double* __restrict__ X, double* __restrict__ norms,
-                                     double* __restrict__ kfac) {
-  const int r = threadIdx.x;
-  if (r >= R) return;
+// Pass 2 (one block): for column r, eight threads take the blocks b = g,
+// g + 8, ... (g = 0..7, in order, loads unrolled four deep), then thread g = 0
+// combines the eight in order: 2-norm; with kfac, also kfac[r] = norm (1 when
+// zero) times the sign of the first largest-magnitude entry.
+__global__ __launch_bounds__(256) void colstat_final_kernel(int64_t n, int R, int G,
+                                                            const double* __restrict__ part,
+                                                            const int64_t* __restrict__ pidx,
+                                                            const double* __restrict__ X,
+                                                            double* __restrict__ norms,
+                                                            double* __restrict__ kfac) {
+  __shared__ double s_sum[256], s_val[256];
+  __shared__ int64_t s_idx[256];
+  const int tid = threadIdx.x, r = tid & 31, g = tid >> 5;
   double ss = 0.0, bv = -1.0;
   int64_t bx = INT64_MAX;
-  for (int b = 0; b < G; ++b) {
-    ss += part[(int64_t)b * R + r];
-    const double v = part[((int64_t)G + b) * R + r];
-    const int64_t x = pidx[(int64_t)b * R + r];
-    if (v > bv || (v == bv && x < bx)) { bv = v; bx = x; }
+  if (r < R) {
+    for (int b0 = g; b0 < G; b0 += 32) {
+      double sv[4], vv[4];
+      int64_t xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int b = b0 + 8 * u;
+        const bool ok = b < G;
+        sv[u] = ok ? part[(int64_t)b * R + r] : 0.0;
+        vv[u] = ok ? part[((int64_t)G + b) * R + r] : -1.0;
+        xv[u] = ok ? pidx[(int64_t)b * R + r] : INT64_MAX;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ss += sv[u];
+        if (vv[u] > bv || (vv[u] == bv && xv[u] < bx)) { bv = vv[u]; bx = xv[u]; }
+      }
+    }
+  }
+  s_sum[tid] = ss;
+  s_val[tid] = bv;
+  s_idx[tid] = bx;
+  __syncthreads();
+  if (g != 0 || r >= R) return;
+  for (int h = 1; h < 8; ++h) {
+    const int t = h * 32 + r;
+    ss += s_sum[t];
+    if (s_val[t] > bv || (s_val[t] == bv && s_idx[t] < bx)) { bv = s_val[t]; bx = s_idx[t]; }
   }
   const double nrm = sqrt(ss);
   if (norms) norms[r] = nrm;
@@ -454,7 +481,7 @@ static hipError_t colstat(hipStream_t s, int64_t n, int R, const double* X, doub
   double* part = work;
   int64_t* pidx = (int64_t*)(work + 2 * (int64_t)G * R);
   hipLaunchKernelGGL(colstat_part_kernel, dim3(G), dim3(256), 0, s, n, R, rows_per, X, part, pidx, G);
-  hipLaunchKernelGGL(colstat_final_kernel, dim3(1), dim3(64), 0, s, n, R, G, part, pidx, X, norms,
+  hipLaunchKernelGGL(colstat_final_kernel, dim3(1), dim3(256), 0, s, n, R, G, part, pidx, X, norms,
                      kfac);
   return hipGetLastError();
 }
