@@ -145,6 +145,22 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
 octen_status octen_compress_batch(octen_t h, const void* X, int64_t t, const double* W,
                                   const float* slice_scale);
 
+/* Sec. 4.1 compression of the next batch, overlapped with the current one
+ * (same arguments and result as octen_compress_batch).  The kernels run on a
+ * second stream of the handle (default priority, created on first use) once
+ * everything enqueued on the handle stream before this call has finished, so
+ * work enqueued after it (the ALS and recovery of the batch added just
+ * before) runs concurrently on the CUs the cooperative ALS leaves free.  The
+ * handle stream waits for the compression at the next call that reads or
+ * rewrites Z, W or the compression workspace (octen_update_replicas, the
+ * compress calls, octen_get_state, octen_autotune, octen_compress_variant,
+ * the learned warm start).  Replaces the previous batch's Z: call it after
+ * octen_update_replicas of that batch.  Stage times of the compression are
+ * taken on the second stream.  Errors as octen_compress_batch, plus
+ * OCTEN_ERR_HIP when the stream or its events cannot be created. */
+octen_status octen_compress_batch_async(octen_t h, const void* X, int64_t t, const double* W,
+                                        const float* slice_scale);
+
 /* Same for a sparse batch given as sorted COO (by k, then i, then j) with
  * slice indices k in [0, t) relative to the batch.  k, i, j: [nnz] int32,
  * v: [nnz] f32, all device arrays; 0 <= nnz < 2^31.  Duplicated coordinates

@@ -19,6 +19,11 @@ struct octen_ctx {
   int64_t I = 0, J = 0;
   int R = 0, P = 0, Q = 0, S = 0, M1 = 0;
   hipStream_t stream = nullptr;
+  // overlapped compression (octen_compress_batch_async): a second stream of
+  // the default priority; ev_z marks the end of the latest compression there
+  hipStream_t side = nullptr;
+  hipEvent_t ev_main = nullptr, ev_z = nullptr;
+  bool z_async = false;       // a compression on the side stream is not joined yet
   bool acc_f64 = true;  // summaries (Y, Z) in f64, else f32
   std::string err;
 
@@ -180,6 +185,17 @@ octen_status dgrow(octen_t h, T** p, int64_t* cap, int64_t count) {
     octen_status s_ = (expr);            \
     if (s_ != OCTEN_OK) return s_;       \
   } while (0)
+
+// Makes the handle stream wait for an overlapped compression (Z, Wz and the
+// compression workspace are then safe to read or rewrite on it).
+static octen_status join_side(octen_t h) {
+  if (h->z_async) {
+    h->z_async = false;
+    if (hipStreamWaitEvent(h->stream, h->ev_z, 0) != hipSuccess)
+      return fail(h, OCTEN_ERR_HIP, "join of the overlapped compression failed");
+  }
+  return OCTEN_OK;
+}
 
 bool valid_dtype_x(int d) { return d == OCTEN_F64 || d == OCTEN_F32; }
 
@@ -459,6 +475,12 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
 octen_status octen_destroy(octen_t h) {
   if (!h) return OCTEN_ERR_ARG;
   hipStreamSynchronize(h->stream);
+  if (h->side) {
+    hipStreamSynchronize(h->side);
+    hipStreamDestroy(h->side);
+  }
+  if (h->ev_main) hipEventDestroy(h->ev_main);
+  if (h->ev_z) hipEventDestroy(h->ev_z);
   if (h->plan) mfma_plan_destroy(h->plan);
   for (int st = 0; st < OCTEN_NUM_STAGES; ++st)
     for (auto e : h->ev[st])
@@ -474,6 +496,7 @@ octen_status octen_compress_batch(octen_t h, const void* X, int64_t t, const dou
   if (!h) return OCTEN_ERR_ARG;
   if (!X || !W || t < 1) return fail(h, OCTEN_ERR_ARG, "X, W must be non-null and t >= 1");
   if (t > (1 << 24)) return fail(h, OCTEN_ERR_ARG, "t too large");
+  OKCHK(join_side(h));
   hipStream_t s = h->stream;
   const int64_t I = h->I, J = h->J, M1 = h->M1;
   CompressShape sh{I, J, h->P, h->Q, h->S, h->M1};
@@ -514,6 +537,29 @@ octen_status octen_compress_batch(octen_t h, const void* X, int64_t t, const dou
   return OCTEN_OK;
 }
 
+octen_status octen_compress_batch_async(octen_t h, const void* X, int64_t t, const double* W,
+                                        const float* slice_scale) {
+  if (!h) return OCTEN_ERR_ARG;
+  if (!h->side) {
+    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_z, hipEventDisableTiming) != hipSuccess)
+      return fail(h, OCTEN_ERR_HIP, "side stream for the overlapped compression");
+  }
+  // everything enqueued on the handle stream so far (the producer of X, the
+  // update that consumed the previous batch) precedes the compression
+  HIPCHK(h, hipEventRecord(h->ev_main, h->stream));
+  HIPCHK(h, hipStreamWaitEvent(h->side, h->ev_main, 0));
+  hipStream_t keep = h->stream;
+  h->stream = h->side;
+  const octen_status st = octen_compress_batch(h, X, t, W, slice_scale);
+  h->stream = keep;
+  if (st != OCTEN_OK) return st;
+  HIPCHK(h, hipEventRecord(h->ev_z, h->side));
+  h->z_async = true;
+  return OCTEN_OK;
+}
+
 octen_status octen_compress_batch_coo(octen_t h, int64_t nnz, const int32_t* k, const int32_t* i,
                                       const int32_t* j, const float* v, int64_t t, const double* W) {
   if (!h) return OCTEN_ERR_ARG;
@@ -521,6 +567,7 @@ octen_status octen_compress_batch_coo(octen_t h, int64_t nnz, const int32_t* k, 
   if (t > (1 << 24)) return fail(h, OCTEN_ERR_ARG, "t too large");
   if (nnz < 0 || nnz >= 0x7fffffffLL) return fail(h, OCTEN_ERR_ARG, "nnz must be in [0, 2^31 - 1)");
   if (nnz > 0 && (!k || !i || !j || !v)) return fail(h, OCTEN_ERR_ARG, "k, i, j, v must be non-null");
+  OKCHK(join_side(h));
   hipStream_t s = h->stream;
   const int64_t M1 = h->M1, P = h->P, Q = h->Q;
   OKCHK(dgrow(h, &h->coo_work, &h->coo_work_cap, (int64_t)coo_work_ints(nnz)));
@@ -580,6 +627,7 @@ octen_status octen_compress_batch_coo(octen_t h, int64_t nnz, const int32_t* k, 
 }
 
 octen_status octen_update_replicas(octen_t h) {
+  if (h) OKCHK(join_side(h));
   if (!h) return OCTEN_ERR_ARG;
   if (!h->z_ready) return fail(h, OCTEN_ERR_STATE, "update before compress");
   hipStream_t s = h->stream;
@@ -612,6 +660,7 @@ octen_status octen_update_replicas(octen_t h) {
 namespace {
 
 octen_status ws_features(octen_t h) {
+  OKCHK(join_side(h));
   if (!h->have_factors) return fail(h, OCTEN_ERR_STATE, "no previous replica factors");
   if (!h->z_any) return fail(h, OCTEN_ERR_STATE, "no compressed batch to sketch");
   hipStream_t s = h->stream;
@@ -903,6 +952,7 @@ octen_status octen_warmstart_targets(octen_t h, float* T) {
 octen_status octen_get_state(octen_t h, int32_t what, void* dst, size_t bytes) {
   if (!h) return OCTEN_ERR_ARG;
   if (!dst) return fail(h, OCTEN_ERR_ARG, "dst is NULL");
+  OKCHK(join_side(h));
   const int64_t P = h->P, Q = h->Q, R = h->R, M1 = h->M1;
   const void* src = nullptr;
   size_t n = 0;
@@ -947,6 +997,7 @@ octen_status octen_get_state(octen_t h, int32_t what, void* dst, size_t bytes) {
 
 octen_status octen_compress_variant(octen_t h, int32_t variant) {
   if (!h) return OCTEN_ERR_ARG;
+  OKCHK(join_side(h));
   if (!h->plan) return fail(h, OCTEN_ERR_UNSUPPORTED, "only MFMA compression has variants");
   if (variant < 0 || variant > 3) return fail(h, OCTEN_ERR_ARG, "variant must be in [0, 3]");
   if (variant == 3 && h->cfg.compress_dtype != OCTEN_BF16)
@@ -959,6 +1010,7 @@ octen_status octen_autotune(octen_t h, const void* X, int64_t t, int32_t* choice
   if (!h) return OCTEN_ERR_ARG;
   if (!h->plan) return fail(h, OCTEN_ERR_UNSUPPORTED, "only MFMA compression is tuned");
   if (!X || t < 1 || t > (1 << 24)) return fail(h, OCTEN_ERR_ARG, "X non-null and t >= 1 required");
+  OKCHK(join_side(h));
   hipStream_t s = h->stream;
   const CompressShape sh{h->I, h->J, h->P, h->Q, h->S, h->M1};
   const int kind = h->cfg.compress_dtype == OCTEN_BF16 ? 2 : 1;

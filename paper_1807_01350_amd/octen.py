@@ -75,6 +75,7 @@ _i32, _i64, _f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 _SIGS = {
     "octen_init": ([ctypes.POINTER(octen_config), _vp, _vp, _vp, ctypes.POINTER(_vp)], _i32),
     "octen_compress_batch": ([_vp, _vp, _i64, _vp, _vp], _i32),
+    "octen_compress_batch_async": ([_vp, _vp, _i64, _vp, _vp], _i32),
     "octen_compress_batch_coo": ([_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp], _i32),
     "octen_update_replicas": ([_vp], _i32),
     "octen_cp_als_replicas": ([_vp, _i32, _f64, _i32, _vp, _vp], _i32),
@@ -162,6 +163,10 @@ def octen_init(cfg, U, V, stream=None):
 
 def octen_compress_batch(h, X, t, W, slice_scale=None):
     return _lib.octen_compress_batch(h, _ptr(X), int(t), _ptr(W), _ptr(slice_scale))
+
+
+def octen_compress_batch_async(h, X, t, W, slice_scale=None):
+    return _lib.octen_compress_batch_async(h, _ptr(X), int(t), _ptr(W), _ptr(slice_scale))
 
 
 def octen_compress_batch_coo(h, nnz, k, i, j, v, t, W):
@@ -465,6 +470,14 @@ class Octen:
 
     def compress_batch(self, X, W, slice_scale=None):
         self._check(octen_compress_batch(self.h, X, X.shape[0], W, slice_scale), "octen_compress_batch")
+        self._tz = int(X.shape[0])
+
+    def compress_batch_async(self, X, W, slice_scale=None):
+        """Compression of the next batch on the handle's second stream,
+        overlapping the ALS and recovery enqueued after it (call after
+        update_replicas of the previous batch)."""
+        self._check(octen_compress_batch_async(self.h, X, X.shape[0], W, slice_scale),
+                    "octen_compress_batch_async")
         self._tz = int(X.shape[0])
 
     def compress_batch_coo(self, k, i, j, v, t, W):
