@@ -431,9 +431,11 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   int done = 0;
   for (int it = 0; it < g.max_iters && alive; ++it) {
     // ------------------------------------------------ mode 1 (rows of A)
-    for (int e = tid; e < RR; e += NT) G[e] = BtB[e] * CtC[e];
-    __syncthreads();
+    // wavefront 0 forms G1 = B'B o C'C itself (both complete: the sweep
+    // before ended with a barrier) while the others start on T
     if (wave == 0) {
+      for (int e = lane; e < RR; e += 64) G[e] = BtB[e] * CtC[e];
+      wave_sync();
       spd_inverse_wave<RMAX>(G, Gi, R, &s_bad);
     } else {
       // T(pair, r) = sum_c X(pair, c) C(c, r) on MFMA, tiles over pairs x r
@@ -627,8 +629,6 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     }
     __syncthreads();
     // ------------------------------------------------ mode 3 partial
-    for (int e = tid; e < RR; e += NT) G[e] = AtA[e] * BtB[e];
-    __syncthreads();
     {
       const int set2 = (nbar + 1) & 1;
       double* dst = NW > 1 ? slot(set2, w) : Mf;
@@ -645,6 +645,9 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       f64x4 keep = {0.0, 0.0, 0.0, 0.0};
       int keep_tile = -1;
       if (wave == 0) {
+        // G3 = A'A o B'B by wavefront 0 (both complete at the barrier above)
+        for (int e = lane; e < RR; e += 64) G[e] = AtA[e] * BtB[e];
+        wave_sync();
         spd_inverse_wave<RMAX>(G, Gi, R, &s_bad);
       } else {
         for (int item = wave - 1; item < ntl * ksp; item += NMW) {
