@@ -172,6 +172,8 @@ __global__ __launch_bounds__(NT) void coo_compress_kernel(
     const T* __restrict__ Vm, const T* __restrict__ Um, int64_t t, int M1, int P, int Q, int S,
     int per_xcd, T* __restrict__ Mout) {
   constexpr int SC = CooTraits<T>::SC;
+  // the SC + 1 segment starts of a pass are read by the lanes of one wavefront
+  static_assert(SC < 64, "segments per pass must fit one wavefront");
   constexpr int QP = QT * 32;
   constexpr int NX = QT > 2 ? 2 : 1;   // columns gathered per lane
   __shared__ T Ub[SC][QP];
