@@ -624,7 +624,7 @@ def main():
     # initial summary (untimed), tuning of the compression kernel and of the
     # ALS launch shape on it (untimed), then warmup batches
     step(0, 0, c.t0)
-    tuned = {"compress": eng.autotune(X[c.t0:c.t0 + t]), "als": eng.autotune_als(10)}
+    tuned = {"compress": eng.autotune(X[c.t0:c.t0 + t]), "als": eng.autotune_als(20)}
     k0 = c.t0
     for b in range(1, args.warmup + 1):
         step(b, k0, t)

@@ -267,11 +267,13 @@ octen_status octen_autotune(octen_t h, const void* X, int64_t t, int32_t* choice
 octen_status octen_compress_variant(octen_t h, int32_t variant);
 
 /* Times the cooperative ALS for `sweeps` sweeps on the current summaries with
- * each workgroups-per-replica count (powers of two and the largest that is
- * co-resident) and the replica slab in LDS or in global memory, starting from
- * the current factors, and keeps the fastest; the factors are restored
- * afterwards.  choice_host: NULL or 10 * workgroups + (1 if the slab is in
- * global memory).  Needs factors from an earlier ALS call.  Synchronises. */
+ * each workgroups-per-replica count that is the smallest one for its slab
+ * height ceil(Q / count) (at most the CUs of one XCD per replica), with the
+ * replica slab in LDS or in global memory, starting from the current factors;
+ * three interleaved rounds, the best time of each candidate counts; keeps the
+ * fastest and restores the factors afterwards.  choice_host: NULL or
+ * 10 * workgroups + (1 if the slab is in global memory).  Needs factors from
+ * an earlier ALS call.  Synchronises. */
 octen_status octen_autotune_als(octen_t h, int32_t sweeps, int32_t* choice_host);
 
 /* A group runs one update step (compress, update, ALS) of many handles as
