@@ -437,10 +437,18 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       for (int e = lane; e < RR; e += 64) G[e] = BtB[e] * CtC[e];
       wave_sync();
       spd_inverse_wave<RMAX>(G, Gi, R, &s_bad);
-    } else {
-      // T(pair, r) = sum_c X(pair, c) C(c, r) on MFMA, tiles over pairs x r
-      const int ptiles = (npair + 15) / 16;
-      for (int tt = wave - 1; tt < ptiles * RT; tt += NT / 64 - 1) {
+    }
+    {
+      // T(pair, r) = sum_c X(pair, c) C(c, r) on MFMA, tiles over pairs x r,
+      // dealt to wavefronts 1..7; when one tile is left over after at least
+      // two whole rounds, wavefront 0 takes it after the inverse
+      constexpr int NMW = NT / 64 - 1;
+      const int ntile = (npair + 15) / 16 * RT;
+      const bool w0_tile = ntile % NMW == 1 && ntile > 2 * NMW;
+      const int t_first = wave == 0 ? (w0_tile ? ntile - 1 : ntile) : wave - 1;
+      const int t_end = wave == 0 || !w0_tile ? ntile : ntile - 1;
+      const int t_step = wave == 0 ? 1 : NMW;
+      for (int tt = t_first; tt < t_end; tt += t_step) {
         const int pt = tt / RT, rt = tt % RT;
         const int pr = pt * 16 + lane % 16;
         const int rr = rt * 16 + lane % 16;
