@@ -17,15 +17,18 @@
 // partials in slab order: results do not depend on timing.
 //
 // The R x R normal matrices are inverted by one wavefront (Gauss-Jordan on
-// the SPD matrix, one row per lane, rows exchanged with lane reads), while the
-// other wavefronts run the slab contractions on v_mfma_f64_16x16x4.
+// the identity-padded SPD matrix, one column per lane, pivot columns read
+// with lane reads), while the other wavefronts run the slab contractions on
+// v_mfma_f64_16x16x4.
 //
 // Workgroups of a replica synchronise through a monotonically increasing
-// counter (agent-scope release, relaxed polling, one acquire); every wait is
-// bounded and raises an error flag when exceeded, after which all workgroups
-// skip to the end.  The launch is cooperative, so all workgroups are resident.
-// Replica p is placed on XCD p % 8 (workgroup x runs on XCD x % 8) so that its
-// counter and partial sums stay in one L2.
+// counter (relaxed bump and polling); every wait is bounded and raises an
+// error flag when exceeded, after which all workgroups skip to the end.  The
+// launch is cooperative, so all workgroups are resident.  Replica p is placed
+// on XCD p % 8 (workgroup x runs on XCD x % 8) so that its counter and
+// partial sums stay in one L2; when the XCC ids recorded at launch confirm
+// that, the barriers need no cache maintenance beyond device-coherent loads
+// of the partials, otherwise they add an agent-scope release and acquire.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
