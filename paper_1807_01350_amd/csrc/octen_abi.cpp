@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/octen.h"
@@ -762,16 +763,14 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, i
                    h->rd_work, octen_ctx::RD_WORK));
   HIPCHK(h, rowdot(s, J, R, M1, h->OpB, M1, 1, h->rhs + (int64_t)M1 * R, R, 1, nullptr, 1.0, 0.0,
                    h->Braw, R, h->rd_work, octen_ctx::RD_WORK));
-  HIPCHK(h, rec_canon(s, I, R, h->Araw, h->Ac, h->ka, h->rd_work, octen_ctx::RD_WORK));
-  HIPCHK(h, rec_canon(s, J, R, h->Braw, h->Bc, h->kb, h->rd_work, octen_ctx::RD_WORK));
+  HIPCHK(h, rec_canon2(s, I, J, R, h->Araw, h->Ac, h->ka, h->Braw, h->Bc, h->kb, h->rd_work,
+                       octen_ctx::RD_WORK));
   if (h->have_prev) {
     HIPCHK(h, rowdot(s, R, R, I, h->Ac, 1, R, h->Aprev, R, 1, nullptr, 1.0, 0.0, h->cross, R, h->rd_work, octen_ctx::RD_WORK));
     HIPCHK(h, rowdot(s, R, R, J, h->Bc, 1, R, h->Bprev, R, 1, nullptr, 1.0, 0.0, h->cross + R * R,
                      R, h->rd_work, octen_ctx::RD_WORK));
-    HIPCHK(h, rec_col_norms(s, I, R, h->Ac, h->norms, h->rd_work, octen_ctx::RD_WORK));
-    HIPCHK(h, rec_col_norms(s, I, R, h->Aprev, h->norms + R, h->rd_work, octen_ctx::RD_WORK));
-    HIPCHK(h, rec_col_norms(s, J, R, h->Bc, h->norms + 2 * R, h->rd_work, octen_ctx::RD_WORK));
-    HIPCHK(h, rec_col_norms(s, J, R, h->Bprev, h->norms + 3 * R, h->rd_work, octen_ctx::RD_WORK));
+    HIPCHK(h, rec_col_norms4(s, I, J, R, h->Ac, h->Aprev, h->Bc, h->Bprev, h->norms, h->rd_work,
+                             octen_ctx::RD_WORK));
     HIPCHK(h, rec_tmatch(s, R, h->cross, h->norms, h->tperm, h->tsign, h->tmargin));
   }
   // temporal rows (reading: incremental solve with the carried history removed)
@@ -812,14 +811,13 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, i
   }
   HIPCHK(h, rec_temporal_finish(s, R, h->K, t, h->kappa, h->tperm, h->tsign, h->bt, h->Chist,
                                 h->Ctmp, h->have_prev ? 1 : 0));
-  // H = Hcur + W^T C_new (canonical convention)
-  HIPCHK(h, hipMemcpyAsync(h->H, h->Hcur, (size_t)M1 * R * 8, hipMemcpyDeviceToDevice, s));
+  // H = Hcur + W^T C_new (canonical convention): the buffers trade places
+  std::swap(h->H, h->Hcur);
   HIPCHK(h, rowdot(s, M1, R, t, h->Wp, 1, M1, h->bt, R, 1, nullptr, 1.0, 1.0, h->H, R, h->rd_work, octen_ctx::RD_WORK));
-  HIPCHK(h, hipMemcpyAsync(h->Aprev, h->Ac, I * R * 8, hipMemcpyDeviceToDevice, s));
-  HIPCHK(h, hipMemcpyAsync(h->Bprev, h->Bc, J * R * 8, hipMemcpyDeviceToDevice, s));
-  HIPCHK(h, hipMemcpyAsync(A, h->Ac, I * R * 8, hipMemcpyDeviceToDevice, s));
-  HIPCHK(h, hipMemcpyAsync(B, h->Bc, J * R * 8, hipMemcpyDeviceToDevice, s));
-  HIPCHK(h, hipMemcpyAsync(C, h->Chist, Knew * R * 8, hipMemcpyDeviceToDevice, s));
+  // outputs in one launch; the canonical factors become the previous ones
+  HIPCHK(h, rec_copy3(s, A, h->Ac, I * R, B, h->Bc, J * R, C, h->Chist, Knew * R));
+  std::swap(h->Ac, h->Aprev);
+  std::swap(h->Bc, h->Bprev);
   h->K = Knew;
   h->t_pend = 0;
   h->have_prev = true;

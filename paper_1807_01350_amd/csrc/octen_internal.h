@@ -133,6 +133,19 @@ hipError_t rec_canon(hipStream_t s, int64_t n, int R, const double* X, double* o
 // norms [4][R] = column norms of Ac, Ap, Bc, Bp.  Writes tperm, tsign.
 hipError_t rec_col_norms(hipStream_t s, int64_t n, int R, const double* X, double* norms,
                          double* work, int64_t work_len);
+// Column norms of Ac, Ap ([nA][R]) and Bc, Bp ([nB][R]) into norms [4][R],
+// one launch when all columns are short.
+hipError_t rec_col_norms4(hipStream_t s, int64_t nA, int64_t nB, int R, const double* Ac,
+                          const double* Ap, const double* Bc, const double* Bp, double* norms,
+                          double* work, int64_t work_len);
+// rec_canon of (XA [nA][R] -> outA, kA) and (XB [nB][R] -> outB, kB), one
+// launch when both are short.
+hipError_t rec_canon2(hipStream_t s, int64_t nA, int64_t nB, int R, const double* XA,
+                      double* outA, double* kA, const double* XB, double* outB, double* kB,
+                      double* work, int64_t work_len);
+// Three device-to-device copies of n1, n2, n3 doubles in one launch.
+hipError_t rec_copy3(hipStream_t s, double* d1, const double* s1, int64_t n1, double* d2,
+                     const double* s2, int64_t n2, double* d3, const double* s3, int64_t n3);
 hipError_t rec_tmatch(hipStream_t s, int R, const double* cross, const double* norms, int* tperm,
                       double* tsign, double* tmargin);
 // Hcur = H[:, tperm] * tsign; rhs_c = rhs2 - Hcur / kappa; kappa = ka * kb.

@@ -245,6 +245,59 @@ __global__ __launch_bounds__(256) void colnorm_kernel(int64_t n, int R, const do
   if (threadIdx.x == 0) norms[r] = nrm;
 }
 
+// colnorm_kernel over four matrices at once: block b takes matrix b / R
+// (Ac, Ap with nA rows, Bc, Bp with nB rows), column b % R.
+__global__ __launch_bounds__(256) void colnorm4_kernel(int64_t nA, int64_t nB, int R,
+                                                       const double* __restrict__ X0,
+                                                       const double* __restrict__ X1,
+                                                       const double* __restrict__ X2,
+                                                       const double* __restrict__ X3,
+                                                       double* __restrict__ norms) {
+  __shared__ double s_sum[256], s_val[256];
+  __shared__ int64_t s_idx[256];
+  const int m = blockIdx.x / R, r = blockIdx.x % R;
+  const double* X = m == 0 ? X0 : m == 1 ? X1 : m == 2 ? X2 : X3;
+  const int64_t n = m < 2 ? nA : nB;
+  double nrm, sv;
+  column_stats(n, R, X, r, s_sum, s_val, s_idx, &nrm, &sv);
+  if (threadIdx.x == 0) norms[m * R + r] = nrm;
+}
+
+// canon_kernel over two matrices at once: block b takes matrix b / R, column
+// b % R.
+__global__ __launch_bounds__(256) void canon2_kernel(int64_t nA, int64_t nB, int R,
+                                                     const double* __restrict__ XA,
+                                                     double* __restrict__ outA,
+                                                     double* __restrict__ kA,
+                                                     const double* __restrict__ XB,
+                                                     double* __restrict__ outB,
+                                                     double* __restrict__ kB) {
+  __shared__ double s_sum[256], s_val[256];
+  __shared__ int64_t s_idx[256];
+  const int m = blockIdx.x / R, r = blockIdx.x % R;
+  const double* X = m == 0 ? XA : XB;
+  double* out = m == 0 ? outA : outB;
+  const int64_t n = m == 0 ? nA : nB;
+  double nrm, sv;
+  column_stats(n, R, X, r, s_sum, s_val, s_idx, &nrm, &sv);
+  const double sg = sv > 0.0 ? 1.0 : (sv < 0.0 ? -1.0 : 1.0);
+  const double k = (nrm > 0.0 ? nrm : 1.0) * sg;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) out[i * R + r] = X[i * R + r] / k;
+  if (threadIdx.x == 0) (m == 0 ? kA : kB)[r] = k;
+}
+
+__global__ __launch_bounds__(256) void copy3_kernel(double* __restrict__ d1,
+                                                    const double* __restrict__ s1, int64_t n1,
+                                                    double* __restrict__ d2,
+                                                    const double* __restrict__ s2, int64_t n2,
+                                                    double* __restrict__ d3,
+                                                    const double* __restrict__ s3, int64_t n3) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < n1; e += stride) d1[e] = s1[e];
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < n2; e += stride) d2[e] = s2[e];
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < n3; e += stride) d3[e] = s3[e];
+}
+
 // Column statistics of X [n][R] (R <= 32) in two passes.  Pass 1: block b
 // takes rows [b rows_per, (b + 1) rows_per); its threads form groups of R,
 // thread (g, r) reads column r of rows g, g + ngrp, ... (a group reads whole
@@ -511,6 +564,46 @@ hipError_t rec_col_norms(hipStream_t s, int64_t n, int R, const double* X, doubl
     return hipGetLastError();
   }
   return colstat(s, n, R, X, norms, nullptr, work, work_len);
+}
+
+hipError_t rec_col_norms4(hipStream_t s, int64_t nA, int64_t nB, int R, const double* Ac,
+                          const double* Ap, const double* Bc, const double* Bp, double* norms,
+                          double* work, int64_t work_len) {
+  if (nA < COLSTAT_SHORT && nB < COLSTAT_SHORT) {
+    hipLaunchKernelGGL(colnorm4_kernel, dim3(4 * R), dim3(256), 0, s, nA, nB, R, Ac, Ap, Bc, Bp,
+                       norms);
+    return hipGetLastError();
+  }
+  hipError_t e = rec_col_norms(s, nA, R, Ac, norms, work, work_len);
+  if (e == hipSuccess) e = rec_col_norms(s, nA, R, Ap, norms + R, work, work_len);
+  if (e == hipSuccess) e = rec_col_norms(s, nB, R, Bc, norms + 2 * R, work, work_len);
+  if (e == hipSuccess) e = rec_col_norms(s, nB, R, Bp, norms + 3 * R, work, work_len);
+  return e;
+}
+
+hipError_t rec_canon2(hipStream_t s, int64_t nA, int64_t nB, int R, const double* XA,
+                      double* outA, double* kA, const double* XB, double* outB, double* kB,
+                      double* work, int64_t work_len) {
+  if (nA < COLSTAT_SHORT && nB < COLSTAT_SHORT) {
+    hipLaunchKernelGGL(canon2_kernel, dim3(2 * R), dim3(256), 0, s, nA, nB, R, XA, outA, kA, XB,
+                       outB, kB);
+    return hipGetLastError();
+  }
+  hipError_t e = rec_canon(s, nA, R, XA, outA, kA, work, work_len);
+  if (e == hipSuccess) e = rec_canon(s, nB, R, XB, outB, kB, work, work_len);
+  return e;
+}
+
+hipError_t rec_copy3(hipStream_t s, double* d1, const double* s1, int64_t n1, double* d2,
+                     const double* s2, int64_t n2, double* d3, const double* s3, int64_t n3) {
+  int64_t n = n1 > n2 ? n1 : n2;
+  if (n3 > n) n = n3;
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(copy3_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d1, s1, n1, d2, s2,
+                     n2, d3, s3, n3);
+  return hipGetLastError();
 }
 
 hipError_t rec_tmatch(hipStream_t s, int R, const double* cross, const double* norms, int* tperm,
