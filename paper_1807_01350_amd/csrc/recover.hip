@@ -113,8 +113,16 @@ __global__ __launch_bounds__(64) void align_kernel(int P, int Q, int R, int S,
   }
   __syncthreads();
   double* Ap = aligned + (int64_t)p * 3 * QR;
+  // element loops over [3][Q][R]: lane = (row offset lq, column lr), rows
+  // stepped by rpl = 64 / R; no division inside the loops
+  const int rpl = 64 / R, lq = lane / R, lr = lane - (lane / R) * R;
   if (p == 0) {
-    for (int64_t e = lane; e < 3 * QR; e += 64) Ap[e] = F0[e] * c0[e % R];
+    if (lq < rpl)
+      for (int n = 0; n < 3; ++n)
+        for (int q = lq; q < Q; q += rpl) {
+          const int64_t e = n * QR + (int64_t)q * R + lr;
+          Ap[e] = F0[e] * c0[lr];
+        }
     if (lane < R) perm_out[lane] = lane;
     if (lane == 0) margin_out[0] = INFINITY;
     return;
@@ -159,11 +167,15 @@ __global__ __launch_bounds__(64) void align_kernel(int P, int Q, int R, int S,
     sim[e] = den > 0.0 ? num / den : 0.0;   // sim reused as d[n][r]
   }
   __syncthreads();
-  for (int64_t e = lane; e < 3 * QR; e += 64) {
-    const int n = (int)(e / QR);
-    const int64_t rem = e % QR;
-    const int q = (int)(rem / R), r = (int)(rem % R);
-    Ap[n * QR + (int64_t)q * R + perm[r]] = sim[n * R + r] * (Fp[e] * cp[r]);
+  if (lq < rpl) {
+    const int pr = perm[lr];
+    for (int n = 0; n < 3; ++n) {
+      const double d = sim[n * R + lr];
+      for (int q = lq; q < Q; q += rpl) {
+        const int64_t e = n * QR + (int64_t)q * R + lr;
+        Ap[n * QR + (int64_t)q * R + pr] = d * (Fp[e] * cp[lr]);
+      }
+    }
   }
 }
 
