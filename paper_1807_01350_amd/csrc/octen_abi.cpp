@@ -542,10 +542,19 @@ octen_status octen_compress_batch_async(octen_t h, const void* X, int64_t t, con
                                         const float* slice_scale) {
   if (!h) return OCTEN_ERR_ARG;
   if (!h->side) {
-    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev_z, hipEventDisableTiming) != hipSuccess)
+    hipStream_t side = nullptr;
+    hipEvent_t em = nullptr, ez = nullptr;
+    if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&em, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ez, hipEventDisableTiming) != hipSuccess) {
+      if (ez) hipEventDestroy(ez);
+      if (em) hipEventDestroy(em);
+      if (side) hipStreamDestroy(side);
       return fail(h, OCTEN_ERR_HIP, "side stream for the overlapped compression");
+    }
+    h->side = side;
+    h->ev_main = em;
+    h->ev_z = ez;
   }
   // everything enqueued on the handle stream so far (the producer of X, the
   // update that consumed the previous batch) precedes the compression
