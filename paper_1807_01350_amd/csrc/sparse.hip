@@ -164,9 +164,13 @@ struct CooTraits<double> {
 
 // One workgroup per (slice k, replica p); blockIdx is mapped so that the P
 // workgroups of one slice run on the same XCD (they read the same nonzeros
-// and the same rows of U and V).
+// and the same rows of U and V).  The FP32 kernels for Q <= 96 are held to
+// 128 registers (four workgroups per CU instead of three, no spills): the
+// gathers are latency-bound, and a 16-replica batch of 100 slices then runs
+// in two waves of workgroups instead of three.
 template <typename T, int QT>
-__global__ __launch_bounds__(NT) void coo_compress_kernel(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
+    sizeof(T) == 4 && QT <= 3 ? 4 : 1))) void coo_compress_kernel(
     const int* __restrict__ seg_start, const int* __restrict__ seg_row,
     const int* __restrict__ slice_seg, const int* __restrict__ jj, const float* __restrict__ vv,
     const T* __restrict__ Vm, const T* __restrict__ Um, int64_t t, int M1, int P, int Q, int S,
