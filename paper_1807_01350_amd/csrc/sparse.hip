@@ -227,11 +227,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
   // rows together, one nonzero of each per step, so their loads overlap.
   constexpr int CH = 32;
   constexpr int SPW = SC / 4;
+  // segment starts c0 .. c0 + SC of a pass (one per lane, clamped to s1;
+  // seg_start holds nseg + 1 entries); the next pass's are loaded while the
+  // current pass's outer products run
   int c0 = s0;
+  int st_next = seg_start[c0 + lane <= s1 ? c0 + lane : s1];
   while (c0 < s1) {
-    // segment starts c0 .. c0 + SC (lanes), their lengths and the long ones
-    const int sl = c0 + lane <= s1 ? c0 + lane : s1;
-    const int st = seg_start[sl];
+    // this pass's segment starts, their lengths and the long ones
+    const int st = st_next;
     const int st1 = __shfl_down(st, 1, 64);
     const bool is_long = lane < SC && c0 + lane < s1 && st1 - st > CH;
     const unsigned long long longm = __ballot(is_long);
@@ -305,6 +308,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int x = 0; x < NX; ++x) r[q][x] = fma(v[q], val[q][x], r[q][x]);
     }
+    const int c0n = c0 + (long_pass ? 1 : ns);
+    st_next = seg_start[c0n + lane <= s1 ? c0n + lane : s1];
 #pragma unroll
     for (int q = 0; q < SPW; ++q) {
       const int sg = wave + 4 * q;
@@ -316,7 +321,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
         }
       }
     }
-    c0 += long_pass ? 1 : ns;
+    c0 = c0n;
     __syncthreads();
     if constexpr (sizeof(T) == 4) {
 #pragma unroll
