@@ -24,7 +24,7 @@
 
 namespace octen {
 
-typedef float f32x16c __attribute__((ext_vector_type(16)));
+typedef float f32x4c __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -204,16 +204,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
     if (b >= Q) { Ub[e / QP][b] = T(0); Rb[e / QP][b] = T(0); }
   }
 
-  constexpr int NTILE = QT * QT;
-  constexpr int TPW = (NTILE + 3) / 4;
+  // FP32: 16 x 16 output tiles (Q = 80 is five of them, no padded work),
+  // dealt to the four wavefronts; at most (2 QT)^2 / 4 = QT^2 per wavefront
+  constexpr int TPW = QT * QT;
+  const int Q16 = (Q + 15) / 16;
+  const int ntile = Q16 * Q16;
+  // tile t -> (t / Q16, t % Q16) by a multiply-high: exact for t < 64, Q16 <= 8
+  const unsigned q16inv = (65536u + (unsigned)Q16 - 1u) / (unsigned)Q16;
   constexpr int NOUT = (QP * QP + NT - 1) / NT;
-  f32x16c acc[sizeof(T) == 4 ? TPW : 1];
+  f32x4c acc[sizeof(T) == 4 ? TPW : 1];
   double accd[sizeof(T) == 8 ? NOUT : 1];
   if constexpr (sizeof(T) == 4) {
 #pragma unroll
     for (int q = 0; q < TPW; ++q)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[q][e] = 0.f;
+      for (int e = 0; e < 4; ++e) acc[q][e] = 0.f;
   } else {
 #pragma unroll
     for (int q = 0; q < NOUT; ++q) accd[q] = 0.0;
@@ -327,13 +332,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int q = 0; q < TPW; ++q) {
         const int tt = wave + 4 * q;
-        if (tt < NTILE) {
-          const int ti = tt / QT, tj = tt % QT;
+        if (tt < ntile) {
+          const int ti = (int)(((unsigned)tt * q16inv) >> 16), tj = tt - ti * Q16;
+          // A = U^T (lane: column ti*16 + lane%16 of segment row kk), B = R
 #pragma unroll
-          for (int ks = 0; ks < SC / 2; ++ks) {
-            const int kk = 2 * ks + lane / 32;
-            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                (float)Ub[kk][ti * 32 + lane % 32], (float)Rb[kk][tj * 32 + lane % 32], acc[q], 0,
+          for (int ks = 0; ks < SC / 4; ++ks) {
+            const int kk = 4 * ks + lane / 16;
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                (float)Ub[kk][ti * 16 + lane % 16], (float)Rb[kk][tj * 16 + lane % 16], acc[q], 0,
                 0, 0);
           }
         }
@@ -359,12 +365,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
       const int tt = wave + 4 * q;
-      if (tt < NTILE) {
-        const int ti = tt / QT, tj = tt % QT;
-        const int bcol = tj * 32 + lane % 32;
+      if (tt < ntile) {
+        const int ti = (int)(((unsigned)tt * q16inv) >> 16), tj = tt - ti * Q16;
+        const int bcol = tj * 16 + lane % 16;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int arow = ti * 32 + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+        for (int e = 0; e < 4; ++e) {
+          const int arow = ti * 16 + 4 * (lane / 16) + e;
           if (arow < Q && bcol < Q) out[arow * Q + bcol] = acc[q][e];
         }
       }
