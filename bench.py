@@ -74,12 +74,13 @@ def gen_stream(torch, I, J, K, R, sigma, seed, dev):
     return X
 
 
-def traffic_from_profile(form):
+def traffic_from_profile(form, source="compress_mfma.hip", profile=None):
     """HBM bytes per launch of the compression kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1807_01350_amd", "csrc", "compress_mfma.hip")
-    prof = os.path.join(ROOT, "profiles", f"compress_pipe_{form}_dense1000_counters.md")
+    src = os.path.join(ROOT, "paper_1807_01350_amd", "csrc", source)
+    prof = os.path.join(ROOT, "profiles",
+                        profile or f"compress_pipe_{form}_dense1000_counters.md")
     if not os.path.exists(prof):
         return None
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -282,7 +283,10 @@ def run_sparse(args):
     kms = st["compress_main"]
     gbs = bytes_launch / (kms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            # both forms gather in FP32 through the same kernel
+            "traffic": traffic_from_profile(None, "sparse.hip",
+                                            "coo_compress_f32_sparse1e5_counters.md"),
             "kernel": "coo_compress (gather of V rows per (k, i) segment + MFMA U^T R)",
             "algorithmic_bytes_per_launch": bytes_launch,
             "algorithmic_flops_per_launch": float(np.mean(flops)),
