@@ -186,13 +186,16 @@ __global__ __launch_bounds__(1024) void spd_solve_kernel(double* __restrict__ Nm
 // Small systems (n <= 112, nrhs <= 32): Gauss-Jordan elimination without
 // pivoting on [N | B] held in LDS, one workgroup; for symmetric positive
 // definite N every pivot is positive (an SPD Schur complement stays SPD).
-// Per pivot j: every row i != j loses N(i,j)/N(j,j) times row j (columns
-// right of j only: the ones left of j are already eliminated and column j is
-// not read again), then row j is divided by its pivot; two barriers per
-// pivot.  Thread t owns rows t/16 + 16k and columns t%16 + 16m, so no
-// element index is divided at run time.  The right-hand columns end as
-// N^{-1} B.  info = j + 1 for a pivot that is not positive (the elimination
-// continues with it skipped).
+// Per pivot j: every row i != j loses N(i,j)/N(j,j) times row j, columns right
+// of j only (the ones left of j are already eliminated, column j is not read
+// again).  Rows are not divided by their pivots during the elimination: a step
+// writes only columns right of j of rows other than j and reads only column j
+// and row j, so one barrier per pivot suffices; N ends diagonal with its
+// pivots unchanged, and the right-hand columns of row i are divided by N(i,i)
+// at the end, giving N^{-1} B.  Thread t owns rows t/16 + 16k and columns
+// t%16 + 16m, so no element index is divided at run time.  info = j + 1 for
+// a pivot that is not positive (the elimination continues with it skipped and
+// its row is returned undivided).
 constexpr int GJ_NMAX = 112, GJ_RMAX = 32;
 __global__ __launch_bounds__(256) void spd_solve_gj_kernel(const double* __restrict__ Nm, int n,
                                                            double* __restrict__ Bm, int nrhs,
@@ -209,23 +212,23 @@ __global__ __launch_bounds__(256) void spd_solve_gj_kernel(const double* __restr
   __syncthreads();
   for (int j = 0; j < n; ++j) {
     const double p = M(j, j);
-    const bool ok = p > 0.0;
-    const double ip = ok ? 1.0 / p : 0.0;
-    if (tid == 0 && !ok && !bad) bad = j + 1;
-    if (ok) {
+    if (p > 0.0) {
+      const double ip = 1.0 / p;
       for (int i = rg; i < n; i += 16) {
         if (i == j) continue;
         const double f = M(i, j) * ip;
         for (int c = j + 1 + cg; c < w; c += 16) M(i, c) = fma(-f, M(j, c), M(i, c));
       }
+    } else if (tid == 0 && !bad) {
+      bad = j + 1;
     }
     __syncthreads();
-    if (ok && rg == 0)
-      for (int c = j + 1 + cg; c < w; c += 16) M(j, c) *= ip;
-    __syncthreads();
   }
-  for (int i = rg; i < n; i += 16)
-    for (int c = cg; c < nrhs; c += 16) Bm[(int64_t)i * nrhs + c] = M(i, n + c);
+  for (int i = rg; i < n; i += 16) {
+    const double p = M(i, i);
+    const double ip = p > 0.0 ? 1.0 / p : 1.0;
+    for (int c = cg; c < nrhs; c += 16) Bm[(int64_t)i * nrhs + c] = M(i, n + c) * ip;
+  }
   if (tid == 0 && bad && *info == 0) *info = bad;
 }
 
