@@ -18,23 +18,24 @@ namespace {
 
 constexpr int MAXR = 32;
 
+// A candidate entry: its value and key = (reference column << 6) | replica
+// row, so that the smaller key is the tie-break order (column first, then
+// row); KEY_NONE marks no candidate.
 struct Cand {
   double v;
-  int c, r;
+  int key;
 };
+constexpr int KEY_NONE = 0x7fffffff;
 
 __device__ __forceinline__ bool better(const Cand& a, const Cand& b) {
-  if (a.v > b.v) return true;
-  if (a.v == b.v) return a.c < b.c || (a.c == b.c && a.r < b.r);
-  return false;
+  return a.v > b.v || (a.v == b.v && a.key < b.key);
 }
 
 __device__ __forceinline__ Cand wave_best(Cand x) {
   for (int off = 32; off > 0; off >>= 1) {
     Cand y;
     y.v = __shfl_xor(x.v, off, 64);
-    y.c = __shfl_xor(x.c, off, 64);
-    y.r = __shfl_xor(x.r, off, 64);
+    y.key = __shfl_xor(x.key, off, 64);
     if (better(y, x)) x = y;
   }
   return x;
@@ -48,48 +49,72 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Exclusive greedy assignment on sim[r][c] (R x R in LDS) by one wavefront of
-// 64 lanes.  perm[r] = c.  Returns the smallest gap between a chosen entry and
-// its best free competitor in the same row or column (+inf if none).
-__device__ double greedy_wave(const double* sim, int R, int* perm, int* rowfree, int* colfree) {
+// Exclusive greedy assignment on sim[r][c] (R x R in LDS, R <= 32) by one
+// wavefront of 64 lanes.  perm[r] = c.  Returns the smallest gap between a
+// chosen entry and its best free competitor in the same row or column (+inf
+// if none).  Each lane keeps its entries (e = lane + 64 k) in registers and
+// every lane tracks the free rows and columns as the same bit masks, so a
+// round is two butterfly reductions with no barrier.
+// EPL entries per lane: R * R <= 64 * EPL.
+template <int EPL>
+__device__ double greedy_wave(const double* sim, int R, int* perm) {
   const int lane = threadIdx.x;
-  for (int e = lane; e < R; e += 64) { rowfree[e] = 1; colfree[e] = 1; perm[e] = -1; }
-  __syncthreads();
+  const int n = R * R, kmax = (n + 63) / 64;
+  double sv[EPL];
+  int sk[EPL];   // (c << 6) | r; 63 in both fields (bits never free) past n
+#pragma unroll
+  for (int k = 0; k < EPL; ++k) {
+    const int e = lane + 64 * k;
+    const bool in = e < n;
+    sv[k] = in ? sim[e] : -INFINITY;
+    sk[k] = in ? ((e % R) << 6) | (e / R) : (63 << 6) | 63;
+  }
+  unsigned long long rowm = (1ull << R) - 1ull, colm = rowm;
+  auto is_free = [&](int key) {
+    return ((rowm >> (key & 63)) & 1ull) && ((colm >> (key >> 6)) & 1ull);
+  };
   double margin = INFINITY;
   for (int round = 0; round < R; ++round) {
-    Cand best{-INFINITY, 1 << 30, 1 << 30};
-    for (int e = lane; e < R * R; e += 64) {
-      const int r = e / R, c = e % R;
-      if (!rowfree[r] || !colfree[c]) continue;
-      Cand x{sim[e], c, r};
-      if (better(x, best)) best = x;
+    Cand best{-INFINITY, KEY_NONE};
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) {
+      if (k < kmax && is_free(sk[k])) {
+        const Cand x{sv[k], sk[k]};
+        if (better(x, best)) best = x;
+      }
     }
     best = wave_best(best);
-    int br = best.r, bc = best.c;
-    if (br >= R || bc >= R) {   // every free entry is NaN: take the first free pair
-      br = 0; bc = 0;
-      while (br < R && !rowfree[br]) ++br;
-      while (bc < R && !colfree[bc]) ++bc;
+    int br, bc;
+    if (best.key == KEY_NONE) {   // every free entry is NaN: take the first free pair
+      br = __builtin_ctzll(rowm);
+      bc = __builtin_ctzll(colm);
+    } else {
+      br = best.key & 63;
+      bc = best.key >> 6;
     }
     double rival = -INFINITY;
-    for (int e = lane; e < R * R; e += 64) {
-      const int r = e / R, c = e % R;
-      if (!rowfree[r] || !colfree[c]) continue;
-      if ((r == br) != (c == bc)) rival = sim[e] > rival ? sim[e] : rival;
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) {
+      if (k < kmax && is_free(sk[k])) {
+        const int r = sk[k] & 63, c = sk[k] >> 6;
+        if ((r == br) != (c == bc)) rival = sv[k] > rival ? sv[k] : rival;
+      }
     }
     rival = wave_max(rival);
     if (rival > -INFINITY) {
       const double g = best.v - rival;
       margin = g < margin ? g : margin;
     }
-    __syncthreads();
-    if (lane == 0) { perm[br] = bc; rowfree[br] = 0; colfree[bc] = 0; }
-    __syncthreads();
+    if (lane == 0) perm[br] = bc;
+    rowm &= ~(1ull << br);
+    colm &= ~(1ull << bc);
   }
+  __syncthreads();
   return margin;
 }
 
 // One block (64 lanes) per replica p.
+template <int EPL>
 __global__ __launch_bounds__(64) void align_kernel(int P, int Q, int R, int S,
                                                    const double* __restrict__ F,
                                                    const double* __restrict__ lam,
@@ -102,7 +127,7 @@ __global__ __launch_bounds__(64) void align_kernel(int P, int Q, int R, int S,
   double* ap = a0 + 3 * SR;        // [3][S][R] this replica's anchors
   double* sim = ap + 3 * SR;       // [R][R]
   __shared__ double c0[MAXR], cp[MAXR];
-  __shared__ int perm[MAXR], rowfree[MAXR], colfree[MAXR];
+  __shared__ int perm[MAXR];
   const int p = blockIdx.x, lane = threadIdx.x;
   const int64_t QR = (int64_t)Q * R;
   const double* F0 = F;
@@ -152,7 +177,7 @@ __global__ __launch_bounds__(64) void align_kernel(int P, int Q, int R, int S,
     sim[e] = s;
   }
   __syncthreads();
-  const double margin = greedy_wave(sim, R, perm, rowfree, colfree);
+  const double margin = greedy_wave<EPL>(sim, R, perm);
   if (lane == 0) margin_out[p] = margin;
   if (lane < R) perm_out[(int64_t)p * R + lane] = perm[lane];
   // least-squares scale of each anchor column onto the reference's
@@ -417,13 +442,14 @@ __global__ __launch_bounds__(256) void colscale_kernel(int64_t n, int R, const d
 }
 
 // cross: [2][R][R] = Ac^T Ap and Bc^T Bp; norms: [4][R] = |Ac|, |Ap|, |Bc|, |Bp|.
+template <int EPL>
 __global__ __launch_bounds__(64) void tmatch_kernel(int R, const double* __restrict__ cross,
                                                     const double* __restrict__ norms,
                                                     int* __restrict__ tperm,
                                                     double* __restrict__ tsign,
                                                     double* __restrict__ tmargin) {
   __shared__ double sim[MAXR * MAXR];
-  __shared__ int perm[MAXR], rowfree[MAXR], colfree[MAXR];
+  __shared__ int perm[MAXR];
   const int lane = threadIdx.x;
   const double* ca = cross;
   const double* cb = cross + R * R;
@@ -434,7 +460,7 @@ __global__ __launch_bounds__(64) void tmatch_kernel(int R, const double* __restr
     sim[e] = fabs(ca[e]) / (da > 0.0 ? da : 1.0) * fabs(cb[e]) / (db > 0.0 ? db : 1.0);
   }
   __syncthreads();
-  const double margin = greedy_wave(sim, R, perm, rowfree, colfree);
+  const double margin = greedy_wave<EPL>(sim, R, perm);
   if (lane < R) {
     const int c = perm[lane];
     const double a = ca[lane * R + c], b = cb[lane * R + c];
@@ -512,8 +538,15 @@ hipError_t rec_align(hipStream_t s, int P, int Q, int R, int S, const double* F,
   if (R > MAXR) return hipErrorInvalidValue;
   const int simn = R * R > 3 * R ? R * R : 3 * R;
   size_t lds = (size_t)(6 * S * R + simn) * sizeof(double);
-  hipLaunchKernelGGL(align_kernel, dim3(P), dim3(64), lds, s, P, Q, R, S, F, lam, aligned, perm,
-                     margin);
+  if (R * R <= 256)
+    hipLaunchKernelGGL(align_kernel<4>, dim3(P), dim3(64), lds, s, P, Q, R, S, F, lam, aligned,
+                       perm, margin);
+  else if (R * R <= 512)
+    hipLaunchKernelGGL(align_kernel<8>, dim3(P), dim3(64), lds, s, P, Q, R, S, F, lam, aligned,
+                       perm, margin);
+  else
+    hipLaunchKernelGGL(align_kernel<16>, dim3(P), dim3(64), lds, s, P, Q, R, S, F, lam, aligned,
+                       perm, margin);
   return hipGetLastError();
 }
 
@@ -621,8 +654,15 @@ hipError_t rec_copy3(hipStream_t s, double* d1, const double* s1, int64_t n1, do
 hipError_t rec_tmatch(hipStream_t s, int R, const double* cross, const double* norms, int* tperm,
                       double* tsign, double* tmargin) {
   if (R > MAXR) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(tmatch_kernel, dim3(1), dim3(64), 0, s, R, cross, norms, tperm, tsign,
-                     tmargin);
+  if (R * R <= 256)
+    hipLaunchKernelGGL(tmatch_kernel<4>, dim3(1), dim3(64), 0, s, R, cross, norms, tperm, tsign,
+                       tmargin);
+  else if (R * R <= 512)
+    hipLaunchKernelGGL(tmatch_kernel<8>, dim3(1), dim3(64), 0, s, R, cross, norms, tperm, tsign,
+                       tmargin);
+  else
+    hipLaunchKernelGGL(tmatch_kernel<16>, dim3(1), dim3(64), 0, s, R, cross, norms, tperm, tsign,
+                       tmargin);
   return hipGetLastError();
 }
 
