@@ -452,6 +452,54 @@ __global__ void rowdot_reduce_kernel(int64_t nrows, int ncols, int nsplit,
   *o = beta != 0.0 ? alpha * sum + beta * *o : alpha * sum;
 }
 
+// Small Gram-type products over a long index: part[g][i][r] = sum over the
+// k range of block g of A[k*sak + i] * B[k*sbk + r], i < n <= 32, r < ncols
+// <= 32.  Each block stages 64 rows of A and B in LDS at a time (every row
+// of both read once from HBM); thread t owns the pairs t + 256 j.  The
+// partials are summed in block order by rowdot_reduce_kernel.
+constexpr int GR_KB = 64;
+__global__ __launch_bounds__(256) void gram_part_kernel(int n, int ncols, int64_t K,
+                                                        const double* __restrict__ A, int64_t sak,
+                                                        const double* __restrict__ B, int64_t sbk,
+                                                        int64_t kchunk, double* __restrict__ part) {
+  __shared__ double As[GR_KB][33], Bs[GR_KB][33];
+  const int tid = threadIdx.x, np = n * ncols;
+  const int64_t k0 = (int64_t)blockIdx.x * kchunk;
+  const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
+  double acc[4];
+  int pi[4], pr[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = tid + 256 * j;
+    acc[j] = 0.0;
+    pi[j] = p < np ? p / ncols : 0;
+    pr[j] = p < np ? p % ncols : 0;
+  }
+  for (int64_t kb = k0; kb < k1; kb += GR_KB) {
+    for (int e = tid; e < GR_KB * 32; e += 256) {
+      const int kk = e >> 5, c = e & 31;
+      const int64_t k = kb + kk;
+      As[kk][c] = (k < k1 && c < n) ? A[k * sak + c] : 0.0;
+      Bs[kk][c] = (k < k1 && c < ncols) ? B[k * sbk + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (tid + 256 * j < np) {
+        double a = acc[j];
+        for (int kk = 0; kk < GR_KB; ++kk) a = fma(As[kk][pi[j]], Bs[kk][pr[j]], a);
+        acc[j] = a;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int p = tid + 256 * j;
+    if (p < np) part[(int64_t)blockIdx.x * np + p] = acc[j];
+  }
+}
+
 typedef double tg_f64x4 __attribute__((ext_vector_type(4)));
 constexpr int TG_KC = 128;   // k rows of B per LDS chunk
 
@@ -529,6 +577,24 @@ hipError_t rowdot(hipStream_t s, int64_t nrows, int ncols, int64_t K, const doub
     hipLaunchKernelGGL(tall_gemm_kernel, dim3((unsigned)((nrows + 63) / 64)), dim3(256), 0, s,
                        nrows, ncols, K, A, sai, B, sbk, alpha, beta, out, ldo);
     return hipGetLastError();
+  }
+  if (sai == 1 && sbr == 1 && !d && nrows <= 32 && ncols <= 32 && K >= 8192 && work) {
+    // R x R Gram-type product over a long index: blocks over k, partials
+    // summed in block order
+    const int64_t np = nrows * ncols;
+    int64_t g = K / 256;
+    if (g > 256) g = 256;
+    if (g * np > work_len) g = work_len / np;
+    if (g >= 2) {
+      int64_t kchunk = (K + g - 1) / g;
+      kchunk = (kchunk + GR_KB - 1) / GR_KB * GR_KB;
+      g = (K + kchunk - 1) / kchunk;
+      hipLaunchKernelGGL(gram_part_kernel, dim3((unsigned)g), dim3(256), 0, s, (int)nrows, ncols,
+                         K, A, sak, B, sbk, kchunk, work);
+      hipLaunchKernelGGL(rowdot_reduce_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0,
+                         s, nrows, ncols, (int)g, work, alpha, beta, out, ldo);
+      return hipGetLastError();
+    }
   }
   const int nblk = (ncols + 31) / 32;
   // split the long index when there are too few rows to fill the GPU; the
