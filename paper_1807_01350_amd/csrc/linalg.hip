@@ -446,7 +446,9 @@ __global__ void rowdot_reduce_kernel(int64_t nrows, int ncols, int nsplit,
   if (e >= nrows * ncols) return;
   const int64_t i = e / ncols;
   const int r = (int)(e % ncols);
+  // split order kept; eight partials loaded ahead of their adds
   double sum = 0.0;
+#pragma unroll 8
   for (int sp = 0; sp < nsplit; ++sp) sum += part[(int64_t)sp * nrows * ncols + e];
   double* o = out + i * ldo + r;
   *o = beta != 0.0 ? alpha * sum + beta * *o : alpha * sum;
