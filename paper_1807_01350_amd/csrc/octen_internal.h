@@ -31,7 +31,9 @@ hipError_t spd_invert(hipStream_t s, double* A, int n, double* work, int* info);
 // out(i, r) = alpha * sum_k A(i,k) d(k) B(k,r) + beta * out(i, r), i < nrows,
 // r < ncols; A(i,k) = A[i*sai + k*sak], B(k,r) = B[k*sbk + r*sbr]; d may be
 // null.  Tall products with unit inner strides (sak = sbr = 1, no d, at least
-// 16384 rows, ncols <= 32) run on FP64 MFMA with A streamed once; otherwise
+// 16384 rows, ncols <= 32) run on FP64 MFMA with A streamed once; small
+// Gram-type products (sai = sbr = 1, no d, nrows and ncols <= 32, K >= 8192,
+// work given) as k-blocked partials in LDS summed in block order; otherwise
 // one wavefront per row and block of 32 columns (small outputs, long k).
 // work (optional, work_len doubles): partial sums for splitting K when there
 // are few rows; without it, one wavefront covers all of K.
