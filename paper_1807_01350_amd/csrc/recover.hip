@@ -144,6 +144,7 @@ __global__ __launch_bounds__(64) void align_kernel(int P, int Q, int R, int S,
   if (p == 0) {
     if (lq < rpl)
       for (int n = 0; n < 3; ++n)
+#pragma unroll 8
         for (int q = lq; q < Q; q += rpl) {
           const int64_t e = n * QR + (int64_t)q * R + lr;
           Ap[e] = F0[e] * c0[lr];
@@ -196,6 +197,8 @@ __global__ __launch_bounds__(64) void align_kernel(int P, int Q, int R, int S,
     const int pr = perm[lr];
     for (int n = 0; n < 3; ++n) {
       const double d = sim[n * R + lr];
+      // eight rows' loads in flight before their stores
+#pragma unroll 8
       for (int q = lq; q < Q; q += rpl) {
         const int64_t e = n * QR + (int64_t)q * R + lr;
         Ap[n * QR + (int64_t)q * R + pr] = d * (Fp[e] * cp[lr]);
