@@ -41,11 +41,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--form", choices=("bf16", "f32"), default="bf16")
+    ap.add_argument("--form", choices=("bf16x2", "bf16", "f32"), default="bf16x2")
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--batch", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fit", action="store_true")
+    ap.add_argument("--no-gate", action="store_true",
+                    help="dense stream: skip the fit gate against the FP64 oracle")
     ap.add_argument("--overlap", action="store_true",
                     help="dense stream: a second pass that overlaps the next batch's "
                          "compression with the current batch's ALS and recovery")
@@ -90,33 +92,6 @@ def traffic_from_profile(form, source="compress_mfma.hip", profile=None):
     if not m or not b or m.group(1) != h:
         return None
     return float(b.group(1))
-
-
-def cpu_baseline(get_batch, n_batches, U, V, init, c, iters, min_seconds=10.0):
-    """The oracle, untuned, on consecutive batches of the same workload (the
-    first one from the given start, the next ones warm-started), until at least
-    min_seconds of CPU work or n_batches batches.  get_batch(b) returns the
-    batch's slices (numpy, f64) and its W rows."""
-    import oracle
-    threads = cores_used()
-    o = oracle.OctenOracle(c.I, c.J, c.R, c.P, c.Q, c.S, U, V)
-    dt, slices, done = 0.0, 0, 0
-    for b in range(n_batches):
-        Xb, Wb = get_batch(b)
-        t0 = time.perf_counter()
-        o.compress_batch(Xb, Wb)
-        o.update_replicas()
-        o.cp_als_replicas(iters, init=init if b == 0 else None)
-        o.recover_factors()
-        dt += time.perf_counter() - t0
-        slices += Xb.shape[0]
-        done += 1
-        if dt >= min_seconds:
-            break
-    return {"value": slices / dt, "unit": "slices/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} consecutive batches of {slices // done} slices of the same stream "
-                      f"through the FP64 oracle (compress, update, {iters} ALS sweeps on all "
-                      f"{c.P} replicas, recover), {dt:.1f} s in total"}
 
 
 def cores_used():
@@ -370,8 +345,9 @@ def run_batched(args):
         A = torch.rand((I, R), generator=g, device=dev, dtype=f64)
         B = torch.rand((J, R), generator=g, device=dev, dtype=f64)
         C = torch.rand(((rounds + 1) * t, R), generator=g, device=dev, dtype=f64)
-        U = torch.randn((I, M1), generator=g, device=dev, dtype=f64)
-        V = torch.randn((J, M1), generator=g, device=dev, dtype=f64)
+        # N(0,1) compression matrices on the bfloat16 grid (as synth draws them)
+        U = torch.randn((I, M1), generator=g, device=dev, dtype=f64).float().bfloat16().double()
+        V = torch.randn((J, M1), generator=g, device=dev, dtype=f64).float().bfloat16().double()
         eng = oc.Octen(I, J, R, P, Q, S, U, V, x_dtype="f32", compress_dtype=args.form)
         X = torch.empty((t, I, J), dtype=torch.float32, device=dev)
         W = torch.empty((t, M1), dtype=f64, device=dev)
@@ -508,11 +484,11 @@ def run_forms(args):
           for b in range(nsteps + 1)]
     init = torch.from_numpy(synth.als_init(c.P, c.Q, c.R, c.config_id)).to(dev)
     results = {}
-    for form in ("fp32_plain", "bf16_graph_learned"):
+    for form in ("fp32_plain", "bf16x2_graph_learned"):
         bf = form.startswith("bf16")
         e = oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, torch.from_numpy(U).to(dev),
                      torch.from_numpy(V).to(dev), x_dtype="f32",
-                     compress_dtype="bf16" if bf else "f32")
+                     compress_dtype="bf16x2" if bf else "f32")
         A = torch.empty((c.I, c.R), dtype=torch.float64, device=dev)
         B = torch.empty((c.J, c.R), dtype=torch.float64, device=dev)
         C = torch.empty((K, c.R), dtype=torch.float64, device=dev)
@@ -561,11 +537,11 @@ def run_forms(args):
         e.close()
         print(f"[bench] {form}: {results[form]}", file=sys.stderr, flush=True)
     net.close()
-    a, b = results["fp32_plain"], results["bf16_graph_learned"]
+    a, b = results["fp32_plain"], results["bf16x2_graph_learned"]
     out = {
         "metric": METRIC, "value": b["slices_per_s"], "unit": "slices/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x2",
         "data": "synthetic (seeded on-device generator; rank-10 U[0,1] CP model + N(0, 0.01^2))",
         "config": {"workload": f"dense1000_f32 forms: {c.t0} initial slices then batches of {t}; "
                                f"P=12, Q=60, S=3; ALS until the replica fit changes by less than "
@@ -581,20 +557,46 @@ def run_forms(args):
     print(json.dumps(out))
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
-              "multi-GPU path", file=sys.stderr)
-        sys.exit(2)
-    if args.workload == "sparse":
-        return run_sparse(args)
-    if args.workload == "forms":
-        return run_forms(args)
-    if args.workload == "batched":
-        if args.warmup + args.steps > 4:
-            args.warmup, args.steps = 1, 3
-        return run_batched(args)
+def oracle_gate(X, c, t0, t, nb, U, V, Ws, init, iters):
+    """The FP64 oracle over the first nb + 1 batches of the stream (t0
+    initial slices, then nb batches of t), each downloaded from the device:
+    the fit of Sec. 5.1 over all slices seen after every batch, and the wall
+    time of the nb update batches (compress, update, ALS, recover; the fit is
+    not timed)."""
+    import oracle
+    o = oracle.OctenOracle(c.I, c.J, c.R, c.P, c.Q, c.S, U, V)
+    host = []
+    fits, dt = [], 0.0
+    k0 = 0
+    for b in range(nb + 1):
+        tt = t0 if b == 0 else t
+        xb = X[k0:k0 + tt].cpu().numpy()
+        host.append(xb)
+        t_start = time.perf_counter()
+        o.compress_batch(xb.astype(np.float64), Ws[b])
+        o.update_replicas()
+        o.cp_als_replicas(iters, init=init if b == 0 else None)
+        A, B, C = o.recover_factors()
+        if b > 0:
+            dt += time.perf_counter() - t_start
+        k0 += tt
+        sse = nx = 0.0
+        q = 0
+        for xs in host:
+            _, s1, n1 = oracle.fit_dense(xs, A, B, C, k0=q)
+            sse += s1
+            nx += n1
+            q += xs.shape[0]
+        fits.append(1.0 - float(np.sqrt(sse / nx)))
+        print(f"[bench] oracle batch {b}: fit {fits[-1]:.6f}", file=sys.stderr, flush=True)
+    return fits, dt
+
+
+def run_dense(args):
+    """The dense 1000 x 1000 stream: the fit gate over exactly its 500
+    initial slices and ten batches of 50 (GPU and FP64 oracle on the same
+    slices, fit after every batch), then warmup and timed batches continuing
+    the same stream."""
     import torch
     from paper_1807_01350_amd import octen as oc
     from paper_1807_01350_amd import synth
@@ -603,9 +605,11 @@ def main():
     torch.cuda.set_device(0)
     c = synth.C2
     t = args.batch
+    ngate = len(c.batches) if not args.no_gate else 0
     nsteps = args.warmup + args.steps
-    nbatch = nsteps + (args.steps if args.overlap else 0)
+    nbatch = ngate + nsteps + (args.steps if args.overlap else 0)
     K = c.t0 + t * nbatch
+    print(f"[bench] generating {K} slices", file=sys.stderr, flush=True)
     X = gen_stream(torch, c.I, c.J, K, c.R, c.sigma, synth.seed_of(c.config_id, 1), dev)
     U, V = synth.compression_UV(c.I, c.J, c.P, c.Q, c.S, c.config_id)
     Ws = [synth.temporal_W(c.t0 if b == 0 else t, c.M1, c.config_id, b) for b in range(nbatch + 1)]
@@ -625,17 +629,42 @@ def main():
         eng.cp_als_replicas(args.iters, init=tinit if b == 0 else None)
         eng.recover_factors_async(A, B, C)
 
+    def gpu_fit():
+        sse = nx = 0.0
+        for q0 in range(0, eng.K, 100):
+            q1 = min(eng.K, q0 + 100)
+            sse, nx = eng.fit_terms(X[q0:q1], q0, A, B, C, acc=(sse, nx))
+        return 1.0 - float(np.sqrt(sse / nx))
+
     # initial summary (untimed), tuning of the compression kernel and of the
-    # ALS launch shape on it (untimed), then warmup batches
+    # ALS launch shape on it (untimed)
     step(0, 0, c.t0)
     tuned = {"compress": eng.autotune(X[c.t0:c.t0 + t]), "als": eng.autotune_als(20)}
     k0 = c.t0
-    for b in range(1, args.warmup + 1):
+    gate = None
+    if ngate:
+        # the fit gate: the stream's own ten batches, the fit after each
+        fits_gpu = [gpu_fit()]
+        for b in range(1, ngate + 1):
+            step(b, k0, t)
+            k0 += t
+            fits_gpu.append(gpu_fit())
+            print(f"[bench] gate batch {b}: gpu fit {fits_gpu[-1]:.6f}", file=sys.stderr, flush=True)
+        fits_or, t_or = oracle_gate(X, c, c.t0, t, ngate, U, V, Ws, init, args.iters)
+        d = [abs(a - b) for a, b in zip(fits_gpu, fits_or)]
+        gate = {"stream": f"{c.t0} initial slices then {ngate} batches of {t} (K = {k0})",
+                "form": args.form, "fit_gpu": [round(x, 6) for x in fits_gpu],
+                "fit_oracle": [round(x, 6) for x in fits_or],
+                "max_abs_dfit": max(d), "bar": 1e-3, "pass": bool(max(d) <= 1e-3),
+                "oracle_update_s": t_or}
+    torch.cuda.synchronize()
+    b0 = ngate + 1
+    for b in range(b0, b0 + args.warmup):
         step(b, k0, t)
         k0 += t
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for b in range(args.warmup + 1, nsteps + 1):
+    for b in range(b0 + args.warmup, b0 + nsteps):
         step(b, k0, t)
         k0 += t
     torch.cuda.synchronize()
@@ -654,27 +683,33 @@ def main():
         "als": last(oc.OCTEN_STAGE_ALS),
         "recover": last(oc.OCTEN_STAGE_RECOVER),
     }
-    # algorithmic bytes / flops of one launch of the compression kernel (modes 1, 2)
-    esz = 2 if args.form == "bf16" else 4
+    # algorithmic bytes / flops of one launch of the compression kernel
+    # (modes 1, 2): X once, the U and V images once; the flops of the plain
+    # product (the two-term form runs twice as many matrix-core products)
+    esz = 4 if args.form == "f32" else 2
     bytes_launch = t * c.I * c.J * 4 + (c.I + c.J) * c.M1 * esz
     flops_launch = 2.0 * t * c.I * c.J * c.M1 + 2.0 * t * c.I * c.P * c.Q * c.Q
+    mfma_flops = flops_launch * (2 if args.form == "bf16x2" else 1)
     kms = st["compress_main"]
     gbs = bytes_launch / (kms * 1e-3) / 1e9
-    tflops = flops_launch / (kms * 1e-3) / 1e12
+    tflops = mfma_flops / (kms * 1e-3) / 1e12
     traffic = traffic_from_profile(args.form)
-    if args.form == "bf16":
-        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
-    else:
+    if args.form == "f32":
         roof = {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_PEAK_TFLOPS["f32"],
                 "unit": "TFLOP/s", "frac": round(tflops / MFMA_PEAK_TFLOPS["f32"], 4),
                 "traffic": traffic}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
     kname = {0: "compress_pipe", 1: "compress_fused (16-byte loads)", 2: "compress_fused",
              3: "compress_pipe2"}.get(tuned["compress"] % 10, "compress")
+    if args.form == "bf16x2":
+        kname = "compress_pipe2 two-term"
     roof["kernel"] = f"{kname} (modes 1 and 2 of the batch compression)"
     roof["algorithmic_bytes_per_launch"] = bytes_launch
     roof["algorithmic_flops_per_launch"] = flops_launch
-    roof["mfma_frac"] = round(tflops / MFMA_PEAK_TFLOPS[args.form], 4)
+    roof["mfma_flops_per_launch"] = mfma_flops
+    roof["mfma_frac"] = round(tflops / MFMA_PEAK_TFLOPS["bf16" if args.form != "f32" else "f32"], 4)
 
     overlap = None
     if args.overlap:
@@ -683,7 +718,7 @@ def main():
         # compression on the handle's second stream, overlapping the current
         # batch's ALS and recovery; every batch still goes through compress,
         # update, ALS and recovery
-        b1 = nsteps + 1
+        b1 = b0 + nsteps
         torch.cuda.synchronize()
         t_ov = time.perf_counter()
         eng.compress_batch_async(X[k0:k0 + t], tW[b1])
@@ -703,18 +738,15 @@ def main():
 
     fit = None
     if not args.no_fit:
-        sse = nx = 0.0
-        for q0 in range(0, eng.K, 100):
-            q1 = min(eng.K, q0 + 100)
-            sse, nx = eng.fit_terms(X[q0:q1], q0, A, B, C, acc=(sse, nx))
-        fit = 1.0 - float(np.sqrt(sse / nx))
+        fit = gpu_fit()
 
     cpu = None
-    if not args.no_cpu_baseline:
-        def get_batch(b):
-            kb = c.t0 + t * (args.warmup + b)
-            return X[kb:kb + t].double().cpu().numpy(), Ws[args.warmup + 1 + b]
-        cpu = cpu_baseline(get_batch, min(4, args.steps), U, V, init, c, args.iters)
+    if gate is not None and not args.no_cpu_baseline:
+        cpu = {"value": ngate * t / gate["oracle_update_s"], "unit": "slices/s",
+               "cores": cores_used(), "kind": "oracle",
+               "sample": f"the {ngate} update batches of {t} slices of the gate run through the "
+                         f"FP64 oracle (compress, update, {args.iters} ALS sweeps on all {c.P} "
+                         f"replicas, recover), {gate['oracle_update_s']:.1f} s in total"}
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "slices/s", "n_gpus": 1,
@@ -723,9 +755,13 @@ def main():
         "data": "synthetic (seeded on-device generator; rank-10 U[0,1] CP model + N(0, 0.01^2))",
         "config": {"workload": f"dense1000_f32: I=J=1000, R=10, {c.t0} initial slices then "
                                f"batches of {t}; P=12, Q=60, S=3; {args.iters} ALS sweeps; "
-                               f"{args.form} compression, f64 solves",
+                               f"{args.form} compression, f64 solves; timed batches continue the "
+                               f"stream after its ten gate batches",
                    "I": c.I, "J": c.J, "R": c.R, "P": c.P, "Q": c.Q, "S": c.S, "batch": t,
                    "initial_slices": c.t0, "als_iters": args.iters, "compress_dtype": args.form},
+        "fit_gate": gate,
+        "fit_oracle": gate["fit_oracle"][-1] if gate else None,
+        "abs_dfit": gate["max_abs_dfit"] if gate else None,
         "compression_gbs": round(gbs, 1),
         "compression_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
         "stage_ms": {k: (round(v, 4) if v is not None else None) for k, v in st.items()},
@@ -737,6 +773,23 @@ def main():
     }
     eng.close()
     print(json.dumps(out))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "sparse":
+        return run_sparse(args)
+    if args.workload == "forms":
+        return run_forms(args)
+    if args.workload == "batched":
+        if args.warmup + args.steps > 4:
+            args.warmup, args.steps = 1, 3
+        return run_batched(args)
+    return run_dense(args)
 
 
 if __name__ == "__main__":

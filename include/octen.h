@@ -55,7 +55,19 @@ typedef enum {
   OCTEN_ERR_UNSUPPORTED = 6  /* valid request this build does not implement */
 } octen_status;
 
-typedef enum { OCTEN_F64 = 0, OCTEN_F32 = 1, OCTEN_BF16 = 2, OCTEN_F16 = 3 } octen_dtype;
+/* Element and arithmetic types.  OCTEN_BF16X2 is the two-term bfloat16 form
+ * of the compression: every slice value x enters the matrix cores as
+ * hi = bf16(x) and lo = bf16(x - hi) (16 significant bits), both multiplied
+ * into float32 accumulators, and the intermediate mode-2 product is carried
+ * into the mode-1 product the same way; it needs compression matrices whose
+ * entries are bfloat16 values.  OCTEN_F16 is reserved (not implemented). */
+typedef enum {
+  OCTEN_F64 = 0,
+  OCTEN_F32 = 1,
+  OCTEN_BF16 = 2,
+  OCTEN_F16 = 3,
+  OCTEN_BF16X2 = 4
+} octen_dtype;
 
 /* ALS starting point (octen_cp_als_replicas). */
 enum { OCTEN_INIT_GIVEN = 0, OCTEN_INIT_PREV = 1, OCTEN_INIT_LEARNED = 2 };
@@ -119,10 +131,14 @@ typedef struct {
   int32_t Q;               /* replica side Q (Sec. 4.1), S < Q <= 128, R <= Q  */
   int32_t S;               /* shared anchor columns (Eq. 1), S >= 1            */
   int32_t x_dtype;         /* element type of X: OCTEN_F64 or OCTEN_F32        */
-  int32_t compress_dtype;  /* compression arithmetic: F64, F32 or BF16 inputs;
-                              accumulation is F64 for F64, else F32           */
-  int32_t als_dtype;       /* MTTKRP arithmetic: OCTEN_F64 or OCTEN_F32;
-                              R x R solves and recovery are always F64        */
+  int32_t compress_dtype;  /* compression arithmetic: F64, F32, BF16 or BF16X2
+                              inputs; accumulation is F64 for F64, else F32;
+                              BF16X2 needs U and V on the bfloat16 grid
+                              (OCTEN_ERR_ARG otherwise), F16 gives
+                              OCTEN_ERR_UNSUPPORTED                          */
+  int32_t als_dtype;       /* MTTKRP arithmetic: OCTEN_F64 (anything else gives
+                              OCTEN_ERR_UNSUPPORTED); R x R solves and
+                              recovery are always F64                         */
   int64_t I;               /* mode-1 size I (problem statement, Sec. 3)        */
   int64_t J;               /* mode-2 size J                                    */
   uint64_t flags;          /* OCTEN_FLAG_*                                     */

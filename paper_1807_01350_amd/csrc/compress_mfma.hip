@@ -108,7 +108,115 @@ struct Args {
   int t, P, Q, G, ncb, nrb, nchunk, tiles;
 };
 
-template <int KIND, int QT, bool VEC>
+// Stage 2 of the two-term form, shared by the bfloat16 kernels: T (the
+// float32 stage-1 accumulators of a BM x BN tile, in the 32x32 MFMA output
+// layout of a 4 x 2 grid of wavefronts) goes through the LDS buffer T2t twice,
+// first as T_hi = bf16(T), then as T_lo = bf16(T - T_hi); each work item (one
+// 32-row tile of one replica's Q x Q output) accumulates both passes.  T_lo
+// is formed with T_hi and kept packed (two values per register) until the
+// second pass, so the float32 accumulators die after the first write.
+template <int QT, int SPLIT>
+__device__ __forceinline__ void stage2_split(const Args& g, const f32x16 (&acc)[2][4], __bf16* T2t,
+                                             int k, int rb, int cb, float sc) {
+  constexpr int BM = Tile<2>::BM, NT = Tile<2>::NT, E = 8;
+  constexpr int T2LD = BM + 8;
+  using T = __bf16;
+  using Frag = bf16x8;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const int p0 = cb * g.G;
+  const int gcount = (g.P - p0) < g.G ? (g.P - p0) : g.G;
+  const int nitems = gcount * QT;
+  const float inv = 1.0f / sc;
+  constexpr int KS = 16;
+  bf16x4 lo[2][4][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = wn * 128 + j * 32 + lane % 32;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = wm * 64 + i * 32 + 8 * q + 4 * (lane / 32);
+        bf16x4 hi;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float v = acc[i][j][4 * q + e];
+          hi[e] = (T)v;
+          lo[i][j][q][e] = (T)(v - (float)hi[e]);
+        }
+        *(bf16x4*)(T2t + col * T2LD + r) = hi;
+      }
+    }
+  f32x16 m[SPLIT][QT];
+#pragma unroll
+  for (int it = 0; it < SPLIT; ++it)
+#pragma unroll
+    for (int j = 0; j < QT; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) m[it][j][e] = 0.f;
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int col = wn * 128 + j * 32 + lane % 32;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = wm * 64 + i * 32 + 8 * q + 4 * (lane / 32);
+            *(bf16x4*)(T2t + col * T2LD + r) = lo[i][j][q];
+          }
+        }
+    }
+    for (int e = tid; e < T2LD; e += NT) T2t[BN * T2LD + e] = (T)0.f;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < SPLIT; ++it) {
+      const int item = wave + it * (NT / 64);
+      if (item >= nitems) continue;
+      const int gg = item / QT, i = item % QT;
+      const int p = p0 + gg;
+      const T* Up = (const T*)g.Upack + ((int64_t)rb * g.P + p) * (BM / KS) * QT * 64 * E;
+      const int* tc = g.tilecol + ((int64_t)cb * g.G + gg) * QT * 32;
+      int colrow[QT];
+#pragma unroll
+      for (int j = 0; j < QT; ++j) colrow[j] = tc[j * 32 + lane % 32];
+#pragma unroll 2
+      for (int ks = 0; ks < BM / KS; ++ks) {
+        const Frag af = *(const Frag*)(Up + ((int64_t)(ks * QT + i) * 64 + lane) * E);
+#pragma unroll
+        for (int j = 0; j < QT; ++j) {
+          const Frag bf = *(const Frag*)(T2t + colrow[j] * T2LD + ks * KS + (lane / 32) * E);
+          m[it][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bf, m[it][j], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int it = 0; it < SPLIT; ++it) {
+    const int item = wave + it * (NT / 64);
+    if (item >= nitems) continue;
+    const int gg = item / QT, i = item % QT;
+    const int p = p0 + gg;
+    float* out = g.Mpart + (((int64_t)k * g.nrb + rb) * g.P + p) * g.Q * g.Q;
+#pragma unroll
+    for (int j = 0; j < QT; ++j) {
+      const int bcol = j * 32 + lane % 32;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int arow = i * 32 + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+        if (arow < g.Q && bcol < g.Q) out[arow * g.Q + bcol] = m[it][j][e] * inv;
+      }
+    }
+  }
+}
+
+// SPLIT > 0 (bfloat16 only): the two-term form of compress_pipe2, with the
+// hi and lo images of each X chunk side by side in LDS.
+template <int KIND, int QT, bool VEC, int SPLIT>
 __global__ __launch_bounds__(Tile<KIND>::NT) void compress_fused(Args g) {
   constexpr int BM = Tile<KIND>::BM, NT = Tile<KIND>::NT;
   using T = typename Kind<KIND>::T;
@@ -118,8 +226,9 @@ __global__ __launch_bounds__(Tile<KIND>::NT) void compress_fused(Args g) {
   constexpr int B_EL = chunk_elems<KIND>(BN / 32);   // B chunk image elements
   constexpr int T2LD = BM + 16 / (int)sizeof(T);     // padded row of T^T
   extern __shared__ __align__(16) unsigned char smem[];
-  T* As = (T*)smem;                 // [2][A_EL]
-  T* Bs = As + 2 * A_EL;            // [2][B_EL]
+  constexpr int NPART = SPLIT > 0 ? 2 : 1;
+  T* As = (T*)smem;                 // [2][NPART][A_EL]
+  T* Bs = As + 2 * NPART * A_EL;    // [2][B_EL]
   T* T2t = (T*)smem;                // [BN + 1][T2LD], reuses the staging buffers
 
   // XCD-aware tile index
@@ -165,15 +274,24 @@ __global__ __launch_bounds__(Tile<KIND>::NT) void compress_fused(Args g) {
 
 #define OCTEN_STORE_CHUNK(buf)                                                       \
   do {                                                                               \
-    T* a_ = As + (buf) * A_EL;                                                       \
+    T* a_ = As + (buf) * NPART * A_EL;                                               \
     if constexpr (KIND == 2) {                                                       \
-      bf16x8 lo, hi;                                                                 \
+      bf16x8 h0, h1, l0, l1;                                                         \
       _Pragma("unroll") for (int q = 0; q < 8; ++q) {                                \
-        lo[q] = (__bf16)(xr[q] * sc);                                                \
-        hi[q] = (__bf16)(xr[8 + q] * sc);                                            \
+        const float x0 = xr[q] * sc, x1 = xr[8 + q] * sc;                            \
+        h0[q] = (__bf16)x0;                                                          \
+        h1[q] = (__bf16)x1;                                                          \
+        if constexpr (SPLIT > 0) {                                                   \
+          l0[q] = (__bf16)(x0 - (float)h0[q]);                                       \
+          l1[q] = (__bf16)(x1 - (float)h1[q]);                                       \
+        }                                                                            \
       }                                                                              \
-      *(bf16x8*)(a_ + a_pos<KIND>(lr, lh * 16)) = lo;                                \
-      *(bf16x8*)(a_ + a_pos<KIND>(lr, lh * 16 + 8)) = hi;                            \
+      *(bf16x8*)(a_ + a_pos<KIND>(lr, lh * 16)) = h0;                                \
+      *(bf16x8*)(a_ + a_pos<KIND>(lr, lh * 16 + 8)) = h1;                            \
+      if constexpr (SPLIT > 0) {                                                     \
+        *(bf16x8*)(a_ + A_EL + a_pos<KIND>(lr, lh * 16)) = l0;                       \
+        *(bf16x8*)(a_ + A_EL + a_pos<KIND>(lr, lh * 16 + 8)) = l1;                   \
+      }                                                                              \
     } else {                                                                         \
       _Pragma("unroll") for (int q = 0; q < 16; ++q)                                 \
         a_[a_pos<KIND>(lr, lh * 16 + q)] = cvt<KIND>(xr[q] * sc);                    \
@@ -196,21 +314,27 @@ __global__ __launch_bounds__(Tile<KIND>::NT) void compress_fused(Args g) {
   for (int c = 0; c < g.nchunk; ++c) {
     const int buf = c & 1;
     if (c + 1 < g.nchunk) OCTEN_LOAD_CHUNK(c + 1);
-    const T* a = As + buf * A_EL;
+    const T* a = As + buf * NPART * A_EL;
     const T* b = Bs + buf * B_EL;
 #pragma unroll
     for (int ks = 0; ks < KC / KS; ++ks) {
-      Frag af[2], bfr[4];
+      Frag af[2], al[2], bfr[4];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i) {
         af[i] = Kind<KIND>::ld(a + ((ks * (BM / 32) + wm * 2 + i) * 64 + lane) * E);
+        if constexpr (SPLIT > 0)
+          al[i] = Kind<KIND>::ld(a + A_EL + ((ks * (BM / 32) + wm * 2 + i) * 64 + lane) * E);
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         bfr[j] = Kind<KIND>::ld(b + ((ks * (BN / 32) + wn * 4 + j) * 64 + lane) * E);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = Kind<KIND>::mma(af[i], bfr[j], acc[i][j]);
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j] = Kind<KIND>::mma(af[i], bfr[j], acc[i][j]);
+          if constexpr (SPLIT > 0) acc[i][j] = Kind<KIND>::mma(al[i], bfr[j], acc[i][j]);
+        }
     }
     if (c + 1 < g.nchunk) OCTEN_STORE_CHUNK(buf ^ 1);
     __syncthreads();
@@ -219,6 +343,10 @@ __global__ __launch_bounds__(Tile<KIND>::NT) void compress_fused(Args g) {
 #undef OCTEN_LOAD_CHUNK
 #undef OCTEN_STORE_CHUNK
 
+  if constexpr (SPLIT > 0) {
+    stage2_split<QT, SPLIT>(g, acc, (__bf16*)smem, k, rb, cb, sc);
+    return;
+  }
   // ---- stage 2: T^T into LDS (in the MFMA input type), zero row at BN
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -509,7 +637,18 @@ constexpr int KC2 = 16;
 
 __device__ __forceinline__ int swz4(int m) { return ((m >> 1) ^ (m >> 2)) & 3; }
 
-template <int QT, bool SCALED>
+//
+// SPLIT > 0 selects the two-term form: every X value x (after the scale) is
+// the pair hi = bf16(x), lo = bf16(x - hi), both multiplied by the same V
+// fragment into the same float32 accumulators, so stage 1 sees x to 16
+// significant bits.  Stage 2 then takes T as the pair T_hi, T_lo in two
+// passes through the same LDS buffer, accumulating into the same output
+// tiles.  The V and U images must hold the compression matrices exactly
+// (they are on the bfloat16 grid; checked when the plan is made).  In this
+// form a work item is one 32-row tile of one replica's output, and SPLIT is
+// the number of items per wavefront (their accumulators stay live across
+// both passes).
+template <int QT, bool SCALED, int SPLIT>
 __global__ __launch_bounds__(Tile<2>::NT) void compress_pipe2(Args g) {
   constexpr int BM = Tile<2>::BM, NT = Tile<2>::NT;
   using T = __bf16;
@@ -606,22 +745,28 @@ __global__ __launch_bounds__(Tile<2>::NT) void compress_pipe2(Args g) {
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
   auto mfmas = [&](const Frags& f) {
-    Frag af[2];
+    Frag af[2], al[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      bf16x8 v;
+      bf16x8 v, w;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        v[e] = (__bf16)(SCALED ? f.a[i][0][e] * sc : f.a[i][0][e]);
-        v[4 + e] = (__bf16)(SCALED ? f.a[i][1][e] * sc : f.a[i][1][e]);
+      for (int e = 0; e < 8; ++e) {
+        const float x = e < 4 ? f.a[i][0][e] : f.a[i][1][e - 4];
+        const float xs = SCALED ? x * sc : x;
+        v[e] = (__bf16)xs;
+        if constexpr (SPLIT > 0) w[e] = (__bf16)(xs - (float)v[e]);
       }
       af[i] = v;
+      if constexpr (SPLIT > 0) al[i] = w;
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j) {
         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], f.b[j], acc[i][j], 0, 0, 0);
+        if constexpr (SPLIT > 0)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], f.b[j], acc[i][j], 0, 0, 0);
+      }
   };
 
   // prologue: chunks 0 .. NS2 - 1 in flight; chunks 0 and 1 landed
@@ -652,6 +797,9 @@ __global__ __launch_bounds__(Tile<2>::NT) void compress_pipe2(Args g) {
   if (c < n2) step(c, f0, f1);
   __syncthreads();
 
+  if constexpr (SPLIT > 0) {
+    stage2_split<QT, SPLIT>(g, acc, T2t, k, rb, cb, sc);
+  } else {
   // ---- stage 2 (as in compress_pipe)
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -720,6 +868,7 @@ __global__ __launch_bounds__(Tile<2>::NT) void compress_pipe2(Args g) {
       }
     }
   }
+  }
 }
 
 // V image: [cb][chunk][ks][nt][lane][E]; element V[j][col] with
@@ -779,9 +928,9 @@ inline int grid_for(int64_t n) {
   return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
 }
 
-template <int KIND, int QT, bool VEC>
+template <int KIND, int QT, bool VEC, int SPLIT = 0>
 hipError_t launch_fused(hipStream_t s, const Args& a, size_t lds) {
-  auto fn = compress_fused<KIND, QT, VEC>;
+  auto fn = compress_fused<KIND, QT, VEC, SPLIT>;
   hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -808,13 +957,13 @@ hipError_t launch_pipe(hipStream_t s, const Args& a) {
   return hipGetLastError();
 }
 
-template <int QT, bool SCALED>
+template <int QT, bool SCALED, int SPLIT>
 hipError_t launch_pipe2(hipStream_t s, const Args& a) {
   constexpr int BM = Tile<2>::BM;
   constexpr size_t stage = (size_t)BM * KC2 * 4 + (size_t)(BN / 32) * 64 * 8 * 2;
   const size_t t2 = (size_t)(BN + 1) * (BM + 8) * 2;
   const size_t lds = NS2 * stage > t2 ? NS2 * stage : t2;
-  auto fn = compress_pipe2<QT, SCALED>;
+  auto fn = compress_pipe2<QT, SCALED, SPLIT>;
   hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -825,10 +974,37 @@ hipError_t launch_pipe2(hipStream_t s, const Args& a) {
 
 hipError_t launch_pipe2_q(hipStream_t s, const Args& a, int QT) {
   switch (QT) {
-    case 1: return a.scale ? launch_pipe2<1, true>(s, a) : launch_pipe2<1, false>(s, a);
-    case 2: return a.scale ? launch_pipe2<2, true>(s, a) : launch_pipe2<2, false>(s, a);
-    case 3: return a.scale ? launch_pipe2<3, true>(s, a) : launch_pipe2<3, false>(s, a);
-    case 4: return a.scale ? launch_pipe2<4, true>(s, a) : launch_pipe2<4, false>(s, a);
+    case 1: return a.scale ? launch_pipe2<1, true, 0>(s, a) : launch_pipe2<1, false, 0>(s, a);
+    case 2: return a.scale ? launch_pipe2<2, true, 0>(s, a) : launch_pipe2<2, false, 0>(s, a);
+    case 3: return a.scale ? launch_pipe2<3, true, 0>(s, a) : launch_pipe2<3, false, 0>(s, a);
+    case 4: return a.scale ? launch_pipe2<4, true, 0>(s, a) : launch_pipe2<4, false, 0>(s, a);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int QT, int SPLIT>
+hipError_t launch_split(hipStream_t s, const Args& a, bool vec, size_t lds) {
+  if (!vec) return launch_fused<2, QT, false, SPLIT>(s, a, lds);
+  return a.scale ? launch_pipe2<QT, true, SPLIT>(s, a) : launch_pipe2<QT, false, SPLIT>(s, a);
+}
+
+// Two-term form: ceil(G * QT / 8) work items per wavefront, each holding QT
+// accumulator tiles; plans keep items * QT <= 4.
+int split_items(int G, int QT) { return (G * QT + 7) / 8; }
+
+hipError_t launch_split_q(hipStream_t s, const Args& a, int QT, bool vec, size_t lds) {
+  const int items = split_items(a.G, QT);
+  if (items * QT > 4) return hipErrorInvalidValue;
+  switch (QT) {
+    case 1:
+      if (items <= 1) return launch_split<1, 1>(s, a, vec, lds);
+      if (items <= 2) return launch_split<1, 2>(s, a, vec, lds);
+      return launch_split<1, 4>(s, a, vec, lds);
+    case 2:
+      if (items <= 1) return launch_split<2, 1>(s, a, vec, lds);
+      return launch_split<2, 2>(s, a, vec, lds);
+    case 3: return launch_split<3, 1>(s, a, vec, lds);
+    case 4: return launch_split<4, 1>(s, a, vec, lds);
   }
   return hipErrorInvalidValue;
 }
@@ -859,7 +1035,7 @@ hipError_t launch_q(hipStream_t s, const Args& a, int QT, size_t lds) {
 
 struct MfmaPlan {
   CompressShape sh;
-  int kind = 0;   // 1 f32, 2 bf16
+  int kind = 0;   // 1 f32, 2 bf16, 3 two-term bf16
   int variant = 0;  // 0 pipelined, 1 register-staged 16-byte loads, 2 scalar loads,
                     // 3 half chunks with register double buffering (bf16 only)
   int G = 0, ncb = 0, nrb = 0, nchunk = 0, QT = 0;
@@ -870,9 +1046,28 @@ struct MfmaPlan {
   size_t lds = 0;
 };
 
-int mfma_plan_max_G(const CompressShape& sh) {
+int mfma_plan_max_G(const CompressShape& sh, int kind) {
   int G = (BN - sh.S) / (sh.Q - sh.S);
+  if (kind == 3) {
+    // the two-term stage 2 keeps its work items' accumulators live across
+    // both passes: items per wavefront * QT <= 4
+    const int QT = (sh.Q + 31) / 32;
+    const int gmax = QT == 1 ? 32 : (QT == 2 ? 8 : 2);
+    if (G > gmax) G = gmax;
+  }
   return G > sh.P ? sh.P : G;
+}
+
+// Counts entries of A (n doubles) that are not bfloat16 values.
+__global__ void off_bf16_grid_kernel(const double* __restrict__ A, int64_t n, int* __restrict__ count) {
+  int c = 0;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const double v = A[x];
+    const __bf16 b = (__bf16)(float)v;
+    c += ((double)(float)b != v) ? 1 : 0;
+  }
+  if (c) atomicAdd(count, c);
 }
 
 int mfma_plan_G(const MfmaPlan* p) { return p->G; }
@@ -882,19 +1077,39 @@ int mfma_plan_variant(const MfmaPlan* p) { return p->variant; }
 hipError_t mfma_plan_create(const CompressShape& sh, int in_kind, const double* U, const double* V,
                             hipStream_t s, MfmaPlan** out, int G_request) {
   *out = nullptr;
-  if (in_kind != 1 && in_kind != 2) return hipErrorInvalidValue;
+  if (in_kind != 1 && in_kind != 2 && in_kind != 3) return hipErrorInvalidValue;
   const int P = sh.P, Q = sh.Q, S = sh.S, M1 = sh.M1;
   if (Q > 128 || S + (Q - S) > BN) return hipErrorNotSupported;
+  if (in_kind == 3) {
+    // the two-term form multiplies the images of U and V as they are: they
+    // must hold the compression matrices exactly
+    int* cnt = nullptr;
+    hipError_t e = hipMalloc(&cnt, sizeof(int));
+    if (e != hipSuccess) return e;
+    int h = 0;
+    e = hipMemsetAsync(cnt, 0, sizeof(int), s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(off_bf16_grid_kernel, dim3(grid_for(sh.I * M1)), dim3(256), 0, s, U,
+                         sh.I * (int64_t)M1, cnt);
+      hipLaunchKernelGGL(off_bf16_grid_kernel, dim3(grid_for(sh.J * M1)), dim3(256), 0, s, V,
+                         sh.J * (int64_t)M1, cnt);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, cnt, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(cnt);
+    if (e != hipSuccess) return e;
+    if (h != 0) return hipErrorInvalidValue;
+  }
   MfmaPlan* p = new MfmaPlan();
   p->sh = sh;
   p->kind = in_kind;
-  int G = (BN - S) / (Q - S);
-  if (G > P) G = P;
+  int G = mfma_plan_max_G(sh, in_kind);
   if (G_request > 0 && G_request < G) G = G_request;
   if (G < 1) { delete p; return hipErrorNotSupported; }
   p->G = G;
   p->ncb = (P + G - 1) / G;
-  const int BM = in_kind == 2 ? Tile<2>::BM : Tile<1>::BM;
+  const int BM = in_kind != 1 ? Tile<2>::BM : Tile<1>::BM;
   p->nrb = (int)((sh.I + BM - 1) / BM);
   p->nchunk = (int)((sh.J + KC - 1) / KC);
   p->QT = (Q + 31) / 32;
@@ -942,7 +1157,8 @@ hipError_t mfma_plan_create(const CompressShape& sh, int in_kind, const double* 
     return e;
   }
   const int T2LD = BM + (in_kind == 1 ? 4 : 8);
-  const size_t stage = 2 * (size_t)((in_kind == 1 ? chunk_elems<1>(BM / 32) : chunk_elems<2>(BM / 32)) +
+  const int npart = in_kind == 3 ? 2 : 1;   // hi and lo X images of the two-term form
+  const size_t stage = 2 * (size_t)(npart * (in_kind == 1 ? chunk_elems<1>(BM / 32) : chunk_elems<2>(BM / 32)) +
                                     (in_kind == 1 ? chunk_elems<1>(BN / 32) : chunk_elems<2>(BN / 32))) * esz;
   const size_t t2 = (size_t)(BN + 1) * T2LD * esz;
   p->lds = stage > t2 ? stage : t2;
@@ -988,7 +1204,9 @@ hipError_t compress_mfma_main(hipStream_t s, const MfmaPlan* p, const float* X, 
   hipError_t e;
   // the 16-byte load paths need J % 4 == 0 and an aligned X
   const int v = vec ? p->variant : 2;
-  if (v == 3 && p->kind == 2)
+  if (p->kind == 3)
+    e = launch_split_q(s, a, p->QT, vec, p->lds);
+  else if (v == 3 && p->kind == 2)
     e = launch_pipe2_q(s, a, p->QT);
   else if (v == 0 || v == 3)
     e = p->kind == 1 ? launch_pipe_q<1>(s, a, p->QT) : launch_pipe_q<2>(s, a, p->QT);

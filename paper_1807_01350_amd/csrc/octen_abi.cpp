@@ -200,6 +200,11 @@ static octen_status join_side(octen_t h) {
 
 bool valid_dtype_x(int d) { return d == OCTEN_F64 || d == OCTEN_F32; }
 
+// Matrix-core input kind of a compression type (see mfma_plan_create).
+int mfma_kind(int compress_dtype) {
+  return compress_dtype == OCTEN_BF16 ? 2 : (compress_dtype == OCTEN_BF16X2 ? 3 : 1);
+}
+
 octen_status validate(const octen_config* c, std::string* msg) {
   if (!c) { *msg = "config is NULL"; return OCTEN_ERR_ARG; }
   if (c->abi_version != OCTEN_ABI_VERSION) { *msg = "ABI version mismatch"; return OCTEN_ERR_ARG; }
@@ -212,8 +217,8 @@ octen_status validate(const octen_config* c, std::string* msg) {
   if (c->R > c->Q) { *msg = "R must be <= Q"; return OCTEN_ERR_ARG; }
   if (!valid_dtype_x(c->x_dtype)) { *msg = "x_dtype must be F64 or F32"; return OCTEN_ERR_ARG; }
   if (c->compress_dtype != OCTEN_F64 && c->compress_dtype != OCTEN_F32 &&
-      c->compress_dtype != OCTEN_BF16) {
-    *msg = "compress_dtype must be F64, F32 or BF16";
+      c->compress_dtype != OCTEN_BF16 && c->compress_dtype != OCTEN_BF16X2) {
+    *msg = "compress_dtype must be F64, F32, BF16 or BF16X2";
     return OCTEN_ERR_UNSUPPORTED;
   }
   if (c->compress_dtype == OCTEN_F64 && c->x_dtype != OCTEN_F64) {
@@ -223,8 +228,8 @@ octen_status validate(const octen_config* c, std::string* msg) {
     *msg = "narrow compression needs f32 slices";
     return OCTEN_ERR_UNSUPPORTED;
   }
-  if (c->als_dtype != OCTEN_F64 && c->als_dtype != OCTEN_F32) {
-    *msg = "als_dtype must be F64 or F32";
+  if (c->als_dtype != OCTEN_F64) {
+    *msg = "als_dtype must be F64";
     return OCTEN_ERR_UNSUPPORTED;
   }
   int64_t M1 = (int64_t)c->S + (int64_t)c->P * (c->Q - c->S);
@@ -460,11 +465,10 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
   }
   if (h->cfg.compress_dtype != OCTEN_F64 && !(h->cfg.flags & OCTEN_FLAG_REFERENCE_PATH)) {
     CompressShape sh{I, J, (int)P, (int)Q, h->S, (int)M1};
-    hipError_t e = mfma_plan_create(sh, h->cfg.compress_dtype == OCTEN_BF16 ? 2 : 1, h->U, h->V, s,
-                                    &h->plan);
+    hipError_t e = mfma_plan_create(sh, mfma_kind(h->cfg.compress_dtype), h->U, h->V, s, &h->plan);
     if (e != hipSuccess) {
-      h->err = std::string("mfma plan: ") + hipGetErrorString(e);
       octen_destroy(h);
+      if (e == hipErrorInvalidValue && cfg->compress_dtype == OCTEN_BF16X2) return OCTEN_ERR_ARG;
       return e == hipErrorNotSupported ? OCTEN_ERR_UNSUPPORTED : OCTEN_ERR_HIP;
     }
   }
@@ -1009,6 +1013,8 @@ octen_status octen_compress_variant(octen_t h, int32_t variant) {
   if (variant < 0 || variant > 3) return fail(h, OCTEN_ERR_ARG, "variant must be in [0, 3]");
   if (variant == 3 && h->cfg.compress_dtype != OCTEN_BF16)
     return fail(h, OCTEN_ERR_UNSUPPORTED, "variant 3 is BF16 only");
+  if (h->cfg.compress_dtype == OCTEN_BF16X2)
+    return fail(h, OCTEN_ERR_UNSUPPORTED, "the two-term form has one kernel variant");
   mfma_plan_set_variant(h->plan, variant);
   return OCTEN_OK;
 }
@@ -1020,13 +1026,14 @@ octen_status octen_autotune(octen_t h, const void* X, int64_t t, int32_t* choice
   OKCHK(join_side(h));
   hipStream_t s = h->stream;
   const CompressShape sh{h->I, h->J, h->P, h->Q, h->S, h->M1};
-  const int kind = h->cfg.compress_dtype == OCTEN_BF16 ? 2 : 1;
-  const int gmax = mfma_plan_max_G(sh);
+  const int kind = mfma_kind(h->cfg.compress_dtype);
+  const int gmax = mfma_plan_max_G(sh, kind);
   std::vector<int> gs{mfma_plan_G(h->plan)};
   if ((gmax + 1) / 2 != gs[0] && gmax > 1) gs.push_back((gmax + 1) / 2);
   const bool vec = (h->J % 4 == 0) && (((uintptr_t)X & 15) == 0);
   std::vector<int> variants = vec ? std::vector<int>{0, 1, 2} : std::vector<int>{2};
   if (vec && kind == 2) variants.push_back(3);   // half chunks, double-buffered fragments
+  if (kind == 3) variants = {mfma_plan_variant(h->plan)};   // one kernel per load path
   std::vector<MfmaPlan*> plans{h->plan};
   for (size_t q = 1; q < gs.size(); ++q) {
     MfmaPlan* pl = nullptr;

@@ -86,9 +86,9 @@ hipError_t compress_mode3_partials(hipStream_t s, const CompressShape& sh, int64
 // MFMA path (f32 or bf16 inputs, f32 accumulate) for dense f32 slices.
 struct MfmaPlan;
 // G_request: replicas per column block (<= 0: as many as fit, the default)
-hipError_t mfma_plan_create(const CompressShape& sh, int in_kind /*1=f32, 2=bf16*/, const double* U,
+hipError_t mfma_plan_create(const CompressShape& sh, int in_kind /*1=f32, 2=bf16, 3=bf16x2*/, const double* U,
                             const double* V, hipStream_t s, MfmaPlan** out, int G_request = 0);
-int mfma_plan_max_G(const CompressShape& sh);
+int mfma_plan_max_G(const CompressShape& sh, int in_kind);
 int mfma_plan_G(const MfmaPlan* p);
 // kernel variant: 0 pipelined (direct-to-LDS loads), 1 register-staged with
 // 16-byte loads, 2 register-staged scalar loads (any J, any alignment)

@@ -122,13 +122,25 @@ def dense_stream(I: int, J: int, K: int, R: int, sigma: float, config_id: int,
     return A, B, C, np.ascontiguousarray(X.astype(dtype))
 
 
+def to_bf16_grid(x):
+    """Nearest value with 8 significant bits (the bfloat16 grid), ties to
+    even, returned as float64.  Used to draw compression matrices whose
+    entries the bfloat16 matrix cores take without rounding."""
+    b = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 def compression_UV(I: int, J: int, P: int, Q: int, S: int, config_id: int):
     """Fixed mode-1/mode-2 compression matrices in deduplicated layout
-    U = [G | H_1 | ... | H_P] (I x M1), same for V; N(0,1) entries."""
+    U = [G | H_1 | ... | H_P] (I x M1), same for V: N(0,1) draws rounded to
+    the bfloat16 grid (8 significant bits).  The method needs only that
+    compression and recovery use the same random matrices; on this grid every
+    arithmetic form of the compression takes them exactly."""
     M1 = S + P * (Q - S)
     g = rng(config_id, PURPOSE_COMPRESSION)
-    U = g.standard_normal((I, M1))
-    V = g.standard_normal((J, M1))
+    U = to_bf16_grid(g.standard_normal((I, M1)))
+    V = to_bf16_grid(g.standard_normal((J, M1)))
     return np.ascontiguousarray(U), np.ascontiguousarray(V)
 
 
