@@ -85,7 +85,12 @@ enum {
   OCTEN_STATE_TPERM = 8,    /* [R] int32 column pairing with previous batch   */
   OCTEN_STATE_ITERS = 9,    /* [P] int32 ALS sweeps done                      */
   OCTEN_STATE_MARGIN = 10,  /* [P] f64 matching margin (replica 0: +inf)      */
-  OCTEN_STATE_FLAGS = 11,   /* [P] int32 health flags, bit0 solve fallback    */
+  OCTEN_STATE_FLAGS = 11,   /* [P] int32 replica flags of the last ALS call:
+                               bit0 a normal-equation solve met a
+                               non-positive pivot, bit1 a barrier between the
+                               replica's workgroups timed out, bit2 factors or
+                               weights not finite, bit3 the replica was not
+                               committed (its starting factors were kept)   */
   /* bookkeeping of the last sparse batch (octen_compress_batch_coo); a
    * segment is one distinct (k, i) pair, numbered in input order */
   OCTEN_STATE_COO_SIZES = 12,     /* [2] int32: nseg, t                      */
@@ -101,7 +106,6 @@ enum {
 };
 
 /* Flags (octen_config.flags). */
-#define OCTEN_FLAG_FUSE_UPDATE 0x1ull    /* compression adds into Y directly  */
 #define OCTEN_FLAG_REFERENCE_PATH 0x2ull /* plain FP64 kernels, no MFMA       */
 #define OCTEN_FLAG_TIMING 0x4ull         /* record HIP events around stages   */
 #define OCTEN_FLAG_ALS_ONE_WG 0x8ull     /* ALS: one workgroup per replica, no
@@ -191,6 +195,25 @@ octen_status octen_compress_batch_coo(octen_t h, int64_t nnz, const int32_t* k,
 /* Eq. 2: Y_p += Z_p for every replica; the slice count K grows by t. */
 octen_status octen_update_replicas(octen_t h);
 
+/* Conditions a handle records on the device (asynchronous calls cannot
+ * return them) until a synchronising call reports them:
+ *  OCTEN_HEALTH_NONFINITE_BATCH  a compressed batch held non-finite values
+ *      (a NaN or Inf slice value): octen_update_replicas left the summaries
+ *      of the replicas concerned unchanged (the slices still count in K);
+ *  OCTEN_HEALTH_ALS_FAILED       octen_cp_als_replicas met a failed solve,
+ *      a barrier time-out or non-finite factors in some replica: that
+ *      replica keeps its starting factors (OCTEN_STATE_FLAGS bit 3).
+ * octen_cp_als_replicas with iters_done_host, octen_recover_factors with
+ * K_out_host and octen_health return OCTEN_ERR_NUMERIC when any bit is set,
+ * and clear the bits. */
+#define OCTEN_HEALTH_NONFINITE_BATCH 0x1
+#define OCTEN_HEALTH_ALS_FAILED 0x2
+
+/* Waits for the handle's work, writes the health bits recorded since the
+ * last report to *bits_host (may be NULL) and clears them: OCTEN_OK when
+ * none is set, OCTEN_ERR_NUMERIC otherwise. */
+octen_status octen_health(octen_t h, int32_t* bits_host);
+
 /* Sec. 4.1: rank-R CP-ALS of every replica summary.  Gauss-Seidel sweeps
  * over modes 1, 2, 3; each mode solves the R x R normal equations in f64
  * (Cholesky) and scales the columns to unit 2-norm; lambda = norms of mode 3.
@@ -201,7 +224,10 @@ octen_status octen_update_replicas(octen_t h);
  * set by octen_warmstart_set where its start fits the updated summary at
  * least as well as the previous factors do, else from those (init ignored;
  * the choice per replica is readable as OCTEN_STATE_WARM_KEEP).
- * iters_done_host: NULL or [P] host int32 (synchronises). */
+ * iters_done_host: NULL or [P] host int32 (synchronises, and then reports
+ * the health bits: OCTEN_ERR_NUMERIC if a replica failed).  A replica whose
+ * solve meets a non-positive pivot, whose barrier times out or whose factors
+ * are not finite is not committed: it keeps its starting factors. */
 octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int32_t init_mode,
                                    const double* init, int32_t* iters_done_host);
 
@@ -211,7 +237,8 @@ octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int
  * A: [I][R], B: [J][R] with unit-norm columns whose largest-magnitude entry is
  * positive, and C: [K][R] (all slices seen so far; the columns of earlier
  * rows follow the current A, B).  c_capacity: rows available in C (>= K).
- * K_out_host: NULL or host int64 (synchronises). */
+ * K_out_host: NULL or host int64 (synchronises, and then reports the health
+ * bits as octen_health does). */
 octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C,
                                    int64_t c_capacity, int64_t* K_out_host);
 

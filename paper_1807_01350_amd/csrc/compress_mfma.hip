@@ -1218,8 +1218,8 @@ hipError_t compress_mfma_main(hipStream_t s, const MfmaPlan* p, const float* X, 
 }
 
 hipError_t compress_mfma_mode3(hipStream_t s, const MfmaPlan* p, int64_t t, const double* W,
-                               const void* work, float* Z) {
-  return compress_mode3_partials(s, p->sh, t, p->nrb, (const float*)work, W, Z);
+                               const void* work, float* Z, int* zbad) {
+  return compress_mode3_partials(s, p->sh, t, p->nrb, (const float*)work, W, Z, zbad);
 }
 
 }  // namespace octen

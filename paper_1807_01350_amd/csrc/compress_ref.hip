@@ -82,7 +82,7 @@ template <typename TM, typename TZ>
 __global__ __launch_bounds__(256) void mode3_kernel(const TM* __restrict__ Mk,
                                                     const double* __restrict__ W, int64_t t,
                                                     int nrb, int M1, int P, int Q, int S,
-                                                    TZ* __restrict__ Z) {
+                                                    TZ* __restrict__ Z, int* __restrict__ zbad) {
   extern __shared__ double sm[];
   double* Ms = sm;                     // [S3_KT][S3_B]
   double* Ws = sm + S3_KT * S3_B;      // [S3_KT][Q]
@@ -120,51 +120,58 @@ __global__ __launch_bounds__(256) void mode3_kernel(const TM* __restrict__ Mk,
     }
     __syncthreads();
   }
+  int bad = 0;
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     int o = tid + u * 256;
     if (o < nout) {
       int bb = o / Q, c = o % Q;
       int b = b0 + bb;
-      if (b < Q) Z[(((int64_t)p * Q + a) * Q + b) * Q + c] = (TZ)acc[u];
+      if (b < Q) {
+        const TZ z = (TZ)acc[u];
+        bad |= isfinite((double)z) ? 0 : 1;
+        Z[(((int64_t)p * Q + a) * Q + b) * Q + c] = z;
+      }
     }
   }
+  // a non-finite slice value reaches every replica's Z: flag the replica
+  if (bad) atomicOr(zbad + p, 1);
 }
 
 }  // namespace
 
 hipError_t compress_mode3_partials(hipStream_t s, const CompressShape& sh, int64_t t, int nrb,
-                                  const float* Mpart, const double* W, float* Z) {
+                                  const float* Mpart, const double* W, float* Z, int* zbad) {
   dim3 grid(sh.P, sh.Q, (sh.Q + S3_B - 1) / S3_B);
   size_t lds = (size_t)(S3_KT * S3_B + S3_KT * sh.Q) * sizeof(double);
   hipLaunchKernelGGL((mode3_kernel<float, float>), grid, dim3(256), lds, s, Mpart, W, t, nrb,
-                     sh.M1, sh.P, sh.Q, sh.S, Z);
+                     sh.M1, sh.P, sh.Q, sh.S, Z, zbad);
   return hipGetLastError();
 }
 
 hipError_t compress_mode3(hipStream_t s, const CompressShape& sh, int64_t t, const void* M,
-                          bool m_f64, const double* W, void* Z, bool z_f64) {
+                          bool m_f64, const double* W, void* Z, bool z_f64, int* zbad) {
   dim3 grid(sh.P, sh.Q, (sh.Q + S3_B - 1) / S3_B);
   size_t lds = (size_t)(S3_KT * S3_B + S3_KT * sh.Q) * sizeof(double);
   if (m_f64 && z_f64)
     hipLaunchKernelGGL((mode3_kernel<double, double>), grid, dim3(256), lds, s,
-                       (const double*)M, W, t, 1, sh.M1, sh.P, sh.Q, sh.S, (double*)Z);
+                       (const double*)M, W, t, 1, sh.M1, sh.P, sh.Q, sh.S, (double*)Z, zbad);
   else if (m_f64 && !z_f64)
     hipLaunchKernelGGL((mode3_kernel<double, float>), grid, dim3(256), lds, s, (const double*)M,
-                       W, t, 1, sh.M1, sh.P, sh.Q, sh.S, (float*)Z);
+                       W, t, 1, sh.M1, sh.P, sh.Q, sh.S, (float*)Z, zbad);
   else if (!m_f64 && z_f64)
     hipLaunchKernelGGL((mode3_kernel<float, double>), grid, dim3(256), lds, s, (const float*)M,
-                       W, t, 1, sh.M1, sh.P, sh.Q, sh.S, (double*)Z);
+                       W, t, 1, sh.M1, sh.P, sh.Q, sh.S, (double*)Z, zbad);
   else
     hipLaunchKernelGGL((mode3_kernel<float, float>), grid, dim3(256), lds, s, (const float*)M, W,
-                       t, 1, sh.M1, sh.P, sh.Q, sh.S, (float*)Z);
+                       t, 1, sh.M1, sh.P, sh.Q, sh.S, (float*)Z, zbad);
   return hipGetLastError();
 }
 
 hipError_t compress_reference(hipStream_t s, const CompressShape& sh, const void* X, bool x_f64,
                               int64_t t, const double* U, const double* V, const double* W,
                               double* T2work, int64_t t2_rows_cap, double* Mwork, void* Z,
-                              bool z_f64) {
+                              bool z_f64, int* zbad) {
   const int64_t I = sh.I, J = sh.J;
   const int M1 = sh.M1;
   int64_t chunk = t2_rows_cap / I;
@@ -186,7 +193,7 @@ hipError_t compress_reference(hipStream_t s, const CompressShape& sh, const void
                        Mwork + k0 * sh.P * sh.Q * sh.Q);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  return compress_mode3(s, sh, t, Mwork, true, W, Z, z_f64);
+  return compress_mode3(s, sh, t, Mwork, true, W, Z, z_f64, zbad);
 }
 
 }  // namespace octen

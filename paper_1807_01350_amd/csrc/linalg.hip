@@ -247,19 +247,43 @@ __global__ void cvt_kernel(const double* in, float* out, int64_t n) {
        i += (int64_t)gridDim.x * blockDim.x)
     out[i] = (float)in[i];
 }
+// Y_p += Z_p where replica p's compressed batch is finite (n values each).
 template <typename T>
-__global__ void axpy_kernel(T* y, const T* x, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    y[i] += x[i];
+__global__ void update_masked_kernel(T* __restrict__ y, const T* __restrict__ x, int P, int64_t n,
+                                     const int* __restrict__ zbad, int* __restrict__ health) {
+  const int64_t tot = (int64_t)P * n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(i / n);
+    if (zbad[p] == 0) y[i] += x[i];
+    else if (i == (int64_t)p * n) atomicOr(health, 1);
+  }
 }
-template <typename T>
-__global__ void nonfinite_kernel(const T* x, int64_t n, int* flag) {
+
+// One workgroup per replica: keep or roll back the replica's new factors.
+__global__ void als_commit_kernel(int QR3, int R, double* __restrict__ F, double* __restrict__ lam,
+                                  const double* __restrict__ F0, const double* __restrict__ lam0,
+                                  int* __restrict__ flags, int* __restrict__ health) {
+  const int p = blockIdx.x;
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  double* f = F + (int64_t)p * QR3;
   int bad = 0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    if (!isfinite((double)x[i])) bad = 1;
-  if (bad) atomicOr(flag, 1);
+  for (int e = threadIdx.x; e < QR3; e += blockDim.x) bad |= isfinite(f[e]) ? 0 : 1;
+  for (int e = threadIdx.x; e < R; e += blockDim.x) bad |= isfinite(lam[(int64_t)p * R + e]) ? 0 : 1;
+  if (bad) atomicOr(&s_bad, 1);
+  __syncthreads();
+  const int fl = flags[p] | (s_bad ? 4 : 0);
+  const bool back = (fl & 7) != 0;
+  if (back) {
+    for (int e = threadIdx.x; e < QR3; e += blockDim.x) f[e] = F0[(int64_t)p * QR3 + e];
+    for (int e = threadIdx.x; e < R; e += blockDim.x) lam[(int64_t)p * R + e] = lam0[(int64_t)p * R + e];
+  }
+  if (threadIdx.x == 0) {
+    flags[p] = fl | (back ? 8 : 0);
+    if (back) atomicOr(health, 2);
+  }
 }
 
 __global__ void scale_kernel(double* X, int64_t rows, int64_t cols, const double* vr,
@@ -355,24 +379,21 @@ hipError_t convert_f64_to_f32(hipStream_t s, const double* in, float* out, int64
   hipLaunchKernelGGL(cvt_kernel, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
   return hipGetLastError();
 }
-hipError_t axpy_acc(hipStream_t s, void* y, const void* x, int64_t n, bool f64) {
-  if (n <= 0) return hipSuccess;
+hipError_t update_masked(hipStream_t s, void* Y, const void* Z, int P, int64_t n, bool f64,
+                         const int* zbad, int* health) {
   if (f64)
-    hipLaunchKernelGGL(axpy_kernel<double>, dim3(grid_for(n)), dim3(256), 0, s, (double*)y,
-                       (const double*)x, n);
+    hipLaunchKernelGGL(update_masked_kernel<double>, dim3(grid_for(P * n)), dim3(256), 0, s,
+                       (double*)Y, (const double*)Z, P, n, zbad, health);
   else
-    hipLaunchKernelGGL(axpy_kernel<float>, dim3(grid_for(n)), dim3(256), 0, s, (float*)y,
-                       (const float*)x, n);
+    hipLaunchKernelGGL(update_masked_kernel<float>, dim3(grid_for(P * n)), dim3(256), 0, s,
+                       (float*)Y, (const float*)Z, P, n, zbad, health);
   return hipGetLastError();
 }
-hipError_t any_nonfinite(hipStream_t s, const void* x, int64_t n, bool f64, int* flag) {
-  if (n <= 0) return hipSuccess;
-  if (f64)
-    hipLaunchKernelGGL(nonfinite_kernel<double>, dim3(grid_for(n)), dim3(256), 0, s,
-                       (const double*)x, n, flag);
-  else
-    hipLaunchKernelGGL(nonfinite_kernel<float>, dim3(grid_for(n)), dim3(256), 0, s,
-                       (const float*)x, n, flag);
+
+hipError_t als_commit(hipStream_t s, int P, int QR3, int R, double* F, double* lam,
+                      const double* F0, const double* lam0, int* flags, int* health) {
+  hipLaunchKernelGGL(als_commit_kernel, dim3(P), dim3(256), 0, s, QR3, R, F, lam, F0, lam0, flags,
+                     health);
   return hipGetLastError();
 }
 

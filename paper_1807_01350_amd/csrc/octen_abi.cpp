@@ -55,6 +55,9 @@ struct octen_ctx {
   // ALS
   double *F = nullptr, *lam = nullptr;     // [P][3][Q][R], [P][R]
   int *iters = nullptr, *flags = nullptr;  // [P]
+  double *F0 = nullptr, *lam0 = nullptr;   // starting factors of the running ALS call
+  int* zbad = nullptr;                     // [P] non-finite entries in replica p's Z
+  int* health = nullptr;                   // [1] OCTEN_HEALTH_* bits since the last report
   int als_nw = 0;                          // workgroups per replica (0: reference kernel)
   bool als_gx = false;                     // slab read from global memory, not LDS
   double* als_slots = nullptr;
@@ -234,6 +237,9 @@ octen_status validate(const octen_config* c, std::string* msg) {
   }
   int64_t M1 = (int64_t)c->S + (int64_t)c->P * (c->Q - c->S);
   if (M1 > (1 << 20)) { *msg = "too many compression columns"; return OCTEN_ERR_ARG; }
+  const uint64_t known = OCTEN_FLAG_REFERENCE_PATH | OCTEN_FLAG_TIMING | OCTEN_FLAG_ALS_ONE_WG |
+                         OCTEN_FLAG_ALS_DEVICE_SYNC;
+  if (c->flags & ~known) { *msg = "unknown flag bits"; return OCTEN_ERR_ARG; }
   return OCTEN_OK;
 }
 
@@ -265,6 +271,25 @@ octen_status build_operator(octen_t h, const double* Pt, int64_t n, double* Op) 
   HIPCHK(h, hipStreamSynchronize(s));
   dfree(h, N);
   return OCTEN_OK;
+}
+
+// Waits for the handle's stream, reads and clears the health bits (the
+// OCTEN_HEALTH_* conditions since the last report): OCTEN_ERR_NUMERIC when
+// any is set.
+octen_status report_health(octen_t h, int32_t* bits_host = nullptr) {
+  int v = 0;
+  HIPCHK(h, hipMemcpyAsync(&v, h->health, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (bits_host) *bits_host = v;
+  if (v == 0) return OCTEN_OK;
+  HIPCHK(h, fill_i32(h->stream, h->health, 1, 0));
+  std::string what;
+  if (v & OCTEN_HEALTH_NONFINITE_BATCH) what += "non-finite compressed batch (summaries not updated)";
+  if (v & OCTEN_HEALTH_ALS_FAILED) {
+    if (!what.empty()) what += "; ";
+    what += "replica fit failed (starting factors kept, see OCTEN_STATE_FLAGS)";
+  }
+  return fail(h, OCTEN_ERR_NUMERIC, what);
 }
 
 int host_info(octen_t h) {
@@ -303,6 +328,12 @@ const char* octen_status_str(octen_status s) {
 }
 
 const char* octen_last_error(octen_t h) { return h ? h->err.c_str() : "null handle"; }
+
+octen_status octen_health(octen_t h, int32_t* bits_host) {
+  if (!h) return OCTEN_ERR_ARG;
+  OKCHK(join_side(h));
+  return report_health(h, bits_host);
+}
 
 octen_status octen_check_identifiable(const octen_config* cfg, int64_t K, int64_t t,
                                       int32_t* bits_host, double* p_min_host) {
@@ -365,6 +396,10 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
   IOK(dalloc(h, &h->lam, P * R));
   IOK(dalloc(h, &h->iters, P));
   IOK(dalloc(h, &h->flags, P));
+  IOK(dalloc(h, &h->F0, P * 3 * Q * R));
+  IOK(dalloc(h, &h->lam0, P * R));
+  IOK(dalloc(h, &h->zbad, P));
+  IOK(dalloc(h, &h->health, 1));
   IOK(dalloc(h, &h->aligned, P * 3 * Q * R));
   IOK(dalloc(h, &h->margin, P));
   IOK(dalloc(h, &h->perm, P * R));
@@ -405,6 +440,8 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
       !hip_ok(hipMemsetAsync(h->H, 0, M1 * R * 8, s), "zero H") ||
       !hip_ok(hipMemsetAsync(h->info, 0, sizeof(int), s), "zero info") ||
       !hip_ok(hipMemsetAsync(h->flags, 0, P * sizeof(int), s), "zero flags") ||
+      !hip_ok(hipMemsetAsync(h->zbad, 0, P * sizeof(int), s), "zero zbad") ||
+      !hip_ok(hipMemsetAsync(h->health, 0, sizeof(int), s), "zero health") ||
       !hip_ok(rec_weights(s, (int)M1, h->S, (int)P, h->w, h->w2), "weights")) {
     octen_destroy(h);
     return OCTEN_ERR_HIP;
@@ -515,13 +552,14 @@ octen_status octen_compress_batch(octen_t h, const void* X, int64_t t, const dou
       OKCHK(dalloc(h, (char**)&h->mfma_work, need));
       h->mfma_work_bytes = need;
     }
+    HIPCHK(h, fill_i32(s, h->zbad, h->P, 0));
     {
       StageTimer tm(h, OCTEN_STAGE_COMPRESS_MAIN);
       HIPCHK(h, compress_mfma_main(s, h->plan, (const float*)X, t, slice_scale, h->mfma_work));
     }
     {
       StageTimer tm(h, OCTEN_STAGE_COMPRESS_MODE3);
-      HIPCHK(h, compress_mfma_mode3(s, h->plan, t, h->Wz, h->mfma_work, (float*)h->Z));
+      HIPCHK(h, compress_mfma_mode3(s, h->plan, t, h->Wz, h->mfma_work, (float*)h->Z, h->zbad));
     }
   } else {
     // reference path: T2 chunk of at most ~64 Mi doubles
@@ -532,9 +570,10 @@ octen_status octen_compress_batch(octen_t h, const void* X, int64_t t, const dou
     want = (want / I) * I;
     OKCHK(dgrow(h, &h->T2, &h->T2_rows, want * M1));
     OKCHK(dgrow(h, &h->Mk, &h->Mk_cap, t * h->P * h->Q * h->Q));
+    HIPCHK(h, fill_i32(s, h->zbad, h->P, 0));
     StageTimer tm(h, OCTEN_STAGE_COMPRESS_MAIN);
     HIPCHK(h, compress_reference(s, sh, X, x_f64, t, h->U, h->V, h->Wz, h->T2, h->T2_rows / M1,
-                                 h->Mk, h->Z, h->acc_f64));
+                                 h->Mk, h->Z, h->acc_f64, h->zbad));
   }
   h->z_ready = true;
   h->z_any = true;
@@ -630,9 +669,10 @@ octen_status octen_compress_batch_coo(octen_t h, int64_t nnz, const int32_t* k, 
     HIPCHK(h, coo_compress(s, f64, t, h->P, h->Q, h->S, h->M1, h->seg_start, h->seg_row,
                            h->slice_seg, j, v, Vm, Um, Mk));
   }
+  HIPCHK(h, fill_i32(s, h->zbad, h->P, 0));
   {
     StageTimer tm(h, OCTEN_STAGE_COMPRESS_MODE3);
-    HIPCHK(h, compress_mode3(s, sh, t, Mk, f64, h->Wz, h->Z, h->acc_f64));
+    HIPCHK(h, compress_mode3(s, sh, t, Mk, f64, h->Wz, h->Z, h->acc_f64, h->zbad));
   }
   h->z_ready = true;
   h->z_any = true;
@@ -648,7 +688,7 @@ octen_status octen_update_replicas(octen_t h) {
   const int64_t n = (int64_t)h->P * h->Q * h->Q * h->Q;
   {
     StageTimer tm(h, OCTEN_STAGE_UPDATE);
-    HIPCHK(h, axpy_acc(s, h->Y, h->Z, n, h->acc_f64));
+    HIPCHK(h, update_masked(s, h->Y, h->Z, h->P, n / h->P, h->acc_f64, h->zbad, h->health));
   }
   // append this batch's W rows to the pending temporal block
   const int64_t M1 = h->M1;
@@ -725,6 +765,13 @@ octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int
     return fail(h, OCTEN_ERR_ARG, "unknown init_mode");
   }
   hipStream_t s = h->stream;
+  const int64_t QR3 = (int64_t)3 * h->Q * h->R;
+  // the starting point, given back to a replica whose fit fails
+  HIPCHK(h, hipMemcpyAsync(h->F0, src, (size_t)h->P * QR3 * 8, hipMemcpyDeviceToDevice, s));
+  if (init_mode == OCTEN_INIT_GIVEN || !h->have_factors)
+    HIPCHK(h, fill_f64(s, h->lam0, (int64_t)h->P * h->R, 1.0));
+  else
+    HIPCHK(h, hipMemcpyAsync(h->lam0, h->lam, (size_t)h->P * h->R * 8, hipMemcpyDeviceToDevice, s));
   {
     StageTimer tm(h, OCTEN_STAGE_ALS);
     HIPCHK(h, fill_i32(s, h->flags, h->P, 0));
@@ -743,15 +790,14 @@ octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int
     if (e != hipSuccess)
       HIPCHK(h, als_reference(s, h->Y, h->acc_f64, h->P, h->Q, h->R, src, h->F, h->lam, h->iters,
                               h->flags, max_iters, tol));
+    HIPCHK(h, als_commit(s, h->P, (int)QR3, h->R, h->F, h->lam, h->F0, h->lam0, h->flags,
+                         h->health));
   }
   h->have_factors = true;
   h->factors_fresh = true;
   if (iters_done_host) {
     HIPCHK(h, hipMemcpyAsync(iters_done_host, h->iters, h->P * sizeof(int), hipMemcpyDeviceToHost, s));
-    int err = 0;
-    if (h->als_err) HIPCHK(h, hipMemcpyAsync(&err, h->als_err, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    if (err) return fail(h, OCTEN_ERR_HIP, "ALS workgroup synchronisation timed out");
+    return report_health(h);
   }
   return OCTEN_OK;
 }
@@ -836,8 +882,8 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, i
   h->have_prev = true;
   h->factors_fresh = false;
   if (K_out_host) {
-    HIPCHK(h, hipStreamSynchronize(s));
     *K_out_host = h->K;
+    return report_health(h);
   }
   return OCTEN_OK;
 }

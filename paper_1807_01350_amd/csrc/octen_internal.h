@@ -52,8 +52,15 @@ hipError_t fill_f64(hipStream_t s, double* p, int64_t n, double v);
 hipError_t fill_i32(hipStream_t s, int* p, int64_t n, int v);
 hipError_t convert_f64_to_f32(hipStream_t s, const double* in, float* out, int64_t n);
 // y[i] += x[i]
-hipError_t axpy_acc(hipStream_t s, void* y, const void* x, int64_t n, bool f64);
-hipError_t any_nonfinite(hipStream_t s, const void* x, int64_t n, bool f64, int* flag);
+// Eq. 2 update: Y_p += Z_p for every replica p whose zbad[p] is zero (n
+// values per replica); a replica left out sets bit 0 of *health.
+hipError_t update_masked(hipStream_t s, void* Y, const void* Z, int P, int64_t n, bool f64,
+                         const int* zbad, int* health);
+// ALS commit: a replica whose flags show a failed solve or barrier, or whose
+// factors or weights are not finite, gets its starting factors F0 / lam0 back
+// (flags bits 2 and 3 as documented in octen.h) and sets bit 1 of *health.
+hipError_t als_commit(hipStream_t s, int P, int QR3, int R, double* F, double* lam,
+                      const double* F0, const double* lam0, int* flags, int* health);
 // X[i][j] *= v[j] (rows x cols)
 hipError_t scale_cols(hipStream_t s, double* X, int64_t rows, int64_t cols, const double* v);
 // X[i][j] *= v[i] * v[j] (n x n)
@@ -72,16 +79,17 @@ struct CompressShape {
 hipError_t compress_reference(hipStream_t s, const CompressShape& sh, const void* X, bool x_f64,
                               int64_t t, const double* U, const double* V, const double* W,
                               double* T2work, int64_t t2_rows_cap, double* Mwork, void* Z,
-                              bool z_f64);
+                              bool z_f64, int* zbad);
 
 // Mode-3 product and store: Z[p][a][b][c] = sum_k M[k][p][a][b] * W[k][col_p(c)].
-// M is f32 or f64 ([t][P][Q][Q]); Z f32 or f64; if accumulate, Y += result too.
+// M is f32 or f64 ([t][P][Q][Q]); Z f32 or f64.  zbad[p] |= 1 when replica p
+// receives a non-finite value (zbad is not cleared here).
 hipError_t compress_mode3(hipStream_t s, const CompressShape& sh, int64_t t, const void* M,
-                          bool m_f64, const double* W, void* Z, bool z_f64);
+                          bool m_f64, const double* W, void* Z, bool z_f64, int* zbad);
 
 // Same with per-row-block partials Mpart [t][nrb][P][Q][Q] f32 summed first.
 hipError_t compress_mode3_partials(hipStream_t s, const CompressShape& sh, int64_t t, int nrb,
-                                  const float* Mpart, const double* W, float* Z);
+                                  const float* Mpart, const double* W, float* Z, int* zbad);
 
 // MFMA path (f32 or bf16 inputs, f32 accumulate) for dense f32 slices.
 struct MfmaPlan;
@@ -101,7 +109,7 @@ hipError_t compress_mfma_main(hipStream_t s, const MfmaPlan* plan, const float* 
                               const float* slice_scale, void* work);
 // Sum of partials and mode 3 into Z.
 hipError_t compress_mfma_mode3(hipStream_t s, const MfmaPlan* plan, int64_t t, const double* W,
-                               const void* work, float* Z);
+                               const void* work, float* Z, int* zbad);
 
 // ------------------------------------------------------------------- ALS ---
 // One workgroup per replica; Y is [P][Q][Q][Q] (f32 or f64).

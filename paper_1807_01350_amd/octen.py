@@ -34,7 +34,6 @@ OCTEN_INIT_GIVEN, OCTEN_INIT_PREV, OCTEN_INIT_LEARNED = 0, 1, 2
  OCTEN_STATE_MARGIN, OCTEN_STATE_FLAGS, OCTEN_STATE_COO_SIZES, OCTEN_STATE_COO_SEG_START,
  OCTEN_STATE_COO_SEG_ROW, OCTEN_STATE_COO_SLICE_SEG, OCTEN_STATE_WARM_KEEP,
  OCTEN_STATE_WARM_FITS) = range(18)
-OCTEN_FLAG_FUSE_UPDATE = 0x1
 OCTEN_FLAG_REFERENCE_PATH = 0x2
 OCTEN_FLAG_TIMING = 0x4
 OCTEN_FLAG_ALS_ONE_WG = 0x8
@@ -79,6 +78,7 @@ _SIGS = {
     "octen_compress_batch_async": ([_vp, _vp, _i64, _vp, _vp], _i32),
     "octen_compress_batch_coo": ([_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp], _i32),
     "octen_update_replicas": ([_vp], _i32),
+    "octen_health": ([_vp, _vp], _i32),
     "octen_cp_als_replicas": ([_vp, _i32, _f64, _i32, _vp, _vp], _i32),
     "octen_recover_factors": ([_vp, _vp, _vp, _vp, _i64, _vp], _i32),
     "octen_fit": ([_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp], _i32),
@@ -177,6 +177,15 @@ def octen_compress_batch_coo(h, nnz, k, i, j, v, t, W):
 
 def octen_update_replicas(h):
     return _lib.octen_update_replicas(h)
+
+
+OCTEN_HEALTH_NONFINITE_BATCH, OCTEN_HEALTH_ALS_FAILED = 0x1, 0x2
+
+
+def octen_health(h):
+    bits = ctypes.c_int32(0)
+    st = _lib.octen_health(h, ctypes.cast(ctypes.byref(bits), _vp))
+    return st, bits.value
 
 
 def octen_cp_als_replicas(h, max_iters, tol, init_mode, init=None, iters_done=None):
@@ -491,6 +500,11 @@ class Octen:
         self._pend += self._tz
         self._tz = 0
 
+    def health(self):
+        """(status, bits) of octen_health: waits, reports and clears the
+        conditions recorded on the device since the last report."""
+        return octen_health(self.h)
+
     def cp_als_replicas(self, iters, tol=0.0, init=None, want_iters=False, learned=False):
         mode = OCTEN_INIT_GIVEN if init is not None else (
             OCTEN_INIT_LEARNED if learned else OCTEN_INIT_PREV)
@@ -502,11 +516,11 @@ class Octen:
 
     def recover_factors(self, A, B, C):
         K = ctypes.c_int64(0)
-        self._check(octen_recover_factors(self.h, A, B, C, C.shape[0],
-                                          ctypes.cast(ctypes.byref(K), _vp)),
-                    "octen_recover_factors")
-        self.K = K.value
-        self._pend = 0
+        st = octen_recover_factors(self.h, A, B, C, C.shape[0], ctypes.cast(ctypes.byref(K), _vp))
+        if st in (OCTEN_OK, OCTEN_ERR_NUMERIC):   # the factors were written either way
+            self.K = K.value
+            self._pend = 0
+        self._check(st, "octen_recover_factors")
         return self.K
 
     def recover_factors_async(self, A, B, C):

@@ -21,6 +21,7 @@ SHAPES = [
     (130, 160, 6, 6, 36, 3, 30, 12, "bf16"),
     (64, 64, 3, 3, 24, 3, 20, 5, "f32"),
     (200, 120, 8, 5, 40, 3, 40, 16, "bf16"),
+    (150, 97, 5, 4, 24, 3, 24, 8, "bf16x2"),
 ]
 ROUNDS = 4
 
@@ -148,6 +149,59 @@ def test_group_fp64_streams_match_oracle():
         for e, o in zip(engs, oras):
             assert rel(e.state(oc.OCTEN_STATE_Y).cpu().numpy(), o.Y) <= 1e-12
             assert rel(e.state(oc.OCTEN_STATE_FACTORS).cpu().numpy(), o.F) <= 1e-10
+    group.close()
+    for e in engs:
+        e.close()
+
+
+def test_group_narrow_streams_fit_gate():
+    """Three float32 streams of uneven shapes (FP32 and two-term BF16
+    compression) stepped as one group: after every round the fit of each
+    (Sec. 5.1, over all slices seen) lies within 1e-3 of the FP64 oracle's
+    on the same slices."""
+    import torch
+    from oracle import OctenOracle, fit_dense
+    from paper_1807_01350_amd import octen as oc
+    spec = [(Case("gn0", 160, 140, 6, 6, 30, 3, (40, 10, 10, 10), iters=20, config_id=74), "f32"),
+            (Case("gn1", 210, 130, 8, 8, 36, 3, (50, 12, 12, 12), iters=20, config_id=75), "bf16x2"),
+            (Case("gn2", 120, 123, 5, 5, 24, 3, (30, 8, 8, 8), iters=20, config_id=76), "bf16x2")]
+    engs, oras, bufs, ins, outs = [], [], [], [], []
+    for c, form in spec:
+        X, U, V, Ws, init = make_inputs(c, x_dtype=np.float32)
+        ins.append((X, U, V, Ws, init))
+        e = oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, torch.from_numpy(U).cuda(),
+                     torch.from_numpy(V).cuda(), x_dtype="f32", compress_dtype=form,
+                     flags=oc.OCTEN_FLAG_ALS_ONE_WG)
+        o = OctenOracle(c.I, c.J, c.R, c.P, c.Q, c.S, U, V)
+        t0 = c.batches[0]
+        e.compress_batch(torch.from_numpy(X[:t0]).cuda(), torch.from_numpy(Ws[0]).cuda())
+        e.update_replicas()
+        e.cp_als_replicas(c.iters, init=torch.from_numpy(init).cuda())
+        o.compress_batch(X[:t0].astype(np.float64), Ws[0]); o.update_replicas()
+        o.cp_als_replicas(c.iters, init=init)
+        out = [torch.empty((n, c.R), dtype=torch.float64, device="cuda") for n in (c.I, c.J, c.K)]
+        e.recover_factors(*out); o.recover_factors()
+        engs.append(e); oras.append(o); outs.append(out)
+        bufs.append((torch.empty((c.batches[1], c.I, c.J), dtype=torch.float32, device="cuda"),
+                     torch.empty((c.batches[1], c.M1), dtype=torch.float64, device="cuda")))
+    group = oc.Group(engs)
+    for r in (1, 2, 3):
+        for (c, form), (X, U, V, Ws, init), (xb, wb), o in zip(spec, ins, bufs, oras):
+            k0 = sum(c.batches[:r])
+            xb.copy_(torch.from_numpy(X[k0:k0 + c.batches[r]]))
+            wb.copy_(torch.from_numpy(Ws[r]))
+            o.compress_batch(X[k0:k0 + c.batches[r]].astype(np.float64), Ws[r])
+            o.update_replicas(); o.cp_als_replicas(c.iters); o.recover_factors()
+        group.step(bufs, spec[0][0].iters)
+        for (c, form), (X, *_), e, o, out in zip(spec, ins, engs, oras, outs):
+            K = e.recover_factors(*out)
+            assert K == o.K
+            sse, nx = e.fit_terms(torch.from_numpy(X[:K]).cuda(), 0, *out)
+            fit = 1.0 - np.sqrt(sse / nx)
+            fit_o = fit_dense(X[:K].astype(np.float64), o.A, o.B, o.C)[0]
+            print(f"[group] round {r} {c.name} {form}: fit {fit:.6f} oracle {fit_o:.6f}",
+                  file=sys.stderr, flush=True)
+            assert abs(fit - fit_o) <= 1e-3, (r, c.name, fit, fit_o)
     group.close()
     for e in engs:
         e.close()

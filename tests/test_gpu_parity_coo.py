@@ -262,3 +262,62 @@ def test_coo_full_size_batch_sampled():
     ref = compress_coo_entries(k, i, j, v, t, U, V, W, P, Q, S, picks)
     got = np.array([Z[p, a, b, :] for p, a, b in picks])
     assert rel(got, ref) <= 1e-5, rel(got, ref)
+
+
+def test_coo_stream_sparse_workload_replicas():
+    """The sparse workload's replica shape (P = 16 replicas of 80^3, S = 3,
+    rank 20) on a 5000 x 5000 stream of truncated-Zipf coordinates, three
+    batches through the whole update: the FP64 handle within 1e-10 of the
+    oracle (factors) and its fit within 1e-10; the FP32-gather handle of the
+    two-term form with its fit within 1e-3 of the oracle's."""
+    import torch
+    from oracle import OctenOracle, fit_coo_identity
+    from paper_1807_01350_amd import octen as oc
+    I = J = 5000
+    R, P, Q, S, per, cid = 20, 16, 80, 3, 4000, 27
+    batches = (20, 10, 10)
+    iters = 10
+    K = sum(batches)
+    _, _, _, k, i, j, v = synth.coo_stream(I, J, K, R, per, 0.01, cid)
+    U, V = synth.compression_UV(I, J, P, Q, S, cid)
+    M1 = S + P * (Q - S)
+    init = synth.als_init(P, Q, R, cid)
+    Ws = [synth.temporal_W(t, M1, cid, b) for b, t in enumerate(batches)]
+    o = OctenOracle(I, J, R, P, Q, S, U, V)
+    engs = {"f64": oc.Octen(I, J, R, P, Q, S, torch.from_numpy(U).cuda(), torch.from_numpy(V).cuda()),
+            "bf16x2": oc.Octen(I, J, R, P, Q, S, torch.from_numpy(U).cuda(),
+                               torch.from_numpy(V).cuda(), x_dtype="f32", compress_dtype="bf16x2")}
+    outs = {f: [torch.empty((n, R), dtype=torch.float64, device="cuda") for n in (I, J, K)]
+            for f in engs}
+    tinit = torch.from_numpy(init).cuda()
+    k0 = 0
+    for b, t in enumerate(batches):
+        sel = (k >= k0) & (k < k0 + t)
+        kb, ib, jb, vb = k[sel] - k0, i[sel], j[sel], v[sel]
+        print(f"[parity-coo] P=16 Q=80 R=20 batch {b} nnz={vb.size}", file=sys.stderr, flush=True)
+        o.compress_batch_coo(kb, ib, jb, vb, t, Ws[b])
+        o.update_replicas()
+        o.cp_als_replicas(iters, init=init if b == 0 else None)
+        Ar, Br, Cr = o.recover_factors()
+        tk, ti, tj, tv, tW = _dev(kb.astype(np.int32), ib, jb, vb, Ws[b])
+        for f, eng in engs.items():
+            eng.compress_batch_coo(tk, ti, tj, tv, t, tW)
+            eng.update_replicas()
+            eng.cp_als_replicas(iters, init=tinit if b == 0 else None)
+            assert eng.recover_factors(*outs[f]) == o.K
+        A, B, C = (x.cpu().numpy() for x in outs["f64"])
+        assert rel(A, Ar) <= 1e-10 and rel(B, Br) <= 1e-10 and rel(C[:o.K], Cr) <= 1e-10, b
+        k0 += t
+        sel = k < k0
+        fit_ref = fit_coo_identity(k[sel], i[sel], j[sel], v[sel], Ar, Br, Cr)[0]
+        tk, ti, tj, tv = _dev(k[sel].astype(np.int32), i[sel], j[sel], v[sel])
+        fits = {}
+        for f, eng in engs.items():
+            nx, inner, gram = eng.fit_coo_terms(tk, ti, tj, tv, 0, *outs[f], k0)
+            fits[f] = 1.0 - np.sqrt(max(nx - 2 * inner + gram, 0.0) / nx)
+        print(f"[parity-coo] batch {b}: fit oracle {fit_ref:.6f} f64 {fits['f64']:.6f} "
+              f"bf16x2 {fits['bf16x2']:.6f}", file=sys.stderr, flush=True)
+        assert abs(fits["f64"] - fit_ref) <= 1e-10
+        assert abs(fits["bf16x2"] - fit_ref) <= 1e-3
+    for eng in engs.values():
+        eng.close()

@@ -30,6 +30,14 @@ CASES = [
     # fit in LDS next to the factor state, so the ALS reads it from global
     # memory (16 workgroups per replica, two replicas on some XCDs)
     Case("gx_slab", 120, 110, 16, 9, 64, 3, (30, 10), iters=20, config_id=15),
+    # the ranks of the sparse and batched workloads: R = 20 with Q = 80 (the
+    # sparse stream's replica side; slab in global memory) and R = 24 with the
+    # slab in LDS, both on the 24-wide inverse; R = 30 with Q = 64 (global
+    # memory) and Q = 32 (LDS) on the 32-wide inverse
+    Case("r20_q80", 120, 120, 20, 4, 80, 3, (40, 10), iters=15, config_id=16),
+    Case("r24_lds", 100, 100, 24, 4, 40, 3, (40, 10), iters=15, config_id=17),
+    Case("r30_q64", 110, 110, 30, 4, 64, 3, (40, 10), iters=12, config_id=18),
+    Case("r30_lds", 100, 100, 30, 4, 32, 3, (40, 10), iters=15, config_id=19),
 ]
 
 _cache = {}
