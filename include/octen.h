@@ -249,6 +249,25 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C,
 octen_status octen_fit(octen_t h, const void* X, int64_t t, int64_t k0, const double* A,
                        const double* B, const double* C, double* out_host);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the dense
+ * fitness terms of octen_fit without a handle and without any allocation,
+ * through the same kernels.  X: [t][I][J] device array of x_dtype
+ * (OCTEN_F64 or OCTEN_F32); A: [I][R], B: [J][R], C: [k0 + t][R] f64 device
+ * arrays (slice k of X is row k0 + k of C); stream: a hipStream_t of the
+ * current device (NULL = default stream).  out_host[0] += sum (X - [[A,B,C]])^2,
+ * out_host[1] += sum X^2 (synchronises the stream).  The block partial sums
+ * live in a fixed device array of 2 * 2048 + 2 doubles (32 KiB) that the
+ * library keeps on every device it has run on until the process ends (at
+ * most 2048 blocks are launched, so no input size overflows it); calls that
+ * overlap on one device race on that array.  OCTEN_ERR_ARG for null
+ * pointers, t, I or J < 1, k0 < 0, R outside [1, 32], t * I >= 2^40 or
+ * another x_dtype; OCTEN_ERR_HIP when the array's address cannot be taken
+ * or a launch or copy fails. */
+octen_status octen_fit_noalloc(const void* X, int32_t x_dtype, int64_t t, int64_t I, int64_t J,
+                               int32_t R, int64_t k0, const double* A, const double* B,
+                               const double* C, void* stream, double* out_host);
+
 /* Sec. 5.1 fitness of a sparse tensor through
  * ||X - Xh||^2 = ||X||^2 - 2 <X, Xh> + sum((A^T A) * (B^T B) * (C^T C)).
  * Nonzeros as in octen_compress_batch_coo (bounds are checked, order is not),

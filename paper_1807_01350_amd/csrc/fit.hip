@@ -2,7 +2,18 @@
 // sum X^2, accumulated in FP64 with a fixed reduction order (deterministic).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
+#include "octen.h"
 #include "octen_internal.h"
+
+// Partial sums of octen_fit_noalloc: 2 doubles per block of fit_kernel, then
+// the 2 reduced terms.  The library holds this array on every device it runs
+// on until the process ends; host code reaches it only through the address
+// taken by hipGetSymbolAddress (the array's name is not a device address in
+// host code).
+constexpr int NOALLOC_PARTS = 2048;
+static __device__ __align__(256) double scratch[2 * NOALLOC_PARTS + 2];
 
 namespace octen {
 
@@ -81,3 +92,60 @@ hipError_t fit_dense(hipStream_t s, const void* X, bool x_f64, int64_t t, int64_
 }
 
 }  // namespace octen
+
+namespace octen {
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, taken once per device.
+hipError_t scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch[dev] = (double*)p;
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+}  // namespace octen
+
+extern "C" octen_status octen_fit_noalloc(const void* X, int32_t x_dtype, int64_t t, int64_t I,
+                                          int64_t J, int32_t R, int64_t k0, const double* A,
+                                          const double* B, const double* C, void* stream,
+                                          double* out_host) {
+  if (!X || !A || !B || !C || !out_host) return OCTEN_ERR_ARG;
+  if (t < 1 || I < 1 || J < 1 || k0 < 0 || R < 1 || R > 32) return OCTEN_ERR_ARG;
+  if (x_dtype != OCTEN_F64 && x_dtype != OCTEN_F32) return OCTEN_ERR_ARG;
+  if (I > ((int64_t)1 << 40) / t) return OCTEN_ERR_ARG;   // t * I rows must stay addressable
+  double* sp = nullptr;
+  if (octen::scratch_address(&sp) != hipSuccess) return OCTEN_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t rows = t * I;
+  // the grid never exceeds the array: at most NOALLOC_PARTS partial pairs;
+  // every pair is written before fit_reduce reads it, so nothing is cleared
+  const int parts = rows < NOALLOC_PARTS ? (int)rows : NOALLOC_PARTS;
+  double* partials = sp;
+  double* terms = sp + 2 * NOALLOC_PARTS;
+  if (octen::fit_dense(s, X, x_dtype == OCTEN_F64, t, I, J, R, k0, A, B, C, partials, parts,
+                       terms) != hipSuccess)
+    return OCTEN_ERR_HIP;
+  double o[2];
+  if (hipMemcpyAsync(o, terms, sizeof(o), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return OCTEN_ERR_HIP;
+  out_host[0] += o[0];
+  out_host[1] += o[1];
+  return OCTEN_OK;
+}

@@ -79,6 +79,7 @@ _SIGS = {
     "octen_compress_batch_coo": ([_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp], _i32),
     "octen_update_replicas": ([_vp], _i32),
     "octen_health": ([_vp, _vp], _i32),
+    "octen_fit_noalloc": ([_vp, _i32, _i64, _i64, _i64, _i32, _i64, _vp, _vp, _vp, _vp, _vp], _i32),
     "octen_cp_als_replicas": ([_vp, _i32, _f64, _i32, _vp, _vp], _i32),
     "octen_recover_factors": ([_vp, _vp, _vp, _vp, _i64, _vp], _i32),
     "octen_fit": ([_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp], _i32),
@@ -180,6 +181,17 @@ def octen_update_replicas(h):
 
 
 OCTEN_HEALTH_NONFINITE_BATCH, OCTEN_HEALTH_ALS_FAILED = 0x1, 0x2
+
+
+def octen_fit_noalloc(X, t, I, J, R, k0, A, B, C, stream=None, acc=(0.0, 0.0)):
+    """Dense fitness terms without a handle and without device allocation
+    (X: float32 or float64 torch tensor [t][I][J]); returns (status,
+    (sse, sum X^2)) with the terms added to acc."""
+    out = (ctypes.c_double * 2)(*acc)
+    xd = OCTEN_F64 if getattr(X, "dtype", None) == torch.float64 else OCTEN_F32
+    st = _lib.octen_fit_noalloc(_ptr(X), xd, int(t), int(I), int(J), int(R), int(k0), _ptr(A),
+                                _ptr(B), _ptr(C), stream, ctypes.cast(out, _vp))
+    return st, (out[0], out[1])
 
 
 def octen_health(h):
