@@ -51,7 +51,8 @@ def parse():
     ap.add_argument("--overlap", action="store_true",
                     help="dense stream: a second pass that overlaps the next batch's "
                          "compression with the current batch's ALS and recovery")
-    ap.add_argument("--workload", choices=("dense", "sparse", "batched", "forms"), default="dense")
+    ap.add_argument("--workload", choices=("dense", "sparse", "batched", "forms", "copy"),
+                    default="dense")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--train-streams", type=int, default=6)
     ap.add_argument("--streams", type=int, default=64)
@@ -775,12 +776,29 @@ def run_dense(args):
     print(json.dumps(out))
 
 
+def run_copy(args):
+    """Counter calibration: a plain device-to-device copy of 256 MiB, three
+    times, whose hardware byte counters (FETCH_SIZE, WRITE_SIZE) are compared
+    with the 3 x 256 MiB read and written."""
+    import torch
+    n = 64 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "copy", "bytes_per_copy": n * 4, "copies": 3}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "copy":
+        return run_copy(args)
     if args.workload == "sparse":
         return run_sparse(args)
     if args.workload == "forms":

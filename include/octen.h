@@ -60,12 +60,11 @@ typedef enum {
  * hi = bf16(x) and lo = bf16(x - hi) (16 significant bits), both multiplied
  * into float32 accumulators, and the intermediate mode-2 product is carried
  * into the mode-1 product the same way; it needs compression matrices whose
- * entries are bfloat16 values.  OCTEN_F16 is reserved (not implemented). */
+ * entries are bfloat16 values.  (Value 3 is not used.) */
 typedef enum {
   OCTEN_F64 = 0,
   OCTEN_F32 = 1,
   OCTEN_BF16 = 2,
-  OCTEN_F16 = 3,
   OCTEN_BF16X2 = 4
 } octen_dtype;
 
@@ -138,8 +137,8 @@ typedef struct {
   int32_t compress_dtype;  /* compression arithmetic: F64, F32, BF16 or BF16X2
                               inputs; accumulation is F64 for F64, else F32;
                               BF16X2 needs U and V on the bfloat16 grid
-                              (OCTEN_ERR_ARG otherwise), F16 gives
-                              OCTEN_ERR_UNSUPPORTED                          */
+                              (OCTEN_ERR_ARG otherwise); any other value
+                              gives OCTEN_ERR_UNSUPPORTED                     */
   int32_t als_dtype;       /* MTTKRP arithmetic: OCTEN_F64 (anything else gives
                               OCTEN_ERR_UNSUPPORTED); R x R solves and
                               recovery are always F64                         */

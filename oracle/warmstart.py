@@ -43,16 +43,24 @@ def mlp_param_shapes(n_in, n_hidden, n_out):
             (n_out, n_hidden), (n_out,)]
 
 
-def mlp_forward(params, X, n_out):
+def _ident(x):
+    return x
+
+
+def mlp_forward(params, X, n_out, rnd=None):
     """Y = X[:, :n_out] + W3 relu(W2 relu(W1 X + b1) + b2) + b3, row-wise.
-    Returns Y and the activations needed by the backward pass."""
+    Returns Y and the activations needed by the backward pass.  rnd, if
+    given, is applied to both operands of every matrix product (a network
+    whose products take narrower operands, e.g. bfloat16, with exact sums);
+    biases, rectifiers and the residual stay exact."""
+    r = rnd or _ident
     W1, b1, W2, b2, W3, b3 = params
     X = np.asarray(X, np.float64)
-    Z1 = X @ W1.T + b1
+    Z1 = r(X) @ r(W1).T + b1
     H1 = np.maximum(Z1, 0.0)
-    Z2 = H1 @ W2.T + b2
+    Z2 = r(H1) @ r(W2).T + b2
     H2 = np.maximum(Z2, 0.0)
-    Y = X[:, :n_out] + H2 @ W3.T + b3
+    Y = X[:, :n_out] + r(H2) @ r(W3).T + b3
     return Y, (X, Z1, H1, Z2, H2)
 
 
@@ -63,21 +71,23 @@ def mse_loss(Y, T):
     return float(np.sum(D * D) / n), 2.0 * D / n
 
 
-def mlp_backward(params, cache, dY):
+def mlp_backward(params, cache, dY, rnd=None):
     """Gradients of a scalar loss with dL/dY given, by the chain rule through
     the three affine maps and the two rectifiers (relu'(0) = 0).  The
-    residual path adds dY to dL/dX but X is an input, so it is not returned."""
+    residual path adds dY to dL/dX but X is an input, so it is not returned.
+    rnd as in mlp_forward: applied to both operands of every product."""
+    r = rnd or _ident
     W1, b1, W2, b2, W3, b3 = params
     X, Z1, H1, Z2, H2 = cache
-    gW3 = dY.T @ H2
+    gW3 = r(dY).T @ r(H2)
     gb3 = dY.sum(0)
-    dH2 = dY @ W3
+    dH2 = r(dY) @ r(W3)
     dZ2 = dH2 * (Z2 > 0)
-    gW2 = dZ2.T @ H1
+    gW2 = r(dZ2).T @ r(H1)
     gb2 = dZ2.sum(0)
-    dH1 = dZ2 @ W2
+    dH1 = r(dZ2) @ r(W2)
     dZ1 = dH1 * (Z1 > 0)
-    gW1 = dZ1.T @ X
+    gW1 = r(dZ1).T @ r(X)
     gb1 = dZ1.sum(0)
     return [gW1, gb1, gW2, gb2, gW3, gb3]
 

@@ -27,7 +27,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OCTEN_ABI_VERSION = 1
 OCTEN_OK, OCTEN_ERR_ARG, OCTEN_ERR_STATE, OCTEN_ERR_HIP, OCTEN_ERR_NOMEM, OCTEN_ERR_NUMERIC, \
     OCTEN_ERR_UNSUPPORTED = range(7)
-OCTEN_F64, OCTEN_F32, OCTEN_BF16, OCTEN_F16, OCTEN_BF16X2 = range(5)
+OCTEN_F64, OCTEN_F32, OCTEN_BF16, OCTEN_BF16X2 = 0, 1, 2, 4
 OCTEN_INIT_GIVEN, OCTEN_INIT_PREV, OCTEN_INIT_LEARNED = 0, 1, 2
 (OCTEN_STATE_Y, OCTEN_STATE_Z, OCTEN_STATE_FACTORS, OCTEN_STATE_LAMBDA, OCTEN_STATE_PERM,
  OCTEN_STATE_ALIGNED, OCTEN_STATE_RHS, OCTEN_STATE_H, OCTEN_STATE_TPERM, OCTEN_STATE_ITERS,
@@ -41,8 +41,7 @@ OCTEN_FLAG_ALS_DEVICE_SYNC = 0x10
 (OCTEN_STAGE_COMPRESS_MAIN, OCTEN_STAGE_COMPRESS_MODE3, OCTEN_STAGE_UPDATE, OCTEN_STAGE_ALS,
  OCTEN_STAGE_RECOVER, OCTEN_STAGE_COO_INDEX) = range(6)
 
-DTYPES = {"f64": OCTEN_F64, "f32": OCTEN_F32, "bf16": OCTEN_BF16, "f16": OCTEN_F16,
-          "bf16x2": OCTEN_BF16X2}
+DTYPES = {"f64": OCTEN_F64, "f32": OCTEN_F32, "bf16": OCTEN_BF16, "bf16x2": OCTEN_BF16X2}
 
 
 class octen_batch_desc(ctypes.Structure):

@@ -35,13 +35,21 @@ DIMS = [(92, 64, 60, 37), (272, 256, 240, 320)]
 
 @pytest.mark.parametrize("n_in,n_h,n_out,n", DIMS)
 def test_forward_matches_oracle(n_in, n_h, n_out, n):
+    """The network is a BF16 network: every product takes bfloat16 operands
+    with float32 sums.  The oracle evaluates that definition (rounded
+    operands, exact sums) from the same inputs: within 1e-4 normwise; the
+    plain FP64 network is within 2e-2."""
     import torch
+    from oracle.precision import round_bf16
     from oracle.warmstart import mlp_forward
     net, p = _net(n_in, n_h, n_out, 31)
     X = np.random.default_rng(1).standard_normal((n, n_in)).astype(np.float32)
     Y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
-    Yr, _ = mlp_forward(_split(p, n_in, n_h, n_out), X, n_out)
+    params = _split(p, n_in, n_h, n_out)
+    Yb, _ = mlp_forward(params, X, n_out, rnd=round_bf16)
+    Yr, _ = mlp_forward(params, X, n_out)
     # compare the learned part (the residual is exact)
+    assert rel(Y - X[:, :n_out], Yb - X[:, :n_out]) <= 1e-4
     assert rel(Y - X[:, :n_out], Yr - X[:, :n_out]) <= 2e-2
     assert np.array_equal(Y.shape, (n, n_out))
     net.close()
@@ -49,29 +57,30 @@ def test_forward_matches_oracle(n_in, n_h, n_out, n):
 
 @pytest.mark.parametrize("n_in,n_h,n_out,n", DIMS)
 def test_gradients_match_oracle(n_in, n_h, n_out, n):
-    """The rectifier masks are decisions taken by floating point: both sides
-    take them from the kernel's forward pass (its hidden activations), and the
-    oracle then runs the backward pass in FP64 from the kernel's output."""
+    """Gradients of the mean squared error against the oracle's own forward
+    and backward pass of the BF16 network (bfloat16 operands in every
+    product, exact sums, rectifier masks from the oracle's forward): within
+    1e-3 normwise per parameter array.  The GPU's loss is also within 1e-2 of
+    the plain FP64 network's."""
     import torch
+    from oracle.precision import round_bf16
     from oracle.warmstart import mlp_backward, mlp_forward, mse_loss
     net, p = _net(n_in, n_h, n_out, 32)
     rng = np.random.default_rng(2)
     X = rng.standard_normal((n, n_in)).astype(np.float32)
     T = rng.standard_normal((n, n_out)).astype(np.float32)
-    tX = torch.from_numpy(X).cuda()
-    g, loss = net.gradients(tX, torch.from_numpy(T).cuda())
-    Yg = net.forward(tX).cpu().numpy().astype(np.float64)
-    H1, H2 = (h.cpu().numpy().astype(np.float64) for h in net.last_activations(n))
+    g, loss = net.gradients(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
     params = _split(p, n_in, n_h, n_out)
-    L, dY = mse_loss(Yg, T.astype(np.float64))
-    gr = mlp_backward(params, (X.astype(np.float64), H1, H1, H2, H2), dY)
-    assert abs(loss - L) <= 1e-6 * L
-    # the loss of the exact forward pass is close as well
+    Yb, cache = mlp_forward(params, X, n_out, rnd=round_bf16)
+    Lb, dY = mse_loss(Yb, T.astype(np.float64))
+    gr = mlp_backward(params, cache, dY, rnd=round_bf16)
+    assert abs(loss - Lb) <= 1e-5 * Lb
     Lx = mse_loss(mlp_forward(params, X, n_out)[0], T.astype(np.float64))[0]
     assert abs(loss - Lx) <= 1e-2 * Lx
     got = _split(g.cpu().numpy(), n_in, n_h, n_out)
     for name, a, b in zip(("W1", "b1", "W2", "b2", "W3", "b3"), got, gr):
-        assert rel(a, b) <= 2e-2, (name, rel(a, b))
+        print(f"[warm] grad {name} rel {rel(a, b):.2e}", file=sys.stderr, flush=True)
+        assert rel(a, b) <= 1e-3, (name, rel(a, b))
     net.close()
 
 
