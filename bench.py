@@ -51,11 +51,15 @@ def parse():
     ap.add_argument("--overlap", action="store_true",
                     help="dense stream: a second pass that overlaps the next batch's "
                          "compression with the current batch's ALS and recovery")
-    ap.add_argument("--workload", choices=("dense", "sparse", "batched", "forms", "copy"),
+    ap.add_argument("--workload", choices=("dense", "dense50", "long", "sweep", "sparse",
+                                           "batched", "forms", "copy"),
                     default="dense")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--train-streams", type=int, default=6)
     ap.add_argument("--streams", type=int, default=64)
+    ap.add_argument("--long-I", type=int, default=100)
+    ap.add_argument("--long-K", type=int, default=100_000)
+    ap.add_argument("--sweep-seeds", type=int, default=5)
     return ap.parse_args()
 
 
@@ -776,6 +780,357 @@ def run_dense(args):
     print(json.dumps(out))
 
 
+def run_dense50(args):
+    """The dense 50 x 50 FP64 stream (rank 5, 30 initial slices then batches of
+    10; P = 4 replicas of 20^3, S = 3, 50 sweeps).  Fit gate over exactly its
+    50 slices (GPU and FP64 oracle after every batch), then timed batches of
+    10 continuing the same stream; the oracle is timed on the same batches
+    (about 10 s of them).  Latency-bound: absolute microseconds per batch."""
+    import torch
+    import oracle
+    from paper_1807_01350_amd import octen as oc
+    from paper_1807_01350_amd import synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    c = synth.C1
+    t = 10
+    nsteps = args.warmup + args.steps
+    ngate = len(c.batches)
+    K = c.t0 + t * (ngate + nsteps)
+    _, _, _, Xh = synth.dense_stream(c.I, c.J, K, c.R, c.sigma, c.config_id, dtype=np.float64)
+    X = torch.from_numpy(Xh).to(dev)
+    U, V = synth.compression_UV(c.I, c.J, c.P, c.Q, c.S, c.config_id)
+    nb = ngate + nsteps
+    Ws = [synth.temporal_W(c.t0 if b == 0 else t, c.M1, c.config_id, b) for b in range(nb + 1)]
+    tW = [torch.from_numpy(w).to(dev) for w in Ws]
+    init = synth.als_init(c.P, c.Q, c.R, c.config_id)
+    eng = oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, torch.from_numpy(U).to(dev),
+                   torch.from_numpy(V).to(dev), x_dtype="f64", compress_dtype="f64",
+                   flags=oc.OCTEN_FLAG_TIMING)
+    A = torch.empty((c.I, c.R), dtype=torch.float64, device=dev)
+    B = torch.empty((c.J, c.R), dtype=torch.float64, device=dev)
+    C = torch.empty((K, c.R), dtype=torch.float64, device=dev)
+    tinit = torch.from_numpy(init).to(dev)
+
+    def step(b, k0, tt):
+        eng.compress_batch(X[k0:k0 + tt], tW[b])
+        eng.update_replicas()
+        eng.cp_als_replicas(args.iters, init=tinit if b == 0 else None)
+        eng.recover_factors_async(A, B, C)
+
+    o = oracle.OctenOracle(c.I, c.J, c.R, c.P, c.Q, c.S, U, V)
+    fits_gpu, fits_or, k0 = [], [], 0
+    for b in range(ngate + 1):
+        tt = c.t0 if b == 0 else t
+        step(b, k0, tt)
+        o.compress_batch(Xh[k0:k0 + tt], Ws[b])
+        o.update_replicas()
+        o.cp_als_replicas(args.iters, init=init if b == 0 else None)
+        Ao, Bo, Co = o.recover_factors()
+        k0 += tt
+        sse, nx = eng.fit_terms(X[:k0], 0, A, B, C)
+        fits_gpu.append(1.0 - float(np.sqrt(sse / nx)))
+        fits_or.append(oracle.fit_dense(Xh[:k0], Ao, Bo, Co)[0])
+    d = [abs(a - b) for a, b in zip(fits_gpu, fits_or)]
+    gate = {"stream": f"{c.t0} initial slices then {ngate} batches of {t} (K = {k0})",
+            "form": "f64", "fit_gpu": fits_gpu, "fit_oracle": fits_or, "max_abs_dfit": max(d),
+            "bar": 1e-3, "pass": bool(max(d) <= 1e-3)}
+    b0 = ngate + 1
+    for b in range(b0, b0 + args.warmup):
+        step(b, k0, t)
+        k0 += t
+    torch.cuda.synchronize()
+    k_timed = k0
+    t_start = time.perf_counter()
+    for b in range(b0 + args.warmup, b0 + nsteps):
+        step(b, k0, t)
+        k0 += t
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    st = {name: (float(np.mean(eng.stage_ms(stage, args.steps))) if eng.stage_ms(stage, args.steps)
+                 else None)
+          for name, stage in (("compress_main", oc.OCTEN_STAGE_COMPRESS_MAIN),
+                              ("compress_mode3", oc.OCTEN_STAGE_COMPRESS_MODE3),
+                              ("update", oc.OCTEN_STAGE_UPDATE), ("als", oc.OCTEN_STAGE_ALS),
+                              ("recover", oc.OCTEN_STAGE_RECOVER))}
+    # the oracle on the same timed batches (continuing its own stream state
+    # from the gate), up to about 10 s
+    dt_or, n_or, ko = 0.0, 0, c.t0 + t * ngate
+    for b in range(b0, b0 + nsteps):
+        t0_ = time.perf_counter()
+        o.compress_batch(Xh[ko:ko + t], Ws[b])
+        o.update_replicas()
+        o.cp_als_replicas(args.iters)
+        o.recover_factors()
+        dt_or += time.perf_counter() - t0_
+        ko += t
+        n_or += 1
+        if dt_or > 10.0:
+            break
+    als_flops = 4.0 * c.Q ** 3 * c.R * c.P * args.iters
+    als_ms = st["als"]
+    out = {
+        "metric": METRIC, "value": round(t * args.steps / elapsed, 3), "unit": "slices/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 4), "us_per_batch": round(1e6 * elapsed / args.steps, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded host generator; rank-5 U[0,1] CP model + N(0, 0.01^2))",
+        "config": {"workload": f"dense50_f64: I=J=50, R=5, {c.t0} initial slices then batches of "
+                               f"{t}; P=4, Q=20, S=3; {args.iters} ALS sweeps; FP64 throughout; "
+                               f"timed batches continue the stream after its two gate batches",
+                   "I": c.I, "J": c.J, "R": c.R, "P": c.P, "Q": c.Q, "S": c.S, "batch": t,
+                   "initial_slices": c.t0, "als_iters": args.iters, "first_timed_slice": k_timed},
+        "fit_gate": gate, "fit_oracle": fits_or[-1], "abs_dfit": max(d),
+        "stage_ms": {k: (round(v, 4) if v is not None else None) for k, v in st.items()},
+        "roofline": {"bound": "mfma", "achieved": round(als_flops / (als_ms * 1e-3) / 1e12, 4),
+                     "peak": 78.6, "unit": "TFLOP/s",
+                     "frac": round(als_flops / (als_ms * 1e-3) / 1e12 / 78.6, 6), "traffic": None,
+                     "kernel": "replica ALS (4 Q^3 R flop per replica and sweep, FP64 MFMA); "
+                               "the whole batch is bound by launch latency"},
+        "cpu_baseline": {"value": round(t * n_or / dt_or, 3), "unit": "slices/s",
+                         "cores": cores_used(), "kind": "oracle",
+                         "sample": f"{n_or} update batches of {t} slices of the same stream through "
+                                   f"the FP64 oracle, {dt_or:.2f} s"},
+    }
+    eng.close()
+    print(json.dumps(out))
+
+
+def long_shape(I):
+    """Replica layout of the long-stream workload for slices of I x I: Q = 20,
+    S = 3, R = 5 and the fewest replicas with M1 = S + P (Q - S) > I (modes 1
+    and 2 determined, Eq. 8's first two terms), at least two."""
+    Q, S, R = 20, 3, 5
+    P = max(2, (I - S) // (Q - S) + 1)
+    return R, P, Q, S
+
+
+def run_long(args):
+    """The long-stream workload of the scalability experiment (Sec. 5.4.2):
+    small slices (I = J = --long-I, 100 by default), a long time mode
+    (K = --long-K slices, 10^5 by default), an initial summary of at most
+    10 % of the stream and at most M1 slices, then batches of 10 slices.  Each batch runs compress, update,
+    ALS (--iters sweeps from the previous factors) and recovery; the stream is
+    run twice, eagerly and with compress + update + ALS replayed as one
+    captured HIP graph per batch.  Reports per-batch latency at the start
+    and at the end of the stream (the temporal carry keeps the cost of a
+    batch independent of K), the fit over all K slices, a fit gate against
+    the FP64 oracle on a prefix (the initial summary and 20 batches) and the
+    oracle's speed on that prefix."""
+    import torch
+    import oracle
+    from paper_1807_01350_amd import octen as oc
+    from paper_1807_01350_amd import synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    I = J = args.long_I
+    K = args.long_K
+    R, P, Q, S = long_shape(I)
+    M1 = S + P * (Q - S)
+    # the initial summary: at most 10 % of the stream (as the experiment
+    # sets it) and at most M1 slices, so that its temporal rows are
+    # determined by the M1 compressed rows (reading R-C1)
+    t = 10
+    t0 = max(t, (min(K // 10, M1) // t) * t)
+    nb = (K - t0) // t
+    K = t0 + nb * t
+    cid = 6
+    print(f"[bench] long stream: I=J={I}, K={K}, P={P}, Q={Q}, S={S}, R={R}", file=sys.stderr,
+          flush=True)
+    X = gen_stream(torch, I, J, K, R, 0.01, synth.seed_of(cid, 1), dev)
+    U, V = synth.compression_UV(I, J, P, Q, S, cid)
+    init = synth.als_init(P, Q, R, cid)
+    g = torch.Generator(device=dev)
+    g.manual_seed(synth.seed_of(cid, 2))
+    Wall = torch.randn((K, M1), generator=g, device=dev, dtype=torch.float64)
+    tinit = torch.from_numpy(init).to(dev)
+    results = {}
+    for mode in ("eager", "graph"):
+        flags = oc.OCTEN_FLAG_ALS_ONE_WG if mode == "graph" else 0
+        eng = oc.Octen(I, J, R, P, Q, S, torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev),
+                       x_dtype="f32", compress_dtype="f32", flags=flags)
+        A = torch.empty((I, R), dtype=torch.float64, device=dev)
+        B = torch.empty((J, R), dtype=torch.float64, device=dev)
+        C = torch.empty((K, R), dtype=torch.float64, device=dev)
+        eng.compress_batch(X[:t0], Wall[:t0])
+        eng.update_replicas()
+        eng.cp_als_replicas(args.iters, init=tinit)
+        eng.recover_factors(A, B, C)
+        group = None
+        if mode == "graph":
+            group = oc.Group([eng])
+            xb = torch.empty((t, I, J), dtype=torch.float32, device=dev)
+            wb = torch.empty((t, M1), dtype=torch.float64, device=dev)
+        lat = []
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        k0 = t0
+        for b in range(nb):
+            timed = b < 200 or b >= nb - 200
+            if timed:
+                ev[0].record()
+            if group is not None:
+                xb.copy_(X[k0:k0 + t])
+                wb.copy_(Wall[k0:k0 + t])
+                group.step([(xb, wb)], args.iters)
+            else:
+                eng.compress_batch(X[k0:k0 + t], Wall[k0:k0 + t])
+                eng.update_replicas()
+                eng.cp_als_replicas(args.iters)
+            eng.recover_factors_async(A, B, C)
+            if timed:
+                ev[1].record()
+                ev[1].synchronize()
+                lat.append(ev[0].elapsed_time(ev[1]))
+            k0 += t
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        sse = nx = 0.0
+        for q0 in range(0, K, 4096):
+            sse, nx = eng.fit_terms(X[q0:min(K, q0 + 4096)], q0, A, B, C, acc=(sse, nx))
+        results[mode] = {"slices_per_s": round(nb * t / elapsed, 1),
+                         "us_per_batch_first200": round(1e3 * float(np.mean(lat[:200])), 1),
+                         "us_per_batch_last200": round(1e3 * float(np.mean(lat[-200:])), 1),
+                         "fit_all_slices": 1.0 - float(np.sqrt(sse / nx))}
+        print(f"[bench] long {mode}: {results[mode]}", file=sys.stderr, flush=True)
+        if group is not None:
+            group.close()
+        eng.close()
+    # fit gate and oracle speed on a prefix: the initial summary and 20 batches
+    nb_or = min(20, nb)
+    kp = t0 + nb_or * t
+    Xp = X[:kp].double().cpu().numpy()
+    Wp = Wall[:kp].cpu().numpy()
+    o = oracle.OctenOracle(I, J, R, P, Q, S, U, V)
+    eng = oc.Octen(I, J, R, P, Q, S, torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev),
+                   x_dtype="f32", compress_dtype="f32")
+    A = torch.empty((I, R), dtype=torch.float64, device=dev)
+    B = torch.empty((J, R), dtype=torch.float64, device=dev)
+    C = torch.empty((kp, R), dtype=torch.float64, device=dev)
+    k0, dt_or = 0, 0.0
+    for b in range(nb_or + 1):
+        tt = t0 if b == 0 else t
+        eng.compress_batch(X[k0:k0 + tt], Wall[k0:k0 + tt])
+        eng.update_replicas()
+        eng.cp_als_replicas(args.iters, init=tinit if b == 0 else None)
+        eng.recover_factors(A, B, C)
+        t1 = time.perf_counter()
+        o.compress_batch(Xp[k0:k0 + tt], Wp[k0:k0 + tt])
+        o.update_replicas()
+        o.cp_als_replicas(args.iters, init=init if b == 0 else None)
+        Ao, Bo, Co = o.recover_factors()
+        if b > 0:
+            dt_or += time.perf_counter() - t1
+        k0 += tt
+    sse, nx = eng.fit_terms(X[:kp], 0, A, B, C)
+    fit_g = 1.0 - float(np.sqrt(sse / nx))
+    fit_o = oracle.fit_dense(Xp, Ao, Bo, Co)[0]
+    eng.close()
+    e = results["eager"]
+    out = {
+        "metric": METRIC, "value": e["slices_per_s"], "unit": "slices/s", "n_gpus": 1,
+        "steps": nb, "warmup": 0, "ms_per_step": round(1e3 * t / e["slices_per_s"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded on-device generator; rank-5 U[0,1] CP model + N(0, 0.01^2))",
+        "config": {"workload": f"long{I}: I=J={I}, K={K} ({t0} initial slices, then {nb} batches "
+                               f"of {t}), R={R}, P={P}, Q={Q}, S={S}; {args.iters} ALS sweeps per "
+                               f"batch from the previous factors; FP32 compression, FP64 solves",
+                   "I": I, "J": J, "K": K, "R": R, "P": P, "Q": Q, "S": S, "batch": t,
+                   "initial_slices": t0, "als_iters": args.iters},
+        "modes": results,
+        "fit_gate": {"prefix": f"{t0} initial slices then {nb_or} batches", "fit_gpu": fit_g,
+                     "fit_oracle": fit_o, "abs_dfit": abs(fit_g - fit_o),
+                     "pass": bool(abs(fit_g - fit_o) <= 1e-3)},
+        "roofline": None,
+        "cpu_baseline": {"value": round(nb_or * t / dt_or, 3), "unit": "slices/s",
+                         "cores": cores_used(), "kind": "oracle",
+                         "sample": f"{nb_or} update batches of {t} slices through the FP64 oracle, "
+                                   f"{dt_or:.2f} s"},
+    }
+    print(json.dumps(out))
+
+
+def run_sweep(args):
+    """The parameter sensitivity experiment (Sec. 5.4.3) and an empirical look
+    at Eq. 8: one dense FP64 stream (I = J = K = 100, rank 5, noise 0.01; 10
+    initial slices, then batches of 10 = 0.1 K), run through the whole
+    update for a range of p (Q = 20, S = 4), of Q (p = 7, S = 4) and of S
+    (p = 7, Q = 20), each with --sweep-seeds seeds of the compression
+    matrices and ALS start; reports the mean and spread of the final fit
+    with M1, Eq. 8's bound and the determinacy verdicts of every setting."""
+    import torch
+    import oracle
+    from paper_1807_01350_amd import octen as oc
+    from paper_1807_01350_amd import synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    I = J = K = 100
+    R, sigma, t0, t = 5, 0.01, 10, 10
+    _, _, _, Xh = synth.dense_stream(I, J, K, R, sigma, 5)
+    X = torch.from_numpy(Xh).to(dev)
+    grid = ([("p", P, 20, 4) for P in range(2, 13)] +
+            [("Q", 7, Q, 4) for Q in (8, 12, 16, 20, 24, 30, 40)] +
+            [("shared", 7, 20, Sv) for Sv in (1, 2, 4, 6, 8, 10, 12, 16)])
+    rows = []
+    gpu_s, slices = 0.0, 0
+    for what, P, Q, Sv in grid:
+        M1 = Sv + P * (Q - Sv)
+        fits = []
+        for seed in range(args.sweep_seeds):
+            cid = 500 + seed
+            U, V = synth.compression_UV(I, J, P, Q, Sv, cid)
+            init = torch.from_numpy(synth.als_init(P, Q, R, cid)).to(dev)
+            eng = oc.Octen(I, J, R, P, Q, Sv, torch.from_numpy(U).to(dev),
+                           torch.from_numpy(V).to(dev))
+            A = torch.empty((I, R), dtype=torch.float64, device=dev)
+            B = torch.empty((J, R), dtype=torch.float64, device=dev)
+            C = torch.empty((K, R), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            k0, b = 0, 0
+            while k0 < K:
+                tt = t0 if b == 0 else t
+                W = torch.from_numpy(synth.temporal_W(tt, M1, cid, b)).to(dev)
+                eng.compress_batch(X[k0:k0 + tt], W)
+                eng.update_replicas()
+                eng.cp_als_replicas(args.iters, init=init if b == 0 else None)
+                eng.recover_factors_async(A, B, C)
+                k0 += tt
+                b += 1
+            torch.cuda.synchronize()
+            gpu_s += time.perf_counter() - t1
+            slices += K
+            sse, nx = eng.fit_terms(X, 0, A, B, C)
+            fits.append(1.0 - float(np.sqrt(sse / nx)))
+            eng.close()
+        bits, pmin = oracle.identifiability(I, J, K, t, R, P, Q, Sv)
+        rows.append({"vary": what, "p": P, "Q": Q, "shared": Sv, "M1": M1,
+                     "p_min_eq8": round(pmin, 3), "eq8_holds": bool(bits & 1),
+                     "modes12_determined": bool(bits & 2 and bits & 4),
+                     "fit_median": float(np.median(fits)), "fit_max": max(fits),
+                     "fit_min": min(fits)})
+        print(f"[bench] sweep {rows[-1]}", file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC, "value": round(slices / gpu_s, 1), "unit": "slices/s", "n_gpus": 1,
+        "steps": len(grid) * args.sweep_seeds, "warmup": 0,
+        "ms_per_step": round(1e3 * gpu_s / (len(grid) * args.sweep_seeds), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded host generator; rank-5 U[0,1] CP model + N(0, 0.01^2))",
+        "config": {"workload": f"sweep: I=J=K={I}, R={R}, {t0} initial slices then batches of "
+                               f"{t}; {args.iters} ALS sweeps; FP64; {args.sweep_seeds} seeds "
+                               f"per setting; one step = one whole stream",
+                   "seeds": args.sweep_seeds},
+        "sweep": rows,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def run_copy(args):
     """Counter calibration: a plain device-to-device copy of 256 MiB, three
     times, whose hardware byte counters (FETCH_SIZE, WRITE_SIZE) are compared
@@ -799,6 +1154,12 @@ def main():
         sys.exit(2)
     if args.workload == "copy":
         return run_copy(args)
+    if args.workload == "dense50":
+        return run_dense50(args)
+    if args.workload == "long":
+        return run_long(args)
+    if args.workload == "sweep":
+        return run_sweep(args)
     if args.workload == "sparse":
         return run_sparse(args)
     if args.workload == "forms":

@@ -37,8 +37,13 @@ DIMS = [(92, 64, 60, 37), (272, 256, 240, 320)]
 def test_forward_matches_oracle(n_in, n_h, n_out, n):
     """The network is a BF16 network: every product takes bfloat16 operands
     with float32 sums.  The oracle evaluates that definition (rounded
-    operands, exact sums) from the same inputs: within 1e-4 normwise; the
-    plain FP64 network is within 2e-2."""
+    operands, exact sums) from the same inputs: within 5e-4 normwise; the
+    plain FP64 network is within 2e-2.  The bar: a hidden value lies within
+    float32-summation distance (about 2^-24 sqrt(K) relative, K the inner
+    length) of a bfloat16 rounding boundary with probability about
+    2^-16 sqrt(K), and then rounds to the neighbouring bfloat16 value (2^-8
+    relative) on one side only; over a layer that is 2^-8 sqrt(2^-16 sqrt(K))
+    normwise, 6e-5 at K = 272, and two hidden layers feed the output."""
     import torch
     from oracle.precision import round_bf16
     from oracle.warmstart import mlp_forward
@@ -49,7 +54,7 @@ def test_forward_matches_oracle(n_in, n_h, n_out, n):
     Yb, _ = mlp_forward(params, X, n_out, rnd=round_bf16)
     Yr, _ = mlp_forward(params, X, n_out)
     # compare the learned part (the residual is exact)
-    assert rel(Y - X[:, :n_out], Yb - X[:, :n_out]) <= 1e-4
+    assert rel(Y - X[:, :n_out], Yb - X[:, :n_out]) <= 5e-4
     assert rel(Y - X[:, :n_out], Yr - X[:, :n_out]) <= 2e-2
     assert np.array_equal(Y.shape, (n, n_out))
     net.close()
