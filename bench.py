@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--form", choices=("bf16x2", "bf16", "f32"), default="bf16x2")
+    ap.add_argument("--als-form", choices=("f64", "bf16x2"), default="f64",
+                    help="arithmetic of the ALS slab contractions (bf16x2: two-term "
+                         "bfloat16 operands, float32 sums; needs a narrow --form)")
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--batch", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -623,7 +626,7 @@ def run_dense(args):
     tinit = torch.from_numpy(init).to(dev)
     eng = oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, torch.from_numpy(U).to(dev),
                    torch.from_numpy(V).to(dev), x_dtype="f32", compress_dtype=args.form,
-                   flags=oc.OCTEN_FLAG_TIMING)
+                   als_dtype=args.als_form, flags=oc.OCTEN_FLAG_TIMING)
     A = torch.empty((c.I, c.R), dtype=torch.float64, device=dev)
     B = torch.empty((c.J, c.R), dtype=torch.float64, device=dev)
     C = torch.empty((K, c.R), dtype=torch.float64, device=dev)
@@ -658,7 +661,8 @@ def run_dense(args):
         fits_or, t_or = oracle_gate(X, c, c.t0, t, ngate, U, V, Ws, init, args.iters)
         d = [abs(a - b) for a, b in zip(fits_gpu, fits_or)]
         gate = {"stream": f"{c.t0} initial slices then {ngate} batches of {t} (K = {k0})",
-                "form": args.form, "fit_gpu": [round(x, 6) for x in fits_gpu],
+                "form": args.form, "als_form": args.als_form,
+                "fit_gpu": [round(x, 6) for x in fits_gpu],
                 "fit_oracle": [round(x, 6) for x in fits_or],
                 "max_abs_dfit": max(d), "bar": 1e-3, "pass": bool(max(d) <= 1e-3),
                 "oracle_update_s": t_or}
@@ -760,10 +764,12 @@ def run_dense(args):
         "data": "synthetic (seeded on-device generator; rank-10 U[0,1] CP model + N(0, 0.01^2))",
         "config": {"workload": f"dense1000_f32: I=J=1000, R=10, {c.t0} initial slices then "
                                f"batches of {t}; P=12, Q=60, S=3; {args.iters} ALS sweeps; "
-                               f"{args.form} compression, f64 solves; timed batches continue the "
-                               f"stream after its ten gate batches",
+                               f"{args.form} compression, {args.als_form} ALS contractions, f64 "
+                               f"solves; timed batches continue the stream after its ten gate "
+                               f"batches",
                    "I": c.I, "J": c.J, "R": c.R, "P": c.P, "Q": c.Q, "S": c.S, "batch": t,
-                   "initial_slices": c.t0, "als_iters": args.iters, "compress_dtype": args.form},
+                   "initial_slices": c.t0, "als_iters": args.iters, "compress_dtype": args.form,
+                   "als_dtype": args.als_form},
         "fit_gate": gate,
         "fit_oracle": gate["fit_oracle"][-1] if gate else None,
         "abs_dfit": gate["max_abs_dfit"] if gate else None,

@@ -139,9 +139,17 @@ typedef struct {
                               BF16X2 needs U and V on the bfloat16 grid
                               (OCTEN_ERR_ARG otherwise); any other value
                               gives OCTEN_ERR_UNSUPPORTED                     */
-  int32_t als_dtype;       /* MTTKRP arithmetic: OCTEN_F64 (anything else gives
-                              OCTEN_ERR_UNSUPPORTED); R x R solves and
-                              recovery are always F64                         */
+  int32_t als_dtype;       /* arithmetic of the two slab contractions of the
+                              replica ALS (Sec. 4.1; Y x3 C and the mode-3
+                              MTTKRP): OCTEN_F64, or OCTEN_BF16X2 = both
+                              operands as two-term bfloat16 expansions,
+                              products hi*hi + lo*hi + hi*lo, float32 sums
+                              (needs a narrow compress_dtype, so the
+                              summaries are float32, and the cooperative ALS:
+                              not with OCTEN_FLAG_ALS_ONE_WG or
+                              OCTEN_FLAG_REFERENCE_PATH);
+                              anything else gives OCTEN_ERR_UNSUPPORTED.
+                              R x R solves and recovery are always F64        */
   int64_t I;               /* mode-1 size I (problem statement, Sec. 3)        */
   int64_t J;               /* mode-2 size J                                    */
   uint64_t flags;          /* OCTEN_FLAG_*                                     */
@@ -358,6 +366,10 @@ typedef struct {
   const float* slice_scale; /* NULL or [t] f32 powers of two                    */
 } octen_batch_desc;
 
+/* handles: n distinct handles (1 <= n <= 4096) on one stream.  A handle
+ * with als_dtype OCTEN_BF16X2 needs its cooperative ALS after the join (a
+ * step whose capture falls back to the branch ALS fails with
+ * OCTEN_ERR_UNSUPPORTED for it). */
 octen_status octen_group_create(const octen_t* handles, int32_t n, octen_group_t* out);
 /* init_mode: OCTEN_INIT_PREV or OCTEN_INIT_LEARNED (every handle then needs
  * a network, octen_warmstart_set).  replayed_host: NULL or 1 when the

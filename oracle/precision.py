@@ -32,7 +32,7 @@ import math
 
 import numpy as np
 
-from .octen_oracle import compress_dense, replica_cols
+from .octen_oracle import compress_dense, gram_hadamard, replica_cols, replica_fit, solve_normal
 
 U_BF16 = 2.0 ** -8    # unit roundoff of bfloat16 (8 significant bits)
 U_F32 = 2.0 ** -24    # unit roundoff of float32 (24 significant bits)
@@ -116,3 +116,105 @@ def error_bound(form, X, U, V, W, P, Q, S, lam=8.0):
         eM = np.einsum("ia,kib->kab", Ua, eT + g2 * Tc)        # (t, Q, Q)
         out[p] = np.tensordot(eM, Wa, axes=([0], [0])) + U_F32 * np.abs(Z[p]) * 1.0001
     return out
+
+
+# ---------------------------------------------------------------------------
+# Two-term bfloat16 form of the replica ALS contractions (Sec. 4.1, the
+# per-replica CP-ALS; the MTTKRP of Sec. 2's unfolded model)
+# ---------------------------------------------------------------------------
+
+def two_term_product(X, B):
+    """X (n x k) times B (k x m) with both operands taken as two-term
+    bfloat16 expansions of their float32 values, x = hi + lo, and each scalar
+    product as hi_x hi_b + lo_x hi_b + hi_x lo_b (the lo_x lo_b term dropped).
+    Every such product of bfloat16 values is exact; the sums here are FP64."""
+    xh, xl = split_bf16(np.asarray(X, np.float32))
+    bh, bl = split_bf16(np.asarray(B, np.float32))
+    return xh @ bh + xl @ bh + xh @ bl
+
+
+def _two_term_abs(X, B):
+    """Sums of the absolute values of the terms two_term_product adds."""
+    xh, xl = split_bf16(np.asarray(X, np.float32))
+    bh, bl = split_bf16(np.asarray(B, np.float32))
+    return np.abs(xh) @ np.abs(bh) + np.abs(xl) @ np.abs(bh) + np.abs(xh) @ np.abs(bl)
+
+
+def als_two_term_bound(tr, Q, lam=8.0):
+    """Normwise relative bound on how far one sweep of the two-term ALS run
+    with float32 sums may lie from cp_als_two_term (exact sums), from the
+    trace of that sweep.  T sums 3 Q terms and M3 3 Q^2 terms in float32
+    (Higham-Mary constant gamma); to first order, a solve F = M G^-1 turns
+    relative errors dM, dG into kappa(G) (dM + dG), the column normalisation
+    at most doubles it, a Gram matrix carries twice its factor's error and an
+    MTTKRP the sum of its operands' errors:
+      dA = 2 k1 eT,  dB = 2 k2 (eT + 3 dA),  dC = 2 k3 (e3 + 3 dA + 3 dB).
+    Returns max(dA, dB, dC)."""
+    eT = gamma(3 * Q, lam, U_F32) * np.linalg.norm(tr["T_abs"]) / np.linalg.norm(tr["T"])
+    e3 = gamma(3 * Q * Q, lam, U_F32) * np.linalg.norm(tr["M3_abs"]) / np.linalg.norm(tr["M3"])
+    k1, k2, k3 = (np.linalg.cond(G) for G in tr["G"])
+    dA = 2 * k1 * eT
+    dB = 2 * k2 * (eT + 3 * dA)
+    dC = 2 * k3 * (e3 + 3 * dA + 3 * dB)
+    return max(dA, dB, dC)
+
+
+def cp_als_two_term(Y, init, iters, tol=0.0, trace=None):
+    """Replica CP-ALS (Gauss-Seidel over modes 1, 2, 3, columns normalised
+    after every mode, lambda from the last mode; the plain oracle's cp_als)
+    in which the two contractions with the slab are taken in the two-term
+    form:
+      T(a, b, r) = sum_c Y(a, b, c) C(c, r)          (serves modes 1 and 2,
+                                                       C being fixed for both)
+      M1(a, r) = sum_b T(a, b, r) B(b, r),  M2(b, r) = sum_a T(a, b, r) A(a, r)
+      W(ab, r) = float32(A(a, r) B(b, r)),  M3(c, r) = sum_ab Y(a, b, c) W(ab, r)
+    with T and M3 by two_term_product; everything else (M1, M2, the Grams, the
+    R x R solves, the norms) in FP64.  Y is the float32 replica summary
+    (Q, Q, Q).  Returns (F, lam, sweeps, fallback flag) like cp_als.
+
+    trace: None or a list that receives, per sweep, a dict with the three
+    normal matrices ("G": [G1, G2, G3]) and, for T and M3, the value and the
+    sum of the absolute values of its terms ("T", "T_abs", "M3", "M3_abs"),
+    for error bounds."""
+    Y = np.asarray(Y, np.float32)
+    Q = Y.shape[0]
+    Yab = Y.reshape(Q * Q, Q)                 # row a Q + b, column c
+    F = [np.array(f, dtype=np.float64) for f in init]
+    R = F[0].shape[1]
+    lam = np.ones(R)
+    done, fit_old, flag = 0, None, False
+    Yd = Y.astype(np.float64)
+
+    Gs = []
+
+    def update(n, M):
+        nonlocal lam, flag
+        G = gram_hadamard(F, n)
+        Gs.append(G)
+        Fn, fb = solve_normal(M, G)
+        flag |= fb
+        nrm = np.linalg.norm(Fn, axis=0)
+        nrm = np.where(nrm > 0, nrm, 1.0)
+        F[n] = Fn / nrm
+        lam = nrm
+
+    for _ in range(iters):
+        Gs.clear()
+        Cf = F[2]
+        T = two_term_product(Yab, Cf).reshape(Q, Q, R)
+        update(0, np.einsum("abr,br->ar", T, F[1]))
+        update(1, np.einsum("abr,ar->br", T, F[0]))
+        W = (F[0][:, None, :] * F[1][None, :, :]).astype(np.float32).reshape(Q * Q, R)
+        M3 = two_term_product(Yab.T, W)
+        update(2, M3)
+        done += 1
+        if trace is not None:
+            trace.append({"G": list(Gs), "T": T.reshape(Q * Q, R),
+                          "T_abs": _two_term_abs(Yab, Cf), "M3": M3,
+                          "M3_abs": _two_term_abs(Yab.T, W)})
+        if tol > 0:
+            fit = replica_fit(Yd, F, lam, M3)
+            if fit_old is not None and abs(fit - fit_old) < tol:
+                break
+            fit_old = fit
+    return F, lam, done, flag

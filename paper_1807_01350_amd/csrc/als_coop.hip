@@ -18,8 +18,10 @@
 //
 // The R x R normal matrices are inverted by one wavefront (Gauss-Jordan on
 // the identity-padded SPD matrix, one column per lane, pivot columns read
-// with lane reads), while the other wavefronts run the slab contractions on
-// v_mfma_f64_16x16x4.
+// with lane reads) while the others work: in mode 1 beside the slab
+// contraction T on v_mfma_f64_16x16x4 (run by the six wavefronts that do not
+// share its SIMD: FP64 MFMA there slows the inverse's FP64 arithmetic down),
+// in modes 2 and 3 beside the sums of the slab partials.
 //
 // Workgroups of a replica synchronise through a monotonically increasing
 // counter (relaxed bump and polling); every wait is bounded and raises an
@@ -37,6 +39,8 @@
 namespace octen {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4a __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8a __attribute__((ext_vector_type(8)));
 
 namespace {
 
@@ -63,6 +67,27 @@ struct CoopArgs {
 // B[l/16][l%16]; element i of lane l holds D[l/16 + 4 i][l%16].
 __device__ __forceinline__ f64x4 mfma64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Two-term bfloat16 form of the contractions (SPLIT kernels).  An operand
+// value v (float) is the pair hi = bf16(v), lo = bf16(v - hi); a product of
+// two operands is taken as hi*hi + lo*hi + hi*lo (the lo*lo term, of relative
+// size 2^-16, is dropped), every product exact in float32 and summed into
+// float32 accumulators.  D(16 x 16) += A(16 x 32) B(32 x 16) on
+// v_mfma_f32_16x16x32_bf16: lane l supplies A[l%16][8 (l/16) + j] and
+// B[8 (l/16) + j][l%16], j = 0..7; element i of lane l holds D[4 (l/16) + i][l%16].
+__device__ __forceinline__ void split8(const float (&v)[8], bf16x8a& hi, bf16x8a& lo) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    hi[j] = (__bf16)v[j];
+    lo[j] = (__bf16)(v[j] - (float)hi[j]);
+  }
+}
+__device__ __forceinline__ f32x4a mma3(bf16x8a ah, bf16x8a al, bf16x8a bh, bf16x8a bl, f32x4a c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+  return c;
 }
 
 // Index of the accelerator complex die (XCD) the calling wavefront runs on.
@@ -128,6 +153,18 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// 1 / p for p > 0 (normal): the hardware reciprocal estimate refined by two
+// Newton steps r <- r + r (1 - p r), each of which squares the relative
+// error, to within a few units in the last place (not the correctly rounded
+// quotient an IEEE division sequence gives, and about a third of its
+// latency).
+__device__ __forceinline__ double recip(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  r = fma(r, fma(-p, r, 1.0), r);
+  r = fma(r, fma(-p, r, 1.0), r);
+  return r;
+}
+
 // Inverse of the SPD matrix G (R x R, LDS) by Gauss-Jordan elimination
 // without pivoting, run by one wavefront on [G | I] stored by columns: lane
 // c keeps column c in registers.  G is padded to RMAX x RMAX with the
@@ -164,7 +201,7 @@ __device__ __forceinline__ void spd_inverse_wave(const double* G, double* Ginv, 
     double piv = col[j];
     badl |= !(piv > 0.0);
     piv = piv > 0.0 ? piv : 1e-300;
-    const double rj = a[j] * (1.0 / piv);
+    const double rj = a[j] * recip(piv);
 #pragma unroll
     for (int i = 0; i < RMAX; ++i)
       if (i != j) a[i] = fma(-col[i], rj, a[i]);
@@ -176,6 +213,19 @@ __device__ __forceinline__ void spd_inverse_wave(const double* G, double* Ginv, 
       if (i < R) Ginv[i * R + (lane - RMAX)] = a[i];
   }
   if (lane == 0 && badl) *bad = 1;
+}
+
+// The inverse as called by the ALS kernel: inline for small ranks; for
+// RMAX >= 10 out of line, so that the registers of its straight-line code
+// do not add to those of the kernel's MFMA phases (it would spill there).
+template <int RMAX>
+__device__ __noinline__ void spd_inverse_call(const double* G, double* Ginv, int R, int* bad) {
+  spd_inverse_wave<RMAX>(G, Ginv, R, bad);
+}
+template <int RMAX>
+__device__ __forceinline__ void spd_inverse(const double* G, double* Ginv, int R, int* bad) {
+  if constexpr (RMAX >= 10) spd_inverse_call<RMAX>(G, Ginv, R, bad);
+  else spd_inverse_wave<RMAX>(G, Ginv, R, bad);
 }
 
 // Quotient of e by a fixed divisor d through a 64-bit product with
@@ -315,8 +365,12 @@ __device__ __forceinline__ double sum_slots(const double* base, int64_t stride, 
 // GX: the slab is read from the summary in global memory on every use (it
 // stays in L2: the replicas of one XCD total a few MB) instead of being held
 // in LDS; for replicas whose slab does not fit next to the factor state.
-template <typename T, int RMAX, bool GX>
+// SPLIT (float summaries only): the two contractions T and M3 take their
+// operands in the two-term bfloat16 form above; the factor C and the rows W
+// are kept in that form in LDS as B-operand fragments (Cb, Wb).
+template <typename T, int RMAX, bool GX, bool SPLIT>
 __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
+  static_assert(!SPLIT || sizeof(T) == 4, "the two-term form takes float summaries");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_ok, s_bad, s_stop, s_local;
   __shared__ double s_nx2, s_fit_old;
@@ -357,12 +411,40 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   double* lamv = CtC + RR;                    // [MAXR]
   double* rlam = lamv + MAXR;                 // [MAXR] 1 / lamv
   double* scr = rlam + MAXR;                  // [NT]
+  // SPLIT: B-operand fragments, [r tile][k chunk of 32][hi, lo][lane][8],
+  // 16-byte aligned; those of W take the place of T when they fit there (T
+  // is dead from the end of mode 2 to the next sweep)
+  const int nkc = QPAD / 32, npc = g.npair_pad / 32;
+  const bool walias = SPLIT && R >= 8 * RT;
+  __bf16* Cb = (__bf16*)(SPLIT ? ((uintptr_t)(scr + NT) + 15) & ~(uintptr_t)15
+                               : (uintptr_t)(scr + NT));                      // C: k = c
+  __bf16* Wb = walias ? (__bf16*)Ts : Cb + (SPLIT ? (int64_t)RT * nkc * 2 * 512 : 0);   // W: k = pair
+  unsigned char* after_frag = (unsigned char*)(
+      Cb + (SPLIT ? (int64_t)RT * nkc * 2 * 512 + (walias ? 0 : (int64_t)RT * npc * 2 * 512) : 0));
+  // fragments of C (after every update of C)
+  auto build_cb = [&]() {
+    for (int e = tid; e < RT * nkc * 64; e += NT) {
+      const int ln = e & 63, kc = (e >> 6) % nkc, rt = (e >> 6) / nkc;
+      const int r = rt * 16 + (ln & 15);
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int c = kc * 32 + 8 * (ln >> 4) + j;
+        v[j] = (c < Q && r < R) ? (float)Cf[c * R + r] : 0.f;
+      }
+      bf16x8a hi, lo;
+      split8(v, hi, lo);
+      __bf16* dst = Cb + ((int64_t)(rt * nkc + kc) * 2 * 64 + ln) * 8;
+      *(bf16x8a*)dst = hi;
+      *(bf16x8a*)(dst + 512) = lo;
+    }
+  };
   const T* Xp = (const T*)g.Y + (int64_t)p * Q2 * Q;
   const T* Xs;                                // [na * Q][QP] (LDS: [npair_pad][QP])
   if constexpr (GX) {
     Xs = Xp + (int64_t)a0 * Q2;
   } else {
-    T* xl = (T*)(scr + NT);
+    T* xl = (T*)after_frag;
     const FastDiv fQP(QP);
     for (int e = tid; e < g.npair_pad * QP; e += NT) {
       const int row = fQP.div(e), col = e - row * QP;
@@ -429,6 +511,7 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   }
   if (wave == 0) gram_wave(Bf, Q, R, BtB);
   if (wave == 1) gram_wave(Cf, Q, R, CtC);
+  if constexpr (SPLIT) build_cb();
   __syncthreads();
 
   int done = 0;
@@ -439,22 +522,50 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     if (wave == 0) {
       for (int e = lane; e < RR; e += 64) G[e] = BtB[e] * CtC[e];
       wave_sync();
-      spd_inverse_wave<RMAX>(G, Gi, R, &s_bad);
+      spd_inverse<RMAX>(G, Gi, R, &s_bad);
     }
     {
       // T(pair, r) = sum_c X(pair, c) C(c, r) on MFMA, tiles over pairs x r,
-      // dealt to wavefronts 1..7; when one tile is left over after at least
+      // dealt to the six wavefronts that do not share a SIMD with the
+      // inverting wavefront 0 (wavefront w runs on SIMD w % 4: wavefront 4
+      // stays idle, so the inverse's FP64 arithmetic does not compete with
+      // FP64 MFMA on its SIMD); when one tile is left over after at least
       // two whole rounds, wavefront 0 takes it after the inverse
-      constexpr int NMW = NT / 64 - 1;
+      constexpr int NMW = NT / 64 - 2;
+      const int mw = wave < 4 ? wave - 1 : wave - 2;     // 0..5 for the MFMA wavefronts
       const int ntile = (npair + 15) / 16 * RT;
       const bool w0_tile = ntile % NMW == 1 && ntile > 2 * NMW;
-      const int t_first = wave == 0 ? (w0_tile ? ntile - 1 : ntile) : wave - 1;
+      const int t_first = wave == 0 ? (w0_tile ? ntile - 1 : ntile) : (wave == 4 ? ntile : mw);
       const int t_end = wave == 0 || !w0_tile ? ntile : ntile - 1;
       const int t_step = wave == 0 ? 1 : NMW;
       for (int tt = t_first; tt < t_end; tt += t_step) {
         const int pt = tt / RT, rt = tt % RT;
         const int pr = pt * 16 + lane % 16;
         const int rr = rt * 16 + lane % 16;
+        if constexpr (SPLIT) {
+          f32x4a acc = {0.f, 0.f, 0.f, 0.f};
+          const __bf16* cb = Cb + ((int64_t)rt * nkc * 2 * 64 + lane) * 8;
+          for (int kc = 0; kc < nkc; ++kc) {
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int c = kc * 32 + 8 * (lane >> 4) + j;
+              if constexpr (GX) v[j] = (pr < npair && c < Q) ? (float)Xs[(int64_t)pr * QP + c] : 0.f;
+              else v[j] = (float)Xs[pr * QP + c];
+            }
+            bf16x8a ah, al;
+            split8(v, ah, al);
+            const bf16x8a bh = *(const bf16x8a*)(cb + (int64_t)kc * 2 * 512);
+            const bf16x8a bl = *(const bf16x8a*)(cb + (int64_t)kc * 2 * 512 + 512);
+            acc = mma3(ah, al, bh, bl, acc);
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int row = pt * 16 + 4 * (lane >> 4) + i;
+            if (row < npair && rr < R) Ts[row * R + rr] = (double)acc[i];
+          }
+          continue;
+        }
         f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
         const bool okc = rr < R;
         const double* cr = Cf + (okc ? rr : R - 1);
@@ -617,7 +728,7 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       }
       wave_sync();
       // ---------------------------------------------- mode 2 solve (B)
-      spd_inverse_wave<RMAX>(G, Gi, R, &s_bad);
+      spd_inverse<RMAX>(G, Gi, R, &s_bad);
       // M2 was formed with the unnormalised A: B = (M2 / lambda_A) G2^{-1},
       // so row k of the inverse takes the factor 1 / lambda_A(k)
       wave_sync();
@@ -633,10 +744,30 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     __syncthreads();
     // W(pair, r) = A(a, r) B(b, r) into Ts; B'B
     gram_all(Bf, Q, R, BtB);
-    for (int e = tid; e < npair * R; e += NT) {
-      const int pr = fR.div(e), r = e - pr * R;
-      const int a = fQ.div(pr), b = pr - a * Q;
-      Ts[e] = Al[a * R + r] * Bf[b * R + r];
+    if constexpr (SPLIT) {
+      // W(pair, r) = A(a, r) B(b, r) as B-operand fragments (k = pair)
+      for (int e = tid; e < RT * npc * 64; e += NT) {
+        const int ln = e & 63, pc = (e >> 6) % npc, rt = (e >> 6) / npc;
+        const int r = rt * 16 + (ln & 15);
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int pr = pc * 32 + 8 * (ln >> 4) + j;
+          const int a = fQ.div(pr), b = pr - a * Q;
+          v[j] = (pr < npair && r < R) ? (float)(Al[a * R + r] * Bf[b * R + r]) : 0.f;
+        }
+        bf16x8a hi, lo;
+        split8(v, hi, lo);
+        __bf16* dst = Wb + ((int64_t)(rt * npc + pc) * 2 * 64 + ln) * 8;
+        *(bf16x8a*)dst = hi;
+        *(bf16x8a*)(dst + 512) = lo;
+      }
+    } else {
+      for (int e = tid; e < npair * R; e += NT) {
+        const int pr = fR.div(e), r = e - pr * R;
+        const int a = fQ.div(pr), b = pr - a * Q;
+        Ts[e] = Al[a * R + r] * Bf[b * R + r];
+      }
     }
     __syncthreads();
     // ------------------------------------------------ mode 3 partial
@@ -647,26 +778,59 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       // tiles are fewer than half the MFMA wavefronts, the pair range is cut
       // in two and the second halves are added through LDS (fixed order)
       const int ctiles = (Q + 15) / 16, ntl = ctiles * RT;
-      constexpr int NMW = NT / 64 - 1;
+      // all eight wavefronts: the mode-3 inverse waits until after the
+      // reduction below, where it overlaps the sum of the partials
+      constexpr int NMW = NT / 64;
       const int ksp = 2 * ntl <= NMW ? 2 : 1;
       // pair range: padded to a multiple of 32 in LDS (zero rows), halves
       // cut at a multiple of 32; from global memory, the exact range
-      const int npp = GX ? npair : ((npair + 31) / 32) * 32;
-      const int kh = ksp == 1 ? npp : (GX ? ((npair + 15) / 16) * 8 : ((npp / 32 + 1) / 2) * 32);
+      const int npp = (GX && !SPLIT) ? npair : ((npair + 31) / 32) * 32;
+      const int kh = ksp == 1 ? npp
+                              : ((GX && !SPLIT) ? ((npair + 15) / 16) * 8 : ((npp / 32 + 1) / 2) * 32);
       f64x4 keep = {0.0, 0.0, 0.0, 0.0};
       int keep_tile = -1;
-      if (wave == 0) {
-        // G3 = A'A o B'B by wavefront 0 (both complete at the barrier above)
-        for (int e = lane; e < RR; e += 64) G[e] = AtA[e] * BtB[e];
-        wave_sync();
-        spd_inverse_wave<RMAX>(G, Gi, R, &s_bad);
-      } else {
-        for (int item = wave - 1; item < ntl * ksp; item += NMW) {
+      {
+        for (int item = wave; item < ntl * ksp; item += NMW) {
           const int tt = item % ntl, part = item / ntl;
           const int kb = part * kh, ke = kb + kh < npp ? kb + kh : npp;
           const int ct = tt / RT, rt = tt % RT;
           const int c = ct * 16 + lane % 16;
           const int rr = rt * 16 + lane % 16;
+          if constexpr (SPLIT) {
+            // M3(c, r) = sum over pairs of X(pair, c) W(pair, r): A = X^T
+            f32x4a acc = {0.f, 0.f, 0.f, 0.f};
+            const __bf16* wb = Wb + ((int64_t)rt * npc * 2 * 64 + lane) * 8;
+            for (int k0 = kb; k0 < ke; k0 += 32) {
+              float v[8];
+#pragma unroll
+              for (int j = 0; j < 8; ++j) {
+                const int pr = k0 + 8 * (lane >> 4) + j;
+                if constexpr (GX) v[j] = (pr < npair && c < Q) ? (float)Xs[(int64_t)pr * QP + c] : 0.f;
+                else v[j] = (float)Xs[pr * QP + c];
+              }
+              bf16x8a ah, al;
+              split8(v, ah, al);
+              const int pc = k0 >> 5;
+              const bf16x8a bh = *(const bf16x8a*)(wb + (int64_t)pc * 2 * 512);
+              const bf16x8a bl = *(const bf16x8a*)(wb + (int64_t)pc * 2 * 512 + 512);
+              acc = mma3(ah, al, bh, bl, acc);
+            }
+            f64x4 accd;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) accd[i] = (double)acc[i];
+            if (ksp == 2 && part == 0) {
+              keep = accd;
+              keep_tile = tt;
+              continue;
+            }
+            double* o = ksp == 2 ? Ml : dst;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int row = ct * 16 + 4 * (lane >> 4) + i;
+              if (row < Q && rr < R) o[row * R + rr] = accd[i];
+            }
+            continue;
+          }
           f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
           const bool okr = rr < R;
           const double* wc = Ts + (okr ? rr : R - 1);
@@ -746,7 +910,7 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
           const int rr = rt * 16 + lane % 16;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int row = ct * 16 + lane / 16 + 4 * i;
+            const int row = ct * 16 + (SPLIT ? 4 * (lane / 16) + i : lane / 16 + 4 * i);
             if (row < Q && rr < R) dst[row * R + rr] = keep[i] + Ml[row * R + rr];
           }
         }
@@ -754,7 +918,15 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       if (NW > 1) {
         alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok, local);
         if (!alive) break;
-        for (int e = tid; e < QR; e += NT) Mf[e] = sum_slots(slot(set2, 0) + e, slot_len, NW);
+        if (wave != 0)
+          for (int e = tid - 64; e < QR; e += NT - 64) Mf[e] = sum_slots(slot(set2, 0) + e, slot_len, NW);
+      }
+      if (wave == 0) {
+        // G3 = A'A o B'B (both complete) by wavefront 0 while the others
+        // sum the partials of M3
+        for (int e = lane; e < RR; e += 64) G[e] = AtA[e] * BtB[e];
+        wave_sync();
+        spd_inverse<RMAX>(G, Gi, R, &s_bad);
       }
     }
     __syncthreads();
@@ -766,6 +938,7 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     for (int e = tid; e < QR; e += NT) Cf[e] *= rlam[fR.mod(e)];
     __syncthreads();
     gram_all(Cf, Q, R, CtC);
+    if constexpr (SPLIT) build_cb();
     __syncthreads();
     ++done;
     if (g.tol > 0.0) {
@@ -816,20 +989,28 @@ static int pad_pairs(int Q, int NW) {
   return ((na_max * Q + 31) / 32) * 32;
 }
 
-size_t als_coop_lds_bytes(int Q, int R, int NW, bool x_f64, bool slab_global) {
+size_t als_coop_lds_bytes(int Q, int R, int NW, bool x_f64, bool slab_global, bool split) {
   const int na_max = (Q + NW - 1) / NW;
   const size_t QR = (size_t)Q * R;
   const size_t QPAD = (size_t)((Q + 31) / 32) * 32;
   const size_t dbl = (size_t)pad_pairs(Q, NW) * R + 3 * QR + QPAD * R + (size_t)na_max * R +
                      5 * (size_t)R * R + 2 * MAXR + NT;
-  return dbl * 8 + (slab_global ? 0 : (size_t)pad_pairs(Q, NW) * (QPAD + 1) * (x_f64 ? 8 : 4));
+  // split: 16-byte alignment slack, then the fragments of C and (unless
+  // they take T's place) W, in bf16
+  const size_t RT = (size_t)(R + 15) / 16;
+  const bool walias = (size_t)R >= 8 * RT;
+  const size_t frag =
+      split ? 16 + RT * (QPAD / 32 + (walias ? 0 : (size_t)pad_pairs(Q, NW) / 32)) * 2 * 512 * 2 : 0;
+  return dbl * 8 + frag +
+         (slab_global ? 0 : (size_t)pad_pairs(Q, NW) * (QPAD + 1) * (x_f64 ? 8 : 4));
 }
 
 hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int R, int NW,
                     bool slab_global, const double* init, double* F, double* lam, int* iters,
                     int* flags, double* slots, unsigned* counters, int* err, int max_iters,
-                    double tol, bool allow_local) {
+                    double tol, bool allow_local, bool split) {
   if (R > MAXR || Q > 128 || NW < 1 || NW > Q || NW > 32) return hipErrorInvalidValue;
+  if (split && y_f64) return hipErrorInvalidValue;
   CoopArgs a;
   a.Y = Y; a.init = init; a.F = F; a.lam = lam; a.iters = iters; a.flags = flags;
   a.slots = slots; a.counters = counters; a.err = err;
@@ -839,7 +1020,7 @@ hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int 
   a.per_xcd = (P + 7) / 8;
   a.slot_len = als_coop_slot_len(Q, R);
   a.max_iters = max_iters; a.tol = tol; a.allow_local = allow_local ? 1 : 0;
-  const size_t lds = als_coop_lds_bytes(Q, R, NW, y_f64, slab_global);
+  const size_t lds = als_coop_lds_bytes(Q, R, NW, y_f64, slab_global, split);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   hipError_t e = fill_i32(s, (int*)counters, 2 * P, 0);
   if (e != hipSuccess) return e;
@@ -848,18 +1029,27 @@ hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int 
   const int grid = 8 * a.per_xcd * NW;
   void* args[] = {&a};
   const void* fn;
-#define OCTEN_ALS_PICK(RM)                                                          \
-  fn = slab_global                                                                  \
-           ? (y_f64 ? (const void*)als_coop_kernel<double, RM, true>                \
-                    : (const void*)als_coop_kernel<float, RM, true>)                \
-           : (y_f64 ? (const void*)als_coop_kernel<double, RM, false>               \
-                    : (const void*)als_coop_kernel<float, RM, false>)
-  if (R <= 8)
+#define OCTEN_ALS_PICK(RM)                                                             \
+  fn = split ? (slab_global ? (const void*)als_coop_kernel<float, RM, true, true>      \
+                            : (const void*)als_coop_kernel<float, RM, false, true>)    \
+       : slab_global                                                                   \
+           ? (y_f64 ? (const void*)als_coop_kernel<double, RM, true, false>            \
+                    : (const void*)als_coop_kernel<float, RM, true, false>)            \
+           : (y_f64 ? (const void*)als_coop_kernel<double, RM, false, false>           \
+                    : (const void*)als_coop_kernel<float, RM, false, false>)
+  // the inverse runs RMAX straight-line steps: exact fits for the common ranks
+  if (R <= 6)
+    OCTEN_ALS_PICK(6);
+  else if (R <= 8)
     OCTEN_ALS_PICK(8);
+  else if (R <= 10)
+    OCTEN_ALS_PICK(10);
   else if (R <= 12)
     OCTEN_ALS_PICK(12);
   else if (R <= 16)
     OCTEN_ALS_PICK(16);
+  else if (R <= 20)
+    OCTEN_ALS_PICK(20);
   else if (R <= 24)
     OCTEN_ALS_PICK(24);
   else

@@ -60,6 +60,7 @@ struct octen_ctx {
   int* health = nullptr;                   // [1] OCTEN_HEALTH_* bits since the last report
   int als_nw = 0;                          // workgroups per replica (0: reference kernel)
   bool als_gx = false;                     // slab read from global memory, not LDS
+  bool als_split = false;                  // contractions on two-term bfloat16 operands
   double* als_slots = nullptr;
   unsigned* als_ctr = nullptr;
   int* als_err = nullptr;
@@ -231,8 +232,15 @@ octen_status validate(const octen_config* c, std::string* msg) {
     *msg = "narrow compression needs f32 slices";
     return OCTEN_ERR_UNSUPPORTED;
   }
-  if (c->als_dtype != OCTEN_F64) {
-    *msg = "als_dtype must be F64";
+  if (c->als_dtype != OCTEN_F64 && c->als_dtype != OCTEN_BF16X2) {
+    *msg = "als_dtype must be F64 or BF16X2";
+    return OCTEN_ERR_UNSUPPORTED;
+  }
+  if (c->als_dtype == OCTEN_BF16X2 &&
+      (c->compress_dtype == OCTEN_F64 || (c->flags & (OCTEN_FLAG_ALS_ONE_WG | OCTEN_FLAG_REFERENCE_PATH)))) {
+    // the two-term contractions exist in the cooperative ALS on float summaries only
+    *msg = "als_dtype BF16X2 needs float summaries (compress_dtype F32, BF16 or BF16X2) and the "
+           "cooperative ALS";
     return OCTEN_ERR_UNSUPPORTED;
   }
   int64_t M1 = (int64_t)c->S + (int64_t)c->P * (c->Q - c->S);
@@ -462,6 +470,7 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
     // and few enough that the slab fits in LDS; if no count lets it fit, the
     // slab stays in global memory and the most workgroups are used
     const int per_xcd = (int)((P + 7) / 8);
+    const bool split = cfg->als_dtype == OCTEN_BF16X2;
     int max_nw = per_xcd > 0 ? 32 / per_xcd : 0;
     if (max_nw > Q) max_nw = (int)Q;
     if (max_nw >= 1) {
@@ -471,20 +480,25 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
       if (nw < 1) nw = 1;
       if (nw > max_nw) nw = max_nw;
       bool gx = false;
-      while (nw < max_nw && als_coop_lds_bytes((int)Q, (int)R, nw, h->acc_f64, false) > lds_cap) ++nw;
-      if (als_coop_lds_bytes((int)Q, (int)R, nw, h->acc_f64, false) > lds_cap) {
+      while (nw < max_nw && als_coop_lds_bytes((int)Q, (int)R, nw, h->acc_f64, false, split) > lds_cap) ++nw;
+      if (als_coop_lds_bytes((int)Q, (int)R, nw, h->acc_f64, false, split) > lds_cap) {
         nw = max_nw;
         gx = true;
       }
       nw = balanced_nw((int)Q, nw);   // same slab height, so the same LDS size
-      if (als_coop_lds_bytes((int)Q, (int)R, nw, h->acc_f64, gx) <= lds_cap) {
+      if (als_coop_lds_bytes((int)Q, (int)R, nw, h->acc_f64, gx, split) <= lds_cap) {
         h->als_nw = nw;
         h->als_gx = gx;
+        h->als_split = split;
         IOK(dalloc(h, &h->als_slots, (size_t)2 * P * nw * als_coop_slot_len((int)Q, (int)R)));
         IOK(dalloc(h, &h->als_ctr, 2 * (size_t)P));
         IOK(dalloc(h, &h->als_err, 1));
       }
     }
+  }
+  if (cfg->als_dtype == OCTEN_BF16X2 && !h->als_split) {
+    octen_destroy(h);
+    return OCTEN_ERR_UNSUPPORTED;   // no cooperative ALS configuration fits
   }
   if (cfg->flags & OCTEN_FLAG_TIMING) {
     for (int st2 = 0; st2 < OCTEN_NUM_STAGES; ++st2) {
@@ -778,13 +792,19 @@ octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int
     hipError_t e = hipErrorNotSupported;
     // group branches run concurrently: no cooperative grid there
     const bool in_branch = h->group_mode;
+    if (h->cfg.als_dtype == OCTEN_BF16X2 && (in_branch || h->als_nw <= 0))
+      return fail(h, OCTEN_ERR_UNSUPPORTED,
+                  "the two-term contractions run in the cooperative ALS only");
     if (h->als_nw > 0 && !in_branch && !(h->cfg.flags & OCTEN_FLAG_ALS_ONE_WG)) {
       e = als_coop(s, h->Y, h->acc_f64, h->P, h->Q, h->R, h->als_nw, h->als_gx, src, h->F,
                    h->lam, h->iters, h->flags, h->als_slots, h->als_ctr, h->als_err, max_iters,
-                   tol, !(h->cfg.flags & OCTEN_FLAG_ALS_DEVICE_SYNC));
+                   tol, !(h->cfg.flags & OCTEN_FLAG_ALS_DEVICE_SYNC), h->als_split);
       if (e != hipSuccess) {
         (void)hipGetLastError();
         h->als_nw = 0;   // cooperative launch not possible here: use the reference kernel
+        if (h->als_split)
+          return fail(h, OCTEN_ERR_UNSUPPORTED,
+                      "cooperative ALS launch failed (the two-term contractions need it)");
       }
     }
     if (e != hipSuccess)
@@ -1152,8 +1172,8 @@ octen_status octen_autotune_als(octen_t h, int32_t sweeps, int32_t* choice_host)
   // every count that is the smallest one for its slab height ceil(Q / nw)
   for (int nw = 2; nw <= max_nw; ++nw) {
     if (balanced_nw(Q, nw) != nw) continue;
-    if (als_coop_lds_bytes(Q, R, nw, h->acc_f64, false) <= cap) cand.push_back({nw, false});
-    if (als_coop_lds_bytes(Q, R, nw, h->acc_f64, true) <= cap) cand.push_back({nw, true});
+    if (als_coop_lds_bytes(Q, R, nw, h->acc_f64, false, h->als_split) <= cap) cand.push_back({nw, false});
+    if (als_coop_lds_bytes(Q, R, nw, h->acc_f64, true, h->als_split) <= cap) cand.push_back({nw, true});
   }
   if (cand.empty()) return fail(h, OCTEN_ERR_UNSUPPORTED, "no cooperative configuration fits");
   // slots for the largest candidate; the current factors are kept aside
@@ -1177,12 +1197,12 @@ octen_status octen_autotune_als(octen_t h, int32_t sweeps, int32_t* choice_host)
     for (size_t q = 0; q < cand.size(); ++q) {
       hipError_t e = als_coop(s, h->Y, h->acc_f64, P, Q, R, cand[q].first, cand[q].second, F0,
                               h->F, h->lam, h->iters, h->flags, slots, h->als_ctr, h->als_err, 1,
-                              0.0, !(h->cfg.flags & OCTEN_FLAG_ALS_DEVICE_SYNC));
+                              0.0, !(h->cfg.flags & OCTEN_FLAG_ALS_DEVICE_SYNC), h->als_split);
       if (e == hipSuccess) e = hipEventRecord(e0, s);
       if (e == hipSuccess)
         e = als_coop(s, h->Y, h->acc_f64, P, Q, R, cand[q].first, cand[q].second, F0, h->F,
                      h->lam, h->iters, h->flags, slots, h->als_ctr, h->als_err, sweeps, 0.0,
-                     !(h->cfg.flags & OCTEN_FLAG_ALS_DEVICE_SYNC));
+                     !(h->cfg.flags & OCTEN_FLAG_ALS_DEVICE_SYNC), h->als_split);
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;

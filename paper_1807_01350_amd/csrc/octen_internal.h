@@ -123,11 +123,12 @@ inline int als_coop_slot_len(int Q, int R) { return Q * R + R * R + 8; }
 // slab_global: the slab is read from Y in global memory instead of LDS.
 // allow_local: replicas whose workgroups all run on one XCD synchronise
 // through its L2 without device-wide write-back and invalidation.
-size_t als_coop_lds_bytes(int Q, int R, int NW, bool x_f64, bool slab_global);
+// split (float summaries): the contractions on two-term bfloat16 operands.
+size_t als_coop_lds_bytes(int Q, int R, int NW, bool x_f64, bool slab_global, bool split);
 hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int R, int NW,
                     bool slab_global, const double* init, double* F, double* lam, int* iters,
                     int* flags, double* slots, unsigned* counters, int* err, int max_iters,
-                    double tol, bool allow_local);
+                    double tol, bool allow_local, bool split);
 
 // -------------------------------------------------------------- recovery ---
 // lambda^(1/3), anchor similarity, exclusive greedy matching, scale alignment.

@@ -69,7 +69,7 @@ def run_oracle(c: Case, X, U, V, Ws, init, tol=0.0):
 
 
 def run_gpu(c: Case, X, U, V, Ws, init, compress_dtype="f64", x_dtype="f64", tol=0.0, flags=0,
-            log=None):
+            log=None, als_dtype="f64"):
     import torch
     from paper_1807_01350_amd import octen as oc
     dev = "cuda"
@@ -78,7 +78,7 @@ def run_gpu(c: Case, X, U, V, Ws, init, compress_dtype="f64", x_dtype="f64", tol
     tV = torch.from_numpy(V).to(dev)
     tinit = torch.from_numpy(init).to(dev)
     eng = oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, tU, tV, x_dtype=x_dtype,
-                   compress_dtype=compress_dtype, flags=flags)
+                   compress_dtype=compress_dtype, als_dtype=als_dtype, flags=flags)
     A = torch.empty((c.I, c.R), dtype=torch.float64, device=dev)
     B = torch.empty((c.J, c.R), dtype=torch.float64, device=dev)
     C = torch.empty((c.K, c.R), dtype=torch.float64, device=dev)
