@@ -90,6 +90,13 @@ __device__ __forceinline__ f32x4a mma3(bf16x8a ah, bf16x8a al, bf16x8a bh, bf16x
   return c;
 }
 
+typedef __attribute__((address_space(3))) double lds_f64;
+// An LDS pointer argument as a wave-uniform (scalar) LDS address.
+__device__ __forceinline__ lds_f64* lds_uniform(const double* p) {
+  const unsigned a = __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(const lds_f64*)p);
+  return (lds_f64*)(uintptr_t)a;
+}
+
 // Index of the accelerator complex die (XCD) the calling wavefront runs on.
 __device__ __forceinline__ unsigned xcd_id() {
   unsigned v;
@@ -176,9 +183,13 @@ __device__ __forceinline__ double recip(double p) {
 // them (no LDS traffic, no cross-lane permutes).  Writes Ginv (LDS) and sets
 // *bad when a pivot is not positive.
 template <int RMAX>
-__device__ __forceinline__ void spd_inverse_wave(const double* G, double* Ginv, int R, int* bad) {
+__device__ __forceinline__ void spd_inverse_wave(const double* G_, double* Ginv_, int R_, int* bad) {
   static_assert(2 * RMAX <= 64, "one wavefront holds [G | I]");
   const int lane = threadIdx.x & 63;
+  // LDS operands, uniform rank (scalar branches when called out of line)
+  const lds_f64* G = lds_uniform(G_);
+  lds_f64* Ginv = lds_uniform(Ginv_);
+  const int R = __builtin_amdgcn_readfirstlane(R_);
   double a[RMAX];
 #pragma unroll
   for (int i = 0; i < RMAX; ++i) {
@@ -215,8 +226,8 @@ __device__ __forceinline__ void spd_inverse_wave(const double* G, double* Ginv, 
   if (lane == 0 && badl) *bad = 1;
 }
 
-// The inverse as called by the ALS kernel: inline for small ranks; for
-// RMAX >= 10 out of line, so that the registers of its straight-line code
+// The inverse as called by the ALS kernel: inline for the smallest ranks; for
+// RMAX >= 8 out of line, so that the registers of its straight-line code
 // do not add to those of the kernel's MFMA phases (it would spill there).
 template <int RMAX>
 __device__ __noinline__ void spd_inverse_call(const double* G, double* Ginv, int R, int* bad) {
@@ -224,7 +235,7 @@ __device__ __noinline__ void spd_inverse_call(const double* G, double* Ginv, int
 }
 template <int RMAX>
 __device__ __forceinline__ void spd_inverse(const double* G, double* Ginv, int R, int* bad) {
-  if constexpr (RMAX >= 10) spd_inverse_call<RMAX>(G, Ginv, R, bad);
+  if constexpr (RMAX >= 8) spd_inverse_call<RMAX>(G, Ginv, R, bad);
   else spd_inverse_wave<RMAX>(G, Ginv, R, bad);
 }
 
@@ -295,9 +306,10 @@ __device__ void gram_all(const double* Fm, int n, int R, double* G) {
   }
 }
 
-// out(q, :) = M(q, :) Ginv for q < n (all threads).  The sum over k runs in
-// blocks of 8 whose sixteen loads are issued together (indices clamped, the
-// terms past R skipped); even and odd k go to two accumulators.
+// out(q, :) = M(q, :) Ginv for q < n (all threads; the few rows of a
+// workgroup's slab in mode 1).  The sum over k runs in blocks of 8 whose
+// sixteen loads are issued together (indices clamped, the terms past R
+// skipped); even and odd k go to two accumulators.
 __device__ void apply_inverse(const double* M, const double* Ginv, double* out, int n, int R) {
   const FastDiv fr(R);
   for (int e = threadIdx.x; e < n * R; e += NT) {
@@ -319,6 +331,128 @@ __device__ void apply_inverse(const double* M, const double* Ginv, double* out, 
       }
     }
     out[e] = s0 + s1;
+  }
+}
+
+// F = M Ginv (n x R, all in LDS) on v_mfma_f64_16x16x4f64: wavefront w takes
+// the 16-row tiles w, w + 8, ..., each with every column tile (R <= 32).
+// With part set, the wavefront also forms its rows' share of F^T F straight
+// from the accumulators (element s of a 16 x 16 result fragment is, lane for
+// lane, both operand fragments of k-step s of that tile's F_t^T F_t) and
+// writes it to part[w] (R x R) when it had a tile: part[0 .. min(8, tiles))
+// then sum to F^T F.  Rows past n and columns past R are exact zeros.  Out
+// of line (its registers stay out of the kernel's MFMA phases); the
+// pointers are LDS ones, cast so that the accesses are LDS instructions.
+__device__ __noinline__ void apply_gram(const double* M_, const double* Gi_, double* F_, int n_,
+                                       int R_, double* part_) {
+  // the arguments are the same in every lane: say so, so that the loops
+  // below are scalar branches and not masked ones
+  const lds_f64* M = lds_uniform(M_);
+  const lds_f64* Ginv = lds_uniform(Gi_);
+  lds_f64* F = lds_uniform(F_);
+  const bool with_part = __builtin_amdgcn_readfirstlane(part_ != nullptr ? 1 : 0) != 0;
+  lds_f64* part = with_part ? lds_uniform(part_) : nullptr;
+  const int n = __builtin_amdgcn_readfirstlane(n_), R = __builtin_amdgcn_readfirstlane(R_);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int RT = (R + 15) >> 4, ks = (R + 3) >> 2, ntr = (n + 15) >> 4;
+  f64x4 g00 = {0.0, 0.0, 0.0, 0.0}, g01 = g00, g11 = g00;
+  for (int rt = wave; rt < ntr; rt += NT / 64) {
+    f64x4 d[2];
+    const int row = rt * 16 + (lane & 15);
+    const int rowc = row < n ? row : n - 1;
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+      if (ct < RT) {
+        const int col = ct * 16 + (lane & 15);
+        const int colc = col < R ? col : R - 1;
+        // operands of four k-steps first (indices clamped), then their MFMAs
+        for (int s0 = 0; s0 < ks; s0 += 4) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int k = 4 * (s0 + u) + (lane >> 4);
+            const int kc = k < R ? k : R - 1;
+            av[u] = M[rowc * R + kc];
+            bv[u] = Ginv[kc * R + colc];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int k = 4 * (s0 + u) + (lane >> 4);
+            if (s0 + u < ks)
+              acc = mfma64((row < n && k < R) ? av[u] : 0.0, col < R ? bv[u] : 0.0, acc);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = rt * 16 + (lane >> 4) + 4 * i;
+          if (r < n && col < R) F[r * R + col] = acc[i];
+        }
+      }
+      d[ct] = acc;
+    }
+    if (with_part) {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        g00 = mfma64(d[0][s4], d[0][s4], g00);
+        if (RT > 1) {
+          g01 = mfma64(d[0][s4], d[1][s4], g01);
+          g11 = mfma64(d[1][s4], d[1][s4], g11);
+        }
+      }
+    }
+  }
+  if (with_part && wave < ntr) {
+    lds_f64* pw = part + wave * R * R;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r1 = (lane >> 4) + 4 * i, r2 = lane & 15;
+      if (r1 < R && r2 < R) pw[r1 * R + r2] = g00[i];
+      if (RT > 1) {
+        // the lower-left block is the transpose of the upper-right one
+        if (r1 < R && r2 + 16 < R) {
+          pw[r1 * R + r2 + 16] = g01[i];
+          pw[(r2 + 16) * R + r1] = g01[i];
+        }
+        if (r1 + 16 < R && r2 + 16 < R) pw[(r1 + 16) * R + r2 + 16] = g11[i];
+      }
+    }
+  }
+}
+
+// 1 / sqrt(d) for d > 0 (normal): the hardware estimate refined by two
+// Newton steps r <- r + r (1 - d r^2) / 2, each squaring the relative error.
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double r = __builtin_amdgcn_rsq(d);
+  r = fma(0.5 * r, fma(-d * r, r, 1.0), r);
+  r = fma(0.5 * r, fma(-d * r, r, 1.0), r);
+  return r;
+}
+
+// From the nslot partial Grams of an unnormalised factor F: lam[r] = the
+// 2-norm of column r (0 replaced by 1), rlam[r] = 1 / lam[r], and the Gram
+// of the normalised factor FtF(r1, r2) = (F^T F)(r1, r2) rlam[r1] rlam[r2];
+// the partials are added in slot order; 1 / lam from rsqrt_nr (a few units
+// in the last place).
+__device__ void norm_gram(const double* part, int nslot, int R, double* FtF, double* lam,
+                          double* rlam) {
+  const int RR = R * R;
+  const FastDiv fr(R);
+  for (int e = threadIdx.x; e < RR; e += NT) {
+    const int r1 = fr.div(e), r2 = e - r1 * R;
+    double sv = 0.0, d1 = 0.0, d2 = 0.0;
+    for (int w = 0; w < nslot; ++w) {
+      sv += part[w * RR + e];
+      d1 += part[w * RR + r1 * (R + 1)];
+      d2 += part[w * RR + r2 * (R + 1)];
+    }
+    // a zero column keeps lambda = 1
+    const double q1 = d1 > 0.0 ? rsqrt_nr(d1) : 1.0, q2 = d2 > 0.0 ? rsqrt_nr(d2) : 1.0;
+    FtF[e] = sv * q1 * q2;
+    if (r1 == r2) {
+      lam[r1] = d1 > 0.0 ? d1 * q1 : 1.0;
+      rlam[r1] = q1;
+    }
   }
 }
 
@@ -411,6 +545,10 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   double* lamv = CtC + RR;                    // [MAXR]
   double* rlam = lamv + MAXR;                 // [MAXR] 1 / lamv
   double* scr = rlam + MAXR;                  // [NT]
+  // the partial Grams of the mode solves go where T is (T is dead from the
+  // end of mode 2 to the next sweep) when they fit there
+  const int nslot = min(NT / 64, (Q + 15) / 16);
+  const bool pg = nslot * RR <= g.npair_pad * R;
   // SPLIT: B-operand fragments, [r tile][k chunk of 32][hi, lo][lane][8],
   // 16-byte aligned; those of W take the place of T when they fit there (T
   // is dead from the end of mode 2 to the next sweep)
@@ -421,8 +559,10 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   __bf16* Wb = walias ? (__bf16*)Ts : Cb + (SPLIT ? (int64_t)RT * nkc * 2 * 512 : 0);   // W: k = pair
   unsigned char* after_frag = (unsigned char*)(
       Cb + (SPLIT ? (int64_t)RT * nkc * 2 * 512 + (walias ? 0 : (int64_t)RT * npc * 2 * 512) : 0));
-  // fragments of C (after every update of C)
-  auto build_cb = [&]() {
+  // fragments of C (after every update of C); with scale, C is first
+  // normalised in place (each element of C belongs to exactly one fragment
+  // entry, so the thread that scales it is the one that reads it)
+  auto build_cb = [&](bool scale) {
     for (int e = tid; e < RT * nkc * 64; e += NT) {
       const int ln = e & 63, kc = (e >> 6) % nkc, rt = (e >> 6) / nkc;
       const int r = rt * 16 + (ln & 15);
@@ -430,7 +570,15 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int c = kc * 32 + 8 * (ln >> 4) + j;
-        v[j] = (c < Q && r < R) ? (float)Cf[c * R + r] : 0.f;
+        double x = 0.0;
+        if (c < Q && r < R) {
+          x = Cf[c * R + r];
+          if (scale) {
+            x *= rlam[r];
+            Cf[c * R + r] = x;
+          }
+        }
+        v[j] = (float)x;
       }
       bf16x8a hi, lo;
       split8(v, hi, lo);
@@ -511,8 +659,9 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   }
   if (wave == 0) gram_wave(Bf, Q, R, BtB);
   if (wave == 1) gram_wave(Cf, Q, R, CtC);
-  if constexpr (SPLIT) build_cb();
+  if constexpr (SPLIT) build_cb(false);
   __syncthreads();
+
 
   int done = 0;
   for (int it = 0; it < g.max_iters && alive; ++it) {
@@ -736,14 +885,17 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     }
     __syncthreads();
     for (int e = tid; e < na * R; e += NT) Al[e] *= rlam[fR.mod(e)];
-    apply_inverse(Mf, Gi, Bf, Q, R);
+    apply_gram(Mf, Gi, Bf, Q, R, pg ? Ts : nullptr);
     __syncthreads();
-    col_norms(Bf, Q, R, lamv, rlam);
+    // lambda_B and B'B of the normalised B from the partial Grams
+    if (pg) norm_gram(Ts, nslot, R, BtB, lamv, rlam);
+    else col_norms(Bf, Q, R, lamv, rlam);
     __syncthreads();
     for (int e = tid; e < QR; e += NT) Bf[e] *= rlam[fR.mod(e)];
     __syncthreads();
-    // W(pair, r) = A(a, r) B(b, r) into Ts; B'B
-    gram_all(Bf, Q, R, BtB);
+    // W(pair, r) = A(a, r) B(b, r) into Ts (B'B here when it was not formed
+    // above)
+    if (!pg) gram_all(Bf, Q, R, BtB);
     if constexpr (SPLIT) {
       // W(pair, r) = A(a, r) B(b, r) as B-operand fragments (k = pair)
       for (int e = tid; e < RT * npc * 64; e += NT) {
@@ -931,15 +1083,20 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     }
     __syncthreads();
     // ------------------------------------------------ mode 3 solve (C)
-    apply_inverse(Mf, Gi, Cf, Q, R);
+    apply_gram(Mf, Gi, Cf, Q, R, pg ? Ts : nullptr);
     __syncthreads();
-    col_norms(Cf, Q, R, lamv, rlam);
+    if (pg) norm_gram(Ts, nslot, R, CtC, lamv, rlam);
+    else col_norms(Cf, Q, R, lamv, rlam);
     __syncthreads();
-    for (int e = tid; e < QR; e += NT) Cf[e] *= rlam[fR.mod(e)];
+    // C normalised (and, two-term, its fragments)
+    if constexpr (SPLIT) build_cb(true);
+    else
+      for (int e = tid; e < QR; e += NT) Cf[e] *= rlam[fR.mod(e)];
     __syncthreads();
-    gram_all(Cf, Q, R, CtC);
-    if constexpr (SPLIT) build_cb();
-    __syncthreads();
+    if (!pg) {
+      gram_all(Cf, Q, R, CtC);
+      __syncthreads();
+    }
     ++done;
     if (g.tol > 0.0) {
       // replica fit from the Gram identity, summed by wavefront 0 in a fixed

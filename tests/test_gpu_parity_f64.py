@@ -2,7 +2,8 @@
 C ABI: compression and update (Sec. 4.1, Eq. 1-2), replica ALS (Sec. 4.1),
 matching (Sec. 4.2) and recovery (Sec. 4.3), and the fit (Sec. 5.1).
 
-Bars: FP64 steps within 1e-10 normwise relative; permutations, pairings and
+Bars: FP64 steps within 1e-10 normwise relative; matching margins within
+1e-9 absolute; permutations, pairings and
 iteration counts bit-exact; fit within 1e-10 absolute."""
 import sys
 
@@ -79,8 +80,11 @@ def test_matching_permutation_exact(result):
     for b, (r, g) in enumerate(zip(ref, got)):
         ok = r["margins"] > 1e-6
         assert np.array_equal(g["perm"][ok], r["perm"][ok]), b
+        # a margin is a difference of two products of three |cos| of unit
+        # columns, each product within a few 1e-10 of the oracle's when the
+        # factors are (the FP64 bar): the bar is absolute
         fin = np.isfinite(r["margins"])
-        assert np.allclose(g["margins"][fin], r["margins"][fin], rtol=1e-8, atol=1e-12)
+        assert np.allclose(g["margins"][fin], r["margins"][fin], rtol=1e-8, atol=1e-9)
         assert np.array_equal(g["tperm"], r["tperm"]), b
 
 
