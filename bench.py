@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 
 METRIC = "new slices/sec & compression HBM GB/s (% peak) at fit within 1e-3 of FP64 oracle"
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f64": 78.6}
 
 
 def parse():
@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--form", choices=("bf16x2", "bf16", "f32"), default="bf16x2")
-    ap.add_argument("--als-form", choices=("f64", "bf16x2"), default="f64",
+    ap.add_argument("--als-form", choices=("f64", "bf16x2"), default="bf16x2",
                     help="arithmetic of the ALS slab contractions (bf16x2: two-term "
                          "bfloat16 operands, float32 sums; needs a narrow --form)")
     ap.add_argument("--iters", type=int, default=50)
@@ -85,8 +85,9 @@ def gen_stream(torch, I, J, K, R, sigma, seed, dev):
 
 
 def traffic_from_profile(form, source="compress_mfma.hip", profile=None):
-    """HBM bytes per launch of the compression kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    """HBM bytes per launch of a kernel (by default the compression kernel of
+    the given form) from the committed rocprofv3 counter summary, if it was
+    taken on the current source of that kernel."""
     import hashlib
     src = os.path.join(ROOT, "paper_1807_01350_amd", "csrc", source)
     prof = os.path.join(ROOT, "profiles",
@@ -703,22 +704,53 @@ def run_dense(args):
     gbs = bytes_launch / (kms * 1e-3) / 1e9
     tflops = mfma_flops / (kms * 1e-3) / 1e12
     traffic = traffic_from_profile(args.form)
-    if args.form == "f32":
-        roof = {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_PEAK_TFLOPS["f32"],
-                "unit": "TFLOP/s", "frac": round(tflops / MFMA_PEAK_TFLOPS["f32"], 4),
-                "traffic": traffic}
+    mpk = "bf16" if args.form != "f32" else "f32"
+    # the binding roof of the compression kernel: MFMA when the form's matrix
+    # work at peak takes longer than its bytes at the HBM peak
+    t_mfma = mfma_flops / (MFMA_PEAK_TFLOPS[mpk] * 1e12)
+    t_hbm = bytes_launch / (HBM_PEAK_GBS * 1e9)
+    if t_mfma > t_hbm:
+        croof = {"bound": "mfma", "achieved": round(tflops, 2), "peak": MFMA_PEAK_TFLOPS[mpk],
+                 "unit": "TFLOP/s", "frac": round(tflops / MFMA_PEAK_TFLOPS[mpk], 4),
+                 "traffic": traffic}
     else:
-        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
+        croof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic}
     kname = {0: "compress_pipe", 1: "compress_fused (16-byte loads)", 2: "compress_fused",
              3: "compress_pipe2"}.get(tuned["compress"] % 10, "compress")
     if args.form == "bf16x2":
         kname = "compress_pipe2 two-term"
-    roof["kernel"] = f"{kname} (modes 1 and 2 of the batch compression)"
-    roof["algorithmic_bytes_per_launch"] = bytes_launch
-    roof["algorithmic_flops_per_launch"] = flops_launch
-    roof["mfma_flops_per_launch"] = mfma_flops
-    roof["mfma_frac"] = round(tflops / MFMA_PEAK_TFLOPS["bf16" if args.form != "f32" else "f32"], 4)
+    croof["kernel"] = f"{kname} (modes 1 and 2 of the batch compression)"
+    croof["algorithmic_bytes_per_launch"] = bytes_launch
+    croof["algorithmic_flops_per_launch"] = flops_launch
+    croof["mfma_flops_per_launch"] = mfma_flops
+    croof["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+    croof["mfma_frac"] = round(tflops / MFMA_PEAK_TFLOPS[mpk], 4)
+    croof["time_at_peaks_us"] = {"mfma": round(t_mfma * 1e6, 1), "hbm": round(t_hbm * 1e6, 1)}
+
+    # the dominant kernel of the step: the cooperative replica ALS, one launch
+    # of args.iters sweeps over all replicas; algorithmic flops of the two slab
+    # contractions per sweep and replica 4 Q^3 R (the R x R work is smaller by
+    # a factor Q^2 / R); the two-term form runs three BF16 products per product
+    als_ms = st["als"]
+    als_flops = 4.0 * c.Q ** 3 * c.R * c.P * args.iters
+    als_tf = als_flops / (als_ms * 1e-3) / 1e12
+    if args.als_form == "bf16x2":
+        als_exec, als_pk = 3.0 * als_flops, "bf16"
+    else:
+        als_exec, als_pk = als_flops, "f64"
+    als_xtf = als_exec / (als_ms * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(als_xtf, 3), "peak": MFMA_PEAK_TFLOPS[als_pk],
+            "unit": "TFLOP/s", "frac": round(als_xtf / MFMA_PEAK_TFLOPS[als_pk], 5),
+            "traffic": traffic_from_profile(args.als_form, source="als_coop.hip",
+                                            profile=f"als_coop_{args.als_form}_dense1000_counters.md"),
+            "kernel": f"als_coop_kernel ({args.als_form} slab contractions, FP64 solves; "
+                      f"{args.iters} sweeps of all {c.P} replicas per launch)",
+            "algorithmic_flops_per_launch": als_flops, "mfma_flops_per_launch": als_exec,
+            "algorithmic_tflops": round(als_tf, 3),
+            "frac_of_fp64_mfma_peak": round(als_tf / MFMA_PEAK_TFLOPS["f64"], 4),
+            "note": "latency-bound: a sweep is a chain of small phases, three one-wavefront "
+                    "R x R inverses and two replica barriers"}
 
     overlap = None
     if args.overlap:
@@ -779,6 +811,7 @@ def run_dense(args):
         "autotuned": tuned,
         "fit": fit,
         "roofline": roof,
+        "roofline_compression": croof,
         "cpu_baseline": cpu,
         "overlapped": overlap,
     }
