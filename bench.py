@@ -45,6 +45,10 @@ def parse():
     ap.add_argument("--als-form", choices=("f64", "bf16x2"), default="bf16x2",
                     help="arithmetic of the ALS slab contractions (bf16x2: two-term "
                          "bfloat16 operands, float32 sums; needs a narrow --form)")
+    ap.add_argument("--als-one-wg", action="store_true",
+                    help="batched workload: every stream's ALS as one workgroup per replica "
+                         "inside its graph branch (all streams concurrently) instead of "
+                         "cooperative launches after the join")
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--batch", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -357,7 +361,8 @@ def run_batched(args):
         # N(0,1) compression matrices on the bfloat16 grid (as synth draws them)
         U = torch.randn((I, M1), generator=g, device=dev, dtype=f64).float().bfloat16().double()
         V = torch.randn((J, M1), generator=g, device=dev, dtype=f64).float().bfloat16().double()
-        eng = oc.Octen(I, J, R, P, Q, S, U, V, x_dtype="f32", compress_dtype=args.form)
+        eng = oc.Octen(I, J, R, P, Q, S, U, V, x_dtype="f32", compress_dtype=args.form,
+                       flags=oc.OCTEN_FLAG_ALS_ONE_WG if args.als_one_wg else 0)
         X = torch.empty((t, I, J), dtype=torch.float32, device=dev)
         W = torch.empty((t, M1), dtype=f64, device=dev)
         init = torch.randn((P, 3, Q, R), generator=g, device=dev, dtype=f64)
@@ -420,7 +425,9 @@ def run_batched(args):
                                f"{args.iters} ALS sweeps in one captured graph, then recovery)",
                    "streams": len(streams), "slices_per_round": slices,
                    "x_bytes_per_round": xbytes, "als_iters": args.iters,
-                   "compress_dtype": args.form},
+                   "compress_dtype": args.form,
+                   "als": "one workgroup per replica in each stream's branch" if args.als_one_wg
+                          else "cooperative, per stream after the join"},
         "round_ms": [round(1e3 * x, 3) for x in times],
         "replayed": replays,
         "x_stream_gbs": round(gbs, 1),

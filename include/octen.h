@@ -188,11 +188,14 @@ octen_status octen_compress_batch(octen_t h, const void* X, int64_t t, const dou
 octen_status octen_compress_batch_async(octen_t h, const void* X, int64_t t, const double* W,
                                         const float* slice_scale);
 
-/* Same for a sparse batch given as sorted COO (by k, then i, then j) with
- * slice indices k in [0, t) relative to the batch.  k, i, j: [nnz] int32,
- * v: [nnz] f32, all device arrays; 0 <= nnz < 2^31.  Duplicated coordinates
- * add up.  The coordinates are checked on the device first (synchronises):
- * OCTEN_ERR_ARG if one is out of range or the order is violated.  The
+/* Same for a sparse batch given as COO with slice indices k in [0, t)
+ * relative to the batch.  k, i, j: [nnz] int32, v: [nnz] f32, all device
+ * arrays (read only); 0 <= nnz < 2^31.  Duplicated coordinates add up.  The
+ * coordinates are checked on the device first (synchronises): OCTEN_ERR_ARG
+ * if one is out of range.  A batch not ordered by k, then i, then j is
+ * sorted on the device into arrays of the handle (a stable radix sort:
+ * equal coordinates keep their order; OCTEN_ERR_UNSUPPORTED if the packed
+ * key ceil(log2 t) + ceil(log2 I) + ceil(log2 J) exceeds 64 bits).  The
  * summaries are dense (Sec. 4.1): f64 arithmetic for compress_dtype F64,
  * f32 gathers and MFMA f32 accumulation otherwise (also for BF16). */
 octen_status octen_compress_batch_coo(octen_t h, int64_t nnz, const int32_t* k,

@@ -41,7 +41,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "replica_cols", "compress_dense", "compress_coo", "coo_segments",
+    "replica_cols", "compress_dense", "compress_coo", "coo_segments", "sort_coo",
     "compress_coo_entries", "update_summaries",
     "mttkrp", "gram_hadamard", "solve_normal", "cp_als", "replica_fit",
     "distribute_lambda", "greedy_assign", "match_replicas", "stack_rhs",
@@ -102,6 +102,15 @@ def compress_coo(k, i, j, v, t, U, V, W, P, Q, S):
             M[kk] = (Up[i[sel]] * v[sel, None]).T @ Vp[j[sel]]
         Z[p] = np.tensordot(M, Wp, axes=([0], [0]))
     return Z
+
+
+def sort_coo(k, i, j, v):
+    """A COO batch in (k, i, j) order (the sparse input of Sec. 4.1, whose
+    segments are runs of equal (k, i)); equal coordinates keep their input
+    order (a stable sort, numpy's lexsort)."""
+    k = np.asarray(k); i = np.asarray(i); j = np.asarray(j); v = np.asarray(v)
+    order = np.lexsort((j, i, k))
+    return k[order], i[order], j[order], v[order]
 
 
 def coo_segments(k, i, t):

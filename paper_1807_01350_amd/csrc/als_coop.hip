@@ -545,10 +545,13 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   double* lamv = CtC + RR;                    // [MAXR]
   double* rlam = lamv + MAXR;                 // [MAXR] 1 / lamv
   double* scr = rlam + MAXR;                  // [NT]
-  // the partial Grams of the mode solves go where T is (T is dead from the
-  // end of mode 2 to the next sweep) when they fit there
+  // the mode-2/3 solves on MFMA with the partial Grams from the result
+  // fragments, which go where T is (T is dead from the end of mode 2 to the
+  // next sweep), when they fit there and the factors have enough rows to
+  // pay for it (below 40 rows the all-thread solve, column norms and Gram
+  // are faster)
   const int nslot = min(NT / 64, (Q + 15) / 16);
-  const bool pg = nslot * RR <= g.npair_pad * R;
+  const bool pg = Q >= 40 && nslot * RR <= g.npair_pad * R;
   // SPLIT: B-operand fragments, [r tile][k chunk of 32][hi, lo][lane][8],
   // 16-byte aligned; those of W take the place of T when they fit there (T
   // is dead from the end of mode 2 to the next sweep)
@@ -885,7 +888,8 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     }
     __syncthreads();
     for (int e = tid; e < na * R; e += NT) Al[e] *= rlam[fR.mod(e)];
-    apply_gram(Mf, Gi, Bf, Q, R, pg ? Ts : nullptr);
+    if (pg) apply_gram(Mf, Gi, Bf, Q, R, Ts);
+    else apply_inverse(Mf, Gi, Bf, Q, R);
     __syncthreads();
     // lambda_B and B'B of the normalised B from the partial Grams
     if (pg) norm_gram(Ts, nslot, R, BtB, lamv, rlam);
@@ -930,9 +934,12 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       // tiles are fewer than half the MFMA wavefronts, the pair range is cut
       // in two and the second halves are added through LDS (fixed order)
       const int ctiles = (Q + 15) / 16, ntl = ctiles * RT;
-      // all eight wavefronts: the mode-3 inverse waits until after the
-      // reduction below, where it overlaps the sum of the partials
-      constexpr int NMW = NT / 64;
+      // when the tiles (and halves) fit on wavefronts 1-7, wavefront 0 forms
+      // and inverts G3 meanwhile; otherwise all eight wavefronts take tiles
+      // and the inverse waits until after the reduction below, where it
+      // overlaps the sum of the partials
+      const bool early = ntl * (2 * ntl <= NT / 64 - 1 ? 2 : 1) <= NT / 64 - 1;
+      const int NMW = early ? NT / 64 - 1 : NT / 64;
       const int ksp = 2 * ntl <= NMW ? 2 : 1;
       // pair range: padded to a multiple of 32 in LDS (zero rows), halves
       // cut at a multiple of 32; from global memory, the exact range
@@ -941,8 +948,12 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
                               : ((GX && !SPLIT) ? ((npair + 15) / 16) * 8 : ((npp / 32 + 1) / 2) * 32);
       f64x4 keep = {0.0, 0.0, 0.0, 0.0};
       int keep_tile = -1;
-      {
-        for (int item = wave; item < ntl * ksp; item += NMW) {
+      if (early && wave == 0) {
+        for (int e = lane; e < RR; e += 64) G[e] = AtA[e] * BtB[e];
+        wave_sync();
+        spd_inverse<RMAX>(G, Gi, R, &s_bad);
+      } else {
+        for (int item = early ? wave - 1 : wave; item < ntl * ksp; item += NMW) {
           const int tt = item % ntl, part = item / ntl;
           const int kb = part * kh, ke = kb + kh < npp ? kb + kh : npp;
           const int ct = tt / RT, rt = tt % RT;
@@ -1070,10 +1081,12 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       if (NW > 1) {
         alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok, local);
         if (!alive) break;
-        if (wave != 0)
+        if (early)
+          for (int e = tid; e < QR; e += NT) Mf[e] = sum_slots(slot(set2, 0) + e, slot_len, NW);
+        else if (wave != 0)
           for (int e = tid - 64; e < QR; e += NT - 64) Mf[e] = sum_slots(slot(set2, 0) + e, slot_len, NW);
       }
-      if (wave == 0) {
+      if (wave == 0 && !early) {
         // G3 = A'A o B'B (both complete) by wavefront 0 while the others
         // sum the partials of M3
         for (int e = lane; e < RR; e += 64) G[e] = AtA[e] * BtB[e];
@@ -1083,7 +1096,8 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     }
     __syncthreads();
     // ------------------------------------------------ mode 3 solve (C)
-    apply_gram(Mf, Gi, Cf, Q, R, pg ? Ts : nullptr);
+    if (pg) apply_gram(Mf, Gi, Cf, Q, R, Ts);
+    else apply_inverse(Mf, Gi, Cf, Q, R);
     __syncthreads();
     if (pg) norm_gram(Ts, nslot, R, CtC, lamv, rlam);
     else col_norms(Cf, Q, R, lamv, rlam);

@@ -90,6 +90,11 @@ struct octen_ctx {
   int* seg_slice = nullptr; int64_t seg_slice_cap = 0;
   int* slice_seg = nullptr; int64_t slice_seg_cap = 0;
   int* coo_small = nullptr;          // [4]: error bits, nseg, t, unused
+  // an unsorted batch, sorted: coordinates, values, radix-sort scratch
+  int *coo_ks = nullptr, *coo_is = nullptr, *coo_js = nullptr;
+  int64_t coo_ks_cap = 0, coo_is_cap = 0, coo_js_cap = 0;
+  float* coo_vs = nullptr;           int64_t coo_vs_cap = 0;
+  double* coo_sort_work = nullptr;   int64_t coo_sort_work_cap = 0;
   int coo_nseg = -1;                 // segments of the last sparse batch
   int64_t coo_t = 0;
   float *Uf = nullptr, *Vf = nullptr;            // f32 copies for sparse gathers
@@ -654,7 +659,34 @@ octen_status octen_compress_batch_coo(octen_t h, int64_t nnz, const int32_t* k, 
   HIPCHK(h, hipMemcpyAsync(hs, h->coo_small, sizeof(hs), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
   if (hs[0] & 1) return fail(h, OCTEN_ERR_ARG, "COO coordinate out of range");
-  if (hs[0] & 2) return fail(h, OCTEN_ERR_ARG, "COO entries not sorted by (k, i, j)");
+  if (hs[0] & 2) {
+    // not in (k, i, j) order: a stable device sort into the handle's
+    // arrays, then the segments of the sorted batch
+    if (coo_sort_key_bits(t, h->I, h->J) > 64)
+      return fail(h, OCTEN_ERR_UNSUPPORTED,
+                  "unsorted COO batch whose packed (k, i, j) key exceeds 64 bits");
+    OKCHK(dgrow(h, &h->coo_ks, &h->coo_ks_cap, nnz));
+    OKCHK(dgrow(h, &h->coo_is, &h->coo_is_cap, nnz));
+    OKCHK(dgrow(h, &h->coo_js, &h->coo_js_cap, nnz));
+    OKCHK(dgrow(h, &h->coo_vs, &h->coo_vs_cap, nnz));
+    OKCHK(dgrow(h, &h->coo_sort_work, &h->coo_sort_work_cap,
+                (int64_t)(coo_sort_work_bytes(nnz) + 7) / 8));
+    {
+      StageTimer tm(h, OCTEN_STAGE_COO_INDEX);
+      HIPCHK(h, coo_sort(s, nnz, k, i, j, v, t, h->I, h->J, h->coo_sort_work, h->coo_ks,
+                         h->coo_is, h->coo_js, h->coo_vs));
+      k = h->coo_ks;
+      i = h->coo_is;
+      j = h->coo_js;
+      v = h->coo_vs;
+      HIPCHK(h, fill_i32(s, h->coo_small, 4, 0));
+      HIPCHK(h, coo_segments(s, nnz, k, i, t, h->coo_work, h->seg_start, h->seg_row,
+                             h->seg_slice, h->slice_seg, h->coo_small + 1));
+      HIPCHK(h, fill_i32(s, h->coo_small + 2, 1, (int)t));
+    }
+    HIPCHK(h, hipMemcpyAsync(hs, h->coo_small, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+  }
   h->coo_nseg = hs[1];
   h->coo_t = t;
   OKCHK(dgrow(h, &h->Wz, &h->Wz_cap, t * M1));

@@ -172,12 +172,21 @@ hipError_t rec_temporal_finish(hipStream_t s, int R, int64_t Kold, int64_t t, co
 hipError_t rec_weights(hipStream_t s, int M1, int S, int P, double* w, double* w2);
 
 // ---------------------------------------------------------------- sparse ---
-// COO batches sorted by (k, i, j).  bad |= 1 for a coordinate outside
+// COO batches by (k, i, j).  bad |= 1 for a coordinate outside
 // [0,t) x [0,I) x [0,J), |= 2 for an order violation (if check_order).
 hipError_t coo_check(hipStream_t s, int64_t nnz, const int* k, const int* i, const int* j,
                      int64_t t, int64_t I, int64_t J, bool check_order, int* bad);
 // Ints of scratch needed by coo_segments.
 size_t coo_work_ints(int64_t nnz);
+// Stable sort of a COO batch by (k, i, j) into ko, io, jo, vo (equal
+// coordinates keep their input order).  Coordinates must be in range (see
+// coo_check); the packed key needs coo_sort_key_bits(t, I, J) <= 64 bits,
+// else hipErrorInvalidValue.  work: coo_sort_work_bytes(nnz) bytes.
+size_t coo_sort_work_bytes(int64_t nnz);
+int coo_sort_key_bits(int64_t t, int64_t I, int64_t J);
+hipError_t coo_sort(hipStream_t s, int64_t nnz, const int* k, const int* i, const int* j,
+                    const float* v, int64_t t, int64_t I, int64_t J, void* work, int* ko, int* io,
+                    int* jo, float* vo);
 // Segments = distinct (k, i) pairs in input order: seg_start [nseg + 1]
 // (last = nnz), seg_row, seg_slice [nseg], slice_seg [t + 1]; nseg_dev gets
 // the count.  Arrays sized for nseg = nnz.

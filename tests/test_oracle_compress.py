@@ -3,7 +3,7 @@ against brute force, closed forms and special cases."""
 import numpy as np
 import pytest
 
-from oracle import (compress_dense, compress_coo, compress_coo_entries, coo_segments,
+from oracle import (compress_dense, compress_coo, compress_coo_entries, coo_segments, sort_coo,
                     update_summaries, replica_cols)
 from paper_1807_01350_amd import synth
 
@@ -168,3 +168,24 @@ def test_coo_entries_match_full_compression(rng):
     got = compress_coo_entries(k, i, j, v, t, U, V, W, P, Q, S, picks)
     for (p, a, b), row in zip(picks, got):
         assert np.allclose(row, Z[p, a, b, :], rtol=1e-13, atol=1e-13)
+
+
+def test_sort_coo_against_python_sort(rng):
+    # brute force: Python's stable sort on (k, i, j) tuples; duplicates keep
+    # their input order (told apart by their values)
+    n = 300
+    k = rng.integers(0, 4, n); i = rng.integers(0, 5, n); j = rng.integers(0, 6, n)
+    v = np.arange(n, dtype=np.float64)
+    ks, is_, js, vs = sort_coo(k, i, j, v)
+    want = sorted(range(n), key=lambda e: (k[e], i[e], j[e]))
+    assert vs.tolist() == [float(e) for e in want]
+    assert ks.tolist() == [int(k[e]) for e in want]
+    assert is_.tolist() == [int(i[e]) for e in want] and js.tolist() == [int(j[e]) for e in want]
+    # compression does not depend on the order of the nonzeros
+    P, Q, S, I, J, t = 2, 4, 1, 5, 6, 4
+    M1 = S + P * (Q - S)
+    U = rng.standard_normal((I, M1)); V = rng.standard_normal((J, M1)); W = rng.standard_normal((t, M1))
+    vv = rng.standard_normal(n)
+    a = compress_coo(k, i, j, vv, t, U, V, W, P, Q, S)
+    b = compress_coo(*sort_coo(k, i, j, vv), t, U, V, W, P, Q, S)
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-12)
