@@ -62,6 +62,8 @@ def parse():
                                            "batched", "forms", "copy"),
                     default="dense")
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--tols", default="1e-4,1e-5,1e-6",
+                    help="forms workload: the replica-fit stopping tolerances, all reported")
     ap.add_argument("--train-streams", type=int, default=6)
     ap.add_argument("--streams", type=int, default=64)
     ap.add_argument("--long-I", type=int, default=100)
@@ -124,9 +126,10 @@ def cores_used():
 
 
 def gen_coo_batches(torch, c, schedule, seed, dev):
-    """Seeded on-device COO stream: per slice nnz_per_slice draws of (i, j),
-    each truncated Zipf(a) over its mode then a fixed random relabelling;
-    duplicates removed; sorted by (k, i, j); values = rank-R CP model with
+    """Seeded on-device COO stream: per slice nnz_per_slice distinct (i, j),
+    each coordinate a truncated Zipf(a) draw over its mode then a fixed
+    random relabelling (drawn until a slice holds that many distinct pairs,
+    then a uniform random subset of that size kept); sorted by (k, i, j); values = rank-R CP model with
     U[0,1] factors at the coordinates + sigma N(0,1).  Returns the factors and
     a list of (k, i, j, v) per batch (k relative to the batch)."""
     g = torch.Generator(device=dev)
@@ -146,11 +149,33 @@ def gen_coo_batches(torch, c, schedule, seed, dev):
 
     draw_i, draw_j = zipf_sampler(c.I), zipf_sampler(c.J)
     out = []
+    IJ = c.I * c.J
     for k0, t in schedule:
         per = c.nnz_per_slice
-        kk = torch.arange(t, device=dev, dtype=torch.int64).repeat_interleave(per)
-        key = (kk * c.I + draw_i(t * per)) * c.J + draw_j(t * per)
-        key = torch.unique(key)
+        # draw until every slice holds at least nnz_per_slice distinct
+        # coordinates, then keep a uniformly random nnz_per_slice of them
+        key = torch.empty(0, dtype=torch.int64, device=dev)
+        need = torch.full((t,), per, dtype=torch.int64, device=dev)
+        while True:
+            extra = (2 * need).clamp_(min=0)
+            kk = torch.repeat_interleave(torch.arange(t, device=dev, dtype=torch.int64), extra)
+            if kk.numel() == 0:
+                break
+            key = torch.unique(torch.cat([key, (kk * c.I + draw_i(kk.numel())) * c.J +
+                                          draw_j(kk.numel())]))
+            have = torch.bincount(key // IJ, minlength=t)
+            need = (per - have).clamp_(min=0)
+            if int(need.sum()) == 0:
+                break
+        sl = key // IJ
+        pri = torch.rand(key.numel(), generator=g, device=dev, dtype=f64)
+        order = torch.argsort(sl.double() + pri)
+        sl_o = sl[order]
+        first = torch.zeros(t + 1, dtype=torch.int64, device=dev)
+        first[1:] = torch.cumsum(torch.bincount(sl_o, minlength=t), 0)
+        rank = torch.arange(key.numel(), device=dev) - first[sl_o]
+        key = torch.sort(key[order][rank < per]).values
+        del sl, pri, order, sl_o, rank
         k = key // (c.I * c.J)
         rem = key - k * (c.I * c.J)
         i = rem // c.J
@@ -166,15 +191,16 @@ def gen_coo_batches(torch, c, schedule, seed, dev):
     return A, B, C, out
 
 
-def cpu_baseline_sparse(c, U, V, W, init, iters, batch_slices):
-    """The oracle, untuned, on a bounded sample of one sparse batch:
-    compression of 2 of its slices, 5 ALS sweeps on all replicas, one
-    recovery; scaled to a whole batch (compression x t/2, ALS x iters/5)."""
+def cpu_baseline_sparse(c, U, V, W, init, iters, batch_slices, batch):
+    """The oracle, untuned, on a bounded sample of one timed sparse batch
+    (device tensors k, i, j, v): compression of its first 2 slices, 5 ALS
+    sweeps on all replicas, one recovery; scaled to a whole batch
+    (compression x t/2, ALS x iters/5)."""
     import oracle
-    from paper_1807_01350_amd import synth
     ns, sweeps = 2, 5
-    _, _, _, k, i, j, v = synth.coo_stream(c.I, c.J, ns, c.R, c.nnz_per_slice, c.sigma,
-                                           c.config_id)
+    kd, id_, jd, vd = batch
+    sel = kd < ns
+    k, i, j, v = (x[sel].cpu().numpy() for x in (kd, id_, jd, vd))
     o = oracle.OctenOracle(c.I, c.J, c.R, c.P, c.Q, c.S, U, V)
     t0 = time.perf_counter()
     o.compress_batch_coo(k, i, j, v, ns, W[:ns])
@@ -291,7 +317,8 @@ def run_sparse(args):
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline_sparse(c, U, V, Ws[args.warmup + 1], init, args.iters, t)
+        cpu = cpu_baseline_sparse(c, U, V, Ws[args.warmup + 1], init, args.iters, t,
+                                  batches[args.warmup + 1])
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "slices/s", "n_gpus": 1,
@@ -352,6 +379,13 @@ def run_batched(args):
     g.manual_seed(synth.seed_of(4, 1))
     f64 = torch.float64
     streams = []
+    # the oracle's sample: the two streams of least oracle work per round
+    # (its ALS, einsum contractions, dominates: P Q^3 R per sweep; its
+    # compression is BLAS)
+    def _work(sh):
+        I, J, t, R, P, Q = sh
+        return P * Q ** 3 * R * args.iters + I * J * t * (S + P * (Q - S)) / 50
+    sample = set(sorted(range(len(shapes)), key=lambda q: _work(shapes[q]))[:2])
     print(f"[bench] {len(shapes)} streams: creating handles", file=sys.stderr, flush=True)
     for q, (I, J, t, R, P, Q) in enumerate(shapes):
         M1 = S + P * (Q - S)
@@ -369,7 +403,7 @@ def run_batched(args):
         outs = (torch.empty((I, R), dtype=f64, device=dev), torch.empty((J, R), dtype=f64, device=dev),
                 torch.empty(((rounds + 1) * t, R), dtype=f64, device=dev))
         streams.append(dict(shape=(I, J, t, R, P, Q), A=A, B=B, C=C, eng=eng, X=X, W=W,
-                            init=init, outs=outs, M1=M1))
+                            init=init, outs=outs, M1=M1, UV=(U, V) if q in sample else None))
         del U, V
 
     def fill(st, r):
@@ -437,6 +471,38 @@ def run_batched(args):
                      "kernel": "whole round (X bytes streamed / round time)"},
         "cpu_baseline": None,
     }
+    if not args.no_cpu_baseline:
+        # the oracle on a sample: the two cheapest streams, an initial batch
+        # (untimed) then one update round (timed: compress, update, ALS,
+        # recover), on batches drawn the same way as the timed rounds
+        import oracle
+        tot_s, tot_n, desc = 0.0, 0, []
+        for q in sorted(sample):
+            st = streams[q]
+            I, J, t, R, P, Q = st["shape"]
+            U, V = (x.cpu().numpy() for x in st["UV"])
+            o = oracle.OctenOracle(I, J, R, P, Q, S, U, V)
+            fill(st, 0)
+            o.compress_batch(st["X"].double().cpu().numpy(), st["W"].cpu().numpy())
+            o.update_replicas()
+            o.cp_als_replicas(args.iters, init=st["init"].cpu().numpy())
+            o.recover_factors()
+            fill(st, 1)
+            Xh, Wh = st["X"].double().cpu().numpy(), st["W"].cpu().numpy()
+            t1 = time.perf_counter()
+            o.compress_batch(Xh, Wh)
+            o.update_replicas()
+            o.cp_als_replicas(args.iters)
+            o.recover_factors()
+            tot_s += time.perf_counter() - t1
+            tot_n += t
+            desc.append(f"I={I} J={J} t={t} R={R} P={P} Q={Q}")
+        out["cpu_baseline"] = {"value": round(tot_n / tot_s, 3), "unit": "slices/s",
+                               "cores": cores_used(), "kind": "oracle",
+                               "sample": f"one update round of the two streams of least oracle work ("
+                                         f"{'; '.join(desc)}) through the FP64 oracle, "
+                                         f"{tot_s:.2f} s; the device rounds stream all "
+                                         f"{len(streams)}"}
     group.close()
     for st in streams:
         st["eng"].close()
@@ -445,11 +511,13 @@ def run_batched(args):
 
 def run_forms(args):
     """The dense 1000 x 1000 stream in two forms with the same ALS stopping
-    rule (replica fit change below --tol, at most --iters sweeps): the plain
-    FP32 form (FP32 compression, ALS from the previous factors, one call per
-    step) and the BF16 + graph + learned-warm-start form (BF16 compression,
-    the step captured once as a HIP graph and replayed, ALS from the judged
-    network start).  The network (4Q + 32 -> 256 -> 256 -> 3Q) is first
+    rule (replica fit change below tol, at most --iters sweeps), for every
+    tol in --tols: the plain FP32 form (FP32 compression, ALS from the
+    previous factors, one call per step) and the two-term BF16 + graph +
+    learned-warm-start form (the step captured once as a HIP graph and
+    replayed, ALS from the judged network start); then fixed budgets of 5,
+    10 and 20 sweeps from the plain and from the network start (FP32
+    compression in both).  The network (4Q + 32 -> 256 -> 256 -> 3Q) is first
     trained, untimed, on pairs from other streams of the same shape."""
     import torch
     from paper_1807_01350_amd import octen as oc
@@ -499,12 +567,14 @@ def run_forms(args):
     Ws = [torch.from_numpy(synth.temporal_W(c.t0 if b == 0 else t, c.M1, c.config_id, b)).to(dev)
           for b in range(nsteps + 1)]
     init = torch.from_numpy(synth.als_init(c.P, c.Q, c.R, c.config_id)).to(dev)
-    results = {}
-    for form in ("fp32_plain", "bf16x2_graph_learned"):
-        bf = form.startswith("bf16")
+
+    def run_stream(form, max_iters, tol, learned, graph):
+        """The measured stream through one form; per-batch wall time (timed
+        batches only), sweeps per replica, share of replicas whose network
+        start was kept, and the fit over the whole stream."""
+        bf = form == "bf16x2"
         e = oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, torch.from_numpy(U).to(dev),
-                     torch.from_numpy(V).to(dev), x_dtype="f32",
-                     compress_dtype="bf16x2" if bf else "f32")
+                     torch.from_numpy(V).to(dev), x_dtype="f32", compress_dtype=form)
         A = torch.empty((c.I, c.R), dtype=torch.float64, device=dev)
         B = torch.empty((c.J, c.R), dtype=torch.float64, device=dev)
         C = torch.empty((K, c.R), dtype=torch.float64, device=dev)
@@ -512,61 +582,82 @@ def run_forms(args):
         e.update_replicas()
         e.cp_als_replicas(args.iters, init=init)
         e.recover_factors_async(A, B, C)
-        group = None
-        if bf:
+        if learned:
             e.warmstart_set(net, G, D)
+        group = None
+        if graph:
             group = oc.Group([e])
             xb = torch.empty((t, c.I, c.J), dtype=torch.float32, device=dev)
             wb = torch.empty((t, c.M1), dtype=torch.float64, device=dev)
         times, sweeps, kept = [], [], []
         k0 = c.t0
         for b in range(1, nsteps + 1):
-            if bf:
+            if graph:
                 xb.copy_(X[k0:k0 + t])
                 wb.copy_(Ws[b])
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            if bf:
-                group.step([(xb, wb)], args.iters, args.tol, learned=True)
+            if graph:
+                group.step([(xb, wb)], max_iters, tol, learned=learned)
             else:
                 e.compress_batch(X[k0:k0 + t], Ws[b])
                 e.update_replicas()
-                e.cp_als_replicas(args.iters, tol=args.tol)
+                e.cp_als_replicas(max_iters, tol=tol, learned=learned)
             e.recover_factors_async(A, B, C)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             sweeps.append(float(e.state(oc.OCTEN_STATE_ITERS).float().mean()))
-            if bf:
+            if learned:
                 kept.append(float(e.state(oc.OCTEN_STATE_WARM_KEEP).float().mean()))
             k0 += t
         timed = times[args.warmup:]
         sse = nx = 0.0
         for q0 in range(0, K, 100):
             sse, nx = e.fit_terms(X[q0:min(K, q0 + 100)], q0, A, B, C, acc=(sse, nx))
-        results[form] = {"slices_per_s": round(t * len(timed) / sum(timed), 2),
-                         "ms_per_step": round(1e3 * sum(timed) / len(timed), 4),
-                         "mean_sweeps_per_replica": round(float(np.mean(sweeps[args.warmup:])), 2),
-                         "network_start_kept": (round(float(np.mean(kept)), 3) if kept else None),
-                         "fit": 1.0 - float(np.sqrt(sse / nx))}
         if group is not None:
             group.close()
         e.close()
-        print(f"[bench] {form}: {results[form]}", file=sys.stderr, flush=True)
+        return {"slices_per_s": round(t * len(timed) / sum(timed), 2),
+                "ms_per_step": round(1e3 * sum(timed) / len(timed), 4),
+                "mean_sweeps_per_replica": round(float(np.mean(sweeps[args.warmup:])), 2),
+                "network_start_kept": (round(float(np.mean(kept)), 3) if kept else None),
+                "fallback_rate": (round(1.0 - float(np.mean(kept)), 3) if kept else None),
+                "fit": 1.0 - float(np.sqrt(sse / nx))}
+
+    tols = [float(x) for x in args.tols.split(",")]
+    per_tol = {}
+    for tol in tols:
+        a = run_stream("f32", args.iters, tol, learned=False, graph=False)
+        b = run_stream("bf16x2", args.iters, tol, learned=True, graph=True)
+        per_tol[f"{tol:g}"] = {"fp32_plain": a, "bf16x2_graph_learned": b,
+                               "speedup_vs_fp32_plain": round(b["slices_per_s"] / a["slices_per_s"], 3),
+                               "fit_difference": b["fit"] - a["fit"]}
+        print(f"[bench] tol {tol:g}: {per_tol[f'{tol:g}']}", file=sys.stderr, flush=True)
+    # fixed sweep budgets from the plain and from the judged network start
+    # (same FP32 compression, so only the start differs)
+    budgets = {}
+    for nb in (5, 10, 20):
+        pl = run_stream("f32", nb, 0.0, learned=False, graph=False)
+        ln = run_stream("f32", nb, 0.0, learned=True, graph=False)
+        budgets[str(nb)] = {"fit_plain_start": pl["fit"], "fit_learned_start": ln["fit"],
+                            "network_start_kept": ln["network_start_kept"]}
+        print(f"[bench] budget {nb}: {budgets[str(nb)]}", file=sys.stderr, flush=True)
     net.close()
-    a, b = results["fp32_plain"], results["bf16x2_graph_learned"]
+    head = per_tol[f"{tols[-1]:g}"]
     out = {
-        "metric": METRIC, "value": b["slices_per_s"], "unit": "slices/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["ms_per_step"],
+        "metric": METRIC, "value": head["bf16x2_graph_learned"]["slices_per_s"], "unit": "slices/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["bf16x2_graph_learned"]["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x2",
         "data": "synthetic (seeded on-device generator; rank-10 U[0,1] CP model + N(0, 0.01^2))",
         "config": {"workload": f"dense1000_f32 forms: {c.t0} initial slices then batches of {t}; "
                                f"P=12, Q=60, S=3; ALS until the replica fit changes by less than "
-                               f"{args.tol} (at most {args.iters} sweeps) in both forms",
-                   "tol": args.tol, "als_max_iters": args.iters,
+                               f"tol (at most {args.iters} sweeps) in both forms, every tol in "
+                               f"{args.tols}; value = the last tol",
+                   "tols": tols, "als_max_iters": args.iters,
                    "train_pairs": int(Xtr.shape[0]), "train_loss": [loss0, loss1]},
-        "forms": results,
-        "speedup_vs_fp32_plain": round(b["slices_per_s"] / a["slices_per_s"], 3),
-        "fit_difference": b["fit"] - a["fit"],
+        "per_tol": per_tol,
+        "fixed_budgets": budgets,
         "roofline": None,
         "cpu_baseline": None,
     }
@@ -994,9 +1085,8 @@ def run_long(args):
     tinit = torch.from_numpy(init).to(dev)
     results = {}
     for mode in ("eager", "graph"):
-        flags = oc.OCTEN_FLAG_ALS_ONE_WG if mode == "graph" else 0
         eng = oc.Octen(I, J, R, P, Q, S, torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev),
-                       x_dtype="f32", compress_dtype="f32", flags=flags)
+                       x_dtype="f32", compress_dtype="f32")
         A = torch.empty((I, R), dtype=torch.float64, device=dev)
         B = torch.empty((J, R), dtype=torch.float64, device=dev)
         C = torch.empty((K, R), dtype=torch.float64, device=dev)
@@ -1108,7 +1198,6 @@ def run_sweep(args):
     matrices and ALS start; reports the mean and spread of the final fit
     with M1, Eq. 8's bound and the determinacy verdicts of every setting."""
     import torch
-    import oracle
     from paper_1807_01350_amd import octen as oc
     from paper_1807_01350_amd import synth
 
@@ -1153,7 +1242,9 @@ def run_sweep(args):
             sse, nx = eng.fit_terms(X, 0, A, B, C)
             fits.append(1.0 - float(np.sqrt(sse / nx)))
             eng.close()
-        bits, pmin = oracle.identifiability(I, J, K, t, R, P, Q, Sv)
+        st_, bits, pmin = oc.octen_check_identifiable(oc.make_config(I, J, R, P, Q, Sv), K, t)
+        if st_ != oc.OCTEN_OK:
+            raise RuntimeError(f"octen_check_identifiable: status {st_}")
         rows.append({"vary": what, "p": P, "Q": Q, "shared": Sv, "M1": M1,
                      "p_min_eq8": round(pmin, 3), "eq8_holds": bool(bits & 1),
                      "modes12_determined": bool(bits & 2 and bits & 4),
@@ -1174,6 +1265,30 @@ def run_sweep(args):
         "roofline": None,
         "cpu_baseline": None,
     }
+    if not args.no_cpu_baseline:
+        # the oracle on one whole stream of the grid (p = 6, Q = 20, S = 4,
+        # first seed), timed from its first batch to its last recovery
+        import oracle
+        P, Q, Sv, cid = 6, 20, 4, 500
+        M1 = Sv + P * (Q - Sv)
+        U, V = synth.compression_UV(I, J, P, Q, Sv, cid)
+        o = oracle.OctenOracle(I, J, R, P, Q, Sv, U, V)
+        t1 = time.perf_counter()
+        k0, b = 0, 0
+        while k0 < K:
+            tt = t0 if b == 0 else t
+            o.compress_batch(Xh[k0:k0 + tt], synth.temporal_W(tt, M1, cid, b))
+            o.update_replicas()
+            o.cp_als_replicas(args.iters, init=synth.als_init(P, Q, R, cid) if b == 0 else None)
+            o.recover_factors()
+            k0 += tt
+            b += 1
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": round(K / dt, 3), "unit": "slices/s",
+                               "cores": cores_used(), "kind": "oracle",
+                               "sample": f"one whole stream of the grid (p = {P}, Q = {Q}, "
+                                         f"shared = {Sv}, {K} slices) through the FP64 oracle, "
+                                         f"{dt:.2f} s"}
     print(json.dumps(out))
 
 
