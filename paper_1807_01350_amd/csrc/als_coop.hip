@@ -239,76 +239,6 @@ __device__ __forceinline__ void spd_inverse(const double* G, double* Ginv, int R
   else spd_inverse_wave<RMAX>(G, Ginv, R, bad);
 }
 
-// Inverse of the SPD matrix G (R x R, R <= 16, LDS) refined from an earlier
-// inverse X of a nearby matrix (the same mode's normal matrix one sweep
-// before) by Newton-Schulz steps X <- X^T (2 I - G X) on
-// v_mfma_f64_16x16x4f64, one wavefront, everything in registers: G padded
-// with the identity to 16 x 16 is the A operand (lane l: G[l % 16][4 s +
-// l / 16] for k-step s), X is kept as a result fragment (element i of lane
-// l: X[l / 16 + 4 i][l % 16]), which is lane for lane the B operand of
-// k-step i of G X and the A operand of k-step i of X^T E; E = 2 I - G X is
-// formed in the same layout and is the B operand of X^T E.  The residual
-// max |G X - I| of every iterate is measured: the first iterate with a
-// residual at most 1e-12 is accepted (written to Ginv and Xo) and 1
-// returned; 0 (nothing written) when the residual exceeds 0.1, stops
-// halving, or four products did not get there: the caller then inverts
-// from scratch.  Each step squares the residual of a symmetric iterate.
-__device__ __noinline__ int ns_refine(const double* G_, const double* X_, double* Ginv_,
-                                      double* Xo_, int R_) {
-  const lds_f64* G = lds_uniform(G_);
-  const lds_f64* X = lds_uniform(X_);
-  lds_f64* Ginv = lds_uniform(Ginv_);
-  lds_f64* Xo = lds_uniform(Xo_);
-  const int R = __builtin_amdgcn_readfirstlane(R_);
-  const int lane = threadIdx.x & 63, r0 = lane >> 4, cl = lane & 15;
-  double ga[4];
-  f64x4 x;
-#pragma unroll
-  for (int s4 = 0; s4 < 4; ++s4) {
-    const int k = 4 * s4 + r0;
-    ga[s4] = (cl < R && k < R) ? G[cl * R + k] : (cl == k ? 1.0 : 0.0);
-    const int r = r0 + 4 * s4;
-    x[s4] = (r < R && cl < R) ? X[r * R + cl] : (r == cl ? 1.0 : 0.0);
-  }
-  double prev = 1.0;
-  for (int it = 0; it < 4; ++it) {
-    f64x4 pg = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) pg = mfma64(ga[s4], x[s4], pg);
-    // a non-finite product ends the refinement (fmax below would skip it)
-    if (__ballot(!(isfinite(pg[0]) && isfinite(pg[1]) && isfinite(pg[2]) && isfinite(pg[3]))))
-      return 0;
-    double m = 0.0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) m = fmax(m, fabs(pg[i] - (r0 + 4 * i == cl ? 1.0 : 0.0)));
-    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-    // every lane holds the same maximum: take it as a scalar
-    m = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(m)),
-                         __builtin_amdgcn_readfirstlane(__double2loint(m)));
-    if (m <= 1e-12) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = r0 + 4 * i;
-        if (r < R && cl < R) {
-          Ginv[r * R + cl] = x[i];
-          Xo[r * R + cl] = x[i];
-        }
-      }
-      return 1;
-    }
-    if (!(m <= 0.1) || !(m < 0.5 * prev)) return 0;
-    prev = m;
-    f64x4 e;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) e[i] = (r0 + 4 * i == cl ? 2.0 : 0.0) - pg[i];
-    f64x4 xn = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) xn = mfma64(x[s4], e[s4], xn);
-    x = xn;
-  }
-  return 0;
-}
-
 // Quotient of e by a fixed divisor d through a 64-bit product with
 // m = ceil(2^32 / d) (2^32 itself for d = 1): exact for e * d < 2^32 (here
 // e < 2^20, d <= 128); the divisors are runtime values, and a general integer
@@ -577,7 +507,6 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   static_assert(!SPLIT || sizeof(T) == 4, "the two-term form takes float summaries");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_ok, s_bad, s_stop, s_local;
-  __shared__ int s_have[3];   // Xprev[mode] holds an inverse
   __shared__ double s_nx2, s_fit_old;
   __shared__ int s_have_old;
 
@@ -616,9 +545,6 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   double* lamv = CtC + RR;                    // [MAXR]
   double* rlam = lamv + MAXR;                 // [MAXR] 1 / lamv
   double* scr = rlam + MAXR;                  // [NT]
-  // RMAX <= 16: the last inverse of each mode, refined in the next sweep
-  constexpr bool REFINE = RMAX <= 16;
-  double* Xprev = scr + NT;                   // [3][R][R]
   // the mode-2/3 solves on MFMA with the partial Grams from the result
   // fragments, which go where T is (T is dead from the end of mode 2 to the
   // next sweep), when they fit there and the factors have enough rows to
@@ -631,9 +557,8 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   // is dead from the end of mode 2 to the next sweep)
   const int nkc = QPAD / 32, npc = g.npair_pad / 32;
   const bool walias = SPLIT && R >= 8 * RT;
-  double* frag0 = Xprev + (REFINE ? 3 * RR : 0);
-  __bf16* Cb = (__bf16*)(SPLIT ? ((uintptr_t)frag0 + 15) & ~(uintptr_t)15
-                               : (uintptr_t)frag0);                           // C: k = c
+  __bf16* Cb = (__bf16*)(SPLIT ? ((uintptr_t)(scr + NT) + 15) & ~(uintptr_t)15
+                               : (uintptr_t)(scr + NT));                      // C: k = c
   __bf16* Wb = walias ? (__bf16*)Ts : Cb + (SPLIT ? (int64_t)RT * nkc * 2 * 512 : 0);   // W: k = pair
   unsigned char* after_frag = (unsigned char*)(
       Cb + (SPLIT ? (int64_t)RT * nkc * 2 * 512 + (walias ? 0 : (int64_t)RT * npc * 2 * 512) : 0));
@@ -684,7 +609,6 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   for (int e = tid; e < na * R; e += NT) Al[e] = F0[a0 * R + e];
   for (int e = tid; e < QR; e += NT) { Bf[e] = F0[QR + e]; Cf[e] = F0[2 * QR + e]; }
   if (tid == 0) { s_bad = 0; s_stop = 0; s_have_old = 0; s_fit_old = 0.0; s_nx2 = 0.0; }
-  if (tid < 3) s_have[tid] = 0;
   __syncthreads();
 
   unsigned* ctr = g.counters + p;
@@ -742,24 +666,6 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   __syncthreads();
 
 
-  // G^-1 into Gi for mode n, by wavefront 0: for RMAX <= 16 refined from
-  // the mode's inverse of the sweep before when that converges (ns_refine),
-  // else (and always in the first sweep) Gauss-Jordan from scratch
-  auto invert = [&](int n) {
-    if constexpr (REFINE) {
-      if (__builtin_amdgcn_readfirstlane(s_have[n]) &&
-          ns_refine(G, Xprev + n * RR, Gi, Xprev + n * RR, R))
-        return;
-      spd_inverse<RMAX>(G, Gi, R, &s_bad);
-      wave_sync();
-      for (int e = lane; e < RR; e += 64) Xprev[n * RR + e] = Gi[e];
-      if (lane == 0) s_have[n] = 1;
-      wave_sync();
-    } else {
-      spd_inverse<RMAX>(G, Gi, R, &s_bad);
-    }
-  };
-
   int done = 0;
   for (int it = 0; it < g.max_iters && alive; ++it) {
     // ------------------------------------------------ mode 1 (rows of A)
@@ -768,7 +674,7 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
     if (wave == 0) {
       for (int e = lane; e < RR; e += 64) G[e] = BtB[e] * CtC[e];
       wave_sync();
-      invert(0);
+      spd_inverse<RMAX>(G, Gi, R, &s_bad);
     }
     {
       // T(pair, r) = sum_c X(pair, c) C(c, r) on MFMA, tiles over pairs x r,
@@ -974,7 +880,7 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       }
       wave_sync();
       // ---------------------------------------------- mode 2 solve (B)
-      invert(1);
+      spd_inverse<RMAX>(G, Gi, R, &s_bad);
       // M2 was formed with the unnormalised A: B = (M2 / lambda_A) G2^{-1},
       // so row k of the inverse takes the factor 1 / lambda_A(k)
       wave_sync();
@@ -1045,7 +951,7 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
       if (early && wave == 0) {
         for (int e = lane; e < RR; e += 64) G[e] = AtA[e] * BtB[e];
         wave_sync();
-        invert(2);
+        spd_inverse<RMAX>(G, Gi, R, &s_bad);
       } else {
         for (int item = early ? wave - 1 : wave; item < ntl * ksp; item += NMW) {
           const int tt = item % ntl, part = item / ntl;
@@ -1185,7 +1091,7 @@ __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
         // sum the partials of M3
         for (int e = lane; e < RR; e += 64) G[e] = AtA[e] * BtB[e];
         wave_sync();
-        invert(2);
+        spd_inverse<RMAX>(G, Gi, R, &s_bad);
       }
     }
     __syncthreads();
@@ -1259,7 +1165,7 @@ size_t als_coop_lds_bytes(int Q, int R, int NW, bool x_f64, bool slab_global, bo
   const size_t QR = (size_t)Q * R;
   const size_t QPAD = (size_t)((Q + 31) / 32) * 32;
   const size_t dbl = (size_t)pad_pairs(Q, NW) * R + 3 * QR + QPAD * R + (size_t)na_max * R +
-                     5 * (size_t)R * R + 2 * MAXR + NT + (R <= 16 ? 3 * (size_t)R * R : 0);
+                     5 * (size_t)R * R + 2 * MAXR + NT;
   // split: 16-byte alignment slack, then the fragments of C and (unless
   // they take T's place) W, in bf16
   const size_t RT = (size_t)(R + 15) / 16;
