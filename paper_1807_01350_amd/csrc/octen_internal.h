@@ -253,4 +253,39 @@ hipError_t fit_dense(hipStream_t s, const void* X, bool x_f64, int64_t t, int64_
                      int R, int64_t k0, const double* A, const double* B, const double* C,
                      double* partials, int nparts, double* out2);
 
+// ---------------------------------------------------------------- N-mode ---
+// Kernels of the N-mode extension (layouts in octen_nmode.h), FP64.
+// out[p][row][q] = T[row][col_p(q)] for rows x M1 input T
+hipError_t nm_gather(hipStream_t s, const double* T, int64_t rows, int M1, int P, int Q, int S,
+                     double* out);
+// out[p][a][q][b] = sum_i in[p][a][i][b] U[i][col_p(q)], a < pre, i < d, b < post
+hipError_t nm_ttm(hipStream_t s, const double* in, int64_t in_stride, int64_t pre, int64_t d,
+                  int64_t post, const double* U, int M1, int P, int Q, int S, double* out,
+                  int64_t out_stride);
+// Z[p][x][c] = sum_k T[p][k][x] W[k][col_p(c)], x < L; zbad[p] |= 1 on a
+// non-finite value
+hipError_t nm_temporal(hipStream_t s, const double* T, int64_t t_stride, int64_t t, int64_t L,
+                       const double* W, int M1, int P, int Q, int S, double* Z, int* zbad);
+// Replica ALS, one workgroup per replica, fixed sweeps; hipErrorInvalidValue
+// when the LDS image or the solve's [G | M^T] does not fit
+size_t nm_als_lds_bytes(int N, int Q, int R);
+hipError_t nm_als(hipStream_t s, const double* Y, int P, int N, int Q, int R, const double* init,
+                  double* F, double* lam, int* flags, int iters);
+// lambda^(1/N) on every mode and the anchor matching to replica 0
+hipError_t nm_align(hipStream_t s, const double* F, const double* lam, int P, int N, int Q, int R,
+                    int S, double* aligned, int* perm, double* margin);
+// rhs [N][M1][R] from aligned [P][N][Q][R]
+hipError_t nm_stack(hipStream_t s, const double* aligned, int P, int N, int Q, int R, int S,
+                    double* rhs);
+// kappa[r] = prod_n k[n][r] over nm modes; ones[r] = 1
+hipError_t nm_kappa(hipStream_t s, const double* k, int nm, int R, double* kappa, double* ones);
+// pairing with the previous batch: cross [nm][R][R], norms [nm][2][R]
+hipError_t nm_tmatch(hipStream_t s, const double* cross, const double* norms, int nm, int R,
+                     int* tperm, double* tsign, double* tmargin);
+// out2 = (sum of squared residuals, sum of squares) of t slices;
+// partials: 2 * nparts doubles
+hipError_t nm_fit(hipStream_t s, const double* X, int64_t t, const int64_t* dims, int nm,
+                  const double* const* A, const double* C, int R, int64_t k0, double* partials,
+                  int nparts, double* out2);
+
 }  // namespace octen

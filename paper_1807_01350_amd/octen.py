@@ -69,6 +69,21 @@ class octen_config(ctypes.Structure):
     ]
 
 
+OCTEN_NM_MAX_MODES = 6
+
+
+class octen_nm_config(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("N", ctypes.c_int32),
+        ("R", ctypes.c_int32),
+        ("P", ctypes.c_int32),
+        ("Q", ctypes.c_int32),
+        ("S", ctypes.c_int32),
+        ("dims", ctypes.c_int64 * (OCTEN_NM_MAX_MODES - 1)),
+    ]
+
+
 _vp = ctypes.c_void_p
 _i32, _i64, _f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 _SIGS = {
@@ -110,6 +125,15 @@ _SIGS = {
     "octen_warmstart_set": ([_vp, _vp, _vp, _i32], _i32),
     "octen_warmstart_features": ([_vp, _vp], _i32),
     "octen_warmstart_targets": ([_vp, _vp], _i32),
+    "octen_nm_init": ([ctypes.POINTER(octen_nm_config), _vp, _vp, ctypes.POINTER(_vp)], _i32),
+    "octen_nm_compress_batch": ([_vp, _vp, _i64, _vp], _i32),
+    "octen_nm_update_replicas": ([_vp], _i32),
+    "octen_nm_cp_als_replicas": ([_vp, _i32, _i32, _vp], _i32),
+    "octen_nm_recover_factors": ([_vp, _vp, _vp, _i64, _vp], _i32),
+    "octen_nm_fit": ([_vp, _vp, _i64, _i64, _vp, _vp, _vp], _i32),
+    "octen_nm_get_state": ([_vp, _i32, _vp, ctypes.c_size_t], _i32),
+    "octen_nm_destroy": ([_vp], _i32),
+    "octen_nm_last_error": ([_vp], ctypes.c_char_p),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -633,4 +657,155 @@ class Octen:
         out = torch.empty(shape, dtype=dt, device=dev)
         self._check(octen_get_state(self.h, what, out, out.numel() * out.element_size()),
                     "octen_get_state")
+        return out
+
+
+# ------------------------------------------------------------------ N-mode ---
+
+def make_nm_config(dims, R, P, Q, S):
+    cfg = octen_nm_config()
+    cfg.abi_version = OCTEN_ABI_VERSION
+    cfg.N = len(dims) + 1
+    cfg.R, cfg.P, cfg.Q, cfg.S = int(R), int(P), int(Q), int(S)
+    for n, d in enumerate(dims[:OCTEN_NM_MAX_MODES - 1]):
+        cfg.dims[n] = int(d)
+    return cfg
+
+
+def _ptr_array(tensors):
+    """Host array of device pointers (None stays NULL)."""
+    arr = (_vp * max(len(tensors), 1))(*[_ptr(x) for x in tensors])
+    return arr
+
+
+def octen_nm_init(cfg, Us, stream=None):
+    h = _vp()
+    arr = _ptr_array(Us) if Us is not None else None
+    st = _lib.octen_nm_init(ctypes.byref(cfg), ctypes.cast(arr, _vp) if arr is not None else None,
+                            stream, ctypes.byref(h))
+    return st, h
+
+
+def octen_nm_compress_batch(h, X, t, W):
+    return _lib.octen_nm_compress_batch(h, _ptr(X), int(t), _ptr(W))
+
+
+def octen_nm_update_replicas(h):
+    return _lib.octen_nm_update_replicas(h)
+
+
+def octen_nm_cp_als_replicas(h, iters, init_mode, init=None):
+    return _lib.octen_nm_cp_als_replicas(h, int(iters), int(init_mode), _ptr(init))
+
+
+def octen_nm_recover_factors(h, As, C, c_capacity, K_out=None):
+    arr = _ptr_array(As)
+    return _lib.octen_nm_recover_factors(h, ctypes.cast(arr, _vp), _ptr(C), int(c_capacity), K_out)
+
+
+def octen_nm_fit(h, X, t, k0, As, C, out):
+    arr = _ptr_array(As)
+    return _lib.octen_nm_fit(h, _ptr(X), int(t), int(k0), ctypes.cast(arr, _vp), _ptr(C), out)
+
+
+def octen_nm_get_state(h, what, dst, nbytes):
+    return _lib.octen_nm_get_state(h, int(what), _ptr(dst), int(nbytes))
+
+
+def octen_nm_destroy(h):
+    return _lib.octen_nm_destroy(h)
+
+
+def octen_nm_last_error(h):
+    return _lib.octen_nm_last_error(h).decode()
+
+
+class OctenN:
+    """One online CP stream of an N-mode tensor growing in its last mode
+    (N = len(dims) + 1).  Us: N - 1 torch float64 device tensors [I_n][M1]."""
+
+    def __init__(self, dims, R, P, Q, S, Us, stream=None):
+        import torch
+        self.torch = torch
+        self.dims = tuple(int(d) for d in dims)
+        self.N = len(self.dims) + 1
+        self.R, self.P, self.Q, self.S = int(R), int(P), int(Q), int(S)
+        self.M1 = self.S + self.P * (self.Q - self.S)
+        self.cfg = make_nm_config(self.dims, R, P, Q, S)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        st, h = octen_nm_init(self.cfg, list(Us), stream.cuda_stream)
+        if st != OCTEN_OK:
+            raise OctenError(st, "octen_nm_init")
+        self.h = h
+        self.K = 0
+
+    def _check(self, st, where):
+        if st != OCTEN_OK:
+            raise OctenError(st, where, octen_nm_last_error(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            octen_nm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def compress_batch(self, X, W):
+        self._check(octen_nm_compress_batch(self.h, X, X.shape[0], W), "octen_nm_compress_batch")
+
+    def update_replicas(self):
+        self._check(octen_nm_update_replicas(self.h), "octen_nm_update_replicas")
+
+    def cp_als_replicas(self, iters, init=None):
+        mode = OCTEN_INIT_GIVEN if init is not None else OCTEN_INIT_PREV
+        self._check(octen_nm_cp_als_replicas(self.h, iters, mode, init), "octen_nm_cp_als_replicas")
+
+    def recover_factors(self, As, C):
+        K = ctypes.c_int64(0)
+        st = octen_nm_recover_factors(self.h, As, C, C.shape[0], ctypes.cast(ctypes.byref(K), _vp))
+        if st in (OCTEN_OK, OCTEN_ERR_NUMERIC):
+            self.K = K.value
+        self._check(st, "octen_nm_recover_factors")
+        return self.K
+
+    def recover_factors_async(self, As, C, t):
+        """Same without waiting for the stream (t: slices since the last
+        recovery, K tracked on the host)."""
+        self._check(octen_nm_recover_factors(self.h, As, C, C.shape[0], None),
+                    "octen_nm_recover_factors")
+        self.K += int(t)
+        return self.K
+
+    def fit_terms(self, X, k0, As, C, acc=None):
+        out = (ctypes.c_double * 2)(*(acc if acc is not None else (0.0, 0.0)))
+        self._check(octen_nm_fit(self.h, X, X.shape[0], k0, As, C, ctypes.cast(out, _vp)),
+                    "octen_nm_fit")
+        return out[0], out[1]
+
+    def state(self, what):
+        torch = self.torch
+        P, Q, R, M1, N = self.P, self.Q, self.R, self.M1, self.N
+        shapes = {
+            OCTEN_STATE_Y: ((P,) + (Q,) * N, torch.float64),
+            OCTEN_STATE_Z: ((P,) + (Q,) * N, torch.float64),
+            OCTEN_STATE_FACTORS: ((P, N, Q, R), torch.float64),
+            OCTEN_STATE_ALIGNED: ((P, N, Q, R), torch.float64),
+            OCTEN_STATE_LAMBDA: ((P, R), torch.float64),
+            OCTEN_STATE_PERM: ((P, R), torch.int32),
+            OCTEN_STATE_RHS: ((N, M1, R), torch.float64),
+            OCTEN_STATE_H: ((M1, R), torch.float64),
+            OCTEN_STATE_TPERM: ((R,), torch.int32),
+            OCTEN_STATE_MARGIN: ((P,), torch.float64),
+            OCTEN_STATE_FLAGS: ((P,), torch.int32),
+        }
+        shape, dt = shapes[what]
+        out = torch.empty(shape, dtype=dt, device="cuda")
+        self._check(octen_nm_get_state(self.h, what, out, out.numel() * out.element_size()),
+                    "octen_nm_get_state")
         return out

@@ -219,3 +219,40 @@ def sketch_matrix(D: int, Q: int, config_id: int):
     """Fixed Gaussian sketch of a replica summary: D x Q^3, N(0, 1/D), FP32."""
     g = rng(config_id, PURPOSE_MLP, sub=77)
     return (g.standard_normal((D, Q ** 3)) / np.sqrt(D)).astype(np.float32)
+
+
+# ---------------------------------------------------------------- N modes ---
+
+def nmode_factors(dims, K: int, R: int, config_id: int):
+    """Ground-truth factors of an N-mode stream (N = len(dims) + 1): one
+    U[0,1] matrix per non-temporal mode and the temporal C (K x R)."""
+    g = rng(config_id, PURPOSE_FACTORS, sub=len(dims))
+    fac = [g.random((int(d), R)) for d in dims]
+    C = g.random((K, R))
+    return fac, C
+
+
+def nmode_slices(fac, C, k0: int, t: int, sigma: float, config_id: int, batch: int):
+    """Slices k0 .. k0+t-1 of the N-mode stream: the rank-R model of the
+    factors plus sigma * N(0,1) (a draw per batch), shape (t, I_1, ...,
+    I_{N-1}), the last mode fastest, float64."""
+    letters = "abcdefg"[:len(fac)]
+    X = np.einsum("kr," + ",".join(l + "r" for l in letters) + "->k" + letters,
+                  C[k0:k0 + t], *fac)
+    if sigma > 0:
+        X += sigma * rng(config_id, PURPOSE_NOISE, sub=batch).standard_normal(X.shape)
+    return np.ascontiguousarray(X)
+
+
+def compression_Us(dims, P: int, Q: int, S: int, config_id: int):
+    """Fixed compression matrices of the non-temporal modes, deduplicated
+    layout (I_n x M1), N(0,1) rounded to the bfloat16 grid as for three modes."""
+    M1 = S + P * (Q - S)
+    g = rng(config_id, PURPOSE_COMPRESSION, sub=len(dims))
+    return [np.ascontiguousarray(to_bf16_grid(g.standard_normal((int(d), M1)))) for d in dims]
+
+
+def nmode_als_init(P: int, N: int, Q: int, R: int, config_id: int):
+    """Seeded N(0,1) starting factors of the first batch: (P, N, Q, R)."""
+    g = rng(config_id, PURPOSE_ALS_INIT, sub=N)
+    return np.ascontiguousarray(g.standard_normal((P, N, Q, R)))

@@ -2,19 +2,23 @@
 every function the header declares, and its host-only logic (argument
 validation, identifiability verdicts) matches the oracle."""
 import ctypes
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "octen.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_functions():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(octen_[a-z_]+)\s*\(", txt)))
+    names = set()
+    for path in HEADERS:
+        txt = open(path).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"\b(octen_[a-z_]+)\s*\(", txt))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -25,7 +29,7 @@ def oc():
 
 def test_library_exports_every_declared_function(oc):
     names = declared_functions()
-    assert "octen_init" in names and "octen_fit" in names
+    assert "octen_init" in names and "octen_fit" in names and "octen_nm_init" in names
     lib = ctypes.CDLL(oc.LIB_PATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
@@ -79,3 +83,39 @@ def test_null_arguments_rejected(oc):
     assert oc.octen_update_replicas(None) == oc.OCTEN_ERR_ARG
     assert oc.octen_destroy(None) == oc.OCTEN_ERR_ARG
     assert oc.octen_status_str(oc.OCTEN_ERR_STATE) == "call out of order"
+
+
+def test_nm_config_struct_layout(oc):
+    assert ctypes.sizeof(oc.octen_nm_config) == 64
+    assert oc.octen_nm_config.dims.offset == 24
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("N", 2, 1), ("N", 7, 1), ("R", 0, 1), ("R", 33, 1), ("P", 0, 1), ("S", 0, 1), ("Q", 3, 1),
+    ("abi_version", 2, 1), ("Q", 33, 6), ("R", 13, 1),
+])
+def test_nm_invalid_config_rejected_before_any_launch(oc, field, value, status):
+    cfg = oc.make_nm_config((30, 40, 50), 5, 4, 12, 3)
+    setattr(cfg, field, value)
+    st, h = oc.octen_nm_init(cfg, [1, 1, 1], None)
+    assert st == status
+    assert not h.value
+
+
+def test_nm_limits_rejected(oc):
+    # Q^N above 2^22 (N = 6, Q = 13) and a zero mode size
+    cfg = oc.make_nm_config((30, 30, 30, 30, 30), 5, 4, 13, 3)
+    st, h = oc.octen_nm_init(cfg, [1] * 5, None)
+    assert st == oc.OCTEN_ERR_UNSUPPORTED and not h.value
+    # R (R + Q) above 1024 (the solve's [G | M^T] in LDS)
+    cfg = oc.make_nm_config((30, 30, 30), 20, 4, 32, 3)
+    st, h = oc.octen_nm_init(cfg, [1] * 3, None)
+    assert st == oc.OCTEN_ERR_UNSUPPORTED and not h.value
+    cfg = oc.make_nm_config((30, 0, 30), 5, 4, 12, 3)
+    st, h = oc.octen_nm_init(cfg, [1] * 3, None)
+    assert st == oc.OCTEN_ERR_ARG and not h.value
+    cfg = oc.make_nm_config((30, 40, 50), 5, 4, 12, 3)
+    st, h = oc.octen_nm_init(cfg, None, None)
+    assert st == oc.OCTEN_ERR_ARG and not h.value
+    assert oc.octen_nm_update_replicas(None) == oc.OCTEN_ERR_ARG
+    assert oc.octen_nm_destroy(None) == oc.OCTEN_ERR_ARG
