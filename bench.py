@@ -14,7 +14,10 @@ Synthetic data are generated on the GPU from a seeded generator (no dataset
 exists for these workloads).  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--form bf16|f32]
-                  [--workload dense|sparse]
+                  [--workload dense|dense50|long|sweep|sparse|batched|forms|nmode]
+
+--workload nmode: the four-mode stream of the higher-order extension
+(100 x 100 x 100 x K, rank 5; P = 10 replicas of 16^4), FP64.
 """
 from __future__ import annotations
 
@@ -59,7 +62,7 @@ def parse():
                     help="dense stream: a second pass that overlaps the next batch's "
                          "compression with the current batch's ALS and recovery")
     ap.add_argument("--workload", choices=("dense", "dense50", "long", "sweep", "sparse",
-                                           "batched", "forms", "copy"),
+                                           "batched", "forms", "nmode", "copy"),
                     default="dense")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--tols", default="1e-4,1e-5,1e-6",
@@ -1034,6 +1037,145 @@ def run_dense50(args):
     print(json.dumps(out))
 
 
+def run_nmode(args):
+    """The four-mode stream of the N-mode extension (supplement, higher-order
+    tensors): X of 100 x 100 x 100 x K with rank-5 U[0,1] factors plus
+    N(0, 0.01^2) noise, streamed along the fourth mode: 20 initial slices, then
+    batches of 10; P = 10 replicas of 16^4 with S = 4 shared anchor rows
+    (M1 = 124 >= 100, every mode determined), 50 ALS sweeps, FP64 throughout.
+    Fit gate against the N-mode oracle over the first three batches, then
+    timed batches continuing the stream; the oracle is timed on the same
+    batches (about 10 s of them)."""
+    import torch
+    from oracle.nmode import OctenNOracle, fit_dense_n
+    from paper_1807_01350_amd import octen as oc
+    from paper_1807_01350_amd import synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    dims, R, P, Q, S, sigma, cid = (100, 100, 100), 5, 10, 16, 4, 0.01, 50
+    N = len(dims) + 1
+    M1 = S + P * (Q - S)
+    t0, t = 20, 10
+    ngate = 3
+    nsteps = args.warmup + args.steps
+    sched = [t0] + [t] * (ngate - 1 + nsteps)
+    K = sum(sched)
+    fac, Ct = synth.nmode_factors(dims, K, R, cid)
+    Us = synth.compression_Us(dims, P, Q, S, cid)
+    init = synth.nmode_als_init(P, N, Q, R, cid)
+    Xh, Ws, k0 = [], [], 0
+    for b, tt in enumerate(sched):
+        Xh.append(synth.nmode_slices(fac, Ct, k0, tt, sigma, cid, b))
+        Ws.append(synth.temporal_W(tt, M1, cid, b))
+        k0 += tt
+    X = [torch.from_numpy(x).to(dev) for x in Xh]
+    tW = [torch.from_numpy(w).to(dev) for w in Ws]
+    eng = oc.OctenN(dims, R, P, Q, S, [torch.from_numpy(u).to(dev) for u in Us])
+    As = [torch.empty((d, R), dtype=torch.float64, device=dev) for d in dims]
+    C = torch.empty((K, R), dtype=torch.float64, device=dev)
+    tinit = torch.from_numpy(init).to(dev)
+    stream = torch.cuda.current_stream()
+    ev = {k: [] for k in ("compress", "als", "step")}
+
+    def step(b, timed=False):
+        if timed:
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record(stream)
+        eng.compress_batch(X[b], tW[b])
+        if timed:
+            e[1].record(stream)
+        eng.update_replicas()
+        if timed:
+            e[2].record(stream)
+        eng.cp_als_replicas(args.iters, init=tinit if b == 0 else None)
+        if timed:
+            e[3].record(stream)
+            ev["compress"].append((e[0], e[1]))
+            ev["als"].append((e[2], e[3]))
+        eng.recover_factors_async(As, C, sched[b])
+
+    o = OctenNOracle(dims, R, P, Q, S, Us)
+    fits_gpu, fits_or, k0 = [], [], 0
+    for b in range(ngate):
+        step(b)
+        o.compress_batch(Xh[b], Ws[b])
+        o.update_replicas()
+        o.cp_als_replicas(args.iters, init=init if b == 0 else None)
+        Ao, Co = o.recover_factors()
+        k0 += sched[b]
+        acc = (0.0, 0.0)
+        kk = 0
+        for bb in range(b + 1):
+            acc = eng.fit_terms(X[bb], kk, As, C, acc)
+            kk += sched[bb]
+        fits_gpu.append(1.0 - float(np.sqrt(acc[0] / acc[1])))
+        fits_or.append(fit_dense_n(np.concatenate(Xh[:b + 1]), Ao, Co)[0])
+    d = [abs(a - b) for a, b in zip(fits_gpu, fits_or)]
+    gate = {"stream": f"{t0} initial slices then {ngate - 1} batches of {t} (K = {k0})",
+            "form": "f64", "fit_gpu": fits_gpu, "fit_oracle": fits_or, "max_abs_dfit": max(d),
+            "bar": 1e-3, "pass": bool(max(d) <= 1e-3)}
+    for b in range(ngate, ngate + args.warmup):
+        step(b)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for b in range(ngate + args.warmup, ngate + nsteps):
+        step(b, timed=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms = {k: float(np.mean([a.elapsed_time(z) for a, z in v])) for k, v in ev.items() if v}
+    # the oracle on the timed batches, continuing its own stream state, up to ~10 s
+    dt_or, n_or = 0.0, 0
+    for b in range(ngate, ngate + nsteps):
+        t0_ = time.perf_counter()
+        o.compress_batch(Xh[b], Ws[b])
+        o.update_replicas()
+        o.cp_als_replicas(args.iters)
+        o.recover_factors()
+        dt_or += time.perf_counter() - t0_
+        n_or += 1
+        if dt_or > 10.0:
+            break
+    # replica ALS: 4 Q^N R flop per replica and sweep (two contractions of the
+    # whole summary with a factor per sweep, as a dimension tree needs)
+    als_flops = 4.0 * Q ** N * R * P * args.iters
+    als_tf = als_flops / (ms["als"] * 1e-3) / 1e12
+    # compression: the batch read once, Z written once (FP64)
+    comp_bytes = 8.0 * (t * np.prod(dims) + P * Q ** N)
+    out = {
+        "metric": METRIC, "value": round(t * args.steps / elapsed, 3), "unit": "slices/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded host generator; rank-5 U[0,1] CP model of four modes + "
+                "N(0, 0.01^2))",
+        "config": {"workload": f"nmode4_f64: 100 x 100 x 100 x K, R=5, {t0} initial slices then "
+                               f"batches of {t}; P=10, Q=16, S=4 (replicas of 16^4); "
+                               f"{args.iters} ALS sweeps; FP64 throughout",
+                   "dims": list(dims), "R": R, "P": P, "Q": Q, "S": S, "batch": t,
+                   "initial_slices": t0, "als_iters": args.iters},
+        "fit_gate": gate, "fit_oracle": fits_or[-1], "abs_dfit": max(d),
+        "stage_ms": {"compress": round(ms["compress"], 4), "als": round(ms["als"], 4)},
+        "roofline": {"bound": "alu", "achieved": round(als_tf, 4), "peak": 78.6,
+                     "unit": "TFLOP/s", "frac": round(als_tf / 78.6, 6), "traffic": None,
+                     "kernel": "nm_als_kernel (4 Q^N R flop per replica and sweep, FP64 vector "
+                               "arithmetic, one workgroup per replica)"},
+        "roofline_compression": {"bound": "hbm",
+                                 "achieved": round(comp_bytes / (ms["compress"] * 1e-3) / 1e9, 2),
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(comp_bytes / (ms["compress"] * 1e-3) / 1e9
+                                               / HBM_PEAK_GBS, 6),
+                                 "kernel": "compression of one batch (GEMM, gather, mode "
+                                           "products, temporal product)"},
+        "cpu_baseline": {"value": round(t * n_or / dt_or, 3), "unit": "slices/s",
+                         "cores": cores_used(), "kind": "oracle",
+                         "sample": f"{n_or} update batches of {t} slices of the same stream "
+                                   f"through the FP64 N-mode oracle, {dt_or:.2f} s"},
+    }
+    eng.close()
+    print(json.dumps(out))
+
+
 def long_shape(I):
     """Replica layout of the long-stream workload for slices of I x I: Q = 20,
     S = 3, R = 5 and the fewest replicas with M1 = S + P (Q - S) > I (modes 1
@@ -1325,6 +1467,8 @@ def main():
         return run_sparse(args)
     if args.workload == "forms":
         return run_forms(args)
+    if args.workload == "nmode":
+        return run_nmode(args)
     if args.workload == "batched":
         if args.warmup + args.steps > 4:
             args.warmup, args.steps = 1, 3

@@ -45,7 +45,7 @@ typedef struct octen_nm_ctx* octen_nm_t;
 typedef struct {
   int32_t abi_version;   /* OCTEN_ABI_VERSION                                  */
   int32_t N;             /* number of modes, 3 <= N <= OCTEN_NM_MAX_MODES      */
-  int32_t R;             /* CP rank, 1 <= R <= 32, R <= Q, R (R + Q) <= 1024   */
+  int32_t R;             /* CP rank, 1 <= R <= 32, R <= Q                      */
   int32_t P;             /* replicas, P >= 1                                   */
   int32_t Q;             /* replica side, S < Q <= 32, Q^N <= 2^22             */
   int32_t S;             /* shared anchor columns, S >= 1                      */
@@ -57,9 +57,11 @@ typedef struct {
  * N - 1 non-temporal modes are built here (OCTEN_ERR_NUMERIC when a U[n]
  * lacks full rank).  OCTEN_ERR_ARG for a bad argument,
  * OCTEN_ERR_UNSUPPORTED for sizes outside the limits above (the replica ALS
- * keeps a replica's factors, Grams and the solve's [G | M^T] in the LDS of
- * one workgroup), OCTEN_ERR_NOMEM when device memory runs out.  The
- * compression workspace grows with the batch: about
+ * keeps a replica's factors and Grams in the LDS of one workgroup),
+ * OCTEN_ERR_NOMEM when device memory runs out.  Device memory: the summaries
+ * Y, Z (16 P Q^N bytes), the ALS's partial contractions (about
+ * 8 P Q^(N-1) RC (1 + 1/Q) bytes, RC = R rounded up to 8, 16 or 32) and the
+ * compression workspace, which grows with the batch: about
  * 8 (t I_1 ... I_{N-2} (M1 + 2 P Q)) bytes. */
 octen_status octen_nm_init(const octen_nm_config* cfg, const double* const* U, void* stream,
                            octen_nm_t* out);

@@ -15,13 +15,16 @@
 // nm_tmatch_kernel.  Fit: nm_fit_kernel + nm_fit_reduce.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "octen_internal.h"
 
 namespace octen {
 
 namespace {
 
-constexpr int NM_NT = 256;
+constexpr int NM_NT = 512;
+constexpr int OCTEN_NM_MAX_MODES_K = 6;
 
 __device__ __forceinline__ int rep_col(int p, int q, int Q, int S) {
   return q < S ? q : S + p * (Q - S) + (q - S);
@@ -83,35 +86,369 @@ __global__ void nm_temporal_kernel(const double* __restrict__ T, int64_t t_strid
   if (bad) atomicOr(zbad + p, 1);
 }
 
+constexpr unsigned NM_SPIN_LIMIT = 1u << 22;
+
 struct NmAlsArgs {
   const double* Y;      // [P][Q^N]
   const double* init;   // [P][N][Q][R]
   double* F;            // [P][N][Q][R]
   double* lam;          // [P][R]
-  int* flags;           // [P]: bit0 non-positive pivot, bit2 not finite
-  int N, Q, R, iters;
-  int64_t QN, QN1;      // Q^N, Q^(N-1)
+  int* flags;           // [P]: bit0 non-positive pivot, bit1 barrier timed out, bit2 not finite
+  double* work;         // [P][work_stride]: T_L, T_R, then the workgroups' intermediates
+  int64_t work_stride;
+  unsigned* ctr;        // [P] barrier counters (zero at launch)
+  int* err;             // [1] a barrier timed out
+  int N, Q, R, iters, W;
+  int QN1;              // Q^(N-1)
+  int inter_lds;        // intermediates in LDS, else in the work buffer
+  int SA, SB;           // doubles of the two intermediate buffers of a workgroup
+  int t_lds;            // the contracted summary T copied to LDS before the mode updates
+  int TMAX;             // doubles of T at most (RC * max(Q^nL, Q^(N-nL)))
 };
 
-// Rank-R CP of each replica by Gauss-Seidel ALS (the N-mode form of the
-// replica ALS, Sec. 4.1): per mode the MTTKRP (each output summed over the
-// other N-1 indices in fixed chunks, the chunks then added in order), the
-// Hadamard product of the other Grams, the solve F = M G^-1 by Gauss-Jordan
-// on [G | M^T] (one barrier per pivot, no pivoting: G is SPD; a
-// non-positive pivot is flagged), unit columns, lambda from the last mode.
+typedef __attribute__((address_space(3))) double lds_f64;
+// An LDS pointer as a wave-uniform (scalar) LDS address.
+__device__ __forceinline__ lds_f64* lds_uniform(const double* p) {
+  const unsigned a = __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(const lds_f64*)p);
+  return (lds_f64*)(uintptr_t)a;
+}
+
+// Orders the LDS accesses of one wavefront (its LDS operations complete in
+// order; the fence keeps the compiler from moving accesses across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Value of x held by lane j (j uniform).
+__device__ __forceinline__ double lane_value(double x, int j) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), j);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), j);
+  return __hiloint2double(hi, lo);
+}
+
+// 1 / p for p > 0: the hardware estimate refined by two Newton steps
+// r <- r + r (1 - p r) (a few units in the last place).
+__device__ __forceinline__ double recip(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  r = fma(r, fma(-p, r, 1.0), r);
+  r = fma(r, fma(-p, r, 1.0), r);
+  return r;
+}
+
+// Barrier of the W workgroups of one replica: every wave waits for its own
+// stores, one thread makes them visible to the other XCDs (agent-scope
+// release), bumps the counter, polls it, and takes the others' stores
+// (agent-scope acquire: the CU's L1 and the XCD's L2 drop stale lines).  A
+// poll that runs past NM_SPIN_LIMIT sets *err; a workgroup that sees *err
+// leaves.  Returns false then.
+__device__ bool nm_barrier(unsigned* ctr, unsigned target, int* err, int* s_ok) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+      if (++spins > NM_SPIN_LIMIT) {
+        __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+// out[(a L + l) Bo + b] = sum_i in[a sa + i si + l sl + b] F(i, r) for
+// a < pre, l < L, b < Bo, i < Q (i ascending).  `first`: in is the summary
+// itself (no r index), one thread per (a, l, b) output computing all RC
+// columns; otherwise in and out carry a trailing [RC] index and one thread
+// computes one (a, l, b, r) output.  The loads of up to 16 consecutive i are
+// issued before any is used (the contraction waits on memory latency
+// otherwise); indexes past Q are clamped and their terms skipped.
+template <int RC>
+__device__ void nm_contract(const double* in, bool first, int pre, int L, int Bo, int sa, int si,
+                            int sl, int Q, const double* Fm, double* out) {
+  constexpr int IB = 16;
+  const int LB = L * Bo;
+  if (first) {
+    const int n = pre * LB;
+    for (int o = threadIdx.x; o < n; o += NM_NT) {
+      const int a = o / LB, rem = o - a * LB, l = rem / Bo, b = rem - l * Bo;
+      double acc[RC];
+#pragma unroll
+      for (int r = 0; r < RC; ++r) acc[r] = 0.0;
+      const double* src = in + a * sa + l * sl + b;
+      for (int i0 = 0; i0 < Q; i0 += IB) {
+        double y[IB];
+#pragma unroll
+        for (int k = 0; k < IB; ++k) y[k] = src[min(i0 + k, Q - 1) * si];
+#pragma unroll
+        for (int k = 0; k < IB; ++k) {
+          if (i0 + k < Q) {
+            const double* f = Fm + (i0 + k) * RC;
+#pragma unroll
+            for (int r = 0; r < RC; ++r) acc[r] = fma(y[k], f[r], acc[r]);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RC; ++r) out[o * RC + r] = acc[r];
+    }
+  } else {
+    const int n = pre * LB * RC;
+    for (int o = threadIdx.x; o < n; o += NM_NT) {
+      const int alb = o / RC, r = o - alb * RC;
+      const int a = alb / LB, rem = alb - a * LB, l = rem / Bo, b = rem - l * Bo;
+      const double* src = in + (a * sa + l * sl + b) * RC + r;
+      double acc = 0.0;
+      for (int i0 = 0; i0 < Q; i0 += IB) {
+        double v[IB];
+#pragma unroll
+        for (int k = 0; k < IB; ++k) v[k] = src[min(i0 + k, Q - 1) * si * RC];
+#pragma unroll
+        for (int k = 0; k < IB; ++k)
+          if (i0 + k < Q) acc = fma(v[k], Fm[(i0 + k) * RC + r], acc);
+      }
+      out[o] = acc;
+    }
+  }
+}
+
+// MTTKRP of mode n (b0 <= n < b1) from T, the summary contracted with the
+// factors of every mode outside the block [b0, b1) ([Q^(b1-b0)][RC], mode b0
+// slowest): M(q, r) = sum over the other modes of the block (at most two:
+// blocks hold at most three modes) of T times their factors.  All threads:
+// each output's terms are split into up to NM_NT / (Q R) chunks, summed in
+// order per chunk and the chunks added in order.  part: NM_NT doubles of LDS.
+template <int RC>
+__device__ void nm_mttkrp_block(const double* T, const double* Fl, double* M, double* part, int n,
+                                int b0, int b1, int Q, int R) {
+  const int tid = threadIdx.x, QR = Q * R, QRC = Q * RC;
+  int o0 = -1, o1 = -1, no = 0;
+  for (int m = b0; m < b1; ++m)
+    if (m != n) {
+      if (no == 0) o0 = m; else o1 = m;
+      ++no;
+    }
+  int st_n = 1, st0 = 0, st1 = 0, ncomb = 1;
+  for (int m = b1 - 1, st = 1; m >= b0; --m, st *= Q) {
+    if (m == n) st_n = st;
+    if (m == o0) st0 = st;
+    if (m == o1) st1 = st;
+  }
+  for (int k = 0; k < no; ++k) ncomb *= Q;
+  int nchunk = NM_NT / QR;
+  if (nchunk < 1) nchunk = 1;
+  if (nchunk > ncomb) nchunk = ncomb;
+  const int clen = (ncomb + nchunk - 1) / nchunk;
+  for (int base = 0; base < QR * nchunk; base += NM_NT) {
+    const int w = base + tid;
+    double s = 0.0;
+    if (w < QR * nchunk) {
+      const int o = w % QR, ch = w / QR;
+      const int q = o / R, r = o - q * R;
+      const int u0 = ch * clen;
+      const int u1 = u0 + clen < ncomb ? u0 + clen : ncomb;
+      const double* t = T + q * st_n * RC + r;
+      const double* f0 = Fl + (o0 >= 0 ? o0 : 0) * QRC + r;
+      const double* f1 = Fl + (o1 >= 0 ? o1 : 0) * QRC + r;
+      for (int u = u0; u < u1; ++u) {
+        const int d0 = no > 1 ? u / Q : u;
+        const int d1 = no > 1 ? u - d0 * Q : 0;
+        double pr = 1.0;
+        if (no > 0) pr *= f0[d0 * RC];
+        if (no > 1) pr *= f1[d1 * RC];
+        s = fma(t[(d0 * st0 + d1 * st1) * RC], pr, s);
+      }
+    }
+    if (nchunk > 1) {
+      part[tid] = s;
+      __syncthreads();
+      if (tid < QR) {
+        double v = 0.0;
+        for (int ch = 0; ch < nchunk; ++ch) v += part[ch * QR + tid];
+        M[tid] = v;
+      }
+    } else if (w < QR) {
+      M[w] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// One wavefront: the update of mode n from its MTTKRP M [Q][R]:
+//  - G = Hadamard product of the other modes' Grams, its inverse by
+//    Gauss-Jordan without pivoting on [G | I] held by columns in the lanes
+//    (lane c keeps column c; G padded to RMAX x RMAX with the identity, so the
+//    padding adds exact zeros),
+//  - F = M G^-1, its Gram, unit columns (nrm = the norms, from the Gram's
+//    diagonal) and the Gram of the unit columns.
+// work: 2 R^2 doubles of LDS.  *bad = 1 when a pivot is not positive.
+template <int RMAX>
+__device__ __forceinline__ void nm_mode_wave(const double* M_, double* Fl_, double* Gr_,
+                                             double* work_, double* nrm_, int n_, int N_, int Q_,
+                                             int R_, int* bad) {
+  constexpr int RC = RMAX;
+  const int lane = threadIdx.x & 63;
+  const int R = __builtin_amdgcn_readfirstlane(R_);
+  const int Q = __builtin_amdgcn_readfirstlane(Q_);
+  const int N = __builtin_amdgcn_readfirstlane(N_);
+  const int n = __builtin_amdgcn_readfirstlane(n_);
+  lds_f64* Fl = lds_uniform(Fl_);
+  lds_f64* Gr = lds_uniform(Gr_);
+  const lds_f64* M = lds_uniform(M_);
+  lds_f64* G = lds_uniform(work_);
+  lds_f64* Gi = G + R * R;
+  lds_f64* nrm = lds_uniform(nrm_);
+  const int RR = R * R, QR = Q * R, QRC = Q * RC;
+  for (int e = lane; e < RR; e += 64) {
+    double v = 1.0;
+    for (int m = 0; m < N; ++m)
+      if (m != n) v *= Gr[m * RR + e];
+    G[e] = v;
+  }
+  wave_sync();
+  double a[RMAX];
+#pragma unroll
+  for (int i = 0; i < RMAX; ++i) {
+    double v = 0.0;
+    if (lane < RMAX) {
+      if (i < R && lane < R) v = G[i * R + lane];
+      else if (i == lane) v = 1.0;
+    } else if (lane == RMAX + i) {
+      v = 1.0;
+    }
+    a[i] = v;
+  }
+  int badl = 0;
+#pragma unroll
+  for (int j = 0; j < RMAX; ++j) {
+    double col[RMAX];
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i) col[i] = lane_value(a[i], j);
+    double piv = col[j];
+    badl |= !(piv > 0.0);
+    piv = piv > 0.0 ? piv : 1e-300;
+    const double rj = a[j] * recip(piv);
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i)
+      if (i != j) a[i] = fma(-col[i], rj, a[i]);
+    a[j] = rj;
+  }
+  if (lane >= RMAX && lane < RMAX + R) {
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i)
+      if (i < R) Gi[i * R + (lane - RMAX)] = a[i];
+  }
+  if (lane == 0 && badl) *bad = 1;
+  wave_sync();
+  // F = M G^-1 (the loads of a row issued together)
+  lds_f64* Fn = Fl + n * QRC;
+  for (int e = lane; e < QR; e += 64) {
+    const int q = e / R, r = e - q * R;
+    double mv[RMAX], gv[RMAX];
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+      mv[k] = k < R ? M[q * R + k] : 0.0;
+      gv[k] = k < R ? Gi[k * R + r] : 0.0;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k)
+      if (k < R) s = fma(mv[k], gv[k], s);
+    Fn[q * RC + r] = s;
+  }
+  wave_sync();
+  // Gram of F, the norms from its diagonal, unit columns and their Gram
+  lds_f64* Gn = Gr + n * RR;
+  for (int e = lane; e < RR; e += 64) {
+    const int r1 = e / R, r2 = e - r1 * R;
+    double s = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < Q; ++q) s = fma(Fn[q * RC + r1], Fn[q * RC + r2], s);
+    G[e] = s;
+  }
+  wave_sync();
+  if (lane < R) {
+    const double v = sqrt(G[lane * R + lane]);
+    nrm[lane] = v > 0.0 ? v : 1.0;
+  }
+  wave_sync();
+  for (int e = lane; e < QR; e += 64) {
+    const int q = e / R, r = e - q * R;
+    Fn[q * RC + r] = Fn[q * RC + r] / nrm[r];
+  }
+  for (int e = lane; e < RR; e += 64) {
+    const int r1 = e / R, r2 = e - r1 * R;
+    Gn[e] = G[e] / (nrm[r1] * nrm[r2]);
+  }
+  wave_sync();
+}
+
+template <int RMAX>
+__device__ __noinline__ void nm_mode_call(const double* M, double* Fl, double* Gr, double* work,
+                                          double* nrm, int n, int N, int Q, int R, int* bad) {
+  nm_mode_wave<RMAX>(M, Fl, Gr, work, nrm, n, N, Q, R, bad);
+}
+
+// Rank-R CP of each replica by Gauss-Seidel ALS over the N modes (the N-mode
+// form of the replica ALS, Sec. 4.1), W workgroups per replica (a
+// cooperative launch when W > 1).  The MTTKRPs follow a dimension tree
+// split after mode nL = N/2: the summary contracted with the factors of
+// modes nL..N-1, one mode at a time, gives T_L [Q^nL][R], from which the
+// MTTKRPs of modes 0..nL-1 are short sums; after those modes are updated,
+// the summary contracted with their factors gives T_R [Q^(N-nL)][R] for
+// modes nL..N-1.  The workgroups of a replica split each contraction (T_L
+// by its rows, T_R by its columns; the partial contractions of a workgroup
+// stay its own), meet at one barrier per half-sweep, and then every one of
+// them runs the same mode updates on the same data (one wavefront,
+// nm_mode_wave), so that all keep identical factors.  lambda: the norms of
+// the last mode.
+template <int RC>
 __global__ __launch_bounds__(NM_NT) void nm_als_kernel(NmAlsArgs g) {
   extern __shared__ double sm[];
-  const int p = blockIdx.x, tid = threadIdx.x;
-  const int N = g.N, Q = g.Q, R = g.R, QR = Q * R, RR = R * R;
-  double* Fl = sm;                       // [N][Q][R]
-  double* M = Fl + N * QR;               // [Q][R]
-  double* Gr = M + QR;                   // [N][R][R] Grams
-  double* aug = Gr + N * RR;             // [R][R + Q]
-  double* part = aug + R * (R + Q);      // [NM_NT] chunk sums
+  const int W = g.W;
+  const int p = blockIdx.x / W, w = blockIdx.x - p * W, tid = threadIdx.x;
+  const int N = g.N, Q = g.Q, R = g.R, QRC = Q * RC, RR = R * R, QR = Q * R;
+  double* Fl = sm;                       // [N][Q][RC], zero beyond R
+  double* Gr = Fl + N * QRC;             // [N][R][R] Grams
+  double* Mb = Gr + N * RR;              // [Q][R] MTTKRP of the mode being updated
+  double* wk = Mb + QR;                  // [2 R^2] mode-update workspace
+  double* part = wk + 2 * RR;            // [NM_NT] chunk sums of the MTTKRP
   double* nrm = part + NM_NT;            // [R]
-  __shared__ int s_bad;
-  const double* Y = g.Y + (int64_t)p * g.QN;
-  for (int e = tid; e < N * QR; e += NM_NT) Fl[e] = g.init[(int64_t)p * N * QR + e];
+  double* Tl = nrm + R;                  // [TMAX] if t_lds
+  double* ldsA = Tl + (g.t_lds ? g.TMAX : 0);
+  __shared__ int s_bad, s_ok;
+  const double* Y = g.Y + (int64_t)p * g.QN1 * Q;
+  const int nL = N / 2;
+  int qpow[OCTEN_NM_MAX_MODES_K + 1];
+  qpow[0] = 1;
+  for (int k = 1; k <= OCTEN_NM_MAX_MODES_K; ++k) qpow[k] = qpow[k - 1] * Q;
+  double* TLg = g.work + (int64_t)p * g.work_stride;          // [Q^nL][RC]
+  double* TRg = TLg + (int64_t)qpow[nL] * RC;                 // [Q^(N-nL)][RC]
+  double* bufA;
+  if (g.inter_lds) {
+    bufA = ldsA;
+  } else {
+    bufA = TRg + (int64_t)qpow[N - nL] * RC + (int64_t)w * (g.SA + g.SB);
+  }
+  double* bufB = bufA + g.SA;
+  // this workgroup's rows of T_L and columns of T_R
+  const int nrow = qpow[nL], ncol = qpow[N - nL];
+  const int a0 = (int)((int64_t)nrow * w / W), a1 = (int)((int64_t)nrow * (w + 1) / W);
+  const int c0 = (int)((int64_t)ncol * w / W), c1 = (int)((int64_t)ncol * (w + 1) / W);
+  for (int e = tid; e < N * QRC; e += NM_NT) {
+    const int m = e / QRC, rem = e - m * QRC, q = rem / RC, r = rem - q * RC;
+    Fl[e] = r < R ? g.init[(int64_t)p * N * QR + m * QR + q * R + r] : 0.0;
+  }
   if (tid == 0) s_bad = 0;
   if (tid < R) nrm[tid] = 1.0;
   __syncthreads();
@@ -119,121 +456,86 @@ __global__ __launch_bounds__(NM_NT) void nm_als_kernel(NmAlsArgs g) {
     for (int e = tid; e < RR; e += NM_NT) {
       const int r1 = e / R, r2 = e - r1 * R;
       double s = 0.0;
-      for (int q = 0; q < Q; ++q) s = fma(Fl[m * QR + q * R + r1], Fl[m * QR + q * R + r2], s);
+      for (int q = 0; q < Q; ++q) s = fma(Fl[m * QRC + q * RC + r1], Fl[m * QRC + q * RC + r2], s);
       Gr[m * RR + e] = s;
     }
   __syncthreads();
-  const int nchunk = QR >= NM_NT ? 1 : NM_NT / QR;
-  const int64_t clen = (g.QN1 + nchunk - 1) / nchunk;
-  for (int it = 0; it < g.iters; ++it) {
-    for (int n = 0; n < N; ++n) {
-      // MTTKRP: output o = (q, r), chunk ch of the other indices
-      for (int base = 0; base < QR * nchunk; base += NM_NT) {
-        const int w = base + tid;
-        double s = 0.0;
-        if (w < QR * nchunk) {
-          const int o = w % QR, ch = w / QR;
-          const int q = o / R, r = o - q * R;
-          const int64_t e0 = (int64_t)ch * clen;
-          const int64_t e1 = e0 + clen < g.QN1 ? e0 + clen : g.QN1;
-          for (int64_t e = e0; e < e1; ++e) {
-            // digits of the other modes (mode N-1 fastest), offset in Y
-            int64_t rem = e, off = 0, stride = 1;
-            double pr = 1.0;
-            for (int m = N - 1; m >= 0; --m) {
-              int dgt;
-              if (m == n) {
-                dgt = q;
-              } else {
-                const int64_t nx = rem / Q;
-                dgt = (int)(rem - nx * Q);
-                rem = nx;
-                pr *= Fl[m * QR + dgt * R + r];
-              }
-              off += dgt * stride;
-              stride *= Q;
-            }
-            s = fma(Y[off], pr, s);
-          }
+  bool alive = true;
+  unsigned nbar = 0;
+  for (int it = 0; it < g.iters && alive; ++it) {
+    for (int side = 0; side < 2 && alive; ++side) {
+      const int b0 = side == 0 ? 0 : nL, b1 = side == 0 ? nL : N;
+      double* Tg = side == 0 ? TLg : TRg;
+      if (side == 0) {
+        // modes nL..N-1 contracted, the first remaining one each time, on
+        // rows [a0, a1) of T_L
+        const int cnt = a1 - a0;
+        const double* src = Y;
+        double* dst = bufA;
+        for (int m = nL; m < N; ++m) {
+          const int post = qpow[N - 1 - m];
+          const bool first = m == nL;
+          if (m == N - 1) dst = TLg + (int64_t)a0 * RC;
+          nm_contract<RC>(first ? Y + (int64_t)a0 * Q * post : src, first, cnt, 1, post, Q * post,
+                          post, 0, Q, Fl + m * QRC, dst);
+          __syncthreads();
+          src = dst;
+          dst = dst == bufA ? bufB : bufA;
         }
-        part[tid] = s;
-        __syncthreads();
-        if (tid < QR && base == 0) {
-          double t = 0.0;
-          for (int ch = 0; ch < nchunk; ++ch) t += part[ch * QR + tid];
-          M[tid] = t;
-        } else if (w < QR * nchunk && nchunk == 1) {
-          M[w] = s;
+      } else {
+        // modes 0..nL-1 contracted on columns [c0, c1) of T_R
+        const int cnt = c1 - c0;
+        const double* src = Y;
+        double* dst = bufA;
+        for (int m = 0; m < nL; ++m) {
+          const int Lk = qpow[nL - 1 - m];
+          const bool first = m == 0;
+          if (m == nL - 1) dst = TRg + (int64_t)c0 * RC;
+          if (first)
+            nm_contract<RC>(Y + c0, true, 1, Lk, cnt, 0, Lk * ncol, ncol, Q, Fl + m * QRC, dst);
+          else
+            nm_contract<RC>(src, false, 1, Lk, cnt, 0, Lk * cnt, cnt, Q, Fl + m * QRC, dst);
+          __syncthreads();
+          src = dst;
+          dst = dst == bufA ? bufB : bufA;
         }
-        __syncthreads();
       }
-      // [G | M^T] with G the Hadamard product of the other Grams
-      for (int e = tid; e < R * (R + Q); e += NM_NT) {
-        const int i = e / (R + Q), c = e - i * (R + Q);
-        double v;
-        if (c < R) {
-          v = 1.0;
-          for (int m = 0; m < N; ++m)
-            if (m != n) v *= Gr[m * RR + i * R + c];
-        } else {
-          v = M[(c - R) * R + i];
-        }
-        aug[e] = v;
+      if (W > 1) {
+        nbar += (unsigned)W;
+        alive = nm_barrier(g.ctr + p, nbar, g.err, &s_ok);
+        if (!alive) break;
       }
-      __syncthreads();
-      for (int j = 0; j < R; ++j) {
-        double piv = aug[j * (R + Q) + j];
-        if (!(piv > 0.0)) {
-          if (tid == 0) s_bad = 1;
-          piv = 1e-300;
-        }
-        const double rp = 1.0 / piv;
-        // every thread reads the pivot row and its own column's factors
-        // before the barrier, then writes
-        double vals[4];
-        int cnt = 0;
-        for (int e = tid; e < R * (R + Q); e += NM_NT) {
-          const int i = e / (R + Q), c = e - i * (R + Q);
-          const double pj = aug[j * (R + Q) + c] * rp;
-          vals[cnt < 4 ? cnt : 3] = (i == j) ? pj : aug[e] - aug[i * (R + Q) + j] * pj;
-          ++cnt;
+      const int tlen = qpow[b1 - b0] * RC;
+      const double* T = Tg;
+      if (g.t_lds) {
+        for (int e0 = tid; e0 < tlen; e0 += 4 * NM_NT) {
+          double v[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) v[k] = e0 + k * NM_NT < tlen ? Tg[e0 + k * NM_NT] : 0.0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (e0 + k * NM_NT < tlen) Tl[e0 + k * NM_NT] = v[k];
         }
         __syncthreads();
-        cnt = 0;
-        for (int e = tid; e < R * (R + Q); e += NM_NT) {
-          aug[e] = vals[cnt < 4 ? cnt : 3];
-          ++cnt;
+        T = Tl;
+      }
+      for (int n = b0; n < b1; ++n) {
+        nm_mttkrp_block<RC>(T, Fl, Mb, part, n, b0, b1, Q, R);
+        if (tid < 64) {
+          if constexpr (RC >= 16)
+            nm_mode_call<RC>(Mb, Fl, Gr, wk, nrm, n, N, Q, R, &s_bad);
+          else
+            nm_mode_wave<RC>(Mb, Fl, Gr, wk, nrm, n, N, Q, R, &s_bad);
         }
         __syncthreads();
       }
-      // F_n = (M G^-1), unit columns
-      double* Fn = Fl + n * QR;
-      for (int e = tid; e < QR; e += NM_NT) {
-        const int q = e / R, r = e - q * R;
-        Fn[e] = aug[r * (R + Q) + R + q];
-      }
-      __syncthreads();
-      if (tid < R) {
-        double s = 0.0;
-        for (int q = 0; q < Q; ++q) s = fma(Fn[q * R + tid], Fn[q * R + tid], s);
-        const double v = sqrt(s);
-        nrm[tid] = v > 0.0 ? v : 1.0;
-      }
-      __syncthreads();
-      for (int e = tid; e < QR; e += NM_NT) Fn[e] /= nrm[e % R];
-      __syncthreads();
-      for (int e = tid; e < RR; e += NM_NT) {
-        const int r1 = e / R, r2 = e - r1 * R;
-        double s = 0.0;
-        for (int q = 0; q < Q; ++q) s = fma(Fn[q * R + r1], Fn[q * R + r2], s);
-        Gr[n * RR + e] = s;
-      }
-      __syncthreads();
     }
   }
+  if (w != 0) return;
   int nf = 0;
   for (int e = tid; e < N * QR; e += NM_NT) {
-    const double v = Fl[e];
+    const int m = e / QR, rem = e - m * QR, q = rem / R, r = rem - q * R;
+    const double v = Fl[m * QRC + q * RC + r];
     nf |= isfinite(v) ? 0 : 1;
     g.F[(int64_t)p * N * QR + e] = v;
   }
@@ -243,6 +545,7 @@ __global__ __launch_bounds__(NM_NT) void nm_als_kernel(NmAlsArgs g) {
   }
   if (nf) atomicOr(g.flags + p, 4);
   if (tid == 0 && s_bad) atomicOr(g.flags + p, 1);
+  if (tid == 0 && !alive) atomicOr(g.flags + p, 2);
 }
 
 // Exclusive greedy assignment on sim (R x R, LDS) by one thread: the largest
@@ -503,24 +806,106 @@ hipError_t nm_temporal(hipStream_t s, const double* T, int64_t t_stride, int64_t
   return hipGetLastError();
 }
 
-size_t nm_als_lds_bytes(int N, int Q, int R) {
-  return (size_t)((size_t)N * Q * R + (size_t)Q * R + (size_t)N * R * R + (size_t)R * (R + Q) +
-                  NM_NT + R) * 8;
+static int nm_rc(int R) { return R <= 8 ? 8 : (R <= 16 ? 16 : 32); }
+
+namespace {
+struct NmAlsPlan {
+  int W, inter_lds, t_lds, SA, SB, TMAX;
+  size_t lds;
+  int64_t work;   // doubles per replica
+};
+
+int64_t ipow64(int64_t b, int e) {
+  int64_t v = 1;
+  for (int i = 0; i < e; ++i) v *= b;
+  return v;
+}
+
+// Workgroups per replica and the place of the intermediates for one launch.
+NmAlsPlan nm_plan(int N, int Q, int R, int W) {
+  NmAlsPlan pl{};
+  const int RC = nm_rc(R);
+  const int nL = N / 2;
+  const int64_t nrow = ipow64(Q, nL), ncol = ipow64(Q, N - nL);
+  pl.W = W;
+  const int64_t crow = (nrow + W - 1) / W, ccol = (ncol + W - 1) / W;
+  // first and second contraction of either half, for the largest share
+  const int64_t sa = std::max(crow * ipow64(Q, N - 1 - nL), ipow64(Q, nL - 1) * ccol) * RC;
+  const int64_t sb = std::max(N - nL >= 3 ? crow * ipow64(Q, N - 2 - nL) : 0,
+                              nL >= 3 ? ipow64(Q, nL - 2) * ccol : 0) * RC;
+  pl.SA = (int)sa;
+  pl.SB = (int)sb;
+  pl.TMAX = (int)(std::max(nrow, ncol) * RC);
+  const size_t base = ((size_t)N * Q * RC + (size_t)N * R * R + (size_t)Q * R +
+                       2 * (size_t)R * R + NM_NT + R) * 8;
+  const size_t cap = 160 * 1024 - 64;
+  size_t lds = base;
+  pl.t_lds = (lds + (size_t)pl.TMAX * 8 <= cap) ? 1 : 0;
+  if (pl.t_lds) lds += (size_t)pl.TMAX * 8;
+  pl.inter_lds = (lds + (size_t)(sa + sb) * 8 <= cap) ? 1 : 0;
+  if (pl.inter_lds) lds += (size_t)(sa + sb) * 8;
+  pl.lds = lds;
+  pl.work = (nrow + ncol) * RC + (pl.inter_lds ? 0 : (int64_t)W * (sa + sb));
+  return pl;
+}
+
+// Workgroups per replica: up to 8, at most one workgroup per CU over all
+// replicas, no more than the rows of T_L or the columns of T_R.
+int nm_pick_w(int P, int N, int Q) {
+  const int nL = N / 2;
+  int W = 256 / (P > 0 ? P : 1);
+  W = W < 8 ? W : 8;
+  const int64_t nrow = ipow64(Q, nL);
+  if (W > nrow) W = (int)nrow;
+  return W < 2 ? 1 : W;
+}
+}  // namespace
+
+size_t nm_als_lds_bytes(int N, int Q, int R) { return nm_plan(N, Q, R, 1).lds; }
+
+int64_t nm_als_work_len(int N, int Q, int R, int P) {
+  const int W = nm_pick_w(P, N, Q);
+  return std::max(nm_plan(N, Q, R, W).work, nm_plan(N, Q, R, 1).work);
 }
 
 hipError_t nm_als(hipStream_t s, const double* Y, int P, int N, int Q, int R, const double* init,
-                  double* F, double* lam, int* flags, int iters) {
+                  double* F, double* lam, int* flags, int iters, double* work, unsigned* ctr,
+                  int* err) {
+  if (N < 3 || N > OCTEN_NM_MAX_MODES_K || ipow64(Q, N) > (1LL << 22) || R > 32 || R > Q || R < 1)
+    return hipErrorInvalidValue;
   NmAlsArgs a;
-  a.Y = Y; a.init = init; a.F = F; a.lam = lam; a.flags = flags;
+  a.Y = Y; a.init = init; a.F = F; a.lam = lam; a.flags = flags; a.work = work;
+  a.ctr = ctr; a.err = err;
   a.N = N; a.Q = Q; a.R = R; a.iters = iters;
-  int64_t qn = 1;
-  for (int n = 0; n < N - 1; ++n) qn *= Q;
-  a.QN1 = qn;
-  a.QN = qn * Q;
-  const size_t lds = nm_als_lds_bytes(N, Q, R);
-  if (lds > 160 * 1024 || (int64_t)R * (R + Q) > 4 * NM_NT) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(nm_als_kernel, dim3(P), dim3(NM_NT), lds, s, a);
-  return hipGetLastError();
+  a.QN1 = (int)ipow64(Q, N - 1);
+  a.work_stride = nm_als_work_len(N, Q, R, P);
+  const int rc = nm_rc(R);
+  const void* fn = rc == 8 ? (const void*)nm_als_kernel<8>
+                           : (rc == 16 ? (const void*)nm_als_kernel<16> : (const void*)nm_als_kernel<32>);
+  int W = nm_pick_w(P, N, Q);
+  if (W > 1) {
+    const NmAlsPlan pl = nm_plan(N, Q, R, W);
+    a.W = W; a.inter_lds = pl.inter_lds; a.t_lds = pl.t_lds; a.SA = pl.SA; a.SB = pl.SB;
+    a.TMAX = pl.TMAX;
+    hipError_t e = fill_i32(s, (int*)ctr, P, 0);
+    if (e == hipSuccess) e = fill_i32(s, err, 1, 0);
+    if (e == hipSuccess && pl.lds <= 160 * 1024 - 64)
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
+    if (e == hipSuccess && pl.lds <= 160 * 1024 - 64) {
+      void* args[] = {&a};
+      e = hipLaunchCooperativeKernel(fn, dim3(P * W), dim3(NM_NT), args, (unsigned)pl.lds, s);
+      if (e == hipSuccess) return hipSuccess;
+    }
+    (void)hipGetLastError();   // no cooperative launch here: one workgroup per replica
+  }
+  const NmAlsPlan pl = nm_plan(N, Q, R, 1);
+  if (pl.lds > 160 * 1024 - 64) return hipErrorInvalidValue;
+  a.W = 1; a.inter_lds = pl.inter_lds; a.t_lds = pl.t_lds; a.SA = pl.SA; a.SB = pl.SB;
+  a.TMAX = pl.TMAX;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
+  if (e != hipSuccess) return e;
+  void* args[] = {&a};
+  return hipLaunchKernel(fn, dim3(P), dim3(NM_NT), args, pl.lds, s);
 }
 
 hipError_t nm_align(hipStream_t s, const double* F, const double* lam, int P, int N, int Q, int R,

@@ -42,6 +42,9 @@ struct octen_nm_ctx {
   // ALS
   double *F = nullptr, *lam = nullptr, *F0 = nullptr, *lam0 = nullptr;
   int *flags = nullptr, *zbad = nullptr, *health = nullptr;
+  double* als_work = nullptr;               // [P][nm_als_work_len] partial contractions
+  unsigned* als_ctr = nullptr;              // [P] barrier counters of the ALS launch
+  int* als_err = nullptr;                   // [1] a barrier of the ALS launch timed out
   // recovery
   double *aligned = nullptr, *margin = nullptr, *rhs = nullptr, *rhs_c = nullptr;
   int* perm = nullptr;
@@ -135,11 +138,11 @@ octen_status validate(const octen_nm_config* c, std::string* msg) {
     }
   const int64_t M1 = (int64_t)c->S + (int64_t)c->P * (c->Q - c->S);
   if (M1 > (1 << 20)) { *msg = "too many compression columns"; return OCTEN_ERR_ARG; }
-  // the replica ALS keeps one replica's factors, Grams and [G | M^T] in the
-  // LDS of one workgroup
-  if (c->Q > 32 || ipow(c->Q, c->N) > (1LL << 22) || (int64_t)c->R * (c->R + c->Q) > 1024 ||
-      nm_als_lds_bytes(c->N, c->Q, c->R) > 160 * 1024) {
-    *msg = "sizes outside the N-mode limits (Q <= 32, Q^N <= 2^22, R (R + Q) <= 1024)";
+  // the replica ALS keeps one replica's factors and Grams in the LDS of one
+  // workgroup
+  if (c->Q > 32 || ipow(c->Q, c->N) > (1LL << 22) ||
+      nm_als_lds_bytes(c->N, c->Q, c->R) > 160 * 1024 - 64) {
+    *msg = "sizes outside the N-mode limits (Q <= 32, Q^N <= 2^22)";
     return OCTEN_ERR_UNSUPPORTED;
   }
   return OCTEN_OK;
@@ -236,6 +239,9 @@ octen_status octen_nm_init(const octen_nm_config* cfg, const double* const* U, v
   IOK(dalloc(h, &h->lam, P * R));
   IOK(dalloc(h, &h->F0, P * N * Q * R));
   IOK(dalloc(h, &h->lam0, P * R));
+  IOK(dalloc(h, &h->als_work, P * nm_als_work_len((int)N, (int)Q, (int)R, (int)P)));
+  IOK(dalloc(h, &h->als_ctr, P));
+  IOK(dalloc(h, &h->als_err, 1));
   IOK(dalloc(h, &h->flags, P));
   IOK(dalloc(h, &h->zbad, P));
   IOK(dalloc(h, &h->health, 1));
@@ -411,7 +417,8 @@ octen_status octen_nm_cp_als_replicas(octen_nm_t h, int32_t iters, int32_t init_
   else
     NMCHK(h, hipMemcpyAsync(h->lam0, h->lam, (size_t)h->P * h->R * 8, hipMemcpyDeviceToDevice, s));
   NMCHK(h, fill_i32(s, h->flags, h->P, 0));
-  NMCHK(h, nm_als(s, h->Y, h->P, h->N, h->Q, h->R, src, h->F, h->lam, h->flags, iters));
+  NMCHK(h, nm_als(s, h->Y, h->P, h->N, h->Q, h->R, src, h->F, h->lam, h->flags, iters,
+                  h->als_work, h->als_ctr, h->als_err));
   NMCHK(h, als_commit(s, h->P, (int)per, h->R, h->F, h->lam, h->F0, h->lam0, h->flags, h->health));
   h->have_factors = true;
   h->factors_fresh = true;

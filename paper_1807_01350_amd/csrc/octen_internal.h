@@ -266,11 +266,16 @@ hipError_t nm_ttm(hipStream_t s, const double* in, int64_t in_stride, int64_t pr
 // non-finite value
 hipError_t nm_temporal(hipStream_t s, const double* T, int64_t t_stride, int64_t t, int64_t L,
                        const double* W, int M1, int P, int Q, int S, double* Z, int* zbad);
-// Replica ALS, one workgroup per replica, fixed sweeps; hipErrorInvalidValue
-// when the LDS image or the solve's [G | M^T] does not fit
+// Replica ALS, fixed sweeps, several workgroups per replica (cooperative
+// launch; one workgroup per replica where that launch is not possible);
+// hipErrorInvalidValue when the LDS image does not fit.  work:
+// P * nm_als_work_len(N, Q, R, P) doubles (contracted summaries and partial
+// contractions); ctr: [P] barrier counters, err: [1] (both cleared here).
 size_t nm_als_lds_bytes(int N, int Q, int R);
+int64_t nm_als_work_len(int N, int Q, int R, int P);
 hipError_t nm_als(hipStream_t s, const double* Y, int P, int N, int Q, int R, const double* init,
-                  double* F, double* lam, int* flags, int iters);
+                  double* F, double* lam, int* flags, int iters, double* work, unsigned* ctr,
+                  int* err);
 // lambda^(1/N) on every mode and the anchor matching to replica 0
 hipError_t nm_align(hipStream_t s, const double* F, const double* lam, int P, int N, int Q, int R,
                     int S, double* aligned, int* perm, double* margin);

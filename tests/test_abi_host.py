@@ -107,9 +107,9 @@ def test_nm_limits_rejected(oc):
     cfg = oc.make_nm_config((30, 30, 30, 30, 30), 5, 4, 13, 3)
     st, h = oc.octen_nm_init(cfg, [1] * 5, None)
     assert st == oc.OCTEN_ERR_UNSUPPORTED and not h.value
-    # R (R + Q) above 1024 (the solve's [G | M^T] in LDS)
-    cfg = oc.make_nm_config((30, 30, 30), 20, 4, 32, 3)
-    st, h = oc.octen_nm_init(cfg, [1] * 3, None)
+    # Q^N above 2^22 at N = 5 (22^5)
+    cfg = oc.make_nm_config((30, 30, 30, 30), 5, 4, 22, 3)
+    st, h = oc.octen_nm_init(cfg, [1] * 4, None)
     assert st == oc.OCTEN_ERR_UNSUPPORTED and not h.value
     cfg = oc.make_nm_config((30, 0, 30), 5, 4, 12, 3)
     st, h = oc.octen_nm_init(cfg, [1] * 3, None)

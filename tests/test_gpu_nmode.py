@@ -48,6 +48,11 @@ CASES = [
     NCase("n4_ragged", (40, 33, 7), 3, 2, 9, 2, (20, 1, 17), 25, config_id=45),
     # rank one, one anchor column
     NCase("n4_rank1", (11, 10, 9), 1, 3, 5, 1, (6, 6), 15, config_id=46),
+    # 130 replicas: one workgroup per replica (no cooperative launch)
+    NCase("n3_many", (6, 5), 2, 130, 5, 2, (5, 3), 10, config_id=49),
+    # the benchmark's four-mode stream at full size (100^3 slices, P = 10
+    # replicas of 16^4, 50 sweeps): its first two batches, every output
+    NCase("nmode4_full", (100, 100, 100), 5, 10, 16, 4, (20, 10), 50, config_id=50),
 ]
 
 
