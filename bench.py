@@ -1159,14 +1159,15 @@ def run_nmode(args):
         "roofline": {"bound": "alu", "achieved": round(als_tf, 4), "peak": 78.6,
                      "unit": "TFLOP/s", "frac": round(als_tf / 78.6, 6), "traffic": None,
                      "kernel": "nm_als_kernel (4 Q^N R flop per replica and sweep, FP64 vector "
-                               "arithmetic, one workgroup per replica)"},
+                               "arithmetic; up to 8 cooperative workgroups per replica); timed "
+                               "with the ALS call's small commit kernels"},
         "roofline_compression": {"bound": "hbm",
                                  "achieved": round(comp_bytes / (ms["compress"] * 1e-3) / 1e9, 2),
                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                  "frac": round(comp_bytes / (ms["compress"] * 1e-3) / 1e9
                                                / HBM_PEAK_GBS, 6),
-                                 "kernel": "compression of one batch (GEMM, gather, mode "
-                                           "products, temporal product)"},
+                                 "kernel": "compression of one batch (GEMM, mode products on "
+                                           "FP64 matrix cores, temporal product)"},
         "cpu_baseline": {"value": round(t * n_or / dt_or, 3), "unit": "slices/s",
                          "cores": cores_used(), "kind": "oracle",
                          "sample": f"{n_or} update batches of {t} slices of the same stream "

@@ -7,9 +7,10 @@
 //
 // Compression (supplement, compressed cubes): the last non-temporal mode is
 // contracted with all M1 compression columns at once (one GEMM, outside
-// these kernels), the columns of each replica are gathered, the remaining
-// non-temporal modes are contracted one by one (nm_ttm_kernel), and the
-// temporal mode last (nm_temporal_kernel, which flags non-finite values).
+// these kernels), the remaining non-temporal modes one by one on FP64 matrix
+// cores (nm_ttm_mfma_kernel, the first reading each replica's columns of the
+// GEMM output in place), and the temporal mode last (nm_temporal_kernel,
+// which flags non-finite values).
 // ALS: one workgroup per replica (nm_als_kernel).  Matching and stacking:
 // nm_align_kernel, nm_stack_kernel; pairing with the previous batch:
 // nm_tmatch_kernel.  Fit: nm_fit_kernel + nm_fit_reduce.
@@ -30,37 +31,59 @@ __device__ __forceinline__ int rep_col(int p, int q, int Q, int S) {
   return q < S ? q : S + p * (Q - S) + (q - S);
 }
 
-// out[p][row][q] = T[row][col_p(q)]
-__global__ void nm_gather_kernel(const double* __restrict__ T, int64_t rows, int M1, int P, int Q,
-                                 int S, double* __restrict__ out) {
-  const int p = blockIdx.y;
-  const int64_t n = rows * Q;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = e / Q;
-    const int q = (int)(e - row * Q);
-    out[(int64_t)p * n + e] = T[row * M1 + rep_col(p, q, Q, S)];
-  }
-}
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// out[p][pre][q][post] = sum_i in[p][pre][i][post] U[i][col_p(q)]
-__global__ void nm_ttm_kernel(const double* __restrict__ in, int64_t in_stride, int64_t pre,
-                              int64_t d, int64_t post, const double* __restrict__ U, int M1, int P,
-                              int Q, int S, double* __restrict__ out, int64_t out_stride) {
-  const int p = blockIdx.y;
-  const int64_t n = pre * Q * post;
-  const double* src = in + (int64_t)p * in_stride;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t a = e / (Q * post);
-    const int64_t rem = e - a * Q * post;
-    const int q = (int)(rem / post);
-    const int64_t b = rem - (int64_t)q * post;
-    const int col = rep_col(p, q, Q, S);
-    const double* x = src + a * d * post + b;
-    double s = 0.0;
-    for (int64_t i = 0; i < d; ++i) s = fma(x[i * post], U[i * M1 + col], s);
-    out[(int64_t)p * out_stride + e] = s;
+// Mode product on FP64 matrix cores: out[p][a][q][b] = sum_i
+// in(p, a, i, b) U[i][col_p(q)] for a < pre, q < Q, b < post, i < d.  One
+// wavefront per 16 x 16 tile of (q, b) of one (p, a), K steps of 4 on
+// v_mfma_f64_16x16x4f64 (lane l supplies A[l%16][l/16] = U[i][col_p(q)] and
+// B[l/16][l%16] = in(p, a, i, b); element k of the result is
+// D[l/16 + 4k][l%16]); indexes past Q, post or d read zero.  in(p, a, i, b)
+// is in[(a d + i) M1 + col_p(b)] when `cols` (the product of X with all M1
+// compression columns of the next mode, shared by the replicas), else
+// in[p in_stride + (a d + i) post + b].
+__global__ __launch_bounds__(256) void nm_ttm_mfma_kernel(
+    const double* __restrict__ in, int64_t in_stride, bool cols, int64_t pre, int d, int post,
+    const double* __restrict__ U, int M1, int P, int Q, int S, double* __restrict__ out,
+    int64_t out_stride, int nqb, int nbb, int64_t ntiles) {
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= ntiles) return;
+  const int bb = (int)(tile % nbb);
+  int64_t rest = tile / nbb;
+  const int qb = (int)(rest % nqb);
+  rest /= nqb;
+  const int64_t a = rest % pre;
+  const int p = (int)(rest / pre);
+  const int li = lane >> 4, lj = lane & 15;
+  const int qa = qb * 16 + lj;                 // A row (q) of this lane
+  const int bn = bb * 16 + lj;                 // B column (b) of this lane
+  const bool qok = qa < Q, bok = bn < post;
+  const int ucol = qok ? rep_col(p, qa, Q, S) : 0;
+  const double* src;
+  int64_t istep;
+  if (cols) {
+    src = in + (a * d) * (int64_t)M1 + (bok ? rep_col(p, bn, Q, S) : 0);
+    istep = M1;
+  } else {
+    src = in + (int64_t)p * in_stride + (a * d) * (int64_t)post + (bok ? bn : 0);
+    istep = post;
+  }
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int i0 = 0; i0 < d; i0 += 4) {
+    const int i = i0 + li;
+    const bool iok = i < d;
+    const double av = (iok && qok) ? U[(int64_t)i * M1 + ucol] : 0.0;
+    const double bv = (iok && bok) ? src[(int64_t)i * istep] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  }
+  if (bok) {
+    double* dst = out + (int64_t)p * out_stride + (a * Q) * (int64_t)post + bn;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int q = qb * 16 + li + 4 * k;
+      if (q < Q) dst[(int64_t)q * post] = acc[k];
+    }
   }
 }
 
@@ -768,12 +791,29 @@ __global__ __launch_bounds__(NM_NT) void nm_fit_kernel(NmFitArgs g) {
   }
 }
 
-__global__ void nm_fit_reduce(const double* __restrict__ partials, int nb, double* __restrict__ out) {
+// out = (sum of partials[0..nb), sum of partials[nb..2 nb)), a fixed order:
+// strided per-thread sums, then a tree
+__global__ __launch_bounds__(256) void nm_fit_reduce(const double* __restrict__ partials, int nb,
+                                                     double* __restrict__ out) {
+  __shared__ double s_a[256], s_b[256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    a += partials[i];
+    b += partials[nb + i];
+  }
+  s_a[threadIdx.x] = a;
+  s_b[threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      s_a[threadIdx.x] += s_a[threadIdx.x + st];
+      s_b[threadIdx.x] += s_b[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
-    double a = 0.0, b = 0.0;
-    for (int i = 0; i < nb; ++i) { a += partials[i]; b += partials[nb + i]; }
-    out[0] = a;
-    out[1] = b;
+    out[0] = s_a[0];
+    out[1] = s_b[0];
   }
 }
 
@@ -784,18 +824,15 @@ unsigned grid_of(int64_t n) {
 
 }  // namespace
 
-hipError_t nm_gather(hipStream_t s, const double* T, int64_t rows, int M1, int P, int Q, int S,
-                     double* out) {
-  hipLaunchKernelGGL(nm_gather_kernel, dim3(grid_of(rows * Q), P), dim3(256), 0, s, T, rows, M1, P,
-                     Q, S, out);
-  return hipGetLastError();
-}
-
-hipError_t nm_ttm(hipStream_t s, const double* in, int64_t in_stride, int64_t pre, int64_t d,
-                  int64_t post, const double* U, int M1, int P, int Q, int S, double* out,
-                  int64_t out_stride) {
-  hipLaunchKernelGGL(nm_ttm_kernel, dim3(grid_of(pre * Q * post), P), dim3(256), 0, s, in,
-                     in_stride, pre, d, post, U, M1, P, Q, S, out, out_stride);
+hipError_t nm_ttm_mfma(hipStream_t s, const double* in, int64_t in_stride, bool cols, int64_t pre,
+                       int d, int post, const double* U, int M1, int P, int Q, int S, double* out,
+                       int64_t out_stride) {
+  const int nqb = (Q + 15) / 16, nbb = (post + 15) / 16;
+  const int64_t ntiles = (int64_t)P * pre * nqb * nbb;
+  const int64_t blocks = (ntiles + 3) / 4;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(nm_ttm_mfma_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, in_stride,
+                     cols, pre, d, post, U, M1, P, Q, S, out, out_stride, nqb, nbb, ntiles);
   return hipGetLastError();
 }
 
@@ -955,7 +992,7 @@ hipError_t nm_fit(hipStream_t s, const double* X, int64_t t, const int64_t* dims
   if (nb > nparts) nb = nparts;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(nm_fit_kernel, dim3((unsigned)nb), dim3(NM_NT), 0, s, g);
-  hipLaunchKernelGGL(nm_fit_reduce, dim3(1), dim3(64), 0, s, partials, (int)nb, out2);
+  hipLaunchKernelGGL(nm_fit_reduce, dim3(1), dim3(256), 0, s, partials, (int)nb, out2);
   return hipGetLastError();
 }
 

@@ -319,8 +319,9 @@ const char* octen_nm_last_error(octen_nm_t h) { return h ? h->err.c_str() : "nul
 
 // Supplement, compressed cubes: the last non-temporal mode against all M1
 // compression columns at once (one GEMM, the shared columns computed once),
-// the columns of each replica gathered, the other non-temporal modes
-// contracted from the last to the first, the temporal mode with W_p last.
+// the other non-temporal modes contracted from the last to the first on FP64
+// matrix cores (the first of them reading each replica's columns of the GEMM
+// output in place), the temporal mode with W_p last.
 octen_status octen_nm_compress_batch(octen_nm_t h, const double* X, int64_t t, const double* W) {
   if (!h) return OCTEN_ERR_ARG;
   if (!X || !W || t < 1) return fail(h, OCTEN_ERR_ARG, "X, W must be non-null and t >= 1");
@@ -331,15 +332,15 @@ octen_status octen_nm_compress_batch(octen_nm_t h, const double* X, int64_t t, c
   int64_t rows = t;   // t * I_1 * ... * I_{N-2}
   for (int n = 0; n < nm - 1; ++n) rows *= h->dims[n];
   if (rows > 0x7fffffffLL) return fail(h, OCTEN_ERR_ARG, "batch too large (t * I_1 ... I_{N-2})");
-  // workspace: the largest per-replica intermediate over the contraction steps
+  // workspace: the largest per-replica intermediate of the mode products
+  // (after mode N-2: t I_1 ... I_{N-3} Q^2, then smaller)
   int64_t big = 0;
   {
-    int64_t pre = rows, post = Q;   // after the gather: [pre][Q]
-    big = pre * post;
+    int64_t pre = rows, post = Q;
     for (int m = nm - 2; m >= 0; --m) {
       pre /= h->dims[m];
+      big = pre * Q * post > big ? pre * Q * post : big;
       post *= Q;
-      big = pre * post > big ? pre * post : big;
     }
   }
   NMOK(dgrow(h, &h->Wz, &h->Wz_cap, t * M1));
@@ -350,17 +351,20 @@ octen_status octen_nm_compress_batch(octen_nm_t h, const double* X, int64_t t, c
   NMCHK(h, fill_i32(s, h->zbad, P, 0));
   NMCHK(h, gemm_f64(s, (int)rows, M1, (int)Ilast, 1, X, Ilast, 1, 0, h->U[nm - 1], M1, 1, 0, h->T1,
                     M1, 1, 0, nullptr, 1.0, 0.0));
-  NMCHK(h, nm_gather(s, h->T1, rows, M1, P, Q, S, h->Ta));
-  double* cur = h->Ta;
-  double* nxt = h->Tb;
+  // the remaining non-temporal modes, last to first; the first product reads
+  // each replica's columns of T1 in place
+  const double* cur = h->T1;
+  double* nxt = h->Ta;
   int64_t pre = rows, post = Q;
   for (int m = nm - 2; m >= 0; --m) {
     const int64_t d = h->dims[m];
     pre /= d;
-    NMCHK(h, nm_ttm(s, cur, pre * d * post, pre, d, post, h->U[m], M1, P, Q, S, nxt,
-                    pre * Q * post));
+    const bool first = m == nm - 2;
+    NMCHK(h, nm_ttm_mfma(s, cur, first ? 0 : pre * d * post, first, pre, (int)d, (int)post,
+                         h->U[m], M1, P, Q, S, nxt, pre * Q * post));
     post *= Q;
-    std::swap(cur, nxt);
+    cur = nxt;
+    nxt = nxt == h->Ta ? h->Tb : h->Ta;
   }
   // cur: [P][t][Q^{N-1}]
   NMCHK(h, nm_temporal(s, cur, t * post, t, post, h->Wz, M1, P, Q, S, h->Z, h->zbad));

@@ -255,13 +255,14 @@ hipError_t fit_dense(hipStream_t s, const void* X, bool x_f64, int64_t t, int64_
 
 // ---------------------------------------------------------------- N-mode ---
 // Kernels of the N-mode extension (layouts in octen_nmode.h), FP64.
-// out[p][row][q] = T[row][col_p(q)] for rows x M1 input T
-hipError_t nm_gather(hipStream_t s, const double* T, int64_t rows, int M1, int P, int Q, int S,
-                     double* out);
-// out[p][a][q][b] = sum_i in[p][a][i][b] U[i][col_p(q)], a < pre, i < d, b < post
-hipError_t nm_ttm(hipStream_t s, const double* in, int64_t in_stride, int64_t pre, int64_t d,
-                  int64_t post, const double* U, int M1, int P, int Q, int S, double* out,
-                  int64_t out_stride);
+// out[p][a][q][b] = sum_i in(p, a, i, b) U[i][col_p(q)], a < pre, i < d,
+// b < post, on FP64 matrix cores (d, post < 2^31): in(p, a, i, b) is
+// in[p in_stride + (a d + i) post + b], or with `cols`
+// in[(a d + i) M1 + col_p(b)] (the product of X with all compression
+// columns of the next mode, shared by the replicas).
+hipError_t nm_ttm_mfma(hipStream_t s, const double* in, int64_t in_stride, bool cols, int64_t pre,
+                       int d, int post, const double* U, int M1, int P, int Q, int S, double* out,
+                       int64_t out_stride);
 // Z[p][x][c] = sum_k T[p][k][x] W[k][col_p(c)], x < L; zbad[p] |= 1 on a
 // non-finite value
 hipError_t nm_temporal(hipStream_t s, const double* T, int64_t t_stride, int64_t t, int64_t L,
