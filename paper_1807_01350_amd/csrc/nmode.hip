@@ -308,13 +308,14 @@ __device__ void nm_mttkrp_block(const double* T, const double* Fl, double* M, do
 }
 
 // One wavefront: the update of mode n from its MTTKRP M [Q][R]:
-//  - G = Hadamard product of the other modes' Grams, its inverse by
-//    Gauss-Jordan without pivoting on [G | I] held by columns in the lanes
-//    (lane c keeps column c; G padded to RMAX x RMAX with the identity, so the
-//    padding adds exact zeros),
-//  - F = M G^-1, its Gram, unit columns (nrm = the norms, from the Gram's
-//    diagonal) and the Gram of the unit columns.
-// work: 2 R^2 doubles of LDS.  *bad = 1 when a pivot is not positive.
+//  - G = Hadamard product of the other modes' Grams;
+//  - F^T = G^-1 M^T by Gauss-Jordan without pivoting on [G | M^T] held by
+//    columns in the lanes: lane c < RMAX keeps column c of G (padded to
+//    RMAX x RMAX with the identity, so the padding adds exact zeros), lane
+//    RMAX + q keeps row q of M; after the RMAX steps lane RMAX + q holds row
+//    q of F (Q + RMAX <= 64);
+//  - the Gram of F, the norms from its diagonal, unit columns and their Gram.
+// work: R^2 doubles of LDS.  *bad = 1 when a pivot is not positive.
 template <int RMAX>
 __device__ __forceinline__ void nm_mode_wave(const double* M_, double* Fl_, double* Gr_,
                                              double* work_, double* nrm_, int n_, int N_, int Q_,
@@ -329,9 +330,8 @@ __device__ __forceinline__ void nm_mode_wave(const double* M_, double* Fl_, doub
   lds_f64* Gr = lds_uniform(Gr_);
   const lds_f64* M = lds_uniform(M_);
   lds_f64* G = lds_uniform(work_);
-  lds_f64* Gi = G + R * R;
   lds_f64* nrm = lds_uniform(nrm_);
-  const int RR = R * R, QR = Q * R, QRC = Q * RC;
+  const int RR = R * R, QRC = Q * RC;
   for (int e = lane; e < RR; e += 64) {
     double v = 1.0;
     for (int m = 0; m < N; ++m)
@@ -339,6 +339,8 @@ __device__ __forceinline__ void nm_mode_wave(const double* M_, double* Fl_, doub
     G[e] = v;
   }
   wave_sync();
+  const int q = lane - RMAX;              // row of M / F held by this lane
+  const bool frow = q >= 0 && q < Q;
   double a[RMAX];
 #pragma unroll
   for (int i = 0; i < RMAX; ++i) {
@@ -346,8 +348,8 @@ __device__ __forceinline__ void nm_mode_wave(const double* M_, double* Fl_, doub
     if (lane < RMAX) {
       if (i < R && lane < R) v = G[i * R + lane];
       else if (i == lane) v = 1.0;
-    } else if (lane == RMAX + i) {
-      v = 1.0;
+    } else if (frow && i < R) {
+      v = M[q * R + i];
     }
     a[i] = v;
   }
@@ -366,37 +368,20 @@ __device__ __forceinline__ void nm_mode_wave(const double* M_, double* Fl_, doub
       if (i != j) a[i] = fma(-col[i], rj, a[i]);
     a[j] = rj;
   }
-  if (lane >= RMAX && lane < RMAX + R) {
+  if (lane == 0 && badl) *bad = 1;
+  lds_f64* Fn = Fl + n * QRC;
+  if (frow) {
 #pragma unroll
     for (int i = 0; i < RMAX; ++i)
-      if (i < R) Gi[i * R + (lane - RMAX)] = a[i];
-  }
-  if (lane == 0 && badl) *bad = 1;
-  wave_sync();
-  // F = M G^-1 (the loads of a row issued together)
-  lds_f64* Fn = Fl + n * QRC;
-  for (int e = lane; e < QR; e += 64) {
-    const int q = e / R, r = e - q * R;
-    double mv[RMAX], gv[RMAX];
-#pragma unroll
-    for (int k = 0; k < RMAX; ++k) {
-      mv[k] = k < R ? M[q * R + k] : 0.0;
-      gv[k] = k < R ? Gi[k * R + r] : 0.0;
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < RMAX; ++k)
-      if (k < R) s = fma(mv[k], gv[k], s);
-    Fn[q * RC + r] = s;
+      if (i < R) Fn[q * RC + i] = a[i];
   }
   wave_sync();
   // Gram of F, the norms from its diagonal, unit columns and their Gram
-  lds_f64* Gn = Gr + n * RR;
   for (int e = lane; e < RR; e += 64) {
     const int r1 = e / R, r2 = e - r1 * R;
     double s = 0.0;
 #pragma unroll 8
-    for (int q = 0; q < Q; ++q) s = fma(Fn[q * RC + r1], Fn[q * RC + r2], s);
+    for (int qq = 0; qq < Q; ++qq) s = fma(Fn[qq * RC + r1], Fn[qq * RC + r2], s);
     G[e] = s;
   }
   wave_sync();
@@ -405,10 +390,12 @@ __device__ __forceinline__ void nm_mode_wave(const double* M_, double* Fl_, doub
     nrm[lane] = v > 0.0 ? v : 1.0;
   }
   wave_sync();
-  for (int e = lane; e < QR; e += 64) {
-    const int q = e / R, r = e - q * R;
-    Fn[q * RC + r] = Fn[q * RC + r] / nrm[r];
+  if (frow) {
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i)
+      if (i < R) Fn[q * RC + i] = a[i] / nrm[i];
   }
+  lds_f64* Gn = Gr + n * RR;
   for (int e = lane; e < RR; e += 64) {
     const int r1 = e / R, r2 = e - r1 * R;
     Gn[e] = G[e] / (nrm[r1] * nrm[r2]);
@@ -444,8 +431,8 @@ __global__ __launch_bounds__(NM_NT) void nm_als_kernel(NmAlsArgs g) {
   double* Fl = sm;                       // [N][Q][RC], zero beyond R
   double* Gr = Fl + N * QRC;             // [N][R][R] Grams
   double* Mb = Gr + N * RR;              // [Q][R] MTTKRP of the mode being updated
-  double* wk = Mb + QR;                  // [2 R^2] mode-update workspace
-  double* part = wk + 2 * RR;            // [NM_NT] chunk sums of the MTTKRP
+  double* wk = Mb + QR;                  // [R^2] mode-update workspace
+  double* part = wk + RR;                // [NM_NT] chunk sums of the MTTKRP
   double* nrm = part + NM_NT;            // [R]
   double* Tl = nrm + R;                  // [TMAX] if t_lds
   double* ldsA = Tl + (g.t_lds ? g.TMAX : 0);
@@ -874,7 +861,7 @@ NmAlsPlan nm_plan(int N, int Q, int R, int W) {
   pl.SB = (int)sb;
   pl.TMAX = (int)(std::max(nrow, ncol) * RC);
   const size_t base = ((size_t)N * Q * RC + (size_t)N * R * R + (size_t)Q * R +
-                       2 * (size_t)R * R + NM_NT + R) * 8;
+                       (size_t)R * R + NM_NT + R) * 8;
   const size_t cap = 160 * 1024 - 64;
   size_t lds = base;
   pl.t_lds = (lds + (size_t)pl.TMAX * 8 <= cap) ? 1 : 0;
