@@ -1181,7 +1181,9 @@ def run_nmode(args):
         "fit_gate": gate, "fit_oracle": fits_or[-1], "abs_dfit": max(d),
         "stage_ms": {"compress": round(ms["compress"], 4), "als": round(ms["als"], 4)},
         "roofline": {"bound": "alu", "achieved": round(als_tf, 4), "peak": 78.6,
-                     "unit": "TFLOP/s", "frac": round(als_tf / 78.6, 6), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(als_tf / 78.6, 6),
+                     "traffic": traffic_from_profile(None, source="nmode.hip",
+                                                     profile="nm_als_nmode4_f64_counters.md"),
                      "kernel": "nm_als_kernel (4 Q^N R flop per replica and sweep, FP64 vector "
                                "arithmetic; up to 8 cooperative workgroups per replica); timed "
                                "with the ALS call's small commit kernels"},
