@@ -52,6 +52,9 @@ def parse():
                     help="batched workload: every stream's ALS as one workgroup per replica "
                          "inside its graph branch (all streams concurrently) instead of "
                          "cooperative launches after the join")
+    ap.add_argument("--als-device-sync", action="store_true",
+                    help="dense stream: agent-scope release and acquire at every ALS replica "
+                         "barrier, also when a replica's workgroups share one XCD")
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--batch", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -728,7 +731,9 @@ def run_dense(args):
     tinit = torch.from_numpy(init).to(dev)
     eng = oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, torch.from_numpy(U).to(dev),
                    torch.from_numpy(V).to(dev), x_dtype="f32", compress_dtype=args.form,
-                   als_dtype=args.als_form, flags=oc.OCTEN_FLAG_TIMING)
+                   als_dtype=args.als_form,
+                   flags=oc.OCTEN_FLAG_TIMING | (oc.OCTEN_FLAG_ALS_DEVICE_SYNC
+                                                 if args.als_device_sync else 0))
     A = torch.empty((c.I, c.R), dtype=torch.float64, device=dev)
     B = torch.empty((c.J, c.R), dtype=torch.float64, device=dev)
     C = torch.empty((K, c.R), dtype=torch.float64, device=dev)
