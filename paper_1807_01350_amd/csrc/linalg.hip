@@ -193,10 +193,14 @@ __global__ __launch_bounds__(1024) void spd_solve_kernel(double* __restrict__ Nm
 // and row j, so one barrier per pivot suffices; N ends diagonal with its
 // pivots unchanged, and the right-hand columns of row i are divided by N(i,i)
 // at the end, giving N^{-1} B.  Thread t owns rows t/16 + 16k and columns
-// t%16 + 16m, so no element index is divided at run time.  info = j + 1 for
-// a pivot that is not positive (the elimination continues with it skipped and
-// its row is returned undivided).
+// t%16 + 16m, so no element index is divided at run time.  Per pivot a
+// thread first loads every operand of its KR x KC elements (they are
+// independent), then updates and stores them: one LDS latency per pivot
+// instead of one per element.  info = j + 1 for a pivot that is not positive
+// (the elimination continues with it skipped and its row is returned
+// undivided).
 constexpr int GJ_NMAX = 112, GJ_RMAX = 32;
+template <int KR, int KC>
 __global__ __launch_bounds__(256) void spd_solve_gj_kernel(const double* __restrict__ Nm, int n,
                                                            double* __restrict__ Bm, int nrhs,
                                                            int* info) {
@@ -214,10 +218,33 @@ __global__ __launch_bounds__(256) void spd_solve_gj_kernel(const double* __restr
     const double p = M(j, j);
     if (p > 0.0) {
       const double ip = 1.0 / p;
-      for (int i = rg; i < n; i += 16) {
-        if (i == j) continue;
-        const double f = M(i, j) * ip;
-        for (int c = j + 1 + cg; c < w; c += 16) M(i, c) = fma(-f, M(j, c), M(i, c));
+      double f[KR], rj[KC], x[KR][KC];
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int i = rg + 16 * k;
+        f[k] = (i < n && i != j) ? M(i, j) : 0.0;
+      }
+#pragma unroll
+      for (int m = 0; m < KC; ++m) {
+        const int c = cg + 16 * m;
+        rj[m] = (c > j && c < w) ? M(j, c) : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < KR; ++k)
+#pragma unroll
+        for (int m = 0; m < KC; ++m) {
+          const int i = rg + 16 * k, c = cg + 16 * m;
+          x[k][m] = (i < n && i != j && c > j && c < w) ? M(i, c) : 0.0;
+        }
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int i = rg + 16 * k;
+        const double fk = f[k] * ip;
+#pragma unroll
+        for (int m = 0; m < KC; ++m) {
+          const int c = cg + 16 * m;
+          if (i < n && i != j && c > j && c < w) M(i, c) = fma(-fk, rj[m], x[k][m]);
+        }
       }
     } else if (tid == 0 && !bad) {
       bad = j + 1;
@@ -354,11 +381,15 @@ hipError_t spd_solve_small(hipStream_t s, double* N, int n, double* Bm, int nrhs
   if (n <= 0) return hipSuccess;
   if (n <= GJ_NMAX && nrhs <= GJ_RMAX) {
     const size_t lds = (size_t)n * (n + nrhs + 1) * sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void*)spd_solve_gj_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    // row and column slots per thread (rows t/16 + 16k, columns t%16 + 16m)
+    const int kr = (n + 15) / 16, kc = (n + nrhs + 15) / 16;
+    const void* fn = (kr <= 4 && kc <= 4)   ? (const void*)spd_solve_gj_kernel<4, 4>
+                     : (kr <= 4 && kc <= 6) ? (const void*)spd_solve_gj_kernel<4, 6>
+                                            : (const void*)spd_solve_gj_kernel<7, 9>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(spd_solve_gj_kernel, dim3(1), dim3(256), lds, s, N, n, Bm, nrhs, info);
-    return hipGetLastError();
+    void* args[] = {&N, &n, &Bm, &nrhs, &info};
+    return hipLaunchKernel(fn, dim3(1), dim3(256), args, lds, s);
   }
   hipLaunchKernelGGL(spd_solve_kernel, dim3(1), dim3(1024), 0, s, N, n, Bm, nrhs, work, info);
   return hipGetLastError();
