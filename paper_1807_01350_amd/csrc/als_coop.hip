@@ -1179,7 +1179,7 @@ size_t als_coop_lds_bytes(int Q, int R, int NW, bool x_f64, bool slab_global, bo
 hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int R, int NW,
                     bool slab_global, const double* init, double* F, double* lam, int* iters,
                     int* flags, double* slots, unsigned* counters, int* err, int max_iters,
-                    double tol, bool allow_local, bool split) {
+                    double tol, bool allow_local, bool split, bool cleared) {
   if (R > MAXR || Q > 128 || NW < 1 || NW > Q || NW > 32) return hipErrorInvalidValue;
   if (split && y_f64) return hipErrorInvalidValue;
   CoopArgs a;
@@ -1193,10 +1193,13 @@ hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int 
   a.max_iters = max_iters; a.tol = tol; a.allow_local = allow_local ? 1 : 0;
   const size_t lds = als_coop_lds_bytes(Q, R, NW, y_f64, slab_global, split);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipError_t e = fill_i32(s, (int*)counters, 2 * P, 0);
-  if (e != hipSuccess) return e;
-  e = fill_i32(s, err, 1, 0);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (!cleared) {
+    e = fill_i32(s, (int*)counters, 2 * P, 0);
+    if (e != hipSuccess) return e;
+    e = fill_i32(s, err, 1, 0);
+    if (e != hipSuccess) return e;
+  }
   const int grid = 8 * a.per_xcd * NW;
   void* args[] = {&a};
   const void* fn;

@@ -259,6 +259,26 @@ __global__ __launch_bounds__(256) void spd_solve_gj_kernel(const double* __restr
   if (tid == 0 && bad && *info == 0) *info = bad;
 }
 
+// Set-up of one ALS call in one launch: F0 = src (the starting factors, given
+// back to a replica whose fit fails), lam0 = lam_src or ones, the replica
+// flags cleared, and (for a cooperative launch) its barrier words cleared.
+__global__ void als_prep_kernel(int64_t nf, double* __restrict__ F0, const double* __restrict__ src,
+                                int64_t nl, double* __restrict__ lam0,
+                                const double* __restrict__ lam_src, int P, int* __restrict__ flags,
+                                unsigned* __restrict__ ctr, int nctr, int* __restrict__ err) {
+  int64_t n = nf > nl ? nf : nl;
+  if (P > n) n = P;
+  if (nctr > n) n = nctr;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < nf) F0[i] = src[i];
+    if (i < nl) lam0[i] = lam_src ? lam_src[i] : 1.0;
+    if (i < P) flags[i] = 0;
+    if (ctr && i < nctr) ctr[i] = 0u;
+    if (err && i == 0) *err = 0;
+  }
+}
+
 __global__ void fill_f64_kernel(double* p, int64_t n, double v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -392,6 +412,17 @@ hipError_t spd_solve_small(hipStream_t s, double* N, int n, double* Bm, int nrhs
     return hipLaunchKernel(fn, dim3(1), dim3(256), args, lds, s);
   }
   hipLaunchKernelGGL(spd_solve_kernel, dim3(1), dim3(1024), 0, s, N, n, Bm, nrhs, work, info);
+  return hipGetLastError();
+}
+
+hipError_t als_prep(hipStream_t s, int64_t nf, double* F0, const double* src, int64_t nl,
+                    double* lam0, const double* lam_src, int P, int* flags, unsigned* ctr,
+                    int nctr, int* err) {
+  int64_t n = nf > nl ? nf : nl;
+  if (P > n) n = P;
+  if (nctr > n) n = nctr;
+  hipLaunchKernelGGL(als_prep_kernel, dim3(grid_for(n)), dim3(256), 0, s, nf, F0, src, nl, lam0,
+                     lam_src, P, flags, ctr, nctr, err);
   return hipGetLastError();
 }
 

@@ -812,25 +812,26 @@ octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int
   }
   hipStream_t s = h->stream;
   const int64_t QR3 = (int64_t)3 * h->Q * h->R;
-  // the starting point, given back to a replica whose fit fails
-  HIPCHK(h, hipMemcpyAsync(h->F0, src, (size_t)h->P * QR3 * 8, hipMemcpyDeviceToDevice, s));
-  if (init_mode == OCTEN_INIT_GIVEN || !h->have_factors)
-    HIPCHK(h, fill_f64(s, h->lam0, (int64_t)h->P * h->R, 1.0));
-  else
-    HIPCHK(h, hipMemcpyAsync(h->lam0, h->lam, (size_t)h->P * h->R * 8, hipMemcpyDeviceToDevice, s));
   {
     StageTimer tm(h, OCTEN_STAGE_ALS);
-    HIPCHK(h, fill_i32(s, h->flags, h->P, 0));
     hipError_t e = hipErrorNotSupported;
     // group branches run concurrently: no cooperative grid there
     const bool in_branch = h->group_mode;
     if (h->cfg.als_dtype == OCTEN_BF16X2 && (in_branch || h->als_nw <= 0))
       return fail(h, OCTEN_ERR_UNSUPPORTED,
                   "the two-term contractions run in the cooperative ALS only");
-    if (h->als_nw > 0 && !in_branch && !(h->cfg.flags & OCTEN_FLAG_ALS_ONE_WG)) {
+    const bool coop = h->als_nw > 0 && !in_branch && !(h->cfg.flags & OCTEN_FLAG_ALS_ONE_WG);
+    // one launch: the starting point (given back to a replica whose fit
+    // fails) and its weights, the replica flags, and the cooperative
+    // launch's barrier words
+    const bool fresh = init_mode == OCTEN_INIT_GIVEN || !h->have_factors;
+    HIPCHK(h, als_prep(s, (int64_t)h->P * QR3, h->F0, src, (int64_t)h->P * h->R, h->lam0,
+                       fresh ? nullptr : h->lam, h->P, h->flags, coop ? h->als_ctr : nullptr,
+                       2 * h->P, coop ? h->als_err : nullptr));
+    if (coop) {
       e = als_coop(s, h->Y, h->acc_f64, h->P, h->Q, h->R, h->als_nw, h->als_gx, src, h->F,
                    h->lam, h->iters, h->flags, h->als_slots, h->als_ctr, h->als_err, max_iters,
-                   tol, !(h->cfg.flags & OCTEN_FLAG_ALS_DEVICE_SYNC), h->als_split);
+                   tol, !(h->cfg.flags & OCTEN_FLAG_ALS_DEVICE_SYNC), h->als_split, true);
       if (e != hipSuccess) {
         (void)hipGetLastError();
         h->als_nw = 0;   // cooperative launch not possible here: use the reference kernel

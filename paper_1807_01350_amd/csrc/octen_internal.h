@@ -49,6 +49,12 @@ hipError_t spd_solve_small(hipStream_t s, double* N, int n, double* Bm, int nrhs
                            int* info);
 
 hipError_t fill_f64(hipStream_t s, double* p, int64_t n, double v);
+// Set-up of one ALS call in one launch: F0[0, nf) = src, lam0[0, nl) = lam_src
+// (ones if null), flags[0, P) = 0, ctr[0, nctr) = 0 and *err = 0 (either
+// skipped if null).
+hipError_t als_prep(hipStream_t s, int64_t nf, double* F0, const double* src, int64_t nl,
+                    double* lam0, const double* lam_src, int P, int* flags, unsigned* ctr,
+                    int nctr, int* err);
 hipError_t fill_i32(hipStream_t s, int* p, int64_t n, int v);
 hipError_t convert_f64_to_f32(hipStream_t s, const double* in, float* out, int64_t n);
 // y[i] += x[i]
@@ -125,10 +131,11 @@ inline int als_coop_slot_len(int Q, int R) { return Q * R + R * R + 8; }
 // through its L2 without device-wide write-back and invalidation.
 // split (float summaries): the contractions on two-term bfloat16 operands.
 size_t als_coop_lds_bytes(int Q, int R, int NW, bool x_f64, bool slab_global, bool split);
+// cleared: counters and err are already zero (als_prep), else cleared here.
 hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int R, int NW,
                     bool slab_global, const double* init, double* F, double* lam, int* iters,
                     int* flags, double* slots, unsigned* counters, int* err, int max_iters,
-                    double tol, bool allow_local, bool split);
+                    double tol, bool allow_local, bool split, bool cleared = false);
 
 // -------------------------------------------------------------- recovery ---
 // lambda^(1/3), anchor similarity, exclusive greedy matching, scale alignment.
