@@ -223,8 +223,40 @@ def test_invalid_state_and_arguments():
         buf = torch.empty(1, dtype=torch.float64, device="cuda")
         assert oc.octen_nm_get_state(eng.h, oc.OCTEN_STATE_Y, buf, 8) == oc.OCTEN_ERR_ARG
         assert oc.octen_nm_get_state(eng.h, 99, buf, 8) == oc.OCTEN_ERR_ARG
+        # recovery before ALS, then a C too small for the rows
+        X = torch.rand((4,) + dims, dtype=torch.float64, device="cuda")
+        W = torch.randn((4, eng.M1), dtype=torch.float64, device="cuda")
+        eng.compress_batch(X, W)
+        eng.update_replicas()
+        As = [torch.zeros((d, R), dtype=torch.float64, device="cuda") for d in dims]
+        with pytest.raises(oc.OctenError) as e:
+            eng.recover_factors(As, torch.zeros((4, R), dtype=torch.float64, device="cuda"))
+        assert e.value.status == oc.OCTEN_ERR_STATE
+        init = torch.randn((P, 4, Q, R), dtype=torch.float64, device="cuda")
+        eng.cp_als_replicas(3, init=init)
+        with pytest.raises(oc.OctenError) as e:
+            eng.recover_factors(As, torch.zeros((3, R), dtype=torch.float64, device="cuda"))
+        assert e.value.status == oc.OCTEN_ERR_ARG
+        assert eng.recover_factors(As, torch.zeros((4, R), dtype=torch.float64, device="cuda")) == 4
     finally:
         eng.close()
+
+
+def test_rank_deficient_compression_matrix_rejected():
+    """A non-temporal compression matrix without full row rank (a zero row in
+    the mode with I_n <= M1 = 8) makes the normal matrix of its
+    least-squares operator singular (an exactly zero pivot): init reports
+    OCTEN_ERR_NUMERIC."""
+    import torch
+    from paper_1807_01350_amd import octen as oc
+    from paper_1807_01350_amd import synth
+    dims, R, P, Q, S = (10, 9, 8), 2, 2, 5, 2
+    Us = synth.compression_Us(dims, P, Q, S, 47)
+    Us[2] = Us[2].copy()
+    Us[2][3] = 0.0
+    with pytest.raises(oc.OctenError) as e:
+        oc.OctenN(dims, R, P, Q, S, [torch.as_tensor(u, device="cuda") for u in Us])
+    assert e.value.status == oc.OCTEN_ERR_NUMERIC
 
 
 def test_nonfinite_batch_leaves_summaries():
