@@ -74,66 +74,84 @@ __global__ __launch_bounds__(256) void stage2_kernel(const double* __restrict__ 
   }
 }
 
-constexpr int S3_B = 16;   // b per block
 constexpr int S3_KT = 32;  // k per LDS tile
 
-// Z[p][a][b][c] = sum_k M[k][p][a][b] * W[k][col_p(c)], b in a block of 16.
-template <typename TM, typename TZ>
+// Z[p][a][b][c] = sum_k M[k][p][a][b] * W[k][col_p(c)] (k ascending, FP64
+// sums of the row-block partials first).  One workgroup per (p, a) covers all
+// (b, c): thread (ty, tx) owns 4 x 4 outputs in each of NSB x NSB blocks of
+// 64 x 64, so that a k step reads 4 + 4 values from LDS for 16 products and W
+// is staged once per workgroup.
+template <typename TM, typename TZ, int NSB>
 __global__ __launch_bounds__(256) void mode3_kernel(const TM* __restrict__ Mk,
                                                     const double* __restrict__ W, int64_t t,
                                                     int nrb, int M1, int P, int Q, int S,
                                                     TZ* __restrict__ Z, int* __restrict__ zbad) {
   extern __shared__ double sm[];
-  double* Ms = sm;                     // [S3_KT][S3_B]
-  double* Ws = sm + S3_KT * S3_B;      // [S3_KT][Q]
-  const int p = blockIdx.x, a = blockIdx.y, b0 = blockIdx.z * S3_B;
-  const int tid = threadIdx.x;
-  const int nout = S3_B * Q;
-  double acc[8];
+  constexpr int QP = 64 * NSB;
+  double* Ms = sm;                     // [S3_KT][QP]
+  double* Ws = sm + S3_KT * QP;        // [S3_KT][QP]
+  const int p = blockIdx.x, a = blockIdx.y;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  double acc[NSB][NSB][4][4];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+  for (int sb = 0; sb < NSB; ++sb)
+#pragma unroll
+    for (int sc = 0; sc < NSB; ++sc)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[sb][sc][i][j] = 0.0;
   for (int64_t k0 = 0; k0 < t; k0 += S3_KT) {
-    for (int e = tid; e < S3_KT * S3_B; e += 256) {
-      int kk = e / S3_B, bb = e % S3_B;
-      int64_t gk = k0 + kk;
-      int b = b0 + bb;
-      double v = 0.0;
-      if (gk < t && b < Q)
+    for (int e = tid; e < S3_KT * QP; e += 256) {
+      const int kk = e / QP, b = e - kk * QP;
+      const int64_t gk = k0 + kk;
+      double v = 0.0, wv = 0.0;
+      if (gk < t && b < Q) {
         for (int rb = 0; rb < nrb; ++rb) v += (double)Mk[(((gk * nrb + rb) * P + p) * Q + a) * Q + b];
+        wv = W[gk * M1 + rep_col(p, b, Q, S)];
+      }
       Ms[e] = v;
-    }
-    for (int e = tid; e < S3_KT * Q; e += 256) {
-      int kk = e / Q, c = e % Q;
-      int64_t gk = k0 + kk;
-      Ws[e] = gk < t ? W[gk * M1 + rep_col(p, c, Q, S)] : 0.0;
+      Ws[e] = wv;
     }
     __syncthreads();
+    for (int kk = 0; kk < S3_KT; ++kk) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      int o = tid + u * 256;
-      if (o < nout) {
-        int bb = o / Q, c = o % Q;
-        double s = acc[u];
-        for (int kk = 0; kk < S3_KT; ++kk) s = fma(Ms[kk * S3_B + bb], Ws[kk * Q + c], s);
-        acc[u] = s;
+      for (int sb = 0; sb < NSB; ++sb) {
+        double mb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) mb[i] = Ms[kk * QP + sb * 64 + ty * 4 + i];
+#pragma unroll
+        for (int sc = 0; sc < NSB; ++sc) {
+          double wc[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) wc[j] = Ws[kk * QP + sc * 64 + tx * 4 + j];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[sb][sc][i][j] = fma(mb[i], wc[j], acc[sb][sc][i][j]);
+        }
       }
     }
     __syncthreads();
   }
   int bad = 0;
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    int o = tid + u * 256;
-    if (o < nout) {
-      int bb = o / Q, c = o % Q;
-      int b = b0 + bb;
-      if (b < Q) {
-        const TZ z = (TZ)acc[u];
-        bad |= isfinite((double)z) ? 0 : 1;
-        Z[(((int64_t)p * Q + a) * Q + b) * Q + c] = z;
+  for (int sb = 0; sb < NSB; ++sb)
+#pragma unroll
+    for (int sc = 0; sc < NSB; ++sc)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int b = sb * 64 + ty * 4 + i;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c = sc * 64 + tx * 4 + j;
+          if (b < Q && c < Q) {
+            const TZ z = (TZ)acc[sb][sc][i][j];
+            bad |= isfinite((double)z) ? 0 : 1;
+            Z[(((int64_t)p * Q + a) * Q + b) * Q + c] = z;
+          }
+        }
       }
-    }
-  }
   // a non-finite slice value reaches every replica's Z: flag the replica
   if (bad) atomicOr(zbad + p, 1);
 }
@@ -142,30 +160,51 @@ __global__ __launch_bounds__(256) void mode3_kernel(const TM* __restrict__ Mk,
 
 hipError_t compress_mode3_partials(hipStream_t s, const CompressShape& sh, int64_t t, int nrb,
                                   const float* Mpart, const double* W, float* Z, int* zbad) {
-  dim3 grid(sh.P, sh.Q, (sh.Q + S3_B - 1) / S3_B);
-  size_t lds = (size_t)(S3_KT * S3_B + S3_KT * sh.Q) * sizeof(double);
-  hipLaunchKernelGGL((mode3_kernel<float, float>), grid, dim3(256), lds, s, Mpart, W, t, nrb,
-                     sh.M1, sh.P, sh.Q, sh.S, Z, zbad);
+  if (sh.Q > 128) return hipErrorInvalidValue;
+  dim3 grid(sh.P, sh.Q);
+  if (sh.Q <= 64) {
+    const size_t lds = (size_t)2 * S3_KT * 64 * sizeof(double);
+    hipLaunchKernelGGL((mode3_kernel<float, float, 1>), grid, dim3(256), lds, s, Mpart, W, t, nrb,
+                       sh.M1, sh.P, sh.Q, sh.S, Z, zbad);
+  } else {
+    const size_t lds = (size_t)2 * S3_KT * 128 * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void*)mode3_kernel<float, float, 2>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((mode3_kernel<float, float, 2>), grid, dim3(256), lds, s, Mpart, W, t, nrb,
+                       sh.M1, sh.P, sh.Q, sh.S, Z, zbad);
+  }
   return hipGetLastError();
 }
 
+namespace {
+template <typename TM, typename TZ>
+hipError_t launch_mode3(hipStream_t s, const CompressShape& sh, int64_t t, const TM* M,
+                        const double* W, TZ* Z, int* zbad) {
+  dim3 grid(sh.P, sh.Q);
+  if (sh.Q <= 64) {
+    hipLaunchKernelGGL((mode3_kernel<TM, TZ, 1>), grid, dim3(256),
+                       (size_t)2 * S3_KT * 64 * sizeof(double), s, M, W, t, 1, sh.M1, sh.P, sh.Q,
+                       sh.S, Z, zbad);
+  } else {
+    const size_t lds = (size_t)2 * S3_KT * 128 * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void*)mode3_kernel<TM, TZ, 2>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((mode3_kernel<TM, TZ, 2>), grid, dim3(256), lds, s, M, W, t, 1, sh.M1, sh.P,
+                       sh.Q, sh.S, Z, zbad);
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
 hipError_t compress_mode3(hipStream_t s, const CompressShape& sh, int64_t t, const void* M,
                           bool m_f64, const double* W, void* Z, bool z_f64, int* zbad) {
-  dim3 grid(sh.P, sh.Q, (sh.Q + S3_B - 1) / S3_B);
-  size_t lds = (size_t)(S3_KT * S3_B + S3_KT * sh.Q) * sizeof(double);
-  if (m_f64 && z_f64)
-    hipLaunchKernelGGL((mode3_kernel<double, double>), grid, dim3(256), lds, s,
-                       (const double*)M, W, t, 1, sh.M1, sh.P, sh.Q, sh.S, (double*)Z, zbad);
-  else if (m_f64 && !z_f64)
-    hipLaunchKernelGGL((mode3_kernel<double, float>), grid, dim3(256), lds, s, (const double*)M,
-                       W, t, 1, sh.M1, sh.P, sh.Q, sh.S, (float*)Z, zbad);
-  else if (!m_f64 && z_f64)
-    hipLaunchKernelGGL((mode3_kernel<float, double>), grid, dim3(256), lds, s, (const float*)M,
-                       W, t, 1, sh.M1, sh.P, sh.Q, sh.S, (double*)Z, zbad);
-  else
-    hipLaunchKernelGGL((mode3_kernel<float, float>), grid, dim3(256), lds, s, (const float*)M, W,
-                       t, 1, sh.M1, sh.P, sh.Q, sh.S, (float*)Z, zbad);
-  return hipGetLastError();
+  if (sh.Q > 128) return hipErrorInvalidValue;
+  if (m_f64 && z_f64) return launch_mode3(s, sh, t, (const double*)M, W, (double*)Z, zbad);
+  if (m_f64 && !z_f64) return launch_mode3(s, sh, t, (const double*)M, W, (float*)Z, zbad);
+  if (!m_f64 && z_f64) return launch_mode3(s, sh, t, (const float*)M, W, (double*)Z, zbad);
+  return launch_mode3(s, sh, t, (const float*)M, W, (float*)Z, zbad);
 }
 
 hipError_t compress_reference(hipStream_t s, const CompressShape& sh, const void* X, bool x_f64,
