@@ -73,8 +73,15 @@ octen_status octen_nm_compress_batch(octen_nm_t h, const double* X, int64_t t, c
 /* Y_p += Z_p (a replica whose compressed batch holds a non-finite value is
  * not updated; reported as OCTEN_ERR_NUMERIC by octen_nm_recover_factors). */
 octen_status octen_nm_update_replicas(octen_nm_t h);
-/* iters ALS sweeps per replica.  init_mode OCTEN_INIT_GIVEN with init
- * [P][N][Q][R] f64 (device), or OCTEN_INIT_PREV (the previous factors). */
+/* iters ALS sweeps per replica (Gauss-Seidel over the N modes; one
+ * cooperative launch with up to 8 workgroups per replica, or one workgroup
+ * per replica where that launch is not possible).  init_mode
+ * OCTEN_INIT_GIVEN with init [P][N][Q][R] f64 (device), or OCTEN_INIT_PREV
+ * (the previous factors).  A replica whose solve meets a non-positive pivot,
+ * whose barrier timed out or whose factors are not finite keeps its starting
+ * factors (OCTEN_STATE_FLAGS bits 0-3 as in octen.h) and is reported as
+ * OCTEN_ERR_NUMERIC by the next synchronising octen_nm_recover_factors.
+ * OCTEN_ERR_STATE before the first update or without previous factors. */
 octen_status octen_nm_cp_als_replicas(octen_nm_t h, int32_t iters, int32_t init_mode,
                                       const double* init);
 /* Matching and recovery.  A: host array of N - 1 device pointers
