@@ -77,10 +77,11 @@ __global__ __launch_bounds__(256) void stage2_kernel(const double* __restrict__ 
 constexpr int S3_KT = 32;  // k per LDS tile
 
 // Z[p][a][b][c] = sum_k M[k][p][a][b] * W[k][col_p(c)] (k ascending, FP64
-// sums of the row-block partials first).  One workgroup per (p, a) covers all
-// (b, c): thread (ty, tx) owns 4 x 4 outputs in each of NSB x NSB blocks of
-// 64 x 64, so that a k step reads 4 + 4 values from LDS for 16 products and W
-// is staged once per workgroup.
+// sums of the row-block partials first), for Q <= 64 * NSB (launched with
+// NSB = 1).  One workgroup per (p, a) covers all (b, c): thread (ty, tx) owns
+// 4 x 4 outputs in each of NSB x NSB blocks of 64 x 64, so that a k step
+// reads 4 + 4 values from LDS for 16 products and W is staged once per
+// workgroup.
 template <typename TM, typename TZ, int NSB>
 __global__ __launch_bounds__(256) void mode3_kernel(const TM* __restrict__ Mk,
                                                     const double* __restrict__ W, int64_t t,
@@ -156,6 +157,70 @@ __global__ __launch_bounds__(256) void mode3_kernel(const TM* __restrict__ Mk,
   if (bad) atomicOr(zbad + p, 1);
 }
 
+constexpr int S3_B = 16;   // b per block
+
+// The same for Q > 64, one workgroup per (p, a, block of 16 b): the 4 x 4
+// tiles of mode3_kernel would leave most of a 128 x 128 block idle there.
+template <typename TM, typename TZ>
+__global__ __launch_bounds__(256) void mode3_bblock_kernel(const TM* __restrict__ Mk,
+                                                    const double* __restrict__ W, int64_t t,
+                                                    int nrb, int M1, int P, int Q, int S,
+                                                    TZ* __restrict__ Z, int* __restrict__ zbad) {
+  extern __shared__ double sm[];
+  double* Ms = sm;                     // [S3_KT][S3_B]
+  double* Ws = sm + S3_KT * S3_B;      // [S3_KT][Q]
+  const int p = blockIdx.x, a = blockIdx.y, b0 = blockIdx.z * S3_B;
+  const int tid = threadIdx.x;
+  const int nout = S3_B * Q;
+  double acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+  for (int64_t k0 = 0; k0 < t; k0 += S3_KT) {
+    for (int e = tid; e < S3_KT * S3_B; e += 256) {
+      int kk = e / S3_B, bb = e % S3_B;
+      int64_t gk = k0 + kk;
+      int b = b0 + bb;
+      double v = 0.0;
+      if (gk < t && b < Q)
+        for (int rb = 0; rb < nrb; ++rb) v += (double)Mk[(((gk * nrb + rb) * P + p) * Q + a) * Q + b];
+      Ms[e] = v;
+    }
+    for (int e = tid; e < S3_KT * Q; e += 256) {
+      int kk = e / Q, c = e % Q;
+      int64_t gk = k0 + kk;
+      Ws[e] = gk < t ? W[gk * M1 + rep_col(p, c, Q, S)] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int o = tid + u * 256;
+      if (o < nout) {
+        int bb = o / Q, c = o % Q;
+        double s = acc[u];
+        for (int kk = 0; kk < S3_KT; ++kk) s = fma(Ms[kk * S3_B + bb], Ws[kk * Q + c], s);
+        acc[u] = s;
+      }
+    }
+    __syncthreads();
+  }
+  int bad = 0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    int o = tid + u * 256;
+    if (o < nout) {
+      int bb = o / Q, c = o % Q;
+      int b = b0 + bb;
+      if (b < Q) {
+        const TZ z = (TZ)acc[u];
+        bad |= isfinite((double)z) ? 0 : 1;
+        Z[(((int64_t)p * Q + a) * Q + b) * Q + c] = z;
+      }
+    }
+  }
+  // a non-finite slice value reaches every replica's Z: flag the replica
+  if (bad) atomicOr(zbad + p, 1);
+}
+
 }  // namespace
 
 hipError_t compress_mode3_partials(hipStream_t s, const CompressShape& sh, int64_t t, int nrb,
@@ -167,12 +232,10 @@ hipError_t compress_mode3_partials(hipStream_t s, const CompressShape& sh, int64
     hipLaunchKernelGGL((mode3_kernel<float, float, 1>), grid, dim3(256), lds, s, Mpart, W, t, nrb,
                        sh.M1, sh.P, sh.Q, sh.S, Z, zbad);
   } else {
-    const size_t lds = (size_t)2 * S3_KT * 128 * sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void*)mode3_kernel<float, float, 2>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((mode3_kernel<float, float, 2>), grid, dim3(256), lds, s, Mpart, W, t, nrb,
-                       sh.M1, sh.P, sh.Q, sh.S, Z, zbad);
+    dim3 g3(sh.P, sh.Q, (sh.Q + S3_B - 1) / S3_B);
+    const size_t lds = (size_t)(S3_KT * S3_B + S3_KT * sh.Q) * sizeof(double);
+    hipLaunchKernelGGL((mode3_bblock_kernel<float, float>), g3, dim3(256), lds, s, Mpart, W, t,
+                       nrb, sh.M1, sh.P, sh.Q, sh.S, Z, zbad);
   }
   return hipGetLastError();
 }
@@ -187,12 +250,10 @@ hipError_t launch_mode3(hipStream_t s, const CompressShape& sh, int64_t t, const
                        (size_t)2 * S3_KT * 64 * sizeof(double), s, M, W, t, 1, sh.M1, sh.P, sh.Q,
                        sh.S, Z, zbad);
   } else {
-    const size_t lds = (size_t)2 * S3_KT * 128 * sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void*)mode3_kernel<TM, TZ, 2>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((mode3_kernel<TM, TZ, 2>), grid, dim3(256), lds, s, M, W, t, 1, sh.M1, sh.P,
-                       sh.Q, sh.S, Z, zbad);
+    dim3 g3(sh.P, sh.Q, (sh.Q + S3_B - 1) / S3_B);
+    const size_t lds = (size_t)(S3_KT * S3_B + S3_KT * sh.Q) * sizeof(double);
+    hipLaunchKernelGGL((mode3_bblock_kernel<TM, TZ>), g3, dim3(256), lds, s, M, W, t, 1, sh.M1,
+                       sh.P, sh.Q, sh.S, Z, zbad);
   }
   return hipGetLastError();
 }
