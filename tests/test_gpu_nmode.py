@@ -48,6 +48,9 @@ CASES = [
     NCase("n4_ragged", (40, 33, 7), 3, 2, 9, 2, (20, 1, 17), 25, config_id=45),
     # rank one, one anchor column
     NCase("n4_rank1", (11, 10, 9), 1, 3, 5, 1, (6, 6), 15, config_id=46),
+    # ranks past 8 and past 16 (the 16- and 32-column instances of the ALS)
+    NCase("n4_r10", (12, 10, 9), 10, 3, 12, 2, (12, 6), 20, config_id=51),
+    NCase("n3_r20", (30, 28), 20, 2, 24, 2, (25, 8), 15, config_id=52),
     # 130 replicas: one workgroup per replica (no cooperative launch)
     NCase("n3_many", (6, 5), 2, 130, 5, 2, (5, 3), 10, config_id=49),
     # the benchmark's four-mode stream at full size (100^3 slices, P = 10
