@@ -409,6 +409,60 @@ __device__ __noinline__ void nm_mode_call(const double* M, double* Fl, double* G
   nm_mode_wave<RMAX>(M, Fl, Gr, work, nrm, n, N, Q, R, bad);
 }
 
+// The first contraction (in = the summary) on FP64 matrix cores, used for
+// RC >= 16 (at RC = 8 half of every 16-wide tile would be padding and the
+// VALU form above is faster): outputs o = (a L + l) Bo + b in tiles of 16 per
+// wavefront, A[o][i] = in[a sa + i si + l sl + b], B[i][r] = F(i, r) (zero
+// past Q and RC), v_mfma_f64_16x16x4f64 over i in steps of 4 (lane t supplies
+// A[t%16][t/16] and B[t/16][t%16]; element k of the result is
+// D[t/16 + 4k][t%16]); all Q / 4 operand loads of a tile are issued before
+// its products (Q <= 32).
+template <int RC>
+__device__ void nm_contract_first_mfma(const double* in, int pre, int L, int Bo, int sa, int si,
+                                       int sl, int Q, const double* Fm, double* out) {
+  constexpr int NT = (RC + 15) / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int LB = L * Bo, n = pre * LB, ntile = (n + 15) / 16;
+  const int m = lane & 15, kq = lane >> 4;
+  for (int tile = wave; tile < ntile; tile += NM_NT / 64) {
+    const int o = tile * 16 + m;
+    const bool ook = o < n;
+    const int oc = ook ? o : n - 1;
+    const int a = oc / LB, rem = oc - a * LB, l = rem / Bo, b = rem - l * Bo;
+    const double* src = in + a * sa + l * sl + b;
+    double av[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = 4 * u + kq;
+      av[u] = (4 * u < Q && ook && i < Q) ? src[i * si] : 0.0;
+    }
+    f64x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (4 * u < Q) {
+        const int i = 4 * u + kq;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int col = t * 16 + m;
+          const double bv = (i < Q && col < RC) ? Fm[i * RC + col] : 0.0;
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv, acc[t], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int col = t * 16 + m;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int o2 = tile * 16 + kq + 4 * k;
+        if (o2 < n && col < RC) out[o2 * RC + col] = acc[t][k];
+      }
+    }
+  }
+}
+
 // Rank-R CP of each replica by Gauss-Seidel ALS over the N modes (the N-mode
 // form of the replica ALS, Sec. 4.1), W workgroups per replica (a
 // cooperative launch when W > 1).  The MTTKRPs follow a dimension tree
@@ -486,8 +540,12 @@ __global__ __launch_bounds__(NM_NT) void nm_als_kernel(NmAlsArgs g) {
           const int post = qpow[N - 1 - m];
           const bool first = m == nL;
           if (m == N - 1) dst = TLg + (int64_t)a0 * RC;
-          nm_contract<RC>(first ? Y + (int64_t)a0 * Q * post : src, first, cnt, 1, post, Q * post,
-                          post, 0, Q, Fl + m * QRC, dst);
+          if (RC >= 16 && first)
+            nm_contract_first_mfma<RC>(Y + (int64_t)a0 * Q * post, cnt, 1, post, Q * post, post, 0,
+                                       Q, Fl + m * QRC, dst);
+          else
+            nm_contract<RC>(first ? Y + (int64_t)a0 * Q * post : src, first, cnt, 1, post,
+                            Q * post, post, 0, Q, Fl + m * QRC, dst);
           __syncthreads();
           src = dst;
           dst = dst == bufA ? bufB : bufA;
@@ -501,7 +559,10 @@ __global__ __launch_bounds__(NM_NT) void nm_als_kernel(NmAlsArgs g) {
           const int Lk = qpow[nL - 1 - m];
           const bool first = m == 0;
           if (m == nL - 1) dst = TRg + (int64_t)c0 * RC;
-          if (first)
+          if (RC >= 16 && first)
+            nm_contract_first_mfma<RC>(Y + c0, 1, Lk, cnt, 0, Lk * ncol, ncol, Q, Fl + m * QRC,
+                                       dst);
+          else if (first)
             nm_contract<RC>(Y + c0, true, 1, Lk, cnt, 0, Lk * ncol, ncol, Q, Fl + m * QRC, dst);
           else
             nm_contract<RC>(src, false, 1, Lk, cnt, 0, Lk * cnt, cnt, Q, Fl + m * QRC, dst);
