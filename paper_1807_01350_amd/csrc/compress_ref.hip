@@ -77,31 +77,26 @@ __global__ __launch_bounds__(256) void stage2_kernel(const double* __restrict__ 
 constexpr int S3_KT = 32;  // k per LDS tile
 
 // Z[p][a][b][c] = sum_k M[k][p][a][b] * W[k][col_p(c)] (k ascending, FP64
-// sums of the row-block partials first), for Q <= 64 * NSB (launched with
-// NSB = 1).  One workgroup per (p, a) covers all (b, c): thread (ty, tx) owns
-// 4 x 4 outputs in each of NSB x NSB blocks of 64 x 64, so that a k step
-// reads 4 + 4 values from LDS for 16 products and W is staged once per
-// workgroup.
-template <typename TM, typename TZ, int NSB>
+// sums of the row-block partials first), for Q <= 64.  One workgroup per
+// (p, a) covers all (b, c): thread (ty, tx) owns 4 x 4 outputs of the 64 x 64
+// block, so that a k step reads 4 + 4 values from LDS for 16 products and W
+// is staged once per workgroup.
+template <typename TM, typename TZ>
 __global__ __launch_bounds__(256) void mode3_kernel(const TM* __restrict__ Mk,
                                                     const double* __restrict__ W, int64_t t,
                                                     int nrb, int M1, int P, int Q, int S,
                                                     TZ* __restrict__ Z, int* __restrict__ zbad) {
   extern __shared__ double sm[];
-  constexpr int QP = 64 * NSB;
+  constexpr int QP = 64;
   double* Ms = sm;                     // [S3_KT][QP]
   double* Ws = sm + S3_KT * QP;        // [S3_KT][QP]
   const int p = blockIdx.x, a = blockIdx.y;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double acc[NSB][NSB][4][4];
+  double acc[4][4];
 #pragma unroll
-  for (int sb = 0; sb < NSB; ++sb)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int sc = 0; sc < NSB; ++sc)
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[sb][sc][i][j] = 0.0;
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
   for (int64_t k0 = 0; k0 < t; k0 += S3_KT) {
     for (int e = tid; e < S3_KT * QP; e += 256) {
       const int kk = e / QP, b = e - kk * QP;
@@ -116,43 +111,32 @@ __global__ __launch_bounds__(256) void mode3_kernel(const TM* __restrict__ Mk,
     }
     __syncthreads();
     for (int kk = 0; kk < S3_KT; ++kk) {
+      double mb[4], wc[4];
 #pragma unroll
-      for (int sb = 0; sb < NSB; ++sb) {
-        double mb[4];
+      for (int i = 0; i < 4; ++i) mb[i] = Ms[kk * QP + ty * 4 + i];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) mb[i] = Ms[kk * QP + sb * 64 + ty * 4 + i];
+      for (int j = 0; j < 4; ++j) wc[j] = Ws[kk * QP + tx * 4 + j];
 #pragma unroll
-        for (int sc = 0; sc < NSB; ++sc) {
-          double wc[4];
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) wc[j] = Ws[kk * QP + sc * 64 + tx * 4 + j];
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[sb][sc][i][j] = fma(mb[i], wc[j], acc[sb][sc][i][j]);
-        }
-      }
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(mb[i], wc[j], acc[i][j]);
     }
     __syncthreads();
   }
   int bad = 0;
 #pragma unroll
-  for (int sb = 0; sb < NSB; ++sb)
+  for (int i = 0; i < 4; ++i) {
+    const int b = ty * 4 + i;
 #pragma unroll
-    for (int sc = 0; sc < NSB; ++sc)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int b = sb * 64 + ty * 4 + i;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int c = sc * 64 + tx * 4 + j;
-          if (b < Q && c < Q) {
-            const TZ z = (TZ)acc[sb][sc][i][j];
-            bad |= isfinite((double)z) ? 0 : 1;
-            Z[(((int64_t)p * Q + a) * Q + b) * Q + c] = z;
-          }
-        }
+    for (int j = 0; j < 4; ++j) {
+      const int c = tx * 4 + j;
+      if (b < Q && c < Q) {
+        const TZ z = (TZ)acc[i][j];
+        bad |= isfinite((double)z) ? 0 : 1;
+        Z[(((int64_t)p * Q + a) * Q + b) * Q + c] = z;
       }
+    }
+  }
   // a non-finite slice value reaches every replica's Z: flag the replica
   if (bad) atomicOr(zbad + p, 1);
 }
@@ -229,7 +213,7 @@ hipError_t compress_mode3_partials(hipStream_t s, const CompressShape& sh, int64
   dim3 grid(sh.P, sh.Q);
   if (sh.Q <= 64) {
     const size_t lds = (size_t)2 * S3_KT * 64 * sizeof(double);
-    hipLaunchKernelGGL((mode3_kernel<float, float, 1>), grid, dim3(256), lds, s, Mpart, W, t, nrb,
+    hipLaunchKernelGGL((mode3_kernel<float, float>), grid, dim3(256), lds, s, Mpart, W, t, nrb,
                        sh.M1, sh.P, sh.Q, sh.S, Z, zbad);
   } else {
     dim3 g3(sh.P, sh.Q, (sh.Q + S3_B - 1) / S3_B);
@@ -246,7 +230,7 @@ hipError_t launch_mode3(hipStream_t s, const CompressShape& sh, int64_t t, const
                         const double* W, TZ* Z, int* zbad) {
   dim3 grid(sh.P, sh.Q);
   if (sh.Q <= 64) {
-    hipLaunchKernelGGL((mode3_kernel<TM, TZ, 1>), grid, dim3(256),
+    hipLaunchKernelGGL((mode3_kernel<TM, TZ>), grid, dim3(256),
                        (size_t)2 * S3_KT * 64 * sizeof(double), s, M, W, t, 1, sh.M1, sh.P, sh.Q,
                        sh.S, Z, zbad);
   } else {
