@@ -264,6 +264,14 @@ __global__ __launch_bounds__(Tile<KIND>::NT) void compress_fused(Args g) {
         if (row_ok && j0 + 4 * q < g.J) v = *(const f32x4*)(xrow + j0 + 4 * q);      \
         xr[4 * q] = v[0]; xr[4 * q + 1] = v[1]; xr[4 * q + 2] = v[2]; xr[4 * q + 3] = v[3]; \
       }                                                                              \
+    } else if (row_ok && j0 + 16 <= g.J) {                                           \
+      /* the 16 floats lie inside the row: four 16-byte loads from a 4-byte */       \
+      /* aligned address (the unaligned access mode of the target) */                \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                \
+        f32x4 v;                                                                     \
+        __builtin_memcpy(&v, xrow + j0 + 4 * q, sizeof(v));                          \
+        xr[4 * q] = v[0]; xr[4 * q + 1] = v[1]; xr[4 * q + 2] = v[2]; xr[4 * q + 3] = v[3]; \
+      }                                                                              \
     } else {                                                                         \
       _Pragma("unroll") for (int q = 0; q < 16; ++q)                                 \
         xr[q] = (row_ok && j0 + q < g.J) ? xrow[j0 + q] : 0.f;                       \

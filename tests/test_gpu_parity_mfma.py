@@ -10,8 +10,9 @@ Every form is checked twice:
     within 2e-2, the two-term BF16 form within 1e-4 (its inputs carry 16
     significant bits: 2^-16 relative, far inside that bar for these data).
 Shapes cover several row and column blocks with ragged tails, the
-register-staged path (J not a multiple of 4), Q > 64 (three 32-wide tiles)
-and a single slice.  The compression matrices are on the bfloat16 grid, as
+register-staged path (J not a multiple of 4: 16-byte loads inside a row,
+guarded scalar loads at its end) at one, two and three 32-wide tiles per
+replica side, Q > 64 and a single slice.  The compression matrices are on the bfloat16 grid, as
 the two-term form requires.
 """
 import sys
@@ -30,6 +31,9 @@ SHAPES = [
     # name, I, J, t, P, Q, S
     ("c2_like", 300, 260, 7, 12, 60, 3),       # 3 column blocks, ragged rows and j
     ("odd_j", 150, 97, 5, 5, 24, 3),           # J % 4 != 0: register-staged loads
+    ("odd_j_split", 140, 203, 3, 16, 20, 3),   # J % 4 != 0, 14 replicas per tile (two-term: 4 passes)
+    ("odd_j_q50", 120, 131, 3, 6, 50, 3),      # J % 4 != 0, two 32-wide tiles (two-term: 2 passes)
+    ("odd_j_q80", 100, 77, 2, 3, 80, 3),       # J % 4 != 0, three 32-wide tiles
     ("q80", 200, 200, 4, 4, 80, 3),            # three 32-wide tiles per replica side
     ("single_slice", 129, 64, 1, 2, 20, 2),    # t = 1, one row past a block
 ]
