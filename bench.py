@@ -52,6 +52,10 @@ def parse():
                     help="batched workload: every stream's ALS as one workgroup per replica "
                          "inside its graph branch (all streams concurrently) instead of "
                          "cooperative launches after the join")
+    ap.add_argument("--als-wg", choices=("few", "spread"), default="few",
+                    help="batched workload: workgroups per replica of the cooperative ALS, the "
+                         "fewest whose slab fits in LDS (few: more streams share a launch) or "
+                         "enough to spread about 2e5 FMAs per workgroup and sweep")
     ap.add_argument("--als-device-sync", action="store_true",
                     help="dense stream: agent-scope release and acquire at every ALS replica "
                          "barrier, also when a replica's workgroups share one XCD")
@@ -402,7 +406,8 @@ def run_batched(args):
         U = torch.randn((I, M1), generator=g, device=dev, dtype=f64).float().bfloat16().double()
         V = torch.randn((J, M1), generator=g, device=dev, dtype=f64).float().bfloat16().double()
         eng = oc.Octen(I, J, R, P, Q, S, U, V, x_dtype="f32", compress_dtype=args.form,
-                       flags=oc.OCTEN_FLAG_ALS_ONE_WG if args.als_one_wg else 0)
+                       flags=(oc.OCTEN_FLAG_ALS_ONE_WG if args.als_one_wg else 0)
+                       | (oc.OCTEN_FLAG_ALS_FEW_WG if args.als_wg == "few" else 0))
         X = torch.empty((t, I, J), dtype=torch.float32, device=dev)
         W = torch.empty((t, M1), dtype=f64, device=dev)
         init = torch.randn((P, 3, Q, R), generator=g, device=dev, dtype=f64)
@@ -467,7 +472,11 @@ def run_batched(args):
                    "x_bytes_per_round": xbytes, "als_iters": args.iters,
                    "compress_dtype": args.form,
                    "als": "one workgroup per replica in each stream's branch" if args.als_one_wg
-                          else "cooperative, per stream after the join"},
+                          else ("cooperative after the join, streams of the same ALS kernel "
+                                "sharing launches; workgroups per replica: "
+                                + ("fewest fitting the slab in LDS" if args.als_wg == "few"
+                                   else "about 2e5 FMAs each per sweep")),
+                   "als_launches": group.als_launches()},
         "round_ms": [round(1e3 * x, 3) for x in times],
         "replayed": replays,
         "x_stream_gbs": round(gbs, 1),
@@ -848,7 +857,7 @@ def run_dense(args):
     als_xtf = als_exec / (als_ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(als_xtf, 3), "peak": MFMA_PEAK_TFLOPS[als_pk],
             "unit": "TFLOP/s", "frac": round(als_xtf / MFMA_PEAK_TFLOPS[als_pk], 5),
-            "traffic": traffic_from_profile(args.als_form, source="als_coop.hip",
+            "traffic": traffic_from_profile(args.als_form, source="als_coop_body.h",
                                             profile=f"als_coop_{args.als_form}_dense1000_counters.md"),
             "kernel": f"als_coop_kernel ({args.als_form} slab contractions, FP64 solves; "
                       f"{args.iters} sweeps of all {c.P} replicas per launch)",

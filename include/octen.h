@@ -115,6 +115,13 @@ enum {
                                             write back and invalidate the L2,
                                             also where all of them run on one
                                             XCD (same results, slower)        */
+#define OCTEN_FLAG_ALS_FEW_WG 0x20ull    /* ALS: the fewest workgroups per
+                                            replica whose slab fits in LDS
+                                            (default: enough to spread about
+                                            2e5 FMAs per workgroup and sweep);
+                                            for handles of a group, whose
+                                            cooperative ALS then share launches
+                                            with more handles               */
 
 /* Stages timed with OCTEN_FLAG_TIMING (octen_stage_time). */
 enum {
@@ -356,10 +363,13 @@ octen_status octen_autotune_als(octen_t h, int32_t sweeps, int32_t* choice_host)
  * The caller rewrites the batch buffers in place between steps.  Every
  * handle must share one stream and hold replica factors already (its first
  * batch goes through its own calls).  Handles
- * whose ALS is a cooperative grid run it after the branches join, one after
- * the other (no cooperative grid shares the GPU with other work of the
- * step); the others (OCTEN_FLAG_ALS_ONE_WG, or replicas too large) run it in
- * their branch, one workgroup per replica.
+ * whose ALS is a cooperative grid run it after the branches join (no
+ * cooperative grid shares the GPU with other work of the step): handles
+ * whose ALS runs the same kernel (summary precision, contraction form, slab
+ * placement and rank class) share one cooperative launch, up to 16 handles,
+ * while all their workgroups fit on the device at once.  The others
+ * (OCTEN_FLAG_ALS_ONE_WG, or replicas too large) run it in their branch, one
+ * workgroup per replica.
  * Recovery stays per handle, outside the graph. */
 typedef struct octen_group* octen_group_t;
 typedef struct {
@@ -379,6 +389,9 @@ octen_status octen_group_create(const octen_t* handles, int32_t n, octen_group_t
  * captured graph was replayed. */
 octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int32_t max_iters,
                               double tol, int32_t init_mode, int32_t* replayed_host);
+/* Number of cooperative ALS launches in the graph of the latest captured
+ * step (0 before the first step, or when the ALS runs in the branches). */
+octen_status octen_group_als_launches(octen_group_t g, int32_t* out_host);
 octen_status octen_group_destroy(octen_group_t g);
 const char* octen_group_last_error(octen_group_t g);
 

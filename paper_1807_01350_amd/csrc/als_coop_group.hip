@@ -1,0 +1,128 @@
+// Several handles' replica ALS in one cooperative launch; the kernel body
+// is in als_coop_body.h.
+#include <vector>
+
+#include "als_coop_body.h"
+
+namespace octen {
+namespace {
+
+// Several handles' ALS in one cooperative grid: member e owns workgroups
+// start[e] .. start[e + 1] - 1 (each range a multiple of 8 long, so that a
+// workgroup's XCD is the same as in a launch of its own).
+constexpr int GROUP_MAX = 16;
+struct CoopGroup {
+  int n;
+  int start[GROUP_MAX + 1];
+  CoopArgs a[GROUP_MAX];
+};
+
+static_assert(sizeof(CoopGroup) <= 4096, "kernel argument block");
+
+template <typename T, int RMAX, bool GX, bool SPLIT>
+__global__ __launch_bounds__(NT) void als_coop_group_kernel(CoopGroup G) {
+  const int b = blockIdx.x;
+  int e = 0;
+  for (int i = 1; i < G.n; ++i) e += b >= G.start[i] ? 1 : 0;
+  e = __builtin_amdgcn_readfirstlane(e);
+  als_coop_body<T, RMAX, GX, SPLIT>(G.a[e], b - G.start[e]);
+}
+
+template <int RM>
+const void* pick_group(bool split, bool gx, bool f64) {
+  if (split)
+    return gx ? (const void*)als_coop_group_kernel<float, RM, true, true>
+              : (const void*)als_coop_group_kernel<float, RM, false, true>;
+  if (gx)
+    return f64 ? (const void*)als_coop_group_kernel<double, RM, true, false>
+               : (const void*)als_coop_group_kernel<float, RM, true, false>;
+  return f64 ? (const void*)als_coop_group_kernel<double, RM, false, false>
+             : (const void*)als_coop_group_kernel<float, RM, false, false>;
+}
+
+// The group kernel of an item: items of equal kernels may share a launch.
+const void* group_fn(const AlsCoopItem& it) {
+  const bool sp = it.split, gx = it.slab_global, f = it.y_f64;
+  switch (rmax_class(it.R)) {
+    case 6: return pick_group<6>(sp, gx, f);
+    case 8: return pick_group<8>(sp, gx, f);
+    case 10: return pick_group<10>(sp, gx, f);
+    case 12: return pick_group<12>(sp, gx, f);
+    case 16: return pick_group<16>(sp, gx, f);
+    case 20: return pick_group<20>(sp, gx, f);
+    case 24: return pick_group<24>(sp, gx, f);
+    default: return pick_group<32>(sp, gx, f);
+  }
+}
+
+// Workgroups of fn that fit on the device at once with lds bytes of LDS each.
+hipError_t coop_capacity(const void* fn, size_t lds, int& cap) {
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0, per = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, NT, lds);
+  cap = per * cus;
+  return e;
+}
+
+}  // namespace
+
+hipError_t als_coop_group(hipStream_t s, const AlsCoopItem* items, int n, int* launches) {
+  int nl = 0;
+  std::vector<CoopArgs> args(n);
+  std::vector<size_t> lds(n);
+  std::vector<bool> done(n, false);
+  for (int i = 0; i < n; ++i)
+    if (!coop_args(items[i], args[i], lds[i])) return hipErrorInvalidValue;
+  // members in handle order: each pack takes the next handles of the same
+  // kernel while their workgroups fit on the device at once
+  for (int i = 0; i < n; ++i) {
+    if (done[i]) continue;
+    const void* gfn = group_fn(items[i]);
+    std::vector<int> pack{i};
+    done[i] = true;
+    size_t plds = lds[i];
+    int used = coop_grid(args[i]);
+    for (int j = i + 1; gfn && j < n && (int)pack.size() < GROUP_MAX; ++j) {
+      if (done[j] || group_fn(items[j]) != gfn) continue;
+      const size_t l2 = lds[j] > plds ? lds[j] : plds;
+      int cap = 0;
+      hipError_t e = coop_capacity(gfn, l2, cap);
+      if (e != hipSuccess) return e;
+      if (used + coop_grid(args[j]) > cap) continue;
+      pack.push_back(j);
+      done[j] = true;
+      plds = l2;
+      used += coop_grid(args[j]);
+    }
+    hipError_t e;
+    if (pack.size() == 1) {
+      const AlsCoopItem& it = items[i];
+      e = als_coop(s, it.Y, it.y_f64, it.P, it.Q, it.R, it.NW, it.slab_global, it.init, it.F,
+                   it.lam, it.iters, it.flags, it.slots, it.counters, it.err, it.max_iters, it.tol,
+                   it.allow_local, it.split, true);
+    } else {
+      CoopGroup G;
+      G.n = (int)pack.size();
+      int off = 0;
+      for (int k = 0; k < G.n; ++k) {
+        G.start[k] = off;
+        G.a[k] = args[pack[k]];
+        off += coop_grid(args[pack[k]]);
+      }
+      for (int k = G.n; k <= GROUP_MAX; ++k) G.start[k] = off;
+      e = hipFuncSetAttribute(gfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds);
+      void* kargs[] = {&G};
+      if (e == hipSuccess)
+        e = hipLaunchCooperativeKernel(gfn, dim3(off), dim3(NT), kargs, (unsigned)plds, s);
+    }
+    if (e != hipSuccess) return e;
+    ++nl;
+  }
+  if (launches) *launches = nl;
+  return hipSuccess;
+}
+
+}  // namespace octen

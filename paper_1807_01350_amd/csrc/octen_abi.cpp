@@ -118,6 +118,7 @@ struct octen_ctx {
 
   std::vector<void*> allocs;
   bool group_mode = false;       // inside a group step: one workgroup per replica ALS
+  AlsCoopItem* als_defer = nullptr;  // set: the cooperative ALS launch is left to the caller
 
   // stage timing (OCTEN_FLAG_TIMING): ring of event pairs per stage
   std::vector<hipEvent_t> ev[OCTEN_NUM_STAGES];   // 2 * OCTEN_TIMING_RING
@@ -251,7 +252,7 @@ octen_status validate(const octen_config* c, std::string* msg) {
   int64_t M1 = (int64_t)c->S + (int64_t)c->P * (c->Q - c->S);
   if (M1 > (1 << 20)) { *msg = "too many compression columns"; return OCTEN_ERR_ARG; }
   const uint64_t known = OCTEN_FLAG_REFERENCE_PATH | OCTEN_FLAG_TIMING | OCTEN_FLAG_ALS_ONE_WG |
-                         OCTEN_FLAG_ALS_DEVICE_SYNC;
+                         OCTEN_FLAG_ALS_DEVICE_SYNC | OCTEN_FLAG_ALS_FEW_WG;
   if (c->flags & ~known) { *msg = "unknown flag bits"; return OCTEN_ERR_ARG; }
   return OCTEN_OK;
 }
@@ -481,7 +482,7 @@ octen_status octen_init(const octen_config* cfg, const double* U, const double* 
     if (max_nw >= 1) {
       const size_t lds_cap = 160 * 1024;
       const double work = 4.0 * (double)Q * Q * Q * R;
-      int nw = (int)ceil(work / 2.0e5);
+      int nw = (cfg->flags & OCTEN_FLAG_ALS_FEW_WG) ? 1 : (int)ceil(work / 2.0e5);
       if (nw < 1) nw = 1;
       if (nw > max_nw) nw = max_nw;
       bool gx = false;
@@ -773,6 +774,16 @@ octen_status ws_features(octen_t h) {
   return OCTEN_OK;
 }
 
+// After the replica ALS: a replica whose fit failed gets its starting factors
+// back; the factors are current.
+octen_status als_finish(octen_t h) {
+  HIPCHK(h, als_commit(h->stream, h->P, 3 * h->Q * h->R, h->R, h->F, h->lam, h->F0, h->lam0,
+                       h->flags, h->health));
+  h->have_factors = true;
+  h->factors_fresh = true;
+  return OCTEN_OK;
+}
+
 // features -> network -> candidate -> judge; the chosen start goes to ws_init
 octen_status learned_init(octen_t h) {
   OKCHK(ws_features(h));
@@ -828,6 +839,14 @@ octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int
     HIPCHK(h, als_prep(s, (int64_t)h->P * QR3, h->F0, src, (int64_t)h->P * h->R, h->lam0,
                        fresh ? nullptr : h->lam, h->P, h->flags, coop ? h->als_ctr : nullptr,
                        2 * h->P, coop ? h->als_err : nullptr));
+    if (coop && h->als_defer) {
+      // a group step launches it with other handles' ALS, then calls als_finish
+      *h->als_defer = AlsCoopItem{h->Y, h->acc_f64, h->P, h->Q, h->R, h->als_nw, h->als_gx, src,
+                                  h->F, h->lam, h->iters, h->flags, h->als_slots, h->als_ctr,
+                                  h->als_err, max_iters, tol,
+                                  !(h->cfg.flags & OCTEN_FLAG_ALS_DEVICE_SYNC), h->als_split};
+      return OCTEN_OK;
+    }
     if (coop) {
       e = als_coop(s, h->Y, h->acc_f64, h->P, h->Q, h->R, h->als_nw, h->als_gx, src, h->F,
                    h->lam, h->iters, h->flags, h->als_slots, h->als_ctr, h->als_err, max_iters,
@@ -843,11 +862,8 @@ octen_status octen_cp_als_replicas(octen_t h, int32_t max_iters, double tol, int
     if (e != hipSuccess)
       HIPCHK(h, als_reference(s, h->Y, h->acc_f64, h->P, h->Q, h->R, src, h->F, h->lam, h->iters,
                               h->flags, max_iters, tol));
-    HIPCHK(h, als_commit(s, h->P, (int)QR3, h->R, h->F, h->lam, h->F0, h->lam0, h->flags,
-                         h->health));
+    OKCHK(als_finish(h));
   }
-  h->have_factors = true;
-  h->factors_fresh = true;
   if (iters_done_host) {
     HIPCHK(h, hipMemcpyAsync(iters_done_host, h->iters, h->P * sizeof(int), hipMemcpyDeviceToHost, s));
     return report_health(h);
@@ -1290,6 +1306,7 @@ struct octen_group {
   int32_t cap_iters = 0;
   double cap_tol = 0.0;
   int32_t cap_init = 0;
+  int32_t als_launches = 0;               // cooperative ALS launches per captured step
   std::string err;
 };
 
@@ -1419,6 +1436,12 @@ octen_status octen_group_destroy(octen_group_t g) {
   return OCTEN_OK;
 }
 
+octen_status octen_group_als_launches(octen_group_t g, int32_t* out_host) {
+  if (!g || !out_host) return OCTEN_ERR_ARG;
+  *out_host = g->exec ? g->als_launches : 0;
+  return OCTEN_OK;
+}
+
 const char* octen_group_last_error(octen_group_t g) { return g ? g->err.c_str() : "null group"; }
 
 octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int32_t max_iters,
@@ -1501,18 +1524,42 @@ octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int
         if (he == hipSuccess) he = hipStreamWaitEvent(g->main, g->join[i], 0);
         done_i = i + 1;
       }
+      // after the join: every cooperative handle's starting point, then
+      // their ALS in as few cooperative launches as fit, then the commits
+      std::vector<AlsCoopItem> items;
+      std::vector<int> who;
       for (int i = 0; !parallel_als && i < n && st == OCTEN_OK && he == hipSuccess && done_i == n;
            ++i) {
         octen_t h = g->hs[i];
         if (!(h->als_nw > 0 && !(h->cfg.flags & OCTEN_FLAG_ALS_ONE_WG))) continue;
         const bool timing = h->timing;
+        AlsCoopItem it{};
         h->timing = false;
         h->stream = g->main;
+        h->als_defer = &it;
         st = octen_cp_als_replicas(h, max_iters, tol, init_mode, nullptr, nullptr);
+        h->als_defer = nullptr;
         h->stream = g->user;
         h->timing = timing;
         if (st != OCTEN_OK) g->err = "handle " + std::to_string(i) + ": " + h->err;
+        if (st == OCTEN_OK && it.P > 0) {   // deferred (else run and committed in the call)
+          items.push_back(it);
+          who.push_back(i);
+        }
       }
+      if (st == OCTEN_OK && he == hipSuccess && !items.empty()) {
+        int nl = 0;
+        he = als_coop_group(g->main, items.data(), (int)items.size(), &nl);
+        if (he == hipSuccess) g->als_launches = nl;
+      }
+      for (size_t k = 0; k < who.size() && st == OCTEN_OK && he == hipSuccess; ++k) {
+        octen_t h = g->hs[who[k]];
+        h->stream = g->main;
+        st = als_finish(h);
+        h->stream = g->user;
+        if (st != OCTEN_OK) g->err = "handle " + std::to_string(who[k]) + ": " + h->err;
+      }
+      if (parallel_als) g->als_launches = 0;
       const hipError_t ee = hipStreamEndCapture(g->main, &graph);
       if (st == OCTEN_OK && he == hipSuccess && ee == hipSuccess && done_i == n) break;
       if (graph) hipGraphDestroy(graph);

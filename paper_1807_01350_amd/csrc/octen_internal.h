@@ -136,6 +136,29 @@ hipError_t als_coop(hipStream_t s, const void* Y, bool y_f64, int P, int Q, int 
                     bool slab_global, const double* init, double* F, double* lam, int* iters,
                     int* flags, double* slots, unsigned* counters, int* err, int max_iters,
                     double tol, bool allow_local, bool split, bool cleared = false);
+// One handle's cooperative ALS (the arguments of als_coop), for als_coop_group.
+struct AlsCoopItem {
+  const void* Y;
+  bool y_f64;
+  int P, Q, R, NW;
+  bool slab_global;
+  const double* init;
+  double* F;
+  double* lam;
+  int* iters;
+  int* flags;
+  double* slots;
+  unsigned* counters;
+  int* err;
+  int max_iters;
+  double tol;
+  bool allow_local, split;
+};
+// The cooperative ALS of n handles (counters and err already zero): handles
+// of the same kernel share a launch while all their workgroups fit on the
+// device at once, up to 16 per launch.
+// launches: NULL or the number of cooperative launches made.
+hipError_t als_coop_group(hipStream_t s, const AlsCoopItem* items, int n, int* launches);
 
 // -------------------------------------------------------------- recovery ---
 // lambda^(1/3), anchor similarity, exclusive greedy matching, scale alignment.

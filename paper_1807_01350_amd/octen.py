@@ -38,6 +38,7 @@ OCTEN_FLAG_REFERENCE_PATH = 0x2
 OCTEN_FLAG_TIMING = 0x4
 OCTEN_FLAG_ALS_ONE_WG = 0x8
 OCTEN_FLAG_ALS_DEVICE_SYNC = 0x10
+OCTEN_FLAG_ALS_FEW_WG = 0x20
 (OCTEN_STAGE_COMPRESS_MAIN, OCTEN_STAGE_COMPRESS_MODE3, OCTEN_STAGE_UPDATE, OCTEN_STAGE_ALS,
  OCTEN_STAGE_RECOVER, OCTEN_STAGE_COO_INDEX) = range(6)
 
@@ -120,6 +121,7 @@ _SIGS = {
     "octen_autotune_als": ([_vp, _i32, _vp], _i32),
     "octen_group_create": ([_vp, _i32, ctypes.POINTER(_vp)], _i32),
     "octen_group_step": ([_vp, _vp, _i32, _f64, _i32, _vp], _i32),
+    "octen_group_als_launches": ([_vp, _vp], _i32),
     "octen_group_destroy": ([_vp], _i32),
     "octen_group_last_error": ([_vp], ctypes.c_char_p),
     "octen_warmstart_set": ([_vp, _vp, _vp, _i32], _i32),
@@ -345,6 +347,10 @@ def octen_group_step(g, descs, max_iters, tol, init_mode=OCTEN_INIT_PREV, replay
                                  int(init_mode), replayed)
 
 
+def octen_group_als_launches(g, out):
+    return _lib.octen_group_als_launches(g, out)
+
+
 def octen_group_destroy(g):
     return _lib.octen_group_destroy(g)
 
@@ -377,6 +383,14 @@ class Group:
         for e, (X, _) in zip(self.engines, batches):
             e._pend += int(X.shape[0])
         return bool(rep.value)
+
+    def als_launches(self):
+        """Cooperative ALS launches in the graph of the latest captured step."""
+        n = ctypes.c_int32(0)
+        st = octen_group_als_launches(self.g, ctypes.cast(ctypes.byref(n), _vp))
+        if st != OCTEN_OK:
+            raise OctenError(st, "octen_group_als_launches", octen_group_last_error(self.g))
+        return int(n.value)
 
     def close(self):
         if getattr(self, "g", None):

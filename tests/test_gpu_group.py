@@ -339,3 +339,62 @@ def test_small_group_runs_cooperative_als_after_the_join():
     group.close()
     for e in grp + twin:
         e.close()
+
+
+def test_group_packs_cooperative_als_of_equal_kernels():
+    """After the join, handles whose ALS runs the same kernel share one
+    cooperative launch (four float-summary FP64-solve handles of rank class
+    6, two of them with the fewest workgroups per replica); a two-term handle
+    takes a launch of its own.  Every replica's result
+    equals the handle-by-handle cooperative calls bit for bit (the
+    convergence test on, so members may stop at different sweeps)."""
+    import torch
+    from paper_1807_01350_amd import octen as oc
+    shapes = [(120, 100, 5, 4, 20, 3, 24, 6, "bf16x2"), (140, 90, 6, 6, 24, 3, 30, 8, "bf16x2"),
+              (100, 130, 5, 8, 22, 3, 20, 5, "f32"), (90, 110, 6, 5, 26, 3, 24, 6, "bf16"),
+              (110, 96, 5, 4, 24, 3, 20, 5, "bf16x2")]
+    als = ["f64", "f64", "f64", "f64", "bf16x2"]
+    streams = _streams(shapes, 120)
+    grp, twin, bufs = [], [], []
+    for q, ((c, form, X, U, V, Ws, init), ad) in enumerate(zip(streams, als)):
+        fl = oc.OCTEN_FLAG_ALS_FEW_WG if q in (1, 3) else 0
+        pair = [oc.Octen(c.I, c.J, c.R, c.P, c.Q, c.S, U, V, x_dtype="f32", compress_dtype=form,
+                         als_dtype=ad, flags=fl) for _ in range(2)]
+        for e in pair:
+            e.compress_batch(X[:c.batches[0]], Ws[0]); e.update_replicas()
+            e.cp_als_replicas(20, init=init)
+            e.recover_factors(torch.empty((c.I, c.R), dtype=torch.float64, device="cuda"),
+                              torch.empty((c.J, c.R), dtype=torch.float64, device="cuda"),
+                              torch.empty((c.K, c.R), dtype=torch.float64, device="cuda"))
+        grp.append(pair[0]); twin.append(pair[1])
+        bufs.append((torch.empty_like(X[:c.batches[1]]), torch.empty_like(Ws[1])))
+    group = oc.Group(grp)
+    flags, iters = [], set()
+    for r in (1, 2, 3):
+        print(f"[group] packed ALS round {r}", file=sys.stderr, flush=True)
+        for (c, form, X, U, V, Ws, init), (xb, wb) in zip(streams, bufs):
+            k0 = sum(c.batches[:r])
+            xb.copy_(X[k0:k0 + c.batches[r]]); wb.copy_(Ws[r])
+        flags.append(group.step(bufs, 20, 1e-6))
+        for e, (xb, wb) in zip(twin, bufs):
+            e.compress_batch(xb, wb); e.update_replicas(); e.cp_als_replicas(20, tol=1e-6)
+        torch.cuda.synchronize()
+        _ = (torch.randn(512, 512, device="cuda") @ torch.randn(512, 512, device="cuda")).sum()
+        torch.cuda.synchronize()
+        for q, (g, e, (c, *_r)) in enumerate(zip(grp, twin, streams)):
+            for what in (oc.OCTEN_STATE_Y, oc.OCTEN_STATE_FACTORS, oc.OCTEN_STATE_LAMBDA,
+                         oc.OCTEN_STATE_ITERS, oc.OCTEN_STATE_FLAGS):
+                a, b = g.state(what).cpu().numpy(), e.state(what).cpu().numpy()
+                assert np.array_equal(a, b), (r, q, what)
+            iters.update(int(v) for v in g.state(oc.OCTEN_STATE_ITERS).cpu().numpy())
+            assert not g.state(oc.OCTEN_STATE_FLAGS).cpu().numpy().any(), (r, q)
+            for e2 in (g, e):
+                e2.recover_factors(torch.empty((c.I, c.R), dtype=torch.float64, device="cuda"),
+                                   torch.empty((c.J, c.R), dtype=torch.float64, device="cuda"),
+                                   torch.empty((c.K, c.R), dtype=torch.float64, device="cuda"))
+    assert flags == [False, True, True]
+    assert group.als_launches() == 2
+    print(f"[group] sweep counts seen: {sorted(iters)}", file=sys.stderr, flush=True)
+    group.close()
+    for e in grp + twin:
+        e.close()
