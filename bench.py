@@ -103,14 +103,17 @@ def gen_stream(torch, I, J, K, R, sigma, seed, dev):
 def traffic_from_profile(form, source="compress_mfma.hip", profile=None):
     """HBM bytes per launch of a kernel (by default the compression kernel of
     the given form) from the committed rocprofv3 counter summary, if it was
-    taken on the current source of that kernel."""
+    taken on the current source of that kernel (one file, or several hashed
+    in the order given)."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1807_01350_amd", "csrc", source)
+    srcs = (source,) if isinstance(source, str) else tuple(source)
     prof = os.path.join(ROOT, "profiles",
                         profile or f"compress_pipe_{form}_dense1000_counters.md")
     if not os.path.exists(prof):
         return None
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    blob = b"".join(open(os.path.join(ROOT, "paper_1807_01350_amd", "csrc", f), "rb").read()
+                    for f in srcs)
+    h = hashlib.sha256(blob).hexdigest()[:16]
     txt = open(prof).read()
     m = re.search(r"source_sha256_16:\s*([0-9a-f]{16})", txt)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
@@ -857,7 +860,8 @@ def run_dense(args):
     als_xtf = als_exec / (als_ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(als_xtf, 3), "peak": MFMA_PEAK_TFLOPS[als_pk],
             "unit": "TFLOP/s", "frac": round(als_xtf / MFMA_PEAK_TFLOPS[als_pk], 5),
-            "traffic": traffic_from_profile(args.als_form, source="als_coop_body.h",
+            "traffic": traffic_from_profile(args.als_form,
+                                            source=("als_coop_body.h", "als_coop_kernel_body.inc"),
                                             profile=f"als_coop_{args.als_form}_dense1000_counters.md"),
             "kernel": f"als_coop_kernel ({args.als_form} slab contractions, FP64 solves; "
                       f"{args.iters} sweeps of all {c.P} replicas per launch)",

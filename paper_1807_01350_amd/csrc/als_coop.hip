@@ -1,5 +1,5 @@
-// Cooperative launch of one handle's replica ALS; the kernel body is in
-// als_coop_body.h.
+// Cooperative launch of one handle's replica ALS (the kernel's statements are
+// in als_coop_kernel_body.inc, its helpers in als_coop_body.h).
 #include "als_coop_body.h"
 
 namespace octen {
@@ -7,7 +7,8 @@ namespace {
 
 template <typename T, int RMAX, bool GX, bool SPLIT>
 __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
-  als_coop_body<T, RMAX, GX, SPLIT>(g, blockIdx.x);
+  const unsigned bid = blockIdx.x;
+#include "als_coop_kernel_body.inc"
 }
 
 template <int RM>

@@ -1,6 +1,7 @@
-// Device code of the cooperative replica ALS, shared by the launch of one
-// handle (als_coop.hip) and the grouped launch of several handles
-// (als_coop_group.hip).
+// Types and device helpers of the cooperative replica ALS kernel, shared by
+// the launch of one handle (als_coop.hip) and the grouped launch of several
+// handles (als_coop_group.hip); the kernel's statements are in
+// als_coop_kernel_body.inc.
 //
 // Per-replica CP-ALS across many workgroups (Sec. 4.1: each replica summary
 // is decomposed on its own; the model and unfoldings are those of Sec. 2).
@@ -508,657 +509,6 @@ __device__ __forceinline__ double sum_slots(const double* base, int64_t stride, 
 // SPLIT (float summaries only): the two contractions T and M3 take their
 // operands in the two-term bfloat16 form above; the factor C and the rows W
 // are kept in that form in LDS as B-operand fragments (Cb, Wb).
-// The ALS of workgroup `bid` of a launch over the replicas of one handle.
-template <typename T, int RMAX, bool GX, bool SPLIT>
-__device__ __forceinline__ void als_coop_body(const CoopArgs& g, const int bid) {
-  static_assert(!SPLIT || sizeof(T) == 4, "the two-term form takes float summaries");
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_ok, s_bad, s_stop, s_local;
-  __shared__ double s_nx2, s_fit_old;
-  __shared__ int s_have_old;
-
-  // placement: workgroup x -> XCD x % 8; replicas p = x % 8 + 8 k live there
-  const int xcd = bid % 8, loc = bid / 8;
-  const int p = xcd + 8 * (loc / g.NW);
-  const int w = loc % g.NW;
-  if (p >= g.P) return;
-
-  const int Q = g.Q, R = g.R, NW = g.NW, QR = Q * R, RR = R * R;
-  const int tid = threadIdx.x, wave = tid / 64, lane = tid & 63;
-  const int a0 = (int)((int64_t)w * Q / NW), a1 = (int)((int64_t)(w + 1) * Q / NW);
-  const int na = a1 - a0;
-  const int npair = na * Q;                   // rows (a, b) of the slab
-  // LDS slab: rows padded to npair_pad and columns to QPAD (a multiple of
-  // 32) with zeros, plus one column against bank conflicts, so that the MFMA
-  // loops run whole groups of 32 without clamping (Cf carries QPAD rows, Ts
-  // npair_pad rows, zero past the data)
-  const int QPAD = ((Q + 31) / 32) * 32;
-  const int QP = GX ? Q : QPAD + 1;           // slab row stride
-  const int RT = (R + 15) / 16;               // 16-wide tiles over r
-  const FastDiv fR(R), fQ(Q);
-  const int64_t Q2 = (int64_t)Q * Q;
-
-  double* Ts = (double*)smem;                 // [npair_pad][R]  T, then W
-  double* Bf = Ts + (int64_t)g.npair_pad * R; // [Q][R]
-  double* Cf = Bf + QR;                       // [QPAD][R]
-  double* Mf = Cf + QPAD * R;                 // reduced M2 / M3
-  double* Ml = Mf + QR;                       // [Q][R] scratch (M1 rows)
-  double* Al = Ml + QR;                       // [na_max][R]
-  double* G = Al + g.na_max * R;              // [R][R]
-  double* Gi = G + RR;                        // inverse
-  double* AtA = Gi + RR;
-  double* BtB = AtA + RR;
-  double* CtC = BtB + RR;
-  double* lamv = CtC + RR;                    // [MAXR]
-  double* rlam = lamv + MAXR;                 // [MAXR] 1 / lamv
-  double* scr = rlam + MAXR;                  // [NT]
-  // the mode-2/3 solves on MFMA with the partial Grams from the result
-  // fragments, which go where T is (T is dead from the end of mode 2 to the
-  // next sweep), when they fit there and the factors have enough rows to
-  // pay for it (below 40 rows the all-thread solve, column norms and Gram
-  // are faster)
-  const int nslot = min(NT / 64, (Q + 15) / 16);
-  const bool pg = Q >= 40 && nslot * RR <= g.npair_pad * R;
-  // SPLIT: B-operand fragments, [r tile][k chunk of 32][hi, lo][lane][8],
-  // 16-byte aligned; those of W take the place of T when they fit there (T
-  // is dead from the end of mode 2 to the next sweep)
-  const int nkc = QPAD / 32, npc = g.npair_pad / 32;
-  const bool walias = SPLIT && R >= 8 * RT;
-  __bf16* Cb = (__bf16*)(SPLIT ? ((uintptr_t)(scr + NT) + 15) & ~(uintptr_t)15
-                               : (uintptr_t)(scr + NT));                      // C: k = c
-  __bf16* Wb = walias ? (__bf16*)Ts : Cb + (SPLIT ? (int64_t)RT * nkc * 2 * 512 : 0);   // W: k = pair
-  unsigned char* after_frag = (unsigned char*)(
-      Cb + (SPLIT ? (int64_t)RT * nkc * 2 * 512 + (walias ? 0 : (int64_t)RT * npc * 2 * 512) : 0));
-  // fragments of C (after every update of C); with scale, C is first
-  // normalised in place (each element of C belongs to exactly one fragment
-  // entry, so the thread that scales it is the one that reads it)
-  auto build_cb = [&](bool scale) {
-    for (int e = tid; e < RT * nkc * 64; e += NT) {
-      const int ln = e & 63, kc = (e >> 6) % nkc, rt = (e >> 6) / nkc;
-      const int r = rt * 16 + (ln & 15);
-      float v[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int c = kc * 32 + 8 * (ln >> 4) + j;
-        double x = 0.0;
-        if (c < Q && r < R) {
-          x = Cf[c * R + r];
-          if (scale) {
-            x *= rlam[r];
-            Cf[c * R + r] = x;
-          }
-        }
-        v[j] = (float)x;
-      }
-      bf16x8a hi, lo;
-      split8(v, hi, lo);
-      __bf16* dst = Cb + ((int64_t)(rt * nkc + kc) * 2 * 64 + ln) * 8;
-      *(bf16x8a*)dst = hi;
-      *(bf16x8a*)(dst + 512) = lo;
-    }
-  };
-  const T* Xp = (const T*)g.Y + (int64_t)p * Q2 * Q;
-  const T* Xs;                                // [na * Q][QP] (LDS: [npair_pad][QP])
-  if constexpr (GX) {
-    Xs = Xp + (int64_t)a0 * Q2;
-  } else {
-    T* xl = (T*)after_frag;
-    const FastDiv fQP(QP);
-    for (int e = tid; e < g.npair_pad * QP; e += NT) {
-      const int row = fQP.div(e), col = e - row * QP;
-      xl[e] = (row < npair && col < Q) ? Xp[(int64_t)a0 * Q2 + (int64_t)row * Q + col] : (T)0;
-    }
-    Xs = xl;
-  }
-  for (int e = npair * R + tid; e < g.npair_pad * R; e += NT) Ts[e] = 0.0;
-  for (int e = QR + tid; e < QPAD * R; e += NT) Cf[e] = 0.0;
-  const double* F0 = g.init + (int64_t)p * 3 * QR;
-  for (int e = tid; e < na * R; e += NT) Al[e] = F0[a0 * R + e];
-  for (int e = tid; e < QR; e += NT) { Bf[e] = F0[QR + e]; Cf[e] = F0[2 * QR + e]; }
-  if (tid == 0) { s_bad = 0; s_stop = 0; s_have_old = 0; s_fit_old = 0.0; s_nx2 = 0.0; }
-  __syncthreads();
-
-  unsigned* ctr = g.counters + p;
-  unsigned nbar = 0;
-  bool alive = true;
-  // a replica whose workgroups all landed on one XCD synchronises through
-  // that XCD's L2 (the placement above asks for this; the mask checks it)
-  bool local = false;
-  if (NW > 1) {
-    unsigned* xmask = g.counters + g.P + p;
-    if (tid == 0)
-      __hip_atomic_fetch_or(xmask, 1u << xcd_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok, false);
-    if (tid == 0)
-      s_local = __popc(__hip_atomic_load(xmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 1;
-    __syncthreads();
-    local = alive && s_local && g.allow_local;
-  }
-  const int slot_len = g.slot_len;
-  // the slot set alternates with the barrier count: a set is rewritten two
-  // barriers later, when every workgroup has finished reading it
-  auto slot = [&](int set, int ww) {
-    return g.slots + (((int64_t)set * g.P + p) * NW + ww) * slot_len;
-  };
-
-  if (g.tol > 0.0) {
-    double s = 0.0;
-    for (int64_t e = tid; e < (int64_t)npair * Q; e += NT) {
-      const double v = (double)Xs[(e / Q) * QP + e % Q];
-      s = fma(v, v, s);
-    }
-    scr[tid] = s;
-    __syncthreads();
-    for (int st = NT / 2; st > 0; st >>= 1) {
-      if (tid < st) scr[tid] += scr[tid + st];
-      __syncthreads();
-    }
-    if (NW > 1) {
-      const int bs = (nbar + 1) & 1;
-      if (tid == 0) slot(bs, w)[0] = scr[0];
-      alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok, local) && alive;
-      if (alive && tid == 0) {
-        double t = 0.0;
-        for (int ww = 0; ww < NW; ++ww) t += slot_load(slot(bs, ww));
-        s_nx2 = t;
-      }
-    } else if (tid == 0) {
-      s_nx2 = scr[0];
-    }
-    __syncthreads();
-  }
-  if (wave == 0) gram_wave(Bf, Q, R, BtB);
-  if (wave == 1) gram_wave(Cf, Q, R, CtC);
-  if constexpr (SPLIT) build_cb(false);
-  __syncthreads();
-
-
-  int done = 0;
-  for (int it = 0; it < g.max_iters && alive; ++it) {
-    // ------------------------------------------------ mode 1 (rows of A)
-    // wavefront 0 forms G1 = B'B o C'C itself (both complete: the sweep
-    // before ended with a barrier) while the others start on T
-    if (wave == 0) {
-      for (int e = lane; e < RR; e += 64) G[e] = BtB[e] * CtC[e];
-      wave_sync();
-      spd_inverse<RMAX>(G, Gi, R, &s_bad);
-    }
-    {
-      // T(pair, r) = sum_c X(pair, c) C(c, r) on MFMA, tiles over pairs x r,
-      // dealt to the six wavefronts that do not share a SIMD with the
-      // inverting wavefront 0 (wavefront w runs on SIMD w % 4: wavefront 4
-      // stays idle, so the inverse's FP64 arithmetic does not compete with
-      // FP64 MFMA on its SIMD); when one tile is left over after at least
-      // two whole rounds, wavefront 0 takes it after the inverse
-      constexpr int NMW = NT / 64 - 2;
-      const int mw = wave < 4 ? wave - 1 : wave - 2;     // 0..5 for the MFMA wavefronts
-      const int ntile = (npair + 15) / 16 * RT;
-      const bool w0_tile = ntile % NMW == 1 && ntile > 2 * NMW;
-      const int t_first = wave == 0 ? (w0_tile ? ntile - 1 : ntile) : (wave == 4 ? ntile : mw);
-      const int t_end = wave == 0 || !w0_tile ? ntile : ntile - 1;
-      const int t_step = wave == 0 ? 1 : NMW;
-      for (int tt = t_first; tt < t_end; tt += t_step) {
-        const int pt = tt / RT, rt = tt % RT;
-        const int pr = pt * 16 + lane % 16;
-        const int rr = rt * 16 + lane % 16;
-        if constexpr (SPLIT) {
-          f32x4a acc = {0.f, 0.f, 0.f, 0.f};
-          const __bf16* cb = Cb + ((int64_t)rt * nkc * 2 * 64 + lane) * 8;
-          for (int kc = 0; kc < nkc; ++kc) {
-            float v[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              const int c = kc * 32 + 8 * (lane >> 4) + j;
-              if constexpr (GX) v[j] = (pr < npair && c < Q) ? (float)Xs[(int64_t)pr * QP + c] : 0.f;
-              else v[j] = (float)Xs[pr * QP + c];
-            }
-            bf16x8a ah, al;
-            split8(v, ah, al);
-            const bf16x8a bh = *(const bf16x8a*)(cb + (int64_t)kc * 2 * 512);
-            const bf16x8a bl = *(const bf16x8a*)(cb + (int64_t)kc * 2 * 512 + 512);
-            acc = mma3(ah, al, bh, bl, acc);
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int row = pt * 16 + 4 * (lane >> 4) + i;
-            if (row < npair && rr < R) Ts[row * R + rr] = (double)acc[i];
-          }
-          continue;
-        }
-        f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-        const bool okc = rr < R;
-        const double* cr = Cf + (okc ? rr : R - 1);
-        if constexpr (!GX) {
-          // LDS slab padded with zeros (rows and columns) and Cf with zero
-          // rows: groups of 32 columns (four steps of 8), all sixteen loads,
-          // then the conversions, then the eight MFMAs (a VALU instruction
-          // issued between MFMAs of one wavefront waits for them)
-          const T* xp = Xs + pr * QP + lane / 16;
-          const double* cp = cr + (lane / 16) * R;
-          for (int c0 = 0; c0 < Q; c0 += 32) {
-            T xv[8];
-            double bv[8], xd[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) { xv[u] = xp[4 * u]; bv[u] = cp[4 * u * R]; }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) xd[u] = (double)xv[u];
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int u = 0; u < 8; u += 2) {
-              acc0 = mfma64(xd[u], bv[u], acc0);
-              acc1 = mfma64(xd[u + 1], bv[u + 1], acc1);
-            }
-            __builtin_amdgcn_sched_barrier(0);
-            xp += 32;
-            cp += 32 * R;
-          }
-        } else {
-          const T* xr = Xs + (pr < npair ? pr : npair - 1) * QP;
-          // whole groups of 32 columns: all sixteen loads first, then the
-          // conversions, then the eight MFMAs (a VALU instruction issued
-          // between MFMAs of one wavefront waits for them); same order of
-          // accumulation as the step loop below
-          int c0 = 0;
-          {
-            const T* xp = xr + lane / 16;
-            const double* cp = cr + (lane / 16) * R;
-            for (; c0 + 32 <= Q; c0 += 32) {
-              T xv[8];
-              double bv[8], xd[8];
-#pragma unroll
-              for (int u = 0; u < 8; ++u) { xv[u] = xp[4 * u]; bv[u] = cp[4 * u * R]; }
-#pragma unroll
-              for (int u = 0; u < 8; ++u) xd[u] = (double)xv[u];
-              __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-              for (int u = 0; u < 8; u += 2) {
-                acc0 = mfma64(xd[u], bv[u], acc0);
-                acc1 = mfma64(xd[u + 1], bv[u + 1], acc1);
-              }
-              __builtin_amdgcn_sched_barrier(0);
-              xp += 32;
-              cp += 32 * R;
-            }
-          }
-          // the rest: indices clamped into range and the k tail zeroed after
-          // the load (no branches around the loads)
-          for (; c0 < Q; c0 += 8) {
-            const int c = c0 + lane / 16, c2 = c + 4;
-            const int cc = c < Q ? c : Q - 1, cc2 = c2 < Q ? c2 : Q - 1;
-            const double x0 = (double)xr[cc], x1 = (double)xr[cc2];
-            const double b0 = cr[cc * R], b1 = cr[cc2 * R];
-            acc0 = mfma64(c < Q ? x0 : 0.0, b0, acc0);
-            acc1 = mfma64(c2 < Q ? x1 : 0.0, b1, acc1);
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int row = pt * 16 + lane / 16 + 4 * i;
-          if (row < npair && okc) Ts[row * R + rr] = acc0[i] + acc1[i];
-        }
-      }
-    }
-    __syncthreads();
-    // M1(la, r) = sum_b T(la, b, r) B(b, r): eight lanes per entry split b,
-    // their partial sums are added across lanes in a fixed order
-    for (int base = 0; base < na * R * 8; base += NT) {
-      const int idx = base + tid, e = idx >> 3, sub = idx & 7;
-      double s0 = 0.0, s1 = 0.0;
-      if (e < na * R) {
-        const int la = fR.div(e), r = e - la * R;
-        const double* tr = Ts + (int64_t)la * QR + r;
-        const double* br = Bf + r;
-        int b = sub;
-        for (; b + 8 < Q; b += 16) {
-          s0 = fma(tr[b * R], br[b * R], s0);
-          s1 = fma(tr[(b + 8) * R], br[(b + 8) * R], s1);
-        }
-        if (b < Q) s0 = fma(tr[b * R], br[b * R], s0);
-      }
-      double sm = s0 + s1;
-      sm += __shfl_xor(sm, 1, 64);
-      sm += __shfl_xor(sm, 2, 64);
-      sm += __shfl_xor(sm, 4, 64);
-      if (e < na * R && sub == 0) Ml[e] = sm;
-    }
-    __syncthreads();
-    apply_inverse(Ml, Gi, Al, na, R);
-    __syncthreads();
-    // ------------------------------------------------ mode 2 partials
-    const int set1 = (nbar + 1) & 1;
-    double* sl = NW > 1 ? slot(set1, w) : nullptr;
-    for (int e = tid; e < QR + RR; e += NT) {
-      double s = 0.0;
-      if (e < QR) {
-        const int b = fR.div(e), r = e - b * R;
-        for (int la = 0; la < na; ++la) s = fma(Ts[((int64_t)la * Q + b) * R + r], Al[la * R + r], s);
-      } else {
-        const int r1 = fR.div(e - QR), r2 = e - QR - r1 * R;
-        for (int la = 0; la < na; ++la) s = fma(Al[la * R + r1], Al[la * R + r2], s);
-      }
-      if (NW > 1) sl[e] = s;
-      else if (e < QR) Mf[e] = s;
-      else AtA[e - QR] = s;
-    }
-    // sums of the partials: wavefront 0 takes A'A and goes on to lambda_A
-    // (norms from diag(A'A)), the normalised A'A, G2 and its inverse, while
-    // the other wavefronts sum M2
-    if (NW > 1) {
-      alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok, local);
-      if (!alive) break;
-      if (wave == 0) {
-        // two entries per lane, both sets of loads in flight together
-        for (int e = lane; e < RR; e += 128) {
-          const double* b0 = slot(set1, 0) + QR + e;
-          const bool two = e + 64 < RR;
-          double v0[16], v1[16];
-          double a0 = 0.0, a1 = 0.0;
-          for (int w0 = 0; w0 < NW; w0 += 16) {
-#pragma unroll
-            for (int u2 = 0; u2 < 16; ++u2) {
-              v0[u2] = w0 + u2 < NW ? slot_load(b0 + (int64_t)(w0 + u2) * slot_len) : 0.0;
-              v1[u2] = (two && w0 + u2 < NW) ? slot_load(b0 + (int64_t)(w0 + u2) * slot_len + 64) : 0.0;
-            }
-#pragma unroll
-            for (int u2 = 0; u2 < 16; ++u2)
-              if (w0 + u2 < NW) { a0 += v0[u2]; a1 += v1[u2]; }
-          }
-          AtA[e] = a0;
-          if (two) AtA[e + 64] = a1;
-        }
-      } else {
-        for (int e = tid - 64; e < QR; e += NT - 64) Mf[e] = sum_slots(slot(set1, 0) + e, slot_len, NW);
-      }
-    } else {
-      __syncthreads();
-    }
-    if (wave == 0) {
-      wave_sync();
-      if (lane < R) {
-        const double n = sqrt(AtA[lane * R + lane]);
-        const double l = n > 0.0 ? n : 1.0;
-        lamv[lane] = l;
-        rlam[lane] = 1.0 / l;
-      }
-      wave_sync();
-      for (int e = lane; e < RR; e += 64) {
-        AtA[e] *= rlam[fR.div(e)] * rlam[fR.mod(e)];
-        G[e] = AtA[e] * CtC[e];
-      }
-      wave_sync();
-      // ---------------------------------------------- mode 2 solve (B)
-      spd_inverse<RMAX>(G, Gi, R, &s_bad);
-      // M2 was formed with the unnormalised A: B = (M2 / lambda_A) G2^{-1},
-      // so row k of the inverse takes the factor 1 / lambda_A(k)
-      wave_sync();
-      for (int e = lane; e < RR; e += 64) Gi[e] *= rlam[fR.div(e)];
-    }
-    __syncthreads();
-    for (int e = tid; e < na * R; e += NT) Al[e] *= rlam[fR.mod(e)];
-    if (pg) apply_gram(Mf, Gi, Bf, Q, R, Ts);
-    else apply_inverse(Mf, Gi, Bf, Q, R);
-    __syncthreads();
-    // lambda_B and B'B of the normalised B from the partial Grams
-    if (pg) norm_gram(Ts, nslot, R, BtB, lamv, rlam);
-    else col_norms(Bf, Q, R, lamv, rlam);
-    __syncthreads();
-    for (int e = tid; e < QR; e += NT) Bf[e] *= rlam[fR.mod(e)];
-    __syncthreads();
-    // W(pair, r) = A(a, r) B(b, r) into Ts (B'B here when it was not formed
-    // above)
-    if (!pg) gram_all(Bf, Q, R, BtB);
-    if constexpr (SPLIT) {
-      // W(pair, r) = A(a, r) B(b, r) as B-operand fragments (k = pair)
-      for (int e = tid; e < RT * npc * 64; e += NT) {
-        const int ln = e & 63, pc = (e >> 6) % npc, rt = (e >> 6) / npc;
-        const int r = rt * 16 + (ln & 15);
-        float v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int pr = pc * 32 + 8 * (ln >> 4) + j;
-          const int a = fQ.div(pr), b = pr - a * Q;
-          v[j] = (pr < npair && r < R) ? (float)(Al[a * R + r] * Bf[b * R + r]) : 0.f;
-        }
-        bf16x8a hi, lo;
-        split8(v, hi, lo);
-        __bf16* dst = Wb + ((int64_t)(rt * npc + pc) * 2 * 64 + ln) * 8;
-        *(bf16x8a*)dst = hi;
-        *(bf16x8a*)(dst + 512) = lo;
-      }
-    } else {
-      for (int e = tid; e < npair * R; e += NT) {
-        const int pr = fR.div(e), r = e - pr * R;
-        const int a = fQ.div(pr), b = pr - a * Q;
-        Ts[e] = Al[a * R + r] * Bf[b * R + r];
-      }
-    }
-    __syncthreads();
-    // ------------------------------------------------ mode 3 partial
-    {
-      const int set2 = (nbar + 1) & 1;
-      double* dst = NW > 1 ? slot(set2, w) : Mf;
-      // M3(c, r) = sum_pair X(pair, c) W(pair, r): tiles over c x r; when the
-      // tiles are fewer than half the MFMA wavefronts, the pair range is cut
-      // in two and the second halves are added through LDS (fixed order)
-      const int ctiles = (Q + 15) / 16, ntl = ctiles * RT;
-      // when the tiles (and halves) fit on wavefronts 1-7, wavefront 0 forms
-      // and inverts G3 meanwhile; otherwise all eight wavefronts take tiles
-      // and the inverse waits until after the reduction below, where it
-      // overlaps the sum of the partials
-      const bool early = ntl * (2 * ntl <= NT / 64 - 1 ? 2 : 1) <= NT / 64 - 1;
-      const int NMW = early ? NT / 64 - 1 : NT / 64;
-      const int ksp = 2 * ntl <= NMW ? 2 : 1;
-      // pair range: padded to a multiple of 32 in LDS (zero rows), halves
-      // cut at a multiple of 32; from global memory, the exact range
-      const int npp = (GX && !SPLIT) ? npair : ((npair + 31) / 32) * 32;
-      const int kh = ksp == 1 ? npp
-                              : ((GX && !SPLIT) ? ((npair + 15) / 16) * 8 : ((npp / 32 + 1) / 2) * 32);
-      f64x4 keep = {0.0, 0.0, 0.0, 0.0};
-      int keep_tile = -1;
-      if (early && wave == 0) {
-        for (int e = lane; e < RR; e += 64) G[e] = AtA[e] * BtB[e];
-        wave_sync();
-        spd_inverse<RMAX>(G, Gi, R, &s_bad);
-      } else {
-        for (int item = early ? wave - 1 : wave; item < ntl * ksp; item += NMW) {
-          const int tt = item % ntl, part = item / ntl;
-          const int kb = part * kh, ke = kb + kh < npp ? kb + kh : npp;
-          const int ct = tt / RT, rt = tt % RT;
-          const int c = ct * 16 + lane % 16;
-          const int rr = rt * 16 + lane % 16;
-          if constexpr (SPLIT) {
-            // M3(c, r) = sum over pairs of X(pair, c) W(pair, r): A = X^T
-            f32x4a acc = {0.f, 0.f, 0.f, 0.f};
-            const __bf16* wb = Wb + ((int64_t)rt * npc * 2 * 64 + lane) * 8;
-            for (int k0 = kb; k0 < ke; k0 += 32) {
-              float v[8];
-#pragma unroll
-              for (int j = 0; j < 8; ++j) {
-                const int pr = k0 + 8 * (lane >> 4) + j;
-                if constexpr (GX) v[j] = (pr < npair && c < Q) ? (float)Xs[(int64_t)pr * QP + c] : 0.f;
-                else v[j] = (float)Xs[pr * QP + c];
-              }
-              bf16x8a ah, al;
-              split8(v, ah, al);
-              const int pc = k0 >> 5;
-              const bf16x8a bh = *(const bf16x8a*)(wb + (int64_t)pc * 2 * 512);
-              const bf16x8a bl = *(const bf16x8a*)(wb + (int64_t)pc * 2 * 512 + 512);
-              acc = mma3(ah, al, bh, bl, acc);
-            }
-            f64x4 accd;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) accd[i] = (double)acc[i];
-            if (ksp == 2 && part == 0) {
-              keep = accd;
-              keep_tile = tt;
-              continue;
-            }
-            double* o = ksp == 2 ? Ml : dst;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int row = ct * 16 + 4 * (lane >> 4) + i;
-              if (row < Q && rr < R) o[row * R + rr] = accd[i];
-            }
-            continue;
-          }
-          f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-          const bool okr = rr < R;
-          const double* wc = Ts + (okr ? rr : R - 1);
-          if constexpr (!GX) {
-            // zero-padded LDS slab and W: groups of 32 pairs as for T
-            const T* xp = Xs + c + (kb + lane / 16) * QP;
-            const double* wp = wc + (kb + lane / 16) * R;
-            for (int k0 = kb; k0 < ke; k0 += 32) {
-              T xv[8];
-              double bv[8], xd[8];
-#pragma unroll
-              for (int u = 0; u < 8; ++u) { xv[u] = xp[4 * u * QP]; bv[u] = wp[4 * u * R]; }
-#pragma unroll
-              for (int u = 0; u < 8; ++u) xd[u] = (double)xv[u];
-              __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-              for (int u = 0; u < 8; u += 2) {
-                acc0 = mfma64(xd[u], bv[u], acc0);
-                acc1 = mfma64(xd[u + 1], bv[u + 1], acc1);
-              }
-              __builtin_amdgcn_sched_barrier(0);
-              xp += 32 * QP;
-              wp += 32 * R;
-            }
-          } else {
-            const T* xc = Xs + (c < Q ? c : Q - 1);
-            // whole groups of 32 pairs as for T above, then the clamped steps
-            int k0 = kb;
-            {
-              const T* xp = xc + (kb + lane / 16) * QP;
-              const double* wp = wc + (kb + lane / 16) * R;
-              for (; k0 + 32 <= ke; k0 += 32) {
-                T xv[8];
-                double bv[8], xd[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) { xv[u] = xp[4 * u * QP]; bv[u] = wp[4 * u * R]; }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) xd[u] = (double)xv[u];
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int u = 0; u < 8; u += 2) {
-                  acc0 = mfma64(xd[u], bv[u], acc0);
-                  acc1 = mfma64(xd[u + 1], bv[u + 1], acc1);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                xp += 32 * QP;
-                wp += 32 * R;
-              }
-            }
-            for (; k0 < ke; k0 += 8) {
-              const int pr = k0 + lane / 16, pr2 = pr + 4;
-              const int pc = pr < ke ? pr : ke - 1, pc2 = pr2 < ke ? pr2 : ke - 1;
-              const double x0 = (double)xc[pc * QP], x1 = (double)xc[pc2 * QP];
-              const double b0 = wc[pc * R], b1 = wc[pc2 * R];
-              acc0 = mfma64(pr < ke ? x0 : 0.0, b0, acc0);
-              acc1 = mfma64(pr2 < ke ? x1 : 0.0, b1, acc1);
-            }
-          }
-          const f64x4 acc = acc0 + acc1;
-          if (ksp == 2 && part == 0) {
-            keep = acc;
-            keep_tile = tt;
-            continue;
-          }
-          double* o = ksp == 2 ? Ml : dst;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int row = ct * 16 + lane / 16 + 4 * i;
-            if (row < Q && okr) o[row * R + rr] = acc[i];
-          }
-        }
-      }
-      if (ksp == 2) {
-        __syncthreads();
-        if (keep_tile >= 0) {
-          const int ct = keep_tile / RT, rt = keep_tile % RT;
-          const int rr = rt * 16 + lane % 16;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int row = ct * 16 + (SPLIT ? 4 * (lane / 16) + i : lane / 16 + 4 * i);
-            if (row < Q && rr < R) dst[row * R + rr] = keep[i] + Ml[row * R + rr];
-          }
-        }
-      }
-      if (NW > 1) {
-        alive = replica_barrier(ctr, (++nbar) * NW, g.err, &s_ok, local);
-        if (!alive) break;
-        if (early)
-          for (int e = tid; e < QR; e += NT) Mf[e] = sum_slots(slot(set2, 0) + e, slot_len, NW);
-        else if (wave != 0)
-          for (int e = tid - 64; e < QR; e += NT - 64) Mf[e] = sum_slots(slot(set2, 0) + e, slot_len, NW);
-      }
-      if (wave == 0 && !early) {
-        // G3 = A'A o B'B (both complete) by wavefront 0 while the others
-        // sum the partials of M3
-        for (int e = lane; e < RR; e += 64) G[e] = AtA[e] * BtB[e];
-        wave_sync();
-        spd_inverse<RMAX>(G, Gi, R, &s_bad);
-      }
-    }
-    __syncthreads();
-    // ------------------------------------------------ mode 3 solve (C)
-    if (pg) apply_gram(Mf, Gi, Cf, Q, R, Ts);
-    else apply_inverse(Mf, Gi, Cf, Q, R);
-    __syncthreads();
-    if (pg) norm_gram(Ts, nslot, R, CtC, lamv, rlam);
-    else col_norms(Cf, Q, R, lamv, rlam);
-    __syncthreads();
-    // C normalised (and, two-term, its fragments)
-    if constexpr (SPLIT) build_cb(true);
-    else
-      for (int e = tid; e < QR; e += NT) Cf[e] *= rlam[fR.mod(e)];
-    __syncthreads();
-    if (!pg) {
-      gram_all(Cf, Q, R, CtC);
-      __syncthreads();
-    }
-    ++done;
-    if (g.tol > 0.0) {
-      // replica fit from the Gram identity, summed by wavefront 0 in a fixed
-      // order (every workgroup of the replica reaches the same decision)
-      if (wave == 0) {
-        double inner = 0.0, nh = 0.0;
-        for (int e = lane; e < QR; e += 64) inner = fma(Mf[e] * lamv[fR.mod(e)], Cf[e], inner);
-        for (int e = lane; e < RR; e += 64)
-          nh += lamv[fR.div(e)] * (AtA[e] * BtB[e] * CtC[e]) * lamv[fR.mod(e)];
-        for (int off = 32; off > 0; off >>= 1) {
-          inner += __shfl_xor(inner, off, 64);
-          nh += __shfl_xor(nh, off, 64);
-        }
-        if (lane == 0) {
-          double res = s_nx2 - 2.0 * inner + nh;
-          if (res < 0.0) res = 0.0;
-          const double fit = s_nx2 > 0.0 ? 1.0 - sqrt(res) / sqrt(s_nx2) : 0.0;
-          s_stop = (s_have_old && fabs(fit - s_fit_old) < g.tol) ? 1 : 0;
-          s_fit_old = fit;
-          s_have_old = 1;
-        }
-      }
-      __syncthreads();
-      if (s_stop) break;
-    }
-  }
-  // write back: slab rows of A from every workgroup; B, C, lambda from slab 0
-  double* Fo = g.F + (int64_t)p * 3 * QR;
-  for (int e = tid; e < na * R; e += NT) Fo[a0 * R + e] = Al[e];
-  if (w == 0) {
-    for (int e = tid; e < QR; e += NT) { Fo[QR + e] = Bf[e]; Fo[2 * QR + e] = Cf[e]; }
-    if (tid < R) g.lam[(int64_t)p * R + tid] = lamv[tid];
-    if (tid == 0) {
-      g.iters[p] = done;
-      if (s_bad) g.flags[p] |= 1;
-      if (!alive) g.flags[p] |= 2;
-    }
-  } else if (tid == 0 && s_bad) {
-    atomicOr(g.flags + p, 1);
-  }
-}
 
 
 inline int pad_pairs(int Q, int NW) {

@@ -1,5 +1,5 @@
-// Several handles' replica ALS in one cooperative launch; the kernel body
-// is in als_coop_body.h.
+// Several handles' replica ALS in one cooperative launch (the kernel's
+// statements are in als_coop_kernel_body.inc, its helpers in als_coop_body.h).
 #include <vector>
 
 #include "als_coop_body.h"
@@ -20,12 +20,13 @@ struct CoopGroup {
 static_assert(sizeof(CoopGroup) <= 4096, "kernel argument block");
 
 template <typename T, int RMAX, bool GX, bool SPLIT>
-__global__ __launch_bounds__(NT) void als_coop_group_kernel(CoopGroup G) {
-  const int b = blockIdx.x;
-  int e = 0;
-  for (int i = 1; i < G.n; ++i) e += b >= G.start[i] ? 1 : 0;
-  e = __builtin_amdgcn_readfirstlane(e);
-  als_coop_body<T, RMAX, GX, SPLIT>(G.a[e], b - G.start[e]);
+__global__ __launch_bounds__(NT) void als_coop_group_kernel(CoopGroup grp_) {
+  int m_ = 0;   // the member whose range holds this workgroup
+  for (int i_ = 1; i_ < grp_.n; ++i_) m_ += (int)blockIdx.x >= grp_.start[i_] ? 1 : 0;
+  m_ = __builtin_amdgcn_readfirstlane(m_);
+  const CoopArgs& g = grp_.a[m_];
+  const unsigned bid = blockIdx.x - (unsigned)grp_.start[m_];
+#include "als_coop_kernel_body.inc"
 }
 
 template <int RM>
