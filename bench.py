@@ -377,7 +377,8 @@ def run_batched(args):
     """Many independent dense FP32 streams of uneven sizes: one initial batch
     per stream through its own calls (autotuned compression), then rounds in
     which all streams' compress + update + ALS run as one captured HIP graph,
-    followed by recovery per stream.  Each round's slices are generated on the
+    followed by the recovery of all streams (octen_group_recover: each on a
+    stream of its own, concurrently).  Each round's slices are generated on the
     device before the round and are not timed."""
     import torch
     from paper_1807_01350_amd import octen as oc
@@ -451,8 +452,7 @@ def run_batched(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         replays.append(group.step(batches, args.iters))
-        for st in streams:
-            st["eng"].recover_factors_async(*st["outs"])
+        group.recover([st["outs"] for st in streams])
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         print(f"[bench] round {r}: {times[-1] * 1e3:.1f} ms, replayed {replays[-1]}",
@@ -470,7 +470,8 @@ def run_batched(args):
         "config": {"workload": f"batched{len(streams)}: {len(streams)} dense FP32 streams, I,J in "
                                f"[200,4000], t in [10,200], R in [5,30], P in [4,16], Q in [20,80], "
                                f"S=3; one step = one round of all streams (compress + update + "
-                               f"{args.iters} ALS sweeps in one captured graph, then recovery)",
+                               f"{args.iters} ALS sweeps in one captured graph, then the recovery of "
+                               f"all streams, each on a stream of its own)",
                    "streams": len(streams), "slices_per_round": slices,
                    "x_bytes_per_round": xbytes, "als_iters": args.iters,
                    "compress_dtype": args.form,

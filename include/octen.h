@@ -370,7 +370,8 @@ octen_status octen_autotune_als(octen_t h, int32_t sweeps, int32_t* choice_host)
  * while all their workgroups fit on the device at once.  The others
  * (OCTEN_FLAG_ALS_ONE_WG, or replicas too large) run it in their branch, one
  * workgroup per replica.
- * Recovery stays per handle, outside the graph. */
+ * Recovery stays outside the graph: per handle, or for all handles at once
+ * with octen_group_recover. */
 typedef struct octen_group* octen_group_t;
 typedef struct {
   const void* X;            /* [t][I][J] in the handle's x_dtype (device)      */
@@ -389,6 +390,16 @@ octen_status octen_group_create(const octen_t* handles, int32_t n, octen_group_t
  * captured graph was replayed. */
 octen_status octen_group_step(octen_group_t g, const octen_batch_desc* desc, int32_t max_iters,
                               double tol, int32_t init_mode, int32_t* replayed_host);
+/* Recovery of every handle of the group after a step: octen_recover_factors
+ * of handle i with A[i], B[i], C[i], c_capacity[i] (host arrays of n device
+ * pointers and n row capacities) and no row count, each handle on a stream
+ * of its own that starts after the work already on the handles' stream and
+ * is joined back into it, so the handles' recoveries run concurrently.  The
+ * results are those of the handle-by-handle calls.  On an error the handles
+ * before it have recovered and the error names the handle; the rest have
+ * not. */
+octen_status octen_group_recover(octen_group_t g, double* const* A, double* const* B,
+                                 double* const* C, const int64_t* c_capacity);
 /* Number of cooperative ALS launches in the graph of the latest captured
  * step (0 before the first step, or when the ALS runs in the branches). */
 octen_status octen_group_als_launches(octen_group_t g, int32_t* out_host);

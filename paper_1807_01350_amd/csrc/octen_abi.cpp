@@ -1436,6 +1436,35 @@ octen_status octen_group_destroy(octen_group_t g) {
   return OCTEN_OK;
 }
 
+octen_status octen_group_recover(octen_group_t g, double* const* A, double* const* B,
+                                 double* const* C, const int64_t* c_capacity) {
+  if (!g) return OCTEN_ERR_ARG;
+  if (!A || !B || !C || !c_capacity) return gfail(g, OCTEN_ERR_ARG, "null argument");
+  const int n = (int)g->hs.size();
+  GHIP(g, hipEventRecord(g->fork, g->user));
+  octen_status st = OCTEN_OK;
+  int used = 0;   // branches that hold work to join
+  for (int i = 0; i < n && st == OCTEN_OK; ++i) {
+    octen_t h = g->hs[i];
+    if (h->stream != g->user) { st = gfail(g, OCTEN_ERR_STATE, "handle stream changed"); break; }
+    const hipError_t e = hipStreamWaitEvent(g->branch[i], g->fork, 0);
+    if (e != hipSuccess) { st = gfail(g, OCTEN_ERR_HIP, std::string("fork: ") + hipGetErrorString(e)); break; }
+    used = i + 1;
+    h->stream = g->branch[i];
+    st = octen_recover_factors(h, A[i], B[i], C[i], c_capacity[i], nullptr);
+    h->stream = g->user;
+    if (st != OCTEN_OK) g->err = "handle " + std::to_string(i) + ": " + h->err;
+  }
+  // join every branch used, also after an error
+  for (int i = 0; i < used; ++i) {
+    hipError_t e = hipEventRecord(g->join[i], g->branch[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(g->user, g->join[i], 0);
+    if (e != hipSuccess && st == OCTEN_OK)
+      st = gfail(g, OCTEN_ERR_HIP, std::string("join: ") + hipGetErrorString(e));
+  }
+  return st;
+}
+
 octen_status octen_group_als_launches(octen_group_t g, int32_t* out_host) {
   if (!g || !out_host) return OCTEN_ERR_ARG;
   *out_host = g->exec ? g->als_launches : 0;

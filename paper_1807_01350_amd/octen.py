@@ -121,6 +121,7 @@ _SIGS = {
     "octen_autotune_als": ([_vp, _i32, _vp], _i32),
     "octen_group_create": ([_vp, _i32, ctypes.POINTER(_vp)], _i32),
     "octen_group_step": ([_vp, _vp, _i32, _f64, _i32, _vp], _i32),
+    "octen_group_recover": ([_vp, _vp, _vp, _vp, _vp], _i32),
     "octen_group_als_launches": ([_vp, _vp], _i32),
     "octen_group_destroy": ([_vp], _i32),
     "octen_group_last_error": ([_vp], ctypes.c_char_p),
@@ -347,6 +348,12 @@ def octen_group_step(g, descs, max_iters, tol, init_mode=OCTEN_INIT_PREV, replay
                                  int(init_mode), replayed)
 
 
+def octen_group_recover(g, As, Bs, Cs, caps):
+    n = len(As)
+    return _lib.octen_group_recover(g, _ptr_array(As), _ptr_array(Bs), _ptr_array(Cs),
+                                    ctypes.cast((ctypes.c_int64 * n)(*caps), _vp))
+
+
 def octen_group_als_launches(g, out):
     return _lib.octen_group_als_launches(g, out)
 
@@ -383,6 +390,17 @@ class Group:
         for e, (X, _) in zip(self.engines, batches):
             e._pend += int(X.shape[0])
         return bool(rep.value)
+
+    def recover(self, outs):
+        """Recovery of every handle after a step, the handles concurrently:
+        outs is a list of (A, B, C) device tensors, one per handle."""
+        st = octen_group_recover(self.g, [A for A, _, _ in outs], [B for _, B, _ in outs],
+                                 [C for _, _, C in outs], [C.shape[0] for _, _, C in outs])
+        if st != OCTEN_OK:
+            raise OctenError(st, "octen_group_recover", octen_group_last_error(self.g))
+        for e in self.engines:
+            e.K += e._pend
+            e._pend = 0
 
     def als_launches(self):
         """Cooperative ALS launches in the graph of the latest captured step."""

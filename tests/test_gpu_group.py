@@ -347,7 +347,8 @@ def test_group_packs_cooperative_als_of_equal_kernels():
     6, two of them with the fewest workgroups per replica); a two-term handle
     takes a launch of its own.  Every replica's result
     equals the handle-by-handle cooperative calls bit for bit (the
-    convergence test on, so members may stop at different sweeps)."""
+    convergence test on, so members may stop at different sweeps), and so
+    does the group's recovery of all handles at once (octen_group_recover)."""
     import torch
     from paper_1807_01350_amd import octen as oc
     shapes = [(120, 100, 5, 4, 20, 3, 24, 6, "bf16x2"), (140, 90, 6, 6, 24, 3, 30, 8, "bf16x2"),
@@ -388,10 +389,18 @@ def test_group_packs_cooperative_als_of_equal_kernels():
                 assert np.array_equal(a, b), (r, q, what)
             iters.update(int(v) for v in g.state(oc.OCTEN_STATE_ITERS).cpu().numpy())
             assert not g.state(oc.OCTEN_STATE_FLAGS).cpu().numpy().any(), (r, q)
-            for e2 in (g, e):
-                e2.recover_factors(torch.empty((c.I, c.R), dtype=torch.float64, device="cuda"),
-                                   torch.empty((c.J, c.R), dtype=torch.float64, device="cuda"),
-                                   torch.empty((c.K, c.R), dtype=torch.float64, device="cuda"))
+        # the group's recovery (handles on their own streams) against the
+        # handle-by-handle calls
+        outs = [tuple(torch.full((n, c.R), float("nan"), dtype=torch.float64, device="cuda")
+                      for n in (c.I, c.J, c.K)) for (c, *_r) in streams]
+        group.recover(outs)
+        for q, (g, e, (c, *_r)) in enumerate(zip(grp, twin, streams)):
+            ref = [torch.empty((n, c.R), dtype=torch.float64, device="cuda") for n in (c.I, c.J, c.K)]
+            K = e.recover_factors(*ref)
+            assert g.K == K, (r, q)
+            (A, B, C), (A2, B2, C2) = outs[q], ref
+            for what, a, b in (("A", A, A2), ("B", B, B2), ("C", C[:K], C2[:K])):
+                assert np.array_equal(a.cpu().numpy(), b.cpu().numpy()), (r, q, what)
     assert flags == [False, True, True]
     assert group.als_launches() == 2
     print(f"[group] sweep counts seen: {sorted(iters)}", file=sys.stderr, flush=True)
