@@ -1,5 +1,6 @@
 // Several handles' replica ALS in one cooperative launch (the kernel's
 // statements are in als_coop_kernel_body.inc, its helpers in als_coop_body.h).
+#include <algorithm>
 #include <vector>
 
 #include "als_coop_body.h"
@@ -77,16 +78,27 @@ hipError_t als_coop_group(hipStream_t s, const AlsCoopItem* items, int n, int* l
   std::vector<bool> done(n, false);
   for (int i = 0; i < n; ++i)
     if (!coop_args(items[i], args[i], lds[i])) return hipErrorInvalidValue;
-  // members in handle order: each pack takes the next handles of the same
-  // kernel while their workgroups fit on the device at once
-  for (int i = 0; i < n; ++i) {
+  // A launch lasts as long as its slowest member: the handles in falling
+  // order of the work of one workgroup per sweep (4 Q^3 R / NW flop, the
+  // contractions), each pack opened by the costliest handle left and filled
+  // first-fit with the next ones of the same kernel while their workgroups
+  // fit on the device at once.
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto cost = [&](int i) {
+    return (double)items[i].Q * items[i].Q * items[i].Q * items[i].R / items[i].NW;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  for (int oi = 0; oi < n; ++oi) {
+    const int i = order[oi];
     if (done[i]) continue;
     const void* gfn = group_fn(items[i]);
     std::vector<int> pack{i};
     done[i] = true;
     size_t plds = lds[i];
     int used = coop_grid(args[i]);
-    for (int j = i + 1; gfn && j < n && (int)pack.size() < GROUP_MAX; ++j) {
+    for (int oj = oi + 1; gfn && oj < n && (int)pack.size() < GROUP_MAX; ++oj) {
+      const int j = order[oj];
       if (done[j] || group_fn(items[j]) != gfn) continue;
       const size_t l2 = lds[j] > plds ? lds[j] : plds;
       int cap = 0;
