@@ -468,16 +468,36 @@ hipError_t als_commit(hipStream_t s, int P, int QR3, int R, double* F, double* l
 // Operands are strided: A(i,k) = A[i*sai + k*sak], B(k,r) = B[k*sbk + r*sbr].
 namespace octen {
 namespace {
-__global__ __launch_bounds__(256) void rowdot_kernel(int64_t nrows, int ncols, int64_t K,
-                                                     const double* __restrict__ A, int64_t sai,
-                                                     int64_t sak, const double* __restrict__ B,
-                                                     int64_t sbk, int64_t sbr,
-                                                     const double* __restrict__ d, double alpha,
-                                                     double beta, double* __restrict__ out,
-                                                     int64_t ldo, int nsplit, int64_t kchunk,
-                                                     double* __restrict__ part) {
+// One product of the kernels below; nsplit, kchunk and part from rowdot_plan.
+struct RowdotJob {
+  int64_t nrows;
+  int ncols;
+  int64_t K;
+  const double* A;
+  int64_t sai, sak;
+  const double* B;
+  int64_t sbk, sbr;
+  const double* d;
+  double alpha, beta;
+  double* out;
+  int64_t ldo;
+  int nsplit;
+  int64_t kchunk;
+  double* part;
+};
+
+// Up to two independent products in one launch: blocks [0, blocks0) work on
+// j0, the rest on j1.
+__global__ __launch_bounds__(256) void rowdot_kernel(RowdotJob j0, RowdotJob j1, int64_t blocks0) {
+  const bool second = (int64_t)blockIdx.x >= blocks0;
+  const RowdotJob& j = second ? j1 : j0;
+  const int64_t nrows = j.nrows, K = j.K, sai = j.sai, sak = j.sak, sbk = j.sbk, sbr = j.sbr;
+  const int ncols = j.ncols, nsplit = j.nsplit;
+  const double* __restrict__ A = j.A;
+  const double* __restrict__ B = j.B;
+  const double* __restrict__ d = j.d;
   const int lane = threadIdx.x & 63;
-  const int64_t wid = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  const int64_t wid = ((int64_t)blockIdx.x - (second ? blocks0 : 0)) * 4 + threadIdx.x / 64;
   const int nblk = (ncols + 31) / 32;
   if (wid >= nrows * nblk * nsplit) return;
   const int sp = (int)(wid % nsplit);
@@ -485,7 +505,7 @@ __global__ __launch_bounds__(256) void rowdot_kernel(int64_t nrows, int ncols, i
   const int64_t i = rest / nblk;
   const int r0 = (int)(rest % nblk) * 32;
   const int nr = ncols - r0 < 32 ? ncols - r0 : 32;
-  const int64_t k0 = sp * kchunk, k1 = k0 + kchunk < K ? k0 + kchunk : K;
+  const int64_t k0 = sp * j.kchunk, k1 = k0 + j.kchunk < K ? k0 + j.kchunk : K;
   double acc[32];
 #pragma unroll
   for (int r = 0; r < 32; ++r) acc[r] = 0.0;
@@ -508,12 +528,12 @@ __global__ __launch_bounds__(256) void rowdot_kernel(int64_t nrows, int ncols, i
   }
   if (lane == 0) {
     if (nsplit == 1) {
-      double* o = out + i * ldo + r0;
+      double* o = j.out + i * j.ldo + r0;
 #pragma unroll
       for (int r = 0; r < 32; ++r)
-        if (r < nr) o[r] = beta != 0.0 ? alpha * acc[r] + beta * o[r] : alpha * acc[r];
+        if (r < nr) o[r] = j.beta != 0.0 ? j.alpha * acc[r] + j.beta * o[r] : j.alpha * acc[r];
     } else {
-      double* o = part + ((int64_t)sp * nrows + i) * ncols + r0;
+      double* o = j.part + ((int64_t)sp * nrows + i) * ncols + r0;
 #pragma unroll
       for (int r = 0; r < 32; ++r)
         if (r < nr) o[r] = acc[r];
@@ -521,20 +541,23 @@ __global__ __launch_bounds__(256) void rowdot_kernel(int64_t nrows, int ncols, i
   }
 }
 
-// out(i, r) = alpha * sum over the splits (in order) + beta * out(i, r)
-__global__ void rowdot_reduce_kernel(int64_t nrows, int ncols, int nsplit,
-                                     const double* __restrict__ part, double alpha, double beta,
-                                     double* __restrict__ out, int64_t ldo) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= nrows * ncols) return;
-  const int64_t i = e / ncols;
-  const int r = (int)(e % ncols);
+// out(i, r) = alpha * sum over the splits (in order) + beta * out(i, r), for
+// up to two products as in rowdot_kernel (256 threads per block).
+__global__ void rowdot_reduce_kernel(RowdotJob j0, RowdotJob j1, int64_t blocks0) {
+  const bool second = (int64_t)blockIdx.x >= blocks0;
+  const RowdotJob& j = second ? j1 : j0;
+  const int64_t e = ((int64_t)blockIdx.x - (second ? blocks0 : 0)) * blockDim.x + threadIdx.x;
+  if (e >= j.nrows * j.ncols) return;
+  const int64_t i = e / j.ncols;
+  const int r = (int)(e % j.ncols);
+  const double* __restrict__ part = j.part;
+  const int64_t stride = j.nrows * j.ncols;
   // split order kept; eight partials loaded ahead of their adds
   double sum = 0.0;
 #pragma unroll 8
-  for (int sp = 0; sp < nsplit; ++sp) sum += part[(int64_t)sp * nrows * ncols + e];
-  double* o = out + i * ldo + r;
-  *o = beta != 0.0 ? alpha * sum + beta * *o : alpha * sum;
+  for (int sp = 0; sp < j.nsplit; ++sp) sum += part[(int64_t)sp * stride + e];
+  double* o = j.out + i * j.ldo + r;
+  *o = j.beta != 0.0 ? j.alpha * sum + j.beta * *o : j.alpha * sum;
 }
 
 // Small Gram-type products over a long index: part[g][i][r] = sum over the
@@ -651,60 +674,136 @@ __global__ __launch_bounds__(256) void tall_gemm_kernel(int64_t n, int R, int64_
 
 }  // namespace
 
+namespace {
+
+RowdotJob make_job(int64_t nrows, int ncols, int64_t K, const double* A, int64_t sai, int64_t sak,
+                   const double* B, int64_t sbk, int64_t sbr, const double* d, double alpha,
+                   double beta, double* out, int64_t ldo) {
+  RowdotJob j;
+  j.nrows = nrows; j.ncols = ncols; j.K = K; j.A = A; j.sai = sai; j.sak = sak; j.B = B;
+  j.sbk = sbk; j.sbr = sbr; j.d = d; j.alpha = alpha; j.beta = beta; j.out = out; j.ldo = ldo;
+  j.nsplit = 1; j.kchunk = K; j.part = nullptr;
+  return j;
+}
+
+// The tall and Gram-type products have kernels of their own (rowdot_special).
+bool rowdot_is_tall(const RowdotJob& j) {
+  return j.sak == 1 && j.sbr == 1 && !j.d && j.ncols <= 32 && j.nrows >= 16384 && j.K >= 32;
+}
+bool rowdot_is_gram(const RowdotJob& j, const double* work) {
+  return j.sai == 1 && j.sbr == 1 && !j.d && j.nrows <= 32 && j.ncols <= 32 && j.K >= 8192 && work;
+}
+
+// Splits of the long index for rowdot_kernel: when there are too few rows to
+// fill the GPU, partial sums go to work (added in split order by
+// rowdot_reduce_kernel).  Returns the kernel's blocks.
+int64_t rowdot_plan(RowdotJob& j, double* work, int64_t work_len) {
+  const int nblk = (j.ncols + 31) / 32;
+  int64_t nsplit = 1;
+  const int64_t waves = j.nrows * nblk;
+  if (work && waves < 2048 && j.K >= 256) {
+    nsplit = (2048 + waves - 1) / waves;
+    const int64_t maxs = j.K / 128;   // at least two 64-wide steps per wavefront
+    if (nsplit > maxs) nsplit = maxs;
+    if (nsplit > 64) nsplit = 64;
+    while (nsplit > 1 && nsplit * j.nrows * j.ncols > work_len) --nsplit;
+    if (nsplit < 1) nsplit = 1;
+  }
+  int64_t kchunk = (j.K + nsplit - 1) / nsplit;
+  kchunk = (kchunk + 63) / 64 * 64;
+  j.nsplit = (int)nsplit;
+  j.kchunk = kchunk;
+  j.part = nsplit > 1 ? work : nullptr;
+  return (waves * nsplit + 3) / 4;
+}
+
+int64_t reduce_blocks(const RowdotJob& j) {
+  return j.nsplit > 1 ? (j.nrows * j.ncols + 255) / 256 : 0;
+}
+
+hipError_t rowdot_special(hipStream_t s, const RowdotJob& j, double* work, int64_t work_len,
+                          bool* done) {
+  *done = false;
+  if (rowdot_is_tall(j)) {
+    // tall product with unit inner strides and enough 64-row blocks to fill
+    // the GPU: FP64 MFMA, A streamed once
+    hipLaunchKernelGGL(tall_gemm_kernel, dim3((unsigned)((j.nrows + 63) / 64)), dim3(256), 0, s,
+                       j.nrows, j.ncols, j.K, j.A, j.sai, j.B, j.sbk, j.alpha, j.beta, j.out,
+                       j.ldo);
+    *done = true;
+    return hipGetLastError();
+  }
+  if (rowdot_is_gram(j, work)) {
+    // R x R Gram-type product over a long index: blocks over k, partials
+    // summed in block order
+    const int64_t np = j.nrows * j.ncols;
+    int64_t g = j.K / 256;
+    if (g > 256) g = 256;
+    if (g * np > work_len) g = work_len / np;
+    if (g >= 2) {
+      int64_t kchunk = (j.K + g - 1) / g;
+      kchunk = (kchunk + GR_KB - 1) / GR_KB * GR_KB;
+      g = (j.K + kchunk - 1) / kchunk;
+      hipLaunchKernelGGL(gram_part_kernel, dim3((unsigned)g), dim3(256), 0, s, (int)j.nrows,
+                         j.ncols, j.K, j.A, j.sak, j.B, j.sbk, kchunk, work);
+      RowdotJob r = j;
+      r.nsplit = (int)g;
+      r.part = work;
+      const int64_t rb = reduce_blocks(r);
+      hipLaunchKernelGGL(rowdot_reduce_kernel, dim3((unsigned)rb), dim3(256), 0, s, r, r, rb);
+      *done = true;
+      return hipGetLastError();
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t rowdot_job(hipStream_t s, RowdotJob j, double* work, int64_t work_len) {
+  if (j.nrows <= 0 || j.ncols <= 0) return hipSuccess;
+  bool done = false;
+  hipError_t e = rowdot_special(s, j, work, work_len, &done);
+  if (e != hipSuccess || done) return e;
+  const int64_t blocks = rowdot_plan(j, work, work_len);
+  hipLaunchKernelGGL(rowdot_kernel, dim3((unsigned)blocks), dim3(256), 0, s, j, j, blocks);
+  const int64_t rb = reduce_blocks(j);
+  if (rb > 0)
+    hipLaunchKernelGGL(rowdot_reduce_kernel, dim3((unsigned)rb), dim3(256), 0, s, j, j, rb);
+  return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t rowdot(hipStream_t s, int64_t nrows, int ncols, int64_t K, const double* A, int64_t sai,
                   int64_t sak, const double* B, int64_t sbk, int64_t sbr, const double* d,
                   double alpha, double beta, double* out, int64_t ldo, double* work,
                   int64_t work_len) {
-  if (nrows <= 0 || ncols <= 0) return hipSuccess;
-  if (sak == 1 && sbr == 1 && !d && ncols <= 32 && nrows >= 16384 && K >= 32) {
-    // tall product with unit inner strides and enough 64-row blocks to fill
-    // the GPU: FP64 MFMA, A streamed once
-    hipLaunchKernelGGL(tall_gemm_kernel, dim3((unsigned)((nrows + 63) / 64)), dim3(256), 0, s,
-                       nrows, ncols, K, A, sai, B, sbk, alpha, beta, out, ldo);
-    return hipGetLastError();
+  return rowdot_job(s, make_job(nrows, ncols, K, A, sai, sak, B, sbk, sbr, d, alpha, beta, out, ldo),
+                    work, work_len);
+}
+
+hipError_t rowdot_pair(hipStream_t s, const RowdotArgs& x, const RowdotArgs& y, double* work,
+                       int64_t work_len) {
+  RowdotJob j0 = make_job(x.nrows, x.ncols, x.K, x.A, x.sai, x.sak, x.B, x.sbk, x.sbr, x.d,
+                          x.alpha, x.beta, x.out, x.ldo);
+  RowdotJob j1 = make_job(y.nrows, y.ncols, y.K, y.A, y.sai, y.sak, y.B, y.sbk, y.sbr, y.d,
+                          y.alpha, y.beta, y.out, y.ldo);
+  const int64_t half = work ? work_len / 2 : 0;
+  double* work1 = work ? work + half : nullptr;
+  if (j0.nrows <= 0 || j0.ncols <= 0 || j1.nrows <= 0 || j1.ncols <= 0 || rowdot_is_tall(j0) ||
+      rowdot_is_tall(j1) || rowdot_is_gram(j0, work) || rowdot_is_gram(j1, work)) {
+    hipError_t e = rowdot_job(s, j0, work, half);
+    return e != hipSuccess ? e : rowdot_job(s, j1, work1, half);
   }
-  if (sai == 1 && sbr == 1 && !d && nrows <= 32 && ncols <= 32 && K >= 8192 && work) {
-    // R x R Gram-type product over a long index: blocks over k, partials
-    // summed in block order
-    const int64_t np = nrows * ncols;
-    int64_t g = K / 256;
-    if (g > 256) g = 256;
-    if (g * np > work_len) g = work_len / np;
-    if (g >= 2) {
-      int64_t kchunk = (K + g - 1) / g;
-      kchunk = (kchunk + GR_KB - 1) / GR_KB * GR_KB;
-      g = (K + kchunk - 1) / kchunk;
-      hipLaunchKernelGGL(gram_part_kernel, dim3((unsigned)g), dim3(256), 0, s, (int)nrows, ncols,
-                         K, A, sak, B, sbk, kchunk, work);
-      hipLaunchKernelGGL(rowdot_reduce_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0,
-                         s, nrows, ncols, (int)g, work, alpha, beta, out, ldo);
-      return hipGetLastError();
-    }
-  }
-  const int nblk = (ncols + 31) / 32;
-  // split the long index when there are too few rows to fill the GPU; the
-  // partial sums are added in split order by a second kernel
-  int64_t nsplit = 1;
-  const int64_t waves = nrows * nblk;
-  if (work && waves < 2048 && K >= 256) {
-    nsplit = (2048 + waves - 1) / waves;
-    const int64_t maxs = K / 128;   // at least two 64-wide steps per wavefront
-    if (nsplit > maxs) nsplit = maxs;
-    if (nsplit > 64) nsplit = 64;
-    while (nsplit > 1 && nsplit * nrows * ncols > work_len) --nsplit;
-    if (nsplit < 1) nsplit = 1;
-  }
-  int64_t kchunk = (K + nsplit - 1) / nsplit;
-  kchunk = (kchunk + 63) / 64 * 64;
-  const int64_t total = waves * nsplit;
-  const int64_t blocks = (total + 3) / 4;
-  hipLaunchKernelGGL(rowdot_kernel, dim3((unsigned)blocks), dim3(256), 0, s, nrows, ncols, K, A,
-                     sai, sak, B, sbk, sbr, d, alpha, beta, out, ldo, (int)nsplit, kchunk, work);
-  if (nsplit > 1) {
-    const int64_t n = nrows * ncols;
-    hipLaunchKernelGGL(rowdot_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       nrows, ncols, (int)nsplit, work, alpha, beta, out, ldo);
-  }
+  const int64_t b0 = rowdot_plan(j0, work, half);
+  const int64_t b1 = rowdot_plan(j1, work1, half);
+  hipLaunchKernelGGL(rowdot_kernel, dim3((unsigned)(b0 + b1)), dim3(256), 0, s, j0, j1, b0);
+  const int64_t r0 = reduce_blocks(j0), r1 = reduce_blocks(j1);
+  if (r0 > 0 && r1 > 0)
+    hipLaunchKernelGGL(rowdot_reduce_kernel, dim3((unsigned)(r0 + r1)), dim3(256), 0, s, j0, j1, r0);
+  else if (r0 > 0)
+    hipLaunchKernelGGL(rowdot_reduce_kernel, dim3((unsigned)r0), dim3(256), 0, s, j0, j0, r0);
+  else if (r1 > 0)
+    hipLaunchKernelGGL(rowdot_reduce_kernel, dim3((unsigned)r1), dim3(256), 0, s, j1, j1, r1);
   return hipGetLastError();
 }
 }  // namespace octen

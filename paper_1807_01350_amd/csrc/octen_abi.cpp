@@ -887,16 +887,17 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, i
   HIPCHK(h, rec_align(s, P, Q, R, S, h->F, h->lam, h->aligned, h->perm, h->margin));
   HIPCHK(h, rec_stack(s, P, Q, R, S, h->aligned, h->rhs));
   // Eq. 7 for modes 1 and 2
-  HIPCHK(h, rowdot(s, I, R, M1, h->OpA, M1, 1, h->rhs, R, 1, nullptr, 1.0, 0.0, h->Araw, R,
-                   h->rd_work, octen_ctx::RD_WORK));
-  HIPCHK(h, rowdot(s, J, R, M1, h->OpB, M1, 1, h->rhs + (int64_t)M1 * R, R, 1, nullptr, 1.0, 0.0,
-                   h->Braw, R, h->rd_work, octen_ctx::RD_WORK));
+  HIPCHK(h, rowdot_pair(s, {I, R, M1, h->OpA, M1, 1, h->rhs, R, 1, nullptr, 1.0, 0.0, h->Araw, R},
+                        {J, R, M1, h->OpB, M1, 1, h->rhs + (int64_t)M1 * R, R, 1, nullptr, 1.0,
+                         0.0, h->Braw, R},
+                        h->rd_work, octen_ctx::RD_WORK));
   HIPCHK(h, rec_canon2(s, I, J, R, h->Araw, h->Ac, h->ka, h->Braw, h->Bc, h->kb, h->rd_work,
                        octen_ctx::RD_WORK));
   if (h->have_prev) {
-    HIPCHK(h, rowdot(s, R, R, I, h->Ac, 1, R, h->Aprev, R, 1, nullptr, 1.0, 0.0, h->cross, R, h->rd_work, octen_ctx::RD_WORK));
-    HIPCHK(h, rowdot(s, R, R, J, h->Bc, 1, R, h->Bprev, R, 1, nullptr, 1.0, 0.0, h->cross + R * R,
-                     R, h->rd_work, octen_ctx::RD_WORK));
+    HIPCHK(h, rowdot_pair(s, {R, R, I, h->Ac, 1, R, h->Aprev, R, 1, nullptr, 1.0, 0.0, h->cross, R},
+                          {R, R, J, h->Bc, 1, R, h->Bprev, R, 1, nullptr, 1.0, 0.0,
+                           h->cross + R * R, R},
+                          h->rd_work, octen_ctx::RD_WORK));
     HIPCHK(h, rec_col_norms4(s, I, J, R, h->Ac, h->Aprev, h->Bc, h->Bprev, h->norms, h->rd_work,
                              octen_ctx::RD_WORK));
     HIPCHK(h, rec_tmatch(s, R, h->cross, h->norms, h->tperm, h->tsign, h->tmargin));
@@ -908,8 +909,9 @@ octen_status octen_recover_factors(octen_t h, double* A, double* B, double* C, i
   OKCHK(dgrow(h, &h->bt, &h->bt_cap, (t > M1 ? t : (int64_t)M1) * R));
   if (t <= M1) {
     OKCHK(dgrow(h, &h->Nt, &h->Nt_cap, t * t));
-    HIPCHK(h, rowdot(s, t, (int)t, M1, h->Wp, M1, 1, h->Wp, 1, M1, h->w2, 1.0, 0.0, h->Nt, t, h->rd_work, octen_ctx::RD_WORK));
-    HIPCHK(h, rowdot(s, t, R, M1, h->Wp, M1, 1, h->rhs_c, R, 1, h->w2, 1.0, 0.0, h->bt, R, h->rd_work, octen_ctx::RD_WORK));
+    HIPCHK(h, rowdot_pair(s, {t, (int)t, M1, h->Wp, M1, 1, h->Wp, 1, M1, h->w2, 1.0, 0.0, h->Nt, t},
+                          {t, R, M1, h->Wp, M1, 1, h->rhs_c, R, 1, h->w2, 1.0, 0.0, h->bt, R},
+                          h->rd_work, octen_ctx::RD_WORK));
     HIPCHK(h, spd_solve_small(s, h->Nt, (int)t, h->bt, R, h->gj_work, h->info));
   } else {
     OKCHK(dgrow(h, &h->Nt, &h->Nt_cap, (int64_t)M1 * M1 + (int64_t)M1 * R));

@@ -41,6 +41,26 @@ hipError_t rowdot(hipStream_t s, int64_t nrows, int ncols, int64_t K, const doub
                   int64_t sak, const double* B, int64_t sbk, int64_t sbr, const double* d,
                   double alpha, double beta, double* out, int64_t ldo, double* work = nullptr,
                   int64_t work_len = 0);
+// The arguments of one rowdot product.
+struct RowdotArgs {
+  int64_t nrows;
+  int ncols;
+  int64_t K;
+  const double* A;
+  int64_t sai, sak;
+  const double* B;
+  int64_t sbk, sbr;
+  const double* d;
+  double alpha, beta;
+  double* out;
+  int64_t ldo;
+};
+// Two independent rowdot products (neither writes what the other reads) in
+// one launch of the row kernel and at most one of the split reduction, each
+// with half of work; products the tall or Gram-type kernels take run one
+// after the other.
+hipError_t rowdot_pair(hipStream_t s, const RowdotArgs& x, const RowdotArgs& y, double* work,
+                       int64_t work_len);
 
 // One-workgroup solve of N X = Bm for SPD N (N: n x n, Bm: n x nrhs, both
 // row-major; Bm is overwritten by the solution, N by its Cholesky factor for
