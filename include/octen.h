@@ -121,7 +121,9 @@ enum {
                                             2e5 FMAs per workgroup and sweep);
                                             for handles of a group, whose
                                             cooperative ALS then share launches
-                                            with more handles               */
+                                            with more handles;
+                                            octen_autotune_als replaces the
+                                            choice by its timed one         */
 
 /* Stages timed with OCTEN_FLAG_TIMING (octen_stage_time). */
 enum {

@@ -393,7 +393,9 @@ class Group:
 
     def recover(self, outs):
         """Recovery of every handle after a step, the handles concurrently:
-        outs is a list of (A, B, C) device tensors, one per handle."""
+        outs is a list of (A, B, C) device tensors, one per handle.  On an
+        error the handles before the one the message names have recovered;
+        the host row counts are then left as they were for all."""
         st = octen_group_recover(self.g, [A for A, _, _ in outs], [B for _, B, _ in outs],
                                  [C for _, _, C in outs], [C.shape[0] for _, _, C in outs])
         if st != OCTEN_OK:
