@@ -367,9 +367,9 @@ octen_status octen_autotune_als(octen_t h, int32_t sweeps, int32_t* choice_host)
  * batch goes through its own calls).  Handles
  * whose ALS is a cooperative grid run it after the branches join (no
  * cooperative grid shares the GPU with other work of the step): handles
- * whose ALS runs the same kernel (summary precision, contraction form, slab
- * placement and rank class) share one cooperative launch, up to 16 handles,
- * while all their workgroups fit on the device at once.  The others
+ * whose ALS runs the same kernel form (summary precision, contraction form
+ * and slab placement; any rank) share one cooperative launch, up to 16
+ * handles, while all their workgroups fit on the device at once.  The others
  * (OCTEN_FLAG_ALS_ONE_WG, or replicas too large) run it in their branch, one
  * workgroup per replica.
  * Recovery stays outside the graph: per handle, or for all handles at once

@@ -5,11 +5,13 @@
 namespace octen {
 namespace {
 
+#define OCTEN_ALS_INVERSE(...) spd_inverse<RMAX>(__VA_ARGS__)
 template <typename T, int RMAX, bool GX, bool SPLIT>
 __global__ __launch_bounds__(NT) void als_coop_kernel(CoopArgs g) {
   const unsigned bid = blockIdx.x;
 #include "als_coop_kernel_body.inc"
 }
+#undef OCTEN_ALS_INVERSE
 
 template <int RM>
 const void* pick_single(bool split, bool gx, bool f64) {

@@ -535,7 +535,7 @@ inline bool coop_args(const AlsCoopItem& it, CoopArgs& a, size_t& lds) {
 }
 
 // The inverse runs RMAX straight-line steps: exact fits for the common ranks.
-inline int rmax_class(int R) {
+__host__ __device__ inline int rmax_class(int R) {
   return R <= 6 ? 6 : R <= 8 ? 8 : R <= 10 ? 10 : R <= 12 ? 12 : R <= 16 ? 16 : R <= 20 ? 20
          : R <= 24 ? 24 : 32;
 }

@@ -20,41 +20,48 @@ struct CoopGroup {
 
 static_assert(sizeof(CoopGroup) <= 4096, "kernel argument block");
 
-template <typename T, int RMAX, bool GX, bool SPLIT>
+// The R x R inverse of rank class rc (wave-uniform): the same code as in a
+// kernel instantiated for that class.
+__device__ __forceinline__ void spd_inverse_class(int rc, const double* G, double* Ginv, int R,
+                                                  int* bad) {
+  switch (rc) {
+    case 6: spd_inverse<6>(G, Ginv, R, bad); break;
+    case 8: spd_inverse<8>(G, Ginv, R, bad); break;
+    case 10: spd_inverse<10>(G, Ginv, R, bad); break;
+    case 12: spd_inverse<12>(G, Ginv, R, bad); break;
+    case 16: spd_inverse<16>(G, Ginv, R, bad); break;
+    case 20: spd_inverse<20>(G, Ginv, R, bad); break;
+    case 24: spd_inverse<24>(G, Ginv, R, bad); break;
+    default: spd_inverse<32>(G, Ginv, R, bad); break;
+  }
+}
+
+// Members of any rank class share a launch: each takes the inverse of its
+// own class.
+#define OCTEN_ALS_INVERSE(...) spd_inverse_class(rclass_, __VA_ARGS__)
+template <typename T, bool GX, bool SPLIT>
 __global__ __launch_bounds__(NT) void als_coop_group_kernel(CoopGroup grp_) {
   int m_ = 0;   // the member whose range holds this workgroup
   for (int i_ = 1; i_ < grp_.n; ++i_) m_ += (int)blockIdx.x >= grp_.start[i_] ? 1 : 0;
   m_ = __builtin_amdgcn_readfirstlane(m_);
   const CoopArgs& g = grp_.a[m_];
   const unsigned bid = blockIdx.x - (unsigned)grp_.start[m_];
+  const int rclass_ = __builtin_amdgcn_readfirstlane(rmax_class(g.R));
 #include "als_coop_kernel_body.inc"
 }
+#undef OCTEN_ALS_INVERSE
 
-template <int RM>
-const void* pick_group(bool split, bool gx, bool f64) {
-  if (split)
-    return gx ? (const void*)als_coop_group_kernel<float, RM, true, true>
-              : (const void*)als_coop_group_kernel<float, RM, false, true>;
-  if (gx)
-    return f64 ? (const void*)als_coop_group_kernel<double, RM, true, false>
-               : (const void*)als_coop_group_kernel<float, RM, true, false>;
-  return f64 ? (const void*)als_coop_group_kernel<double, RM, false, false>
-             : (const void*)als_coop_group_kernel<float, RM, false, false>;
-}
-
-// The group kernel of an item: items of equal kernels may share a launch.
+// The group kernel of an item: items of equal kernels may share a launch
+// (summary precision, contraction form and slab placement; any rank class).
 const void* group_fn(const AlsCoopItem& it) {
-  const bool sp = it.split, gx = it.slab_global, f = it.y_f64;
-  switch (rmax_class(it.R)) {
-    case 6: return pick_group<6>(sp, gx, f);
-    case 8: return pick_group<8>(sp, gx, f);
-    case 10: return pick_group<10>(sp, gx, f);
-    case 12: return pick_group<12>(sp, gx, f);
-    case 16: return pick_group<16>(sp, gx, f);
-    case 20: return pick_group<20>(sp, gx, f);
-    case 24: return pick_group<24>(sp, gx, f);
-    default: return pick_group<32>(sp, gx, f);
-  }
+  if (it.split)
+    return it.slab_global ? (const void*)als_coop_group_kernel<float, true, true>
+                          : (const void*)als_coop_group_kernel<float, false, true>;
+  if (it.slab_global)
+    return it.y_f64 ? (const void*)als_coop_group_kernel<double, true, false>
+                    : (const void*)als_coop_group_kernel<float, true, false>;
+  return it.y_f64 ? (const void*)als_coop_group_kernel<double, false, false>
+                  : (const void*)als_coop_group_kernel<float, false, false>;
 }
 
 // Workgroups of fn that fit on the device at once with lds bytes of LDS each.

@@ -175,8 +175,8 @@ struct AlsCoopItem {
   bool allow_local, split;
 };
 // The cooperative ALS of n handles (counters and err already zero): handles
-// of the same kernel share a launch while all their workgroups fit on the
-// device at once, up to 16 per launch.
+// of the same kernel form (any rank) share a launch while all their
+// workgroups fit on the device at once, up to 16 per launch.
 // launches: NULL or the number of cooperative launches made.
 hipError_t als_coop_group(hipStream_t s, const AlsCoopItem* items, int n, int* launches);
 

@@ -343,16 +343,17 @@ def test_small_group_runs_cooperative_als_after_the_join():
 
 def test_group_packs_cooperative_als_of_equal_kernels():
     """After the join, handles whose ALS runs the same kernel share one
-    cooperative launch (four float-summary FP64-solve handles of rank class
-    6, two of them with the fewest workgroups per replica); a two-term handle
-    takes a launch of its own.  Every replica's result
+    cooperative launch (four float-summary FP64-solve handles of ranks 5, 6,
+    9 and 13, three rank classes, each member taking its own class's
+    inverse; two of them with the fewest workgroups per replica); a
+    two-term handle takes a launch of its own.  Every replica's result
     equals the handle-by-handle cooperative calls bit for bit (the
     convergence test on, so members may stop at different sweeps), and so
     does the group's recovery of all handles at once (octen_group_recover)."""
     import torch
     from paper_1807_01350_amd import octen as oc
     shapes = [(120, 100, 5, 4, 20, 3, 24, 6, "bf16x2"), (140, 90, 6, 6, 24, 3, 30, 8, "bf16x2"),
-              (100, 130, 5, 8, 22, 3, 20, 5, "f32"), (90, 110, 6, 5, 26, 3, 24, 6, "bf16"),
+              (100, 130, 9, 8, 22, 3, 20, 5, "f32"), (90, 110, 13, 5, 26, 3, 24, 6, "bf16"),
               (110, 96, 5, 4, 24, 3, 20, 5, "bf16x2")]
     als = ["f64", "f64", "f64", "f64", "bf16x2"]
     streams = _streams(shapes, 120)
