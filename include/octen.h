@@ -52,7 +52,7 @@ typedef enum {
   OCTEN_ERR_HIP = 3,         /* HIP runtime error; see octen_last_error */
   OCTEN_ERR_NOMEM = 4,       /* device allocation failed */
   OCTEN_ERR_NUMERIC = 5,     /* non-finite values or a failed solve */
-  OCTEN_ERR_UNSUPPORTED = 6  /* valid request this build does not implement */
+  OCTEN_ERR_UNSUPPORTED = 6  /* valid request the library does not implement */
 } octen_status;
 
 /* Element and arithmetic types.  OCTEN_BF16X2 is the two-term bfloat16 form
